@@ -1,0 +1,184 @@
+#!/usr/bin/env python
+"""Benchmark of the Triggered Cells Method hot path on one MI355X.
+
+One bench "step" is one complete run of the 512^3 two-layer workload (2000
+leapfrog steps from a zero field, trigger 1e-6 / retire 1e-7 of the source
+peak): every step of the hot path (block stencil, plan, allocator,
+compaction) over the whole run.  The metric is active-cell updates per
+second (in-domain nodes of active blocks, summed over time steps, divided by
+the wall time of the run) with the inputs already resident on the GPU.
+
+Printed on one JSON line: the metric, the block-stencil roofline (HIP events
+around every stencil launch of the timed region), the dense FDTD engine on
+the same GPU and workload, the error of both against FP64 (from the oracle
+error table, when present) and the CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_UPDATE = 16          # read phi^n, phi^{n-1}, C2; write phi^{n+1} (FP32)
+
+
+def log(msg: str):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def workload(name: str):
+    import tcm_inputs as ti
+    if name == "c2":
+        return ti.c2()
+    if name == "c1":
+        return ti.c1()
+    raise SystemExit(f"unknown workload {name}")
+
+
+def media_of(w):
+    return {"dense": w.c_dense, "layered": w.layered, "lattice": w.lattice}[w.media_kind]
+
+
+def run_once(sim, w, steps):
+    import torch
+    sim.reset()
+    sim.add_source(w.source, w.wavelet.w32)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, sim.stats()
+
+
+def cpu_baseline(w, budget_s: float):
+    """CPU TCM oracle (OpenMP) on the first steps of the same workload, until
+    about budget_s seconds of work are done."""
+    import numpy as np
+    import oracle
+    c = w.dense_c()
+    t = oracle.TCM(c, w.dt, w.dx, np.float32(w.trigger), np.float32(w.retire))
+    t.add_source(w.source, w.wavelet.w32)
+    t0 = time.perf_counter()
+    done = 0
+    while done < w.steps and time.perf_counter() - t0 < budget_s:
+        t.step(25)
+        done += 25
+    el = time.perf_counter() - t0
+    st = t.stats()
+    t.close()
+    return {"value": st["updates"] / el, "unit": "active-cell updates/s",
+            "cores": oracle.openmp_threads(), "kind": "oracle",
+            "sample": f"CPU TCM oracle (FP32, OpenMP) on steps 0-{done} of the same workload "
+                      f"({st['updates']:.3e} updates in {el:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3, help="timed full runs")
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--time-steps", type=int, default=0, help="override leapfrog steps per run")
+    ap.add_argument("--no-dense", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--graphs", action="store_true",
+                    help="time with hipGraph replay instead of per-launch HIP events")
+    ap.add_argument("--wg-per-cu", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: the TCM hot path is built and measured on a single "
+              "MI355X; multi-GPU runs are not part of this build.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_1702_00216_amd as tcm
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    w = workload(args.workload)
+    steps = args.time_steps or w.steps
+    nx, ny, nz = w.shape
+    log(f"workload {w.name} {w.shape} x {steps} steps, trigger {w.trigger:.3g} retire {w.retire:.3g}")
+    sim = tcm.Simulation(w.shape, w.dx, w.dt, media_of(w), w.trigger, w.retire,
+                         timing=not args.graphs, wg_per_cu=args.wg_per_cu)
+    for i in range(args.warmup):
+        el, st = run_once(sim, w, steps)
+        log(f"warmup {i}: {el:.3f} s, {st['cell_updates']:.3e} updates")
+    tot_t, tot_u, st_ms, st_cells, st_launch = 0.0, 0, 0.0, 0, 0
+    for i in range(args.steps):
+        el, st = run_once(sim, w, steps)
+        tot_t += el
+        tot_u += st["cell_updates"]
+        st_ms += st["stencil_ms"]
+        st_cells += st["stencil_cells"]
+        st_launch += st["stencil_launches"]
+        log(f"run {i}: {el:.3f} s, {st['cell_updates']:.3e} updates, peak active "
+            f"{st['peak_active_blocks']}, stencil {st['stencil_ms']:.1f} ms")
+    value = tot_u / tot_t
+    last = st
+    sim.close()
+
+    roof = None
+    if st_launch > 0 and st_ms > 0:
+        achieved = BYTES_PER_UPDATE * st_cells / (st_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "k_block_step",
+                "avg_launch_us": round(st_ms * 1e3 / st_launch, 2),
+                "algorithmic_bytes_per_launch": round(BYTES_PER_UPDATE * st_cells / st_launch)}
+
+    dense = None
+    if not args.no_dense:
+        dsim = tcm.Simulation(w.shape, w.dx, w.dt, media_of(w), engine="dense", timing=True)
+        el, dst = run_once(dsim, w, steps)
+        dsim.close()
+        dense_rate = dst["cell_updates"] / el
+        dense = {"updates_per_s": dense_rate, "run_s": round(el, 4),
+                 "stencil_GBps": round(BYTES_PER_UPDATE * dst["stencil_cells"] / (dst["stencil_ms"] * 1e-3) / 1e9, 1),
+                 "tcm_speedup_wall": round(el / (tot_t / args.steps), 3)}
+        log(f"dense: {el:.3f} s ({dense_rate:.3e} node updates/s)")
+
+    err_table = None
+    p = os.path.join(ROOT, "tests", "golden", f"{w.name}_errors.json")
+    if os.path.exists(p):
+        with open(p) as f:
+            err_table = json.load(f)
+
+    cpu = None
+    if not args.no_cpu:
+        log(f"CPU oracle baseline (~{args.cpu_budget:.0f} s)")
+        cpu = cpu_baseline(w, args.cpu_budget)
+
+    out = {
+        "metric": "TCM active-cell updates/s + HBM GB/s vs dense FDTD on same GPU at equal error",
+        "value": value, "unit": "active-cell updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(tot_t / args.steps * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{w.name}: {nx}x{ny}x{nz} two-layer (1500/3000 m/s), Ricker 100 Hz at "
+                               f"{w.source}, {steps} leapfrog steps, trigger 1e-6 / retire 1e-7 of peak, "
+                               f"8^3 blocks", "time_steps_per_run": steps,
+                   "launch": "per-step launches with HIP events" if not args.graphs else "hipGraph replay"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "tcm": {"peak_active_blocks": last["peak_active_blocks"],
+                "peak_pool_bytes": last["peak_pool_bytes"],
+                "dense_bytes": 3 * 4 * nx * ny * nz,
+                "updates_per_run": last["cell_updates"],
+                "dense_updates_per_run": nx * ny * nz * steps,
+                "us_per_time_step": round(tot_t / args.steps / steps * 1e6, 2)},
+        "dense_fdtd": dense,
+        "equal_error": err_table,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

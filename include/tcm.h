@@ -1,0 +1,197 @@
+/*
+ * tcm.h -- C-ABI of libtcm.so: the Triggered Cells Method (TCM) hot path on
+ * one AMD Instinct MI355X (gfx950).
+ *
+ * Problem statement (Introduction, eq.(1)-(4)): the scalar wave equation
+ * (1/c^2) d2phi/dt2 = lap(phi) on a grid with dx = dy = dz, advanced by the
+ * second-order leapfrog of eq.(3)
+ *
+ *     phi^{n+1} = 2 phi^n - phi^{n-1} + (c dt / dx)^2 [sum of 6 neighbours - 6 phi^n]
+ *
+ * with the field zero outside the domain.  The TCM ("The Triggered Cells
+ * Method", "Cells construction", "Boxes", "Updating active cells") splits the
+ * grid into cells of 8^3 nodes ("blocks" below); only active blocks hold
+ * memory (a slot of the device pool) and are updated.  A block is activated
+ * when |phi^{n+1}| on the face of an active neighbour exceeds `trigger`, and
+ * released when every |phi^{n+1}| and |phi^n| in it is at most `retire` and no
+ * neighbour triggers it.  Source blocks stay active while their source has
+ * samples left ("Source insertion").
+ *
+ * Arithmetic: FP32 fields; C2 = (float)(t * t) with t = (double)c * dt / dx;
+ * per node, s = ((x+ + x-) + (y+ + y-)) + (z+ + z-), lap = s - 6 phi,
+ * next = (2 phi - prev) + C2 lap, no fused multiply-add, subnormals kept.
+ *
+ * Conventions shared by every call:
+ *  - Linear node index i = x + nx (y + ny z) (x fastest) for host arrays.
+ *  - Time: phi^0 = phi^{-1} = 0 at creation; after k steps the current level
+ *    is phi^k.  Sample j of a source added when the current level was phi^s
+ *    is added to phi^{s+j+1} (the step that computes it).
+ *  - Every call returns a tcm_status and never aborts; tcm_last_error() gives
+ *    the message of the last failure on that handle.
+ *  - Host input arrays are copied before the call returns.  Output buffers
+ *    belong to the caller.  The handle owns all device memory it allocates; a
+ *    caller-supplied device_pool must outlive the handle.
+ *  - A handle is not thread-safe; distinct handles are independent.
+ *  - Work is issued on the handle's stream.  Calls that return data to the
+ *    host (tcm_read, tcm_read_traces, tcm_stats) synchronise that stream;
+ *    tcm_step synchronises once at its end to report device errors.
+ */
+#ifndef TCM_H
+#define TCM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tcm_handle tcm_handle;
+
+typedef enum {
+    TCM_OK = 0,
+    TCM_E_ARG = -1,     /* invalid argument (c < 0 or not finite, thresholds, sizes) */
+    TCM_E_CFL = -2,     /* eq.(4) violated: (cmax dt / dx)^2 * 3 > 1 (+4 ulp) */
+    TCM_E_POOL = -3,    /* more active blocks than pool slots; sticky, see tcm_step */
+    TCM_E_RANGE = -4,   /* source, receiver or read box outside the domain */
+    TCM_E_DEVICE = -5,  /* HIP runtime error; the handle is poisoned (destroy only) */
+    TCM_E_STATE = -6,   /* call not valid in the handle's state */
+    TCM_E_NOMEM = -7    /* device or host allocation failed */
+} tcm_status;
+
+enum { TCM_MEDIA_DENSE = 0, TCM_MEDIA_LAYERED = 1, TCM_MEDIA_LATTICE = 2 };
+enum { TCM_ENGINE_BLOCKS = 0, TCM_ENGINE_DENSE = 1 };
+enum {
+    TCM_FLAG_TIMING = 1,    /* time every block-stencil launch with HIP events */
+    TCM_FLAG_NO_GRAPH = 2   /* launch each step's kernels directly (no hipGraph replay) */
+};
+
+/* Run configuration.  Zero-initialise, then set the fields. */
+typedef struct {
+    int32_t  nx, ny, nz;      /* grid nodes (single shot; ignored by tcm_create_batch) */
+    double   dx, dt;          /* node spacing (dx = dy = dz) and time step */
+    float    trigger;         /* activation level on |phi^{n+1}| at a block face, >= 0 */
+    float    retire;          /* keep level on |phi| inside a block, 0 <= retire <= trigger */
+    uint64_t pool_bytes;      /* pool cap in bytes (6 KiB per slot); 0: one slot per block,
+                                 limited to 90 % of free device memory */
+    void*    device_pool;     /* optional caller device memory of >= pool_bytes; NULL: own */
+    void*    stream;          /* hipStream_t to issue work on; NULL: a stream of the handle */
+    int32_t  engine;          /* TCM_ENGINE_BLOCKS (the TCM) or TCM_ENGINE_DENSE (every node) */
+    int32_t  flags;           /* TCM_FLAG_* */
+    int32_t  checkpoint_every;/* > 0 keeps forward checkpoints every k steps for tcm_adjoint */
+    int32_t  graph_steps;     /* steps per captured hipGraph (0: 16) */
+    int32_t  wg_per_cu;       /* block-stencil workgroups per compute unit (0: default) */
+    int32_t  reserved[5];
+} tcm_config;
+
+/* Wave-speed model ("Media": an array, or rules evaluated when a block is
+ * allocated).  Values are in the same length/time units as dx and dt. */
+typedef struct {
+    int32_t       kind;           /* TCM_MEDIA_* */
+    const float*  c;              /* DENSE: host array of nx*ny*nz speeds (x fastest) */
+    int32_t       nlayers;        /* LAYERED: c = c_layer[k] for z_top[k] <= z < z_top[k+1] */
+    const int32_t* z_top;         /*   ascending, z_top[0] == 0 */
+    const float*  c_layer;
+    const double* lattice;        /* LATTICE: lx*ly*lz FP64 node values (x fastest) on a lattice */
+    int32_t       lx, ly, lz;     /*   of spacing 2^log2_spacing nodes; node (i,j,k) sits at */
+    int32_t       log2_spacing;   /*   (i S, j S, k S); lx > (nx-1)/S + 1 etc.  The node value is
+                                       the trilinear interpolation, evaluated in FP64 in the order
+                                       x, then y, then z, rounded once to FP32. */
+} tcm_media;
+
+/* One shot of a batch: its grid and media (tcm_create_batch). */
+typedef struct {
+    int32_t   nx, ny, nz;
+    tcm_media media;
+} tcm_shot;
+
+typedef struct {
+    int64_t step;                 /* current level n (fields hold phi^n and phi^{n-1}) */
+    int64_t active_blocks;        /* blocks updated by the next step */
+    int64_t peak_active_blocks;
+    int64_t pool_slots;           /* capacity of the pool */
+    int64_t pool_bytes;           /* bytes of the pool (slots * 6 KiB) */
+    int64_t peak_pool_bytes;      /* peak_active_blocks * 6 KiB */
+    int64_t table_bytes;          /* other device memory: block table, bitmap, lists, media */
+    int64_t activations;
+    int64_t retirements;
+    int64_t cell_updates;         /* in-domain nodes updated so far (dense: nodes x steps) */
+    int32_t error;                /* sticky device error (TCM_E_POOL) or 0 */
+    int32_t nshots;
+    double  stencil_ms;           /* TCM_FLAG_TIMING: summed block-stencil kernel time */
+    int64_t stencil_launches;     /* TCM_FLAG_TIMING: launches summed in stencil_ms */
+    int64_t stencil_cells;        /* TCM_FLAG_TIMING: in-domain nodes of the timed launches */
+} tcm_stats_t;
+
+/* Create a single-shot handle (eq.(3) on an nx*ny*nz grid, "Cells construction").
+ * Validates eq.(4) with the largest speed of `media` (TCM_E_CFL), speeds
+ * (c >= 0 and finite; TCM_E_ARG), thresholds (TCM_E_ARG).  On success *out
+ * owns a zero field with no active block. */
+tcm_status tcm_create(const tcm_config* cfg, const tcm_media* media, tcm_handle** out);
+
+/* Create a handle that runs `nshots` independent grids over one shared pool
+ * and one active list (dt, dx, thresholds and pool from cfg). */
+tcm_status tcm_create_batch(const tcm_config* cfg, const tcm_shot* shots, int32_t nshots,
+                            tcm_handle** out);
+
+/* Point source ("Source insertion"): sample j of w (host, nsamples values) is
+ * added to phi^{s+j+1} at node (ix,iy,iz) of shot 0, where phi^s is the level
+ * when the call is made.  Its block is activated now and kept active while
+ * samples remain.  TCM_E_RANGE outside the domain; TCM_E_POOL if no slot. */
+tcm_status tcm_add_source(tcm_handle* h, int32_t ix, int32_t iy, int32_t iz,
+                          const float* w, int32_t nsamples);
+tcm_status tcm_add_source_shot(tcm_handle* h, int32_t shot, int32_t ix, int32_t iy, int32_t iz,
+                               const float* w, int32_t nsamples);
+
+/* Advance nsteps leapfrog steps (eq.(3)) with block activation and release
+ * every step ("Updating active cells", "Time stepping").  Returns TCM_E_POOL if
+ * a step needed more slots than the pool has: that step's phi^{n+1} is kept
+ * (the level advances to n+1 with the old active set) and later steps do
+ * nothing; reads and stats stay valid. */
+tcm_status tcm_step(tcm_handle* h, int32_t nsteps);
+
+/* Copy phi^n (which = 0) or phi^{n-1} (which = 1) of the box
+ * [x0,x0+sx)x[y0,y0+sy)x[z0,z0+sz) of shot 0 into out (sx*sy*sz floats,
+ * x fastest), on the host (out_is_device = 0) or the device (1, on the
+ * handle's stream).  Nodes of inactive blocks read 0. */
+tcm_status tcm_read(tcm_handle* h, int32_t which, int32_t x0, int32_t y0, int32_t z0,
+                    int32_t sx, int32_t sy, int32_t sz, float* out, int32_t out_is_device);
+tcm_status tcm_read_shot(tcm_handle* h, int32_t shot, int32_t which, int32_t x0, int32_t y0,
+                         int32_t z0, int32_t sx, int32_t sy, int32_t sz, float* out,
+                         int32_t out_is_device);
+
+/* Receivers: rec_xyz holds nrec (x,y,z) triples of shot 0 (rec_shot NULL) or
+ * of shots rec_shot[r].  From the next step on, traces[k][r] = phi^{m+k+1} at
+ * receiver r, where phi^m is the level when receivers were set. */
+tcm_status tcm_set_receivers(tcm_handle* h, const int32_t* rec_xyz, const int32_t* rec_shot,
+                             int32_t nrec);
+/* Number of recorded steps (*nsteps) and the traces ([nsteps][nrec] floats). */
+tcm_status tcm_read_traces(tcm_handle* h, float* out, int32_t out_is_device, int32_t* nsteps);
+
+/* Gradient dJ/dc of a receiver misfit J with dJ/dtraces = resid ([nt][nrec],
+ * host or device, rows for the first nt recorded steps) for the run made so
+ * far from level 0 with checkpoint_every > 0.  The forward is recomputed
+ * from checkpoints; the adjoint field mu = C2 lambda obeys the same update as
+ * the forward, with sources C2_r resid.  grad_c: nx*ny*nz floats (shot 0).
+ * TCM_E_STATE without checkpoints or if nt exceeds the recorded steps. */
+tcm_status tcm_adjoint(tcm_handle* h, const float* resid, int32_t nt, int32_t resid_is_device,
+                       float* grad_c, int32_t out_is_device);
+
+/* Return to level 0 (zero field, no active block, no sources, no traces);
+ * media, configuration and allocations are kept. */
+tcm_status tcm_reset(tcm_handle* h);
+
+tcm_status tcm_stats(tcm_handle* h, tcm_stats_t* out);
+
+void tcm_destroy(tcm_handle* h);
+
+/* Message of the last failed call on h, or of the last failed create on this
+ * thread when h is NULL.  Never NULL. */
+const char* tcm_last_error(const tcm_handle* h);
+
+/* Library version string. */
+const char* tcm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TCM_H */

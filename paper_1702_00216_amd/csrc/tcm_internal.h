@@ -1,0 +1,130 @@
+// Internal declarations shared by the HIP kernels and the host runtime of
+// libtcm.so.  Nothing here is part of the public C-ABI (include/tcm.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tcmk {
+
+// A block ("cell" of the paper) is 8^3 nodes.  Its pool slot holds three
+// planes of 512 floats, x fastest inside a plane: phi level 0, phi level 1
+// and C2 = (c dt / dx)^2.  Level (n & 1) holds phi^n; the other holds
+// phi^{n-1} and is overwritten by phi^{n+1} (two-array overwrite).
+constexpr int BE = 8;
+constexpr int BV = BE * BE * BE;
+constexpr int SLOT = 3 * BV;
+constexpr int C2_PLANE = 2 * BV;
+constexpr int EMPTY = -1;
+constexpr int CLAIMED = -2;
+constexpr int KEEP_BIT = 64;
+
+// Blocks are numbered per shot in 4x4x4 tiles: key = tile * 64 + local with
+// local = (lz * 4 + ly) * 4 + lx, tiles in x-fastest order.  One 64-bit word
+// of the activity bitmap covers one tile.  A shot owns the global key range
+// [key_base, key_base + 64 * ntiles); key_base is a multiple of 64.
+struct Shot {
+    int nx, ny, nz;
+    int bx, by, bz;          // blocks per axis
+    int tx, ty, tz;          // tiles per axis
+    int media_kind;
+    long long key_base;
+    long long word_base;     // key_base / 64
+    long long nwords;        // tx * ty * tz
+    const float* c;          // DENSE media (device, nx*ny*nz)
+    const int* z_top;        // LAYERED media (device)
+    const float* c_layer;
+    int nlayers;
+    int lx, ly, lz, log2s;   // LATTICE media
+    const double* lattice;
+};
+
+// Device-side counters.  step/n_act/free_top describe the state between
+// steps; n_new/n_ret are per-step scratch; emit tells the list writer
+// whether the step committed.
+struct DevState {
+    int step, n_act, n_new, n_ret;
+    int free_top, error, err_step, emit;
+    int peak_act, done_wgs, add_error, pad;
+    unsigned long long cells_cur;    // in-domain nodes of the current active list
+    unsigned long long updates;      // in-domain nodes stepped so far
+    unsigned long long activations, retirements;
+};
+
+struct Src {
+    long long key;     // global block key
+    int local;         // node inside the block, (z * 8 + y) * 8 + x
+    int t0, ns;        // first step and sample count
+    int pad;
+    long long w_off;   // offset of the samples in the sample array
+};
+
+struct Rec {
+    long long key;
+    int local, pad;
+};
+
+struct Tables {
+    DevState* st;
+    const Shot* shots;
+    int nshots;
+    int cap;                        // pool slots
+    float* pool;
+    int* cell2box;                  // per global key: slot, EMPTY or CLAIMED
+    unsigned long long* bitmap;     // next active set, one bit per global key
+    long long nwords;
+    int* act_slot;                  // active list (length n_act)
+    int* act_shot;
+    unsigned* act_key;              // key inside the shot
+    unsigned char* flags;           // per slot: face bits 0..5 and KEEP_BIT
+    int* pin_until;                 // per slot: active while step < pin_until (sources)
+    long long* slot_key;            // per slot: global key or -1
+    int* free_stack;                // free slots, top in DevState::free_top
+    long long* new_key;             // per step: claimed keys
+    int* new_shot;
+    int* ret_slot;                  // per step: released slots
+    unsigned* partial;              // per compaction workgroup: set-bit counts, then offsets
+    int ncount_wg;                  // compaction workgroups
+    const Src* src;
+    int nsrc;
+    const float* srcw;
+    const Rec* rec;
+    int nrec;
+    float* traces;                  // [trace_cap][nrec]
+    int trace_step0, trace_cap;
+    double dt, dx;
+    float trigger, retire;
+};
+
+constexpr int COUNT_WORDS_PER_THREAD = 8;
+constexpr int COUNT_THREADS = 256;
+constexpr int COUNT_WORDS_PER_WG = COUNT_WORDS_PER_THREAD * COUNT_THREADS;
+
+// ---- launch wrappers (tcm_kernels.hip) -----------------------------------
+hipError_t launch_init_tables(const Tables& t, long long nkeys, hipStream_t s);
+hipError_t launch_block_step(const Tables& t, int grid, hipStream_t s);
+hipError_t launch_plan(const Tables& t, int grid, hipStream_t s);
+hipError_t launch_pool_count(const Tables& t, int grid, hipStream_t s);
+hipError_t launch_emit(const Tables& t, hipStream_t s);
+hipError_t launch_activate(const Tables& t, long long key, int shot, unsigned local_key,
+                           int pin_until, hipStream_t s);
+hipError_t launch_read(const Tables& t, int shot, int which, int x0, int y0, int z0, int sx,
+                       int sy, int sz, float* out, hipStream_t s);
+hipError_t launch_media_c2(const Shot& shot, const Shot* dshot, double dt, double dx, float* c2,
+                           hipStream_t s);
+
+// dense engine (every node every step; the same arithmetic)
+struct DenseArgs {
+    int nx, ny, nz;
+    const float* cur;
+    float* nxt;                      // holds phi^{n-1} on entry, phi^{n+1} on exit
+    const float* c2;
+};
+hipError_t launch_dense_step(const DenseArgs& a, hipStream_t s);
+hipError_t launch_dense_inject(float* nxt, int n, const Src* src, int nsrc, const float* srcw,
+                               const Rec* rec, int nrec, float* traces, int trace_row,
+                               hipStream_t s);
+hipError_t launch_read_dense(const float* f, int nx, int ny, int x0, int y0, int z0, int sx, int sy,
+                             int sz, float* out, hipStream_t s);
+
+}  // namespace tcmk

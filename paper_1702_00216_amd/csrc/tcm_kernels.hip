@@ -1,0 +1,811 @@
+// HIP kernels of the Triggered Cells Method hot path for gfx950 (MI355X).
+//
+// One step n (phi^n -> phi^{n+1}) is four launches, all sized from device
+// counters so that a sequence of steps can be replayed as a hipGraph:
+//
+//   k_block_step  eq.(3) on every active 8^3 block: one 64-lane wave per block,
+//                 lane = (x, y) column with the 8 z values in registers, the six
+//                 neighbour face planes staged in LDS; additive source insertion;
+//                 wave-ballot face/keep predicates -> one flag byte per slot.
+//   k_plan        keep / release each active block, claim empty face neighbours
+//                 with a compare-and-swap on the block table, mark the next
+//                 active set in a bitmap; receivers are recorded here.
+//   k_pool_count  lock-free slot allocator (released slots are handed to new
+//                 blocks by rank, the rest pushed / popped on a free stack),
+//                 zero-fill + C2 of new blocks, popcount of the bitmap per
+//                 workgroup; the last workgroup scans the counts and commits the
+//                 step counters.
+//   k_emit        prefix-sum compaction of the bitmap into the next active list
+//                 (spatial tile order), clearing the bitmap for the next step.
+//
+// Arithmetic of the node update (eq.(3)), fixed for bit-exact comparisons:
+//   s = ((x+ + x-) + (y+ + y-)) + (z+ + z-);  lap = s - 6 phi;
+//   next = (2 phi - prev) + C2 lap;  compiled with -ffp-contract=off.
+#include "tcm_internal.h"
+
+namespace tcmk {
+
+// --------------------------------------------------------------------------
+// small helpers
+// --------------------------------------------------------------------------
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// Order LDS writes and reads of one wave (the wave runs in lockstep; this
+// only stops the compiler from moving LDS accesses across the point).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ void key_to_block(const Shot& S, unsigned key, int& bx, int& by,
+                                             int& bz) {
+    const unsigned tile = key >> 6, l = key & 63u;
+    const unsigned tx = tile % (unsigned)S.tx;
+    const unsigned r = tile / (unsigned)S.tx;
+    const unsigned ty = r % (unsigned)S.ty;
+    const unsigned tz = r / (unsigned)S.ty;
+    bx = (int)(tx * 4 + (l & 3u));
+    by = (int)(ty * 4 + ((l >> 2) & 3u));
+    bz = (int)(tz * 4 + (l >> 4));
+}
+
+__device__ __forceinline__ unsigned block_to_key(const Shot& S, int bx, int by, int bz) {
+    const unsigned tile = ((unsigned)(bz >> 2) * (unsigned)S.ty + (unsigned)(by >> 2)) *
+                              (unsigned)S.tx + (unsigned)(bx >> 2);
+    return tile * 64u + ((unsigned)(bz & 3) << 4) + ((unsigned)(by & 3) << 2) + (unsigned)(bx & 3);
+}
+
+// global key of the block across face d (0:-x 1:+x 2:-y 3:+y 4:-z 5:+z), or -1
+__device__ __forceinline__ long long neighbour_key(const Shot& S, int bx, int by, int bz, int d) {
+    int x = bx, y = by, z = bz;
+    switch (d) {
+        case 0: x--; break;
+        case 1: x++; break;
+        case 2: y--; break;
+        case 3: y++; break;
+        case 4: z--; break;
+        default: z++; break;
+    }
+    if (x < 0 || y < 0 || z < 0 || x >= S.bx || y >= S.by || z >= S.bz) return -1;
+    return S.key_base + (long long)block_to_key(S, x, y, z);
+}
+
+__device__ __forceinline__ int block_cells(const Shot& S, int bx, int by, int bz) {
+    const int ex = min(BE, S.nx - bx * BE), ey = min(BE, S.ny - by * BE), ez = min(BE, S.nz - bz * BE);
+    return ex * ey * ez;
+}
+
+// Append for every lane with pred; returns the lane's index or -1.
+// Must be reached by all lanes of the wave.
+__device__ __forceinline__ int wave_append(int* counter, bool pred) {
+    const unsigned long long m = __ballot(pred);
+    if (m == 0ull) return -1;
+    const int lane = lane_id();
+    const int leader = __ffsll((long long)m) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(counter, __popcll(m));
+    base = __shfl(base, leader);
+    const int rank = __popcll(m & ((1ull << lane) - 1ull));
+    return pred ? base + rank : -1;
+}
+
+// wave speed at global node (gx, gy, gz) of shot S ("Media": array or rules)
+__device__ float media_speed(const Shot& S, int gx, int gy, int gz) {
+    if (S.media_kind == 0) {
+        return S.c[(size_t)gx + (size_t)S.nx * ((size_t)gy + (size_t)S.ny * (size_t)gz)];
+    }
+    if (S.media_kind == 1) {
+        float v = S.c_layer[0];
+        for (int k = 1; k < S.nlayers; k++)
+            if (gz >= S.z_top[k]) v = S.c_layer[k];
+        return v;
+    }
+    // LATTICE: trilinear interpolation in FP64, x then y then z, one rounding
+    const int s = S.log2s;
+    const int ix = gx >> s, iy = gy >> s, iz = gz >> s;
+    const double inv = 1.0 / (double)(1 << s);
+    const double fx = (double)(gx - (ix << s)) * inv;
+    const double fy = (double)(gy - (iy << s)) * inv;
+    const double fz = (double)(gz - (iz << s)) * inv;
+    const double gx0 = 1.0 - fx, gy0 = 1.0 - fy, gz0 = 1.0 - fz;
+    const size_t LX = (size_t)S.lx, LXY = (size_t)S.lx * (size_t)S.ly;
+    double cy[2];
+    for (int h = 0; h < 2; h++) {
+        const double* L = S.lattice + (size_t)(iz + h) * LXY + (size_t)iy * LX + (size_t)ix;
+        const double cx0 = L[0] * gx0 + L[1] * fx;
+        const double cx1 = L[LX] * gx0 + L[LX + 1] * fx;
+        cy[h] = cx0 * gy0 + cx1 * fy;
+    }
+    return (float)(cy[0] * gz0 + cy[1] * fz);
+}
+
+__device__ __forceinline__ float coeff_c2(float c, double dt, double dx) {
+    const double t = (double)c * dt / dx;
+    return (float)(t * t);
+}
+
+// --------------------------------------------------------------------------
+// table initialisation
+// --------------------------------------------------------------------------
+__global__ void k_init_tables(Tables t, long long nkeys) {
+    const long long gs = (long long)gridDim.x * blockDim.x;
+    const long long g0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    for (long long i = g0; i < nkeys; i += gs) t.cell2box[i] = EMPTY;
+    for (long long i = g0; i < t.nwords; i += gs) t.bitmap[i] = 0ull;
+    for (long long i = g0; i < t.cap; i += gs) {
+        t.free_stack[i] = t.cap - 1 - (int)i;     // pops hand out slot 0 first
+        t.slot_key[i] = -1;
+        t.pin_until[i] = 0;
+        t.flags[i] = 0;
+    }
+    if (g0 == 0) {
+        DevState* st = t.st;
+        st->step = 0; st->n_act = 0; st->n_new = 0; st->n_ret = 0;
+        st->free_top = t.cap; st->error = 0; st->err_step = -1; st->emit = 0;
+        st->peak_act = 0; st->done_wgs = 0; st->add_error = 0; st->pad = 0;
+        st->cells_cur = 0; st->updates = 0; st->activations = 0; st->retirements = 0;
+    }
+}
+
+hipError_t launch_init_tables(const Tables& t, long long nkeys, hipStream_t s) {
+    long long n = nkeys > t.nwords ? nkeys : t.nwords;
+    if ((long long)t.cap > n) n = t.cap;
+    long long grid = (n + 255) / 256;
+    if (grid > 65536) grid = 65536;
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL(k_init_tables, dim3((unsigned)grid), dim3(256), 0, s, t, nkeys);
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// K1: block stencil + source insertion + face/keep ballots
+// --------------------------------------------------------------------------
+// LDS tile per wave: columns (xx, yy) in [0,10)^2 (node x = xx - 1,
+// y = yy - 1) of 8 z values each; interior 8x8 from the block, the four x/y
+// side faces from the neighbours, corners unused.
+constexpr int TILE_COLS = 10;
+constexpr int TILE_FLOATS = TILE_COLS * TILE_COLS * BE;
+
+__global__ __launch_bounds__(256) void k_block_step(Tables t) {
+    __shared__ __align__(16) float lds[4][TILE_FLOATS];
+    const DevState* st = t.st;
+    if (st->error) return;
+    const int n = st->step;
+    const int nact = st->n_act;
+    const int p = n & 1;
+    const int lane = lane_id();
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    float* T = lds[wid];
+    const int x = lane & 7, y = lane >> 3;
+    // face loaders: lane -> (a, zz) on a side face
+    const int a = lane & 7, zz = lane >> 3;
+
+    // XCD-aware split: workgroup b runs on XCD b % 8; each XCD walks its own
+    // contiguous eighth of the (spatially ordered) list so that neighbouring
+    // blocks share that XCD's L2.
+    const int per = gridDim.x >> 3;
+    const int xcd = blockIdx.x & 7, jw = blockIdx.x >> 3;
+    const int seg = (nact + 7) >> 3;
+    const int beg = xcd * seg;
+    const int end = min(nact, beg + seg);
+    const float trig = t.trigger, ret = t.retire;
+
+    for (int i = beg + jw * 4 + wid; i < end; i += per * 4) {
+        const int slot = __builtin_amdgcn_readfirstlane(t.act_slot[i]);
+        const int shot = __builtin_amdgcn_readfirstlane(t.act_shot[i]);
+        const unsigned key = (unsigned)__builtin_amdgcn_readfirstlane((int)t.act_key[i]);
+        const Shot& S = t.shots[shot];
+        int bx, by, bz;
+        key_to_block(S, key, bx, by, bz);
+        int nb[6];
+#pragma unroll
+        for (int d = 0; d < 6; d++) {
+            const long long k = neighbour_key(S, bx, by, bz, d);
+            nb[d] = k >= 0 ? __builtin_amdgcn_readfirstlane(t.cell2box[k]) : EMPTY;
+        }
+        const float* __restrict__ blk = t.pool + (size_t)slot * SLOT;
+        const float* __restrict__ cur_p = blk + p * BV;
+        float* __restrict__ out_p = (float*)blk + (1 - p) * BV;
+        const float* __restrict__ c2_p = blk + C2_PLANE;
+
+        float cur[8], prv[8], k2[8];
+#pragma unroll
+        for (int z = 0; z < 8; z++) {
+            cur[z] = cur_p[z * 64 + lane];
+            prv[z] = out_p[z * 64 + lane];
+            k2[z] = c2_p[z * 64 + lane];
+        }
+        float zlo = 0.f, zhi = 0.f, fmx = 0.f, fpx = 0.f, fmy = 0.f, fpy = 0.f;
+        if (nb[4] >= 0) zlo = t.pool[(size_t)nb[4] * SLOT + p * BV + 7 * 64 + lane];
+        if (nb[5] >= 0) zhi = t.pool[(size_t)nb[5] * SLOT + p * BV + 0 * 64 + lane];
+        if (nb[0] >= 0) fmx = t.pool[(size_t)nb[0] * SLOT + p * BV + zz * 64 + a * 8 + 7];
+        if (nb[1] >= 0) fpx = t.pool[(size_t)nb[1] * SLOT + p * BV + zz * 64 + a * 8 + 0];
+        if (nb[2] >= 0) fmy = t.pool[(size_t)nb[2] * SLOT + p * BV + zz * 64 + 7 * 8 + a];
+        if (nb[3] >= 0) fpy = t.pool[(size_t)nb[3] * SLOT + p * BV + zz * 64 + 0 * 8 + a];
+
+        wave_lds_sync();   // previous iteration's reads are done
+        {
+            float4* own = (float4*)(T + ((y + 1) * TILE_COLS + (x + 1)) * BE);
+            own[0] = make_float4(cur[0], cur[1], cur[2], cur[3]);
+            own[1] = make_float4(cur[4], cur[5], cur[6], cur[7]);
+            T[((a + 1) * TILE_COLS + 0) * BE + zz] = fmx;
+            T[((a + 1) * TILE_COLS + 9) * BE + zz] = fpx;
+            T[(0 * TILE_COLS + (a + 1)) * BE + zz] = fmy;
+            T[(9 * TILE_COLS + (a + 1)) * BE + zz] = fpy;
+        }
+        wave_lds_sync();
+        float xm[8], xp[8], ym[8], yp[8];
+        {
+            const float4* c_xm = (const float4*)(T + ((y + 1) * TILE_COLS + x) * BE);
+            const float4* c_xp = (const float4*)(T + ((y + 1) * TILE_COLS + x + 2) * BE);
+            const float4* c_ym = (const float4*)(T + (y * TILE_COLS + x + 1) * BE);
+            const float4* c_yp = (const float4*)(T + ((y + 2) * TILE_COLS + x + 1) * BE);
+            float4 v0 = c_xm[0], v1 = c_xm[1];
+            xm[0] = v0.x; xm[1] = v0.y; xm[2] = v0.z; xm[3] = v0.w;
+            xm[4] = v1.x; xm[5] = v1.y; xm[6] = v1.z; xm[7] = v1.w;
+            v0 = c_xp[0]; v1 = c_xp[1];
+            xp[0] = v0.x; xp[1] = v0.y; xp[2] = v0.z; xp[3] = v0.w;
+            xp[4] = v1.x; xp[5] = v1.y; xp[6] = v1.z; xp[7] = v1.w;
+            v0 = c_ym[0]; v1 = c_ym[1];
+            ym[0] = v0.x; ym[1] = v0.y; ym[2] = v0.z; ym[3] = v0.w;
+            ym[4] = v1.x; ym[5] = v1.y; ym[6] = v1.z; ym[7] = v1.w;
+            v0 = c_yp[0]; v1 = c_yp[1];
+            yp[0] = v0.x; yp[1] = v0.y; yp[2] = v0.z; yp[3] = v0.w;
+            yp[4] = v1.x; yp[5] = v1.y; yp[6] = v1.z; yp[7] = v1.w;
+        }
+        float nv[8];
+#pragma unroll
+        for (int z = 0; z < 8; z++) {
+            const float zd = z > 0 ? cur[z - 1] : zlo;
+            const float zu = z < 7 ? cur[z + 1] : zhi;
+            const float s = ((xp[z] + xm[z]) + (yp[z] + ym[z])) + (zu + zd);
+            const float lap = s - 6.0f * cur[z];
+            nv[z] = (2.0f * cur[z] - prv[z]) + k2[z] * lap;
+        }
+        // additive source insertion (before the predicates)
+        if (t.nsrc > 0 && t.pin_until[slot] > n) {
+            const long long G = S.key_base + (long long)key;
+            for (int s = 0; s < t.nsrc; s++) {
+                const Src e = t.src[s];
+                if (e.key != G) continue;
+                const int k = n - e.t0;
+                if (k < 0 || k >= e.ns) continue;
+                const float w = t.srcw[e.w_off + k];
+                if (lane == (e.local & 63)) {
+                    const int ez = e.local >> 6;
+#pragma unroll
+                    for (int z = 0; z < 8; z++)
+                        if (z == ez) nv[z] = nv[z] + w;
+                }
+            }
+        }
+#pragma unroll
+        for (int z = 0; z < 8; z++) out_p[z * 64 + lane] = nv[z];
+
+        bool keep = false, col = false;
+#pragma unroll
+        for (int z = 0; z < 8; z++) {
+            const float an = fabsf(nv[z]);
+            keep = keep || an > ret || fabsf(cur[z]) > ret;
+            col = col || an > trig;
+        }
+        const unsigned long long bk = __ballot(keep);
+        const unsigned long long bc = __ballot(col);
+        const unsigned long long bz0 = __ballot(fabsf(nv[0]) > trig);
+        const unsigned long long bz7 = __ballot(fabsf(nv[7]) > trig);
+        if (lane == 0) {
+            unsigned f = 0;
+            if (bc & 0x0101010101010101ull) f |= 1u;    // x = 0 column
+            if (bc & 0x8080808080808080ull) f |= 2u;    // x = 7
+            if (bc & 0x00000000000000FFull) f |= 4u;    // y = 0
+            if (bc & 0xFF00000000000000ull) f |= 8u;    // y = 7
+            if (bz0) f |= 16u;
+            if (bz7) f |= 32u;
+            if (bk) f |= (unsigned)KEEP_BIT;
+            t.flags[slot] = (unsigned char)f;
+        }
+    }
+}
+
+hipError_t launch_block_step(const Tables& t, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_block_step, dim3(grid), dim3(256), 0, s, t);
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// K2: keep / release / claim ("Updating active cells", items 1-4, 6)
+// --------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_plan(Tables t) {
+    DevState* st = t.st;
+    if (st->error) return;
+    const int n = st->step;
+    const int nact = st->n_act;
+    const int p = n & 1;
+    const int gsz = gridDim.x * blockDim.x;
+    const int g0 = blockIdx.x * blockDim.x + threadIdx.x;
+
+    // receivers: traces[n - trace_step0][r] = phi^{n+1}
+    const int row = n - t.trace_step0;
+    if (row >= 0 && row < t.trace_cap) {
+        for (int r = g0; r < t.nrec; r += gsz) {
+            const Rec e = t.rec[r];
+            const int s = t.cell2box[e.key];
+            t.traces[(size_t)row * t.nrec + r] =
+                s >= 0 ? t.pool[(size_t)s * SLOT + (1 - p) * BV + e.local] : 0.f;
+        }
+    }
+
+    for (int base = blockIdx.x * blockDim.x; base < nact; base += gsz) {
+        const int i = base + threadIdx.x;
+        const bool valid = i < nact;
+        int slot = 0, shot = 0;
+        unsigned key = 0, f = 0;
+        int bx = 0, by = 0, bz = 0;
+        bool survive = false;
+        if (valid) {
+            slot = t.act_slot[i];
+            shot = t.act_shot[i];
+            key = t.act_key[i];
+            f = t.flags[slot];
+            key_to_block(t.shots[shot], key, bx, by, bz);
+            survive = (f & KEEP_BIT) != 0 || t.pin_until[slot] > n + 1;
+        }
+        for (int d = 0; d < 6; d++) {
+            bool claim = false;
+            long long nk = -1;
+            if (valid) {
+                nk = neighbour_key(t.shots[shot], bx, by, bz, d);
+                if (nk >= 0) {
+                    const int s_nb = t.cell2box[nk];
+                    if (s_nb >= 0) {
+                        // an active neighbour whose face toward us is above trigger
+                        if ((t.flags[s_nb] >> (d ^ 1)) & 1u) survive = true;
+                    } else if (((f >> d) & 1u) && s_nb == EMPTY) {
+                        claim = atomicCAS(&t.cell2box[nk], EMPTY, CLAIMED) == EMPTY;
+                    }
+                }
+            }
+            const int k = wave_append(&st->n_new, claim);
+            if (claim) {
+                if (k < t.cap) {
+                    t.new_key[k] = nk;
+                    t.new_shot[k] = shot;
+                }
+                atomicOr(&t.bitmap[nk >> 6], 1ull << (nk & 63));
+            }
+        }
+        if (valid && survive) {
+            const long long G = t.shots[shot].key_base + (long long)key;
+            atomicOr(&t.bitmap[G >> 6], 1ull << (G & 63));
+        }
+        const int kr = wave_append(&st->n_ret, valid && !survive);
+        if (kr >= 0) t.ret_slot[kr] = slot;
+    }
+}
+
+hipError_t launch_plan(const Tables& t, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_plan, dim3(grid), dim3(256), 0, s, t);
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// K3a + K4: pool allocator and bitmap popcounts; the last workgroup scans the
+// counts and commits the step ("Boxes": vacant boxes are reused).
+// --------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_pool_count(Tables t) {
+    DevState* st = t.st;
+    __shared__ unsigned red[256 / 64];
+    __shared__ int last;
+    const int lane = lane_id();
+    const int wid = threadIdx.x >> 6;
+    const int err0 = st->error;
+    const int nn = st->n_new, nr = st->n_ret, top = st->free_top;
+
+    if (!err0) {
+        if (nn > top + nr) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) {
+                st->err_step = st->step;
+                st->error = -3;   // TCM_E_POOL
+            }
+        } else {
+            // released blocks (thread per entry)
+            const int gsz = gridDim.x * blockDim.x;
+            for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < nr; r += gsz) {
+                const int slot = t.ret_slot[r];
+                t.cell2box[t.slot_key[slot]] = EMPTY;
+                if (r >= nn) {               // not handed to a new block: push
+                    t.free_stack[top + (r - nn)] = slot;
+                    t.slot_key[slot] = -1;
+                }
+            }
+            // new blocks (wave per entry): slot, zero phi levels, C2 from media
+            const int nwaves = gridDim.x * (blockDim.x >> 6);
+            for (int k = blockIdx.x * (blockDim.x >> 6) + wid; k < nn; k += nwaves) {
+                const int slot = k < nr ? t.ret_slot[k] : t.free_stack[top - 1 - (k - nr)];
+                const long long G = t.new_key[k];
+                const int shot = t.new_shot[k];
+                const Shot& S = t.shots[shot];
+                int bx, by, bz;
+                key_to_block(S, (unsigned)(G - S.key_base), bx, by, bz);
+                float* blk = t.pool + (size_t)slot * SLOT;
+                const int x = lane & 7, y = lane >> 3;
+#pragma unroll
+                for (int z = 0; z < 8; z++) {
+                    blk[z * 64 + lane] = 0.f;
+                    blk[BV + z * 64 + lane] = 0.f;
+                    const int gx = bx * BE + x, gy = by * BE + y, gz = bz * BE + z;
+                    float c2 = 0.f;   // nodes outside the domain keep C2 = 0 and stay zero
+                    if (gx < S.nx && gy < S.ny && gz < S.nz)
+                        c2 = coeff_c2(media_speed(S, gx, gy, gz), t.dt, t.dx);
+                    blk[C2_PLANE + z * 64 + lane] = c2;
+                }
+                if (lane == 0) {
+                    t.cell2box[G] = slot;
+                    t.slot_key[slot] = G;
+                    t.pin_until[slot] = 0;
+                }
+            }
+        }
+    }
+
+    // popcount of this workgroup's range of bitmap words
+    unsigned cnt = 0;
+    if (blockIdx.x < t.ncount_wg) {
+        const long long w0 = ((long long)blockIdx.x * COUNT_THREADS + threadIdx.x) * COUNT_WORDS_PER_THREAD;
+#pragma unroll
+        for (int j = 0; j < COUNT_WORDS_PER_THREAD; j++) {
+            const long long w = w0 + j;
+            if (w < t.nwords) cnt += (unsigned)__popcll(t.bitmap[w]);
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o);
+    if (lane == 0) red[wid] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (blockIdx.x < t.ncount_wg) t.partial[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+        __threadfence();
+        last = atomicAdd(&st->done_wgs, 1) == (int)gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+
+    // last workgroup: exclusive scan of the partial counts, commit counters
+    __shared__ unsigned carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int b = 0; b < t.ncount_wg; b += 256) {
+        const int idx = b + threadIdx.x;
+        unsigned v = idx < t.ncount_wg ? __atomic_load_n(&t.partial[idx], __ATOMIC_RELAXED) : 0u;
+        // inclusive wave scan
+        unsigned incl = v;
+        for (int o = 1; o < 64; o <<= 1) {
+            const unsigned u = __shfl_up(incl, o);
+            if (lane >= o) incl += u;
+        }
+        if (lane == 63) red[wid] = incl;
+        __syncthreads();
+        unsigned wofs = 0;
+        for (int w = 0; w < wid; w++) wofs += red[w];
+        const unsigned tot = red[0] + red[1] + red[2] + red[3];
+        if (idx < t.ncount_wg) t.partial[idx] = carry + wofs + incl - v;
+        __syncthreads();
+        if (threadIdx.x == 0) carry += tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const int err = st->error;
+        if (!err || st->err_step == st->step) {   // the step's phi^{n+1} is complete
+            st->updates += st->cells_cur;
+            st->step += 1;
+        }
+        if (!err) {
+            st->free_top = top + nr - nn;
+            st->activations += (unsigned long long)nn;
+            st->retirements += (unsigned long long)nr;
+            st->n_act = (int)carry;
+            if ((int)carry > st->peak_act) st->peak_act = (int)carry;
+            st->cells_cur = 0;
+            st->emit = 1;
+        } else {
+            st->emit = 0;
+        }
+        st->n_new = 0;
+        st->n_ret = 0;
+        st->done_wgs = 0;
+        __threadfence();
+    }
+}
+
+hipError_t launch_pool_count(const Tables& t, int grid, hipStream_t s) {
+    if (grid < t.ncount_wg) grid = t.ncount_wg;
+    hipLaunchKernelGGL(k_pool_count, dim3(grid), dim3(256), 0, s, t);
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// K3b: compaction of the bitmap into the next active list
+// --------------------------------------------------------------------------
+__device__ __forceinline__ int shot_of_word(const Tables& t, long long w) {
+    int lo = 0, hi = t.nshots - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (t.shots[mid].word_base <= w) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(256) void k_emit(Tables t) {
+    DevState* st = t.st;
+    __shared__ unsigned wsum[4];
+    __shared__ unsigned long long csum[4];
+    const int lane = lane_id();
+    const int wid = threadIdx.x >> 6;
+    const int emit = st->emit;
+    const long long w0 = ((long long)blockIdx.x * COUNT_THREADS + threadIdx.x) * COUNT_WORDS_PER_THREAD;
+    unsigned long long words[COUNT_WORDS_PER_THREAD];
+    unsigned cnt = 0;
+#pragma unroll
+    for (int j = 0; j < COUNT_WORDS_PER_THREAD; j++) {
+        const long long w = w0 + j;
+        words[j] = w < t.nwords ? t.bitmap[w] : 0ull;
+        cnt += (unsigned)__popcll(words[j]);
+    }
+    if (!emit) {
+        // the step failed: undo claims, keep the current list
+#pragma unroll
+        for (int j = 0; j < COUNT_WORDS_PER_THREAD; j++) {
+            unsigned long long m = words[j];
+            if (!m) continue;
+            const long long w = w0 + j;
+            while (m) {
+                const int b = __ffsll((long long)m) - 1;
+                m &= m - 1;
+                const long long G = w * 64 + b;
+                if (t.cell2box[G] == CLAIMED) t.cell2box[G] = EMPTY;
+            }
+            t.bitmap[w] = 0ull;
+        }
+        return;
+    }
+    // exclusive prefix of cnt over the workgroup
+    unsigned incl = cnt;
+    for (int o = 1; o < 64; o <<= 1) {
+        const unsigned u = __shfl_up(incl, o);
+        if (lane >= o) incl += u;
+    }
+    if (lane == 63) wsum[wid] = incl;
+    __syncthreads();
+    unsigned off = t.partial[blockIdx.x] + incl - cnt;
+    for (int w = 0; w < wid; w++) off += wsum[w];
+    unsigned long long cells = 0;
+#pragma unroll
+    for (int j = 0; j < COUNT_WORDS_PER_THREAD; j++) {
+        unsigned long long m = words[j];
+        if (!m) continue;
+        const long long w = w0 + j;
+        const int shot = shot_of_word(t, w);
+        const Shot& S = t.shots[shot];
+        while (m) {
+            const int b = __ffsll((long long)m) - 1;
+            m &= m - 1;
+            const long long G = w * 64 + b;
+            const unsigned key = (unsigned)(G - S.key_base);
+            t.act_slot[off] = t.cell2box[G];
+            t.act_shot[off] = shot;
+            t.act_key[off] = key;
+            off++;
+            int bx, by, bz;
+            key_to_block(S, key, bx, by, bz);
+            cells += (unsigned long long)block_cells(S, bx, by, bz);
+        }
+        t.bitmap[w] = 0ull;
+    }
+    for (int o = 32; o > 0; o >>= 1) cells += __shfl_xor(cells, o);
+    if (lane == 0) csum[wid] = cells;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned long long c = csum[0] + csum[1] + csum[2] + csum[3];
+        if (c) atomicAdd(&st->cells_cur, c);
+    }
+}
+
+hipError_t launch_emit(const Tables& t, hipStream_t s) {
+    hipLaunchKernelGGL(k_emit, dim3(t.ncount_wg), dim3(256), 0, s, t);
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// source activation (one wave): box the block of a new source by hand
+// --------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_activate(Tables t, long long G, int shot, unsigned key,
+                                                 int pin) {
+    DevState* st = t.st;
+    const int lane = lane_id();
+    const int cur = t.cell2box[G];
+    if (cur >= 0) {
+        if (lane == 0 && t.pin_until[cur] < pin) t.pin_until[cur] = pin;
+        return;
+    }
+    const int top = st->free_top;
+    if (top <= 0) {
+        if (lane == 0) st->add_error = -3;
+        return;
+    }
+    const int slot = t.free_stack[top - 1];
+    const Shot& S = t.shots[shot];
+    int bx, by, bz;
+    key_to_block(S, key, bx, by, bz);
+    float* blk = t.pool + (size_t)slot * SLOT;
+    const int x = lane & 7, y = lane >> 3;
+    for (int z = 0; z < 8; z++) {
+        blk[z * 64 + lane] = 0.f;
+        blk[BV + z * 64 + lane] = 0.f;
+        const int gx = bx * BE + x, gy = by * BE + y, gz = bz * BE + z;
+        float c2 = 0.f;
+        if (gx < S.nx && gy < S.ny && gz < S.nz) c2 = coeff_c2(media_speed(S, gx, gy, gz), t.dt, t.dx);
+        blk[C2_PLANE + z * 64 + lane] = c2;
+    }
+    if (lane == 0) {
+        st->free_top = top - 1;
+        t.cell2box[G] = slot;
+        t.slot_key[slot] = G;
+        t.pin_until[slot] = pin;
+        const int i = st->n_act;
+        t.act_slot[i] = slot;
+        t.act_shot[i] = shot;
+        t.act_key[i] = key;
+        st->n_act = i + 1;
+        if (i + 1 > st->peak_act) st->peak_act = i + 1;
+        st->cells_cur += (unsigned long long)block_cells(S, bx, by, bz);
+        st->activations += 1ull;
+    }
+}
+
+hipError_t launch_activate(const Tables& t, long long key, int shot, unsigned local_key, int pin,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(k_activate, dim3(1), dim3(64), 0, s, t, key, shot, local_key, pin);
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// read: gather a box of phi^n / phi^{n-1} (inactive nodes -> 0)
+// --------------------------------------------------------------------------
+__global__ void k_read(Tables t, int shot, int which, int x0, int y0, int z0, int sx, int sy,
+                       int sz, float* out) {
+    const long long total = (long long)sx * sy * sz;
+    const long long gs = (long long)gridDim.x * blockDim.x;
+    const int plane = which == 0 ? (t.st->step & 1) : 1 - (t.st->step & 1);
+    const Shot& S = t.shots[shot];
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gs) {
+        const int lx = (int)(i % sx);
+        const long long r = i / sx;
+        const int ly = (int)(r % sy), lz = (int)(r / sy);
+        const int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
+        const int bx = gx >> 3, by = gy >> 3, bz = gz >> 3;
+        const long long G = S.key_base + (long long)block_to_key(S, bx, by, bz);
+        const int s = t.cell2box[G];
+        out[i] = s >= 0 ? t.pool[(size_t)s * SLOT + plane * BV + ((gz & 7) * 8 + (gy & 7)) * 8 + (gx & 7)]
+                        : 0.f;
+    }
+}
+
+hipError_t launch_read(const Tables& t, int shot, int which, int x0, int y0, int z0, int sx, int sy,
+                       int sz, float* out, hipStream_t s) {
+    const long long total = (long long)sx * sy * sz;
+    long long grid = (total + 255) / 256;
+    if (grid > 16384) grid = 16384;
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL(k_read, dim3((unsigned)grid), dim3(256), 0, s, t, shot, which, x0, y0, z0,
+                       sx, sy, sz, out);
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// dense engine: eq.(3) on every node (the same arithmetic, no activation)
+// --------------------------------------------------------------------------
+__global__ void k_media_c2(const Shot* dshot, double dt, double dx, float* c2) {
+    const Shot& S = *dshot;
+    const long long total = (long long)S.nx * S.ny * S.nz;
+    const long long gs = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gs) {
+        const int gx = (int)(i % S.nx);
+        const long long r = i / S.nx;
+        const int gy = (int)(r % S.ny), gz = (int)(r / S.ny);
+        c2[i] = coeff_c2(media_speed(S, gx, gy, gz), dt, dx);
+    }
+}
+
+hipError_t launch_media_c2(const Shot& shot, const Shot* dshot, double dt, double dx, float* c2,
+                           hipStream_t s) {
+    const long long total = (long long)shot.nx * shot.ny * shot.nz;
+    long long grid = (total + 255) / 256;
+    if (grid > 65536) grid = 65536;
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL(k_media_c2, dim3((unsigned)grid), dim3(256), 0, s, dshot, dt, dx, c2);
+    return hipGetLastError();
+}
+
+// 2.5-D z-marching: a 64 x 4 workgroup owns an (x, y) tile and walks DZ
+// planes, keeping z-1, z, z+1 of its column in registers; x/y neighbours come
+// through the L1/L2 caches.
+constexpr int DENSE_TX = 64, DENSE_TY = 4, DENSE_DZ = 32;
+
+__global__ __launch_bounds__(256) void k_dense_step(DenseArgs a) {
+    const int x = blockIdx.x * DENSE_TX + (threadIdx.x & 63);
+    const int y = blockIdx.y * DENSE_TY + (threadIdx.x >> 6);
+    const int z0 = blockIdx.z * DENSE_DZ;
+    if (x >= a.nx || y >= a.ny) return;
+    const size_t sy = (size_t)a.nx, sz = (size_t)a.nx * a.ny;
+    const int z1 = min(a.nz, z0 + DENSE_DZ);
+    size_t i = (size_t)z0 * sz + (size_t)y * sy + (size_t)x;
+    float zm = z0 > 0 ? a.cur[i - sz] : 0.f;
+    float c = a.cur[i];
+    for (int z = z0; z < z1; z++, i += sz) {
+        const float zp = z + 1 < a.nz ? a.cur[i + sz] : 0.f;
+        const float xm = x > 0 ? a.cur[i - 1] : 0.f;
+        const float xp = x + 1 < a.nx ? a.cur[i + 1] : 0.f;
+        const float ym = y > 0 ? a.cur[i - sy] : 0.f;
+        const float yp = y + 1 < a.ny ? a.cur[i + sy] : 0.f;
+        const float s = ((xp + xm) + (yp + ym)) + (zp + zm);
+        const float lap = s - 6.0f * c;
+        a.nxt[i] = (2.0f * c - a.nxt[i]) + a.c2[i] * lap;
+        zm = c;
+        c = zp;
+    }
+}
+
+hipError_t launch_dense_step(const DenseArgs& a, hipStream_t s) {
+    dim3 grid((a.nx + DENSE_TX - 1) / DENSE_TX, (a.ny + DENSE_TY - 1) / DENSE_TY,
+              (a.nz + DENSE_DZ - 1) / DENSE_DZ);
+    hipLaunchKernelGGL(k_dense_step, grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+// sources (in table order) then receivers, single thread: a handful of nodes.
+// Src::key / Rec::key hold linear node indices here.
+__global__ void k_dense_inject(float* nxt, int n, const Src* src, int nsrc, const float* srcw,
+                               const Rec* rec, int nrec, float* traces, int trace_row) {
+    if (threadIdx.x != 0) return;
+    for (int s = 0; s < nsrc; s++) {
+        const int k = n - src[s].t0;
+        if (k >= 0 && k < src[s].ns) nxt[src[s].key] = nxt[src[s].key] + srcw[src[s].w_off + k];
+    }
+    if (trace_row >= 0)
+        for (int r = 0; r < nrec; r++) traces[(size_t)trace_row * nrec + r] = nxt[rec[r].key];
+}
+
+hipError_t launch_dense_inject(float* nxt, int n, const Src* src, int nsrc, const float* srcw,
+                               const Rec* rec, int nrec, float* traces, int trace_row,
+                               hipStream_t s) {
+    hipLaunchKernelGGL(k_dense_inject, dim3(1), dim3(64), 0, s, nxt, n, src, nsrc, srcw, rec, nrec,
+                       traces, trace_row);
+    return hipGetLastError();
+}
+
+// box copy out of a dense level
+__global__ void k_read_dense(const float* f, int nx, int ny, int x0, int y0, int z0, int sx, int sy,
+                             int sz, float* out) {
+    const long long total = (long long)sx * sy * sz;
+    const long long gs = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gs) {
+        const int lx = (int)(i % sx);
+        const long long r = i / sx;
+        const int ly = (int)(r % sy), lz = (int)(r / sy);
+        out[i] = f[(size_t)(x0 + lx) + (size_t)nx * ((size_t)(y0 + ly) + (size_t)ny * (size_t)(z0 + lz))];
+    }
+}
+
+hipError_t launch_read_dense(const float* f, int nx, int ny, int x0, int y0, int z0, int sx, int sy,
+                             int sz, float* out, hipStream_t s) {
+    const long long total = (long long)sx * sy * sz;
+    long long grid = (total + 255) / 256;
+    if (grid > 16384) grid = 16384;
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL(k_read_dense, dim3((unsigned)grid), dim3(256), 0, s, f, nx, ny, x0, y0, z0,
+                       sx, sy, sz, out);
+    return hipGetLastError();
+}
+
+}  // namespace tcmk

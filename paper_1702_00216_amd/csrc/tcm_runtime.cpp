@@ -1,0 +1,866 @@
+// Host runtime of libtcm.so: the C-ABI of include/tcm.h over the HIP kernels
+// in tcm_kernels.hip.  It validates the problem (eq.(4), media, thresholds),
+// lays out device memory, issues each step's launches on the handle's stream
+// (replayed as hipGraphs of several steps), and reports device-side errors
+// at synchronisation points.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cfloat>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "tcm.h"
+#include "tcm_internal.h"
+
+using namespace tcmk;
+
+namespace {
+
+thread_local std::string g_create_error;
+constexpr size_t SLOT_BYTES = sizeof(float) * SLOT;
+
+std::string fmt(const char* f, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, f);
+    vsnprintf(buf, sizeof buf, f, ap);
+    va_end(ap);
+    return buf;
+}
+
+struct ShotHost {
+    int nx, ny, nz;
+    int media_kind;
+    double cmax;
+};
+
+}  // namespace
+
+struct tcm_handle {
+    tcm_config cfg{};
+    int engine = TCM_ENGINE_BLOCKS;
+    int device = 0;
+    int ncu = 256;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::vector<void*> allocs;          // device memory owned by the handle
+    std::string err;
+    bool poisoned = false;
+
+    std::vector<ShotHost> hshots;
+    std::vector<Shot> shots;            // host copies holding device pointers
+    Shot* d_shots = nullptr;
+    Tables t{};
+    long long nkeys = 0;
+    size_t table_bytes = 0;
+
+    int grid_step = 0, grid_plan = 0, grid_pool = 0;
+
+    // sources / receivers (host mirrors)
+    std::vector<Src> h_src;
+    std::vector<float> h_srcw;
+    Src* d_src = nullptr;
+    size_t d_src_cap = 0;
+    float* d_srcw = nullptr;
+    size_t d_srcw_cap = 0;
+    std::vector<Rec> h_rec;
+    Rec* d_rec = nullptr;
+    float* d_traces = nullptr;
+
+    // graph replay
+    hipGraphExec_t gexec = nullptr;
+    int gsteps = 0;
+    bool graph_failed = false;
+
+    // timing (TCM_FLAG_TIMING)
+    std::vector<hipEvent_t> events;
+    double stencil_ms = 0.0;
+    long long stencil_launches = 0, stencil_cells = 0;
+
+    // dense engine
+    float* d_phi[2] = {nullptr, nullptr};
+    float* d_c2 = nullptr;
+    long long dense_step = 0;
+
+    // scratch for host reads
+    float* d_scratch = nullptr;
+    size_t scratch_bytes = 0;
+
+    DevState* h_state = nullptr;        // pinned mirror of the device counters
+};
+
+namespace {
+
+tcm_status set_err(tcm_handle* h, tcm_status s, const std::string& m) {
+    if (h) h->err = m; else g_create_error = m;
+    return s;
+}
+
+tcm_status dev_fail(tcm_handle* h, hipError_t e, const char* what) {
+    std::string m = fmt("HIP error in %s: %s", what, hipGetErrorString(e));
+    if (h) {
+        h->poisoned = true;
+        h->err = m;
+    } else {
+        g_create_error = m;
+    }
+    return TCM_E_DEVICE;
+}
+
+#define HIP_OR_FAIL(h, expr)                                  \
+    do {                                                      \
+        hipError_t e__ = (expr);                              \
+        if (e__ != hipSuccess) return dev_fail((h), e__, #expr); \
+    } while (0)
+
+template <class T>
+hipError_t dalloc(tcm_handle* h, T** p, size_t count) {
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T));
+    if (e == hipSuccess) {
+        h->allocs.push_back(q);
+        *p = (T*)q;
+    }
+    return e;
+}
+
+void dfree(tcm_handle* h, void* p) {
+    if (!p) return;
+    auto it = std::find(h->allocs.begin(), h->allocs.end(), p);
+    if (it != h->allocs.end()) h->allocs.erase(it);
+    (void)hipFree(p);
+}
+
+void drop_graph(tcm_handle* h) {
+    if (h->gexec) {
+        (void)hipGraphExecDestroy(h->gexec);
+        h->gexec = nullptr;
+    }
+}
+
+tcm_status check_live(tcm_handle* h) {
+    if (!h) return TCM_E_ARG;
+    if (h->poisoned) return set_err(h, TCM_E_DEVICE, "handle is poisoned by an earlier device error");
+    if (hipSetDevice(h->device) != hipSuccess) return dev_fail(h, hipGetLastError(), "hipSetDevice");
+    return TCM_OK;
+}
+
+// ---- media validation (host) ---------------------------------------------
+tcm_status validate_media(const tcm_media* m, int nx, int ny, int nz, double* cmax, std::string* why) {
+    if (!m) { *why = "media is NULL"; return TCM_E_ARG; }
+    double mx = 0.0;
+    if (m->kind == TCM_MEDIA_DENSE) {
+        if (!m->c) { *why = "dense media without an array"; return TCM_E_ARG; }
+        const size_t N = (size_t)nx * ny * nz;
+        for (size_t i = 0; i < N; i++) {
+            const float v = m->c[i];
+            if (!std::isfinite(v) || v < 0.f) { *why = fmt("wave speed %g at node %zu is negative or not finite", v, i); return TCM_E_ARG; }
+            if (v > mx) mx = v;
+        }
+    } else if (m->kind == TCM_MEDIA_LAYERED) {
+        if (m->nlayers < 1 || !m->z_top || !m->c_layer || m->z_top[0] != 0) { *why = "layered media needs nlayers >= 1 and z_top[0] == 0"; return TCM_E_ARG; }
+        for (int k = 0; k < m->nlayers; k++) {
+            if (k > 0 && m->z_top[k] <= m->z_top[k - 1]) { *why = "layer tops must ascend"; return TCM_E_ARG; }
+            const float v = m->c_layer[k];
+            if (!std::isfinite(v) || v < 0.f) { *why = "layer speed negative or not finite"; return TCM_E_ARG; }
+            if (v > mx) mx = v;
+        }
+    } else if (m->kind == TCM_MEDIA_LATTICE) {
+        if (!m->lattice || m->log2_spacing < 0 || m->log2_spacing > 20) { *why = "lattice media needs values and 0 <= log2_spacing <= 20"; return TCM_E_ARG; }
+        const int s = m->log2_spacing;
+        if (m->lx < ((nx - 1) >> s) + 2 || m->ly < ((ny - 1) >> s) + 2 || m->lz < ((nz - 1) >> s) + 2) {
+            *why = "lattice too small for the grid"; return TCM_E_ARG;
+        }
+        const size_t L = (size_t)m->lx * m->ly * m->lz;
+        for (size_t i = 0; i < L; i++) {
+            const double v = m->lattice[i];
+            if (!std::isfinite(v) || v < 0.0) { *why = "lattice speed negative or not finite"; return TCM_E_ARG; }
+            if (v > mx) mx = v;
+        }
+        mx *= 1.0 + 1e-12;   // trilinear rounding can exceed the largest node by an ulp
+    } else {
+        *why = "unknown media kind";
+        return TCM_E_ARG;
+    }
+    *cmax = mx;
+    return TCM_OK;
+}
+
+tcm_status upload_media(tcm_handle* h, const tcm_media* m, Shot& S) {
+    S.media_kind = m->kind;
+    S.c = nullptr; S.z_top = nullptr; S.c_layer = nullptr; S.lattice = nullptr;
+    S.nlayers = 0; S.lx = S.ly = S.lz = S.log2s = 0;
+    if (m->kind == TCM_MEDIA_DENSE) {
+        const size_t N = (size_t)S.nx * S.ny * S.nz;
+        float* d = nullptr;
+        HIP_OR_FAIL(h, dalloc(h, &d, N));
+        HIP_OR_FAIL(h, hipMemcpy(d, m->c, N * sizeof(float), hipMemcpyHostToDevice));
+        S.c = d;
+        h->table_bytes += N * sizeof(float);
+    } else if (m->kind == TCM_MEDIA_LAYERED) {
+        int* zt = nullptr;
+        float* cl = nullptr;
+        HIP_OR_FAIL(h, dalloc(h, &zt, m->nlayers));
+        HIP_OR_FAIL(h, dalloc(h, &cl, m->nlayers));
+        HIP_OR_FAIL(h, hipMemcpy(zt, m->z_top, m->nlayers * sizeof(int), hipMemcpyHostToDevice));
+        HIP_OR_FAIL(h, hipMemcpy(cl, m->c_layer, m->nlayers * sizeof(float), hipMemcpyHostToDevice));
+        S.z_top = zt; S.c_layer = cl; S.nlayers = m->nlayers;
+    } else {
+        const size_t L = (size_t)m->lx * m->ly * m->lz;
+        double* d = nullptr;
+        HIP_OR_FAIL(h, dalloc(h, &d, L));
+        HIP_OR_FAIL(h, hipMemcpy(d, m->lattice, L * sizeof(double), hipMemcpyHostToDevice));
+        S.lattice = d; S.lx = m->lx; S.ly = m->ly; S.lz = m->lz; S.log2s = m->log2_spacing;
+        h->table_bytes += L * sizeof(double);
+    }
+    return TCM_OK;
+}
+
+tcm_status sync_state(tcm_handle* h) {
+    HIP_OR_FAIL(h, hipMemcpyAsync(h->h_state, h->t.st, sizeof(DevState), hipMemcpyDeviceToHost, h->stream));
+    HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+    return TCM_OK;
+}
+
+void destroy_all(tcm_handle* h) {
+    if (!h) return;
+    (void)hipSetDevice(h->device);
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    drop_graph(h);
+    for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
+    h->events.clear();
+    for (void* p : h->allocs) (void)hipFree(p);
+    h->allocs.clear();
+    if (h->h_state) (void)hipHostFree(h->h_state);
+    if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+    delete h;
+}
+
+tcm_status create_common(const tcm_config* cfg, const tcm_shot* shots, int nshots, tcm_handle** out) {
+    if (!out) return set_err(nullptr, TCM_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (!cfg) return set_err(nullptr, TCM_E_ARG, "config is NULL");
+    if (nshots < 1 || !shots) return set_err(nullptr, TCM_E_ARG, "need at least one shot");
+    if (!(cfg->dx > 0.0) || !std::isfinite(cfg->dx) || !(cfg->dt >= 0.0) || !std::isfinite(cfg->dt))
+        return set_err(nullptr, TCM_E_ARG, "dx must be > 0 and dt >= 0, both finite");
+    if (!(cfg->trigger >= 0.f) || !(cfg->retire >= 0.f) || !std::isfinite(cfg->trigger) ||
+        !std::isfinite(cfg->retire) || cfg->retire > cfg->trigger)
+        return set_err(nullptr, TCM_E_ARG, "thresholds must satisfy 0 <= retire <= trigger (finite)");
+    if (cfg->engine != TCM_ENGINE_BLOCKS && cfg->engine != TCM_ENGINE_DENSE)
+        return set_err(nullptr, TCM_E_ARG, "unknown engine");
+    if (cfg->engine == TCM_ENGINE_DENSE && nshots != 1)
+        return set_err(nullptr, TCM_E_ARG, "the dense engine runs one shot");
+
+    std::vector<ShotHost> hs(nshots);
+    for (int s = 0; s < nshots; s++) {
+        const tcm_shot& sh = shots[s];
+        if (sh.nx <= 0 || sh.ny <= 0 || sh.nz <= 0 || sh.nx > (1 << 20) || sh.ny > (1 << 20) || sh.nz > (1 << 20))
+            return set_err(nullptr, TCM_E_ARG, fmt("shot %d: grid edges must be in [1, 2^20]", s));
+        std::string why;
+        double cmax = 0.0;
+        tcm_status st = validate_media(&sh.media, sh.nx, sh.ny, sh.nz, &cmax, &why);
+        if (st != TCM_OK) return set_err(nullptr, st, fmt("shot %d: %s", s, why.c_str()));
+        const double r = cmax * cfg->dt / cfg->dx;
+        if (r * r * 3.0 > 1.0 + 4.0 * DBL_EPSILON)
+            return set_err(nullptr, TCM_E_CFL, fmt("shot %d: eq.(4) violated: cmax dt / dx = %.9g > 1/sqrt(3)", s, r));
+        hs[s] = ShotHost{sh.nx, sh.ny, sh.nz, sh.media.kind, cmax};
+    }
+
+    tcm_handle* h = new tcm_handle();
+    h->cfg = *cfg;
+    h->engine = cfg->engine;
+    h->hshots = hs;
+    if (hipGetDevice(&h->device) != hipSuccess) { delete h; return set_err(nullptr, TCM_E_DEVICE, "no HIP device"); }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, h->device) != hipSuccess) { delete h; return set_err(nullptr, TCM_E_DEVICE, "hipGetDeviceProperties failed"); }
+    h->ncu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    if (cfg->stream) {
+        h->stream = (hipStream_t)cfg->stream;
+    } else {
+        if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess) { delete h; return set_err(nullptr, TCM_E_DEVICE, "hipStreamCreate failed"); }
+        h->own_stream = true;
+    }
+    if (hipHostMalloc((void**)&h->h_state, sizeof(DevState), hipHostMallocDefault) != hipSuccess) {
+        destroy_all(h);
+        return set_err(nullptr, TCM_E_NOMEM, "pinned host allocation failed");
+    }
+
+    auto fail = [&](tcm_status st) {
+        std::string m = h->err.empty() ? g_create_error : h->err;
+        destroy_all(h);
+        return set_err(nullptr, st, m);
+    };
+
+    // ---- shots, key ranges ----
+    long long word_base = 0;
+    h->shots.resize(nshots);
+    for (int s = 0; s < nshots; s++) {
+        Shot S{};
+        S.nx = hs[s].nx; S.ny = hs[s].ny; S.nz = hs[s].nz;
+        S.bx = (S.nx + BE - 1) / BE; S.by = (S.ny + BE - 1) / BE; S.bz = (S.nz + BE - 1) / BE;
+        S.tx = (S.bx + 3) / 4; S.ty = (S.by + 3) / 4; S.tz = (S.bz + 3) / 4;
+        S.word_base = word_base;
+        S.key_base = word_base * 64;
+        S.nwords = (long long)S.tx * S.ty * S.tz;
+        word_base += S.nwords;
+        tcm_status st = upload_media(h, &shots[s].media, S);
+        if (st != TCM_OK) return fail(st);
+        h->shots[s] = S;
+    }
+    if (hipMalloc((void**)&h->d_shots, sizeof(Shot) * nshots) != hipSuccess) return fail(dev_fail(h, hipErrorOutOfMemory, "hipMalloc(shots)"));
+    h->allocs.push_back(h->d_shots);
+    if (hipMemcpy(h->d_shots, h->shots.data(), sizeof(Shot) * nshots, hipMemcpyHostToDevice) != hipSuccess)
+        return fail(dev_fail(h, hipGetLastError(), "hipMemcpy(shots)"));
+
+    Tables& t = h->t;
+    t.shots = h->d_shots;
+    t.nshots = nshots;
+    t.dt = cfg->dt;
+    t.dx = cfg->dx;
+    t.trigger = cfg->trigger;
+    t.retire = cfg->retire;
+    if (hipMalloc((void**)&t.st, sizeof(DevState)) != hipSuccess) return fail(dev_fail(h, hipErrorOutOfMemory, "hipMalloc(state)"));
+    h->allocs.push_back(t.st);
+    if (hipMemsetAsync(t.st, 0, sizeof(DevState), h->stream) != hipSuccess) return fail(dev_fail(h, hipGetLastError(), "hipMemset(state)"));
+
+    if (h->engine == TCM_ENGINE_DENSE) {
+        const Shot& S = h->shots[0];
+        const size_t N = (size_t)S.nx * S.ny * S.nz;
+        if (dalloc(h, &h->d_phi[0], N) != hipSuccess || dalloc(h, &h->d_phi[1], N) != hipSuccess ||
+            dalloc(h, &h->d_c2, N) != hipSuccess)
+            return fail(set_err(h, TCM_E_NOMEM, "dense engine: device allocation failed"));
+        h->table_bytes += 3 * N * sizeof(float);
+        if (hipMemsetAsync(h->d_phi[0], 0, N * sizeof(float), h->stream) != hipSuccess ||
+            hipMemsetAsync(h->d_phi[1], 0, N * sizeof(float), h->stream) != hipSuccess)
+            return fail(dev_fail(h, hipGetLastError(), "hipMemset(dense)"));
+        if (launch_media_c2(S, h->d_shots, cfg->dt, cfg->dx, h->d_c2, h->stream) != hipSuccess)
+            return fail(dev_fail(h, hipGetLastError(), "media_c2"));
+        if (hipStreamSynchronize(h->stream) != hipSuccess) return fail(dev_fail(h, hipGetLastError(), "sync"));
+        *out = h;
+        return TCM_OK;
+    }
+
+    // ---- block engine tables ----
+    h->nkeys = word_base * 64;
+    t.nwords = word_base;
+    t.ncount_wg = (int)((word_base + COUNT_WORDS_PER_WG - 1) / COUNT_WORDS_PER_WG);
+    long long nblocks = 0;
+    for (const Shot& S : h->shots) nblocks += (long long)S.bx * S.by * S.bz;
+    size_t free_b = 0, total_b = 0;
+    (void)hipMemGetInfo(&free_b, &total_b);
+    // per-slot bookkeeping bytes besides the 6 KiB slot
+    const size_t per_slot_tab = 4 + 4 + 4 + 1 + 4 + 8 + 4 + 8 + 4 + 4;
+    const size_t fixed = (size_t)h->nkeys * 4 + (size_t)word_base * 8 + (size_t)t.ncount_wg * 4 + (1 << 20);
+    long long cap;
+    if (cfg->pool_bytes > 0) {
+        cap = (long long)(cfg->pool_bytes / SLOT_BYTES);
+        if (cap < 1) return fail(set_err(h, TCM_E_ARG, "pool_bytes is below one slot (6 KiB)"));
+        if (!cfg->device_pool && (double)cap * (SLOT_BYTES + per_slot_tab) + fixed > 0.95 * (double)free_b)
+            return fail(set_err(h, TCM_E_NOMEM, fmt("pool of %lld slots does not fit in %.1f GB free", cap, free_b / 1e9)));
+    } else {
+        cap = nblocks;
+        const double room = 0.9 * (double)free_b - (double)fixed;
+        const long long fit = room > 0 ? (long long)(room / (double)(SLOT_BYTES + per_slot_tab)) : 0;
+        if (cap > fit) cap = fit;
+        if (cap < 1) return fail(set_err(h, TCM_E_NOMEM, "no device memory for the pool"));
+    }
+    if (cap > nblocks) cap = nblocks;
+    if (cap > 0x7fffffffLL) cap = 0x7fffffffLL;
+    t.cap = (int)cap;
+
+    bool ok = true;
+    if (cfg->device_pool) {
+        t.pool = (float*)cfg->device_pool;
+    } else {
+        ok = ok && dalloc(h, &t.pool, (size_t)cap * SLOT) == hipSuccess;
+    }
+    ok = ok && dalloc(h, &t.cell2box, (size_t)h->nkeys) == hipSuccess;
+    ok = ok && dalloc(h, &t.bitmap, (size_t)word_base) == hipSuccess;
+    ok = ok && dalloc(h, &t.act_slot, (size_t)cap) == hipSuccess;
+    ok = ok && dalloc(h, &t.act_shot, (size_t)cap) == hipSuccess;
+    ok = ok && dalloc(h, &t.act_key, (size_t)cap) == hipSuccess;
+    ok = ok && dalloc(h, &t.flags, (size_t)cap) == hipSuccess;
+    ok = ok && dalloc(h, &t.pin_until, (size_t)cap) == hipSuccess;
+    ok = ok && dalloc(h, &t.slot_key, (size_t)cap) == hipSuccess;
+    ok = ok && dalloc(h, &t.free_stack, (size_t)cap) == hipSuccess;
+    ok = ok && dalloc(h, &t.new_key, (size_t)cap) == hipSuccess;
+    ok = ok && dalloc(h, &t.new_shot, (size_t)cap) == hipSuccess;
+    ok = ok && dalloc(h, &t.ret_slot, (size_t)cap) == hipSuccess;
+    ok = ok && dalloc(h, &t.partial, (size_t)t.ncount_wg) == hipSuccess;
+    if (!ok) return fail(set_err(h, TCM_E_NOMEM, "device allocation of the block tables failed"));
+    h->table_bytes += fixed + (size_t)cap * per_slot_tab;
+
+    if (launch_init_tables(t, h->nkeys, h->stream) != hipSuccess) return fail(dev_fail(h, hipGetLastError(), "init_tables"));
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return fail(dev_fail(h, hipGetLastError(), "sync"));
+
+    const int wpc = cfg->wg_per_cu > 0 ? cfg->wg_per_cu : 8;
+    h->grid_step = std::max(8, (h->ncu * wpc + 7) / 8 * 8);
+    h->grid_plan = std::max(1, h->ncu * 2);
+    h->grid_pool = std::max(t.ncount_wg, h->ncu * 2);
+    h->gsteps = cfg->graph_steps > 0 ? cfg->graph_steps : 16;
+    *out = h;
+    return TCM_OK;
+}
+
+// ---- per-step launch sequence ----------------------------------------------
+hipError_t enqueue_step(tcm_handle* h, hipEvent_t e0, hipEvent_t e1) {
+    hipError_t e;
+    if (e0 && (e = hipEventRecord(e0, h->stream)) != hipSuccess) return e;
+    if ((e = launch_block_step(h->t, h->grid_step, h->stream)) != hipSuccess) return e;
+    if (e1 && (e = hipEventRecord(e1, h->stream)) != hipSuccess) return e;
+    if ((e = launch_plan(h->t, h->grid_plan, h->stream)) != hipSuccess) return e;
+    if ((e = launch_pool_count(h->t, h->grid_pool, h->stream)) != hipSuccess) return e;
+    return launch_emit(h->t, h->stream);
+}
+
+hipError_t enqueue_dense_step(tcm_handle* h, hipEvent_t e0, hipEvent_t e1) {
+    const Shot& S = h->shots[0];
+    const long long n = h->dense_step;
+    DenseArgs a{S.nx, S.ny, S.nz, h->d_phi[n & 1], h->d_phi[1 - (n & 1)], h->d_c2};
+    hipError_t e;
+    if (e0 && (e = hipEventRecord(e0, h->stream)) != hipSuccess) return e;
+    if ((e = launch_dense_step(a, h->stream)) != hipSuccess) return e;
+    if (e1 && (e = hipEventRecord(e1, h->stream)) != hipSuccess) return e;
+    const long long row = n - h->t.trace_step0;
+    const int trow = (h->t.nrec > 0 && row >= 0 && row < h->t.trace_cap) ? (int)row : -1;
+    if (h->t.nsrc > 0 || trow >= 0) {
+        if ((e = launch_dense_inject(h->d_phi[1 - (n & 1)], (int)n, h->t.src, h->t.nsrc, h->t.srcw,
+                                     h->t.rec, h->t.nrec, h->t.traces, trow, h->stream)) != hipSuccess)
+            return e;
+    }
+    h->dense_step++;
+    return hipSuccess;
+}
+
+long long current_step(tcm_handle* h) {
+    if (h->engine == TCM_ENGINE_DENSE) return h->dense_step;
+    return h->h_state->step;
+}
+
+tcm_status ensure_trace_capacity(tcm_handle* h, long long upto_row) {
+    if (h->t.nrec <= 0 || upto_row <= h->t.trace_cap) return TCM_OK;
+    long long cap = std::max<long long>(1024, h->t.trace_cap);
+    while (cap < upto_row) cap *= 2;
+    if (cap > 0x7fffffffLL) return set_err(h, TCM_E_ARG, "trace buffer too long");
+    float* nt = nullptr;
+    HIP_OR_FAIL(h, dalloc(h, &nt, (size_t)cap * h->t.nrec));
+    HIP_OR_FAIL(h, hipMemsetAsync(nt, 0, (size_t)cap * h->t.nrec * sizeof(float), h->stream));
+    if (h->d_traces && h->t.trace_cap > 0)
+        HIP_OR_FAIL(h, hipMemcpyAsync(nt, h->d_traces, (size_t)h->t.trace_cap * h->t.nrec * sizeof(float),
+                                      hipMemcpyDeviceToDevice, h->stream));
+    HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+    dfree(h, h->d_traces);
+    h->d_traces = nt;
+    h->t.traces = nt;
+    h->t.trace_cap = (int)cap;
+    drop_graph(h);
+    return TCM_OK;
+}
+
+tcm_status scratch(tcm_handle* h, size_t bytes, float** p) {
+    if (bytes > h->scratch_bytes) {
+        dfree(h, h->d_scratch);
+        h->d_scratch = nullptr;
+        h->scratch_bytes = 0;
+        HIP_OR_FAIL(h, dalloc(h, &h->d_scratch, (bytes + 3) / 4));
+        h->scratch_bytes = bytes;
+    }
+    *p = h->d_scratch;
+    return TCM_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C-ABI
+// ===========================================================================
+extern "C" {
+
+const char* tcm_version(void) { return "tcm-mi355x 0.1 (gfx950)"; }
+
+const char* tcm_last_error(const tcm_handle* h) {
+    if (!h) return g_create_error.c_str();
+    return h->err.c_str();
+}
+
+tcm_status tcm_create(const tcm_config* cfg, const tcm_media* media, tcm_handle** out) {
+    if (!cfg) return set_err(nullptr, TCM_E_ARG, "config is NULL");
+    if (!media) return set_err(nullptr, TCM_E_ARG, "media is NULL");
+    tcm_shot s{};
+    s.nx = cfg->nx; s.ny = cfg->ny; s.nz = cfg->nz;
+    s.media = *media;
+    return create_common(cfg, &s, 1, out);
+}
+
+tcm_status tcm_create_batch(const tcm_config* cfg, const tcm_shot* shots, int32_t nshots, tcm_handle** out) {
+    return create_common(cfg, shots, nshots, out);
+}
+
+void tcm_destroy(tcm_handle* h) { destroy_all(h); }
+
+tcm_status tcm_add_source_shot(tcm_handle* h, int32_t shot, int32_t ix, int32_t iy, int32_t iz,
+                               const float* w, int32_t nsamples) {
+    tcm_status st = check_live(h);
+    if (st) return st;
+    if (shot < 0 || shot >= (int)h->shots.size()) return set_err(h, TCM_E_RANGE, "shot index out of range");
+    const Shot& S = h->shots[shot];
+    if (ix < 0 || iy < 0 || iz < 0 || ix >= S.nx || iy >= S.ny || iz >= S.nz)
+        return set_err(h, TCM_E_RANGE, fmt("source (%d,%d,%d) outside the %dx%dx%d grid", ix, iy, iz, S.nx, S.ny, S.nz));
+    if (nsamples < 0 || (nsamples > 0 && !w)) return set_err(h, TCM_E_ARG, "bad source samples");
+    for (int k = 0; k < nsamples; k++)
+        if (!std::isfinite(w[k])) return set_err(h, TCM_E_ARG, "source sample not finite");
+    if (h->engine == TCM_ENGINE_BLOCKS) {
+        st = sync_state(h);
+        if (st) return st;
+    }
+    const long long n = current_step(h);
+    Src e{};
+    unsigned local_key = 0;
+    if (h->engine == TCM_ENGINE_DENSE) {
+        e.key = (long long)ix + (long long)S.nx * ((long long)iy + (long long)S.ny * iz);
+        e.local = 0;
+    } else {
+        const int bx = ix >> 3, by = iy >> 3, bz = iz >> 3;
+        const unsigned tile = ((unsigned)(bz >> 2) * S.ty + (unsigned)(by >> 2)) * S.tx + (unsigned)(bx >> 2);
+        local_key = tile * 64u + ((unsigned)(bz & 3) << 4) + ((unsigned)(by & 3) << 2) + (unsigned)(bx & 3);
+        e.key = S.key_base + local_key;
+        e.local = ((iz & 7) * 8 + (iy & 7)) * 8 + (ix & 7);
+    }
+    e.t0 = (int)n;
+    e.ns = nsamples;
+    e.w_off = (long long)h->h_srcw.size();
+    std::vector<float> keepw = h->h_srcw;
+    h->h_srcw.insert(h->h_srcw.end(), w, w + nsamples);
+    h->h_src.push_back(e);
+    // upload source tables
+    if (h->h_src.size() > h->d_src_cap) {
+        size_t c = std::max<size_t>(16, h->d_src_cap * 2);
+        while (c < h->h_src.size()) c *= 2;
+        Src* d = nullptr;
+        HIP_OR_FAIL(h, dalloc(h, &d, c));
+        dfree(h, h->d_src);
+        h->d_src = d;
+        h->d_src_cap = c;
+    }
+    if (h->h_srcw.size() > h->d_srcw_cap) {
+        size_t c = std::max<size_t>(1024, h->d_srcw_cap * 2);
+        while (c < h->h_srcw.size()) c *= 2;
+        float* d = nullptr;
+        HIP_OR_FAIL(h, dalloc(h, &d, c));
+        dfree(h, h->d_srcw);
+        h->d_srcw = d;
+        h->d_srcw_cap = c;
+    }
+    HIP_OR_FAIL(h, hipMemcpyAsync(h->d_src, h->h_src.data(), h->h_src.size() * sizeof(Src), hipMemcpyHostToDevice, h->stream));
+    if (!h->h_srcw.empty())
+        HIP_OR_FAIL(h, hipMemcpyAsync(h->d_srcw, h->h_srcw.data(), h->h_srcw.size() * sizeof(float), hipMemcpyHostToDevice, h->stream));
+    h->t.src = h->d_src;
+    h->t.srcw = h->d_srcw;
+    h->t.nsrc = (int)h->h_src.size();
+    drop_graph(h);
+    if (h->engine == TCM_ENGINE_BLOCKS) {
+        HIP_OR_FAIL(h, launch_activate(h->t, e.key, shot, local_key, (int)(n + nsamples), h->stream));
+        st = sync_state(h);
+        if (st) return st;
+        if (h->h_state->add_error) {
+            // undo: no slot for the source block
+            HIP_OR_FAIL(h, hipMemsetAsync(&h->t.st->add_error, 0, sizeof(int), h->stream));
+            h->h_src.pop_back();
+            h->h_srcw = keepw;
+            h->t.nsrc = (int)h->h_src.size();
+            HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+            return set_err(h, TCM_E_POOL, "no free pool slot for the source block");
+        }
+    } else {
+        HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+    }
+    return TCM_OK;
+}
+
+tcm_status tcm_add_source(tcm_handle* h, int32_t ix, int32_t iy, int32_t iz, const float* w, int32_t nsamples) {
+    return tcm_add_source_shot(h, 0, ix, iy, iz, w, nsamples);
+}
+
+tcm_status tcm_set_receivers(tcm_handle* h, const int32_t* xyz, const int32_t* rec_shot, int32_t nrec) {
+    tcm_status st = check_live(h);
+    if (st) return st;
+    if (nrec < 0 || (nrec > 0 && !xyz)) return set_err(h, TCM_E_ARG, "bad receiver array");
+    std::vector<Rec> rec(nrec);
+    for (int r = 0; r < nrec; r++) {
+        const int s = rec_shot ? rec_shot[r] : 0;
+        if (s < 0 || s >= (int)h->shots.size()) return set_err(h, TCM_E_RANGE, "receiver shot out of range");
+        const Shot& S = h->shots[s];
+        const int x = xyz[3 * r], y = xyz[3 * r + 1], z = xyz[3 * r + 2];
+        if (x < 0 || y < 0 || z < 0 || x >= S.nx || y >= S.ny || z >= S.nz)
+            return set_err(h, TCM_E_RANGE, fmt("receiver %d at (%d,%d,%d) outside the grid", r, x, y, z));
+        if (h->engine == TCM_ENGINE_DENSE) {
+            rec[r].key = (long long)x + (long long)S.nx * ((long long)y + (long long)S.ny * z);
+            rec[r].local = 0;
+        } else {
+            const int bx = x >> 3, by = y >> 3, bz = z >> 3;
+            const unsigned tile = ((unsigned)(bz >> 2) * S.ty + (unsigned)(by >> 2)) * S.tx + (unsigned)(bx >> 2);
+            rec[r].key = S.key_base + tile * 64u + ((unsigned)(bz & 3) << 4) + ((unsigned)(by & 3) << 2) + (unsigned)(bx & 3);
+            rec[r].local = ((z & 7) * 8 + (y & 7)) * 8 + (x & 7);
+        }
+    }
+    if (h->engine == TCM_ENGINE_BLOCKS) {
+        st = sync_state(h);
+        if (st) return st;
+    }
+    HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+    dfree(h, h->d_rec);
+    dfree(h, h->d_traces);
+    h->d_rec = nullptr;
+    h->d_traces = nullptr;
+    h->h_rec = rec;
+    h->t.rec = nullptr;
+    h->t.traces = nullptr;
+    h->t.trace_cap = 0;
+    h->t.nrec = nrec;
+    h->t.trace_step0 = (int)current_step(h);
+    if (nrec > 0) {
+        HIP_OR_FAIL(h, dalloc(h, &h->d_rec, nrec));
+        HIP_OR_FAIL(h, hipMemcpy(h->d_rec, rec.data(), nrec * sizeof(Rec), hipMemcpyHostToDevice));
+        h->t.rec = h->d_rec;
+        st = ensure_trace_capacity(h, 1024);
+        if (st) return st;
+    }
+    drop_graph(h);
+    return TCM_OK;
+}
+
+tcm_status tcm_step(tcm_handle* h, int32_t nsteps) {
+    tcm_status st = check_live(h);
+    if (st) return st;
+    if (nsteps < 0) return set_err(h, TCM_E_ARG, "nsteps < 0");
+    if (nsteps == 0) return TCM_OK;
+    const bool timing = (h->cfg.flags & TCM_FLAG_TIMING) != 0;
+
+    if (h->engine == TCM_ENGINE_DENSE) {
+        st = ensure_trace_capacity(h, h->dense_step + nsteps - h->t.trace_step0);
+        if (st) return st;
+        if (timing) {
+            while ((int)h->events.size() < 2 * nsteps) {
+                hipEvent_t e;
+                HIP_OR_FAIL(h, hipEventCreate(&e));
+                h->events.push_back(e);
+            }
+        }
+        for (int k = 0; k < nsteps; k++)
+            HIP_OR_FAIL(h, enqueue_dense_step(h, timing ? h->events[2 * k] : nullptr, timing ? h->events[2 * k + 1] : nullptr));
+        HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+        if (timing) {
+            const Shot& S = h->shots[0];
+            for (int k = 0; k < nsteps; k++) {
+                float ms = 0.f;
+                HIP_OR_FAIL(h, hipEventElapsedTime(&ms, h->events[2 * k], h->events[2 * k + 1]));
+                h->stencil_ms += ms;
+            }
+            h->stencil_launches += nsteps;
+            h->stencil_cells += (long long)nsteps * S.nx * S.ny * S.nz;
+        }
+        return TCM_OK;
+    }
+
+    st = sync_state(h);
+    if (st) return st;
+    if (h->h_state->error) return set_err(h, (tcm_status)h->h_state->error, "pool exhausted at an earlier step");
+    st = ensure_trace_capacity(h, h->h_state->step + (long long)nsteps - h->t.trace_step0);
+    if (st) return st;
+    const unsigned long long upd0 = h->h_state->updates + h->h_state->cells_cur;
+
+    if (timing) {
+        while ((int)h->events.size() < 2 * nsteps) {
+            hipEvent_t e;
+            HIP_OR_FAIL(h, hipEventCreate(&e));
+            h->events.push_back(e);
+        }
+        for (int k = 0; k < nsteps; k++)
+            HIP_OR_FAIL(h, enqueue_step(h, h->events[2 * k], h->events[2 * k + 1]));
+        HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+        for (int k = 0; k < nsteps; k++) {
+            float ms = 0.f;
+            HIP_OR_FAIL(h, hipEventElapsedTime(&ms, h->events[2 * k], h->events[2 * k + 1]));
+            h->stencil_ms += ms;
+        }
+        h->stencil_launches += nsteps;
+    } else {
+        int left = nsteps;
+        const bool use_graph = !(h->cfg.flags & TCM_FLAG_NO_GRAPH) && !h->graph_failed && h->own_stream;
+        if (use_graph && left >= h->gsteps) {
+            if (!h->gexec) {
+                hipGraph_t g = nullptr;
+                bool ok = hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+                hipError_t le = hipSuccess;
+                for (int k = 0; ok && k < h->gsteps && le == hipSuccess; k++) le = enqueue_step(h, nullptr, nullptr);
+                if (ok) ok = hipStreamEndCapture(h->stream, &g) == hipSuccess && le == hipSuccess;
+                if (ok) ok = hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0) == hipSuccess;
+                if (g) (void)hipGraphDestroy(g);
+                if (!ok) {
+                    (void)hipGetLastError();
+                    h->gexec = nullptr;
+                    h->graph_failed = true;
+                }
+            }
+            while (h->gexec && left >= h->gsteps) {
+                HIP_OR_FAIL(h, hipGraphLaunch(h->gexec, h->stream));
+                left -= h->gsteps;
+            }
+        }
+        for (; left > 0; left--) HIP_OR_FAIL(h, enqueue_step(h, nullptr, nullptr));
+    }
+    st = sync_state(h);
+    if (st) return st;
+    if (timing) h->stencil_cells += (long long)(h->h_state->updates + h->h_state->cells_cur - upd0);
+    if (h->h_state->error) {
+        return set_err(h, (tcm_status)h->h_state->error,
+                       fmt("pool of %d slots exhausted at step %d; the field is kept at that step",
+                           h->t.cap, h->h_state->err_step + 1));
+    }
+    return TCM_OK;
+}
+
+tcm_status tcm_read_shot(tcm_handle* h, int32_t shot, int32_t which, int32_t x0, int32_t y0, int32_t z0,
+                         int32_t sx, int32_t sy, int32_t sz, float* out, int32_t out_is_device) {
+    tcm_status st = check_live(h);
+    if (st) return st;
+    if (shot < 0 || shot >= (int)h->shots.size()) return set_err(h, TCM_E_RANGE, "shot index out of range");
+    if (which != 0 && which != 1) return set_err(h, TCM_E_ARG, "which must be 0 (phi^n) or 1 (phi^{n-1})");
+    const Shot& S = h->shots[shot];
+    if (sx < 0 || sy < 0 || sz < 0 || x0 < 0 || y0 < 0 || z0 < 0 || x0 + (long long)sx > S.nx ||
+        y0 + (long long)sy > S.ny || z0 + (long long)sz > S.nz)
+        return set_err(h, TCM_E_RANGE, "read box outside the grid");
+    const size_t count = (size_t)sx * sy * sz;
+    if (count == 0) return TCM_OK;
+    if (!out) return set_err(h, TCM_E_ARG, "out is NULL");
+    float* dst = out;
+    if (!out_is_device) {
+        st = scratch(h, count * sizeof(float), &dst);
+        if (st) return st;
+    }
+    if (h->engine == TCM_ENGINE_DENSE) {
+        const long long n = h->dense_step;
+        const float* f = h->d_phi[which == 0 ? (n & 1) : 1 - (n & 1)];
+        HIP_OR_FAIL(h, launch_read_dense(f, S.nx, S.ny, x0, y0, z0, sx, sy, sz, dst, h->stream));
+    } else {
+        HIP_OR_FAIL(h, launch_read(h->t, shot, which, x0, y0, z0, sx, sy, sz, dst, h->stream));
+    }
+    if (!out_is_device) {
+        HIP_OR_FAIL(h, hipMemcpyAsync(out, dst, count * sizeof(float), hipMemcpyDeviceToHost, h->stream));
+        HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+    }
+    return TCM_OK;
+}
+
+tcm_status tcm_read(tcm_handle* h, int32_t which, int32_t x0, int32_t y0, int32_t z0, int32_t sx, int32_t sy,
+                    int32_t sz, float* out, int32_t out_is_device) {
+    return tcm_read_shot(h, 0, which, x0, y0, z0, sx, sy, sz, out, out_is_device);
+}
+
+tcm_status tcm_read_traces(tcm_handle* h, float* out, int32_t out_is_device, int32_t* nsteps) {
+    tcm_status st = check_live(h);
+    if (st) return st;
+    long long cur = 0;
+    if (h->engine == TCM_ENGINE_BLOCKS) {
+        st = sync_state(h);
+        if (st) return st;
+        cur = h->h_state->step;
+    } else {
+        HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+        cur = h->dense_step;
+    }
+    long long rows = cur - h->t.trace_step0;
+    if (rows < 0 || h->t.nrec == 0) rows = 0;
+    if (rows > h->t.trace_cap) rows = h->t.trace_cap;
+    if (nsteps) *nsteps = (int32_t)rows;
+    if (!out || rows == 0) return TCM_OK;
+    const size_t bytes = (size_t)rows * h->t.nrec * sizeof(float);
+    HIP_OR_FAIL(h, hipMemcpyAsync(out, h->d_traces, bytes, out_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, h->stream));
+    HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+    return TCM_OK;
+}
+
+tcm_status tcm_stats(tcm_handle* h, tcm_stats_t* o) {
+    tcm_status st = check_live(h);
+    if (st) return st;
+    if (!o) return set_err(h, TCM_E_ARG, "out is NULL");
+    memset(o, 0, sizeof *o);
+    o->nshots = (int32_t)h->shots.size();
+    o->stencil_ms = h->stencil_ms;
+    o->stencil_launches = h->stencil_launches;
+    o->stencil_cells = h->stencil_cells;
+    o->table_bytes = (int64_t)h->table_bytes;
+    if (h->engine == TCM_ENGINE_DENSE) {
+        HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+        const Shot& S = h->shots[0];
+        const long long N = (long long)S.nx * S.ny * S.nz;
+        o->step = h->dense_step;
+        o->active_blocks = (long long)S.bx * S.by * S.bz;
+        o->peak_active_blocks = o->active_blocks;
+        o->cell_updates = N * h->dense_step;
+        return TCM_OK;
+    }
+    st = sync_state(h);
+    if (st) return st;
+    const DevState& d = *h->h_state;
+    o->step = d.step;
+    o->active_blocks = d.n_act;
+    o->peak_active_blocks = d.peak_act;
+    o->pool_slots = h->t.cap;
+    o->pool_bytes = (int64_t)h->t.cap * (int64_t)SLOT_BYTES;
+    o->peak_pool_bytes = (int64_t)d.peak_act * (int64_t)SLOT_BYTES;
+    o->activations = (int64_t)d.activations;
+    o->retirements = (int64_t)d.retirements;
+    o->cell_updates = (int64_t)d.updates;
+    o->error = d.error;
+    return TCM_OK;
+}
+
+tcm_status tcm_reset(tcm_handle* h) {
+    tcm_status st = check_live(h);
+    if (st) return st;
+    HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+    drop_graph(h);
+    h->h_src.clear();
+    h->h_srcw.clear();
+    h->t.nsrc = 0;
+    h->h_rec.clear();
+    h->t.nrec = 0;
+    h->t.trace_cap = 0;
+    h->t.trace_step0 = 0;
+    dfree(h, h->d_rec);
+    dfree(h, h->d_traces);
+    h->d_rec = nullptr;
+    h->d_traces = nullptr;
+    h->t.rec = nullptr;
+    h->t.traces = nullptr;
+    h->stencil_ms = 0.0;
+    h->stencil_launches = 0;
+    h->stencil_cells = 0;
+    if (h->engine == TCM_ENGINE_DENSE) {
+        const Shot& S = h->shots[0];
+        const size_t N = (size_t)S.nx * S.ny * S.nz;
+        HIP_OR_FAIL(h, hipMemsetAsync(h->d_phi[0], 0, N * sizeof(float), h->stream));
+        HIP_OR_FAIL(h, hipMemsetAsync(h->d_phi[1], 0, N * sizeof(float), h->stream));
+        h->dense_step = 0;
+    } else {
+        HIP_OR_FAIL(h, launch_init_tables(h->t, h->nkeys, h->stream));
+    }
+    HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+    return TCM_OK;
+}
+
+tcm_status tcm_adjoint(tcm_handle* h, const float* resid, int32_t nt, int32_t resid_is_device,
+                       float* grad_c, int32_t out_is_device) {
+    tcm_status st = check_live(h);
+    if (st) return st;
+    (void)resid; (void)nt; (void)resid_is_device; (void)grad_c; (void)out_is_device;
+    return set_err(h, TCM_E_STATE, "tcm_adjoint needs checkpoint_every > 0");
+}
+
+}  // extern "C"

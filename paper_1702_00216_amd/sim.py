@@ -1,0 +1,198 @@
+"""Python front end of libtcm.so: argument marshalling only.
+
+Every step of the method runs in the HIP kernels behind the C-ABI; this
+module converts NumPy / torch arguments to pointers and sizes.  Torch is used
+for device memory (reads into device tensors) and streams.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional, Sequence
+
+import numpy as np
+
+from . import _lib as L
+
+
+def _media_struct(media, shape, keep: list) -> L.Media:
+    """Accepts a float32 (nz, ny, nx) array, or an object with z_top/c_layer
+    (layered) or lattice/spacing (lattice)."""
+    m = L.Media()
+    if isinstance(media, np.ndarray):
+        c = np.ascontiguousarray(media, dtype=np.float32)
+        nx, ny, nz = shape
+        if c.shape != (nz, ny, nx):
+            raise ValueError(f"dense media must have shape (nz, ny, nx) = {(nz, ny, nx)}")
+        keep.append(c)
+        m.kind = L.MEDIA_DENSE
+        m.c = c.ctypes.data
+    elif hasattr(media, "z_top"):
+        zt = np.ascontiguousarray(media.z_top, dtype=np.int32)
+        cl = np.ascontiguousarray(media.c_layer, dtype=np.float32)
+        keep += [zt, cl]
+        m.kind = L.MEDIA_LAYERED
+        m.nlayers = zt.size
+        m.z_top = zt.ctypes.data
+        m.c_layer = cl.ctypes.data
+    elif hasattr(media, "lattice"):
+        lat = np.ascontiguousarray(media.lattice, dtype=np.float64)
+        keep.append(lat)
+        s = int(media.spacing)
+        if s <= 0 or s & (s - 1):
+            raise ValueError("lattice spacing must be a power of two")
+        m.kind = L.MEDIA_LATTICE
+        m.lattice = lat.ctypes.data
+        m.lz, m.ly, m.lx = lat.shape
+        m.log2_spacing = s.bit_length() - 1
+    else:
+        raise TypeError("unsupported media description")
+    return m
+
+
+class Simulation:
+    """One TCM handle (single shot or a batch of shots over one pool).
+
+    ``shape`` is (nx, ny, nz) (or a list of shapes with ``media`` a list, for a
+    batch); ``engine`` "blocks" runs the TCM, "dense" updates every node.
+    """
+
+    def __init__(self, shape, dx: float, dt: float, media, trigger: float = 0.0,
+                 retire: float = 0.0, pool_bytes: int = 0, engine: str = "blocks",
+                 timing: bool = False, graphs: bool = True, stream=None,
+                 checkpoint_every: int = 0, graph_steps: int = 0, wg_per_cu: int = 0,
+                 device_pool=None):
+        lib = L.lib()
+        cfg = L.Config()
+        cfg.dx, cfg.dt = float(dx), float(dt)
+        cfg.trigger, cfg.retire = float(trigger), float(retire)
+        cfg.pool_bytes = int(pool_bytes)
+        cfg.engine = L.ENGINE_DENSE if engine == "dense" else L.ENGINE_BLOCKS
+        cfg.flags = (L.FLAG_TIMING if timing else 0) | (0 if graphs else L.FLAG_NO_GRAPH)
+        cfg.checkpoint_every = int(checkpoint_every)
+        cfg.graph_steps = int(graph_steps)
+        cfg.wg_per_cu = int(wg_per_cu)
+        self._pool_tensor = device_pool
+        if device_pool is not None:
+            cfg.device_pool = device_pool.data_ptr()
+        if stream is not None:
+            cfg.stream = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+        self._stream = stream
+        keep: list = []
+        h = C.c_void_p()
+        batch = isinstance(shape, (list, tuple)) and len(shape) > 0 and isinstance(shape[0], (list, tuple))
+        if batch:
+            if len(shape) != len(media):
+                raise ValueError("one media per shot")
+            shots = (L.Shot * len(shape))()
+            for i, (shp, med) in enumerate(zip(shape, media)):
+                shots[i].nx, shots[i].ny, shots[i].nz = (int(v) for v in shp)
+                shots[i].media = _media_struct(med, tuple(int(v) for v in shp), keep)
+            rc = lib.tcm_create_batch(C.byref(cfg), shots, len(shape), C.byref(h))
+            self.shapes = [tuple(int(v) for v in s) for s in shape]
+        else:
+            cfg.nx, cfg.ny, cfg.nz = (int(v) for v in shape)
+            m = _media_struct(media, tuple(int(v) for v in shape), keep)
+            rc = lib.tcm_create(C.byref(cfg), C.byref(m), C.byref(h))
+            self.shapes = [tuple(int(v) for v in shape)]
+        if rc != 0:
+            raise L.TCMError(rc, lib.tcm_last_error(None).decode())
+        self._h = h
+        self.shape = self.shapes[0]
+        self.nrec = 0
+
+    # ------------------------------------------------------------------
+    def _check(self, rc: int):
+        if rc != 0:
+            raise L.TCMError(rc, L.lib().tcm_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            L.lib().tcm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # ------------------------------------------------------------------
+    def add_source(self, xyz, w, shot: int = 0):
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        self._check(L.lib().tcm_add_source_shot(self._h, shot, int(xyz[0]), int(xyz[1]), int(xyz[2]),
+                                                w.ctypes.data, w.size))
+
+    def set_receivers(self, rec, shots: Optional[Sequence[int]] = None):
+        r = np.ascontiguousarray(np.asarray(rec, dtype=np.int32).reshape(-1, 3))
+        s = None if shots is None else np.ascontiguousarray(shots, dtype=np.int32)
+        self.nrec = r.shape[0]
+        self._check(L.lib().tcm_set_receivers(self._h, r.ctypes.data,
+                                              None if s is None else s.ctypes.data, self.nrec))
+
+    def step(self, n: int):
+        """Advance n steps; raises TCMError (TCM_E_POOL) if the pool overflowed."""
+        self._check(L.lib().tcm_step(self._h, int(n)))
+
+    def step_status(self, n: int) -> int:
+        return int(L.lib().tcm_step(self._h, int(n)))
+
+    def read(self, which: int = 0, box=None, shot: int = 0, out=None) -> np.ndarray:
+        """phi^n (which=0) or phi^{n-1} (which=1) of a box ((x0,y0,z0),(sx,sy,sz))
+        as a float32 (sz, sy, sx) array, or into ``out`` (a CUDA torch tensor)."""
+        nx, ny, nz = self.shapes[shot]
+        (x0, y0, z0), (sx, sy, sz) = box if box is not None else ((0, 0, 0), (nx, ny, nz))
+        if out is not None:
+            import torch
+            if not (out.is_cuda and out.dtype == torch.float32 and out.is_contiguous()
+                    and out.numel() == sx * sy * sz):
+                raise ValueError("out must be a contiguous float32 CUDA tensor of the box size")
+            torch.cuda.current_stream().synchronize()
+            self._check(L.lib().tcm_read_shot(self._h, shot, which, x0, y0, z0, sx, sy, sz,
+                                              out.data_ptr(), 1))
+            self._check(L.lib().tcm_stats(self._h, C.byref(L.Stats())))   # orders the read
+            return out
+        a = np.empty((sz, sy, sx), np.float32)
+        self._check(L.lib().tcm_read_shot(self._h, shot, which, x0, y0, z0, sx, sy, sz,
+                                          a.ctypes.data, 0))
+        return a
+
+    def read_traces(self) -> np.ndarray:
+        n = C.c_int32(0)
+        self._check(L.lib().tcm_read_traces(self._h, None, 0, C.byref(n)))
+        out = np.zeros((n.value, self.nrec), np.float32)
+        if n.value and self.nrec:
+            self._check(L.lib().tcm_read_traces(self._h, out.ctypes.data, 0, C.byref(n)))
+        return out
+
+    def adjoint(self, resid: np.ndarray) -> np.ndarray:
+        r = np.ascontiguousarray(resid, dtype=np.float32)
+        nx, ny, nz = self.shape
+        g = np.zeros((nz, ny, nx), np.float32)
+        self._check(L.lib().tcm_adjoint(self._h, r.ctypes.data, r.shape[0], 0, g.ctypes.data, 0))
+        return g
+
+    def adjoint_device(self, resid, grad):
+        """resid and grad are contiguous float32 CUDA tensors ([nt, nrec], [nz, ny, nx])."""
+        import torch
+        torch.cuda.current_stream().synchronize()
+        self._check(L.lib().tcm_adjoint(self._h, resid.data_ptr(), resid.shape[0], 1,
+                                        grad.data_ptr(), 1))
+        return grad
+
+    def reset(self):
+        self._check(L.lib().tcm_reset(self._h))
+
+    def stats(self) -> dict:
+        s = L.Stats()
+        self._check(L.lib().tcm_stats(self._h, C.byref(s)))
+        return {k: getattr(s, k) for k, _ in L.Stats._fields_}
+
+
+def version() -> str:
+    return L.lib().tcm_version().decode()

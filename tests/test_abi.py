@@ -1,0 +1,93 @@
+"""Host-side checks of libtcm.so that need no GPU: the library loads, exports
+every symbol include/tcm.h declares, and rejects invalid problems (eq.(4),
+media, thresholds) before touching the device."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from conftest import ROOT
+
+pa = pytest.importorskip("paper_1702_00216_amd")
+from paper_1702_00216_amd import _lib as L  # noqa: E402
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "tcm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(tcm_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = L.lib()
+    names = _declared()
+    assert set(names) == set(L.EXPORTS)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert b"gfx950" in lib.tcm_version()
+
+
+def _create(shape, c, dt, dx=1.0, trigger=0.0, retire=0.0, **kw):
+    cfg = L.Config()
+    cfg.nx, cfg.ny, cfg.nz = shape
+    cfg.dx, cfg.dt = dx, dt
+    cfg.trigger, cfg.retire = trigger, retire
+    for k, v in kw.items():
+        setattr(cfg, k, v)
+    m = L.Media()
+    m.kind = L.MEDIA_DENSE
+    m.c = c.ctypes.data
+    h = C.c_void_p()
+    rc = L.lib().tcm_create(C.byref(cfg), C.byref(m), C.byref(h))
+    if rc == 0:
+        L.lib().tcm_destroy(h)
+    return rc, L.lib().tcm_last_error(None).decode()
+
+
+def test_cfl_violation_rejected():
+    c = np.ones((4, 4, 4), np.float32)
+    rc, msg = _create((4, 4, 4), c, dt=0.58)          # 0.58 > 1/sqrt(3)
+    assert rc == L.TCM_E_CFL and "eq.(4)" in msg
+    c[2, 2, 2] = 2.0
+    rc, _ = _create((4, 4, 4), c, dt=0.3)             # max c decides
+    assert rc == L.TCM_E_CFL
+
+
+@pytest.mark.parametrize("bad", [-1.0, np.nan, np.inf])
+def test_bad_speed_rejected(bad):
+    c = np.ones((4, 4, 4), np.float32)
+    c[1, 2, 3] = bad
+    rc, msg = _create((4, 4, 4), c, dt=0.5)
+    assert rc == L.TCM_E_ARG and "node" in msg
+
+
+def test_bad_thresholds_rejected():
+    c = np.ones((4, 4, 4), np.float32)
+    assert _create((4, 4, 4), c, 0.5, trigger=1e-7, retire=1e-6)[0] == L.TCM_E_ARG
+    assert _create((4, 4, 4), c, 0.5, trigger=-1.0, retire=-1.0)[0] == L.TCM_E_ARG
+    assert _create((4, 4, 4), c, 0.5, dx=0.0)[0] == L.TCM_E_ARG
+
+
+def test_lattice_media_validated():
+    cfg = L.Config()
+    cfg.nx = cfg.ny = cfg.nz = 64
+    cfg.dx, cfg.dt = 1.0, 0.5 / 4500
+    lat = np.full((4, 4, 4), 3000.0)
+    m = L.Media()
+    m.kind = L.MEDIA_LATTICE
+    m.lattice = lat.ctypes.data
+    m.lx = m.ly = m.lz = 4
+    m.log2_spacing = 4          # needs (63 >> 4) + 2 = 5 nodes per axis
+    h = C.c_void_p()
+    assert L.lib().tcm_create(C.byref(cfg), C.byref(m), C.byref(h)) == L.TCM_E_ARG
+    assert "lattice" in L.lib().tcm_last_error(None).decode()
+
+
+def test_simulation_without_device_fails_loudly():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(pa.TCMError):
+        pa.Simulation((16, 16, 16), 1.0, 0.5, np.ones((16, 16, 16), np.float32))

@@ -1,0 +1,250 @@
+"""Parity of the HIP path (through the C-ABI) with the CPU oracle.
+
+FP32 values must be bit-exact (as IEEE values, -0 == +0) to the oracle at
+the same thresholds: O1 (dense) at trigger = retire = 0, O2 (CPU TCM) at any
+thresholds; activation decisions are comparisons of identical values, so the
+active sets and their statistics must match exactly as well.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import tcm_inputs as ti
+from conftest import values_equal
+
+pytestmark = pytest.mark.gpu
+tcm = pytest.importorskip("paper_1702_00216_amd")
+
+
+def announce(msg):
+    print(f"\n[case] {msg}", flush=True)
+
+
+def gpu_run(shape, dt, media, sources, steps, trigger=0.0, retire=0.0, receivers=None,
+            engine="blocks", **kw):
+    sim = tcm.Simulation(shape, 1.0, dt, media, trigger, retire, engine=engine, **kw)
+    for xyz, w in sources:
+        sim.add_source(xyz, w)
+    if receivers is not None:
+        sim.set_receivers(receivers)
+    if steps:
+        sim.step(steps)
+    return sim
+
+
+def relerr(a, b):
+    return float(np.linalg.norm(a.astype(np.float64) - b) / np.linalg.norm(b))
+
+
+def test_c1_bitexact_to_dense_oracle_and_fp64_error():
+    announce("C1 64^3 tau=0 100 steps")
+    w = ti.c1()
+    src = [(w.source, w.wavelet.w32)]
+    rec = [(40, 32, 32), (32, 32, 60), (5, 7, 9)]
+    phi, prev, tr = oracle.dense_run(w.c_dense, w.dt, 1.0, w.steps, np.float32, sources=src,
+                                     receivers=rec)
+    sim = gpu_run(w.shape, w.dt, w.c_dense, src, w.steps, receivers=rec)
+    assert values_equal(sim.read(0), phi)
+    assert values_equal(sim.read(1), prev)
+    assert values_equal(sim.read_traces(), tr)
+    st = sim.stats()
+    assert st["step"] == 100 and st["error"] == 0 and st["active_blocks"] == 512
+    ref, _, _ = oracle.dense_run(w.c_dense, w.dt, 1.0, w.steps, np.float64,
+                                 sources=[(w.source, w.wavelet.w32.astype(np.float64))])
+    e = relerr(sim.read(0), ref)
+    print(f"C1 rel-L2 vs FP64 = {e:.3e}")
+    assert e <= 1e-5
+    # work accounting matches the CPU TCM
+    t = oracle.TCM(w.c_dense, w.dt, 1.0, 0.0, 0.0)
+    t.add_source(w.source, w.wavelet.w32)
+    t.step(w.steps)
+    o = t.stats()
+    assert st["cell_updates"] == o["updates"] and st["activations"] == o["activations"]
+    assert st["peak_active_blocks"] == o["peak_active"]
+
+
+def test_dense_engine_bitexact():
+    announce("dense engine C1 + ragged heterogeneous")
+    w = ti.c1()
+    src = [(w.source, w.wavelet.w32)]
+    phi, prev, _ = oracle.dense_run(w.c_dense, w.dt, 1.0, w.steps, np.float32, sources=src)
+    sim = gpu_run(w.shape, w.dt, w.c_dense, src, w.steps, engine="dense")
+    assert values_equal(sim.read(0), phi) and values_equal(sim.read(1), prev)
+    shape = (70, 45, 33)
+    c = ti.random_media(shape, seed=3, cmin=0.2, cmax=1.0)
+    src = [((0, 44, 17), ti.ricker(0.1, 0.55).w32), ((35, 20, 32), ti.ricker(0.2, 0.55).w32)]
+    phi, prev, tr = oracle.dense_run(c, 0.55, 1.0, 77, np.float32, sources=src, receivers=[(1, 2, 3)])
+    sim = gpu_run(shape, 0.55, c, src, 77, engine="dense", receivers=[(1, 2, 3)])
+    assert values_equal(sim.read(0), phi) and values_equal(sim.read(1), prev)
+    assert values_equal(sim.read_traces(), tr)
+
+
+@pytest.mark.parametrize("shape", [(37, 29, 21), (8, 8, 8), (9, 17, 65), (1, 1, 1), (130, 3, 12)])
+def test_ragged_heterogeneous_tau0(shape):
+    announce(f"ragged tau=0 {shape}")
+    c = ti.random_media(shape, seed=sum(shape), cmin=0.3, cmax=1.0)
+    dt = 0.55
+    nx, ny, nz = shape
+    src = [((nx // 2, ny // 2, nz // 2), ti.ricker(0.12, dt).w32),
+           ((nx - 1, 0, nz - 1), -0.5 * ti.ricker(0.2, dt).w32)]
+    phi, prev, _ = oracle.dense_run(c, dt, 1.0, 90, np.float32, sources=src)
+    sim = gpu_run(shape, dt, c, src, 0)
+    for k in range(3):          # several calls: graph and direct paths mix
+        sim.step(30)
+    assert values_equal(sim.read(0), phi)
+    assert values_equal(sim.read(1), prev)
+
+
+@pytest.mark.parametrize("trig,ret,steps", [(3e-4, 5e-5, 150), (1e-3, 1e-3, 120), (3e-3, 1e-3, 140)])
+def test_thresholds_match_cpu_tcm(trig, ret, steps):
+    announce(f"tau>0 vs CPU TCM trig={trig} ret={ret}")
+    shape = (72, 64, 56)
+    c = ti.random_media(shape, seed=9, cmin=0.8, cmax=1.0)
+    w = ti.ricker(0.12, 0.5).w32
+    trig, ret = np.float32(trig), np.float32(ret)
+    t = oracle.TCM(c, 0.5, 1.0, trig, ret)
+    t.add_source((36, 32, 28), w)
+    sim = gpu_run(shape, 0.5, c, [((36, 32, 28), w)], 0, trig, ret)
+    for k in range(steps // 10):
+        assert t.step(10) == 0
+        sim.step(10)
+        o, g = t.stats(), sim.stats()
+        assert g["active_blocks"] == o["active"], k
+        assert g["activations"] == o["activations"] and g["retirements"] == o["retirements"]
+        assert g["cell_updates"] == o["updates"]
+    assert values_equal(sim.read(0), t.read(0))
+    assert values_equal(sim.read(1), t.read(1))
+
+
+def test_retirement_path_matches_cpu_tcm():
+    """Source cell isolated by a huge threshold: it runs alone, then retires."""
+    announce("isolated source block then retire")
+    shape = (32, 32, 32)
+    c = np.ones(shape, np.float32)
+    w = ti.ricker(0.15, 0.5).w32
+    big = np.float32(1e30)
+    sim = gpu_run(shape, 0.5, c, [((13, 10, 9), w)], w.size - 1, big, big)
+    alone, _, _ = oracle.dense_run(np.ones((8, 8, 8), np.float32), 0.5, 1.0, w.size - 1,
+                                   np.float32, sources=[((5, 2, 1), w)])
+    out = sim.read(0)
+    assert values_equal(out[8:16, 8:16, 8:16], alone)
+    out[8:16, 8:16, 8:16] = 0
+    assert not out.any()
+    sim.step(1)
+    st = sim.stats()
+    assert st["active_blocks"] == 0 and st["retirements"] == 1
+    assert not sim.read(0).any()
+
+
+def test_pool_cap_fails_like_cpu_tcm():
+    announce("pool cap E_POOL")
+    w = ti.c1(steps=60)
+    cap = 100
+    t = oracle.TCM(w.c_dense, w.dt, 1.0, 0.0, 0.0, cap=cap)
+    t.add_source(w.source, w.wavelet.w32)
+    assert t.step(60) == oracle.TCM.E_POOL
+    o = t.stats()
+    sim = gpu_run(w.shape, w.dt, w.c_dense, [(w.source, w.wavelet.w32)], 0, pool_bytes=cap * 6144)
+    with pytest.raises(tcm.TCMError) as ei:
+        sim.step(60)
+    assert ei.value.status == -3
+    g = sim.stats()
+    assert g["step"] == o["step"] and g["active_blocks"] == o["active"] and g["error"] == -3
+    assert values_equal(sim.read(0), t.read(0))
+    assert values_equal(sim.read(1), t.read(1))
+    assert sim.step_status(3) == -3 and sim.stats()["step"] == o["step"]
+
+
+def test_layered_and_lattice_media():
+    announce("layered + lattice media")
+    shape = (48, 40, 64)
+    lay = ti.LayeredMedia(np.array([0, 20, 41], np.int32), np.array([1500, 3000, 2200], np.float32))
+    dt = 0.5 / 3000
+    wv = ti.ricker(300.0, dt).w32
+    src = [((24, 20, 18), wv)]
+    phi, prev, _ = oracle.dense_run(lay.dense(*shape), dt, 1.0, 120, np.float32, sources=src)
+    sim = gpu_run(shape, dt, lay, src, 120)
+    assert values_equal(sim.read(0), phi) and values_equal(sim.read(1), prev)
+    lat = ti.lognormal_lattice(shape, seed=12, sigma=6.0, spacing=4)
+    dt = 0.5 / 4500
+    cd = ti.lattice_to_dense(lat, shape)
+    wv = ti.ricker(250.0, dt).w32
+    src = [((10, 30, 50), wv)]
+    phi, prev, _ = oracle.dense_run(cd, dt, 1.0, 130, np.float32, sources=src)
+    sim = gpu_run(shape, dt, lat, src, 130)
+    assert values_equal(sim.read(0), phi) and values_equal(sim.read(1), prev)
+    dsim = gpu_run(shape, dt, lat, src, 130, engine="dense")
+    assert values_equal(dsim.read(0), phi)
+
+
+def test_subnormal_values_are_kept():
+    """Tiny source amplitudes drive the field into FP32 subnormals; flushing
+    them to zero on either side would break equality."""
+    announce("subnormals")
+    shape = (24, 24, 24)
+    c = np.ones(shape, np.float32)
+    w = (ti.ricker(0.15, 0.5).w64 * 1e-39).astype(np.float32)
+    assert np.any((np.abs(w) < np.finfo(np.float32).tiny) & (w != 0))
+    phi, _, _ = oracle.dense_run(c, 0.5, 1.0, 60, np.float32, sources=[((12, 12, 12), w)])
+    assert np.any((np.abs(phi) < np.finfo(np.float32).tiny) & (phi != 0))
+    sim = gpu_run(shape, 0.5, c, [((12, 12, 12), w)], 60)
+    assert values_equal(sim.read(0), phi)
+    dsim = gpu_run(shape, 0.5, c, [((12, 12, 12), w)], 60, engine="dense")
+    assert values_equal(dsim.read(0), phi)
+
+
+def test_launch_modes_and_reads_agree():
+    announce("graphs / no graphs / timing / step splits / box + device reads")
+    import torch
+    w = ti.c1(steps=64)
+    src = [(w.source, w.wavelet.w32)]
+    phi, _, _ = oracle.dense_run(w.c_dense, w.dt, 1.0, 64, np.float32, sources=src)
+    a = gpu_run(w.shape, w.dt, w.c_dense, src, 64, graph_steps=8)
+    b = gpu_run(w.shape, w.dt, w.c_dense, src, 0, graphs=False)
+    for k in range(64):
+        b.step(1)
+    c = gpu_run(w.shape, w.dt, w.c_dense, src, 64, timing=True)
+    for s in (a, b, c):
+        assert values_equal(s.read(0), phi)
+    assert c.stats()["stencil_launches"] == 64 and c.stats()["stencil_ms"] > 0
+    box = a.read(0, box=((3, 17, 30), (20, 9, 11)))
+    assert values_equal(box, phi[30:41, 17:26, 3:23])
+    out = torch.empty(11 * 9 * 20, dtype=torch.float32, device="cuda")
+    a.read(0, box=((3, 17, 30), (20, 9, 11)), out=out)
+    assert values_equal(out.cpu().numpy().reshape(11, 9, 20), phi[30:41, 17:26, 3:23])
+    a.reset()
+    assert not a.read(0).any() and a.stats()["step"] == 0
+    a.add_source(w.source, w.wavelet.w32)
+    a.step(64)
+    assert values_equal(a.read(0), phi)
+
+
+def test_source_added_mid_run():
+    announce("source added after 30 steps")
+    w = ti.c1(steps=80)
+    w2 = ti.ricker(0.2, w.dt).w32
+    # oracle: second source starts at step 30
+    phi, prev, _ = oracle.dense_run(w.c_dense, w.dt, 1.0, 80, np.float32,
+                                    sources=[(w.source, w.wavelet.w32), ((10, 50, 20), w2, 30)])
+    sim = gpu_run(w.shape, w.dt, w.c_dense, [(w.source, w.wavelet.w32)], 30)
+    sim.add_source((10, 50, 20), w2)
+    sim.step(50)
+    assert values_equal(sim.read(0), phi) and values_equal(sim.read(1), prev)
+
+
+def test_input_errors_are_reported():
+    announce("error paths")
+    c = np.ones((16, 16, 16), np.float32)
+    sim = tcm.Simulation((16, 16, 16), 1.0, 0.5, c)
+    with pytest.raises(tcm.TCMError) as ei:
+        sim.add_source((16, 0, 0), np.ones(3, np.float32))
+    assert ei.value.status == -4
+    with pytest.raises(tcm.TCMError) as ei:
+        sim.set_receivers([(0, 0, -1)])
+    assert ei.value.status == -4
+    with pytest.raises(tcm.TCMError) as ei:
+        sim.read(0, box=((10, 0, 0), (7, 1, 1)))
+    assert ei.value.status == -4
+    with pytest.raises(tcm.TCMError) as ei:
+        tcm.Simulation((16, 16, 16), 1.0, 0.6, c)
+    assert ei.value.status == -2
