@@ -91,6 +91,8 @@ def main():
     ap.add_argument("--graphs", action="store_true",
                     help="time with hipGraph replay instead of per-launch HIP events")
     ap.add_argument("--wg-per-cu", type=int, default=0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a 1 GiB device-to-device torch copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the TCM hot path is built and measured on a single "
@@ -145,11 +147,32 @@ def main():
                  "tcm_speedup_wall": round(el / (tot_t / args.steps), 3)}
         log(f"dense: {el:.3f} s ({dense_rate:.3e} node updates/s)")
 
+    copy = None
+    if args.copy_calibration:
+        n = 1 << 28                                   # 1 GiB of float32 per buffer
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        times = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            b.copy_(a)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        copy = {"bytes_read": 4 * n, "bytes_written": 4 * n,
+                "best_GBps": round(8 * n / min(times) / 1e9, 1)}
+        del a, b
+        log(f"copy calibration: {copy}")
+
     err_table = None
-    p = os.path.join(ROOT, "tests", "golden", f"{w.name}_errors.json")
+    p = os.path.join(ROOT, "tests", "golden", f"{w.name}_golden.json")
     if os.path.exists(p):
         with open(p) as f:
-            err_table = json.load(f)
+            g = json.load(f)
+        err_table = {"reference": "FP64 dense oracle, last step, relative L2",
+                     "dense_fp32": g.get("err_dense_fp32"),
+                     "tcm_fp32_at_workload_thresholds": g.get("tcm", {}).get("err"),
+                     "tcm_sweep": g.get("sweep")}
 
     cpu = None
     if not args.no_cpu:
@@ -176,6 +199,7 @@ def main():
                 "us_per_time_step": round(tot_t / args.steps / steps * 1e6, 2)},
         "dense_fdtd": dense,
         "equal_error": err_table,
+        "copy_calibration": copy,
     }
     print(json.dumps(out), flush=True)
 

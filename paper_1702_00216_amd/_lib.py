@@ -65,6 +65,14 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with "
                               "`python -m paper_1702_00216_amd.build` (hipcc, gfx950)")
+        # PyTorch ships its own HIP runtime (same soname as /opt/rocm's).  Load it
+        # first so that libtcm.so binds to that one copy: device pointers and
+        # streams are then shared with torch, and only one runtime opens the GPU.
+        try:
+            import torch  # noqa: F401
+            import torch.cuda  # noqa: F401
+        except Exception:
+            pass
         L = C.CDLL(LIB_PATH)
         P, I, F = C.c_void_p, C.c_int32, C.POINTER
         H = C.c_void_p

@@ -20,7 +20,9 @@ ARCH = os.environ.get("TCM_OFFLOAD_ARCH", "gfx950")
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-ffp-contract=off", "-fno-fast-math",
           "-Wall", "-Wno-unused-result", f"-I{INCLUDE}", f"-I{CSRC}"]
-DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# code object v5 loads under the HIP runtime that PyTorch ships as well as /opt/rocm's
+DEVICE = [f"--offload-arch={ARCH}", "-mcode-object-version=5", "-Xclang", "-target-feature", "-Xclang",
+          "-packed-fp32-ops"]
 
 SOURCES = [("tcm_kernels.hip", True), ("tcm_runtime.cpp", False)]
 

@@ -83,8 +83,8 @@ struct Tables {
     long long* new_key;             // per step: claimed keys
     int* new_shot;
     int* ret_slot;                  // per step: released slots
-    unsigned* partial;              // per compaction workgroup: set-bit counts, then offsets
-    int ncount_wg;                  // compaction workgroups
+    unsigned* partial;              // per 64-word chunk of the bitmap: set bits, then offsets
+    int nchunks;                    // ceil(nwords / 64)
     const Src* src;
     int nsrc;
     const float* srcw;
@@ -96,15 +96,16 @@ struct Tables {
     float trigger, retire;
 };
 
-constexpr int COUNT_WORDS_PER_THREAD = 8;
-constexpr int COUNT_THREADS = 256;
-constexpr int COUNT_WORDS_PER_WG = COUNT_WORDS_PER_THREAD * COUNT_THREADS;
+// The compaction works on chunks of 64 bitmap words (4096 blocks).
+constexpr int CHUNK_WORDS = 64;
+// Upper bound on the workgroups of k_pool_count (it counts chunks in a loop).
+constexpr int POOL_COUNT_MAX_WG = 1024;
 
 // ---- launch wrappers (tcm_kernels.hip) -----------------------------------
 hipError_t launch_init_tables(const Tables& t, long long nkeys, hipStream_t s);
 hipError_t launch_block_step(const Tables& t, int grid, hipStream_t s);
 hipError_t launch_plan(const Tables& t, int grid, hipStream_t s);
-hipError_t launch_pool_count(const Tables& t, int grid, hipStream_t s);
+hipError_t launch_pool_count(const Tables& t, int grid, hipStream_t s);   // grid <= POOL_COUNT_MAX_WG
 hipError_t launch_emit(const Tables& t, hipStream_t s);
 hipError_t launch_activate(const Tables& t, long long key, int shot, unsigned local_key,
                            int pin_until, hipStream_t s);

@@ -375,9 +375,21 @@ __global__ __launch_bounds__(256) void k_plan(Tables t) {
                 atomicOr(&t.bitmap[nk >> 6], 1ull << (nk & 63));
             }
         }
-        if (valid && survive) {
-            const long long G = t.shots[shot].key_base + (long long)key;
-            atomicOr(&t.bitmap[G >> 6], 1ull << (G & 63));
+        // survivors: the list is in key order, so a wave's keys fall in one or
+        // two bitmap words; OR the bits within each run of equal words and let
+        // the first lane of the run do the atomic
+        {
+            const long long G = valid ? t.shots[shot].key_base + (long long)key : -1;
+            const long long word = valid && survive ? (G >> 6) : -1;
+            unsigned long long bits = valid && survive ? (1ull << (G & 63)) : 0ull;
+            const int lane = lane_id();
+            for (int o = 1; o < 64; o <<= 1) {
+                const unsigned long long ob = __shfl_down(bits, o);
+                const long long ow = __shfl_down(word, o);
+                if (lane + o < 64 && ow == word) bits |= ob;
+            }
+            const long long prev_word = __shfl_up(word, 1);
+            if (word >= 0 && (lane == 0 || prev_word != word)) atomicOr(&t.bitmap[word], bits);
         }
         const int kr = wave_append(&st->n_ret, valid && !survive);
         if (kr >= 0) t.ret_slot[kr] = slot;
@@ -395,7 +407,7 @@ hipError_t launch_plan(const Tables& t, int grid, hipStream_t s) {
 // --------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_pool_count(Tables t) {
     DevState* st = t.st;
-    __shared__ unsigned red[256 / 64];
+    __shared__ unsigned red[4];
     __shared__ int last;
     const int lane = lane_id();
     const int wid = threadIdx.x >> 6;
@@ -449,21 +461,17 @@ __global__ __launch_bounds__(256) void k_pool_count(Tables t) {
         }
     }
 
-    // popcount of this workgroup's range of bitmap words
-    unsigned cnt = 0;
-    if (blockIdx.x < t.ncount_wg) {
-        const long long w0 = ((long long)blockIdx.x * COUNT_THREADS + threadIdx.x) * COUNT_WORDS_PER_THREAD;
-#pragma unroll
-        for (int j = 0; j < COUNT_WORDS_PER_THREAD; j++) {
-            const long long w = w0 + j;
-            if (w < t.nwords) cnt += (unsigned)__popcll(t.bitmap[w]);
-        }
+    // popcount of 64-word chunks: wave w of workgroup g counts chunks
+    // (g * 4 + w) + k * (gridDim.x * 4)
+    const int nw = blockDim.x >> 6;
+    for (long long c = (long long)blockIdx.x * nw + wid; c < t.nchunks; c += (long long)gridDim.x * nw) {
+        const long long w = c * CHUNK_WORDS + lane;
+        unsigned cnt = w < t.nwords ? (unsigned)__popcll(t.bitmap[w]) : 0u;
+        for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o);
+        if (lane == 0) t.partial[c] = cnt;
     }
-    for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o);
-    if (lane == 0) red[wid] = cnt;
     __syncthreads();
     if (threadIdx.x == 0) {
-        if (blockIdx.x < t.ncount_wg) t.partial[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
         __threadfence();
         last = atomicAdd(&st->done_wgs, 1) == (int)gridDim.x - 1;
     }
@@ -471,28 +479,28 @@ __global__ __launch_bounds__(256) void k_pool_count(Tables t) {
     if (!last) return;
     __threadfence();
 
-    // last workgroup: exclusive scan of the partial counts, commit counters
-    __shared__ unsigned carry;
-    if (threadIdx.x == 0) carry = 0;
+    // last workgroup: exclusive scan of the chunk counts (each thread a
+    // contiguous run of chunks), then commit the step's counters
+    const int nc = t.nchunks;
+    const int per = (nc + (int)blockDim.x - 1) / (int)blockDim.x;
+    const int c0 = min(nc, (int)threadIdx.x * per), c1 = min(nc, c0 + per);
+    unsigned mine = 0;
+    for (int c = c0; c < c1; c++) mine += __atomic_load_n(&t.partial[c], __ATOMIC_RELAXED);
+    unsigned incl = mine;
+    for (int o = 1; o < 64; o <<= 1) {
+        const unsigned u = __shfl_up(incl, o);
+        if (lane >= o) incl += u;
+    }
+    if (lane == 63) red[wid] = incl;
     __syncthreads();
-    for (int b = 0; b < t.ncount_wg; b += 256) {
-        const int idx = b + threadIdx.x;
-        unsigned v = idx < t.ncount_wg ? __atomic_load_n(&t.partial[idx], __ATOMIC_RELAXED) : 0u;
-        // inclusive wave scan
-        unsigned incl = v;
-        for (int o = 1; o < 64; o <<= 1) {
-            const unsigned u = __shfl_up(incl, o);
-            if (lane >= o) incl += u;
-        }
-        if (lane == 63) red[wid] = incl;
-        __syncthreads();
-        unsigned wofs = 0;
-        for (int w = 0; w < wid; w++) wofs += red[w];
-        const unsigned tot = red[0] + red[1] + red[2] + red[3];
-        if (idx < t.ncount_wg) t.partial[idx] = carry + wofs + incl - v;
-        __syncthreads();
-        if (threadIdx.x == 0) carry += tot;
-        __syncthreads();
+    unsigned run = incl - mine;
+    for (int w = 0; w < wid; w++) run += red[w];
+    unsigned total = 0;
+    for (int w = 0; w < nw; w++) total += red[w];
+    for (int c = c0; c < c1; c++) {
+        const unsigned v = __atomic_load_n(&t.partial[c], __ATOMIC_RELAXED);
+        t.partial[c] = run;
+        run += v;
     }
     if (threadIdx.x == 0) {
         const int err = st->error;
@@ -504,8 +512,8 @@ __global__ __launch_bounds__(256) void k_pool_count(Tables t) {
             st->free_top = top + nr - nn;
             st->activations += (unsigned long long)nn;
             st->retirements += (unsigned long long)nr;
-            st->n_act = (int)carry;
-            if ((int)carry > st->peak_act) st->peak_act = (int)carry;
+            st->n_act = (int)total;
+            if ((int)total > st->peak_act) st->peak_act = (int)total;
             st->cells_cur = 0;
             st->emit = 1;
         } else {
@@ -519,7 +527,8 @@ __global__ __launch_bounds__(256) void k_pool_count(Tables t) {
 }
 
 hipError_t launch_pool_count(const Tables& t, int grid, hipStream_t s) {
-    if (grid < t.ncount_wg) grid = t.ncount_wg;
+    if (grid > POOL_COUNT_MAX_WG) grid = POOL_COUNT_MAX_WG;
+    if (grid < 1) grid = 1;
     hipLaunchKernelGGL(k_pool_count, dim3(grid), dim3(256), 0, s, t);
     return hipGetLastError();
 }
@@ -536,75 +545,56 @@ __device__ __forceinline__ int shot_of_word(const Tables& t, long long w) {
     return lo;
 }
 
+// One workgroup per 64-word chunk.  Every wave loads the chunk (lane = word)
+// and forms the exclusive prefix of the word popcounts; wave v then emits
+// words v, v+4, ... with lane = bit, so each word's blocks are written as
+// one contiguous run in key order.
 __global__ __launch_bounds__(256) void k_emit(Tables t) {
     DevState* st = t.st;
-    __shared__ unsigned wsum[4];
     __shared__ unsigned long long csum[4];
     const int lane = lane_id();
     const int wid = threadIdx.x >> 6;
     const int emit = st->emit;
-    const long long w0 = ((long long)blockIdx.x * COUNT_THREADS + threadIdx.x) * COUNT_WORDS_PER_THREAD;
-    unsigned long long words[COUNT_WORDS_PER_THREAD];
-    unsigned cnt = 0;
-#pragma unroll
-    for (int j = 0; j < COUNT_WORDS_PER_THREAD; j++) {
-        const long long w = w0 + j;
-        words[j] = w < t.nwords ? t.bitmap[w] : 0ull;
-        cnt += (unsigned)__popcll(words[j]);
-    }
-    if (!emit) {
-        // the step failed: undo claims, keep the current list
-#pragma unroll
-        for (int j = 0; j < COUNT_WORDS_PER_THREAD; j++) {
-            unsigned long long m = words[j];
-            if (!m) continue;
-            const long long w = w0 + j;
-            while (m) {
-                const int b = __ffsll((long long)m) - 1;
-                m &= m - 1;
-                const long long G = w * 64 + b;
-                if (t.cell2box[G] == CLAIMED) t.cell2box[G] = EMPTY;
-            }
-            t.bitmap[w] = 0ull;
-        }
-        return;
-    }
-    // exclusive prefix of cnt over the workgroup
+    const long long chunk = blockIdx.x;
+    const long long w_lane = chunk * CHUNK_WORDS + lane;
+    const unsigned long long myword = w_lane < t.nwords ? t.bitmap[w_lane] : 0ull;
+    const unsigned cnt = (unsigned)__popcll(myword);
     unsigned incl = cnt;
     for (int o = 1; o < 64; o <<= 1) {
         const unsigned u = __shfl_up(incl, o);
         if (lane >= o) incl += u;
     }
-    if (lane == 63) wsum[wid] = incl;
-    __syncthreads();
-    unsigned off = t.partial[blockIdx.x] + incl - cnt;
-    for (int w = 0; w < wid; w++) off += wsum[w];
+    const unsigned base = emit ? t.partial[chunk] : 0u;
     unsigned long long cells = 0;
-#pragma unroll
-    for (int j = 0; j < COUNT_WORDS_PER_THREAD; j++) {
-        unsigned long long m = words[j];
-        if (!m) continue;
-        const long long w = w0 + j;
+    for (int j = wid; j < CHUNK_WORDS; j += 4) {
+        const unsigned long long m = __shfl(myword, j);
+        if (m == 0ull) continue;
+        const long long w = chunk * CHUNK_WORDS + j;
+        const bool mine = (m >> lane) & 1ull;
+        const long long G = w * 64 + lane;
+        if (!emit) {
+            // the step failed: undo its claims, keep the current list
+            if (mine && t.cell2box[G] == CLAIMED) t.cell2box[G] = EMPTY;
+            continue;
+        }
+        const unsigned off = base + __shfl(incl - cnt, j) +
+                             (unsigned)__popcll(m & ((1ull << lane) - 1ull));
         const int shot = shot_of_word(t, w);
         const Shot& S = t.shots[shot];
-        while (m) {
-            const int b = __ffsll((long long)m) - 1;
-            m &= m - 1;
-            const long long G = w * 64 + b;
+        if (mine) {
             const unsigned key = (unsigned)(G - S.key_base);
             t.act_slot[off] = t.cell2box[G];
             t.act_shot[off] = shot;
             t.act_key[off] = key;
-            off++;
             int bx, by, bz;
             key_to_block(S, key, bx, by, bz);
             cells += (unsigned long long)block_cells(S, bx, by, bz);
         }
-        t.bitmap[w] = 0ull;
     }
     for (int o = 32; o > 0; o >>= 1) cells += __shfl_xor(cells, o);
     if (lane == 0) csum[wid] = cells;
-    __syncthreads();
+    __syncthreads();                       // every wave has read the chunk
+    if (wid == 0 && w_lane < t.nwords && myword) t.bitmap[w_lane] = 0ull;
     if (threadIdx.x == 0) {
         const unsigned long long c = csum[0] + csum[1] + csum[2] + csum[3];
         if (c) atomicAdd(&st->cells_cur, c);
@@ -612,7 +602,7 @@ __global__ __launch_bounds__(256) void k_emit(Tables t) {
 }
 
 hipError_t launch_emit(const Tables& t, hipStream_t s) {
-    hipLaunchKernelGGL(k_emit, dim3(t.ncount_wg), dim3(256), 0, s, t);
+    hipLaunchKernelGGL(k_emit, dim3(t.nchunks), dim3(256), 0, s, t);
     return hipGetLastError();
 }
 

@@ -348,14 +348,14 @@ tcm_status create_common(const tcm_config* cfg, const tcm_shot* shots, int nshot
     // ---- block engine tables ----
     h->nkeys = word_base * 64;
     t.nwords = word_base;
-    t.ncount_wg = (int)((word_base + COUNT_WORDS_PER_WG - 1) / COUNT_WORDS_PER_WG);
+    t.nchunks = (int)((word_base + CHUNK_WORDS - 1) / CHUNK_WORDS);
     long long nblocks = 0;
     for (const Shot& S : h->shots) nblocks += (long long)S.bx * S.by * S.bz;
     size_t free_b = 0, total_b = 0;
     (void)hipMemGetInfo(&free_b, &total_b);
     // per-slot bookkeeping bytes besides the 6 KiB slot
     const size_t per_slot_tab = 4 + 4 + 4 + 1 + 4 + 8 + 4 + 8 + 4 + 4;
-    const size_t fixed = (size_t)h->nkeys * 4 + (size_t)word_base * 8 + (size_t)t.ncount_wg * 4 + (1 << 20);
+    const size_t fixed = (size_t)h->nkeys * 4 + (size_t)word_base * 8 + (size_t)t.nchunks * 4 + (1 << 20);
     long long cap;
     if (cfg->pool_bytes > 0) {
         cap = (long long)(cfg->pool_bytes / SLOT_BYTES);
@@ -391,7 +391,7 @@ tcm_status create_common(const tcm_config* cfg, const tcm_shot* shots, int nshot
     ok = ok && dalloc(h, &t.new_key, (size_t)cap) == hipSuccess;
     ok = ok && dalloc(h, &t.new_shot, (size_t)cap) == hipSuccess;
     ok = ok && dalloc(h, &t.ret_slot, (size_t)cap) == hipSuccess;
-    ok = ok && dalloc(h, &t.partial, (size_t)t.ncount_wg) == hipSuccess;
+    ok = ok && dalloc(h, &t.partial, (size_t)t.nchunks) == hipSuccess;
     if (!ok) return fail(set_err(h, TCM_E_NOMEM, "device allocation of the block tables failed"));
     h->table_bytes += fixed + (size_t)cap * per_slot_tab;
 
@@ -401,7 +401,7 @@ tcm_status create_common(const tcm_config* cfg, const tcm_shot* shots, int nshot
     const int wpc = cfg->wg_per_cu > 0 ? cfg->wg_per_cu : 8;
     h->grid_step = std::max(8, (h->ncu * wpc + 7) / 8 * 8);
     h->grid_plan = std::max(1, h->ncu * 2);
-    h->grid_pool = std::max(t.ncount_wg, h->ncu * 2);
+    h->grid_pool = std::min(POOL_COUNT_MAX_WG, std::max(64, std::min(t.nchunks, h->ncu)));
     h->gsteps = cfg->graph_steps > 0 ? cfg->graph_steps : 16;
     *out = h;
     return TCM_OK;

@@ -1,0 +1,118 @@
+"""Write the stored expected values of the full-size workloads.
+
+Calls only the CPU oracle (oracle/) and the input generators (tcm_inputs/).
+Usage:  python tests/golden/make_golden.py c2 [--sweep]
+
+c2: the 512^3 two-layer workload, 2000 steps.  Stores
+  * the relative L2 error at the last step against the FP64 dense oracle of
+    the FP32 dense oracle and of the FP32 CPU TCM at the workload's
+    thresholds (trigger 1e-6, retire 1e-7 of the source peak), and with
+    --sweep at trigger = k * peak (retire = trigger / 10) for k in
+    {1e-10, 1e-9, 1e-8, 1e-7, 1e-6, 1e-5};
+  * SHA-256 of the CPU TCM's final phi^n and phi^{n-1} (float32, -0 -> +0),
+    values at 4096 seeded sample nodes, traces at 8 receivers, and its
+    statistics (peak active cells, activations, retirements, node updates).
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import oracle  # noqa: E402
+import tcm_inputs as ti  # noqa: E402
+
+
+def digest(a: np.ndarray) -> str:
+    a = np.ascontiguousarray(a, dtype=np.float32) + np.float32(0.0)   # -0 -> +0
+    return hashlib.sha256(a.tobytes()).hexdigest()
+
+
+def relerr(a, ref) -> float:
+    return float(np.linalg.norm(a.astype(np.float64) - ref) / np.linalg.norm(ref))
+
+
+def c2_receivers(shape):
+    nx, ny, nz = shape
+    return [(nx // 2, ny // 2, nz // 4), (nx // 4, ny // 2, nz // 8), (nx - 3, 5, 2),
+            (nx // 2, ny // 2, nz - 2), (17, ny - 9, nz // 2), (nx // 2 + 1, ny // 2, nz // 2),
+            (3, 3, 3), (nx // 3, 2 * ny // 3, 3 * nz // 5)]
+
+
+def sample_nodes(shape, n=4096, seed=77):
+    nx, ny, nz = shape
+    rng = np.random.default_rng(seed)
+    return np.stack([rng.integers(0, nx, n), rng.integers(0, ny, n), rng.integers(0, nz, n)], 1)
+
+
+def log(m):
+    print(f"[golden {time.strftime('%H:%M:%S')}] {m}", flush=True)
+
+
+def make_c2(sweep: bool):
+    w = ti.c2()
+    c = w.layered.dense(*w.shape)
+    out_path = os.path.join(HERE, "c2_golden.json")
+    res = json.load(open(out_path)) if os.path.exists(out_path) else {}
+    res["workload"] = {"shape": w.shape, "steps": w.steps, "dt": w.dt, "source": w.source,
+                       "trigger": w.trigger, "retire": w.retire, "peak": w.wavelet.peak}
+    t0 = time.time()
+    ref, _, _ = oracle.dense_run(c.astype(np.float64), w.dt, w.dx, w.steps, np.float64,
+                                 sources=[(w.source, w.wavelet.w32.astype(np.float64))])
+    log(f"FP64 dense done in {time.time() - t0:.0f} s")
+    t0 = time.time()
+    d32, _, _ = oracle.dense_run(c, w.dt, w.dx, w.steps, np.float32, sources=[(w.source, w.wavelet.w32)])
+    res["err_dense_fp32"] = relerr(d32, ref)
+    res["dense_fp32_sha256"] = digest(d32)
+    del d32
+    log(f"FP32 dense done in {time.time() - t0:.0f} s, err {res['err_dense_fp32']:.3e}")
+    rec = c2_receivers(w.shape)
+    t0 = time.time()
+    t = oracle.TCM(c, w.dt, w.dx, np.float32(w.trigger), np.float32(w.retire))
+    t.add_source(w.source, w.wavelet.w32)
+    t.set_receivers(rec)
+    rc, tr = t.step(w.steps, traces=True)
+    assert rc == 0
+    phi, prev = t.read(0), t.read(1)
+    st = t.stats()
+    t.close()
+    log(f"FP32 CPU TCM done in {time.time() - t0:.0f} s")
+    nodes = sample_nodes(w.shape)
+    res["tcm"] = {"err": relerr(phi, ref), "phi_sha256": digest(phi), "prev_sha256": digest(prev),
+                  "stats": st, "receivers": rec, "traces_sha256": digest(tr),
+                  "traces_last": tr[-1].tolist(),
+                  "sample_nodes": nodes.tolist(),
+                  "sample_phi": phi[nodes[:, 2], nodes[:, 1], nodes[:, 0]].tolist()}
+    json.dump(res, open(out_path, "w"))
+    log(f"TCM err {res['tcm']['err']:.3e}, stats {st}")
+    if sweep:
+        res.setdefault("sweep", {})
+        for k in (1e-10, 1e-9, 1e-8, 1e-7, 1e-6, 1e-5):
+            t0 = time.time()
+            trig = np.float32(k * w.wavelet.peak)
+            t = oracle.TCM(c, w.dt, w.dx, trig, np.float32(trig / 10))
+            t.add_source(w.source, w.wavelet.w32)
+            assert t.step(w.steps) == 0
+            p = t.read(0)
+            s = t.stats()
+            t.close()
+            res["sweep"][f"{k:g}"] = {"err": relerr(p, ref), "updates": s["updates"],
+                                      "peak_active": s["peak_active"], "sha256": digest(p)}
+            json.dump(res, open(out_path, "w"))
+            log(f"sweep {k:g}: err {res['sweep'][f'{k:g}']['err']:.3e} updates {s['updates']:.3e} "
+                f"({time.time() - t0:.0f} s)")
+
+
+if __name__ == "__main__":
+    which = sys.argv[1] if len(sys.argv) > 1 else "c2"
+    if which == "c2":
+        make_c2("--sweep" in sys.argv)
+    else:
+        raise SystemExit(f"unknown workload {which}")
