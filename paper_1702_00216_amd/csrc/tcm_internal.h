@@ -76,6 +76,7 @@ struct Tables {
     int* act_slot;                  // active list (length n_act)
     int* act_shot;
     unsigned* act_key;              // key inside the shot
+    int* rows;                      // per list entry: slot, 6 neighbour slots (or EMPTY), global key
     unsigned char* flags;           // per slot: face bits 0..5 and KEEP_BIT
     int* pin_until;                 // per slot: active while step < pin_until (sources)
     long long* slot_key;            // per slot: global key or -1
@@ -104,6 +105,7 @@ constexpr int POOL_COUNT_MAX_WG = 1024;
 // ---- launch wrappers (tcm_kernels.hip) -----------------------------------
 hipError_t launch_init_tables(const Tables& t, long long nkeys, hipStream_t s);
 hipError_t launch_block_step(const Tables& t, int grid, hipStream_t s);
+int block_step_occupancy();        // resident 256-thread workgroups per CU
 hipError_t launch_plan(const Tables& t, int grid, hipStream_t s);
 hipError_t launch_pool_count(const Tables& t, int grid, hipStream_t s);   // grid <= POOL_COUNT_MAX_WG
 hipError_t launch_emit(const Tables& t, hipStream_t s);

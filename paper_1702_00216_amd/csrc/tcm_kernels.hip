@@ -30,6 +30,15 @@ namespace tcmk {
 // --------------------------------------------------------------------------
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
+// Read-only (for the reading kernel) tables addressed uniformly by a wave are
+// read through the scalar data cache: constant address space loads.
+template <class T>
+using scalar_ptr = const __attribute__((address_space(4))) T*;
+template <class T>
+__device__ __forceinline__ scalar_ptr<T> as_scalar(const T* p) {
+    return (scalar_ptr<T>)(p);
+}
+
 // Order LDS writes and reads of one wave (the wave runs in lockstep; this
 // only stops the compiler from moving LDS accesses across the point).
 __device__ __forceinline__ void wave_lds_sync() {
@@ -191,19 +200,27 @@ __global__ __launch_bounds__(256) void k_block_step(Tables t) {
     const int end = min(nact, beg + seg);
     const float trig = t.trigger, ret = t.retire;
 
-    for (int i = beg + jw * 4 + wid; i < end; i += per * 4) {
-        const int slot = __builtin_amdgcn_readfirstlane(t.act_slot[i]);
-        const int shot = __builtin_amdgcn_readfirstlane(t.act_shot[i]);
-        const unsigned key = (unsigned)__builtin_amdgcn_readfirstlane((int)t.act_key[i]);
-        const Shot& S = t.shots[shot];
-        int bx, by, bz;
-        key_to_block(S, key, bx, by, bz);
-        int nb[6];
+    // Each list entry has a row {slot, 6 neighbour slots, global key} written by
+    // the compaction; the next row is fetched while the current block is
+    // processed, so only the data loads sit on the critical path.
+    const scalar_ptr<int> rows = as_scalar((const int*)t.rows);
+    const scalar_ptr<int> pin_until = as_scalar((const int*)t.pin_until);
+    const int stride = per * 4;
+    int i = beg + jw * 4 + wid;
+    int r[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (i < end) {
 #pragma unroll
-        for (int d = 0; d < 6; d++) {
-            const long long k = neighbour_key(S, bx, by, bz, d);
-            nb[d] = k >= 0 ? __builtin_amdgcn_readfirstlane(t.cell2box[k]) : EMPTY;
+        for (int k = 0; k < 8; k++) r[k] = rows[8 * (size_t)i + k];
+    }
+    for (; i < end; i += stride) {
+        const int slot = r[0];
+        const int nb[6] = {r[1], r[2], r[3], r[4], r[5], r[6]};
+        const int G = r[7];
+        if (i + stride < end) {
+#pragma unroll
+            for (int k = 0; k < 8; k++) r[k] = rows[8 * (size_t)(i + stride) + k];
         }
+        const int pinned = t.nsrc > 0 ? pin_until[slot] : 0;
         const float* __restrict__ blk = t.pool + (size_t)slot * SLOT;
         const float* __restrict__ cur_p = blk + p * BV;
         float* __restrict__ out_p = (float*)blk + (1 - p) * BV;
@@ -264,11 +281,10 @@ __global__ __launch_bounds__(256) void k_block_step(Tables t) {
             nv[z] = (2.0f * cur[z] - prv[z]) + k2[z] * lap;
         }
         // additive source insertion (before the predicates)
-        if (t.nsrc > 0 && t.pin_until[slot] > n) {
-            const long long G = S.key_base + (long long)key;
+        if (pinned > n) {
             for (int s = 0; s < t.nsrc; s++) {
                 const Src e = t.src[s];
-                if (e.key != G) continue;
+                if (e.key != (long long)G) continue;
                 const int k = n - e.t0;
                 if (k < 0 || k >= e.ns) continue;
                 const float w = t.srcw[e.w_off + k];
@@ -306,6 +322,12 @@ __global__ __launch_bounds__(256) void k_block_step(Tables t) {
             t.flags[slot] = (unsigned char)f;
         }
     }
+}
+
+int block_step_occupancy() {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_block_step, 256, 0) != hipSuccess) return 0;
+    return nb;
 }
 
 hipError_t launch_block_step(const Tables& t, int grid, hipStream_t s) {
@@ -583,12 +605,22 @@ __global__ __launch_bounds__(256) void k_emit(Tables t) {
         const Shot& S = t.shots[shot];
         if (mine) {
             const unsigned key = (unsigned)(G - S.key_base);
-            t.act_slot[off] = t.cell2box[G];
+            const int slot = t.cell2box[G];
+            t.act_slot[off] = slot;
             t.act_shot[off] = shot;
             t.act_key[off] = key;
             int bx, by, bz;
             key_to_block(S, key, bx, by, bz);
             cells += (unsigned long long)block_cells(S, bx, by, bz);
+            int nb[6];
+#pragma unroll
+            for (int d = 0; d < 6; d++) {
+                const long long nk = neighbour_key(S, bx, by, bz, d);
+                nb[d] = nk >= 0 ? t.cell2box[nk] : EMPTY;
+            }
+            int4* rp = (int4*)(t.rows + 8 * (size_t)off);
+            rp[0] = make_int4(slot, nb[0], nb[1], nb[2]);
+            rp[1] = make_int4(nb[3], nb[4], nb[5], (int)G);
         }
     }
     for (int o = 32; o > 0; o >>= 1) cells += __shfl_xor(cells, o);
@@ -646,6 +678,14 @@ __global__ __launch_bounds__(64) void k_activate(Tables t, long long G, int shot
         t.act_slot[i] = slot;
         t.act_shot[i] = shot;
         t.act_key[i] = key;
+        int nb[6];
+        for (int d = 0; d < 6; d++) {
+            const long long nk = neighbour_key(S, bx, by, bz, d);
+            nb[d] = nk >= 0 ? t.cell2box[nk] : EMPTY;
+        }
+        int4* rp = (int4*)(t.rows + 8 * (size_t)i);
+        rp[0] = make_int4(slot, nb[0], nb[1], nb[2]);
+        rp[1] = make_int4(nb[3], nb[4], nb[5], (int)G);
         st->n_act = i + 1;
         if (i + 1 > st->peak_act) st->peak_act = i + 1;
         st->cells_cur += (unsigned long long)block_cells(S, bx, by, bz);

@@ -347,6 +347,8 @@ tcm_status create_common(const tcm_config* cfg, const tcm_shot* shots, int nshot
 
     // ---- block engine tables ----
     h->nkeys = word_base * 64;
+    if (h->nkeys > 0x7fffffffLL)
+        return fail(set_err(h, TCM_E_ARG, "more than 2^31 block keys: grid too large for one handle"));
     t.nwords = word_base;
     t.nchunks = (int)((word_base + CHUNK_WORDS - 1) / CHUNK_WORDS);
     long long nblocks = 0;
@@ -354,7 +356,7 @@ tcm_status create_common(const tcm_config* cfg, const tcm_shot* shots, int nshot
     size_t free_b = 0, total_b = 0;
     (void)hipMemGetInfo(&free_b, &total_b);
     // per-slot bookkeeping bytes besides the 6 KiB slot
-    const size_t per_slot_tab = 4 + 4 + 4 + 1 + 4 + 8 + 4 + 8 + 4 + 4;
+    const size_t per_slot_tab = 4 + 4 + 4 + 32 + 1 + 4 + 8 + 4 + 8 + 4 + 4;
     const size_t fixed = (size_t)h->nkeys * 4 + (size_t)word_base * 8 + (size_t)t.nchunks * 4 + (1 << 20);
     long long cap;
     if (cfg->pool_bytes > 0) {
@@ -384,6 +386,7 @@ tcm_status create_common(const tcm_config* cfg, const tcm_shot* shots, int nshot
     ok = ok && dalloc(h, &t.act_slot, (size_t)cap) == hipSuccess;
     ok = ok && dalloc(h, &t.act_shot, (size_t)cap) == hipSuccess;
     ok = ok && dalloc(h, &t.act_key, (size_t)cap) == hipSuccess;
+    ok = ok && dalloc(h, &t.rows, (size_t)cap * 8) == hipSuccess;
     ok = ok && dalloc(h, &t.flags, (size_t)cap) == hipSuccess;
     ok = ok && dalloc(h, &t.pin_until, (size_t)cap) == hipSuccess;
     ok = ok && dalloc(h, &t.slot_key, (size_t)cap) == hipSuccess;
@@ -398,8 +401,11 @@ tcm_status create_common(const tcm_config* cfg, const tcm_shot* shots, int nshot
     if (launch_init_tables(t, h->nkeys, h->stream) != hipSuccess) return fail(dev_fail(h, hipGetLastError(), "init_tables"));
     if (hipStreamSynchronize(h->stream) != hipSuccess) return fail(dev_fail(h, hipGetLastError(), "sync"));
 
-    const int wpc = cfg->wg_per_cu > 0 ? cfg->wg_per_cu : 8;
-    h->grid_step = std::max(8, (h->ncu * wpc + 7) / 8 * 8);
+    // persistent stencil grid: exactly the resident workgroups (a larger grid
+    // would leave a tail of workgroups that start after the first wave of them)
+    const int occ = block_step_occupancy();
+    const int wpc = cfg->wg_per_cu > 0 ? cfg->wg_per_cu : (occ > 0 ? occ : 4);
+    h->grid_step = std::max(8, (h->ncu * wpc) / 8 * 8);
     h->grid_plan = std::max(1, h->ncu * 2);
     h->grid_pool = std::min(POOL_COUNT_MAX_WG, std::max(64, std::min(t.nchunks, h->ncu)));
     h->gsteps = cfg->graph_steps > 0 ? cfg->graph_steps : 16;
