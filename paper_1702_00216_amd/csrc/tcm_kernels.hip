@@ -838,4 +838,85 @@ hipError_t launch_read_dense(const float* f, int nx, int ny, int x0, int y0, int
     return hipGetLastError();
 }
 
+// --------------------------------------------------------------------------
+// adjoint support: receiver coefficients, gradient accumulation, final scale
+// --------------------------------------------------------------------------
+__global__ void k_receiver_c2(const Shot* shots, const int* xyz, const int* rshot, int nrec,
+                              double dt, double dx, float* out) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrec) return;
+    const Shot& S = shots[rshot ? rshot[r] : 0];
+    out[r] = coeff_c2(media_speed(S, xyz[3 * r], xyz[3 * r + 1], xyz[3 * r + 2]), dt, dx);
+}
+
+hipError_t launch_receiver_c2(const Shot* shots, const int* xyz, const int* rshot, int nrec,
+                              double dt, double dx, float* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_receiver_c2, dim3((nrec + 255) / 256), dim3(256), 0, s, shots, xyz, rshot,
+                       nrec, dt, dx, out);
+    return hipGetLastError();
+}
+
+// g += mu^m * (L u^{m-1}) over the blocks where the adjoint field is active
+// (mu is zero elsewhere).  mu: current level of the adjoint tables; u: the
+// forward level as a dense grid of shot 0; L with zero ghosts, in FP64.
+__global__ __launch_bounds__(256) void k_adjoint_grad(Tables mu, const float* __restrict__ u,
+                                                       double* __restrict__ g) {
+    const DevState* st = mu.st;
+    const int nact = st->n_act;
+    const int plane = st->step & 1;
+    const Shot& S = mu.shots[0];
+    const int lane = lane_id();
+    const int x = lane & 7, y = lane >> 3;
+    const size_t sy = (size_t)S.nx, sz = (size_t)S.nx * S.ny;
+    const int nwaves = gridDim.x * (blockDim.x >> 6);
+    for (int i = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); i < nact; i += nwaves) {
+        const int slot = mu.act_slot[i];
+        int bx, by, bz;
+        key_to_block(S, mu.act_key[i], bx, by, bz);
+        const int gx = bx * BE + x, gy = by * BE + y;
+        if (gx >= S.nx || gy >= S.ny) continue;
+        const float* m = mu.pool + (size_t)slot * SLOT + plane * BV;
+        for (int z = 0; z < BE; z++) {
+            const int gz = bz * BE + z;
+            if (gz >= S.nz) break;
+            const size_t idx = (size_t)gz * sz + (size_t)gy * sy + (size_t)gx;
+            const double c = u[idx];
+            const double xm = gx > 0 ? u[idx - 1] : 0.0, xp = gx + 1 < S.nx ? u[idx + 1] : 0.0;
+            const double ym = gy > 0 ? u[idx - sy] : 0.0, yp = gy + 1 < S.ny ? u[idx + sy] : 0.0;
+            const double zm = gz > 0 ? u[idx - sz] : 0.0, zp = gz + 1 < S.nz ? u[idx + sz] : 0.0;
+            const double lap = (((xp + xm) + (yp + ym)) + (zp + zm)) - 6.0 * c;
+            g[idx] += (double)m[z * 64 + lane] * lap;
+        }
+    }
+}
+
+hipError_t launch_adjoint_grad(const Tables& mu, int grid, const float* u, double* g, hipStream_t s) {
+    hipLaunchKernelGGL(k_adjoint_grad, dim3(grid), dim3(256), 0, s, mu, u, g);
+    return hipGetLastError();
+}
+
+// dJ/dc = (2 / c) g, zero where c = 0 (there dC2/dc = 0)
+__global__ void k_grad_finish(const Shot* dshot, const double* g, float* out) {
+    const Shot& S = *dshot;
+    const long long total = (long long)S.nx * S.ny * S.nz;
+    const long long gs = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gs) {
+        const int gx = (int)(i % S.nx);
+        const long long r = i / S.nx;
+        const int gy = (int)(r % S.ny), gz = (int)(r / S.ny);
+        const double c = media_speed(S, gx, gy, gz);
+        out[i] = c != 0.0 ? (float)(2.0 / c * g[i]) : 0.f;
+    }
+}
+
+hipError_t launch_grad_finish(const Shot& shot, const Shot* dshot, const double* g, float* out,
+                              hipStream_t s) {
+    const long long total = (long long)shot.nx * shot.ny * shot.nz;
+    long long grid = (total + 255) / 256;
+    if (grid > 65536) grid = 65536;
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL(k_grad_finish, dim3((unsigned)grid), dim3(256), 0, s, dshot, g, out);
+    return hipGetLastError();
+}
+
 }  // namespace tcmk

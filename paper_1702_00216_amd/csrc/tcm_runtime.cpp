@@ -92,6 +92,19 @@ struct tcm_handle {
     size_t scratch_bytes = 0;
 
     DevState* h_state = nullptr;        // pinned mirror of the device counters
+
+    // receivers as given (positions of the adjoint sources)
+    std::vector<int> rec_xyz, rec_shot;
+
+    // forward checkpoints for tcm_adjoint: full copies of the block-engine
+    // state at levels 0, K, 2K, ... (K = checkpoint_every)
+    struct Ckpt {
+        long long step = -1;
+        char* buf = nullptr;
+    };
+    std::vector<Ckpt> ckpts;
+    bool in_adjoint = false;
+    tcm_handle* adj = nullptr;          // tables of the adjoint field (shares the media)
 };
 
 namespace {
@@ -231,6 +244,11 @@ void destroy_all(tcm_handle* h) {
     if (!h) return;
     (void)hipSetDevice(h->device);
     if (h->stream) (void)hipStreamSynchronize(h->stream);
+    if (h->adj) destroy_all(h->adj);
+    h->adj = nullptr;
+    for (auto& c : h->ckpts)
+        if (c.buf) (void)hipFree(c.buf);
+    h->ckpts.clear();
     drop_graph(h);
     for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
     h->events.clear();
@@ -239,6 +257,105 @@ void destroy_all(tcm_handle* h) {
     if (h->h_state) (void)hipHostFree(h->h_state);
     if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
     delete h;
+}
+
+// Device state of the engine (dense arrays or block tables) for the shots
+// already in h->shots / h->d_shots.
+tcm_status setup_engine(tcm_handle* h, long long word_base) {
+    const tcm_config* cfg = &h->cfg;
+    const int nshots = (int)h->shots.size();
+    Tables& t = h->t;
+    t.shots = h->d_shots;
+    t.nshots = nshots;
+    t.dt = cfg->dt;
+    t.dx = cfg->dx;
+    t.trigger = cfg->trigger;
+    t.retire = cfg->retire;
+    if (hipMalloc((void**)&t.st, sizeof(DevState)) != hipSuccess) return dev_fail(h, hipErrorOutOfMemory, "hipMalloc(state)");
+    h->allocs.push_back(t.st);
+    if (hipMemsetAsync(t.st, 0, sizeof(DevState), h->stream) != hipSuccess) return dev_fail(h, hipGetLastError(), "hipMemset(state)");
+
+    if (h->engine == TCM_ENGINE_DENSE) {
+        const Shot& S = h->shots[0];
+        const size_t N = (size_t)S.nx * S.ny * S.nz;
+        if (dalloc(h, &h->d_phi[0], N) != hipSuccess || dalloc(h, &h->d_phi[1], N) != hipSuccess ||
+            dalloc(h, &h->d_c2, N) != hipSuccess)
+            return set_err(h, TCM_E_NOMEM, "dense engine: device allocation failed");
+        h->table_bytes += 3 * N * sizeof(float);
+        if (hipMemsetAsync(h->d_phi[0], 0, N * sizeof(float), h->stream) != hipSuccess ||
+            hipMemsetAsync(h->d_phi[1], 0, N * sizeof(float), h->stream) != hipSuccess)
+            return dev_fail(h, hipGetLastError(), "hipMemset(dense)");
+        if (launch_media_c2(S, h->d_shots, cfg->dt, cfg->dx, h->d_c2, h->stream) != hipSuccess)
+            return dev_fail(h, hipGetLastError(), "media_c2");
+        if (hipStreamSynchronize(h->stream) != hipSuccess) return dev_fail(h, hipGetLastError(), "sync");
+        return TCM_OK;
+    }
+
+    // ---- block engine tables ----
+    h->nkeys = word_base * 64;
+    if (h->nkeys > 0x7fffffffLL)
+        return set_err(h, TCM_E_ARG, "more than 2^31 block keys: grid too large for one handle");
+    t.nwords = word_base;
+    t.nchunks = (int)((word_base + CHUNK_WORDS - 1) / CHUNK_WORDS);
+    long long nblocks = 0;
+    for (const Shot& S : h->shots) nblocks += (long long)S.bx * S.by * S.bz;
+    size_t free_b = 0, total_b = 0;
+    (void)hipMemGetInfo(&free_b, &total_b);
+    // per-slot bookkeeping bytes besides the 6 KiB slot
+    const size_t per_slot_tab = 4 + 4 + 4 + 32 + 1 + 4 + 8 + 4 + 8 + 4 + 4;
+    const size_t fixed = (size_t)h->nkeys * 4 + (size_t)word_base * 8 + (size_t)t.nchunks * 4 + (1 << 20);
+    long long cap;
+    if (cfg->pool_bytes > 0) {
+        cap = (long long)(cfg->pool_bytes / SLOT_BYTES);
+        if (cap < 1) return set_err(h, TCM_E_ARG, "pool_bytes is below one slot (6 KiB)");
+        if (!cfg->device_pool && (double)cap * (SLOT_BYTES + per_slot_tab) + fixed > 0.95 * (double)free_b)
+            return set_err(h, TCM_E_NOMEM, fmt("pool of %lld slots does not fit in %.1f GB free", cap, free_b / 1e9));
+    } else {
+        cap = nblocks;
+        const double room = 0.9 * (double)free_b - (double)fixed;
+        const long long fit = room > 0 ? (long long)(room / (double)(SLOT_BYTES + per_slot_tab)) : 0;
+        if (cap > fit) cap = fit;
+        if (cap < 1) return set_err(h, TCM_E_NOMEM, "no device memory for the pool");
+    }
+    if (cap > nblocks) cap = nblocks;
+    if (cap > 0x7fffffffLL) cap = 0x7fffffffLL;
+    t.cap = (int)cap;
+
+    bool ok = true;
+    if (cfg->device_pool) {
+        t.pool = (float*)cfg->device_pool;
+    } else {
+        ok = ok && dalloc(h, &t.pool, (size_t)cap * SLOT) == hipSuccess;
+    }
+    ok = ok && dalloc(h, &t.cell2box, (size_t)h->nkeys) == hipSuccess;
+    ok = ok && dalloc(h, &t.bitmap, (size_t)word_base) == hipSuccess;
+    ok = ok && dalloc(h, &t.act_slot, (size_t)cap) == hipSuccess;
+    ok = ok && dalloc(h, &t.act_shot, (size_t)cap) == hipSuccess;
+    ok = ok && dalloc(h, &t.act_key, (size_t)cap) == hipSuccess;
+    ok = ok && dalloc(h, &t.rows, (size_t)cap * 8) == hipSuccess;
+    ok = ok && dalloc(h, &t.flags, (size_t)cap) == hipSuccess;
+    ok = ok && dalloc(h, &t.pin_until, (size_t)cap) == hipSuccess;
+    ok = ok && dalloc(h, &t.slot_key, (size_t)cap) == hipSuccess;
+    ok = ok && dalloc(h, &t.free_stack, (size_t)cap) == hipSuccess;
+    ok = ok && dalloc(h, &t.new_key, (size_t)cap) == hipSuccess;
+    ok = ok && dalloc(h, &t.new_shot, (size_t)cap) == hipSuccess;
+    ok = ok && dalloc(h, &t.ret_slot, (size_t)cap) == hipSuccess;
+    ok = ok && dalloc(h, &t.partial, (size_t)t.nchunks) == hipSuccess;
+    if (!ok) return set_err(h, TCM_E_NOMEM, "device allocation of the block tables failed");
+    h->table_bytes += fixed + (size_t)cap * per_slot_tab;
+
+    if (launch_init_tables(t, h->nkeys, h->stream) != hipSuccess) return dev_fail(h, hipGetLastError(), "init_tables");
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return dev_fail(h, hipGetLastError(), "sync");
+
+    // persistent stencil grid: exactly the resident workgroups (a larger grid
+    // would leave a tail of workgroups that start after the first wave of them)
+    const int occ = block_step_occupancy();
+    const int wpc = cfg->wg_per_cu > 0 ? cfg->wg_per_cu : (occ > 0 ? occ : 4);
+    h->grid_step = std::max(8, (h->ncu * wpc) / 8 * 8);
+    h->grid_plan = std::max(1, h->ncu * 2);
+    h->grid_pool = std::min(POOL_COUNT_MAX_WG, std::max(64, std::min(t.nchunks, h->ncu)));
+    h->gsteps = cfg->graph_steps > 0 ? cfg->graph_steps : 16;
+    return TCM_OK;
 }
 
 tcm_status create_common(const tcm_config* cfg, const tcm_shot* shots, int nshots, tcm_handle** out) {
@@ -317,98 +434,8 @@ tcm_status create_common(const tcm_config* cfg, const tcm_shot* shots, int nshot
     if (hipMemcpy(h->d_shots, h->shots.data(), sizeof(Shot) * nshots, hipMemcpyHostToDevice) != hipSuccess)
         return fail(dev_fail(h, hipGetLastError(), "hipMemcpy(shots)"));
 
-    Tables& t = h->t;
-    t.shots = h->d_shots;
-    t.nshots = nshots;
-    t.dt = cfg->dt;
-    t.dx = cfg->dx;
-    t.trigger = cfg->trigger;
-    t.retire = cfg->retire;
-    if (hipMalloc((void**)&t.st, sizeof(DevState)) != hipSuccess) return fail(dev_fail(h, hipErrorOutOfMemory, "hipMalloc(state)"));
-    h->allocs.push_back(t.st);
-    if (hipMemsetAsync(t.st, 0, sizeof(DevState), h->stream) != hipSuccess) return fail(dev_fail(h, hipGetLastError(), "hipMemset(state)"));
-
-    if (h->engine == TCM_ENGINE_DENSE) {
-        const Shot& S = h->shots[0];
-        const size_t N = (size_t)S.nx * S.ny * S.nz;
-        if (dalloc(h, &h->d_phi[0], N) != hipSuccess || dalloc(h, &h->d_phi[1], N) != hipSuccess ||
-            dalloc(h, &h->d_c2, N) != hipSuccess)
-            return fail(set_err(h, TCM_E_NOMEM, "dense engine: device allocation failed"));
-        h->table_bytes += 3 * N * sizeof(float);
-        if (hipMemsetAsync(h->d_phi[0], 0, N * sizeof(float), h->stream) != hipSuccess ||
-            hipMemsetAsync(h->d_phi[1], 0, N * sizeof(float), h->stream) != hipSuccess)
-            return fail(dev_fail(h, hipGetLastError(), "hipMemset(dense)"));
-        if (launch_media_c2(S, h->d_shots, cfg->dt, cfg->dx, h->d_c2, h->stream) != hipSuccess)
-            return fail(dev_fail(h, hipGetLastError(), "media_c2"));
-        if (hipStreamSynchronize(h->stream) != hipSuccess) return fail(dev_fail(h, hipGetLastError(), "sync"));
-        *out = h;
-        return TCM_OK;
-    }
-
-    // ---- block engine tables ----
-    h->nkeys = word_base * 64;
-    if (h->nkeys > 0x7fffffffLL)
-        return fail(set_err(h, TCM_E_ARG, "more than 2^31 block keys: grid too large for one handle"));
-    t.nwords = word_base;
-    t.nchunks = (int)((word_base + CHUNK_WORDS - 1) / CHUNK_WORDS);
-    long long nblocks = 0;
-    for (const Shot& S : h->shots) nblocks += (long long)S.bx * S.by * S.bz;
-    size_t free_b = 0, total_b = 0;
-    (void)hipMemGetInfo(&free_b, &total_b);
-    // per-slot bookkeeping bytes besides the 6 KiB slot
-    const size_t per_slot_tab = 4 + 4 + 4 + 32 + 1 + 4 + 8 + 4 + 8 + 4 + 4;
-    const size_t fixed = (size_t)h->nkeys * 4 + (size_t)word_base * 8 + (size_t)t.nchunks * 4 + (1 << 20);
-    long long cap;
-    if (cfg->pool_bytes > 0) {
-        cap = (long long)(cfg->pool_bytes / SLOT_BYTES);
-        if (cap < 1) return fail(set_err(h, TCM_E_ARG, "pool_bytes is below one slot (6 KiB)"));
-        if (!cfg->device_pool && (double)cap * (SLOT_BYTES + per_slot_tab) + fixed > 0.95 * (double)free_b)
-            return fail(set_err(h, TCM_E_NOMEM, fmt("pool of %lld slots does not fit in %.1f GB free", cap, free_b / 1e9)));
-    } else {
-        cap = nblocks;
-        const double room = 0.9 * (double)free_b - (double)fixed;
-        const long long fit = room > 0 ? (long long)(room / (double)(SLOT_BYTES + per_slot_tab)) : 0;
-        if (cap > fit) cap = fit;
-        if (cap < 1) return fail(set_err(h, TCM_E_NOMEM, "no device memory for the pool"));
-    }
-    if (cap > nblocks) cap = nblocks;
-    if (cap > 0x7fffffffLL) cap = 0x7fffffffLL;
-    t.cap = (int)cap;
-
-    bool ok = true;
-    if (cfg->device_pool) {
-        t.pool = (float*)cfg->device_pool;
-    } else {
-        ok = ok && dalloc(h, &t.pool, (size_t)cap * SLOT) == hipSuccess;
-    }
-    ok = ok && dalloc(h, &t.cell2box, (size_t)h->nkeys) == hipSuccess;
-    ok = ok && dalloc(h, &t.bitmap, (size_t)word_base) == hipSuccess;
-    ok = ok && dalloc(h, &t.act_slot, (size_t)cap) == hipSuccess;
-    ok = ok && dalloc(h, &t.act_shot, (size_t)cap) == hipSuccess;
-    ok = ok && dalloc(h, &t.act_key, (size_t)cap) == hipSuccess;
-    ok = ok && dalloc(h, &t.rows, (size_t)cap * 8) == hipSuccess;
-    ok = ok && dalloc(h, &t.flags, (size_t)cap) == hipSuccess;
-    ok = ok && dalloc(h, &t.pin_until, (size_t)cap) == hipSuccess;
-    ok = ok && dalloc(h, &t.slot_key, (size_t)cap) == hipSuccess;
-    ok = ok && dalloc(h, &t.free_stack, (size_t)cap) == hipSuccess;
-    ok = ok && dalloc(h, &t.new_key, (size_t)cap) == hipSuccess;
-    ok = ok && dalloc(h, &t.new_shot, (size_t)cap) == hipSuccess;
-    ok = ok && dalloc(h, &t.ret_slot, (size_t)cap) == hipSuccess;
-    ok = ok && dalloc(h, &t.partial, (size_t)t.nchunks) == hipSuccess;
-    if (!ok) return fail(set_err(h, TCM_E_NOMEM, "device allocation of the block tables failed"));
-    h->table_bytes += fixed + (size_t)cap * per_slot_tab;
-
-    if (launch_init_tables(t, h->nkeys, h->stream) != hipSuccess) return fail(dev_fail(h, hipGetLastError(), "init_tables"));
-    if (hipStreamSynchronize(h->stream) != hipSuccess) return fail(dev_fail(h, hipGetLastError(), "sync"));
-
-    // persistent stencil grid: exactly the resident workgroups (a larger grid
-    // would leave a tail of workgroups that start after the first wave of them)
-    const int occ = block_step_occupancy();
-    const int wpc = cfg->wg_per_cu > 0 ? cfg->wg_per_cu : (occ > 0 ? occ : 4);
-    h->grid_step = std::max(8, (h->ncu * wpc) / 8 * 8);
-    h->grid_plan = std::max(1, h->ncu * 2);
-    h->grid_pool = std::min(POOL_COUNT_MAX_WG, std::max(64, std::min(t.nchunks, h->ncu)));
-    h->gsteps = cfg->graph_steps > 0 ? cfg->graph_steps : 16;
+    tcm_status st = setup_engine(h, word_base);
+    if (st != TCM_OK) return fail(st);
     *out = h;
     return TCM_OK;
 }
@@ -480,6 +507,121 @@ tcm_status scratch(tcm_handle* h, size_t bytes, float** p) {
     return TCM_OK;
 }
 
+
+// ---- checkpoints ------------------------------------------------------------
+struct CkPart {
+    void* dev;
+    size_t bytes;
+};
+
+std::vector<CkPart> ck_parts(tcm_handle* h) {
+    const Tables& t = h->t;
+    const size_t cap = (size_t)t.cap;
+    return {{t.pool, cap * SLOT_BYTES},          {t.cell2box, (size_t)h->nkeys * 4},
+            {t.act_slot, cap * 4},               {t.act_shot, cap * 4},
+            {t.act_key, cap * 4},                {t.rows, cap * 32},
+            {t.flags, cap},                      {t.pin_until, cap * 4},
+            {t.slot_key, cap * 8},               {t.free_stack, cap * 4},
+            {t.st, sizeof(DevState)}};
+}
+
+size_t ck_bytes(tcm_handle* h) {
+    size_t b = 0;
+    for (const CkPart& p : ck_parts(h)) b += (p.bytes + 255) / 256 * 256;
+    return b;
+}
+
+tcm_status ck_save(tcm_handle* h, char** buf) {
+    if (!*buf) {
+        void* q = nullptr;
+        if (hipMalloc(&q, ck_bytes(h)) != hipSuccess) {
+            (void)hipGetLastError();
+            return set_err(h, TCM_E_NOMEM, "no device memory for a forward checkpoint");
+        }
+        *buf = (char*)q;
+    }
+    size_t off = 0;
+    for (const CkPart& p : ck_parts(h)) {
+        HIP_OR_FAIL(h, hipMemcpyAsync(*buf + off, p.dev, p.bytes, hipMemcpyDeviceToDevice, h->stream));
+        off += (p.bytes + 255) / 256 * 256;
+    }
+    return TCM_OK;
+}
+
+tcm_status ck_restore(tcm_handle* h, const char* buf) {
+    size_t off = 0;
+    for (const CkPart& p : ck_parts(h)) {
+        HIP_OR_FAIL(h, hipMemcpyAsync(p.dev, buf + off, p.bytes, hipMemcpyDeviceToDevice, h->stream));
+        off += (p.bytes + 255) / 256 * 256;
+    }
+    return TCM_OK;
+}
+
+void ck_clear(tcm_handle* h) {
+    for (auto& c : h->ckpts)
+        if (c.buf) (void)hipFree(c.buf);
+    h->ckpts.clear();
+}
+
+// Issue n steps (graph replays where possible); no synchronisation.
+tcm_status issue_steps(tcm_handle* h, int n) {
+    int left = n;
+    const bool use_graph = !(h->cfg.flags & TCM_FLAG_NO_GRAPH) && !h->graph_failed && h->own_stream;
+    if (use_graph && left >= h->gsteps) {
+        if (!h->gexec) {
+            hipGraph_t g = nullptr;
+            bool ok = hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+            hipError_t le = hipSuccess;
+            for (int k = 0; ok && k < h->gsteps && le == hipSuccess; k++) le = enqueue_step(h, nullptr, nullptr);
+            if (ok) ok = hipStreamEndCapture(h->stream, &g) == hipSuccess && le == hipSuccess;
+            if (ok) ok = hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0) == hipSuccess;
+            if (g) (void)hipGraphDestroy(g);
+            if (!ok) {
+                (void)hipGetLastError();
+                h->gexec = nullptr;
+                h->graph_failed = true;
+            }
+        }
+        while (h->gexec && left >= h->gsteps) {
+            HIP_OR_FAIL(h, hipGraphLaunch(h->gexec, h->stream));
+            left -= h->gsteps;
+        }
+    }
+    for (; left > 0; left--) HIP_OR_FAIL(h, enqueue_step(h, nullptr, nullptr));
+    return TCM_OK;
+}
+
+// Tables for the adjoint field: same shots and media (shared), own pool.
+tcm_status make_adjoint_handle(tcm_handle* h) {
+    tcm_handle* a = new tcm_handle();
+    a->cfg = h->cfg;
+    a->cfg.checkpoint_every = 0;
+    a->cfg.flags = TCM_FLAG_NO_GRAPH;
+    a->cfg.device_pool = nullptr;
+    a->cfg.stream = h->stream;
+    a->engine = TCM_ENGINE_BLOCKS;
+    a->device = h->device;
+    a->ncu = h->ncu;
+    a->stream = h->stream;
+    a->own_stream = false;
+    a->hshots = h->hshots;
+    a->shots = h->shots;
+    a->d_shots = h->d_shots;            // owned by h
+    if (hipHostMalloc((void**)&a->h_state, sizeof(DevState), hipHostMallocDefault) != hipSuccess) {
+        delete a;
+        return set_err(h, TCM_E_NOMEM, "pinned host allocation failed");
+    }
+    long long word_base = 0;
+    for (const Shot& S : a->shots) word_base += S.nwords;
+    tcm_status st = setup_engine(a, word_base);
+    if (st != TCM_OK) {
+        std::string m = a->err;
+        destroy_all(a);
+        return set_err(h, st, "adjoint tables: " + m);
+    }
+    h->adj = a;
+    return TCM_OK;
+}
 }  // namespace
 
 // ===========================================================================
@@ -525,6 +667,7 @@ tcm_status tcm_add_source_shot(tcm_handle* h, int32_t shot, int32_t ix, int32_t 
         if (st) return st;
     }
     const long long n = current_step(h);
+    if (n > 0 && !h->ckpts.empty()) ck_clear(h);   // earlier checkpoints no longer replay this run
     Src e{};
     unsigned local_key = 0;
     if (h->engine == TCM_ENGINE_DENSE) {
@@ -624,6 +767,9 @@ tcm_status tcm_set_receivers(tcm_handle* h, const int32_t* xyz, const int32_t* r
     h->d_rec = nullptr;
     h->d_traces = nullptr;
     h->h_rec = rec;
+    h->rec_xyz.assign(xyz, xyz + 3 * (size_t)nrec);
+    h->rec_shot.assign((size_t)nrec, 0);
+    if (rec_shot) h->rec_shot.assign(rec_shot, rec_shot + nrec);
     h->t.rec = nullptr;
     h->t.traces = nullptr;
     h->t.trace_cap = 0;
@@ -680,45 +826,52 @@ tcm_status tcm_step(tcm_handle* h, int32_t nsteps) {
     if (st) return st;
     const unsigned long long upd0 = h->h_state->updates + h->h_state->cells_cur;
 
-    if (timing) {
-        while ((int)h->events.size() < 2 * nsteps) {
+    // one run of n steps: per-launch HIP events around the stencil, or graph replay
+    auto run_chunk = [&](int n) -> tcm_status {
+        if (!timing) return issue_steps(h, n);
+        while ((int)h->events.size() < 2 * n) {
             hipEvent_t e;
             HIP_OR_FAIL(h, hipEventCreate(&e));
             h->events.push_back(e);
         }
-        for (int k = 0; k < nsteps; k++)
+        for (int k = 0; k < n; k++)
             HIP_OR_FAIL(h, enqueue_step(h, h->events[2 * k], h->events[2 * k + 1]));
         HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
-        for (int k = 0; k < nsteps; k++) {
+        for (int k = 0; k < n; k++) {
             float ms = 0.f;
             HIP_OR_FAIL(h, hipEventElapsedTime(&ms, h->events[2 * k], h->events[2 * k + 1]));
             h->stencil_ms += ms;
         }
-        h->stencil_launches += nsteps;
-    } else {
+        h->stencil_launches += n;
+        return TCM_OK;
+    };
+    if (h->cfg.checkpoint_every > 0 && !h->in_adjoint) {
+        // stop at every checkpoint level and copy the state before stepping on
+        const int K = h->cfg.checkpoint_every;
+        long long cur = h->h_state->step;
         int left = nsteps;
-        const bool use_graph = !(h->cfg.flags & TCM_FLAG_NO_GRAPH) && !h->graph_failed && h->own_stream;
-        if (use_graph && left >= h->gsteps) {
-            if (!h->gexec) {
-                hipGraph_t g = nullptr;
-                bool ok = hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
-                hipError_t le = hipSuccess;
-                for (int k = 0; ok && k < h->gsteps && le == hipSuccess; k++) le = enqueue_step(h, nullptr, nullptr);
-                if (ok) ok = hipStreamEndCapture(h->stream, &g) == hipSuccess && le == hipSuccess;
-                if (ok) ok = hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0) == hipSuccess;
-                if (g) (void)hipGraphDestroy(g);
-                if (!ok) {
-                    (void)hipGetLastError();
-                    h->gexec = nullptr;
-                    h->graph_failed = true;
+        while (left > 0) {
+            if (cur % K == 0) {
+                const size_t idx = (size_t)(cur / K);
+                if (h->ckpts.size() <= idx) h->ckpts.resize(idx + 1);
+                if (h->ckpts[idx].step != cur) {
+                    st = ck_save(h, &h->ckpts[idx].buf);
+                    if (st) return st;
+                    h->ckpts[idx].step = cur;
                 }
             }
-            while (h->gexec && left >= h->gsteps) {
-                HIP_OR_FAIL(h, hipGraphLaunch(h->gexec, h->stream));
-                left -= h->gsteps;
-            }
+            const int chunk = (int)std::min<long long>(left, K - cur % K);
+            st = run_chunk(chunk);
+            if (st) return st;
+            st = sync_state(h);
+            if (st) return st;
+            if (h->h_state->error) break;
+            cur = h->h_state->step;
+            left -= chunk;
         }
-        for (; left > 0; left--) HIP_OR_FAIL(h, enqueue_step(h, nullptr, nullptr));
+    } else {
+        st = run_chunk(nsteps);
+        if (st) return st;
     }
     st = sync_state(h);
     if (st) return st;
@@ -832,6 +985,9 @@ tcm_status tcm_reset(tcm_handle* h) {
     if (st) return st;
     HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
     drop_graph(h);
+    ck_clear(h);
+    h->rec_xyz.clear();
+    h->rec_shot.clear();
     h->h_src.clear();
     h->h_srcw.clear();
     h->t.nsrc = 0;
@@ -865,8 +1021,118 @@ tcm_status tcm_adjoint(tcm_handle* h, const float* resid, int32_t nt, int32_t re
                        float* grad_c, int32_t out_is_device) {
     tcm_status st = check_live(h);
     if (st) return st;
-    (void)resid; (void)nt; (void)resid_is_device; (void)grad_c; (void)out_is_device;
-    return set_err(h, TCM_E_STATE, "tcm_adjoint needs checkpoint_every > 0");
+    if (h->engine != TCM_ENGINE_BLOCKS || h->shots.size() != 1)
+        return set_err(h, TCM_E_STATE, "tcm_adjoint runs on a single-shot block-engine handle");
+    const int K = h->cfg.checkpoint_every;
+    if (K <= 0) return set_err(h, TCM_E_STATE, "tcm_adjoint needs checkpoint_every > 0");
+    const int nrec = h->t.nrec;
+    if (nrec <= 0 || h->t.trace_step0 != 0)
+        return set_err(h, TCM_E_STATE, "receivers must be set before the first step");
+    if (!resid || !grad_c) return set_err(h, TCM_E_ARG, "resid and grad_c are required");
+    st = sync_state(h);
+    if (st) return st;
+    if (h->h_state->error) return set_err(h, TCM_E_STATE, "the forward run failed (pool)");
+    const long long cur = h->h_state->step;
+    if (nt <= 0 || nt > cur) return set_err(h, TCM_E_STATE, fmt("nt = %d outside the %lld recorded steps", nt, cur));
+    const int nseg = (nt + K - 1) / K;
+    if ((int)h->ckpts.size() < nseg) return set_err(h, TCM_E_STATE, "forward checkpoints missing (sources added after step 0?)");
+    for (int j = 0; j < nseg; j++)
+        if (h->ckpts[j].step != (long long)j * K) return set_err(h, TCM_E_STATE, "forward checkpoints missing");
+
+    const Shot& S = h->shots[0];
+    const size_t N = (size_t)S.nx * S.ny * S.nz;
+    std::vector<float> r((size_t)nt * nrec);
+    HIP_OR_FAIL(h, hipMemcpy(r.data(), resid, r.size() * sizeof(float),
+                             resid_is_device ? hipMemcpyDeviceToHost : hipMemcpyHostToHost));
+    // C2 at the receivers (the adjoint sources are C2_r * resid)
+    std::vector<float> c2r(nrec);
+    {
+        int* dx = nullptr;
+        float* dc = nullptr;
+        HIP_OR_FAIL(h, hipMalloc((void**)&dx, sizeof(int) * 3 * nrec));
+        HIP_OR_FAIL(h, hipMalloc((void**)&dc, sizeof(float) * nrec));
+        HIP_OR_FAIL(h, hipMemcpy(dx, h->rec_xyz.data(), sizeof(int) * 3 * nrec, hipMemcpyHostToDevice));
+        HIP_OR_FAIL(h, launch_receiver_c2(h->d_shots, dx, nullptr, nrec, h->cfg.dt, h->cfg.dx, dc, h->stream));
+        HIP_OR_FAIL(h, hipMemcpyAsync(c2r.data(), dc, sizeof(float) * nrec, hipMemcpyDeviceToHost, h->stream));
+        HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+        (void)hipFree(dx);
+        (void)hipFree(dc);
+    }
+    if (!h->adj) {
+        st = make_adjoint_handle(h);
+        if (st) return st;
+    }
+    tcm_handle* a = h->adj;
+    st = tcm_reset(a);
+    if (st) return set_err(h, st, std::string("adjoint tables: ") + a->err);
+    {
+        // adjoint step k (k = 0..nt-1) produces mu^{nt-k}; its source sample at
+        // receiver r is C2_r * resid[nt-1-k][r]
+        std::vector<float> w(nt);
+        for (int q = 0; q < nrec; q++) {
+            for (int k = 0; k < nt; k++) w[k] = c2r[q] * r[(size_t)(nt - 1 - k) * nrec + q];
+            st = tcm_add_source_shot(a, 0, h->rec_xyz[3 * q], h->rec_xyz[3 * q + 1], h->rec_xyz[3 * q + 2],
+                                     w.data(), nt);
+            if (st) return set_err(h, st, std::string("adjoint source: ") + a->err);
+        }
+    }
+    // keep the caller's forward state
+    char* now = nullptr;
+    st = ck_save(h, &now);
+    if (st) return st;
+    float* lvl = nullptr;
+    double* g = nullptr;
+    auto cleanup = [&]() {
+        if (lvl) (void)hipFree(lvl);
+        if (g) (void)hipFree(g);
+        if (now) (void)hipFree(now);
+        h->in_adjoint = false;
+    };
+    if (hipMalloc((void**)&lvl, sizeof(float) * N * (size_t)K) != hipSuccess ||
+        hipMalloc((void**)&g, sizeof(double) * N) != hipSuccess) {
+        (void)hipGetLastError();
+        cleanup();
+        return set_err(h, TCM_E_NOMEM, "no device memory for the adjoint level buffers");
+    }
+    h->in_adjoint = true;
+    hipError_t e = hipMemsetAsync(g, 0, sizeof(double) * N, h->stream);
+    const int ggrid = h->ncu * 4;
+    for (int j = nseg - 1; j >= 0 && e == hipSuccess; j--) {
+        const int s0 = j * K, end = std::min(s0 + K, nt);
+        st = ck_restore(h, h->ckpts[j].buf);
+        if (st) { cleanup(); return st; }
+        // forward levels s0 .. end-1 into lvl[0 .. end-1-s0]
+        e = launch_read(h->t, 0, 0, 0, 0, 0, S.nx, S.ny, S.nz, lvl, h->stream);
+        for (int l = 1; l < end - s0 && e == hipSuccess; l++) {
+            e = enqueue_step(h, nullptr, nullptr);
+            if (e == hipSuccess) e = launch_read(h->t, 0, 0, 0, 0, 0, S.nx, S.ny, S.nz, lvl + (size_t)l * N, h->stream);
+        }
+        // adjoint levels mu^{end} .. mu^{s0+1}, each with L u^{m-1}
+        for (int m = end; m > s0 && e == hipSuccess; m--) {
+            e = enqueue_step(a, nullptr, nullptr);
+            if (e == hipSuccess) e = launch_adjoint_grad(a->t, ggrid, lvl + (size_t)(m - 1 - s0) * N, g, h->stream);
+        }
+    }
+    if (e != hipSuccess) { cleanup(); return dev_fail(h, e, "adjoint sweep"); }
+    float* dst = grad_c;
+    if (!out_is_device) {
+        st = scratch(h, N * sizeof(float), &dst);
+        if (st) { cleanup(); return st; }
+    }
+    e = launch_grad_finish(S, h->d_shots, g, dst, h->stream);
+    if (e == hipSuccess && !out_is_device)
+        e = hipMemcpyAsync(grad_c, dst, N * sizeof(float), hipMemcpyDeviceToHost, h->stream);
+    if (e != hipSuccess) { cleanup(); return dev_fail(h, e, "adjoint gradient"); }
+    st = sync_state(a);
+    if (st) { cleanup(); return set_err(h, st, "adjoint tables failed"); }
+    const int aerr = a->h_state->error;
+    st = ck_restore(h, now);
+    if (st) { cleanup(); return st; }
+    st = sync_state(h);
+    cleanup();
+    if (st) return st;
+    if (aerr) return set_err(h, TCM_E_POOL, "pool exhausted in the adjoint field");
+    return TCM_OK;
 }
 
 }  // extern "C"

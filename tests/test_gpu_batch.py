@@ -1,0 +1,80 @@
+"""Batched shots over one shared pool: each shot must be bit-exact to its own
+single-shot run and to the CPU oracle (the shots never interact)."""
+import numpy as np
+import pytest
+
+import oracle
+import tcm_inputs as ti
+from conftest import values_equal
+
+pytestmark = pytest.mark.gpu
+tcm = pytest.importorskip("paper_1702_00216_amd")
+
+
+def announce(msg):
+    print(f"\n[case] {msg}", flush=True)
+
+
+def make_shots(n=5, seed=4, lo=20, hi=56):
+    rng = np.random.default_rng(seed)
+    shots = []
+    for i in range(n):
+        shape = tuple(int(v) for v in rng.integers(lo, hi + 1, size=3))
+        lat = ti.lognormal_lattice(shape, seed=100 + i, sigma=5.0, spacing=4)
+        src = tuple(int(rng.integers(2, e - 2)) for e in shape)
+        shots.append((shape, lat, src))
+    return shots
+
+
+@pytest.mark.parametrize("trig", [0.0, 3e-4])
+def test_batch_equals_single_shots_and_oracle(trig):
+    announce(f"batch of 5 shots, trigger {trig}")
+    dt = 0.5 / 4500
+    w = ti.ricker(300.0, dt).w32
+    shots = make_shots()
+    trig = np.float32(trig)
+    ret = np.float32(trig / 4)
+    b = tcm.Simulation([s[0] for s in shots], 1.0, dt, [s[1] for s in shots], trig, ret)
+    for i, (shape, lat, src) in enumerate(shots):
+        b.add_source(src, w, shot=i)
+    rec = [(1, 2, 3), (5, 5, 5), (0, 0, 0)]
+    b.set_receivers(rec, shots=[0, 2, 4])
+    b.step(75)
+    traces = b.read_traces()
+    for i, (shape, lat, src) in enumerate(shots):
+        single = tcm.Simulation(shape, 1.0, dt, lat, trig, ret)
+        single.add_source(src, w)
+        single.step(75)
+        assert values_equal(b.read(0, shot=i), single.read(0)), i
+        assert values_equal(b.read(1, shot=i), single.read(1)), i
+        cd = ti.lattice_to_dense(lat, shape)
+        t = oracle.TCM(cd, dt, 1.0, trig, ret)
+        t.add_source(src, w)
+        t.step(75)
+        assert values_equal(b.read(0, shot=i), t.read(0)), i
+        if trig == 0:
+            phi, _, _ = oracle.dense_run(cd, dt, 1.0, 75, np.float32, sources=[(src, w)])
+            assert values_equal(b.read(0, shot=i), phi), i
+    for r, (xyz, s) in enumerate(zip(rec, [0, 2, 4])):
+        shape, lat, src = shots[s]
+        cd = ti.lattice_to_dense(lat, shape)
+        t = oracle.TCM(cd, dt, 1.0, trig, ret)
+        t.add_source(src, w)
+        t.set_receivers([xyz])
+        _, tr = t.step(75, traces=True)
+        assert values_equal(traces[:, r], tr[:, 0])
+
+
+def test_batch_shared_pool_overflow_is_reported():
+    announce("batch pool overflow")
+    dt = 0.5 / 4500
+    w = ti.ricker(300.0, dt).w32
+    shots = make_shots(3, seed=9)
+    b = tcm.Simulation([s[0] for s in shots], 1.0, dt, [s[1] for s in shots], pool_bytes=40 * 6144)
+    for i, (shape, lat, src) in enumerate(shots):
+        b.add_source(src, w, shot=i)
+    with pytest.raises(tcm.TCMError) as ei:
+        b.step(200)
+    assert ei.value.status == -3
+    st = b.stats()
+    assert st["error"] == -3 and st["active_blocks"] <= 40
