@@ -2,6 +2,7 @@
 
 Calls only the CPU oracle (oracle/) and the input generators (tcm_inputs/).
 Usage:  python tests/golden/make_golden.py c2 [--sweep]
+        python tests/golden/make_golden.py c5
 
 c2: the 512^3 two-layer workload, 2000 steps.  Stores
   * the relative L2 error at the last step against the FP64 dense oracle of
@@ -110,9 +111,62 @@ def make_c2(sweep: bool):
                 f"({time.time() - t0:.0f} s)")
 
 
+def make_c5():
+    """256^3 lognormal model, 1000 steps, 128 receivers on z = 240, misfit
+    against FP64 traces of the +2 % anomaly model.  Stores the FP64 adjoint
+    gradient (O3) on every 8th node per axis, at 4096 seeded nodes, and at 32
+    nodes (seed 55, |grad| > 1e-3 max) together with FP64 central differences
+    of J (h = 1e-4 c) there."""
+    w = ti.c5()
+    shape = w.shape
+    c = ti.lattice_to_dense(w.lattice, shape).astype(np.float64)
+    c_true = ti.lattice_to_dense(ti.c5_true_lattice(w.lattice), shape).astype(np.float64)
+    src = [(w.source, w.wavelet.w32.astype(np.float64))]
+    rec = w.receivers
+    nt = w.steps
+    t0 = time.time()
+    d_obs = oracle.dense_run(c_true, w.dt, w.dx, nt, np.float64, sources=src, receivers=rec)[2]
+    tr = oracle.dense_run(c, w.dt, w.dx, nt, np.float64, sources=src, receivers=rec)[2]
+    resid = tr - d_obs
+    J0 = 0.5 * float(np.sum(resid ** 2))
+    log(f"c5 forward runs done in {time.time() - t0:.0f} s, J = {J0:.6e}")
+    t0 = time.time()
+    g = oracle.adjoint_f64(c, w.dt, w.dx, src, rec, resid, ckpt=50)
+    log(f"c5 FP64 adjoint done in {time.time() - t0:.0f} s")
+    gmax = float(np.max(np.abs(g)))
+    rng = np.random.default_rng(55)
+    cand = np.argwhere(np.abs(g) > 1e-3 * gmax)
+    pick = cand[rng.choice(len(cand), size=32, replace=False)]
+    res = {"workload": {"shape": shape, "steps": nt, "dt": w.dt, "source": w.source,
+                        "receivers": rec.tolist()},
+           "J": J0, "grad_norm": float(np.linalg.norm(g)), "grad_max": gmax,
+           "sub8": {"step": 8, "file": "c5_grad_sub8.npy"}}
+    np.save(os.path.join(HERE, "c5_grad_sub8.npy"), g[::8, ::8, ::8].astype(np.float32))
+    nodes = sample_nodes(shape, seed=78)
+    res["sample_nodes"] = nodes.tolist()
+    res["sample_grad"] = g[nodes[:, 2], nodes[:, 1], nodes[:, 0]].tolist()
+    fd_cells = []
+    for (z, y, x) in pick:
+        h = 1e-4 * c[z, y, x]
+        cp = c.copy()
+        cp[z, y, x] += h
+        Jp = 0.5 * float(np.sum((oracle.dense_run(cp, w.dt, w.dx, nt, np.float64, sources=src,
+                                                  receivers=rec)[2] - d_obs) ** 2))
+        cp[z, y, x] -= 2 * h
+        Jm = 0.5 * float(np.sum((oracle.dense_run(cp, w.dt, w.dx, nt, np.float64, sources=src,
+                                                  receivers=rec)[2] - d_obs) ** 2))
+        fd = (Jp - Jm) / (2 * h)
+        fd_cells.append({"xyz": [int(x), int(y), int(z)], "fd": fd, "adjoint": float(g[z, y, x])})
+        res["fd_cells"] = fd_cells
+        json.dump(res, open(os.path.join(HERE, "c5_golden.json"), "w"))
+        log(f"fd ({x},{y},{z}): fd {fd:.6e} adjoint {g[z, y, x]:.6e}")
+
+
 if __name__ == "__main__":
     which = sys.argv[1] if len(sys.argv) > 1 else "c2"
     if which == "c2":
         make_c2("--sweep" in sys.argv)
+    elif which == "c5":
+        make_c5()
     else:
         raise SystemExit(f"unknown workload {which}")
