@@ -97,6 +97,155 @@ def cpu_baseline(w, budget_s: float):
                       f"({st['updates']:.3e} updates in {el:.1f} s)"}
 
 
+def _line(metric_value, steps, warmup, ms, config, **extra):
+    out = {"metric": "TCM active-cell updates/s + HBM GB/s vs dense FDTD on same GPU at equal error",
+           "value": metric_value, "unit": "active-cell updates/s", "n_gpus": 1, "steps": steps,
+           "warmup": warmup, "ms_per_step": round(ms, 3), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": config}
+    out.update(extra)
+    print(json.dumps(out), flush=True)
+
+
+def bench_c3(args, tcm):
+    """Virtual 4096^3 lognormal domain (dense arrays would need 824.6 GB):
+    3000 steps with the block pool capped at 64 GB."""
+    import numpy as np
+    import torch
+    import tcm_inputs as ti
+    t0 = time.perf_counter()
+    w = ti.c3()
+    steps = args.time_steps or w.steps
+    log(f"c3 media lattice {w.lattice.lattice.shape} built in {time.perf_counter() - t0:.1f} s")
+    sim = tcm.Simulation(w.shape, w.dx, w.dt, w.lattice, w.trigger, w.retire,
+                         pool_bytes=w.pool_bytes, timing=True, wg_per_cu=args.wg_per_cu)
+    sim.add_source(w.source, w.wavelet.w32)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done, err, hist = 0, None, []
+    while done < steps:
+        n = min(250, steps - done)
+        rc = sim.step_status(n)
+        st = sim.stats()
+        done = st["step"]
+        hist.append((done, st["active_blocks"]))
+        log(f"c3 step {done}: active {st['active_blocks']}, {time.perf_counter() - t0:.1f} s")
+        if rc != 0:
+            err = rc
+            break
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    st = sim.stats()
+    sim.close()
+    nx, ny, nz = w.shape
+    achieved = BYTES_PER_UPDATE * st["stencil_cells"] / (st["stencil_ms"] * 1e-3) / 1e9
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline_crop(w, args.cpu_budget)
+    _line(st["cell_updates"] / el, 1, 0, el * 1e3,
+          {"workload": f"c3: virtual {nx}x{ny}x{nz} lognormal (sigma 16, [1500,4500], seed 3), Ricker "
+                       f"100 Hz at the centre, {steps} steps, trigger 1e-6 / retire 1e-7 of peak, "
+                       f"pool cap {w.pool_bytes / 1e9:.0f} GB", "time_steps_per_run": steps},
+          roofline={"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "kernel": "k_block_step"},
+          cpu_baseline=cpu,
+          tcm={"steps_done": st["step"], "error": err, "peak_active_blocks": st["peak_active_blocks"],
+               "peak_pool_bytes": st["peak_pool_bytes"], "pool_bytes": st["pool_bytes"],
+               "table_bytes": st["table_bytes"], "dense_bytes": 3 * 4 * nx * ny * nz,
+               "updates": st["cell_updates"], "activations": st["activations"],
+               "retirements": st["retirements"], "active_history": hist})
+
+
+def cpu_baseline_crop(w, budget_s: float, edge: int = 768):
+    """CPU TCM oracle on the first steps of the workload restricted to an edge^3
+    crop around the source (exact while the stencil's light cone stays inside)."""
+    import numpy as np
+    import oracle
+    import tcm_inputs as ti
+    o = tuple(int(s) - edge // 2 for s in w.source)
+    c = ti.lattice_to_dense(w.lattice, w.shape, origin=o, extent=(edge,) * 3)
+    t = oracle.TCM(c, w.dt, w.dx, np.float32(w.trigger), np.float32(w.retire))
+    t.add_source(tuple(edge // 2 for _ in range(3)), w.wavelet.w32)
+    t0 = time.perf_counter()
+    done = 0
+    while done < min(w.steps, edge // 2) and time.perf_counter() - t0 < budget_s:
+        t.step(25)
+        done += 25
+    el = time.perf_counter() - t0
+    st = t.stats()
+    t.close()
+    return {"value": st["updates"] / el, "unit": "active-cell updates/s",
+            "cores": oracle.openmp_threads(), "kind": "oracle",
+            "sample": f"CPU TCM oracle (FP32, OpenMP) on steps 0-{done} of the workload on a "
+                      f"{edge}^3 crop around the source ({st['updates']:.3e} updates in {el:.1f} s)"}
+
+
+def bench_c4(args, tcm):
+    """64 shots of uneven size over one shared pool, hipGraph step loop,
+    against the same shots run one after another."""
+    import numpy as np
+    import torch
+    import tcm_inputs as ti
+    shots = ti.c4_shots()
+    steps = args.time_steps or shots[0].steps
+    w0 = shots[0]
+    shapes = [s.shape for s in shots]
+    media = [s.lattice for s in shots]
+    sim = tcm.Simulation(shapes, 1.0, w0.dt, media, w0.trigger, w0.retire,
+                         wg_per_cu=args.wg_per_cu, graph_steps=args.graph_steps)
+
+    def run_batch():
+        sim.reset()
+        for i, s in enumerate(shots):
+            sim.add_source(s.source, s.wavelet.w32, shot=i)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(steps)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, sim.stats()
+
+    for i in range(args.warmup):
+        el, st = run_batch()
+        log(f"c4 warmup {i}: {el:.3f} s")
+    tot, upd = 0.0, 0
+    for i in range(args.steps):
+        el, st = run_batch()
+        tot += el
+        upd += st["cell_updates"]
+        log(f"c4 run {i}: {el:.3f} s, {st['cell_updates']:.3e} updates, peak active {st['peak_active_blocks']}")
+    sim.close()
+    seq = None
+    if not args.no_dense:          # the same shots one after another, one handle each
+        t_seq, u_seq = 0.0, 0
+        for s in shots:
+            one = tcm.Simulation(s.shape, 1.0, s.dt, s.lattice, s.trigger, s.retire,
+                                 wg_per_cu=args.wg_per_cu)
+            one.add_source(s.source, s.wavelet.w32)
+            one.step(8)
+            one.reset()
+            one.add_source(s.source, s.wavelet.w32)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            one.step(steps)
+            torch.cuda.synchronize()
+            t_seq += time.perf_counter() - t0
+            u_seq += one.stats()["cell_updates"]
+            one.close()
+        seq = {"seconds": round(t_seq, 4), "updates_per_s": u_seq / t_seq,
+               "batch_speedup": round(t_seq / (tot / args.steps), 3)}
+        log(f"c4 one-by-one: {t_seq:.3f} s")
+    cells = sum(a * b * c for a, b, c in shapes)
+    _line(upd / tot, args.steps, args.warmup, tot / args.steps * 1e3,
+          {"workload": f"c4: {len(shots)} shots, edges 96..384 (seed 4), lognormal media, "
+                       f"{steps} steps, trigger 1e-6 / retire 1e-7, shared pool, hipGraph replay",
+           "time_steps_per_run": steps, "dense_equivalent_nodes": cells},
+          roofline=None, cpu_baseline=None,
+          tcm={"peak_active_blocks": st["peak_active_blocks"], "peak_pool_bytes": st["peak_pool_bytes"],
+               "updates_per_run": st["cell_updates"]},
+          one_by_one=seq)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -110,6 +259,7 @@ def main():
     ap.add_argument("--graphs", action="store_true",
                     help="time with hipGraph replay instead of per-launch HIP events")
     ap.add_argument("--wg-per-cu", type=int, default=0)
+    ap.add_argument("--graph-steps", type=int, default=0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device-to-device torch copy (counter calibration)")
     args = ap.parse_args()
@@ -123,6 +273,10 @@ def main():
     import paper_1702_00216_amd as tcm
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.workload == "c3":
+        return bench_c3(args, tcm)
+    if args.workload == "c4":
+        return bench_c4(args, tcm)
     w = workload(args.workload)
     steps = args.time_steps or w.steps
     nx, ny, nz = w.shape

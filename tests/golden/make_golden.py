@@ -3,6 +3,7 @@
 Calls only the CPU oracle (oracle/) and the input generators (tcm_inputs/).
 Usage:  python tests/golden/make_golden.py c2 [--sweep]
         python tests/golden/make_golden.py c5
+        python tests/golden/make_golden.py c4
 
 c2: the 512^3 two-layer workload, 2000 steps.  Stores
   * the relative L2 error at the last step against the FP64 dense oracle of
@@ -162,11 +163,28 @@ def make_c5():
         log(f"fd ({x},{y},{z}): fd {fd:.6e} adjoint {g[z, y, x]:.6e}")
 
 
+def make_c4():
+    """Shots 0-3 of the 64-shot workload at threshold 0: SHA-256 of the FP32
+    dense oracle's final phi^n (equal to the TCM at threshold 0)."""
+    shots = ti.c4_shots()[:4]
+    res = {"shots": []}
+    for s in shots:
+        t0 = time.time()
+        cd = ti.lattice_to_dense(s.lattice, s.shape)
+        phi, _, _ = oracle.dense_run(cd, s.dt, s.dx, s.steps, np.float32,
+                                     sources=[(s.source, s.wavelet.w32)])
+        res["shots"].append({"shape": s.shape, "source": s.source, "phi_sha256": digest(phi)})
+        json.dump(res, open(os.path.join(HERE, "c4_golden.json"), "w"))
+        log(f"{s.name} {s.shape}: {time.time() - t0:.0f} s")
+
+
 if __name__ == "__main__":
     which = sys.argv[1] if len(sys.argv) > 1 else "c2"
     if which == "c2":
         make_c2("--sweep" in sys.argv)
     elif which == "c5":
         make_c5()
+    elif which == "c4":
+        make_c4()
     else:
         raise SystemExit(f"unknown workload {which}")
