@@ -62,7 +62,9 @@ enum { TCM_MEDIA_DENSE = 0, TCM_MEDIA_LAYERED = 1, TCM_MEDIA_LATTICE = 2 };
 enum { TCM_ENGINE_BLOCKS = 0, TCM_ENGINE_DENSE = 1 };
 enum {
     TCM_FLAG_TIMING = 1,    /* time every block-stencil launch with HIP events */
-    TCM_FLAG_NO_GRAPH = 2   /* launch each step's kernels directly (no hipGraph replay) */
+    TCM_FLAG_NO_GRAPH = 2,  /* launch each step's kernels directly (no hipGraph replay) */
+    TCM_FLAG_NO_UNIFORM_C2 = 4  /* always read the per-node C2 plane (no scalar C2 for
+                                   blocks whose C2 is uniform, "Media" hybrid engine) */
 };
 
 /* Run configuration.  Zero-initialise, then set the fields. */
@@ -80,7 +82,12 @@ typedef struct {
     int32_t  checkpoint_every;/* > 0 keeps forward checkpoints every k steps for tcm_adjoint */
     int32_t  graph_steps;     /* steps per captured hipGraph (0: 16) */
     int32_t  wg_per_cu;       /* block-stencil workgroups per compute unit (0: default) */
-    int32_t  reserved[5];
+    int32_t  shutdown_steps;  /* shutdown process, eq.(6): a block that no longer qualifies
+                                 stays shutdown_steps more steps with both field levels
+                                 multiplied by shutdown_alpha after each, then is released;
+                                 0 releases at once.  At most 255. */
+    float    shutdown_alpha;  /*   the decay factor alpha; total attenuation A = alpha^n */
+    int32_t  reserved[3];
 } tcm_config;
 
 /* Wave-speed model ("Media": an array, or rules evaluated when a block is
@@ -120,6 +127,9 @@ typedef struct {
     double  stencil_ms;           /* TCM_FLAG_TIMING: summed block-stencil kernel time */
     int64_t stencil_launches;     /* TCM_FLAG_TIMING: launches summed in stencil_ms */
     int64_t stencil_cells;        /* TCM_FLAG_TIMING: in-domain nodes of the timed launches */
+    int64_t uniform_cell_updates; /* of cell_updates, nodes of blocks read with a scalar C2 */
+    int64_t stencil_cells_uniform;/* TCM_FLAG_TIMING: of stencil_cells, nodes with a scalar C2 */
+    int64_t decay_block_steps;    /* block-steps of the shutdown decay (eq.(6)) */
 } tcm_stats_t;
 
 /* Create a single-shot handle (eq.(3) on an nx*ny*nz grid, "Cells construction").
@@ -175,6 +185,30 @@ tcm_status tcm_read_traces(tcm_handle* h, float* out, int32_t out_is_device, int
  * TCM_E_STATE without checkpoints or if nt exceeds the recorded steps. */
 tcm_status tcm_adjoint(tcm_handle* h, const float* resid, int32_t nt, int32_t resid_is_device,
                        float* grad_c, int32_t out_is_device);
+
+/* Launch-shape choice of the block engine (tcm_autotune). */
+typedef struct {
+    int32_t wg_per_cu;            /* chosen block-stencil workgroups per compute unit */
+    int32_t graph_steps;          /* chosen steps per captured hipGraph */
+    double  ms_per_step;          /* probe time per step of the choice */
+    int32_t ncand;                /* candidates timed */
+    int32_t cand_wg_per_cu[32];
+    int32_t cand_graph_steps[32];
+    double  cand_ms_per_step[32];
+} tcm_tuning;
+
+/* Time probe_steps steps from the current state for each candidate launch
+ * shape (workgroups per CU of the persistent stencil grid x steps per
+ * graph), restore the state after each probe, and keep the fastest shape
+ * for later tcm_step calls.  The block edge stays 8 (one 64-lane wave per
+ * block).  The field, statistics and traces are unchanged on return.
+ * TCM_E_STATE for the dense engine or a failed run; out may be NULL. */
+tcm_status tcm_autotune(tcm_handle* h, int32_t probe_steps, tcm_tuning* out);
+
+/* Set the launch shape directly (for example a stored tcm_autotune choice):
+ * wg_per_cu in [1, resident workgroups per CU], graph_steps >= 1.  Block
+ * engine only; TCM_E_ARG out of range. */
+tcm_status tcm_set_launch(tcm_handle* h, int32_t wg_per_cu, int32_t graph_steps);
 
 /* Return to level 0 (zero field, no active block, no sources, no traces);
  * media, configuration and allocations are kept. */

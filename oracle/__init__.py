@@ -94,6 +94,9 @@ def _declare(L):
         f = getattr(L, f"otcm_check_{sfx}")
         f.argtypes = [_P]
         f.restype = _I
+        f = getattr(L, f"otcm_set_shutdown_{sfx}")
+        f.argtypes = [_P, _I, real]
+        f.restype = _I
     L.oracle_adjoint_f64.argtypes = [_I, _I, _I, _P, _D, _D, _I, _P, _P, _P, _P, _P,
                                      _I, _P, _I, _P, _I, _P]
     L.oracle_adjoint_f64.restype = _I
@@ -196,7 +199,8 @@ class TCM:
     E_POOL = -3
 
     def __init__(self, c: np.ndarray, dt: float, dx: float, trigger: float = 0.0,
-                 retire: float = 0.0, block: int = 8, cap: int = 0, dtype=np.float32):
+                 retire: float = 0.0, block: int = 8, cap: int = 0, dtype=np.float32,
+                 shutdown_steps: int = 0, shutdown_alpha: float = 1.0):
         self.dtype, self.sfx = _dt(dtype)
         c = np.ascontiguousarray(c, dtype=self.dtype)
         self.shape = (c.shape[2], c.shape[1], c.shape[0])
@@ -208,6 +212,9 @@ class TCM:
         if not self._h:
             raise MemoryError("otcm_create failed")
         self.nrec = 0
+        if shutdown_steps:
+            if self._f("otcm_set_shutdown")(self._h, int(shutdown_steps), shutdown_alpha) != 0:
+                raise ValueError("shutdown_steps must be in [0, 255]")
         nx, ny, nz = self.shape
         self.cells_shape = (-(-nz // block), -(-ny // block), -(-nx // block))
 

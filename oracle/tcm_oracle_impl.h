@@ -106,6 +106,11 @@ typedef struct SFX(otcm) {
     int nrec; int64_t* rec_cell; int* rec_local;
     int error;
     int64_t peak_active, activations, retirements, updates;
+    /* shutdown process (eq.(6)): decay steps and factor; Table 1 Shutdown_log */
+    int sd_steps;
+    REAL sd_alpha;
+    int* shutdown_log;
+    int64_t decays;
 } SFX(otcm);
 
 void SFX(otcm_destroy)(SFX(otcm)* t);
@@ -173,6 +178,7 @@ static int SFX(box_cell)(SFX(otcm)* t, int64_t cell) {
     t->cell2box[cell] = j;
     t->box2cell[j] = (int)cell;   /* cell ids of tested grids fit in int */
     t->triggered[cell] = 1;
+    t->shutdown_log[cell] = 0;
     return j;
 }
 
@@ -209,7 +215,10 @@ SFX(otcm)* SFX(otcm_create)(int nx, int ny, int nz, int B, const REAL* c, double
     t->boxes = (REAL*)malloc((size_t)t->cap * 3 * (size_t)t->B3 * sizeof(REAL));
     t->vacant = (int*)malloc((size_t)t->cap * sizeof(int));
     t->active = (int64_t*)malloc((size_t)t->M * sizeof(int64_t));
-    if (!t->c || !t->triggered || !t->hist || !t->max_val || !t->cell2box || !t->box2cell ||
+    t->shutdown_log = (int*)calloc((size_t)t->M, sizeof(int));
+    t->sd_alpha = (REAL)1;
+    if (!t->shutdown_log ||
+        !t->c || !t->triggered || !t->hist || !t->max_val || !t->cell2box || !t->box2cell ||
         !t->boxes || !t->vacant || !t->active) {
         SFX(otcm_destroy)(t);
         return NULL;
@@ -221,7 +230,7 @@ void SFX(otcm_destroy)(SFX(otcm)* t)
 {
     if (!t) return;
     free(t->c); free(t->triggered); free(t->hist); free(t->max_val); free(t->cell2box);
-    free(t->box2cell); free(t->boxes); free(t->vacant); free(t->active);
+    free(t->box2cell); free(t->boxes); free(t->vacant); free(t->active); free(t->shutdown_log);
     free(t->src_cell); free(t->src_local); free(t->src_t0); free(t->src_ns); free(t->src_off);
     free(t->src_w); free(t->rec_cell); free(t->rec_local);
     free(t);
@@ -424,9 +433,30 @@ int SFX(otcm_step)(SFX(otcm)* t, int nsteps, REAL* traces, unsigned order_seed)
                 if (nb >= 0) next[nb] = 1;
             }
         }
+        /* 6. shutdown process (eq.(6)) for active cells that are no longer triggered */
+        unsigned char* decay = NULL;
+        if (t->sd_steps > 0) {
+            decay = (unsigned char*)calloc((size_t)t->M, 1);
+            for (int64_t a = 0; a < t->nactive; a++) {
+                const int64_t cell = t->active[a];
+                int* lg = &t->shutdown_log[cell];
+                if (next[cell]) {
+                    *lg = 0;                       /* triggered again: shutdown cancelled */
+                } else if (*lg == 0) {
+                    *lg = t->sd_steps;             /* start */
+                    next[cell] = 1;
+                    decay[cell] = 1;
+                } else if (*lg > 1) {
+                    *lg -= 1;
+                    next[cell] = 1;
+                    decay[cell] = 1;
+                }                                  /* *lg == 1: finished, unboxed below */
+            }
+        }
         int64_t count = 0;
         for (int64_t i = 0; i < t->M; i++) count += next[i];
         if (count > t->cap) {
+            free(decay);
             /* pool exhausted: keep phi^{n+1} with the current active set and stop */
             for (int64_t a = 0; a < t->nactive; a++) t->hist[t->active[a]] = 0;
             t->cur ^= 1;
@@ -434,7 +464,17 @@ int SFX(otcm_step)(SFX(otcm)* t, int nsteps, REAL* traces, unsigned order_seed)
             t->error = -3;
             break;
         }
-        /* 6/7. cells that are no longer triggered are unboxed (immediate shutdown) */
+        if (decay) {
+            for (int64_t a = 0; a < t->nactive; a++) {
+                const int64_t cell = t->active[a];
+                if (!decay[cell]) continue;
+                REAL* q = SFX(box_plane)(t, t->cell2box[cell], 0);
+                for (int k = 0; k < 2 * B * B * B; k++) q[k] = q[k] * t->sd_alpha;
+                t->decays++;
+            }
+            free(decay);
+        }
+        /* 7. cells that finished the shutdown (or have none) are unboxed */
         for (int64_t a = 0; a < t->nactive; a++) {
             const int64_t cell = t->active[a];
             if (!next[cell]) { SFX(unbox_cell)(t, cell); t->retirements++; }
@@ -493,6 +533,18 @@ int SFX(otcm_stats)(const SFX(otcm)* t, int64_t* out)
 int SFX(otcm_triggered)(const SFX(otcm)* t, unsigned char* out)
 {
     memcpy(out, t->triggered, (size_t)t->M);
+    return 0;
+}
+
+/* Shutdown process of eq.(6): a cell that is no longer triggered is kept for
+ * n more activation updates while both of its field levels are multiplied by
+ * alpha after each of them (total attenuation A = alpha^n), then unboxed.
+ * n = 0 unboxes at once. */
+int SFX(otcm_set_shutdown)(SFX(otcm)* t, int n, REAL alpha)
+{
+    if (n < 0 || n > 255) return -1;
+    t->sd_steps = n;
+    t->sd_alpha = alpha;
     return 0;
 }
 

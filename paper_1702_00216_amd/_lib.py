@@ -13,13 +13,14 @@ STATUS_NAMES = {0: "TCM_OK", -1: "TCM_E_ARG", -2: "TCM_E_CFL", -3: "TCM_E_POOL",
                 -5: "TCM_E_DEVICE", -6: "TCM_E_STATE", -7: "TCM_E_NOMEM"}
 MEDIA_DENSE, MEDIA_LAYERED, MEDIA_LATTICE = 0, 1, 2
 ENGINE_BLOCKS, ENGINE_DENSE = 0, 1
-FLAG_TIMING, FLAG_NO_GRAPH = 1, 2
+FLAG_TIMING, FLAG_NO_GRAPH, FLAG_NO_UNIFORM_C2 = 1, 2, 4
 
 # every symbol include/tcm.h declares
 EXPORTS = [
     "tcm_create", "tcm_create_batch", "tcm_add_source", "tcm_add_source_shot", "tcm_step",
     "tcm_read", "tcm_read_shot", "tcm_set_receivers", "tcm_read_traces", "tcm_adjoint",
-    "tcm_reset", "tcm_stats", "tcm_destroy", "tcm_last_error", "tcm_version",
+    "tcm_reset", "tcm_stats", "tcm_destroy", "tcm_last_error", "tcm_version", "tcm_autotune",
+    "tcm_set_launch",
 ]
 
 
@@ -30,7 +31,8 @@ class Config(C.Structure):
                 ("pool_bytes", C.c_uint64), ("device_pool", C.c_void_p), ("stream", C.c_void_p),
                 ("engine", C.c_int32), ("flags", C.c_int32), ("checkpoint_every", C.c_int32),
                 ("graph_steps", C.c_int32), ("wg_per_cu", C.c_int32),
-                ("reserved", C.c_int32 * 5)]
+                ("shutdown_steps", C.c_int32), ("shutdown_alpha", C.c_float),
+                ("reserved", C.c_int32 * 3)]
 
 
 class Media(C.Structure):
@@ -52,7 +54,14 @@ class Stats(C.Structure):
                 ("retirements", C.c_int64), ("cell_updates", C.c_int64),
                 ("error", C.c_int32), ("nshots", C.c_int32),
                 ("stencil_ms", C.c_double), ("stencil_launches", C.c_int64),
-                ("stencil_cells", C.c_int64)]
+                ("stencil_cells", C.c_int64), ("uniform_cell_updates", C.c_int64),
+                ("stencil_cells_uniform", C.c_int64), ("decay_block_steps", C.c_int64)]
+
+
+class Tuning(C.Structure):
+    _fields_ = [("wg_per_cu", C.c_int32), ("graph_steps", C.c_int32), ("ms_per_step", C.c_double),
+                ("ncand", C.c_int32), ("cand_wg_per_cu", C.c_int32 * 32),
+                ("cand_graph_steps", C.c_int32 * 32), ("cand_ms_per_step", C.c_double * 32)]
 
 
 _lib = None
@@ -87,6 +96,8 @@ def lib():
         L.tcm_read_traces.argtypes = [H, P, I, F(C.c_int32)]
         L.tcm_adjoint.argtypes = [H, P, I, I, P, I]
         L.tcm_reset.argtypes = [H]
+        L.tcm_autotune.argtypes = [H, I, F(Tuning)]
+        L.tcm_set_launch.argtypes = [H, I, I]
         L.tcm_stats.argtypes = [H, F(Stats)]
         L.tcm_destroy.argtypes = [H]
         L.tcm_destroy.restype = None

@@ -45,9 +45,12 @@ struct Shot {
 struct DevState {
     int step, n_act, n_new, n_ret;
     int free_top, error, err_step, emit;
-    int peak_act, done_wgs, add_error, pad;
+    int peak_act, done_wgs, add_error, n_dec;
     unsigned long long cells_cur;    // in-domain nodes of the current active list
     unsigned long long updates;      // in-domain nodes stepped so far
+    unsigned long long cells_cur_u;  // ... of those, nodes of blocks with a uniform C2
+    unsigned long long updates_u;
+    unsigned long long decays;       // block-steps of the shutdown decay
     unsigned long long activations, retirements;
 };
 
@@ -79,6 +82,12 @@ struct Tables {
     int* rows;                      // per list entry: slot, 6 neighbour slots (or EMPTY), global key
     unsigned char* flags;           // per slot: face bits 0..5 and KEEP_BIT
     int* pin_until;                 // per slot: active while step < pin_until (sources)
+    float* slot_c2u;                // per slot: the block's C2 if uniform over the block, else NaN
+    unsigned char* sdlog;           // per slot: shutdown steps left (0: not shutting down)
+    int* dec_slot;                  // per step: slots whose levels are multiplied by alpha
+    int shutdown_steps;             // eq.(6) n (0: release at once)
+    float shutdown_alpha;           // eq.(6) alpha
+    int uniform_c2;                 // 1: blocks with a uniform C2 read it as a scalar
     long long* slot_key;            // per slot: global key or -1
     int* free_stack;                // free slots, top in DevState::free_top
     long long* new_key;             // per step: claimed keys

@@ -134,6 +134,33 @@ __device__ __forceinline__ float coeff_c2(float c, double dt, double dx) {
     return (float)(t * t);
 }
 
+// Zero both phi levels of a new slot and fill its C2 plane from the media
+// (one wave, lane = (x, y) column).  Returns (to every lane) the block's C2 if
+// all 512 nodes are in the domain and share it ("homogenic" cell of Table 1),
+// else NaN.
+__device__ float fill_slot(const Tables& t, const Shot& S, float* blk, int bx, int by, int bz) {
+    const int lane = lane_id();
+    const int x = lane & 7, y = lane >> 3;
+    float first = 0.f;
+    bool same = true;
+#pragma unroll
+    for (int z = 0; z < 8; z++) {
+        blk[z * 64 + lane] = 0.f;
+        blk[BV + z * 64 + lane] = 0.f;
+        const int gx = bx * BE + x, gy = by * BE + y, gz = bz * BE + z;
+        float c2 = 0.f;   // nodes outside the domain keep C2 = 0 and stay zero
+        const bool in = gx < S.nx && gy < S.ny && gz < S.nz;
+        if (in) c2 = coeff_c2(media_speed(S, gx, gy, gz), t.dt, t.dx);
+        blk[C2_PLANE + z * 64 + lane] = c2;
+        if (z == 0) first = c2;
+        same = same && in && c2 == first;
+    }
+    const float ref = __shfl(first, 0);
+    same = same && first == ref;
+    const bool uniform = t.uniform_c2 && __ballot(!same) == 0ull;
+    return uniform ? ref : __builtin_nanf("");
+}
+
 // --------------------------------------------------------------------------
 // table initialisation
 // --------------------------------------------------------------------------
@@ -147,13 +174,16 @@ __global__ void k_init_tables(Tables t, long long nkeys) {
         t.slot_key[i] = -1;
         t.pin_until[i] = 0;
         t.flags[i] = 0;
+        t.slot_c2u[i] = __builtin_nanf("");
+        t.sdlog[i] = 0;
     }
     if (g0 == 0) {
         DevState* st = t.st;
         st->step = 0; st->n_act = 0; st->n_new = 0; st->n_ret = 0;
         st->free_top = t.cap; st->error = 0; st->err_step = -1; st->emit = 0;
-        st->peak_act = 0; st->done_wgs = 0; st->add_error = 0; st->pad = 0;
+        st->peak_act = 0; st->done_wgs = 0; st->add_error = 0; st->n_dec = 0;
         st->cells_cur = 0; st->updates = 0; st->activations = 0; st->retirements = 0;
+        st->cells_cur_u = 0; st->updates_u = 0; st->decays = 0;
     }
 }
 
@@ -205,6 +235,7 @@ __global__ __launch_bounds__(256) void k_block_step(Tables t) {
     // processed, so only the data loads sit on the critical path.
     const scalar_ptr<int> rows = as_scalar((const int*)t.rows);
     const scalar_ptr<int> pin_until = as_scalar((const int*)t.pin_until);
+    const scalar_ptr<float> slot_c2u = as_scalar((const float*)t.slot_c2u);
     const int stride = per * 4;
     int i = beg + jw * 4 + wid;
     int r[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -221,6 +252,7 @@ __global__ __launch_bounds__(256) void k_block_step(Tables t) {
             for (int k = 0; k < 8; k++) r[k] = rows[8 * (size_t)(i + stride) + k];
         }
         const int pinned = t.nsrc > 0 ? pin_until[slot] : 0;
+        const float c2u = slot_c2u[slot];
         const float* __restrict__ blk = t.pool + (size_t)slot * SLOT;
         const float* __restrict__ cur_p = blk + p * BV;
         float* __restrict__ out_p = (float*)blk + (1 - p) * BV;
@@ -231,7 +263,13 @@ __global__ __launch_bounds__(256) void k_block_step(Tables t) {
         for (int z = 0; z < 8; z++) {
             cur[z] = cur_p[z * 64 + lane];
             prv[z] = out_p[z * 64 + lane];
-            k2[z] = c2_p[z * 64 + lane];
+        }
+        if (c2u == c2u) {            // uniform block: one coefficient, no C2 plane read
+#pragma unroll
+            for (int z = 0; z < 8; z++) k2[z] = c2u;
+        } else {
+#pragma unroll
+            for (int z = 0; z < 8; z++) k2[z] = c2_p[z * 64 + lane];
         }
         float zlo = 0.f, zhi = 0.f, fmx = 0.f, fpx = 0.f, fmy = 0.f, fpy = 0.f;
         if (nb[4] >= 0) zlo = t.pool[(size_t)nb[4] * SLOT + p * BV + 7 * 64 + lane];
@@ -397,13 +435,32 @@ __global__ __launch_bounds__(256) void k_plan(Tables t) {
                 atomicOr(&t.bitmap[nk >> 6], 1ull << (nk & 63));
             }
         }
+        // shutdown process (eq.(6)): a block that no longer qualifies keeps
+        // running for shutdown_steps more steps with both levels scaled by
+        // alpha after each, then is released; qualifying again cancels it
+        bool release = valid && !survive, decay = false;
+        if (valid && t.shutdown_steps > 0) {
+            const int sd = t.sdlog[slot];
+            if (survive) {
+                if (sd) t.sdlog[slot] = 0;
+            } else if (sd == 0) {
+                t.sdlog[slot] = (unsigned char)t.shutdown_steps;
+                release = false;
+                decay = true;
+            } else if (sd > 1) {
+                t.sdlog[slot] = (unsigned char)(sd - 1);
+                release = false;
+                decay = true;
+            }
+        }
         // survivors: the list is in key order, so a wave's keys fall in one or
         // two bitmap words; OR the bits within each run of equal words and let
         // the first lane of the run do the atomic
         {
             const long long G = valid ? t.shots[shot].key_base + (long long)key : -1;
-            const long long word = valid && survive ? (G >> 6) : -1;
-            unsigned long long bits = valid && survive ? (1ull << (G & 63)) : 0ull;
+            const bool stays = valid && !release;
+            const long long word = stays ? (G >> 6) : -1;
+            unsigned long long bits = stays ? (1ull << (G & 63)) : 0ull;
             const int lane = lane_id();
             for (int o = 1; o < 64; o <<= 1) {
                 const unsigned long long ob = __shfl_down(bits, o);
@@ -413,7 +470,9 @@ __global__ __launch_bounds__(256) void k_plan(Tables t) {
             const long long prev_word = __shfl_up(word, 1);
             if (word >= 0 && (lane == 0 || prev_word != word)) atomicOr(&t.bitmap[word], bits);
         }
-        const int kr = wave_append(&st->n_ret, valid && !survive);
+        const int kd = wave_append(&st->n_dec, decay);
+        if (kd >= 0) t.dec_slot[kd] = slot;
+        const int kr = wave_append(&st->n_ret, release);
         if (kr >= 0) t.ret_slot[kr] = slot;
     }
 }
@@ -462,24 +521,27 @@ __global__ __launch_bounds__(256) void k_pool_count(Tables t) {
                 const Shot& S = t.shots[shot];
                 int bx, by, bz;
                 key_to_block(S, (unsigned)(G - S.key_base), bx, by, bz);
-                float* blk = t.pool + (size_t)slot * SLOT;
-                const int x = lane & 7, y = lane >> 3;
-#pragma unroll
-                for (int z = 0; z < 8; z++) {
-                    blk[z * 64 + lane] = 0.f;
-                    blk[BV + z * 64 + lane] = 0.f;
-                    const int gx = bx * BE + x, gy = by * BE + y, gz = bz * BE + z;
-                    float c2 = 0.f;   // nodes outside the domain keep C2 = 0 and stay zero
-                    if (gx < S.nx && gy < S.ny && gz < S.nz)
-                        c2 = coeff_c2(media_speed(S, gx, gy, gz), t.dt, t.dx);
-                    blk[C2_PLANE + z * 64 + lane] = c2;
-                }
+                const float c2u = fill_slot(t, S, t.pool + (size_t)slot * SLOT, bx, by, bz);
                 if (lane == 0) {
+                    t.slot_c2u[slot] = c2u;
+                    t.sdlog[slot] = 0;
                     t.cell2box[G] = slot;
                     t.slot_key[slot] = G;
                     t.pin_until[slot] = 0;
                 }
             }
+        }
+    }
+
+    // shutdown decay (eq.(6)): both stored levels of the listed blocks times alpha
+    if (!err0 && nn <= top + nr) {
+        const int nd = st->n_dec;
+        const float alpha = t.shutdown_alpha;
+        const int nwaves = gridDim.x * (blockDim.x >> 6);
+        for (int k = blockIdx.x * (blockDim.x >> 6) + wid; k < nd; k += nwaves) {
+            float* blk = t.pool + (size_t)t.dec_slot[k] * SLOT;
+#pragma unroll
+            for (int j = 0; j < 16; j++) blk[j * 64 + lane] = blk[j * 64 + lane] * alpha;
         }
     }
 
@@ -528,21 +590,25 @@ __global__ __launch_bounds__(256) void k_pool_count(Tables t) {
         const int err = st->error;
         if (!err || st->err_step == st->step) {   // the step's phi^{n+1} is complete
             st->updates += st->cells_cur;
+            st->updates_u += st->cells_cur_u;
             st->step += 1;
         }
         if (!err) {
             st->free_top = top + nr - nn;
             st->activations += (unsigned long long)nn;
             st->retirements += (unsigned long long)nr;
+            st->decays += (unsigned long long)st->n_dec;
             st->n_act = (int)total;
             if ((int)total > st->peak_act) st->peak_act = (int)total;
             st->cells_cur = 0;
+            st->cells_cur_u = 0;
             st->emit = 1;
         } else {
             st->emit = 0;
         }
         st->n_new = 0;
         st->n_ret = 0;
+        st->n_dec = 0;
         st->done_wgs = 0;
         __threadfence();
     }
@@ -573,7 +639,7 @@ __device__ __forceinline__ int shot_of_word(const Tables& t, long long w) {
 // one contiguous run in key order.
 __global__ __launch_bounds__(256) void k_emit(Tables t) {
     DevState* st = t.st;
-    __shared__ unsigned long long csum[4];
+    __shared__ unsigned long long csum[4], usum[4];
     const int lane = lane_id();
     const int wid = threadIdx.x >> 6;
     const int emit = st->emit;
@@ -587,7 +653,7 @@ __global__ __launch_bounds__(256) void k_emit(Tables t) {
         if (lane >= o) incl += u;
     }
     const unsigned base = emit ? t.partial[chunk] : 0u;
-    unsigned long long cells = 0;
+    unsigned long long cells = 0, ucells = 0;
     for (int j = wid; j < CHUNK_WORDS; j += 4) {
         const unsigned long long m = __shfl(myword, j);
         if (m == 0ull) continue;
@@ -611,7 +677,10 @@ __global__ __launch_bounds__(256) void k_emit(Tables t) {
             t.act_key[off] = key;
             int bx, by, bz;
             key_to_block(S, key, bx, by, bz);
-            cells += (unsigned long long)block_cells(S, bx, by, bz);
+            const unsigned long long bc = (unsigned long long)block_cells(S, bx, by, bz);
+            cells += bc;
+            const float u = t.slot_c2u[slot];
+            if (u == u) ucells += bc;
             int nb[6];
 #pragma unroll
             for (int d = 0; d < 6; d++) {
@@ -623,13 +692,21 @@ __global__ __launch_bounds__(256) void k_emit(Tables t) {
             rp[1] = make_int4(nb[3], nb[4], nb[5], (int)G);
         }
     }
-    for (int o = 32; o > 0; o >>= 1) cells += __shfl_xor(cells, o);
-    if (lane == 0) csum[wid] = cells;
+    for (int o = 32; o > 0; o >>= 1) {
+        cells += __shfl_xor(cells, o);
+        ucells += __shfl_xor(ucells, o);
+    }
+    if (lane == 0) {
+        csum[wid] = cells;
+        usum[wid] = ucells;
+    }
     __syncthreads();                       // every wave has read the chunk
     if (wid == 0 && w_lane < t.nwords && myword) t.bitmap[w_lane] = 0ull;
     if (threadIdx.x == 0) {
         const unsigned long long c = csum[0] + csum[1] + csum[2] + csum[3];
+        const unsigned long long u = usum[0] + usum[1] + usum[2] + usum[3];
         if (c) atomicAdd(&st->cells_cur, c);
+        if (u) atomicAdd(&st->cells_cur_u, u);
     }
 }
 
@@ -659,17 +736,10 @@ __global__ __launch_bounds__(64) void k_activate(Tables t, long long G, int shot
     const Shot& S = t.shots[shot];
     int bx, by, bz;
     key_to_block(S, key, bx, by, bz);
-    float* blk = t.pool + (size_t)slot * SLOT;
-    const int x = lane & 7, y = lane >> 3;
-    for (int z = 0; z < 8; z++) {
-        blk[z * 64 + lane] = 0.f;
-        blk[BV + z * 64 + lane] = 0.f;
-        const int gx = bx * BE + x, gy = by * BE + y, gz = bz * BE + z;
-        float c2 = 0.f;
-        if (gx < S.nx && gy < S.ny && gz < S.nz) c2 = coeff_c2(media_speed(S, gx, gy, gz), t.dt, t.dx);
-        blk[C2_PLANE + z * 64 + lane] = c2;
-    }
+    const float c2u = fill_slot(t, S, t.pool + (size_t)slot * SLOT, bx, by, bz);
     if (lane == 0) {
+        t.slot_c2u[slot] = c2u;
+        t.sdlog[slot] = 0;
         st->free_top = top - 1;
         t.cell2box[G] = slot;
         t.slot_key[slot] = G;
@@ -689,6 +759,7 @@ __global__ __launch_bounds__(64) void k_activate(Tables t, long long G, int shot
         st->n_act = i + 1;
         if (i + 1 > st->peak_act) st->peak_act = i + 1;
         st->cells_cur += (unsigned long long)block_cells(S, bx, by, bz);
+        if (c2u == c2u) st->cells_cur_u += (unsigned long long)block_cells(S, bx, by, bz);
         st->activations += 1ull;
     }
 }

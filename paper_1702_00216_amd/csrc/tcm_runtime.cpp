@@ -80,7 +80,7 @@ struct tcm_handle {
     // timing (TCM_FLAG_TIMING)
     std::vector<hipEvent_t> events;
     double stencil_ms = 0.0;
-    long long stencil_launches = 0, stencil_cells = 0;
+    long long stencil_launches = 0, stencil_cells = 0, stencil_cells_u = 0;
 
     // dense engine
     float* d_phi[2] = {nullptr, nullptr};
@@ -302,7 +302,7 @@ tcm_status setup_engine(tcm_handle* h, long long word_base) {
     size_t free_b = 0, total_b = 0;
     (void)hipMemGetInfo(&free_b, &total_b);
     // per-slot bookkeeping bytes besides the 6 KiB slot
-    const size_t per_slot_tab = 4 + 4 + 4 + 32 + 1 + 4 + 8 + 4 + 8 + 4 + 4;
+    const size_t per_slot_tab = 4 + 4 + 4 + 32 + 1 + 4 + 4 + 1 + 4 + 8 + 4 + 8 + 4 + 4;
     const size_t fixed = (size_t)h->nkeys * 4 + (size_t)word_base * 8 + (size_t)t.nchunks * 4 + (1 << 20);
     long long cap;
     if (cfg->pool_bytes > 0) {
@@ -335,6 +335,12 @@ tcm_status setup_engine(tcm_handle* h, long long word_base) {
     ok = ok && dalloc(h, &t.rows, (size_t)cap * 8) == hipSuccess;
     ok = ok && dalloc(h, &t.flags, (size_t)cap) == hipSuccess;
     ok = ok && dalloc(h, &t.pin_until, (size_t)cap) == hipSuccess;
+    ok = ok && dalloc(h, &t.slot_c2u, (size_t)cap) == hipSuccess;
+    ok = ok && dalloc(h, &t.sdlog, (size_t)cap) == hipSuccess;
+    ok = ok && dalloc(h, &t.dec_slot, (size_t)cap) == hipSuccess;
+    t.shutdown_steps = cfg->shutdown_steps;
+    t.shutdown_alpha = cfg->shutdown_alpha;
+    t.uniform_c2 = (cfg->flags & TCM_FLAG_NO_UNIFORM_C2) ? 0 : 1;
     ok = ok && dalloc(h, &t.slot_key, (size_t)cap) == hipSuccess;
     ok = ok && dalloc(h, &t.free_stack, (size_t)cap) == hipSuccess;
     ok = ok && dalloc(h, &t.new_key, (size_t)cap) == hipSuccess;
@@ -370,6 +376,10 @@ tcm_status create_common(const tcm_config* cfg, const tcm_shot* shots, int nshot
         return set_err(nullptr, TCM_E_ARG, "thresholds must satisfy 0 <= retire <= trigger (finite)");
     if (cfg->engine != TCM_ENGINE_BLOCKS && cfg->engine != TCM_ENGINE_DENSE)
         return set_err(nullptr, TCM_E_ARG, "unknown engine");
+    if (cfg->shutdown_steps < 0 || cfg->shutdown_steps > 255 ||
+        (cfg->shutdown_steps > 0 && !(std::isfinite(cfg->shutdown_alpha) && cfg->shutdown_alpha >= 0.f &&
+                                      cfg->shutdown_alpha <= 1.f)))
+        return set_err(nullptr, TCM_E_ARG, "shutdown needs 0 <= steps <= 255 and 0 <= alpha <= 1");
     if (cfg->engine == TCM_ENGINE_DENSE && nshots != 1)
         return set_err(nullptr, TCM_E_ARG, "the dense engine runs one shot");
 
@@ -521,6 +531,7 @@ std::vector<CkPart> ck_parts(tcm_handle* h) {
             {t.act_slot, cap * 4},               {t.act_shot, cap * 4},
             {t.act_key, cap * 4},                {t.rows, cap * 32},
             {t.flags, cap},                      {t.pin_until, cap * 4},
+            {t.slot_c2u, cap * 4},               {t.sdlog, cap},
             {t.slot_key, cap * 8},               {t.free_stack, cap * 4},
             {t.st, sizeof(DevState)}};
 }
@@ -825,6 +836,7 @@ tcm_status tcm_step(tcm_handle* h, int32_t nsteps) {
     st = ensure_trace_capacity(h, h->h_state->step + (long long)nsteps - h->t.trace_step0);
     if (st) return st;
     const unsigned long long upd0 = h->h_state->updates + h->h_state->cells_cur;
+    const unsigned long long updu0 = h->h_state->updates_u + h->h_state->cells_cur_u;
 
     // one run of n steps: per-launch HIP events around the stencil, or graph replay
     auto run_chunk = [&](int n) -> tcm_status {
@@ -875,7 +887,10 @@ tcm_status tcm_step(tcm_handle* h, int32_t nsteps) {
     }
     st = sync_state(h);
     if (st) return st;
-    if (timing) h->stencil_cells += (long long)(h->h_state->updates + h->h_state->cells_cur - upd0);
+    if (timing) {
+        h->stencil_cells += (long long)(h->h_state->updates + h->h_state->cells_cur - upd0);
+        h->stencil_cells_u += (long long)(h->h_state->updates_u + h->h_state->cells_cur_u - updu0);
+    }
     if (h->h_state->error) {
         return set_err(h, (tcm_status)h->h_state->error,
                        fmt("pool of %d slots exhausted at step %d; the field is kept at that step",
@@ -953,6 +968,7 @@ tcm_status tcm_stats(tcm_handle* h, tcm_stats_t* o) {
     o->stencil_ms = h->stencil_ms;
     o->stencil_launches = h->stencil_launches;
     o->stencil_cells = h->stencil_cells;
+    o->stencil_cells_uniform = h->stencil_cells_u;
     o->table_bytes = (int64_t)h->table_bytes;
     if (h->engine == TCM_ENGINE_DENSE) {
         HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
@@ -976,6 +992,8 @@ tcm_status tcm_stats(tcm_handle* h, tcm_stats_t* o) {
     o->activations = (int64_t)d.activations;
     o->retirements = (int64_t)d.retirements;
     o->cell_updates = (int64_t)d.updates;
+    o->uniform_cell_updates = (int64_t)d.updates_u;
+    o->decay_block_steps = (int64_t)d.decays;
     o->error = d.error;
     return TCM_OK;
 }
@@ -1004,6 +1022,7 @@ tcm_status tcm_reset(tcm_handle* h) {
     h->stencil_ms = 0.0;
     h->stencil_launches = 0;
     h->stencil_cells = 0;
+    h->stencil_cells_u = 0;
     if (h->engine == TCM_ENGINE_DENSE) {
         const Shot& S = h->shots[0];
         const size_t N = (size_t)S.nx * S.ny * S.nz;
@@ -1132,6 +1151,99 @@ tcm_status tcm_adjoint(tcm_handle* h, const float* resid, int32_t nt, int32_t re
     cleanup();
     if (st) return st;
     if (aerr) return set_err(h, TCM_E_POOL, "pool exhausted in the adjoint field");
+    return TCM_OK;
+}
+
+tcm_status tcm_autotune(tcm_handle* h, int32_t probe_steps, tcm_tuning* out) {
+    tcm_status st = check_live(h);
+    if (st) return st;
+    if (h->engine != TCM_ENGINE_BLOCKS) return set_err(h, TCM_E_STATE, "autotune applies to the block engine");
+    if (probe_steps < 1) return set_err(h, TCM_E_ARG, "probe_steps must be >= 1");
+    st = sync_state(h);
+    if (st) return st;
+    if (h->h_state->error) return set_err(h, TCM_E_STATE, "the run has failed (pool)");
+    st = ensure_trace_capacity(h, h->h_state->step + (long long)probe_steps - h->t.trace_step0);
+    if (st) return st;
+    char* snap = nullptr;
+    st = ck_save(h, &snap);
+    if (st) return st;
+    const int occ = std::max(1, block_step_occupancy());
+    std::vector<int> wpcs;
+    for (int v : {1, 2, 3, 4, 6, 8})
+        if (v <= occ) wpcs.push_back(v);
+    if (std::find(wpcs.begin(), wpcs.end(), occ) == wpcs.end()) wpcs.push_back(occ);
+    const int gss[] = {8, 16, 32};
+    const int keep_grid = h->grid_step, keep_gs = h->gsteps, keep_flags = h->cfg.flags;
+    h->cfg.flags &= ~TCM_FLAG_TIMING;
+    hipEvent_t e0, e1;
+    HIP_OR_FAIL(h, hipEventCreate(&e0));
+    HIP_OR_FAIL(h, hipEventCreate(&e1));
+    tcm_tuning res{};
+    res.ms_per_step = 1e300;
+    int best_grid = keep_grid, best_gs = keep_gs;
+    for (int wpc : wpcs) {
+        for (int gs : gss) {
+            if (res.ncand >= 32) break;
+            h->grid_step = std::max(8, (h->ncu * wpc) / 8 * 8);
+            h->gsteps = gs;
+            drop_graph(h);
+            // one untimed graph launch so capture/instantiation is not timed
+            st = ck_restore(h, snap);
+            if (!st) st = issue_steps(h, std::min(gs, probe_steps));
+            if (!st) st = ck_restore(h, snap);
+            if (st) break;
+            HIP_OR_FAIL(h, hipEventRecord(e0, h->stream));
+            st = issue_steps(h, probe_steps);
+            if (st) break;
+            HIP_OR_FAIL(h, hipEventRecord(e1, h->stream));
+            HIP_OR_FAIL(h, hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIP_OR_FAIL(h, hipEventElapsedTime(&ms, e0, e1));
+            const double per = ms / probe_steps;
+            res.cand_wg_per_cu[res.ncand] = wpc;
+            res.cand_graph_steps[res.ncand] = gs;
+            res.cand_ms_per_step[res.ncand] = per;
+            res.ncand++;
+            if (per < res.ms_per_step) {
+                res.ms_per_step = per;
+                res.wg_per_cu = wpc;
+                res.graph_steps = gs;
+                best_grid = h->grid_step;
+                best_gs = gs;
+            }
+        }
+        if (st) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    h->cfg.flags = keep_flags;
+    tcm_status rs = ck_restore(h, snap);
+    (void)hipFree(snap);
+    drop_graph(h);
+    if (st || rs) {
+        h->grid_step = keep_grid;
+        h->gsteps = keep_gs;
+        return st ? st : rs;
+    }
+    h->grid_step = best_grid;
+    h->gsteps = best_gs;
+    st = sync_state(h);
+    if (st) return st;
+    if (out) *out = res;
+    return TCM_OK;
+}
+
+tcm_status tcm_set_launch(tcm_handle* h, int32_t wg_per_cu, int32_t graph_steps) {
+    tcm_status st = check_live(h);
+    if (st) return st;
+    if (h->engine != TCM_ENGINE_BLOCKS) return set_err(h, TCM_E_STATE, "launch shape applies to the block engine");
+    const int occ = std::max(1, block_step_occupancy());
+    if (wg_per_cu < 1 || wg_per_cu > occ || graph_steps < 1)
+        return set_err(h, TCM_E_ARG, fmt("launch shape needs 1 <= wg_per_cu <= %d and graph_steps >= 1", occ));
+    HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+    h->grid_step = std::max(8, (h->ncu * wg_per_cu) / 8 * 8);
+    h->gsteps = graph_steps;
+    drop_graph(h);
     return TCM_OK;
 }
 

@@ -60,17 +60,21 @@ class Simulation:
                  retire: float = 0.0, pool_bytes: int = 0, engine: str = "blocks",
                  timing: bool = False, graphs: bool = True, stream=None,
                  checkpoint_every: int = 0, graph_steps: int = 0, wg_per_cu: int = 0,
-                 device_pool=None):
+                 device_pool=None, uniform_c2: bool = True, shutdown_steps: int = 0,
+                 shutdown_alpha: float = 1.0):
         lib = L.lib()
         cfg = L.Config()
         cfg.dx, cfg.dt = float(dx), float(dt)
         cfg.trigger, cfg.retire = float(trigger), float(retire)
         cfg.pool_bytes = int(pool_bytes)
         cfg.engine = L.ENGINE_DENSE if engine == "dense" else L.ENGINE_BLOCKS
-        cfg.flags = (L.FLAG_TIMING if timing else 0) | (0 if graphs else L.FLAG_NO_GRAPH)
+        cfg.flags = ((L.FLAG_TIMING if timing else 0) | (0 if graphs else L.FLAG_NO_GRAPH)
+                     | (0 if uniform_c2 else L.FLAG_NO_UNIFORM_C2))
         cfg.checkpoint_every = int(checkpoint_every)
         cfg.graph_steps = int(graph_steps)
         cfg.wg_per_cu = int(wg_per_cu)
+        cfg.shutdown_steps = int(shutdown_steps)
+        cfg.shutdown_alpha = float(shutdown_alpha)
         self._pool_tensor = device_pool
         if device_pool is not None:
             cfg.device_pool = device_pool.data_ptr()
@@ -184,6 +188,42 @@ class Simulation:
         self._check(L.lib().tcm_adjoint(self._h, resid.data_ptr(), resid.shape[0], 1,
                                         grad.data_ptr(), 1))
         return grad
+
+    def autotune(self, probe_steps: int = 32, cache: Optional[str] = None,
+                 key: Optional[str] = None) -> dict:
+        """Pick the launch shape (stencil workgroups per CU, steps per graph)
+        by timing probe_steps steps from the current state for each candidate;
+        the state is unchanged.  With ``cache`` (a JSON file) and ``key``, a
+        stored choice is applied without probing and new choices are stored."""
+        import json
+        import os
+        if cache and key and os.path.exists(cache):
+            with open(cache) as f:
+                stored = json.load(f).get(key)
+            if stored:
+                self._apply_tuning(stored["wg_per_cu"], stored["graph_steps"])
+                return dict(stored, cached=True)
+        t = L.Tuning()
+        self._check(L.lib().tcm_autotune(self._h, int(probe_steps), C.byref(t)))
+        res = {"wg_per_cu": t.wg_per_cu, "graph_steps": t.graph_steps,
+               "ms_per_step": t.ms_per_step, "cached": False,
+               "candidates": [(t.cand_wg_per_cu[i], t.cand_graph_steps[i], t.cand_ms_per_step[i])
+                              for i in range(t.ncand)]}
+        if cache and key:
+            data = {}
+            if os.path.exists(cache):
+                with open(cache) as f:
+                    data = json.load(f)
+            data[key] = {k: res[k] for k in ("wg_per_cu", "graph_steps", "ms_per_step")}
+            with open(cache, "w") as f:
+                json.dump(data, f, indent=1)
+        return res
+
+    def _apply_tuning(self, wg_per_cu: int, graph_steps: int):
+        self._check(L.lib().tcm_set_launch(self._h, int(wg_per_cu), int(graph_steps)))
+
+    def set_launch(self, wg_per_cu: int, graph_steps: int):
+        self._apply_tuning(wg_per_cu, graph_steps)
 
     def reset(self):
         self._check(L.lib().tcm_reset(self._h))

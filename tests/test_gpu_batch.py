@@ -78,3 +78,37 @@ def test_batch_shared_pool_overflow_is_reported():
     assert ei.value.status == -3
     st = b.stats()
     assert st["error"] == -3 and st["active_blocks"] <= 40
+
+
+def test_autotune_keeps_state_and_results(tmp_path):
+    announce("autotune: state unchanged, results unchanged, cache")
+    dt = 0.5 / 4500
+    w = ti.ricker(300.0, dt).w32
+    shots = make_shots(4, seed=21)
+    def fresh():
+        b = tcm.Simulation([s[0] for s in shots], 1.0, dt, [s[1] for s in shots], 1e-4, 1e-5)
+        for i, (shape, lat, src) in enumerate(shots):
+            b.add_source(src, w, shot=i)
+        return b
+    a = fresh()
+    a.step(40)
+    before = [a.read(0, shot=i) for i in range(4)], a.stats()
+    res = a.autotune(probe_steps=8)
+    after = [a.read(0, shot=i) for i in range(4)], a.stats()
+    for x, y in zip(before[0], after[0]):
+        assert values_equal(x, y)
+    for k in ("step", "active_blocks", "cell_updates", "activations", "retirements"):
+        assert before[1][k] == after[1][k], k
+    assert res["candidates"] and (res["wg_per_cu"], res["graph_steps"]) in \
+        [(c[0], c[1]) for c in res["candidates"]]
+    a.step(60)
+    ref = fresh()
+    ref.step(100)
+    for i in range(4):
+        assert values_equal(a.read(0, shot=i), ref.read(0, shot=i))
+    cache = str(tmp_path / "tune.json")
+    r1 = ref.autotune(probe_steps=4, cache=cache, key="gfx950/test")
+    r2 = fresh().autotune(probe_steps=4, cache=cache, key="gfx950/test")
+    assert not r1["cached"] and r2["cached"] and r2["wg_per_cu"] == r1["wg_per_cu"]
+    with pytest.raises(tcm.TCMError):
+        ref.set_launch(0, 16)

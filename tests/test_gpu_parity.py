@@ -248,3 +248,63 @@ def test_input_errors_are_reported():
     with pytest.raises(tcm.TCMError) as ei:
         tcm.Simulation((16, 16, 16), 1.0, 0.6, c)
     assert ei.value.status == -2
+
+
+def test_uniform_c2_blocks_give_identical_results():
+    """Blocks whose C2 is uniform read it as one scalar (the paper's hybrid
+    engine for homogeneous cells); values are identical either way."""
+    announce("uniform-C2 blocks on/off")
+    shape = (70, 45, 60)                          # partial blocks in x, y and z
+    lay = ti.LayeredMedia(np.array([0, 24, 37], np.int32), np.array([1500, 3000, 2200], np.float32))
+    dt = 0.5 / 3000
+    src = [((33, 20, 30), ti.ricker(300.0, dt).w32)]
+    trig, ret = np.float32(1e-5), np.float32(1e-6)
+    a = gpu_run(shape, dt, lay, src, 150, trig, ret, timing=True)
+    b = gpu_run(shape, dt, lay, src, 150, trig, ret, uniform_c2=False, timing=True)
+    assert values_equal(a.read(0), b.read(0)) and values_equal(a.read(1), b.read(1))
+    t = oracle.TCM(lay.dense(*shape), dt, 1.0, trig, ret)
+    t.add_source(*src[0])
+    t.step(150)
+    assert values_equal(a.read(0), t.read(0))
+    sa, sb = a.stats(), b.stats()
+    assert sa["cell_updates"] == sb["cell_updates"] == t.stats()["updates"]
+    assert sb["uniform_cell_updates"] == 0
+    # blocks straddling z = 37 (not a multiple of 8) or cut by the domain edge are not uniform
+    assert 0 < sa["uniform_cell_updates"] < sa["cell_updates"]
+    assert 0 < sa["stencil_cells_uniform"] <= sa["stencil_cells"]
+
+
+@pytest.mark.parametrize("n,alpha", [(20, 0.8), (3, 0.0), (1, 1.0)])
+def test_shutdown_decay_matches_cpu_tcm(n, alpha):
+    announce(f"shutdown decay n={n} alpha={alpha}")
+    shape = (72, 64, 56)
+    c = ti.random_media(shape, seed=9, cmin=0.8, cmax=1.0)
+    w = ti.ricker(0.12, 0.5).w32
+    trig, ret = np.float32(3e-3), np.float32(1e-3)
+    t = oracle.TCM(c, 0.5, 1.0, trig, ret, shutdown_steps=n, shutdown_alpha=np.float32(alpha))
+    t.add_source((36, 32, 28), w)
+    sim = gpu_run(shape, 0.5, c, [((36, 32, 28), w)], 0, trig, ret, shutdown_steps=n,
+                  shutdown_alpha=alpha)
+    for k in range(14):
+        assert t.step(10) == 0
+        sim.step(10)
+        o, g = t.stats(), sim.stats()
+        assert g["active_blocks"] == o["active"], k
+        assert g["activations"] == o["activations"] and g["retirements"] == o["retirements"], k
+        assert g["cell_updates"] == o["updates"], k
+    assert values_equal(sim.read(0), t.read(0))
+    assert values_equal(sim.read(1), t.read(1))
+
+
+def test_shutdown_total_attenuation_eq6_on_gpu():
+    announce("eq.(6) A = alpha^n on the GPU")
+    c = np.ones((16, 16, 16), np.float32)
+    sim = gpu_run((16, 16, 16), 0.0, c, [((3, 3, 3), np.array([1.0, -1.0], np.float32))], 0,
+                  2.0, 2.0, shutdown_steps=5, shutdown_alpha=0.5)
+    vals = []
+    for k in range(8):
+        sim.step(1)
+        vals.append(float(sim.read(0)[3, 3, 3]))
+    assert vals[:7] == [1.0, 0.5, 0.25, 0.125, 0.0625, 0.03125, 0.0]
+    st = sim.stats()
+    assert st["active_blocks"] == 0 and st["decay_block_steps"] == 5

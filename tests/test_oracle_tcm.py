@@ -172,3 +172,52 @@ def test_threshold_error_is_ordered_and_bounded():
     assert errs[1e-6] < 5e-5 and errs[1e-5] < 5e-4 and errs[1e-4] < 5e-3
     assert errs[1e-6] < errs[1e-5] < errs[1e-4]
     assert all(work[a] > work[b] for a, b in zip(rels, rels[1:]))
+
+
+def test_shutdown_decay_total_attenuation_eq6():
+    """With C2 = 0 a field with phi^n = phi^{n-1} is stationary; once its cell
+    stops qualifying, n decay steps scale it by alpha each (A = alpha^n,
+    eq.(6)), then the cell is unboxed."""
+    c = np.ones((16, 16, 16), np.float32)
+    n, alpha = 5, np.float32(0.5)
+    t = oracle.TCM(c, 0.0, 1.0, np.float32(2.0), np.float32(2.0), shutdown_steps=n,
+                   shutdown_alpha=alpha)
+    t.add_source((3, 3, 3), np.array([1.0, -1.0], np.float32))
+    vals = []
+    for k in range(8):
+        assert t.step(1) == 0
+        vals.append(float(t.read(0)[3, 3, 3]))
+    assert vals[:2] == [1.0, 0.5]
+    assert vals[1:6] == [0.5 ** j for j in range(1, 6)]
+    assert vals[5] == oracle.decay_total(0.5, n)
+    assert vals[6] == 0.0 and t.stats()["active"] == 0 and t.check() == 0
+
+
+def test_shutdown_decay_matches_explicit_emulation():
+    """Isolated source cell (thresholds above every value): after the last
+    sample it decays for n steps; emulate with the dense oracle on the cell
+    alone plus explicit alpha scalings of both levels."""
+    shape = (24, 24, 24)
+    c = np.ones(shape[::-1], np.float32)
+    w = ti.ricker(0.15, 0.5).w32
+    big = np.float32(1e30)
+    n, alpha = 7, np.float32(0.8)
+    t = oracle.TCM(c, 0.5, 1.0, big, big, shutdown_steps=n, shutdown_alpha=alpha)
+    t.add_source((13, 10, 9), w)
+    alone = np.ones((8, 8, 8), np.float32)
+    phi = np.zeros((8, 8, 8), np.float32)
+    prev = np.zeros((8, 8, 8), np.float32)
+    ns = w.size
+    for k in range(ns + n + 2):
+        assert t.step(1) == 0
+        phi, prev, _ = oracle.dense_run(alone, 0.5, 1.0, 1, np.float32, phi=phi, phi_prev=prev,
+                                        step0=k, sources=[((5, 2, 1), w)])
+        if ns - 1 <= k < ns - 1 + n:          # cell no longer pinned: decay steps
+            phi = phi * alpha
+            prev = prev * alpha
+        if k == ns - 1 + n:                   # shutdown finished: unboxed
+            phi[:] = 0
+            prev[:] = 0
+        out = t.read(0)
+        assert values_equal(out[8:16, 8:16, 8:16], phi), k
+    assert t.stats()["active"] == 0 and t.check() == 0
