@@ -87,7 +87,11 @@ typedef struct {
                                  multiplied by shutdown_alpha after each, then is released;
                                  0 releases at once.  At most 255. */
     float    shutdown_alpha;  /*   the decay factor alpha; total attenuation A = alpha^n */
-    int32_t  reserved[3];
+    float    trigger_rel;     /* adaptive levels (Table 1 Trig_level): each step uses
+                                 max(trigger, trigger_rel * M) and max(retire, retire_rel * M),
+                                 M = max |phi^{n+1}| over the domain after insertion; */
+    float    retire_rel;      /*   0 <= retire_rel <= trigger_rel; both 0: constant levels */
+    int32_t  reserved[1];
 } tcm_config;
 
 /* Wave-speed model ("Media": an array, or rules evaluated when a block is
@@ -130,6 +134,8 @@ typedef struct {
     int64_t uniform_cell_updates; /* of cell_updates, nodes of blocks read with a scalar C2 */
     int64_t stencil_cells_uniform;/* TCM_FLAG_TIMING: of stencil_cells, nodes with a scalar C2 */
     int64_t decay_block_steps;    /* block-steps of the shutdown decay (eq.(6)) */
+    double  trigger_level;        /* levels used by the last step (adaptive or constant) */
+    double  retire_level;
 } tcm_stats_t;
 
 /* Create a single-shot handle (eq.(3) on an nx*ny*nz grid, "Cells construction").

@@ -97,6 +97,12 @@ def _declare(L):
         f = getattr(L, f"otcm_set_shutdown_{sfx}")
         f.argtypes = [_P, _I, real]
         f.restype = _I
+        f = getattr(L, f"otcm_set_adaptive_{sfx}")
+        f.argtypes = [_P, real, real]
+        f.restype = _I
+        f = getattr(L, f"otcm_levels_{sfx}")
+        f.argtypes = [_P, _P]
+        f.restype = _I
     L.oracle_adjoint_f64.argtypes = [_I, _I, _I, _P, _D, _D, _I, _P, _P, _P, _P, _P,
                                      _I, _P, _I, _P, _I, _P]
     L.oracle_adjoint_f64.restype = _I
@@ -200,7 +206,8 @@ class TCM:
 
     def __init__(self, c: np.ndarray, dt: float, dx: float, trigger: float = 0.0,
                  retire: float = 0.0, block: int = 8, cap: int = 0, dtype=np.float32,
-                 shutdown_steps: int = 0, shutdown_alpha: float = 1.0):
+                 shutdown_steps: int = 0, shutdown_alpha: float = 1.0,
+                 trigger_rel: float = 0.0, retire_rel: float = 0.0):
         self.dtype, self.sfx = _dt(dtype)
         c = np.ascontiguousarray(c, dtype=self.dtype)
         self.shape = (c.shape[2], c.shape[1], c.shape[0])
@@ -215,6 +222,9 @@ class TCM:
         if shutdown_steps:
             if self._f("otcm_set_shutdown")(self._h, int(shutdown_steps), shutdown_alpha) != 0:
                 raise ValueError("shutdown_steps must be in [0, 255]")
+        if trigger_rel or retire_rel:
+            if self._f("otcm_set_adaptive")(self._h, trigger_rel, retire_rel) != 0:
+                raise ValueError("need 0 <= retire_rel <= trigger_rel")
         nx, ny, nz = self.shape
         self.cells_shape = (-(-nz // block), -(-ny // block), -(-nx // block))
 
@@ -266,6 +276,12 @@ class TCM:
         out = np.zeros(self.cells_shape, np.uint8)
         self._f("otcm_triggered")(self._h, _ptr(out))
         return out
+
+    def levels(self):
+        """(trigger, keep level) used by the last activation update."""
+        out = np.zeros(2, self.dtype)
+        self._f("otcm_levels")(self._h, _ptr(out))
+        return float(out[0]), float(out[1])
 
     def check(self) -> int:
         return self._f("otcm_check")(self._h)

@@ -111,6 +111,9 @@ typedef struct SFX(otcm) {
     REAL sd_alpha;
     int* shutdown_log;
     int64_t decays;
+    /* adaptive trigger (Table 1 Trig_level relative to the domain maximum) */
+    REAL trig_rel, ret_rel;
+    REAL last_trig, last_ret;
 } SFX(otcm);
 
 void SFX(otcm_destroy)(SFX(otcm)* t);
@@ -399,6 +402,8 @@ int SFX(otcm_step)(SFX(otcm)* t, int nsteps, REAL* traces, unsigned order_seed)
         /* ---- activation process ("Updating active cells") ---- */
         /* 1. maximal absolute value per active cell (whole box, each face, and phi^n) */
         memset(next, 0, (size_t)t->M);
+        REAL* cmax = (REAL*)malloc(sizeof(REAL) * 8 * (size_t)(t->nactive > 0 ? t->nactive : 1));
+        REAL dom_max = 0;
         for (int64_t a = 0; a < t->nactive; a++) {
             const int64_t cell = t->active[a];
             const int j = t->cell2box[cell];
@@ -421,18 +426,36 @@ int SFX(otcm_step)(SFX(otcm)* t, int nsteps, REAL* traces, unsigned order_seed)
                         if (z == B - 1 && v > face[5]) face[5] = v;
                     }
             t->max_val[cell] = mx;
+            for (int f = 0; f < 6; f++) cmax[8 * a + f] = face[f];
+            cmax[8 * a + 6] = mx;
+            cmax[8 * a + 7] = mprev;
+            if (mx > dom_max) dom_max = mx;
+        }
+        /* trigger and keep levels: constant, or relative to the domain maximum */
+        REAL trig = t->trigger, ret = t->retire;
+        if (t->trig_rel > 0 || t->ret_rel > 0) {
+            const REAL at = t->trig_rel * dom_max, ar = t->ret_rel * dom_max;
+            if (at > trig) trig = at;
+            if (ar > ret) ret = ar;
+        }
+        t->last_trig = trig;
+        t->last_ret = ret;
+        for (int64_t a = 0; a < t->nactive; a++) {
+            const int64_t cell = t->active[a];
+            const REAL* m = cmax + 8 * a;
             /* 2. register the current active cells */
             t->hist[cell] = 1;
             /* 3. keep cells whose field (new or current level) is above the retire level,
              *    and source cells that still insert samples */
-            if (mx > t->retire || mprev > t->retire || SFX(pinned)(t, cell, n + 1)) next[cell] = 1;
+            if (m[6] > ret || m[7] > ret || SFX(pinned)(t, cell, n + 1)) next[cell] = 1;
             /* 4. trigger the face neighbours across faces whose field exceeds the trigger */
             for (int f = 0; f < 6; f++) {
-                if (!(face[f] > t->trigger)) continue;
+                if (!(m[f] > trig)) continue;
                 const int64_t nb = SFX(linked_cell)(t, cell, f);
                 if (nb >= 0) next[nb] = 1;
             }
         }
+        free(cmax);
         /* 6. shutdown process (eq.(6)) for active cells that are no longer triggered */
         unsigned char* decay = NULL;
         if (t->sd_steps > 0) {
@@ -545,6 +568,25 @@ int SFX(otcm_set_shutdown)(SFX(otcm)* t, int n, REAL alpha)
     if (n < 0 || n > 255) return -1;
     t->sd_steps = n;
     t->sd_alpha = alpha;
+    return 0;
+}
+
+/* Adaptive levels: at each activation update the trigger is
+ * max(trigger, trig_rel * M) and the keep level max(retire, ret_rel * M), M
+ * the maximal |phi^{n+1}| over the active cells (item 1 of the update). */
+int SFX(otcm_set_adaptive)(SFX(otcm)* t, REAL trig_rel, REAL ret_rel)
+{
+    if (!(trig_rel >= 0) || !(ret_rel >= 0) || ret_rel > trig_rel) return -1;
+    t->trig_rel = trig_rel;
+    t->ret_rel = ret_rel;
+    return 0;
+}
+
+/* Levels used by the last activation update: out[0] trigger, out[1] keep level. */
+int SFX(otcm_levels)(const SFX(otcm)* t, REAL* out)
+{
+    out[0] = t->last_trig;
+    out[1] = t->last_ret;
     return 0;
 }
 

@@ -32,7 +32,8 @@ class Config(C.Structure):
                 ("engine", C.c_int32), ("flags", C.c_int32), ("checkpoint_every", C.c_int32),
                 ("graph_steps", C.c_int32), ("wg_per_cu", C.c_int32),
                 ("shutdown_steps", C.c_int32), ("shutdown_alpha", C.c_float),
-                ("reserved", C.c_int32 * 3)]
+                ("trigger_rel", C.c_float), ("retire_rel", C.c_float),
+                ("reserved", C.c_int32 * 1)]
 
 
 class Media(C.Structure):
@@ -55,7 +56,8 @@ class Stats(C.Structure):
                 ("error", C.c_int32), ("nshots", C.c_int32),
                 ("stencil_ms", C.c_double), ("stencil_launches", C.c_int64),
                 ("stencil_cells", C.c_int64), ("uniform_cell_updates", C.c_int64),
-                ("stencil_cells_uniform", C.c_int64), ("decay_block_steps", C.c_int64)]
+                ("stencil_cells_uniform", C.c_int64), ("decay_block_steps", C.c_int64),
+                ("trigger_level", C.c_double), ("retire_level", C.c_double)]
 
 
 class Tuning(C.Structure):

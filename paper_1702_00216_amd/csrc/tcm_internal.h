@@ -51,6 +51,9 @@ struct DevState {
     unsigned long long cells_cur_u;  // ... of those, nodes of blocks with a uniform C2
     unsigned long long updates_u;
     unsigned long long decays;       // block-steps of the shutdown decay
+    unsigned maxbits;                // adaptive levels: max |phi^{n+1}| of this step (float bits)
+    float trig_cur, ret_cur;         // levels used by the last plan
+    int pad2;
     unsigned long long activations, retirements;
 };
 
@@ -87,6 +90,9 @@ struct Tables {
     int* dec_slot;                  // per step: slots whose levels are multiplied by alpha
     int shutdown_steps;             // eq.(6) n (0: release at once)
     float shutdown_alpha;           // eq.(6) alpha
+    int adaptive;                   // levels relative to the domain maximum (Table 1 Trig_level)
+    float trigger_rel, retire_rel;
+    float* bmax;                    // adaptive: per slot 6 face maxima, max |phi^{n+1}|, max |phi^n|
     int uniform_c2;                 // 1: blocks with a uniform C2 read it as a scalar
     long long* slot_key;            // per slot: global key or -1
     int* free_stack;                // free slots, top in DevState::free_top
@@ -114,7 +120,7 @@ constexpr int POOL_COUNT_MAX_WG = 1024;
 // ---- launch wrappers (tcm_kernels.hip) -----------------------------------
 hipError_t launch_init_tables(const Tables& t, long long nkeys, hipStream_t s);
 hipError_t launch_block_step(const Tables& t, int grid, hipStream_t s);
-int block_step_occupancy();        // resident 256-thread workgroups per CU
+int block_step_occupancy(bool adaptive = false);   // resident 256-thread workgroups per CU
 hipError_t launch_plan(const Tables& t, int grid, hipStream_t s);
 hipError_t launch_pool_count(const Tables& t, int grid, hipStream_t s);   // grid <= POOL_COUNT_MAX_WG
 hipError_t launch_emit(const Tables& t, hipStream_t s);

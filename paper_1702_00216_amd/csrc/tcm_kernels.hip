@@ -184,6 +184,7 @@ __global__ void k_init_tables(Tables t, long long nkeys) {
         st->peak_act = 0; st->done_wgs = 0; st->add_error = 0; st->n_dec = 0;
         st->cells_cur = 0; st->updates = 0; st->activations = 0; st->retirements = 0;
         st->cells_cur_u = 0; st->updates_u = 0; st->decays = 0;
+        st->maxbits = 0u; st->trig_cur = t.trigger; st->ret_cur = t.retire; st->pad2 = 0;
     }
 }
 
@@ -206,6 +207,7 @@ hipError_t launch_init_tables(const Tables& t, long long nkeys, hipStream_t s) {
 constexpr int TILE_COLS = 10;
 constexpr int TILE_FLOATS = TILE_COLS * TILE_COLS * BE;
 
+template <bool ADAPT>
 __global__ __launch_bounds__(256) void k_block_step(Tables t) {
     __shared__ __align__(16) float lds[4][TILE_FLOATS];
     const DevState* st = t.st;
@@ -229,6 +231,7 @@ __global__ __launch_bounds__(256) void k_block_step(Tables t) {
     const int beg = xcd * seg;
     const int end = min(nact, beg + seg);
     const float trig = t.trigger, ret = t.retire;
+    float wave_max = 0.f;
 
     // Each list entry has a row {slot, 6 neighbour slots, global key} written by
     // the compaction; the next row is fetched while the current block is
@@ -337,39 +340,69 @@ __global__ __launch_bounds__(256) void k_block_step(Tables t) {
 #pragma unroll
         for (int z = 0; z < 8; z++) out_p[z * 64 + lane] = nv[z];
 
-        bool keep = false, col = false;
+        if constexpr (ADAPT) {
+            // per-block maxima (Table 1 Max_cell_val, per face and whole block);
+            // the plan compares them with this step's levels
+            float colmax = 0.f, curmax = 0.f;
 #pragma unroll
-        for (int z = 0; z < 8; z++) {
-            const float an = fabsf(nv[z]);
-            keep = keep || an > ret || fabsf(cur[z]) > ret;
-            col = col || an > trig;
-        }
-        const unsigned long long bk = __ballot(keep);
-        const unsigned long long bc = __ballot(col);
-        const unsigned long long bz0 = __ballot(fabsf(nv[0]) > trig);
-        const unsigned long long bz7 = __ballot(fabsf(nv[7]) > trig);
-        if (lane == 0) {
-            unsigned f = 0;
-            if (bc & 0x0101010101010101ull) f |= 1u;    // x = 0 column
-            if (bc & 0x8080808080808080ull) f |= 2u;    // x = 7
-            if (bc & 0x00000000000000FFull) f |= 4u;    // y = 0
-            if (bc & 0xFF00000000000000ull) f |= 8u;    // y = 7
-            if (bz0) f |= 16u;
-            if (bz7) f |= 32u;
-            if (bk) f |= (unsigned)KEEP_BIT;
-            t.flags[slot] = (unsigned char)f;
+            for (int z = 0; z < 8; z++) {
+                colmax = fmaxf(colmax, fabsf(nv[z]));
+                curmax = fmaxf(curmax, fabsf(cur[z]));
+            }
+            float v[8] = {x == 0 ? colmax : 0.f, x == 7 ? colmax : 0.f, y == 0 ? colmax : 0.f,
+                          y == 7 ? colmax : 0.f, fabsf(nv[0]), fabsf(nv[7]), colmax, curmax};
+            for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
+                for (int k = 0; k < 8; k++) v[k] = fmaxf(v[k], __shfl_xor(v[k], o));
+            }
+            if (lane == 0) {
+                float4* bm = (float4*)(t.bmax + 8 * (size_t)slot);
+                bm[0] = make_float4(v[0], v[1], v[2], v[3]);
+                bm[1] = make_float4(v[4], v[5], v[6], v[7]);
+            }
+            wave_max = fmaxf(wave_max, v[6]);
+        } else {
+            bool keep = false, col = false;
+#pragma unroll
+            for (int z = 0; z < 8; z++) {
+                const float an = fabsf(nv[z]);
+                keep = keep || an > ret || fabsf(cur[z]) > ret;
+                col = col || an > trig;
+            }
+            const unsigned long long bk = __ballot(keep);
+            const unsigned long long bc = __ballot(col);
+            const unsigned long long bz0 = __ballot(fabsf(nv[0]) > trig);
+            const unsigned long long bz7 = __ballot(fabsf(nv[7]) > trig);
+            if (lane == 0) {
+                unsigned f = 0;
+                if (bc & 0x0101010101010101ull) f |= 1u;    // x = 0 column
+                if (bc & 0x8080808080808080ull) f |= 2u;    // x = 7
+                if (bc & 0x00000000000000FFull) f |= 4u;    // y = 0
+                if (bc & 0xFF00000000000000ull) f |= 8u;    // y = 7
+                if (bz0) f |= 16u;
+                if (bz7) f |= 32u;
+                if (bk) f |= (unsigned)KEEP_BIT;
+                t.flags[slot] = (unsigned char)f;
+            }
         }
     }
+    if (ADAPT && lane == 0 && wave_max > 0.f)
+        atomicMax((unsigned*)&t.st->maxbits, __float_as_uint(wave_max));   // non-negative floats order as integers
 }
 
-int block_step_occupancy() {
+int block_step_occupancy(bool adaptive) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_block_step, 256, 0) != hipSuccess) return 0;
-    return nb;
+    hipError_t e = adaptive
+        ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_block_step<true>, 256, 0)
+        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_block_step<false>, 256, 0);
+    return e == hipSuccess ? nb : 0;
 }
 
 hipError_t launch_block_step(const Tables& t, int grid, hipStream_t s) {
-    hipLaunchKernelGGL(k_block_step, dim3(grid), dim3(256), 0, s, t);
+    if (t.adaptive)
+        hipLaunchKernelGGL(k_block_step<true>, dim3(grid), dim3(256), 0, s, t);
+    else
+        hipLaunchKernelGGL(k_block_step<false>, dim3(grid), dim3(256), 0, s, t);
     return hipGetLastError();
 }
 
@@ -386,6 +419,17 @@ __global__ __launch_bounds__(256) void k_plan(Tables t) {
     const int g0 = blockIdx.x * blockDim.x + threadIdx.x;
 
     // receivers: traces[n - trace_step0][r] = phi^{n+1}
+    // levels of this step: constant, or relative to the domain maximum
+    float trig = t.trigger, ret = t.retire;
+    if (t.adaptive) {
+        const float M = __uint_as_float(st->maxbits);
+        trig = fmaxf(trig, t.trigger_rel * M);
+        ret = fmaxf(ret, t.retire_rel * M);
+        if (g0 == 0) {
+            st->trig_cur = trig;
+            st->ret_cur = ret;
+        }
+    }
     const int row = n - t.trace_step0;
     if (row >= 0 && row < t.trace_cap) {
         for (int r = g0; r < t.nrec; r += gsz) {
@@ -407,7 +451,15 @@ __global__ __launch_bounds__(256) void k_plan(Tables t) {
             slot = t.act_slot[i];
             shot = t.act_shot[i];
             key = t.act_key[i];
-            f = t.flags[slot];
+            if (t.adaptive) {
+                const float* bm = t.bmax + 8 * (size_t)slot;
+                f = 0;
+                for (int d = 0; d < 6; d++)
+                    if (bm[d] > trig) f |= 1u << d;
+                if (bm[6] > ret || bm[7] > ret) f |= (unsigned)KEEP_BIT;
+            } else {
+                f = t.flags[slot];
+            }
             key_to_block(t.shots[shot], key, bx, by, bz);
             survive = (f & KEEP_BIT) != 0 || t.pin_until[slot] > n + 1;
         }
@@ -420,7 +472,9 @@ __global__ __launch_bounds__(256) void k_plan(Tables t) {
                     const int s_nb = t.cell2box[nk];
                     if (s_nb >= 0) {
                         // an active neighbour whose face toward us is above trigger
-                        if ((t.flags[s_nb] >> (d ^ 1)) & 1u) survive = true;
+                        const bool face = t.adaptive ? t.bmax[8 * (size_t)s_nb + (d ^ 1)] > trig
+                                                     : ((t.flags[s_nb] >> (d ^ 1)) & 1u) != 0;
+                        if (face) survive = true;
                     } else if (((f >> d) & 1u) && s_nb == EMPTY) {
                         claim = atomicCAS(&t.cell2box[nk], EMPTY, CLAIMED) == EMPTY;
                     }
@@ -609,6 +663,7 @@ __global__ __launch_bounds__(256) void k_pool_count(Tables t) {
         st->n_new = 0;
         st->n_ret = 0;
         st->n_dec = 0;
+        st->maxbits = 0u;
         st->done_wgs = 0;
         __threadfence();
     }

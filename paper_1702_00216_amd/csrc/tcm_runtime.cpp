@@ -340,6 +340,10 @@ tcm_status setup_engine(tcm_handle* h, long long word_base) {
     ok = ok && dalloc(h, &t.dec_slot, (size_t)cap) == hipSuccess;
     t.shutdown_steps = cfg->shutdown_steps;
     t.shutdown_alpha = cfg->shutdown_alpha;
+    t.adaptive = (cfg->trigger_rel > 0.f || cfg->retire_rel > 0.f) ? 1 : 0;
+    t.trigger_rel = cfg->trigger_rel;
+    t.retire_rel = cfg->retire_rel;
+    ok = ok && dalloc(h, &t.bmax, t.adaptive ? (size_t)cap * 8 : 1) == hipSuccess;
     t.uniform_c2 = (cfg->flags & TCM_FLAG_NO_UNIFORM_C2) ? 0 : 1;
     ok = ok && dalloc(h, &t.slot_key, (size_t)cap) == hipSuccess;
     ok = ok && dalloc(h, &t.free_stack, (size_t)cap) == hipSuccess;
@@ -355,7 +359,7 @@ tcm_status setup_engine(tcm_handle* h, long long word_base) {
 
     // persistent stencil grid: exactly the resident workgroups (a larger grid
     // would leave a tail of workgroups that start after the first wave of them)
-    const int occ = block_step_occupancy();
+    const int occ = block_step_occupancy(t.adaptive != 0);
     const int wpc = cfg->wg_per_cu > 0 ? cfg->wg_per_cu : (occ > 0 ? occ : 4);
     h->grid_step = std::max(8, (h->ncu * wpc) / 8 * 8);
     h->grid_plan = std::max(1, h->ncu * 2);
@@ -380,6 +384,9 @@ tcm_status create_common(const tcm_config* cfg, const tcm_shot* shots, int nshot
         (cfg->shutdown_steps > 0 && !(std::isfinite(cfg->shutdown_alpha) && cfg->shutdown_alpha >= 0.f &&
                                       cfg->shutdown_alpha <= 1.f)))
         return set_err(nullptr, TCM_E_ARG, "shutdown needs 0 <= steps <= 255 and 0 <= alpha <= 1");
+    if (!(cfg->trigger_rel >= 0.f) || !(cfg->retire_rel >= 0.f) || !std::isfinite(cfg->trigger_rel) ||
+        !std::isfinite(cfg->retire_rel) || cfg->retire_rel > cfg->trigger_rel)
+        return set_err(nullptr, TCM_E_ARG, "relative levels must satisfy 0 <= retire_rel <= trigger_rel");
     if (cfg->engine == TCM_ENGINE_DENSE && nshots != 1)
         return set_err(nullptr, TCM_E_ARG, "the dense engine runs one shot");
 
@@ -994,6 +1001,8 @@ tcm_status tcm_stats(tcm_handle* h, tcm_stats_t* o) {
     o->cell_updates = (int64_t)d.updates;
     o->uniform_cell_updates = (int64_t)d.updates_u;
     o->decay_block_steps = (int64_t)d.decays;
+    o->trigger_level = d.trig_cur;
+    o->retire_level = d.ret_cur;
     o->error = d.error;
     return TCM_OK;
 }
@@ -1167,7 +1176,7 @@ tcm_status tcm_autotune(tcm_handle* h, int32_t probe_steps, tcm_tuning* out) {
     char* snap = nullptr;
     st = ck_save(h, &snap);
     if (st) return st;
-    const int occ = std::max(1, block_step_occupancy());
+    const int occ = std::max(1, block_step_occupancy(h->t.adaptive != 0));
     std::vector<int> wpcs;
     for (int v : {1, 2, 3, 4, 6, 8})
         if (v <= occ) wpcs.push_back(v);
@@ -1237,7 +1246,7 @@ tcm_status tcm_set_launch(tcm_handle* h, int32_t wg_per_cu, int32_t graph_steps)
     tcm_status st = check_live(h);
     if (st) return st;
     if (h->engine != TCM_ENGINE_BLOCKS) return set_err(h, TCM_E_STATE, "launch shape applies to the block engine");
-    const int occ = std::max(1, block_step_occupancy());
+    const int occ = std::max(1, block_step_occupancy(h->t.adaptive != 0));
     if (wg_per_cu < 1 || wg_per_cu > occ || graph_steps < 1)
         return set_err(h, TCM_E_ARG, fmt("launch shape needs 1 <= wg_per_cu <= %d and graph_steps >= 1", occ));
     HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));

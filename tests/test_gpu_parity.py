@@ -308,3 +308,29 @@ def test_shutdown_total_attenuation_eq6_on_gpu():
     assert vals[:7] == [1.0, 0.5, 0.25, 0.125, 0.0625, 0.03125, 0.0]
     st = sim.stats()
     assert st["active_blocks"] == 0 and st["decay_block_steps"] == 5
+
+
+@pytest.mark.parametrize("rt,rr,n", [(1e-3, 1e-4, 0), (3e-2, 3e-2, 0), (1e-3, 2e-4, 10)])
+def test_adaptive_levels_match_cpu_tcm(rt, rr, n):
+    """Levels relative to the domain maximum (Table 1 Trig_level): the GPU uses
+    the same per-step levels and makes the same decisions as the CPU TCM."""
+    announce(f"adaptive levels rel {rt}/{rr} shutdown {n}")
+    shape = (72, 64, 56)
+    c = ti.random_media(shape, seed=9, cmin=0.8, cmax=1.0)
+    w = ti.ricker(0.12, 0.5).w32
+    rt, rr = np.float32(rt), np.float32(rr)
+    t = oracle.TCM(c, 0.5, 1.0, 0.0, 0.0, trigger_rel=rt, retire_rel=rr, shutdown_steps=n,
+                   shutdown_alpha=np.float32(0.7))
+    t.add_source((36, 32, 28), w)
+    sim = gpu_run(shape, 0.5, c, [((36, 32, 28), w)], 0, trigger_rel=rt, retire_rel=rr,
+                  shutdown_steps=n, shutdown_alpha=0.7)
+    for k in range(30):
+        assert t.step(5) == 0
+        sim.step(5)
+        o, g = t.stats(), sim.stats()
+        assert (g["trigger_level"], g["retire_level"]) == t.levels(), k
+        assert g["active_blocks"] == o["active"], k
+        assert g["activations"] == o["activations"] and g["retirements"] == o["retirements"], k
+        assert g["cell_updates"] == o["updates"], k
+    assert values_equal(sim.read(0), t.read(0))
+    assert values_equal(sim.read(1), t.read(1))

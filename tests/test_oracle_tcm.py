@@ -221,3 +221,27 @@ def test_shutdown_decay_matches_explicit_emulation():
         out = t.read(0)
         assert values_equal(out[8:16, 8:16, 8:16], phi), k
     assert t.stats()["active"] == 0 and t.check() == 0
+
+
+def test_adaptive_levels_follow_domain_maximum():
+    """Table 1 Trig_level relative to the domain maximum: the levels of each
+    update are rel * max|phi^{n+1}| (the cell holding the maximum is kept)."""
+    w = ti.c1(steps=80)
+    rt, rr = np.float32(1e-3), np.float32(1e-4)
+    t = oracle.TCM(w.c_dense, w.dt, 1.0, 0.0, 0.0, trigger_rel=rt, retire_rel=rr)
+    t.add_source(w.source, w.wavelet.w32)
+    work = []
+    for k in range(80):
+        assert t.step(1) == 0
+        m = np.float32(np.max(np.abs(t.read(0))))
+        trig, ret = t.levels()
+        assert trig == float(rt * m) and ret == float(rr * m), k
+        work.append(t.stats()["updates"])
+    fixed = oracle.TCM(w.c_dense, w.dt, 1.0, 0.0, 0.0)
+    fixed.add_source(w.source, w.wavelet.w32)
+    fixed.step(80)
+    assert work[-1] < fixed.stats()["updates"]
+    zero = oracle.TCM(w.c_dense, w.dt, 1.0, 0.0, 0.0, trigger_rel=0.0, retire_rel=0.0)
+    zero.add_source(w.source, w.wavelet.w32)
+    zero.step(80)
+    assert values_equal(zero.read(0), fixed.read(0))
