@@ -91,7 +91,11 @@ typedef struct {
                                  max(trigger, trigger_rel * M) and max(retire, retire_rel * M),
                                  M = max |phi^{n+1}| over the domain after insertion; */
     float    retire_rel;      /*   0 <= retire_rel <= trigger_rel; both 0: constant levels */
-    int32_t  reserved[1];
+    int32_t  trigger_interval;/* activation update after every k-th step (eq.(5)), 1 <= k <= 8
+                                 (0: 1).  With k > 1 a block holding any |phi| above the
+                                 trigger activates all 26 nearest and diagonal blocks (Figure 3),
+                                 and a source block's 26 neighbours are activated with it, so
+                                 that trigger = retire = 0 stays equal to the dense grid. */
 } tcm_config;
 
 /* Wave-speed model ("Media": an array, or rules evaluated when a block is

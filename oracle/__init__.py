@@ -103,6 +103,9 @@ def _declare(L):
         f = getattr(L, f"otcm_levels_{sfx}")
         f.argtypes = [_P, _P]
         f.restype = _I
+        f = getattr(L, f"otcm_set_interval_{sfx}")
+        f.argtypes = [_P, _I]
+        f.restype = _I
     L.oracle_adjoint_f64.argtypes = [_I, _I, _I, _P, _D, _D, _I, _P, _P, _P, _P, _P,
                                      _I, _P, _I, _P, _I, _P]
     L.oracle_adjoint_f64.restype = _I
@@ -207,7 +210,7 @@ class TCM:
     def __init__(self, c: np.ndarray, dt: float, dx: float, trigger: float = 0.0,
                  retire: float = 0.0, block: int = 8, cap: int = 0, dtype=np.float32,
                  shutdown_steps: int = 0, shutdown_alpha: float = 1.0,
-                 trigger_rel: float = 0.0, retire_rel: float = 0.0):
+                 trigger_rel: float = 0.0, retire_rel: float = 0.0, interval: int = 1):
         self.dtype, self.sfx = _dt(dtype)
         c = np.ascontiguousarray(c, dtype=self.dtype)
         self.shape = (c.shape[2], c.shape[1], c.shape[0])
@@ -222,6 +225,9 @@ class TCM:
         if shutdown_steps:
             if self._f("otcm_set_shutdown")(self._h, int(shutdown_steps), shutdown_alpha) != 0:
                 raise ValueError("shutdown_steps must be in [0, 255]")
+        if interval != 1:
+            if self._f("otcm_set_interval")(self._h, int(interval)) != 0:
+                raise ValueError("interval must be in [1, block edge]")
         if trigger_rel or retire_rel:
             if self._f("otcm_set_adaptive")(self._h, trigger_rel, retire_rel) != 0:
                 raise ValueError("need 0 <= retire_rel <= trigger_rel")

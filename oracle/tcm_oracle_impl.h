@@ -114,6 +114,9 @@ typedef struct SFX(otcm) {
     /* adaptive trigger (Table 1 Trig_level relative to the domain maximum) */
     REAL trig_rel, ret_rel;
     REAL last_trig, last_ret;
+    /* activation update every `interval` steps (eq.(5)); > 1 uses the 26 nearest
+     * and diagonal cells (Table 1 Linked_cells + Diag_cells, Figure 3) */
+    int interval;
 } SFX(otcm);
 
 void SFX(otcm_destroy)(SFX(otcm)* t);
@@ -220,6 +223,7 @@ SFX(otcm)* SFX(otcm_create)(int nx, int ny, int nz, int B, const REAL* c, double
     t->active = (int64_t*)malloc((size_t)t->M * sizeof(int64_t));
     t->shutdown_log = (int*)calloc((size_t)t->M, sizeof(int));
     t->sd_alpha = (REAL)1;
+    t->interval = 1;
     if (!t->shutdown_log ||
         !t->c || !t->triggered || !t->hist || !t->max_val || !t->cell2box || !t->box2cell ||
         !t->boxes || !t->vacant || !t->active) {
@@ -263,6 +267,21 @@ int SFX(otcm_add_source)(SFX(otcm)* t, int x, int y, int z, const REAL* w, int n
     if (t->cell2box[cell] < 0) {
         if (SFX(box_cell)(t, cell) < 0) return -3;
         t->activations++;
+    }
+    if (t->interval > 1) {
+        /* the source reaches the cells around it before the next update */
+        int cx, cy, cz;
+        SFX(cell_coords)(t, cell, &cx, &cy, &cz);
+        for (int dz = -1; dz <= 1; dz++)
+            for (int dy = -1; dy <= 1; dy++)
+                for (int dx = -1; dx <= 1; dx++) {
+                    const int x2 = cx + dx, y2 = cy + dy, z2 = cz + dz;
+                    if (x2 < 0 || y2 < 0 || z2 < 0 || x2 >= t->mx || y2 >= t->my || z2 >= t->mz) continue;
+                    const int64_t nb = (int64_t)x2 + (int64_t)t->mx * ((int64_t)y2 + (int64_t)t->my * z2);
+                    if (t->cell2box[nb] >= 0) continue;
+                    if (SFX(box_cell)(t, nb) < 0) return -3;
+                    t->activations++;
+                }
     }
     const int s = t->nsrc++;
     t->src_cell = (int64_t*)realloc(t->src_cell, sizeof(int64_t) * t->nsrc);
@@ -399,7 +418,12 @@ int SFX(otcm_step)(SFX(otcm)* t, int nsteps, REAL* traces, unsigned order_seed)
         }
         for (int64_t a = 0; a < t->nactive; a++) t->updates += SFX(cell_ncells)(t, t->active[a]);
 
-        /* ---- activation process ("Updating active cells") ---- */
+        /* ---- activation process ("Updating active cells"), every `interval` steps ---- */
+        if ((n + 1) % t->interval != 0) {
+            t->cur ^= 1;
+            t->step++;
+            continue;
+        }
         /* 1. maximal absolute value per active cell (whole box, each face, and phi^n) */
         memset(next, 0, (size_t)t->M);
         REAL* cmax = (REAL*)malloc(sizeof(REAL) * 8 * (size_t)(t->nactive > 0 ? t->nactive : 1));
@@ -448,11 +472,28 @@ int SFX(otcm_step)(SFX(otcm)* t, int nsteps, REAL* traces, unsigned order_seed)
             /* 3. keep cells whose field (new or current level) is above the retire level,
              *    and source cells that still insert samples */
             if (m[6] > ret || m[7] > ret || SFX(pinned)(t, cell, n + 1)) next[cell] = 1;
-            /* 4. trigger the face neighbours across faces whose field exceeds the trigger */
-            for (int f = 0; f < 6; f++) {
-                if (!(m[f] > trig)) continue;
-                const int64_t nb = SFX(linked_cell)(t, cell, f);
-                if (nb >= 0) next[nb] = 1;
+            if (t->interval == 1) {
+                /* 4. trigger the face neighbours across faces whose field exceeds the trigger */
+                for (int f = 0; f < 6; f++) {
+                    if (!(m[f] > trig)) continue;
+                    const int64_t nb = SFX(linked_cell)(t, cell, f);
+                    if (nb >= 0) next[nb] = 1;
+                }
+            } else if (m[6] > trig || m[7] > trig || SFX(pinned)(t, cell, n + 1)) {
+                /* 4-5. a cell above the trigger anywhere (either level), or one whose
+                 *      source still inserts, triggers its nearest and diagonal
+                 *      neighbours (Figure 3 a-c) */
+                int cx, cy, cz;
+                SFX(cell_coords)(t, cell, &cx, &cy, &cz);
+                for (int dz = -1; dz <= 1; dz++)
+                    for (int dy = -1; dy <= 1; dy++)
+                        for (int dx = -1; dx <= 1; dx++) {
+                            const int x = cx + dx, y = cy + dy, z = cz + dz;
+                            if ((dx | dy | dz) == 0 || x < 0 || y < 0 || z < 0 || x >= t->mx ||
+                                y >= t->my || z >= t->mz)
+                                continue;
+                            next[(int64_t)x + (int64_t)t->mx * ((int64_t)y + (int64_t)t->my * z)] = 1;
+                        }
             }
         }
         free(cmax);
@@ -579,6 +620,17 @@ int SFX(otcm_set_adaptive)(SFX(otcm)* t, REAL trig_rel, REAL ret_rel)
     if (!(trig_rel >= 0) || !(ret_rel >= 0) || ret_rel > trig_rel) return -1;
     t->trig_rel = trig_rel;
     t->ret_rel = ret_rel;
+    return 0;
+}
+
+/* Run the activation update after every k-th step (1 <= k <= block edge).
+ * With k > 1 a cell holding any |phi^{n+1}| above the trigger activates all 26
+ * cells around it (nearest and diagonal), so that a value moving one node per
+ * step cannot leave the active region before the next update. */
+int SFX(otcm_set_interval)(SFX(otcm)* t, int k)
+{
+    if (k < 1 || k > t->B) return -1;
+    t->interval = k;
     return 0;
 }
 

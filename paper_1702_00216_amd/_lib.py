@@ -33,7 +33,7 @@ class Config(C.Structure):
                 ("graph_steps", C.c_int32), ("wg_per_cu", C.c_int32),
                 ("shutdown_steps", C.c_int32), ("shutdown_alpha", C.c_float),
                 ("trigger_rel", C.c_float), ("retire_rel", C.c_float),
-                ("reserved", C.c_int32 * 1)]
+                ("trigger_interval", C.c_int32)]
 
 
 class Media(C.Structure):

@@ -18,6 +18,7 @@ constexpr int C2_PLANE = 2 * BV;
 constexpr int EMPTY = -1;
 constexpr int CLAIMED = -2;
 constexpr int KEEP_BIT = 64;
+constexpr int HOT_BIT = 128;       // any |phi| of either level above the trigger
 
 // Blocks are numbered per shot in 4x4x4 tiles: key = tile * 64 + local with
 // local = (lz * 4 + ly) * 4 + lx, tiles in x-fastest order.  One 64-bit word
@@ -90,6 +91,7 @@ struct Tables {
     int* dec_slot;                  // per step: slots whose levels are multiplied by alpha
     int shutdown_steps;             // eq.(6) n (0: release at once)
     float shutdown_alpha;           // eq.(6) alpha
+    int interval;                   // activation update after every interval-th step (1..8)
     int adaptive;                   // levels relative to the domain maximum (Table 1 Trig_level)
     float trigger_rel, retire_rel;
     float* bmax;                    // adaptive: per slot 6 face maxima, max |phi^{n+1}|, max |phi^n|
@@ -122,6 +124,7 @@ hipError_t launch_init_tables(const Tables& t, long long nkeys, hipStream_t s);
 hipError_t launch_block_step(const Tables& t, int grid, hipStream_t s);
 int block_step_occupancy(bool adaptive = false);   // resident 256-thread workgroups per CU
 hipError_t launch_plan(const Tables& t, int grid, hipStream_t s);
+hipError_t launch_advance(const Tables& t, hipStream_t s);   // step without an activation update
 hipError_t launch_pool_count(const Tables& t, int grid, hipStream_t s);   // grid <= POOL_COUNT_MAX_WG
 hipError_t launch_emit(const Tables& t, hipStream_t s);
 hipError_t launch_activate(const Tables& t, long long key, int shot, unsigned local_key,

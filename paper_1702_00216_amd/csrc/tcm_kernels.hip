@@ -362,15 +362,17 @@ __global__ __launch_bounds__(256) void k_block_step(Tables t) {
             }
             wave_max = fmaxf(wave_max, v[6]);
         } else {
-            bool keep = false, col = false;
+            bool keep = false, col = false, hot = false;
 #pragma unroll
             for (int z = 0; z < 8; z++) {
-                const float an = fabsf(nv[z]);
-                keep = keep || an > ret || fabsf(cur[z]) > ret;
+                const float an = fabsf(nv[z]), ac = fabsf(cur[z]);
+                keep = keep || an > ret || ac > ret;
                 col = col || an > trig;
+                hot = hot || ac > trig;
             }
             const unsigned long long bk = __ballot(keep);
             const unsigned long long bc = __ballot(col);
+            const unsigned long long bh = __ballot(hot);
             const unsigned long long bz0 = __ballot(fabsf(nv[0]) > trig);
             const unsigned long long bz7 = __ballot(fabsf(nv[7]) > trig);
             if (lane == 0) {
@@ -382,6 +384,7 @@ __global__ __launch_bounds__(256) void k_block_step(Tables t) {
                 if (bz0) f |= 16u;
                 if (bz7) f |= 32u;
                 if (bk) f |= (unsigned)KEEP_BIT;
+                if (bc | bh) f |= (unsigned)HOT_BIT;
                 t.flags[slot] = (unsigned char)f;
             }
         }
@@ -457,36 +460,77 @@ __global__ __launch_bounds__(256) void k_plan(Tables t) {
                 for (int d = 0; d < 6; d++)
                     if (bm[d] > trig) f |= 1u << d;
                 if (bm[6] > ret || bm[7] > ret) f |= (unsigned)KEEP_BIT;
+                if (bm[6] > trig || bm[7] > trig) f |= (unsigned)HOT_BIT;
             } else {
                 f = t.flags[slot];
             }
             key_to_block(t.shots[shot], key, bx, by, bz);
             survive = (f & KEEP_BIT) != 0 || t.pin_until[slot] > n + 1;
         }
-        for (int d = 0; d < 6; d++) {
-            bool claim = false;
-            long long nk = -1;
-            if (valid) {
-                nk = neighbour_key(t.shots[shot], bx, by, bz, d);
-                if (nk >= 0) {
-                    const int s_nb = t.cell2box[nk];
-                    if (s_nb >= 0) {
-                        // an active neighbour whose face toward us is above trigger
-                        const bool face = t.adaptive ? t.bmax[8 * (size_t)s_nb + (d ^ 1)] > trig
-                                                     : ((t.flags[s_nb] >> (d ^ 1)) & 1u) != 0;
-                        if (face) survive = true;
-                    } else if (((f >> d) & 1u) && s_nb == EMPTY) {
-                        claim = atomicCAS(&t.cell2box[nk], EMPTY, CLAIMED) == EMPTY;
+        if (t.interval <= 1) {
+            for (int d = 0; d < 6; d++) {
+                bool claim = false;
+                long long nk = -1;
+                if (valid) {
+                    nk = neighbour_key(t.shots[shot], bx, by, bz, d);
+                    if (nk >= 0) {
+                        const int s_nb = t.cell2box[nk];
+                        if (s_nb >= 0) {
+                            // an active neighbour whose face toward us is above trigger
+                            const bool face = t.adaptive ? t.bmax[8 * (size_t)s_nb + (d ^ 1)] > trig
+                                                         : ((t.flags[s_nb] >> (d ^ 1)) & 1u) != 0;
+                            if (face) survive = true;
+                        } else if (((f >> d) & 1u) && s_nb == EMPTY) {
+                            claim = atomicCAS(&t.cell2box[nk], EMPTY, CLAIMED) == EMPTY;
+                        }
                     }
                 }
-            }
-            const int k = wave_append(&st->n_new, claim);
-            if (claim) {
-                if (k < t.cap) {
-                    t.new_key[k] = nk;
-                    t.new_shot[k] = shot;
+                const int k = wave_append(&st->n_new, claim);
+                if (claim) {
+                    if (k < t.cap) {
+                        t.new_key[k] = nk;
+                        t.new_shot[k] = shot;
+                    }
+                    atomicOr(&t.bitmap[nk >> 6], 1ull << (nk & 63));
                 }
-                atomicOr(&t.bitmap[nk >> 6], 1ull << (nk & 63));
+            }
+        } else {
+            // update every `interval` (<= 8) steps: values move at most one node
+            // per step, so a block that is hot (or still inserting a source)
+            // must have all 26 nearest and diagonal neighbours active
+            const bool hot = valid && (((f & HOT_BIT) != 0) || t.pin_until[slot] > n + 1);
+            for (int d = 0; d < 27; d++) {
+                if (d == 13) continue;
+                bool claim = false;
+                long long nk = -1;
+                if (valid) {
+                    const Shot& S = t.shots[shot];
+                    const int x2 = bx + d % 3 - 1, y2 = by + (d / 3) % 3 - 1, z2 = bz + d / 9 - 1;
+                    if (x2 >= 0 && y2 >= 0 && z2 >= 0 && x2 < S.bx && y2 < S.by && z2 < S.bz) {
+                        nk = S.key_base + (long long)block_to_key(S, x2, y2, z2);
+                        const int s_nb = t.cell2box[nk];
+                        if (s_nb >= 0) {
+                            bool nhot;
+                            if (t.adaptive) {
+                                const float* bm = t.bmax + 8 * (size_t)s_nb;
+                                nhot = bm[6] > trig || bm[7] > trig;
+                            } else {
+                                nhot = (t.flags[s_nb] & HOT_BIT) != 0;
+                            }
+                            if (nhot || t.pin_until[s_nb] > n + 1) survive = true;
+                        } else if (hot && s_nb == EMPTY) {
+                            claim = atomicCAS(&t.cell2box[nk], EMPTY, CLAIMED) == EMPTY;
+                        }
+                    }
+                }
+                const int k = wave_append(&st->n_new, claim);
+                if (claim) {
+                    if (k < t.cap) {
+                        t.new_key[k] = nk;
+                        t.new_shot[k] = shot;
+                    }
+                    atomicOr(&t.bitmap[nk >> 6], 1ull << (nk & 63));
+                }
             }
         }
         // shutdown process (eq.(6)): a block that no longer qualifies keeps
@@ -533,6 +577,36 @@ __global__ __launch_bounds__(256) void k_plan(Tables t) {
 
 hipError_t launch_plan(const Tables& t, int grid, hipStream_t s) {
     hipLaunchKernelGGL(k_plan, dim3(grid), dim3(256), 0, s, t);
+    return hipGetLastError();
+}
+
+// A step without an activation update (update interval > 1): record the
+// receivers of phi^{n+1}, then advance the step counter.  One workgroup.
+__global__ __launch_bounds__(256) void k_advance(Tables t) {
+    DevState* st = t.st;
+    if (st->error) return;
+    const int n = st->step;
+    const int p = n & 1;
+    const int row = n - t.trace_step0;
+    if (row >= 0 && row < t.trace_cap) {
+        for (int r = threadIdx.x; r < t.nrec; r += blockDim.x) {
+            const Rec e = t.rec[r];
+            const int s = t.cell2box[e.key];
+            t.traces[(size_t)row * t.nrec + r] =
+                s >= 0 ? t.pool[(size_t)s * SLOT + (1 - p) * BV + e.local] : 0.f;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        st->updates += st->cells_cur;
+        st->updates_u += st->cells_cur_u;
+        st->step = n + 1;
+        st->maxbits = 0u;
+    }
+}
+
+hipError_t launch_advance(const Tables& t, hipStream_t s) {
+    hipLaunchKernelGGL(k_advance, dim3(1), dim3(256), 0, s, t);
     return hipGetLastError();
 }
 

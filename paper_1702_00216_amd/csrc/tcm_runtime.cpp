@@ -60,6 +60,7 @@ struct tcm_handle {
     size_t table_bytes = 0;
 
     int grid_step = 0, grid_plan = 0, grid_pool = 0;
+    long long hstep = 0;                // index of the next step to enqueue
 
     // sources / receivers (host mirrors)
     std::vector<Src> h_src;
@@ -259,6 +260,12 @@ void destroy_all(tcm_handle* h) {
     delete h;
 }
 
+// graphs hold whole activation-update intervals
+int round_graph_steps(const tcm_handle* h, int gs) {
+    const int k = h->t.interval > 1 ? h->t.interval : 1;
+    return std::max(k, (gs + k - 1) / k * k);
+}
+
 // Device state of the engine (dense arrays or block tables) for the shots
 // already in h->shots / h->d_shots.
 tcm_status setup_engine(tcm_handle* h, long long word_base) {
@@ -364,7 +371,8 @@ tcm_status setup_engine(tcm_handle* h, long long word_base) {
     h->grid_step = std::max(8, (h->ncu * wpc) / 8 * 8);
     h->grid_plan = std::max(1, h->ncu * 2);
     h->grid_pool = std::min(POOL_COUNT_MAX_WG, std::max(64, std::min(t.nchunks, h->ncu)));
-    h->gsteps = cfg->graph_steps > 0 ? cfg->graph_steps : 16;
+    t.interval = cfg->trigger_interval > 1 ? cfg->trigger_interval : 1;
+    h->gsteps = round_graph_steps(h, cfg->graph_steps > 0 ? cfg->graph_steps : 16);
     return TCM_OK;
 }
 
@@ -387,6 +395,8 @@ tcm_status create_common(const tcm_config* cfg, const tcm_shot* shots, int nshot
     if (!(cfg->trigger_rel >= 0.f) || !(cfg->retire_rel >= 0.f) || !std::isfinite(cfg->trigger_rel) ||
         !std::isfinite(cfg->retire_rel) || cfg->retire_rel > cfg->trigger_rel)
         return set_err(nullptr, TCM_E_ARG, "relative levels must satisfy 0 <= retire_rel <= trigger_rel");
+    if (cfg->trigger_interval < 0 || cfg->trigger_interval > BE)
+        return set_err(nullptr, TCM_E_ARG, "trigger_interval must be in [0, 8] (0 and 1: every step)");
     if (cfg->engine == TCM_ENGINE_DENSE && nshots != 1)
         return set_err(nullptr, TCM_E_ARG, "the dense engine runs one shot");
 
@@ -458,11 +468,17 @@ tcm_status create_common(const tcm_config* cfg, const tcm_shot* shots, int nshot
 }
 
 // ---- per-step launch sequence ----------------------------------------------
+// Step h->hstep: the stencil, then the activation update when the step ends
+// an update interval ("Updating active cells", eq.(5)), else only the
+// receivers and the step counter.
 hipError_t enqueue_step(tcm_handle* h, hipEvent_t e0, hipEvent_t e1) {
     hipError_t e;
+    const long long n = h->hstep++;
+    const int k = h->t.interval > 1 ? h->t.interval : 1;
     if (e0 && (e = hipEventRecord(e0, h->stream)) != hipSuccess) return e;
     if ((e = launch_block_step(h->t, h->grid_step, h->stream)) != hipSuccess) return e;
     if (e1 && (e = hipEventRecord(e1, h->stream)) != hipSuccess) return e;
+    if ((n + 1) % k != 0) return launch_advance(h->t, h->stream);
     if ((e = launch_plan(h->t, h->grid_plan, h->stream)) != hipSuccess) return e;
     if ((e = launch_pool_count(h->t, h->grid_pool, h->stream)) != hipSuccess) return e;
     return launch_emit(h->t, h->stream);
@@ -584,13 +600,21 @@ void ck_clear(tcm_handle* h) {
 // Issue n steps (graph replays where possible); no synchronisation.
 tcm_status issue_steps(tcm_handle* h, int n) {
     int left = n;
+    const int kint = h->t.interval > 1 ? h->t.interval : 1;
+    // graphs hold whole update intervals: start them at an interval boundary
+    while (kint > 1 && left > 0 && h->hstep % kint != 0) {
+        HIP_OR_FAIL(h, enqueue_step(h, nullptr, nullptr));
+        left--;
+    }
     const bool use_graph = !(h->cfg.flags & TCM_FLAG_NO_GRAPH) && !h->graph_failed && h->own_stream;
     if (use_graph && left >= h->gsteps) {
         if (!h->gexec) {
             hipGraph_t g = nullptr;
+            const long long keep_step = h->hstep;
             bool ok = hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
             hipError_t le = hipSuccess;
             for (int k = 0; ok && k < h->gsteps && le == hipSuccess; k++) le = enqueue_step(h, nullptr, nullptr);
+            h->hstep = keep_step;          // capturing issues nothing
             if (ok) ok = hipStreamEndCapture(h->stream, &g) == hipSuccess && le == hipSuccess;
             if (ok) ok = hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0) == hipSuccess;
             if (g) (void)hipGraphDestroy(g);
@@ -603,6 +627,7 @@ tcm_status issue_steps(tcm_handle* h, int n) {
         while (h->gexec && left >= h->gsteps) {
             HIP_OR_FAIL(h, hipGraphLaunch(h->gexec, h->stream));
             left -= h->gsteps;
+            h->hstep += h->gsteps;
         }
     }
     for (; left > 0; left--) HIP_OR_FAIL(h, enqueue_step(h, nullptr, nullptr));
@@ -732,6 +757,17 @@ tcm_status tcm_add_source_shot(tcm_handle* h, int32_t shot, int32_t ix, int32_t 
     drop_graph(h);
     if (h->engine == TCM_ENGINE_BLOCKS) {
         HIP_OR_FAIL(h, launch_activate(h->t, e.key, shot, local_key, (int)(n + nsamples), h->stream));
+        if (h->t.interval > 1) {
+            // the source reaches the 26 blocks around it before the next update
+            const int bx = ix >> 3, by = iy >> 3, bz = iz >> 3;
+            for (int d = 0; d < 27; d++) {
+                const int x2 = bx + d % 3 - 1, y2 = by + (d / 3) % 3 - 1, z2 = bz + d / 9 - 1;
+                if (d == 13 || x2 < 0 || y2 < 0 || z2 < 0 || x2 >= S.bx || y2 >= S.by || z2 >= S.bz) continue;
+                const unsigned tile2 = ((unsigned)(z2 >> 2) * S.ty + (unsigned)(y2 >> 2)) * S.tx + (unsigned)(x2 >> 2);
+                const unsigned lk = tile2 * 64u + ((unsigned)(z2 & 3) << 4) + ((unsigned)(y2 & 3) << 2) + (unsigned)(x2 & 3);
+                HIP_OR_FAIL(h, launch_activate(h->t, S.key_base + lk, shot, lk, 0, h->stream));
+            }
+        }
         st = sync_state(h);
         if (st) return st;
         if (h->h_state->add_error) {
@@ -844,6 +880,7 @@ tcm_status tcm_step(tcm_handle* h, int32_t nsteps) {
     if (st) return st;
     const unsigned long long upd0 = h->h_state->updates + h->h_state->cells_cur;
     const unsigned long long updu0 = h->h_state->updates_u + h->h_state->cells_cur_u;
+    h->hstep = h->h_state->step;
 
     // one run of n steps: per-launch HIP events around the stencil, or graph replay
     auto run_chunk = [&](int n) -> tcm_status {
@@ -886,6 +923,7 @@ tcm_status tcm_step(tcm_handle* h, int32_t nsteps) {
             if (st) return st;
             if (h->h_state->error) break;
             cur = h->h_state->step;
+            h->hstep = cur;
             left -= chunk;
         }
     } else {
@@ -1041,6 +1079,7 @@ tcm_status tcm_reset(tcm_handle* h) {
     } else {
         HIP_OR_FAIL(h, launch_init_tables(h->t, h->nkeys, h->stream));
     }
+    h->hstep = 0;
     HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
     return TCM_OK;
 }
@@ -1093,6 +1132,7 @@ tcm_status tcm_adjoint(tcm_handle* h, const float* resid, int32_t nt, int32_t re
     tcm_handle* a = h->adj;
     st = tcm_reset(a);
     if (st) return set_err(h, st, std::string("adjoint tables: ") + a->err);
+    a->hstep = 0;
     {
         // adjoint step k (k = 0..nt-1) produces mu^{nt-k}; its source sample at
         // receiver r is C2_r * resid[nt-1-k][r]
@@ -1129,6 +1169,7 @@ tcm_status tcm_adjoint(tcm_handle* h, const float* resid, int32_t nt, int32_t re
         const int s0 = j * K, end = std::min(s0 + K, nt);
         st = ck_restore(h, h->ckpts[j].buf);
         if (st) { cleanup(); return st; }
+        h->hstep = s0;
         // forward levels s0 .. end-1 into lvl[0 .. end-1-s0]
         e = launch_read(h->t, 0, 0, 0, 0, 0, S.nx, S.ny, S.nz, lvl, h->stream);
         for (int l = 1; l < end - s0 && e == hipSuccess; l++) {
@@ -1194,12 +1235,15 @@ tcm_status tcm_autotune(tcm_handle* h, int32_t probe_steps, tcm_tuning* out) {
         for (int gs : gss) {
             if (res.ncand >= 32) break;
             h->grid_step = std::max(8, (h->ncu * wpc) / 8 * 8);
-            h->gsteps = gs;
+            h->gsteps = round_graph_steps(h, gs);
             drop_graph(h);
             // one untimed graph launch so capture/instantiation is not timed
+            const long long step0 = h->h_state->step;
             st = ck_restore(h, snap);
+            h->hstep = step0;
             if (!st) st = issue_steps(h, std::min(gs, probe_steps));
             if (!st) st = ck_restore(h, snap);
+            h->hstep = step0;
             if (st) break;
             HIP_OR_FAIL(h, hipEventRecord(e0, h->stream));
             st = issue_steps(h, probe_steps);
@@ -1210,15 +1254,15 @@ tcm_status tcm_autotune(tcm_handle* h, int32_t probe_steps, tcm_tuning* out) {
             HIP_OR_FAIL(h, hipEventElapsedTime(&ms, e0, e1));
             const double per = ms / probe_steps;
             res.cand_wg_per_cu[res.ncand] = wpc;
-            res.cand_graph_steps[res.ncand] = gs;
+            res.cand_graph_steps[res.ncand] = h->gsteps;
             res.cand_ms_per_step[res.ncand] = per;
             res.ncand++;
             if (per < res.ms_per_step) {
                 res.ms_per_step = per;
                 res.wg_per_cu = wpc;
-                res.graph_steps = gs;
+                res.graph_steps = h->gsteps;
                 best_grid = h->grid_step;
-                best_gs = gs;
+                best_gs = h->gsteps;
             }
         }
         if (st) break;
@@ -1251,7 +1295,7 @@ tcm_status tcm_set_launch(tcm_handle* h, int32_t wg_per_cu, int32_t graph_steps)
         return set_err(h, TCM_E_ARG, fmt("launch shape needs 1 <= wg_per_cu <= %d and graph_steps >= 1", occ));
     HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
     h->grid_step = std::max(8, (h->ncu * wg_per_cu) / 8 * 8);
-    h->gsteps = graph_steps;
+    h->gsteps = round_graph_steps(h, graph_steps);
     drop_graph(h);
     return TCM_OK;
 }

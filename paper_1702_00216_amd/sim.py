@@ -61,7 +61,8 @@ class Simulation:
                  timing: bool = False, graphs: bool = True, stream=None,
                  checkpoint_every: int = 0, graph_steps: int = 0, wg_per_cu: int = 0,
                  device_pool=None, uniform_c2: bool = True, shutdown_steps: int = 0,
-                 shutdown_alpha: float = 1.0, trigger_rel: float = 0.0, retire_rel: float = 0.0):
+                 shutdown_alpha: float = 1.0, trigger_rel: float = 0.0, retire_rel: float = 0.0,
+                 trigger_interval: int = 1):
         lib = L.lib()
         cfg = L.Config()
         cfg.dx, cfg.dt = float(dx), float(dt)
@@ -77,6 +78,7 @@ class Simulation:
         cfg.shutdown_alpha = float(shutdown_alpha)
         cfg.trigger_rel = float(trigger_rel)
         cfg.retire_rel = float(retire_rel)
+        cfg.trigger_interval = int(trigger_interval)
         self._pool_tensor = device_pool
         if device_pool is not None:
             cfg.device_pool = device_pool.data_ptr()

@@ -334,3 +334,43 @@ def test_adaptive_levels_match_cpu_tcm(rt, rr, n):
         assert g["cell_updates"] == o["updates"], k
     assert values_equal(sim.read(0), t.read(0))
     assert values_equal(sim.read(1), t.read(1))
+
+
+@pytest.mark.parametrize("k", [2, 5, 8])
+def test_update_interval_exact_at_tau0(k):
+    """Activation update every k steps with the 26-block lookahead: threshold
+    0 stays equal to the dense grid, through graph replays and direct steps."""
+    announce(f"update interval {k} at tau=0")
+    shape = (37, 29, 21)
+    c = ti.random_media(shape, seed=7, cmin=0.3, cmax=1.0)
+    dt = 0.55
+    srcs = [((16, 8, 8), ti.ricker(0.12, dt).w32), ((36, 0, 20), -0.5 * ti.ricker(0.2, dt).w32)]
+    phi, prev, tr = oracle.dense_run(c, dt, 1.0, 97, np.float32, sources=srcs, receivers=[(3, 4, 5)])
+    sim = gpu_run(shape, dt, c, srcs, 0, trigger_interval=k, graph_steps=8, receivers=[(3, 4, 5)])
+    for chunk in (13, 40, 44):
+        sim.step(chunk)
+    assert values_equal(sim.read(0), phi) and values_equal(sim.read(1), prev)
+    assert values_equal(sim.read_traces(), tr)
+
+
+@pytest.mark.parametrize("k,rel,n", [(8, False, 0), (4, True, 0), (8, False, 5)])
+def test_update_interval_matches_cpu_tcm(k, rel, n):
+    announce(f"update interval {k} vs CPU TCM (adaptive {rel}, shutdown {n})")
+    shape = (72, 64, 56)
+    c = ti.random_media(shape, seed=9, cmin=0.8, cmax=1.0)
+    w = ti.ricker(0.12, 0.5).w32
+    kw = dict(trigger_rel=np.float32(1e-3), retire_rel=np.float32(1e-4)) if rel else {}
+    trig, ret = (0.0, 0.0) if rel else (np.float32(3e-3), np.float32(1e-3))
+    t = oracle.TCM(c, 0.5, 1.0, trig, ret, interval=k, shutdown_steps=n,
+                   shutdown_alpha=np.float32(0.6), **kw)
+    t.add_source((36, 32, 28), w)
+    sim = gpu_run(shape, 0.5, c, [((36, 32, 28), w)], 0, trig, ret, trigger_interval=k,
+                  shutdown_steps=n, shutdown_alpha=0.6, **kw)
+    for step in (3, 17, 40, 40, 40):
+        assert t.step(step) == 0
+        sim.step(step)
+        o, g = t.stats(), sim.stats()
+        assert g["active_blocks"] == o["active"]
+        assert g["activations"] == o["activations"] and g["retirements"] == o["retirements"]
+        assert g["cell_updates"] == o["updates"]
+    assert values_equal(sim.read(0), t.read(0)) and values_equal(sim.read(1), t.read(1))

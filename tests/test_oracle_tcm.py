@@ -245,3 +245,28 @@ def test_adaptive_levels_follow_domain_maximum():
     zero.add_source(w.source, w.wavelet.w32)
     zero.step(80)
     assert values_equal(zero.read(0), fixed.read(0))
+
+
+@pytest.mark.parametrize("k", [2, 5, 8])
+def test_update_interval_with_diagonal_lookahead_is_exact_at_tau0(k):
+    """Activation every k <= 8 steps with the 26-cell neighbourhood keeps the
+    threshold-0 TCM equal to the dense grid (values move one node per step);
+    eq.(5) with a cell length of 8 nodes gives k = 8 at Courant 0.5."""
+    assert oracle.update_interval(1.0, 8.0, 1.0, 0.5) == 8.0
+    shape = (37, 29, 21)
+    c = ti.random_media(shape, seed=7, cmin=0.3, cmax=1.0)
+    dt = 0.55
+    srcs = [((16, 8, 8), ti.ricker(0.12, dt).w32), ((36, 0, 20), -0.5 * ti.ricker(0.2, dt).w32)]
+    phi, prev, _ = _run_dense(c, dt, 97, srcs, np.float32)
+    t = oracle.TCM(c, dt, 1.0, 0.0, 0.0, interval=k)
+    for xyz, w in srcs:
+        t.add_source(xyz, w)
+    for chunk in (13, 40, 44):
+        assert t.step(chunk) == 0 and t.check() == 0
+    assert values_equal(t.read(0), phi) and values_equal(t.read(1), prev)
+
+
+def test_update_interval_rejects_more_than_a_cell():
+    w = ti.c1()
+    with pytest.raises(ValueError):
+        oracle.TCM(w.c_dense, w.dt, 1.0, interval=9)
