@@ -129,6 +129,7 @@ hipError_t launch_pool_count(const Tables& t, int grid, hipStream_t s);   // gri
 hipError_t launch_emit(const Tables& t, hipStream_t s);
 hipError_t launch_activate(const Tables& t, long long key, int shot, unsigned local_key,
                            int pin_until, hipStream_t s);
+hipError_t launch_refresh_rows(const Tables& t, hipStream_t s);
 hipError_t launch_read(const Tables& t, int shot, int which, int x0, int y0, int z0, int sx,
                        int sy, int sz, float* out, hipStream_t s);
 hipError_t launch_media_c2(const Shot& shot, const Shot* dshot, double dt, double dx, float* c2,

@@ -893,6 +893,32 @@ __global__ __launch_bounds__(64) void k_activate(Tables t, long long G, int shot
     }
 }
 
+// Rewrite the neighbour row of every active entry from the block table
+// (after blocks were activated outside the step sequence).
+__global__ void k_refresh_rows(Tables t) {
+    const int nact = t.st->n_act;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nact; i += gridDim.x * blockDim.x) {
+        const int shot = t.act_shot[i];
+        const unsigned key = t.act_key[i];
+        const Shot& S = t.shots[shot];
+        int bx, by, bz;
+        key_to_block(S, key, bx, by, bz);
+        int nb[6];
+        for (int d = 0; d < 6; d++) {
+            const long long nk = neighbour_key(S, bx, by, bz, d);
+            nb[d] = nk >= 0 ? t.cell2box[nk] : EMPTY;
+        }
+        int4* rp = (int4*)(t.rows + 8 * (size_t)i);
+        rp[0] = make_int4(t.act_slot[i], nb[0], nb[1], nb[2]);
+        rp[1] = make_int4(nb[3], nb[4], nb[5], (int)(S.key_base + (long long)key));
+    }
+}
+
+hipError_t launch_refresh_rows(const Tables& t, hipStream_t s) {
+    hipLaunchKernelGGL(k_refresh_rows, dim3(256), dim3(256), 0, s, t);
+    return hipGetLastError();
+}
+
 hipError_t launch_activate(const Tables& t, long long key, int shot, unsigned local_key, int pin,
                            hipStream_t s) {
     hipLaunchKernelGGL(k_activate, dim3(1), dim3(64), 0, s, t, key, shot, local_key, pin);

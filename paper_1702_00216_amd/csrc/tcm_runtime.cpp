@@ -768,6 +768,8 @@ tcm_status tcm_add_source_shot(tcm_handle* h, int32_t shot, int32_t ix, int32_t 
                 HIP_OR_FAIL(h, launch_activate(h->t, S.key_base + lk, shot, lk, 0, h->stream));
             }
         }
+        // rows written before later activations name those blocks EMPTY
+        HIP_OR_FAIL(h, launch_refresh_rows(h->t, h->stream));
         st = sync_state(h);
         if (st) return st;
         if (h->h_state->add_error) {
