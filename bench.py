@@ -274,6 +274,12 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-uniform-c2", action="store_true",
                     help="read the per-node C2 plane for every block")
+    ap.add_argument("--interval", type=int, default=1, help="activation update every k steps (1..8)")
+    ap.add_argument("--shutdown-steps", type=int, default=0)
+    ap.add_argument("--shutdown-alpha", type=float, default=1.0)
+    ap.add_argument("--trigger", type=float, default=None, help="trigger, relative to the source peak")
+    ap.add_argument("--retire", type=float, default=None, help="retire level, relative to the source peak")
+    ap.add_argument("--no-equal-error", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device-to-device torch copy (counter calibration)")
     args = ap.parse_args()
@@ -292,12 +298,17 @@ def main():
     if args.workload == "c4":
         return bench_c4(args, tcm)
     w = workload(args.workload)
+    if args.trigger is not None:
+        w.trigger = args.trigger * w.wavelet.peak
+    if args.retire is not None:
+        w.retire = args.retire * w.wavelet.peak
     steps = args.time_steps or w.steps
     nx, ny, nz = w.shape
     log(f"workload {w.name} {w.shape} x {steps} steps, trigger {w.trigger:.3g} retire {w.retire:.3g}")
+    opts = dict(uniform_c2=not args.no_uniform_c2, trigger_interval=args.interval,
+                shutdown_steps=args.shutdown_steps, shutdown_alpha=args.shutdown_alpha)
     sim = tcm.Simulation(w.shape, w.dx, w.dt, media_of(w), w.trigger, w.retire,
-                         timing=not args.graphs, wg_per_cu=args.wg_per_cu,
-                         uniform_c2=not args.no_uniform_c2)
+                         timing=not args.graphs, wg_per_cu=args.wg_per_cu, **opts)
     for i in range(args.warmup):
         el, st = run_once(sim, w, steps)
         log(f"warmup {i}: {el:.3f} s, {st['cell_updates']:.3e} updates")
@@ -370,6 +381,26 @@ def main():
                      "tcm_fp32_at_workload_thresholds": g.get("tcm", {}).get("err"),
                      "tcm_sweep": g.get("sweep")}
 
+    # equal error: the TCM at the largest swept trigger (retire = trigger / 10)
+    # whose FP64-relative error is within twice the dense FP32 error
+    eq = None
+    if err_table and err_table.get("tcm_sweep") and not args.no_equal_error and dense:
+        lim = 2.0 * err_table["dense_fp32"]
+        ok = [(float(k), v) for k, v in err_table["tcm_sweep"].items() if v["err"] <= lim]
+        if ok:
+            rel, rec = max(ok, key=lambda kv: kv[0])
+            esim = tcm.Simulation(w.shape, w.dx, w.dt, media_of(w), rel * w.wavelet.peak,
+                                  rel * w.wavelet.peak / 10, timing=True)
+            run_once(esim, w, steps)
+            el, est = run_once(esim, w, steps)
+            esim.close()
+            eq = {"trigger_rel": rel, "retire_rel": rel / 10, "err_tcm": rec["err"],
+                  "err_dense_fp32": err_table["dense_fp32"], "run_s": round(el, 4),
+                  "updates": est["cell_updates"], "updates_per_s": est["cell_updates"] / el,
+                  "speedup_vs_dense": round(dense["run_s"] / el, 3),
+                  "same_work_as_oracle": est["cell_updates"] == rec["updates"]}
+            log(f"equal error (trigger {rel:g}): {el:.3f} s, {dense['run_s'] / el:.2f}x dense")
+
     cpu = None
     if not args.no_cpu:
         log(f"CPU oracle baseline (~{args.cpu_budget:.0f} s)")
@@ -395,6 +426,9 @@ def main():
                 "us_per_time_step": round(tot_t / args.steps / steps * 1e6, 2)},
         "dense_fdtd": dense,
         "equal_error": err_table,
+        "equal_error_run": eq,
+        "options": {"interval": args.interval, "shutdown": [args.shutdown_steps, args.shutdown_alpha],
+                    "uniform_c2": not args.no_uniform_c2},
         "copy_calibration": copy,
     }
     print(json.dumps(out), flush=True)

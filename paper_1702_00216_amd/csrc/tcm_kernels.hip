@@ -265,14 +265,16 @@ __global__ __launch_bounds__(256) void k_block_step(Tables t) {
 #pragma unroll
         for (int z = 0; z < 8; z++) {
             cur[z] = cur_p[z * 64 + lane];
-            prv[z] = out_p[z * 64 + lane];
+            // phi^{n-1} and C2 are read once per step: stream them past L2 so
+            // that it keeps the phi^n lines the neighbours' faces re-read
+            prv[z] = __builtin_nontemporal_load(&out_p[z * 64 + lane]);
         }
         if (c2u == c2u) {            // uniform block: one coefficient, no C2 plane read
 #pragma unroll
             for (int z = 0; z < 8; z++) k2[z] = c2u;
         } else {
 #pragma unroll
-            for (int z = 0; z < 8; z++) k2[z] = c2_p[z * 64 + lane];
+            for (int z = 0; z < 8; z++) k2[z] = __builtin_nontemporal_load(&c2_p[z * 64 + lane]);
         }
         float zlo = 0.f, zhi = 0.f, fmx = 0.f, fpx = 0.f, fmy = 0.f, fpy = 0.f;
         if (nb[4] >= 0) zlo = t.pool[(size_t)nb[4] * SLOT + p * BV + 7 * 64 + lane];
@@ -338,7 +340,7 @@ __global__ __launch_bounds__(256) void k_block_step(Tables t) {
             }
         }
 #pragma unroll
-        for (int z = 0; z < 8; z++) out_p[z * 64 + lane] = nv[z];
+        for (int z = 0; z < 8; z++) __builtin_nontemporal_store(nv[z], &out_p[z * 64 + lane]);
 
         if constexpr (ADAPT) {
             // per-block maxima (Table 1 Max_cell_val, per face and whole block);
