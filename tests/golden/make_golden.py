@@ -4,6 +4,7 @@ Calls only the CPU oracle (oracle/) and the input generators (tcm_inputs/).
 Usage:  python tests/golden/make_golden.py c2 [--sweep]
         python tests/golden/make_golden.py c5
         python tests/golden/make_golden.py c4
+        python tests/golden/make_golden.py c2k8
 
 c2: the 512^3 two-layer workload, 2000 steps.  Stores
   * the relative L2 error at the last step against the FP64 dense oracle of
@@ -163,6 +164,35 @@ def make_c5():
         log(f"fd ({x},{y},{z}): fd {fd:.6e} adjoint {g[z, y, x]:.6e}")
 
 
+def make_c2k8():
+    """The 512^3 two-layer workload with the activation update every 8 steps
+    (eq.(5) with 8-node cells at Courant 0.5) and the 26-cell lookahead:
+    error against FP64 dense, final-field hashes and statistics of the CPU TCM,
+    at the workload thresholds and at trigger 1e-9 / retire 1e-10 of the peak."""
+    w = ti.c2()
+    c = w.layered.dense(*w.shape)
+    out_path = os.path.join(HERE, "c2k8_golden.json")
+    res = {"interval": 8, "workload": {"shape": w.shape, "steps": w.steps}}
+    t0 = time.time()
+    ref, _, _ = oracle.dense_run(c.astype(np.float64), w.dt, w.dx, w.steps, np.float64,
+                                 sources=[(w.source, w.wavelet.w32.astype(np.float64))])
+    log(f"FP64 dense done in {time.time() - t0:.0f} s")
+    for name, trig, ret in (("workload", w.trigger, w.retire),
+                            ("1e-09", 1e-9 * w.wavelet.peak, 1e-10 * w.wavelet.peak)):
+        t0 = time.time()
+        t = oracle.TCM(c, w.dt, w.dx, np.float32(trig), np.float32(ret), interval=8)
+        t.add_source(w.source, w.wavelet.w32)
+        assert t.step(w.steps) == 0
+        phi, prev = t.read(0), t.read(1)
+        st = t.stats()
+        t.close()
+        res[name] = {"trigger": float(np.float32(trig)), "retire": float(np.float32(ret)),
+                     "err": relerr(phi, ref), "phi_sha256": digest(phi), "prev_sha256": digest(prev),
+                     "stats": st}
+        json.dump(res, open(out_path, "w"))
+        log(f"c2k8 {name}: err {res[name]['err']:.3e} updates {st['updates']:.3e} ({time.time() - t0:.0f} s)")
+
+
 def make_c4():
     """Shots 0-3 of the 64-shot workload at threshold 0: SHA-256 of the FP32
     dense oracle's final phi^n (equal to the TCM at threshold 0)."""
@@ -186,5 +216,7 @@ if __name__ == "__main__":
         make_c5()
     elif which == "c4":
         make_c4()
+    elif which == "c2k8":
+        make_c2k8()
     else:
         raise SystemExit(f"unknown workload {which}")
