@@ -312,6 +312,16 @@ def main():
     for i in range(args.warmup):
         el, st = run_once(sim, w, steps)
         log(f"warmup {i}: {el:.3f} s, {st['cell_updates']:.3e} updates")
+    tuning = None
+    if not args.no_autotune and not args.wg_per_cu:
+        # pick the launch shape on the mid-run active set, then time from step 0
+        sim.reset()
+        sim.add_source(w.source, w.wavelet.w32)
+        sim.step(steps // 2)
+        tuning = sim.autotune(probe_steps=32, cache=os.environ.get("TCM_TUNE_CACHE"),
+                              key=f"gfx950/{w.name}/k{args.interval}")
+        tuning.pop("candidates", None)
+        log(f"autotune: wg_per_cu {tuning['wg_per_cu']} graph_steps {tuning['graph_steps']}")
     tot_t, tot_u, st_ms, st_cells, st_launch, st_cells_u = 0.0, 0, 0.0, 0, 0, 0
     for i in range(args.steps):
         el, st = run_once(sim, w, steps)
@@ -415,7 +425,8 @@ def main():
         "config": {"workload": f"{w.name}: {nx}x{ny}x{nz} two-layer (1500/3000 m/s), Ricker 100 Hz at "
                                f"{w.source}, {steps} leapfrog steps, trigger 1e-6 / retire 1e-7 of peak, "
                                f"8^3 blocks", "time_steps_per_run": steps,
-                   "launch": "per-step launches with HIP events" if not args.graphs else "hipGraph replay"},
+                   "launch": "hipGraph replay" + (" with HIP events around every stencil launch"
+                                                  if not args.graphs else "")},
         "roofline": roof,
         "cpu_baseline": cpu,
         "tcm": {"peak_active_blocks": last["peak_active_blocks"],
@@ -428,7 +439,7 @@ def main():
         "equal_error": err_table,
         "equal_error_run": eq,
         "options": {"interval": args.interval, "shutdown": [args.shutdown_steps, args.shutdown_alpha],
-                    "uniform_c2": not args.no_uniform_c2},
+                    "uniform_c2": not args.no_uniform_c2, "autotune": tuning},
         "copy_calibration": copy,
     }
     print(json.dumps(out), flush=True)
