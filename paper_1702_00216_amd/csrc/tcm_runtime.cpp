@@ -73,10 +73,8 @@ struct tcm_handle {
     Rec* d_rec = nullptr;
     float* d_traces = nullptr;
 
-    // graph replay (gexec_t: the same steps with HIP events around each stencil launch)
+    // graph replay
     hipGraphExec_t gexec = nullptr;
-    hipGraphExec_t gexec_t = nullptr;
-    std::vector<hipEvent_t> gevents;
     int gsteps = 0;
     bool graph_failed = false;
 
@@ -156,10 +154,6 @@ void drop_graph(tcm_handle* h) {
     if (h->gexec) {
         (void)hipGraphExecDestroy(h->gexec);
         h->gexec = nullptr;
-    }
-    if (h->gexec_t) {
-        (void)hipGraphExecDestroy(h->gexec_t);
-        h->gexec_t = nullptr;
     }
 }
 
@@ -259,8 +253,6 @@ void destroy_all(tcm_handle* h) {
     drop_graph(h);
     for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
     h->events.clear();
-    for (hipEvent_t e : h->gevents) (void)hipEventDestroy(e);
-    h->gevents.clear();
     for (void* p : h->allocs) (void)hipFree(p);
     h->allocs.clear();
     if (h->h_state) (void)hipHostFree(h->h_state);
@@ -642,73 +634,25 @@ tcm_status issue_steps(tcm_handle* h, int n) {
     return TCM_OK;
 }
 
-// Issue n steps with HIP events around every stencil launch and add their
-// times to the statistics; graph replays carry the event records, and each
-// replay's events are read before the next replay re-records them.
+// Issue n steps directly, with HIP events around every stencil launch, and add
+// their times to the statistics.  (Event records captured into a graph
+// cannot be timed, so timed runs do not replay graphs.)
 tcm_status issue_steps_timed(tcm_handle* h, int n) {
-    int left = n;
-    auto direct = [&](int m) -> tcm_status {
-        while ((int)h->events.size() < 2 * m) {
-            hipEvent_t e;
-            HIP_OR_FAIL(h, hipEventCreate(&e));
-            h->events.push_back(e);
-        }
-        for (int k = 0; k < m; k++)
-            HIP_OR_FAIL(h, enqueue_step(h, h->events[2 * k], h->events[2 * k + 1]));
-        HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
-        for (int k = 0; k < m; k++) {
-            float ms = 0.f;
-            HIP_OR_FAIL(h, hipEventElapsedTime(&ms, h->events[2 * k], h->events[2 * k + 1]));
-            h->stencil_ms += ms;
-        }
-        h->stencil_launches += m;
-        return TCM_OK;
-    };
-    const int kint = h->t.interval > 1 ? h->t.interval : 1;
-    if (kint > 1 && h->hstep % kint != 0) {
-        const int m = (int)std::min<long long>(left, kint - h->hstep % kint);
-        tcm_status st = direct(m);
-        if (st) return st;
-        left -= m;
+    while ((int)h->events.size() < 2 * n) {
+        hipEvent_t e;
+        HIP_OR_FAIL(h, hipEventCreate(&e));
+        h->events.push_back(e);
     }
-    const bool use_graph = !(h->cfg.flags & TCM_FLAG_NO_GRAPH) && !h->graph_failed && h->own_stream;
-    if (use_graph && left >= h->gsteps) {
-        if (!h->gexec_t) {
-            while ((int)h->gevents.size() < 2 * h->gsteps) {
-                hipEvent_t e;
-                HIP_OR_FAIL(h, hipEventCreate(&e));
-                h->gevents.push_back(e);
-            }
-            hipGraph_t g = nullptr;
-            const long long keep_step = h->hstep;
-            bool ok = hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
-            hipError_t le = hipSuccess;
-            for (int k = 0; ok && k < h->gsteps && le == hipSuccess; k++)
-                le = enqueue_step(h, h->gevents[2 * k], h->gevents[2 * k + 1]);
-            h->hstep = keep_step;
-            if (ok) ok = hipStreamEndCapture(h->stream, &g) == hipSuccess && le == hipSuccess;
-            if (ok) ok = hipGraphInstantiate(&h->gexec_t, g, nullptr, nullptr, 0) == hipSuccess;
-            if (g) (void)hipGraphDestroy(g);
-            if (!ok) {
-                (void)hipGetLastError();
-                h->gexec_t = nullptr;
-                h->graph_failed = true;
-            }
-        }
-        while (h->gexec_t && left >= h->gsteps) {
-            HIP_OR_FAIL(h, hipGraphLaunch(h->gexec_t, h->stream));
-            HIP_OR_FAIL(h, hipEventSynchronize(h->gevents[2 * h->gsteps - 1]));
-            for (int k = 0; k < h->gsteps; k++) {
-                float ms = 0.f;
-                HIP_OR_FAIL(h, hipEventElapsedTime(&ms, h->gevents[2 * k], h->gevents[2 * k + 1]));
-                h->stencil_ms += ms;
-            }
-            h->stencil_launches += h->gsteps;
-            left -= h->gsteps;
-            h->hstep += h->gsteps;
-        }
+    for (int k = 0; k < n; k++)
+        HIP_OR_FAIL(h, enqueue_step(h, h->events[2 * k], h->events[2 * k + 1]));
+    HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+    for (int k = 0; k < n; k++) {
+        float ms = 0.f;
+        HIP_OR_FAIL(h, hipEventElapsedTime(&ms, h->events[2 * k], h->events[2 * k + 1]));
+        h->stencil_ms += ms;
     }
-    return left > 0 ? direct(left) : TCM_OK;
+    h->stencil_launches += n;
+    return TCM_OK;
 }
 
 // Tables for the adjoint field: same shots and media (shared), own pool.
@@ -961,8 +905,8 @@ tcm_status tcm_step(tcm_handle* h, int32_t nsteps) {
     const unsigned long long updu0 = h->h_state->updates_u + h->h_state->cells_cur_u;
     h->hstep = h->h_state->step;
 
-    // one run of n steps: graph replay, with HIP events around every stencil
-    // launch when timing
+    // one run of n steps: graph replay, or direct launches with HIP events
+    // around every stencil launch when timing
     auto run_chunk = [&](int n) -> tcm_status {
         return timing ? issue_steps_timed(h, n) : issue_steps(h, n);
     };
