@@ -280,6 +280,8 @@ def main():
     ap.add_argument("--trigger", type=float, default=None, help="trigger, relative to the source peak")
     ap.add_argument("--retire", type=float, default=None, help="retire level, relative to the source peak")
     ap.add_argument("--no-equal-error", action="store_true")
+    ap.add_argument("--no-graph-replay", action="store_true",
+                    help="skip the hipGraph replay run (counter-collection runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device-to-device torch copy (counter calibration)")
     args = ap.parse_args()
@@ -337,7 +339,7 @@ def main():
     last = st
     sim.close()
     graph_run = None
-    if not args.graphs:
+    if not args.graphs and not args.no_graph_replay:
         # the same runs replayed as hipGraphs (no per-launch events)
         gsim = tcm.Simulation(w.shape, w.dx, w.dt, media_of(w), w.trigger, w.retire,
                               timing=False, wg_per_cu=(tuning or {}).get("wg_per_cu", args.wg_per_cu),
@@ -434,7 +436,8 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"{w.name}: {nx}x{ny}x{nz} two-layer (1500/3000 m/s), Ricker 100 Hz at "
-                               f"{w.source}, {steps} leapfrog steps, trigger 1e-6 / retire 1e-7 of peak, "
+                               f"{w.source}, {steps} leapfrog steps, trigger {w.trigger / w.wavelet.peak:g} / "
+                               f"retire {w.retire / w.wavelet.peak:g} of peak, "
                                f"8^3 blocks", "time_steps_per_run": steps,
                    "launch": "per-step launches with HIP events around every stencil launch"
                              if not args.graphs else "hipGraph replay"},

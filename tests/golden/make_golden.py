@@ -5,6 +5,7 @@ Usage:  python tests/golden/make_golden.py c2 [--sweep]
         python tests/golden/make_golden.py c5
         python tests/golden/make_golden.py c4
         python tests/golden/make_golden.py c2k8
+        python tests/golden/make_golden.py c5resid
 
 c2: the 512^3 two-layer workload, 2000 steps.  Stores
   * the relative L2 error at the last step against the FP64 dense oracle of
@@ -164,6 +165,25 @@ def make_c5():
         log(f"fd ({x},{y},{z}): fd {fd:.6e} adjoint {g[z, y, x]:.6e}")
 
 
+def make_c5resid():
+    """The residual (FP64 traces of the model minus FP64 traces of the +2 %
+    anomaly model) that the stored c5 adjoint gradient was computed with,
+    rounded to FP32 (c5_resid.npy), so the GPU adjoint can be fed the same
+    input."""
+    w = ti.c5()
+    c = ti.lattice_to_dense(w.lattice, w.shape).astype(np.float64)
+    c_true = ti.lattice_to_dense(ti.c5_true_lattice(w.lattice), w.shape).astype(np.float64)
+    src = [(w.source, w.wavelet.w32.astype(np.float64))]
+    d_obs = oracle.dense_run(c_true, w.dt, w.dx, w.steps, np.float64, sources=src, receivers=w.receivers)[2]
+    tr = oracle.dense_run(c, w.dt, w.dx, w.steps, np.float64, sources=src, receivers=w.receivers)[2]
+    resid = tr - d_obs
+    J = 0.5 * float(np.sum(resid ** 2))
+    g = json.load(open(os.path.join(HERE, "c5_golden.json")))
+    assert abs(J - g["J"]) <= 1e-12 * abs(g["J"]), (J, g["J"])
+    np.save(os.path.join(HERE, "c5_resid.npy"), resid.astype(np.float32))
+    log(f"c5 resid saved, J = {J:.6e}")
+
+
 def make_c2k8():
     """The 512^3 two-layer workload with the activation update every 8 steps
     (eq.(5) with 8-node cells at Courant 0.5) and the 26-cell lookahead:
@@ -218,5 +238,7 @@ if __name__ == "__main__":
         make_c4()
     elif which == "c2k8":
         make_c2k8()
+    elif which == "c5resid":
+        make_c5resid()
     else:
         raise SystemExit(f"unknown workload {which}")
