@@ -280,6 +280,8 @@ def main():
     ap.add_argument("--trigger", type=float, default=None, help="trigger, relative to the source peak")
     ap.add_argument("--retire", type=float, default=None, help="retire level, relative to the source peak")
     ap.add_argument("--no-equal-error", action="store_true")
+    ap.add_argument("--no-interval8", action="store_true",
+                    help="skip the runs with the activation update every 8 steps")
     ap.add_argument("--no-graph-replay", action="store_true",
                     help="skip the hipGraph replay run (counter-collection runs)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -424,6 +426,34 @@ def main():
                   "same_work_as_oracle": est["cell_updates"] == rec["updates"]}
             log(f"equal error (trigger {rel:g}): {el:.3f} s, {dense['run_s'] / el:.2f}x dense")
 
+    # the paper's activation update every n steps (eq.(5): n = 8 for 8-node
+    # blocks at Courant 0.5) with the 26-neighbour lookahead, at the workload
+    # thresholds and at the equal-error trigger; errors from the CPU TCM
+    k8 = None
+    p8 = os.path.join(ROOT, "tests", "golden", f"{w.name}k8_golden.json")
+    if args.interval == 1 and not args.no_interval8 and os.path.exists(p8) and not args.time_steps:
+        with open(p8) as f:
+            g8 = json.load(f)
+        k8 = {"interval": g8["interval"]}
+        for name in ("workload", "1e-09"):
+            o = g8[name]
+            ksim = tcm.Simulation(w.shape, w.dx, w.dt, media_of(w), o["trigger"], o["retire"],
+                                  timing=True, trigger_interval=g8["interval"],
+                                  wg_per_cu=(tuning or {}).get("wg_per_cu", args.wg_per_cu))
+            run_once(ksim, w, steps)
+            el, kst = run_once(ksim, w, steps)
+            ksim.close()
+            rec = {"trigger_rel": round(o["trigger"] / w.wavelet.peak, 12),
+                   "retire_rel": round(o["retire"] / w.wavelet.peak, 12), "run_s": round(el, 4),
+                   "updates": kst["cell_updates"], "updates_per_s": kst["cell_updates"] / el,
+                   "err": o["err"], "same_work_as_oracle": kst["cell_updates"] == o["stats"]["updates"]}
+            if dense:
+                rec["speedup_vs_dense"] = round(dense["run_s"] / el, 3)
+                if err_table:
+                    rec["within_equal_error"] = o["err"] <= 2.0 * err_table["dense_fp32"]
+            k8[name] = rec
+            log(f"interval 8 ({name}): {el:.3f} s, {kst['cell_updates']:.3e} updates, err {o['err']:.3e}")
+
     cpu = None
     if not args.no_cpu:
         log(f"CPU oracle baseline (~{args.cpu_budget:.0f} s)")
@@ -453,6 +483,7 @@ def main():
         "equal_error": err_table,
         "equal_error_run": eq,
         "graph_replay": graph_run,
+        "interval8": k8,
         "options": {"interval": args.interval, "shutdown": [args.shutdown_steps, args.shutdown_alpha],
                     "uniform_c2": not args.no_uniform_c2, "autotune": tuning},
         "copy_calibration": copy,

@@ -73,9 +73,11 @@ typedef struct {
     double   dx, dt;          /* node spacing (dx = dy = dz) and time step */
     float    trigger;         /* activation level on |phi^{n+1}| at a block face, >= 0 */
     float    retire;          /* keep level on |phi| inside a block, 0 <= retire <= trigger */
-    uint64_t pool_bytes;      /* pool cap in bytes (6 KiB per slot); 0: one slot per block,
+    uint64_t pool_bytes;      /* pool cap in bytes (6 KiB per slot); 0: one slot per block
+                                 key (the blocks of the domain, padded to whole 4x4x4 tiles),
                                  limited to 90 % of free device memory */
-    void*    device_pool;     /* optional caller device memory of >= pool_bytes; NULL: own */
+    void*    device_pool;     /* optional caller device memory of >= pool_bytes (then
+                                 pool_bytes is required, TCM_E_ARG otherwise); NULL: own */
     void*    stream;          /* hipStream_t to issue work on; NULL: a stream of the handle */
     int32_t  engine;          /* TCM_ENGINE_BLOCKS (the TCM) or TCM_ENGINE_DENSE (every node) */
     int32_t  flags;           /* TCM_FLAG_* */

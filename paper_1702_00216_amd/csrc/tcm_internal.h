@@ -40,12 +40,12 @@ struct Shot {
     const double* lattice;
 };
 
-// Device-side counters.  step/n_act/free_top describe the state between
+// Device-side counters.  step/n_act/free_cnt describe the state between
 // steps; n_new/n_ret are per-step scratch; emit tells the list writer
 // whether the step committed.
 struct DevState {
     int step, n_act, n_new, n_ret;
-    int free_top, error, err_step, emit;
+    int free_cnt, error, err_step, emit;
     int peak_act, done_wgs, add_error, n_dec;
     unsigned long long cells_cur;    // in-domain nodes of the current active list
     unsigned long long updates;      // in-domain nodes stepped so far
@@ -96,13 +96,13 @@ struct Tables {
     float trigger_rel, retire_rel;
     float* bmax;                    // adaptive: per slot 6 face maxima, max |phi^{n+1}|, max |phi^n|
     int uniform_c2;                 // 1: blocks with a uniform C2 read it as a scalar
-    long long* slot_key;            // per slot: global key or -1
-    int* free_stack;                // free slots, top in DevState::free_top
+    long long* slot_key;            // per slot: global key, or -1 when the slot is free
     long long* new_key;             // per step: claimed keys
     int* new_shot;
-    int* ret_slot;                  // per step: released slots
-    unsigned* partial;              // per 64-word chunk of the bitmap: set bits, then offsets
-    int nchunks;                    // ceil(nwords / 64)
+    int* ret_slot;                  // per step: released slots ...
+    long long* ret_key;             //   ... and the global keys they held
+    unsigned* partial;              // per 16-word chunk of the bitmap: set bits, then offsets
+    int nchunks;                    // ceil(nwords / 16)
     const Src* src;
     int nsrc;
     const float* srcw;
@@ -114,8 +114,9 @@ struct Tables {
     float trigger, retire;
 };
 
-// The compaction works on chunks of 64 bitmap words (4096 blocks).
-constexpr int CHUNK_WORDS = 64;
+// The compaction works on chunks of 16 bitmap words (1024 blocks), one
+// workgroup per chunk.
+constexpr int CHUNK_WORDS = 16;
 // Upper bound on the workgroups of k_pool_count (it counts chunks in a loop).
 constexpr int POOL_COUNT_MAX_WG = 1024;
 

@@ -10,10 +10,11 @@
 //   k_plan        keep / release each active block, claim empty face neighbours
 //                 with a compare-and-swap on the block table, mark the next
 //                 active set in a bitmap; receivers are recorded here.
-//   k_pool_count  lock-free slot allocator (released slots are handed to new
-//                 blocks by rank, the rest pushed / popped on a free stack),
-//                 zero-fill + C2 of new blocks, popcount of the bitmap per
-//                 workgroup; the last workgroup scans the counts and commits the
+//   k_pool_count  lock-free slot allocator: a new block claims the first free
+//                 slot at or after (global key mod pool size) with a
+//                 compare-and-swap, so the pool keeps the spatial order of the
+//                 active list; zero-fill + C2 of new blocks; popcounts of the
+//                 bitmap; the last workgroup scans the counts and commits the
 //                 step counters.
 //   k_emit        prefix-sum compaction of the bitmap into the next active list
 //                 (spatial tile order), clearing the bitmap for the next step.
@@ -170,7 +171,6 @@ __global__ void k_init_tables(Tables t, long long nkeys) {
     for (long long i = g0; i < nkeys; i += gs) t.cell2box[i] = EMPTY;
     for (long long i = g0; i < t.nwords; i += gs) t.bitmap[i] = 0ull;
     for (long long i = g0; i < t.cap; i += gs) {
-        t.free_stack[i] = t.cap - 1 - (int)i;     // pops hand out slot 0 first
         t.slot_key[i] = -1;
         t.pin_until[i] = 0;
         t.flags[i] = 0;
@@ -180,7 +180,7 @@ __global__ void k_init_tables(Tables t, long long nkeys) {
     if (g0 == 0) {
         DevState* st = t.st;
         st->step = 0; st->n_act = 0; st->n_new = 0; st->n_ret = 0;
-        st->free_top = t.cap; st->error = 0; st->err_step = -1; st->emit = 0;
+        st->free_cnt = t.cap; st->error = 0; st->err_step = -1; st->emit = 0;
         st->peak_act = 0; st->done_wgs = 0; st->add_error = 0; st->n_dec = 0;
         st->cells_cur = 0; st->updates = 0; st->activations = 0; st->retirements = 0;
         st->cells_cur_u = 0; st->updates_u = 0; st->decays = 0;
@@ -412,6 +412,41 @@ hipError_t launch_block_step(const Tables& t, int grid, hipStream_t s) {
 }
 
 // --------------------------------------------------------------------------
+// slot placement (whole wave): claim the first free slot at or after
+// G mod cap, 64 slots per probe, with a compare-and-swap on slot_key.  With a
+// pool of at least one slot per key this is the identity, so the pool is laid
+// out in the order of the active list and the stencil streams it; a smaller
+// pool wraps the key range over the slots.  Returns -1 only if no slot was
+// free in a full pass.
+// --------------------------------------------------------------------------
+__device__ int place_slot(const Tables& t, long long G) {
+    const int lane = lane_id();
+    const long long cap = t.cap;
+    const long long start = G % cap;
+    const long long passes = cap / 64 + 2;
+    for (long long it = 0; it < passes; it++) {
+        long long s = start + it * 64 + lane;
+        s %= cap;
+        unsigned long long* p = (unsigned long long*)&t.slot_key[s];
+        const unsigned long long v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        unsigned long long m = __ballot(v == ~0ull);
+        while (m) {
+            const int l = __ffsll((long long)m) - 1;
+            bool won = false;
+            if (lane == l) {
+                unsigned long long expected = ~0ull;
+                won = __hip_atomic_compare_exchange_strong(p, &expected, (unsigned long long)G,
+                                                           __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_AGENT);
+            }
+            if (__ballot(won)) return __shfl((int)s, l);
+            m &= m - 1;
+        }
+    }
+    return -1;
+}
+
+// --------------------------------------------------------------------------
 // K2: keep / release / claim ("Updating active cells", items 1-4, 6)
 // --------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_plan(Tables t) {
@@ -452,10 +487,19 @@ __global__ __launch_bounds__(256) void k_plan(Tables t) {
         unsigned key = 0, f = 0;
         int bx = 0, by = 0, bz = 0;
         bool survive = false;
+        // the entry's list row: slot, the 6 face neighbours' slots (as in
+        // cell2box when the list was written; only this kernel, the
+        // allocator and source activation, which rewrites the rows, change
+        // cell2box between two plans), global key
+        int nbs[6] = {EMPTY, EMPTY, EMPTY, EMPTY, EMPTY, EMPTY};
         if (valid) {
-            slot = t.act_slot[i];
+            const int4* rp = (const int4*)(t.rows + 8 * (size_t)i);
+            const int4 r0 = rp[0], r1 = rp[1];
+            slot = r0.x;
+            nbs[0] = r0.y; nbs[1] = r0.z; nbs[2] = r0.w;
+            nbs[3] = r1.x; nbs[4] = r1.y; nbs[5] = r1.z;
             shot = t.act_shot[i];
-            key = t.act_key[i];
+            key = (unsigned)((long long)r1.w - t.shots[shot].key_base);
             if (t.adaptive) {
                 const float* bm = t.bmax + 8 * (size_t)slot;
                 f = 0;
@@ -470,22 +514,21 @@ __global__ __launch_bounds__(256) void k_plan(Tables t) {
             survive = (f & KEEP_BIT) != 0 || t.pin_until[slot] > n + 1;
         }
         if (t.interval <= 1) {
+            // an active neighbour whose face toward us is above trigger keeps us
+#pragma unroll
+            for (int d = 0; d < 6; d++) {
+                if (nbs[d] >= 0) {
+                    const bool face = t.adaptive ? t.bmax[8 * (size_t)nbs[d] + (d ^ 1)] > trig
+                                                 : ((t.flags[nbs[d]] >> (d ^ 1)) & 1u) != 0;
+                    if (face) survive = true;
+                }
+            }
             for (int d = 0; d < 6; d++) {
                 bool claim = false;
                 long long nk = -1;
-                if (valid) {
+                if (valid && nbs[d] == EMPTY && ((f >> d) & 1u)) {
                     nk = neighbour_key(t.shots[shot], bx, by, bz, d);
-                    if (nk >= 0) {
-                        const int s_nb = t.cell2box[nk];
-                        if (s_nb >= 0) {
-                            // an active neighbour whose face toward us is above trigger
-                            const bool face = t.adaptive ? t.bmax[8 * (size_t)s_nb + (d ^ 1)] > trig
-                                                         : ((t.flags[s_nb] >> (d ^ 1)) & 1u) != 0;
-                            if (face) survive = true;
-                        } else if (((f >> d) & 1u) && s_nb == EMPTY) {
-                            claim = atomicCAS(&t.cell2box[nk], EMPTY, CLAIMED) == EMPTY;
-                        }
-                    }
+                    if (nk >= 0) claim = atomicCAS(&t.cell2box[nk], EMPTY, CLAIMED) == EMPTY;
                 }
                 const int k = wave_append(&st->n_new, claim);
                 if (claim) {
@@ -573,7 +616,10 @@ __global__ __launch_bounds__(256) void k_plan(Tables t) {
         const int kd = wave_append(&st->n_dec, decay);
         if (kd >= 0) t.dec_slot[kd] = slot;
         const int kr = wave_append(&st->n_ret, release);
-        if (kr >= 0) t.ret_slot[kr] = slot;
+        if (kr >= 0) {
+            t.ret_slot[kr] = slot;
+            t.ret_key[kr] = t.shots[shot].key_base + (long long)key;
+        }
     }
 }
 
@@ -623,30 +669,41 @@ __global__ __launch_bounds__(256) void k_pool_count(Tables t) {
     const int lane = lane_id();
     const int wid = threadIdx.x >> 6;
     const int err0 = st->error;
-    const int nn = st->n_new, nr = st->n_ret, top = st->free_top;
+    const int nn = st->n_new, nr = st->n_ret, nfree = st->free_cnt;
 
     if (!err0) {
-        if (nn > top + nr) {
+        if (nn > nfree + nr) {
             if (blockIdx.x == 0 && threadIdx.x == 0) {
                 st->err_step = st->step;
                 st->error = -3;   // TCM_E_POOL
             }
         } else {
-            // released blocks (thread per entry)
+            // Only when the free slots alone cannot hold the new blocks are
+            // released slots handed over directly: new block k < handoff takes
+            // released slot k.  Every other released slot is freed, and every
+            // other new block claims a slot by placement.  At least as many
+            // slots are free as there are placing blocks, so every placement
+            // succeeds (slots freed here may be taken as well).
+            const int handoff = nn > nfree ? nn - nfree : 0;
             const int gsz = gridDim.x * blockDim.x;
             for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < nr; r += gsz) {
-                const int slot = t.ret_slot[r];
-                t.cell2box[t.slot_key[slot]] = EMPTY;
-                if (r >= nn) {               // not handed to a new block: push
-                    t.free_stack[top + (r - nn)] = slot;
-                    t.slot_key[slot] = -1;
-                }
+                t.cell2box[t.ret_key[r]] = EMPTY;
+                if (r >= handoff)
+                    __hip_atomic_store(&t.slot_key[t.ret_slot[r]], -1LL, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
             }
             // new blocks (wave per entry): slot, zero phi levels, C2 from media
             const int nwaves = gridDim.x * (blockDim.x >> 6);
             for (int k = blockIdx.x * (blockDim.x >> 6) + wid; k < nn; k += nwaves) {
-                const int slot = k < nr ? t.ret_slot[k] : t.free_stack[top - 1 - (k - nr)];
                 const long long G = t.new_key[k];
+                const int slot = k < handoff ? t.ret_slot[k] : place_slot(t, G);
+                if (slot < 0) {                      // unreachable (see above): fail the step
+                    if (lane == 0) {
+                        st->err_step = st->step;
+                        st->error = -6;
+                    }
+                    continue;
+                }
                 const int shot = t.new_shot[k];
                 const Shot& S = t.shots[shot];
                 int bx, by, bz;
@@ -664,7 +721,7 @@ __global__ __launch_bounds__(256) void k_pool_count(Tables t) {
     }
 
     // shutdown decay (eq.(6)): both stored levels of the listed blocks times alpha
-    if (!err0 && nn <= top + nr) {
+    if (!err0 && nn <= nfree + nr) {
         const int nd = st->n_dec;
         const float alpha = t.shutdown_alpha;
         const int nwaves = gridDim.x * (blockDim.x >> 6);
@@ -675,14 +732,17 @@ __global__ __launch_bounds__(256) void k_pool_count(Tables t) {
         }
     }
 
-    // popcount of 64-word chunks: wave w of workgroup g counts chunks
-    // (g * 4 + w) + k * (gridDim.x * 4)
+    // popcounts of the 16-word chunks: a wave loads 64 words (lane = word)
+    // and sums each group of 16 lanes; wave w of workgroup g takes quads of
+    // chunks (g * 4 + w) + k * (gridDim.x * 4)
     const int nw = blockDim.x >> 6;
-    for (long long c = (long long)blockIdx.x * nw + wid; c < t.nchunks; c += (long long)gridDim.x * nw) {
-        const long long w = c * CHUNK_WORDS + lane;
+    const long long nquads = ((long long)t.nchunks + 3) >> 2;
+    for (long long q = (long long)blockIdx.x * nw + wid; q < nquads; q += (long long)gridDim.x * nw) {
+        const long long w = q * 64 + lane;
         unsigned cnt = w < t.nwords ? (unsigned)__popcll(t.bitmap[w]) : 0u;
-        for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o);
-        if (lane == 0) t.partial[c] = cnt;
+        for (int o = 8; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o);
+        const long long c = q * 4 + (lane >> 4);
+        if ((lane & 15) == 0 && c < t.nchunks) t.partial[c] = cnt;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -724,7 +784,7 @@ __global__ __launch_bounds__(256) void k_pool_count(Tables t) {
             st->step += 1;
         }
         if (!err) {
-            st->free_top = top + nr - nn;
+            st->free_cnt = nfree + nr - nn;
             st->activations += (unsigned long long)nn;
             st->retirements += (unsigned long long)nr;
             st->decays += (unsigned long long)st->n_dec;
@@ -764,10 +824,10 @@ __device__ __forceinline__ int shot_of_word(const Tables& t, long long w) {
     return lo;
 }
 
-// One workgroup per 64-word chunk.  Every wave loads the chunk (lane = word)
+// One workgroup per 16-word chunk.  Every wave loads the chunk (lane = word)
 // and forms the exclusive prefix of the word popcounts; wave v then emits
-// words v, v+4, ... with lane = bit, so each word's blocks are written as
-// one contiguous run in key order.
+// words 4v .. 4v+3 with lane = bit, so each word's blocks are written as one
+// contiguous run in key order.
 __global__ __launch_bounds__(256) void k_emit(Tables t) {
     DevState* st = t.st;
     __shared__ unsigned long long csum[4], usum[4];
@@ -776,7 +836,8 @@ __global__ __launch_bounds__(256) void k_emit(Tables t) {
     const int emit = st->emit;
     const long long chunk = blockIdx.x;
     const long long w_lane = chunk * CHUNK_WORDS + lane;
-    const unsigned long long myword = w_lane < t.nwords ? t.bitmap[w_lane] : 0ull;
+    const bool word_lane = lane < CHUNK_WORDS && w_lane < t.nwords;
+    const unsigned long long myword = word_lane ? t.bitmap[w_lane] : 0ull;
     const unsigned cnt = (unsigned)__popcll(myword);
     unsigned incl = cnt;
     for (int o = 1; o < 64; o <<= 1) {
@@ -785,7 +846,7 @@ __global__ __launch_bounds__(256) void k_emit(Tables t) {
     }
     const unsigned base = emit ? t.partial[chunk] : 0u;
     unsigned long long cells = 0, ucells = 0;
-    for (int j = wid; j < CHUNK_WORDS; j += 4) {
+    for (int j = wid * (CHUNK_WORDS / 4); j < (wid + 1) * (CHUNK_WORDS / 4); j++) {
         const unsigned long long m = __shfl(myword, j);
         if (m == 0ull) continue;
         const long long w = chunk * CHUNK_WORDS + j;
@@ -832,7 +893,7 @@ __global__ __launch_bounds__(256) void k_emit(Tables t) {
         usum[wid] = ucells;
     }
     __syncthreads();                       // every wave has read the chunk
-    if (wid == 0 && w_lane < t.nwords && myword) t.bitmap[w_lane] = 0ull;
+    if (wid == 0 && word_lane && myword) t.bitmap[w_lane] = 0ull;
     if (threadIdx.x == 0) {
         const unsigned long long c = csum[0] + csum[1] + csum[2] + csum[3];
         const unsigned long long u = usum[0] + usum[1] + usum[2] + usum[3];
@@ -858,12 +919,15 @@ __global__ __launch_bounds__(64) void k_activate(Tables t, long long G, int shot
         if (lane == 0 && t.pin_until[cur] < pin) t.pin_until[cur] = pin;
         return;
     }
-    const int top = st->free_top;
-    if (top <= 0) {
+    if (st->free_cnt <= 0) {
         if (lane == 0) st->add_error = -3;
         return;
     }
-    const int slot = t.free_stack[top - 1];
+    const int slot = place_slot(t, G);
+    if (slot < 0) {                      // unreachable: a slot is free
+        if (lane == 0) st->add_error = -6;
+        return;
+    }
     const Shot& S = t.shots[shot];
     int bx, by, bz;
     key_to_block(S, key, bx, by, bz);
@@ -871,7 +935,7 @@ __global__ __launch_bounds__(64) void k_activate(Tables t, long long G, int shot
     if (lane == 0) {
         t.slot_c2u[slot] = c2u;
         t.sdlog[slot] = 0;
-        st->free_top = top - 1;
+        st->free_cnt -= 1;
         t.cell2box[G] = slot;
         t.slot_key[slot] = G;
         t.pin_until[slot] = pin;

@@ -304,12 +304,10 @@ tcm_status setup_engine(tcm_handle* h, long long word_base) {
         return set_err(h, TCM_E_ARG, "more than 2^31 block keys: grid too large for one handle");
     t.nwords = word_base;
     t.nchunks = (int)((word_base + CHUNK_WORDS - 1) / CHUNK_WORDS);
-    long long nblocks = 0;
-    for (const Shot& S : h->shots) nblocks += (long long)S.bx * S.by * S.bz;
     size_t free_b = 0, total_b = 0;
     (void)hipMemGetInfo(&free_b, &total_b);
     // per-slot bookkeeping bytes besides the 6 KiB slot
-    const size_t per_slot_tab = 4 + 4 + 4 + 32 + 1 + 4 + 4 + 1 + 4 + 8 + 4 + 8 + 4 + 4;
+    const size_t per_slot_tab = 4 + 4 + 4 + 32 + 1 + 4 + 4 + 1 + 4 + 8 + 8 + 4 + 4 + 8;
     const size_t fixed = (size_t)h->nkeys * 4 + (size_t)word_base * 8 + (size_t)t.nchunks * 4 + (1 << 20);
     long long cap;
     if (cfg->pool_bytes > 0) {
@@ -318,13 +316,15 @@ tcm_status setup_engine(tcm_handle* h, long long word_base) {
         if (!cfg->device_pool && (double)cap * (SLOT_BYTES + per_slot_tab) + fixed > 0.95 * (double)free_b)
             return set_err(h, TCM_E_NOMEM, fmt("pool of %lld slots does not fit in %.1f GB free", cap, free_b / 1e9));
     } else {
-        cap = nblocks;
+        // one slot per key (tiles padded at the domain edges included): new
+        // blocks are then placed at slot = key, in the order of the list
+        cap = h->nkeys;
         const double room = 0.9 * (double)free_b - (double)fixed;
         const long long fit = room > 0 ? (long long)(room / (double)(SLOT_BYTES + per_slot_tab)) : 0;
         if (cap > fit) cap = fit;
         if (cap < 1) return set_err(h, TCM_E_NOMEM, "no device memory for the pool");
     }
-    if (cap > nblocks) cap = nblocks;
+    if (cap > h->nkeys) cap = h->nkeys;
     if (cap > 0x7fffffffLL) cap = 0x7fffffffLL;
     t.cap = (int)cap;
 
@@ -353,10 +353,10 @@ tcm_status setup_engine(tcm_handle* h, long long word_base) {
     ok = ok && dalloc(h, &t.bmax, t.adaptive ? (size_t)cap * 8 : 1) == hipSuccess;
     t.uniform_c2 = (cfg->flags & TCM_FLAG_NO_UNIFORM_C2) ? 0 : 1;
     ok = ok && dalloc(h, &t.slot_key, (size_t)cap) == hipSuccess;
-    ok = ok && dalloc(h, &t.free_stack, (size_t)cap) == hipSuccess;
     ok = ok && dalloc(h, &t.new_key, (size_t)cap) == hipSuccess;
     ok = ok && dalloc(h, &t.new_shot, (size_t)cap) == hipSuccess;
     ok = ok && dalloc(h, &t.ret_slot, (size_t)cap) == hipSuccess;
+    ok = ok && dalloc(h, &t.ret_key, (size_t)cap) == hipSuccess;
     ok = ok && dalloc(h, &t.partial, (size_t)t.nchunks) == hipSuccess;
     if (!ok) return set_err(h, TCM_E_NOMEM, "device allocation of the block tables failed");
     h->table_bytes += fixed + (size_t)cap * per_slot_tab;
@@ -370,7 +370,7 @@ tcm_status setup_engine(tcm_handle* h, long long word_base) {
     const int wpc = cfg->wg_per_cu > 0 ? cfg->wg_per_cu : (occ > 0 ? occ : 4);
     h->grid_step = std::max(8, (h->ncu * wpc) / 8 * 8);
     h->grid_plan = std::max(1, h->ncu * 2);
-    h->grid_pool = std::min(POOL_COUNT_MAX_WG, std::max(64, std::min(t.nchunks, h->ncu)));
+    h->grid_pool = std::min(POOL_COUNT_MAX_WG, std::max(64, std::min((t.nchunks + 3) / 4, h->ncu)));
     t.interval = cfg->trigger_interval > 1 ? cfg->trigger_interval : 1;
     h->gsteps = round_graph_steps(h, cfg->graph_steps > 0 ? cfg->graph_steps : 16);
     return TCM_OK;
@@ -397,6 +397,8 @@ tcm_status create_common(const tcm_config* cfg, const tcm_shot* shots, int nshot
         return set_err(nullptr, TCM_E_ARG, "relative levels must satisfy 0 <= retire_rel <= trigger_rel");
     if (cfg->trigger_interval < 0 || cfg->trigger_interval > BE)
         return set_err(nullptr, TCM_E_ARG, "trigger_interval must be in [0, 8] (0 and 1: every step)");
+    if (cfg->device_pool && cfg->pool_bytes < SLOT_BYTES)
+        return set_err(nullptr, TCM_E_ARG, "a caller device_pool needs its size in pool_bytes");
     if (cfg->engine == TCM_ENGINE_DENSE && nshots != 1)
         return set_err(nullptr, TCM_E_ARG, "the dense engine runs one shot");
 
@@ -555,8 +557,7 @@ std::vector<CkPart> ck_parts(tcm_handle* h) {
             {t.act_key, cap * 4},                {t.rows, cap * 32},
             {t.flags, cap},                      {t.pin_until, cap * 4},
             {t.slot_c2u, cap * 4},               {t.sdlog, cap},
-            {t.slot_key, cap * 8},               {t.free_stack, cap * 4},
-            {t.st, sizeof(DevState)}};
+            {t.slot_key, cap * 8},               {t.st, sizeof(DevState)}};
 }
 
 size_t ck_bytes(tcm_handle* h) {

@@ -59,6 +59,30 @@ def test_c2_full_run_bitexact_to_cpu_tcm():
     assert digest(tr) == g["traces_sha256"]
 
 
+@pytest.mark.parametrize("name", ["workload", "1e-09"])
+def test_c2_interval8_full_run_bitexact_to_cpu_tcm(name):
+    """512^3 two-layer, 2000 steps with the activation update every 8 steps
+    (eq.(5)) and the 26-neighbour lookahead, at the workload thresholds and at
+    trigger 1e-9 / retire 1e-10 of the peak: both final levels and the work
+    statistics equal the CPU TCM."""
+    announce(f"C2 interval 8 ({name}) vs stored CPU TCM result")
+    g = load("c2k8_golden.json")
+    o = g[name]
+    w = ti.c2()
+    sim = tcm.Simulation(w.shape, w.dx, w.dt, w.layered, o["trigger"], o["retire"], timing=True,
+                         trigger_interval=g["interval"])
+    sim.add_source(w.source, w.wavelet.w32)
+    sim.step(w.steps)
+    st = sim.stats()
+    s = o["stats"]
+    assert st["step"] == s["step"] and st["active_blocks"] == s["active"]
+    assert st["peak_active_blocks"] == s["peak_active"]
+    assert st["activations"] == s["activations"] and st["retirements"] == s["retirements"]
+    assert st["cell_updates"] == s["updates"]
+    assert digest(sim.read(0)) == o["phi_sha256"]
+    assert digest(sim.read(1)) == o["prev_sha256"]
+
+
 def test_c3_virtual_4096_first_steps_match_cpu_tcm_on_crop():
     """Virtual 4096^3 domain with the 64 GB pool cap: after 200 steps every
     nonzero node lies within 200 nodes of the source, so the CPU TCM on the
