@@ -101,8 +101,11 @@ struct Tables {
     int* new_shot;
     int* ret_slot;                  // per step: released slots ...
     long long* ret_key;             //   ... and the global keys they held
-    unsigned* partial;              // per 16-word chunk of the bitmap: set bits, then offsets
-    int nchunks;                    // ceil(nwords / 16)
+    unsigned* partial;              // per 16-word chunk: set bits, then offset inside its range
+    int nchunks;                    // ceil(nwords / 16); the bitmap is padded to whole chunks
+    unsigned* wg_total;             // per k_pool_count workgroup: set bits of its chunk range,
+                                    // then the offset of the range in the next list
+    int chunks_per_wg;              // chunks per k_pool_count workgroup (contiguous ranges)
     const Src* src;
     int nsrc;
     const float* srcw;
@@ -117,7 +120,8 @@ struct Tables {
 // The compaction works on chunks of 16 bitmap words (1024 blocks), one
 // workgroup per chunk.
 constexpr int CHUNK_WORDS = 16;
-// Upper bound on the workgroups of k_pool_count (it counts chunks in a loop).
+// Upper bound on the workgroups of k_pool_count; each takes chunks_per_wg
+// consecutive chunks, so its grid must be the one chunks_per_wg was set for.
 constexpr int POOL_COUNT_MAX_WG = 1024;
 
 // ---- launch wrappers (tcm_kernels.hip) -----------------------------------
@@ -126,7 +130,7 @@ hipError_t launch_block_step(const Tables& t, int grid, hipStream_t s);
 int block_step_occupancy(bool adaptive = false);   // resident 256-thread workgroups per CU
 hipError_t launch_plan(const Tables& t, int grid, hipStream_t s);
 hipError_t launch_advance(const Tables& t, hipStream_t s);   // step without an activation update
-hipError_t launch_pool_count(const Tables& t, int grid, hipStream_t s);   // grid <= POOL_COUNT_MAX_WG
+hipError_t launch_pool_count(const Tables& t, int grid, hipStream_t s);   // grid * chunks_per_wg >= nchunks
 hipError_t launch_emit(const Tables& t, hipStream_t s);
 hipError_t launch_activate(const Tables& t, long long key, int shot, unsigned local_key,
                            int pin_until, hipStream_t s);

@@ -4,9 +4,11 @@
 // counters so that a sequence of steps can be replayed as a hipGraph:
 //
 //   k_block_step  eq.(3) on every active 8^3 block: one 64-lane wave per block,
-//                 lane = (x, y) column with the 8 z values in registers, the six
-//                 neighbour face planes staged in LDS; additive source insertion;
-//                 wave-ballot face/keep predicates -> one flag byte per slot.
+//                 lane = (x, y) column with the 8 z values in registers, the
+//                 neighbour face planes staged in LDS (x faces shared between
+//                 the waves of a workgroup, which take x-adjacent blocks);
+//                 additive source insertion; wave-ballot face/keep predicates
+//                 -> one flag byte per slot.
 //   k_plan        keep / release each active block, claim empty face neighbours
 //                 with a compare-and-swap on the block table, mark the next
 //                 active set in a bitmap; receivers are recorded here.
@@ -38,14 +40,6 @@ using scalar_ptr = const __attribute__((address_space(4))) T*;
 template <class T>
 __device__ __forceinline__ scalar_ptr<T> as_scalar(const T* p) {
     return (scalar_ptr<T>)(p);
-}
-
-// Order LDS writes and reads of one wave (the wave runs in lockstep; this
-// only stops the compiler from moving LDS accesses across the point).
-__device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 __device__ __forceinline__ void key_to_block(const Shot& S, unsigned key, int& bx, int& by,
@@ -169,7 +163,7 @@ __global__ void k_init_tables(Tables t, long long nkeys) {
     const long long gs = (long long)gridDim.x * blockDim.x;
     const long long g0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     for (long long i = g0; i < nkeys; i += gs) t.cell2box[i] = EMPTY;
-    for (long long i = g0; i < t.nwords; i += gs) t.bitmap[i] = 0ull;
+    for (long long i = g0; i < (long long)t.nchunks * CHUNK_WORDS; i += gs) t.bitmap[i] = 0ull;
     for (long long i = g0; i < t.cap; i += gs) {
         t.slot_key[i] = -1;
         t.pin_until[i] = 0;
@@ -209,7 +203,9 @@ constexpr int TILE_FLOATS = TILE_COLS * TILE_COLS * BE;
 
 template <bool ADAPT>
 __global__ __launch_bounds__(256) void k_block_step(Tables t) {
-    __shared__ __align__(16) float lds[4][TILE_FLOATS];
+    // two sets of per-wave tiles: iteration k writes set k & 1, so one
+    // workgroup barrier per iteration separates writes from every read
+    __shared__ __align__(16) float lds[2][4][TILE_FLOATS];
     const DevState* st = t.st;
     if (st->error) return;
     const int n = st->step;
@@ -217,7 +213,6 @@ __global__ __launch_bounds__(256) void k_block_step(Tables t) {
     const int p = n & 1;
     const int lane = lane_id();
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    float* T = lds[wid];
     const int x = lane & 7, y = lane >> 3;
     // face loaders: lane -> (a, zz) on a side face
     const int a = lane & 7, zz = lane >> 3;
@@ -240,65 +235,91 @@ __global__ __launch_bounds__(256) void k_block_step(Tables t) {
     const scalar_ptr<int> pin_until = as_scalar((const int*)t.pin_until);
     const scalar_ptr<float> slot_c2u = as_scalar((const float*)t.slot_c2u);
     const int stride = per * 4;
-    int i = beg + jw * 4 + wid;
+    // The workgroup's four waves take consecutive entries ib + wid, so the
+    // loop count is uniform over the workgroup (barriers below).  In a full
+    // tile consecutive entries are x neighbours: a wave then takes the x face
+    // shared with the previous / next wave's block from that wave's tile.
+    int ib = beg + jw * 4;
     int r[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    if (i < end) {
+    int sl_prev = EMPTY, sl_next = EMPTY;
+    {
+        const int i = ib + wid;
+        if (i < end) {
 #pragma unroll
-        for (int k = 0; k < 8; k++) r[k] = rows[8 * (size_t)i + k];
+            for (int k = 0; k < 8; k++) r[k] = rows[8 * (size_t)i + k];
+            if (wid > 0) sl_prev = rows[8 * (size_t)(i - 1)];
+            if (wid < 3 && i + 1 < end) sl_next = rows[8 * (size_t)(i + 1)];
+        }
     }
-    for (; i < end; i += stride) {
+    int buf = 0;
+    for (; ib < end; ib += stride, buf ^= 1) {
+        const int i = ib + wid;
+        const bool have = i < end;
         const int slot = r[0];
         const int nb[6] = {r[1], r[2], r[3], r[4], r[5], r[6]};
         const int G = r[7];
-        if (i + stride < end) {
+        const bool share_m = have && wid > 0 && nb[0] >= 0 && nb[0] == sl_prev;
+        const bool share_p = have && wid < 3 && nb[1] >= 0 && nb[1] == sl_next;
+        {
+            const int in = i + stride;
+            sl_prev = EMPTY;
+            sl_next = EMPTY;
+            if (in < end) {
 #pragma unroll
-            for (int k = 0; k < 8; k++) r[k] = rows[8 * (size_t)(i + stride) + k];
+                for (int k = 0; k < 8; k++) r[k] = rows[8 * (size_t)in + k];
+                if (wid > 0) sl_prev = rows[8 * (size_t)(in - 1)];
+                if (wid < 3 && in + 1 < end) sl_next = rows[8 * (size_t)(in + 1)];
+            }
         }
-        const int pinned = t.nsrc > 0 ? pin_until[slot] : 0;
+        float* T = lds[buf][wid];
+        float cur[8], prv[8], k2[8];
+        float zlo = 0.f, zhi = 0.f;
+        int pinned = 0;
+        float* __restrict__ out_p = nullptr;
+        if (have) {
+        pinned = t.nsrc > 0 ? pin_until[slot] : 0;
         const float c2u = slot_c2u[slot];
         const float* __restrict__ blk = t.pool + (size_t)slot * SLOT;
         const float* __restrict__ cur_p = blk + p * BV;
-        float* __restrict__ out_p = (float*)blk + (1 - p) * BV;
+        out_p = (float*)blk + (1 - p) * BV;
         const float* __restrict__ c2_p = blk + C2_PLANE;
-
-        float cur[8], prv[8], k2[8];
 #pragma unroll
         for (int z = 0; z < 8; z++) {
             cur[z] = cur_p[z * 64 + lane];
-            // phi^{n-1} and C2 are read once per step: stream them past L2 so
-            // that it keeps the phi^n lines the neighbours' faces re-read
             prv[z] = __builtin_nontemporal_load(&out_p[z * 64 + lane]);
         }
-        if (c2u == c2u) {            // uniform block: one coefficient, no C2 plane read
+        if (c2u == c2u) {
 #pragma unroll
             for (int z = 0; z < 8; z++) k2[z] = c2u;
         } else {
 #pragma unroll
             for (int z = 0; z < 8; z++) k2[z] = __builtin_nontemporal_load(&c2_p[z * 64 + lane]);
         }
-        float zlo = 0.f, zhi = 0.f, fmx = 0.f, fpx = 0.f, fmy = 0.f, fpy = 0.f;
         if (nb[4] >= 0) zlo = t.pool[(size_t)nb[4] * SLOT + p * BV + 7 * 64 + lane];
         if (nb[5] >= 0) zhi = t.pool[(size_t)nb[5] * SLOT + p * BV + 0 * 64 + lane];
-        if (nb[0] >= 0) fmx = t.pool[(size_t)nb[0] * SLOT + p * BV + zz * 64 + a * 8 + 7];
-        if (nb[1] >= 0) fpx = t.pool[(size_t)nb[1] * SLOT + p * BV + zz * 64 + a * 8 + 0];
+        float fmx = 0.f, fpx = 0.f, fmy = 0.f, fpy = 0.f;
+        if (nb[0] >= 0 && !share_m) fmx = t.pool[(size_t)nb[0] * SLOT + p * BV + zz * 64 + a * 8 + 7];
+        if (nb[1] >= 0 && !share_p) fpx = t.pool[(size_t)nb[1] * SLOT + p * BV + zz * 64 + a * 8 + 0];
         if (nb[2] >= 0) fmy = t.pool[(size_t)nb[2] * SLOT + p * BV + zz * 64 + 7 * 8 + a];
         if (nb[3] >= 0) fpy = t.pool[(size_t)nb[3] * SLOT + p * BV + zz * 64 + 0 * 8 + a];
-
-        wave_lds_sync();   // previous iteration's reads are done
-        {
-            float4* own = (float4*)(T + ((y + 1) * TILE_COLS + (x + 1)) * BE);
-            own[0] = make_float4(cur[0], cur[1], cur[2], cur[3]);
-            own[1] = make_float4(cur[4], cur[5], cur[6], cur[7]);
-            T[((a + 1) * TILE_COLS + 0) * BE + zz] = fmx;
-            T[((a + 1) * TILE_COLS + 9) * BE + zz] = fpx;
-            T[(0 * TILE_COLS + (a + 1)) * BE + zz] = fmy;
-            T[(9 * TILE_COLS + (a + 1)) * BE + zz] = fpy;
+        float4* own = (float4*)(T + ((y + 1) * TILE_COLS + (x + 1)) * BE);
+        own[0] = make_float4(cur[0], cur[1], cur[2], cur[3]);
+        own[1] = make_float4(cur[4], cur[5], cur[6], cur[7]);
+        T[((a + 1) * TILE_COLS + 0) * BE + zz] = fmx;
+        T[((a + 1) * TILE_COLS + 9) * BE + zz] = fpx;
+        T[(0 * TILE_COLS + (a + 1)) * BE + zz] = fmy;
+        T[(9 * TILE_COLS + (a + 1)) * BE + zz] = fpy;
         }
-        wave_lds_sync();
+        __syncthreads();   // every wave's tile of this set is written
+        if (!have) continue;
         float xm[8], xp[8], ym[8], yp[8];
         {
-            const float4* c_xm = (const float4*)(T + ((y + 1) * TILE_COLS + x) * BE);
-            const float4* c_xp = (const float4*)(T + ((y + 1) * TILE_COLS + x + 2) * BE);
+            const float* Tm = lds[buf][wid > 0 ? wid - 1 : 0];
+            const float* Tp = lds[buf][wid < 3 ? wid + 1 : 3];
+            const float4* c_xm = (const float4*)(x == 0 && share_m ? Tm + ((y + 1) * TILE_COLS + 8) * BE
+                                                                   : T + ((y + 1) * TILE_COLS + x) * BE);
+            const float4* c_xp = (const float4*)(x == 7 && share_p ? Tp + ((y + 1) * TILE_COLS + 1) * BE
+                                                                   : T + ((y + 1) * TILE_COLS + x + 2) * BE);
             const float4* c_ym = (const float4*)(T + (y * TILE_COLS + x + 1) * BE);
             const float4* c_yp = (const float4*)(T + ((y + 2) * TILE_COLS + x + 1) * BE);
             float4 v0 = c_xm[0], v1 = c_xm[1];
@@ -732,18 +753,51 @@ __global__ __launch_bounds__(256) void k_pool_count(Tables t) {
         }
     }
 
-    // popcounts of the 16-word chunks: a wave loads 64 words (lane = word)
-    // and sums each group of 16 lanes; wave w of workgroup g takes quads of
-    // chunks (g * 4 + w) + k * (gridDim.x * 4)
-    const int nw = blockDim.x >> 6;
-    const long long nquads = ((long long)t.nchunks + 3) >> 2;
-    for (long long q = (long long)blockIdx.x * nw + wid; q < nquads; q += (long long)gridDim.x * nw) {
-        const long long w = q * 64 + lane;
-        unsigned cnt = w < t.nwords ? (unsigned)__popcll(t.bitmap[w]) : 0u;
-        for (int o = 8; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o);
-        const long long c = q * 4 + (lane >> 4);
-        if ((lane & 15) == 0 && c < t.nchunks) t.partial[c] = cnt;
+    // Two-level scan of the bitmap.  Workgroup g owns chunks
+    // [g * C, g * C + C): each thread counts a contiguous run of them, the
+    // workgroup scans the runs and stores every chunk's offset inside the
+    // range and the range total; the last workgroup to finish turns the
+    // totals into range offsets.
+    const int C = t.chunks_per_wg;
+    const long long c0 = (long long)blockIdx.x * C;
+    const long long c1 = min((long long)t.nchunks, c0 + C);
+    const int K = (C + (int)blockDim.x - 1) / (int)blockDim.x;
+    const long long tc0 = c0 + (long long)threadIdx.x * K;
+    unsigned tsum = 0;
+    for (int k = 0; k < K; k++) {
+        const long long c = tc0 + k;
+        if (c >= c1) break;
+        const ulonglong2* bw = (const ulonglong2*)(t.bitmap + c * CHUNK_WORDS);
+        unsigned cnt = 0;
+#pragma unroll
+        for (int j = 0; j < CHUNK_WORDS / 2; j++) {
+            const ulonglong2 v = bw[j];
+            cnt += (unsigned)__popcll(v.x) + (unsigned)__popcll(v.y);
+        }
+        t.partial[c] = cnt;
+        tsum += cnt;
     }
+    const int nw = blockDim.x >> 6;
+    unsigned incl = tsum;
+    for (int o = 1; o < 64; o <<= 1) {
+        const unsigned u = __shfl_up(incl, o);
+        if (lane >= o) incl += u;
+    }
+    if (lane == 63) red[wid] = incl;
+    __syncthreads();
+    unsigned run = incl - tsum, wg_sum = 0;
+    for (int w = 0; w < nw; w++) {
+        if (w < wid) run += red[w];
+        wg_sum += red[w];
+    }
+    for (int k = 0; k < K; k++) {
+        const long long c = tc0 + k;
+        if (c >= c1) break;
+        const unsigned v = t.partial[c];
+        t.partial[c] = run;
+        run += v;
+    }
+    if (threadIdx.x == 0) t.wg_total[blockIdx.x] = wg_sum;
     __syncthreads();
     if (threadIdx.x == 0) {
         __threadfence();
@@ -753,27 +807,28 @@ __global__ __launch_bounds__(256) void k_pool_count(Tables t) {
     if (!last) return;
     __threadfence();
 
-    // last workgroup: exclusive scan of the chunk counts (each thread a
-    // contiguous run of chunks), then commit the step's counters
-    const int nc = t.nchunks;
-    const int per = (nc + (int)blockDim.x - 1) / (int)blockDim.x;
-    const int c0 = min(nc, (int)threadIdx.x * per), c1 = min(nc, c0 + per);
+    // last workgroup: exclusive scan of the range totals (at most 1024, each
+    // thread a contiguous run), then commit the step's counters
+    const int ng = gridDim.x;
+    const int per = (ng + (int)blockDim.x - 1) / (int)blockDim.x;
+    const int g0 = min(ng, (int)threadIdx.x * per), g1 = min(ng, g0 + per);
     unsigned mine = 0;
-    for (int c = c0; c < c1; c++) mine += __atomic_load_n(&t.partial[c], __ATOMIC_RELAXED);
-    unsigned incl = mine;
+    for (int g = g0; g < g1; g++) mine += __atomic_load_n(&t.wg_total[g], __ATOMIC_RELAXED);
+    incl = mine;
     for (int o = 1; o < 64; o <<= 1) {
         const unsigned u = __shfl_up(incl, o);
         if (lane >= o) incl += u;
     }
+    __syncthreads();                       // red[] is reused
     if (lane == 63) red[wid] = incl;
     __syncthreads();
-    unsigned run = incl - mine;
+    run = incl - mine;
     for (int w = 0; w < wid; w++) run += red[w];
     unsigned total = 0;
     for (int w = 0; w < nw; w++) total += red[w];
-    for (int c = c0; c < c1; c++) {
-        const unsigned v = __atomic_load_n(&t.partial[c], __ATOMIC_RELAXED);
-        t.partial[c] = run;
+    for (int g = g0; g < g1; g++) {
+        const unsigned v = __atomic_load_n(&t.wg_total[g], __ATOMIC_RELAXED);
+        t.wg_total[g] = run;
         run += v;
     }
     if (threadIdx.x == 0) {
@@ -806,8 +861,8 @@ __global__ __launch_bounds__(256) void k_pool_count(Tables t) {
 }
 
 hipError_t launch_pool_count(const Tables& t, int grid, hipStream_t s) {
-    if (grid > POOL_COUNT_MAX_WG) grid = POOL_COUNT_MAX_WG;
-    if (grid < 1) grid = 1;
+    if (grid < 1 || grid > POOL_COUNT_MAX_WG || (long long)grid * t.chunks_per_wg < t.nchunks)
+        return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_pool_count, dim3(grid), dim3(256), 0, s, t);
     return hipGetLastError();
 }
@@ -844,7 +899,7 @@ __global__ __launch_bounds__(256) void k_emit(Tables t) {
         const unsigned u = __shfl_up(incl, o);
         if (lane >= o) incl += u;
     }
-    const unsigned base = emit ? t.partial[chunk] : 0u;
+    const unsigned base = emit ? t.wg_total[chunk / t.chunks_per_wg] + t.partial[chunk] : 0u;
     unsigned long long cells = 0, ucells = 0;
     for (int j = wid * (CHUNK_WORDS / 4); j < (wid + 1) * (CHUNK_WORDS / 4); j++) {
         const unsigned long long m = __shfl(myword, j);

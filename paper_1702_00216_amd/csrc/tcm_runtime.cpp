@@ -335,7 +335,7 @@ tcm_status setup_engine(tcm_handle* h, long long word_base) {
         ok = ok && dalloc(h, &t.pool, (size_t)cap * SLOT) == hipSuccess;
     }
     ok = ok && dalloc(h, &t.cell2box, (size_t)h->nkeys) == hipSuccess;
-    ok = ok && dalloc(h, &t.bitmap, (size_t)word_base) == hipSuccess;
+    ok = ok && dalloc(h, &t.bitmap, (size_t)t.nchunks * CHUNK_WORDS) == hipSuccess;
     ok = ok && dalloc(h, &t.act_slot, (size_t)cap) == hipSuccess;
     ok = ok && dalloc(h, &t.act_shot, (size_t)cap) == hipSuccess;
     ok = ok && dalloc(h, &t.act_key, (size_t)cap) == hipSuccess;
@@ -358,6 +358,7 @@ tcm_status setup_engine(tcm_handle* h, long long word_base) {
     ok = ok && dalloc(h, &t.ret_slot, (size_t)cap) == hipSuccess;
     ok = ok && dalloc(h, &t.ret_key, (size_t)cap) == hipSuccess;
     ok = ok && dalloc(h, &t.partial, (size_t)t.nchunks) == hipSuccess;
+    ok = ok && dalloc(h, &t.wg_total, (size_t)POOL_COUNT_MAX_WG) == hipSuccess;
     if (!ok) return set_err(h, TCM_E_NOMEM, "device allocation of the block tables failed");
     h->table_bytes += fixed + (size_t)cap * per_slot_tab;
 
@@ -371,6 +372,7 @@ tcm_status setup_engine(tcm_handle* h, long long word_base) {
     h->grid_step = std::max(8, (h->ncu * wpc) / 8 * 8);
     h->grid_plan = std::max(1, h->ncu * 2);
     h->grid_pool = std::min(POOL_COUNT_MAX_WG, std::max(64, std::min((t.nchunks + 3) / 4, h->ncu)));
+    h->t.chunks_per_wg = (t.nchunks + h->grid_pool - 1) / h->grid_pool;
     t.interval = cfg->trigger_interval > 1 ? cfg->trigger_interval : 1;
     h->gsteps = round_graph_steps(h, cfg->graph_steps > 0 ? cfg->graph_steps : 16);
     return TCM_OK;
