@@ -54,7 +54,7 @@ struct DevState {
     unsigned long long decays;       // block-steps of the shutdown decay
     unsigned maxbits;                // adaptive levels: max |phi^{n+1}| of this step (float bits)
     float trig_cur, ret_cur;         // levels used by the last plan
-    int pad2;
+    int n_ne;                        // per step: chunks of the bitmap with a set bit
     unsigned long long activations, retirements;
 };
 
@@ -105,7 +105,9 @@ struct Tables {
     int nchunks;                    // ceil(nwords / 16); the bitmap is padded to whole chunks
     unsigned* wg_total;             // per k_pool_count workgroup: set bits of its chunk range,
                                     // then the offset of the range in the next list
-    int chunks_per_wg;              // chunks per k_pool_count workgroup (contiguous ranges)
+    int chunks_per_wg;              // chunks per scanning k_pool_count workgroup (contiguous)
+    int scan_wgs;                   // the first scan_wgs workgroups of k_pool_count scan
+    int* ne_chunks;                 // per step: the chunks with a set bit (any order)
     const Src* src;
     int nsrc;
     const float* srcw;
@@ -120,8 +122,8 @@ struct Tables {
 // The compaction works on chunks of 16 bitmap words (1024 blocks), one
 // workgroup per chunk.
 constexpr int CHUNK_WORDS = 16;
-// Upper bound on the workgroups of k_pool_count; each takes chunks_per_wg
-// consecutive chunks, so its grid must be the one chunks_per_wg was set for.
+// Upper bound on the scanning workgroups of k_pool_count; each takes
+// chunks_per_wg consecutive chunks (scan_wgs * chunks_per_wg >= nchunks).
 constexpr int POOL_COUNT_MAX_WG = 1024;
 
 // ---- launch wrappers (tcm_kernels.hip) -----------------------------------
@@ -130,8 +132,8 @@ hipError_t launch_block_step(const Tables& t, int grid, hipStream_t s);
 int block_step_occupancy(bool adaptive = false);   // resident 256-thread workgroups per CU
 hipError_t launch_plan(const Tables& t, int grid, hipStream_t s);
 hipError_t launch_advance(const Tables& t, hipStream_t s);   // step without an activation update
-hipError_t launch_pool_count(const Tables& t, int grid, hipStream_t s);   // grid * chunks_per_wg >= nchunks
-hipError_t launch_emit(const Tables& t, hipStream_t s);
+hipError_t launch_pool_count(const Tables& t, int grid, hipStream_t s);   // grid >= scan_wgs
+hipError_t launch_emit(const Tables& t, int grid, hipStream_t s);
 hipError_t launch_activate(const Tables& t, long long key, int shot, unsigned local_key,
                            int pin_until, hipStream_t s);
 hipError_t launch_refresh_rows(const Tables& t, hipStream_t s);

@@ -178,7 +178,7 @@ __global__ void k_init_tables(Tables t, long long nkeys) {
         st->peak_act = 0; st->done_wgs = 0; st->add_error = 0; st->n_dec = 0;
         st->cells_cur = 0; st->updates = 0; st->activations = 0; st->retirements = 0;
         st->cells_cur_u = 0; st->updates_u = 0; st->decays = 0;
-        st->maxbits = 0u; st->trig_cur = t.trigger; st->ret_cur = t.retire; st->pad2 = 0;
+        st->maxbits = 0u; st->trig_cur = t.trigger; st->ret_cur = t.retire; st->n_ne = 0;
     }
 }
 
@@ -479,6 +479,7 @@ __global__ __launch_bounds__(256) void k_plan(Tables t) {
     const int gsz = gridDim.x * blockDim.x;
     const int g0 = blockIdx.x * blockDim.x + threadIdx.x;
 
+    if (g0 == 0) st->n_ne = 0;   // filled by the allocator's scan, read by the compaction
     // receivers: traces[n - trace_step0][r] = phi^{n+1}
     // levels of this step: constant, or relative to the domain maximum
     float trig = t.trigger, ret = t.retire;
@@ -753,29 +754,35 @@ __global__ __launch_bounds__(256) void k_pool_count(Tables t) {
         }
     }
 
-    // Two-level scan of the bitmap.  Workgroup g owns chunks
-    // [g * C, g * C + C): each thread counts a contiguous run of them, the
-    // workgroup scans the runs and stores every chunk's offset inside the
-    // range and the range total; the last workgroup to finish turns the
-    // totals into range offsets.
+    // Two-level scan of the bitmap by the first scan_wgs workgroups (the
+    // rest only allocate).  Workgroup g owns chunks [g * C, g * C + C): each
+    // thread counts a contiguous run of them, the workgroup scans the runs
+    // and stores every chunk's offset inside the range and the range total;
+    // the last scanning workgroup to finish turns the totals into range
+    // offsets.
+    if ((int)blockIdx.x >= t.scan_wgs) return;
     const int C = t.chunks_per_wg;
     const long long c0 = (long long)blockIdx.x * C;
     const long long c1 = min((long long)t.nchunks, c0 + C);
     const int K = (C + (int)blockDim.x - 1) / (int)blockDim.x;
     const long long tc0 = c0 + (long long)threadIdx.x * K;
     unsigned tsum = 0;
-    for (int k = 0; k < K; k++) {
+    for (int k = 0; k < K; k++) {                // K is uniform: every lane runs the ballots
         const long long c = tc0 + k;
-        if (c >= c1) break;
-        const ulonglong2* bw = (const ulonglong2*)(t.bitmap + c * CHUNK_WORDS);
         unsigned cnt = 0;
+        if (c < c1) {
+            const ulonglong2* bw = (const ulonglong2*)(t.bitmap + c * CHUNK_WORDS);
 #pragma unroll
-        for (int j = 0; j < CHUNK_WORDS / 2; j++) {
-            const ulonglong2 v = bw[j];
-            cnt += (unsigned)__popcll(v.x) + (unsigned)__popcll(v.y);
+            for (int j = 0; j < CHUNK_WORDS / 2; j++) {
+                const ulonglong2 v = bw[j];
+                cnt += (unsigned)__popcll(v.x) + (unsigned)__popcll(v.y);
+            }
+            t.partial[c] = cnt;
+            tsum += cnt;
         }
-        t.partial[c] = cnt;
-        tsum += cnt;
+        // the compaction visits only the chunks listed here
+        const int q = wave_append(&st->n_ne, cnt > 0u);
+        if (q >= 0) t.ne_chunks[q] = (int)c;
     }
     const int nw = blockDim.x >> 6;
     unsigned incl = tsum;
@@ -801,7 +808,7 @@ __global__ __launch_bounds__(256) void k_pool_count(Tables t) {
     __syncthreads();
     if (threadIdx.x == 0) {
         __threadfence();
-        last = atomicAdd(&st->done_wgs, 1) == (int)gridDim.x - 1;
+        last = atomicAdd(&st->done_wgs, 1) == t.scan_wgs - 1;
     }
     __syncthreads();
     if (!last) return;
@@ -809,7 +816,7 @@ __global__ __launch_bounds__(256) void k_pool_count(Tables t) {
 
     // last workgroup: exclusive scan of the range totals (at most 1024, each
     // thread a contiguous run), then commit the step's counters
-    const int ng = gridDim.x;
+    const int ng = t.scan_wgs;
     const int per = (ng + (int)blockDim.x - 1) / (int)blockDim.x;
     const int g0 = min(ng, (int)threadIdx.x * per), g1 = min(ng, g0 + per);
     unsigned mine = 0;
@@ -861,7 +868,8 @@ __global__ __launch_bounds__(256) void k_pool_count(Tables t) {
 }
 
 hipError_t launch_pool_count(const Tables& t, int grid, hipStream_t s) {
-    if (grid < 1 || grid > POOL_COUNT_MAX_WG || (long long)grid * t.chunks_per_wg < t.nchunks)
+    if (t.scan_wgs < 1 || t.scan_wgs > POOL_COUNT_MAX_WG || grid < t.scan_wgs ||
+        (long long)t.scan_wgs * t.chunks_per_wg < t.nchunks)
         return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_pool_count, dim3(grid), dim3(256), 0, s, t);
     return hipGetLastError();
@@ -879,65 +887,75 @@ __device__ __forceinline__ int shot_of_word(const Tables& t, long long w) {
     return lo;
 }
 
-// One workgroup per 16-word chunk.  Every wave loads the chunk (lane = word)
-// and forms the exclusive prefix of the word popcounts; wave v then emits
-// words 4v .. 4v+3 with lane = bit, so each word's blocks are written as one
-// contiguous run in key order.
-__global__ __launch_bounds__(256) void k_emit(Tables t) {
+// Workgroups of 16 waves take the chunks with a set bit (listed by the
+// allocator's scan; all chunks when the grid covers them) in turn.  Every wave loads the chunk (lane = word) and
+// forms the exclusive prefix of the word popcounts; wave v then emits word v
+// with lane = bit, so each word's blocks are written as one contiguous run in
+// key order.
+constexpr int EMIT_WAVES = CHUNK_WORDS;
+__global__ __launch_bounds__(64 * EMIT_WAVES) void k_emit(Tables t) {
     DevState* st = t.st;
-    __shared__ unsigned long long csum[4], usum[4];
+    __shared__ unsigned long long csum[EMIT_WAVES], usum[EMIT_WAVES];
     const int lane = lane_id();
     const int wid = threadIdx.x >> 6;
     const int emit = st->emit;
-    const long long chunk = blockIdx.x;
-    const long long w_lane = chunk * CHUNK_WORDS + lane;
-    const bool word_lane = lane < CHUNK_WORDS && w_lane < t.nwords;
-    const unsigned long long myword = word_lane ? t.bitmap[w_lane] : 0ull;
-    const unsigned cnt = (unsigned)__popcll(myword);
-    unsigned incl = cnt;
-    for (int o = 1; o < 64; o <<= 1) {
-        const unsigned u = __shfl_up(incl, o);
-        if (lane >= o) incl += u;
-    }
-    const unsigned base = emit ? t.wg_total[chunk / t.chunks_per_wg] + t.partial[chunk] : 0u;
+    // a grid that covers every chunk takes them directly (empty ones cost a
+    // load); otherwise it walks the list of non-empty chunks
+    const bool direct = t.nchunks <= (int)gridDim.x;
+    const int nq = direct ? t.nchunks : st->n_ne;
     unsigned long long cells = 0, ucells = 0;
-    for (int j = wid * (CHUNK_WORDS / 4); j < (wid + 1) * (CHUNK_WORDS / 4); j++) {
-        const unsigned long long m = __shfl(myword, j);
-        if (m == 0ull) continue;
-        const long long w = chunk * CHUNK_WORDS + j;
-        const bool mine = (m >> lane) & 1ull;
-        const long long G = w * 64 + lane;
-        if (!emit) {
-            // the step failed: undo its claims, keep the current list
-            if (mine && t.cell2box[G] == CLAIMED) t.cell2box[G] = EMPTY;
-            continue;
+    for (int q = blockIdx.x; q < nq; q += gridDim.x) {      // uniform over the workgroup
+        const long long chunk = direct ? q : t.ne_chunks[q];
+        const long long w_lane = chunk * CHUNK_WORDS + lane;
+        const bool word_lane = lane < CHUNK_WORDS && w_lane < t.nwords;
+        const unsigned long long myword = word_lane ? t.bitmap[w_lane] : 0ull;
+        const unsigned cnt = (unsigned)__popcll(myword);
+        unsigned incl = cnt;
+        for (int o = 1; o < 64; o <<= 1) {
+            const unsigned u = __shfl_up(incl, o);
+            if (lane >= o) incl += u;
         }
-        const unsigned off = base + __shfl(incl - cnt, j) +
-                             (unsigned)__popcll(m & ((1ull << lane) - 1ull));
-        const int shot = shot_of_word(t, w);
-        const Shot& S = t.shots[shot];
-        if (mine) {
-            const unsigned key = (unsigned)(G - S.key_base);
-            const int slot = t.cell2box[G];
-            t.act_slot[off] = slot;
-            t.act_shot[off] = shot;
-            t.act_key[off] = key;
-            int bx, by, bz;
-            key_to_block(S, key, bx, by, bz);
-            const unsigned long long bc = (unsigned long long)block_cells(S, bx, by, bz);
-            cells += bc;
-            const float u = t.slot_c2u[slot];
-            if (u == u) ucells += bc;
-            int nb[6];
-#pragma unroll
-            for (int d = 0; d < 6; d++) {
-                const long long nk = neighbour_key(S, bx, by, bz, d);
-                nb[d] = nk >= 0 ? t.cell2box[nk] : EMPTY;
+        const unsigned base = emit ? t.wg_total[chunk / t.chunks_per_wg] + t.partial[chunk] : 0u;
+        for (int j = wid; j == wid; j++) {          // the wave's own word
+            const unsigned long long m = __shfl(myword, j);
+            if (m == 0ull) continue;
+            const long long w = chunk * CHUNK_WORDS + j;
+            const bool mine = (m >> lane) & 1ull;
+            const long long G = w * 64 + lane;
+            if (!emit) {
+                // the step failed: undo its claims, keep the current list
+                if (mine && t.cell2box[G] == CLAIMED) t.cell2box[G] = EMPTY;
+                continue;
             }
-            int4* rp = (int4*)(t.rows + 8 * (size_t)off);
-            rp[0] = make_int4(slot, nb[0], nb[1], nb[2]);
-            rp[1] = make_int4(nb[3], nb[4], nb[5], (int)G);
+            const unsigned off = base + __shfl(incl - cnt, j) +
+                                 (unsigned)__popcll(m & ((1ull << lane) - 1ull));
+            const int shot = shot_of_word(t, w);
+            const Shot& S = t.shots[shot];
+            if (mine) {
+                const unsigned key = (unsigned)(G - S.key_base);
+                const int slot = t.cell2box[G];
+                t.act_slot[off] = slot;
+                t.act_shot[off] = shot;
+                t.act_key[off] = key;
+                int bx, by, bz;
+                key_to_block(S, key, bx, by, bz);
+                const unsigned long long bc = (unsigned long long)block_cells(S, bx, by, bz);
+                cells += bc;
+                const float u = t.slot_c2u[slot];
+                if (u == u) ucells += bc;
+                int nb[6];
+#pragma unroll
+                for (int d = 0; d < 6; d++) {
+                    const long long nk = neighbour_key(S, bx, by, bz, d);
+                    nb[d] = nk >= 0 ? t.cell2box[nk] : EMPTY;
+                }
+                int4* rp = (int4*)(t.rows + 8 * (size_t)off);
+                rp[0] = make_int4(slot, nb[0], nb[1], nb[2]);
+                rp[1] = make_int4(nb[3], nb[4], nb[5], (int)G);
+            }
         }
+        __syncthreads();                       // every wave has read the chunk
+        if (wid == 0 && word_lane && myword) t.bitmap[w_lane] = 0ull;
     }
     for (int o = 32; o > 0; o >>= 1) {
         cells += __shfl_xor(cells, o);
@@ -947,18 +965,20 @@ __global__ __launch_bounds__(256) void k_emit(Tables t) {
         csum[wid] = cells;
         usum[wid] = ucells;
     }
-    __syncthreads();                       // every wave has read the chunk
-    if (wid == 0 && word_lane && myword) t.bitmap[w_lane] = 0ull;
+    __syncthreads();
     if (threadIdx.x == 0) {
-        const unsigned long long c = csum[0] + csum[1] + csum[2] + csum[3];
-        const unsigned long long u = usum[0] + usum[1] + usum[2] + usum[3];
+        unsigned long long c = 0, u = 0;
+        for (int w = 0; w < EMIT_WAVES; w++) {
+            c += csum[w];
+            u += usum[w];
+        }
         if (c) atomicAdd(&st->cells_cur, c);
         if (u) atomicAdd(&st->cells_cur_u, u);
     }
 }
 
-hipError_t launch_emit(const Tables& t, hipStream_t s) {
-    hipLaunchKernelGGL(k_emit, dim3(t.nchunks), dim3(256), 0, s, t);
+hipError_t launch_emit(const Tables& t, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_emit, dim3(grid), dim3(64 * EMIT_WAVES), 0, s, t);
     return hipGetLastError();
 }
 

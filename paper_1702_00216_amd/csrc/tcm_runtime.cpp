@@ -59,7 +59,7 @@ struct tcm_handle {
     long long nkeys = 0;
     size_t table_bytes = 0;
 
-    int grid_step = 0, grid_plan = 0, grid_pool = 0;
+    int grid_step = 0, grid_plan = 0, grid_pool = 0, grid_emit = 0;
     long long hstep = 0;                // index of the next step to enqueue
 
     // sources / receivers (host mirrors)
@@ -359,6 +359,7 @@ tcm_status setup_engine(tcm_handle* h, long long word_base) {
     ok = ok && dalloc(h, &t.ret_key, (size_t)cap) == hipSuccess;
     ok = ok && dalloc(h, &t.partial, (size_t)t.nchunks) == hipSuccess;
     ok = ok && dalloc(h, &t.wg_total, (size_t)POOL_COUNT_MAX_WG) == hipSuccess;
+    ok = ok && dalloc(h, &t.ne_chunks, (size_t)t.nchunks) == hipSuccess;
     if (!ok) return set_err(h, TCM_E_NOMEM, "device allocation of the block tables failed");
     h->table_bytes += fixed + (size_t)cap * per_slot_tab;
 
@@ -370,9 +371,15 @@ tcm_status setup_engine(tcm_handle* h, long long word_base) {
     const int occ = block_step_occupancy(t.adaptive != 0);
     const int wpc = cfg->wg_per_cu > 0 ? cfg->wg_per_cu : (occ > 0 ? occ : 4);
     h->grid_step = std::max(8, (h->ncu * wpc) / 8 * 8);
-    h->grid_plan = std::max(1, h->ncu * 2);
-    h->grid_pool = std::min(POOL_COUNT_MAX_WG, std::max(64, std::min((t.nchunks + 3) / 4, h->ncu)));
-    h->t.chunks_per_wg = (t.nchunks + h->grid_pool - 1) / h->grid_pool;
+    // one plan thread per entry up to 4 x 256 x CUs entries; the allocator
+    // fills new blocks with 2 workgroups per CU, of which the first scan_wgs
+    // also scan the bitmap
+    h->grid_plan = std::max(1, h->ncu * 4);
+    t.scan_wgs = std::min(POOL_COUNT_MAX_WG, std::max(64, std::min((t.nchunks + 3) / 4, h->ncu)));
+    t.chunks_per_wg = (t.nchunks + t.scan_wgs - 1) / t.scan_wgs;
+    h->grid_pool = std::max(t.scan_wgs, h->ncu * 2);
+    // compaction: 16-wave workgroups over the non-empty chunks
+    h->grid_emit = std::max(1, std::min(t.nchunks, h->ncu * 2));
     t.interval = cfg->trigger_interval > 1 ? cfg->trigger_interval : 1;
     h->gsteps = round_graph_steps(h, cfg->graph_steps > 0 ? cfg->graph_steps : 16);
     return TCM_OK;
@@ -485,7 +492,7 @@ hipError_t enqueue_step(tcm_handle* h, hipEvent_t e0, hipEvent_t e1) {
     if ((n + 1) % k != 0) return launch_advance(h->t, h->stream);
     if ((e = launch_plan(h->t, h->grid_plan, h->stream)) != hipSuccess) return e;
     if ((e = launch_pool_count(h->t, h->grid_pool, h->stream)) != hipSuccess) return e;
-    return launch_emit(h->t, h->stream);
+    return launch_emit(h->t, h->grid_emit, h->stream);
 }
 
 hipError_t enqueue_dense_step(tcm_handle* h, hipEvent_t e0, hipEvent_t e1) {

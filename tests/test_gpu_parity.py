@@ -155,6 +155,62 @@ def test_pool_cap_fails_like_cpu_tcm():
     assert sim.step_status(3) == -3 and sim.stats()["step"] == o["step"]
 
 
+@pytest.mark.parametrize("slack", [0, -1])
+def test_pool_exact_fit_hands_released_slots_over(slack):
+    """A pool of exactly the peak active count: at step 45 the step's new
+    blocks exceed the free slots and released slots are handed over directly
+    (placement wraps the key range over 47 slots).  One slot fewer fails with
+    E_POOL at the same step as the CPU TCM with that cap."""
+    announce(f"pool of peak{slack:+d} slots, released slots handed over")
+    shape = (48, 32, 32)
+    c = np.ones(shape[::-1], np.float32)
+    w = ti.ricker(0.15, 0.5).w32
+    lev = np.float32(3e-2)
+    ref = oracle.TCM(c, 0.5, 1.0, lev, lev)
+    ref.add_source((10, 16, 16), w)
+    assert ref.step(200) == 0
+    cap = ref.stats()["peak_active"] + slack
+    t = oracle.TCM(c, 0.5, 1.0, lev, lev, cap=cap)
+    t.add_source((10, 16, 16), w)
+    rc = t.step(200)
+    assert rc == (0 if slack == 0 else oracle.TCM.E_POOL)
+    sim = gpu_run(shape, 0.5, c, [((10, 16, 16), w)], 0, lev, lev, pool_bytes=cap * 6144)
+    assert sim.step_status(200) == rc
+    g, o = sim.stats(), t.stats()
+    assert g["step"] == o["step"] and g["active_blocks"] == o["active"]
+    assert g["activations"] == o["activations"] and g["retirements"] == o["retirements"]
+    assert g["cell_updates"] == o["updates"]
+    assert values_equal(sim.read(0), t.read(0)) and values_equal(sim.read(1), t.read(1))
+
+
+def test_zero_speed_region_and_no_source():
+    """c = 0 inside a box (C2 = 0 there: phi^{n+1} = 2 phi^n - phi^{n-1}),
+    at threshold 0 (dense oracle) and above it (CPU TCM); a handle without a
+    source stays empty."""
+    announce("zero-speed box; no source")
+    shape = (40, 36, 44)
+    c = ti.random_media(shape, seed=12, cmin=0.4, cmax=1.0)
+    c[10:26, 8:30, 20:33] = 0.0
+    w = ti.ricker(0.12, 0.5).w32
+    src = [((12, 18, 16), w)]
+    phi, prev, _ = oracle.dense_run(c, 0.5, 1.0, 90, np.float32, sources=src)
+    sim = gpu_run(shape, 0.5, c, src, 90)
+    assert values_equal(sim.read(0), phi) and values_equal(sim.read(1), prev)
+    lev = np.float32(1e-3)
+    t = oracle.TCM(c, 0.5, 1.0, lev, np.float32(2e-4))
+    t.add_source(*src[0])
+    assert t.step(90) == 0
+    sim = gpu_run(shape, 0.5, c, src, 90, lev, np.float32(2e-4))
+    assert values_equal(sim.read(0), t.read(0))
+    assert sim.stats()["cell_updates"] == t.stats()["updates"]
+    empty = gpu_run(shape, 0.5, c, [], 0)
+    assert not empty.read(0).any()
+    empty.step(25)
+    st = empty.stats()
+    assert st["step"] == 25 and st["active_blocks"] == 0 and st["cell_updates"] == 0
+    assert not empty.read(0).any() and not empty.read(1).any()
+
+
 def test_layered_and_lattice_media():
     announce("layered + lattice media")
     shape = (48, 40, 64)
