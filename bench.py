@@ -56,12 +56,20 @@ def run_once(sim, w, steps):
     return time.perf_counter() - t0, sim.stats()
 
 
+def kernel_source_hash() -> str:
+    """sha256 (16 hex digits) of the k_block_step function source: the
+    counters in profiles/ are used only while it is unchanged."""
+    import hashlib
+    src = open(os.path.join(ROOT, "paper_1702_00216_amd", "csrc", "tcm_kernels.hip")).read()
+    a = src.index("template <bool ADAPT>\n__global__")
+    b = src.index("int block_step_occupancy")
+    return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
+
+
 def measured_traffic(name: str):
     """HBM bytes per k_block_step dispatch from the committed rocprofv3 counter
     summary, if it was taken on the current kernel source; else None."""
-    import hashlib
     p = os.path.join(ROOT, "profiles", f"k_block_step_{name}_traffic.md")
-    src = os.path.join(ROOT, "paper_1702_00216_amd", "csrc", "tcm_kernels.hip")
     if not os.path.exists(p):
         return None
     kv = {}
@@ -69,8 +77,7 @@ def measured_traffic(name: str):
         if "=" in line and not line.startswith(" "):
             k, v = line.strip().split("=", 1)
             kv[k] = v
-    cur = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    if kv.get("kernel_source_sha256_16") != cur:
+    if kv.get("k_block_step_source_sha256_16") != kernel_source_hash():
         return None
     return int(kv["traffic_bytes_per_dispatch"])
 
