@@ -98,10 +98,26 @@ def cpu_baseline(w, budget_s: float):
     el = time.perf_counter() - t0
     st = t.stats()
     t.close()
+    cores = oracle.openmp_threads()
+    # the same sample on one core (the paper's own figures are single-CPU)
+    oracle.set_threads(1)
+    t = oracle.TCM(c, w.dt, w.dx, np.float32(w.trigger), np.float32(w.retire))
+    t.add_source(w.source, w.wavelet.w32)
+    t0 = time.perf_counter()
+    done1 = 0
+    while done1 < done and time.perf_counter() - t0 < budget_s / 2:
+        t.step(25)
+        done1 += 25
+    el1 = time.perf_counter() - t0
+    st1 = t.stats()
+    t.close()
+    oracle.set_threads(cores)
     return {"value": st["updates"] / el, "unit": "active-cell updates/s",
-            "cores": oracle.openmp_threads(), "kind": "oracle",
+            "cores": cores, "kind": "oracle",
             "sample": f"CPU TCM oracle (FP32, OpenMP) on steps 0-{done} of the same workload "
-                      f"({st['updates']:.3e} updates in {el:.1f} s)"}
+                      f"({st['updates']:.3e} updates in {el:.1f} s)",
+            "single_core": {"value": st1["updates"] / el1, "cores": 1,
+                            "sample": f"steps 0-{done1} ({st1['updates']:.3e} updates in {el1:.1f} s)"}}
 
 
 def _line(metric_value, steps, warmup, ms, config, **extra):
@@ -264,6 +280,79 @@ def bench_c4(args, tcm):
           one_by_one=seq, autotune=tuning)
 
 
+def bench_c5(args, tcm):
+    """256^3 lognormal model, 1000 steps, 128 receivers on z = 240: the forward
+    with a checkpoint every 50 steps, then the adjoint gradient dJ/dc at the
+    stored FP64 residual (threshold 0, so every node is stepped)."""
+    import numpy as np
+    import torch
+    import tcm_inputs as ti
+    w = ti.c5()
+    steps = args.time_steps or w.steps
+    c = ti.lattice_to_dense(w.lattice, w.shape)
+    p = os.path.join(ROOT, "tests", "golden", "c5_resid.npy")
+    if steps == w.steps and os.path.exists(p):
+        resid = np.load(p)
+    else:
+        resid = np.random.default_rng(55).standard_normal((steps, len(w.receivers))).astype(np.float32)
+    sim = tcm.Simulation(w.shape, w.dx, w.dt, c, checkpoint_every=50, wg_per_cu=args.wg_per_cu)
+
+    def run():
+        sim.reset()
+        sim.add_source(w.source, w.wavelet.w32)
+        sim.set_receivers(w.receivers)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(steps)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        g = sim.adjoint(resid)
+        t2 = time.perf_counter()
+        return t1 - t0, t2 - t1, g
+
+    for i in range(args.warmup):
+        f, a, _ = run()
+        log(f"c5 warmup {i}: forward {f:.3f} s, adjoint {a:.3f} s")
+    tf, ta = 0.0, 0.0
+    for i in range(args.steps):
+        f, a, g = run()
+        tf += f
+        ta += a
+        log(f"c5 run {i}: forward {f:.3f} s, adjoint {a:.3f} s, |g| {np.linalg.norm(g):.3e}")
+    sim.close()
+    nodes = w.shape[0] * w.shape[1] * w.shape[2]
+    tot = (tf + ta) / args.steps
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        k = 8
+        while True:      # the FP64 oracle adjoint on the first k steps, ~budget seconds
+            r = np.random.default_rng(56).standard_normal((k, len(w.receivers)))
+            t0 = time.perf_counter()
+            oracle.adjoint_f64(c, w.dt, w.dx, [(w.source, w.wavelet.w32.astype(np.float64))],
+                               w.receivers, r, ckpt=max(1, k // 2))
+            el = time.perf_counter() - t0
+            if el > args.cpu_budget / 4 or k >= steps:
+                break
+            k *= 2
+        cpu = {"value": nodes * k / el, "unit": "gradient node-steps/s", "cores": oracle.openmp_threads(),
+               "kind": "oracle", "sample": f"FP64 oracle adjoint (forward with checkpoints, recompute, "
+                                           f"adjoint) on the first {k} steps of the model ({el:.1f} s)"}
+        log(f"c5 CPU oracle: {k} steps in {el:.1f} s")
+    out = {"metric": "TCM adjoint: gradient dJ/dc node-steps/s (forward with checkpoints + adjoint)",
+           "value": nodes * steps / tot, "unit": "gradient node-steps/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(tot * 1e3, 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": f"c5: 256^3 lognormal (seed 5), Ricker 100 Hz at {w.source}, {steps} steps, "
+                                  f"128 receivers on z = 240, checkpoints every 50, threshold 0",
+                      "time_steps_per_run": steps},
+           "roofline": None, "cpu_baseline": cpu,
+           "adjoint": {"forward_s": round(tf / args.steps, 4), "adjoint_s": round(ta / args.steps, 4),
+                       "adjoint_over_forward": round(ta / tf, 3)}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -308,6 +397,8 @@ def main():
         return bench_c3(args, tcm)
     if args.workload == "c4":
         return bench_c4(args, tcm)
+    if args.workload == "c5":
+        return bench_c5(args, tcm)
     w = workload(args.workload)
     if args.trigger is not None:
         w.trigger = args.trigger * w.wavelet.peak

@@ -117,6 +117,8 @@ def _declare(L):
     L.oracle_decay_total.restype = _D
     L.oracle_openmp_threads.argtypes = []
     L.oracle_openmp_threads.restype = _I
+    L.oracle_set_threads.argtypes = [_I]
+    L.oracle_set_threads.restype = None
 
 
 def _ptr(a: Optional[np.ndarray]):
@@ -329,3 +331,8 @@ def decay_total(alpha: float, n: int) -> float:
 
 def openmp_threads() -> int:
     return int(lib().oracle_openmp_threads())
+
+
+def set_threads(n: int) -> None:
+    """OpenMP threads of the oracle's parallel loops from now on."""
+    lib().oracle_set_threads(int(n))

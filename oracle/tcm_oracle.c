@@ -80,3 +80,14 @@ int oracle_openmp_threads(void)
     return 1;
 #endif
 }
+
+/* Thread count of the following parallel loops (timing on one core). */
+void oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    extern void omp_set_num_threads(int);
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
