@@ -128,7 +128,10 @@ constexpr int POOL_COUNT_MAX_WG = 1024;
 
 // ---- launch wrappers (tcm_kernels.hip) -----------------------------------
 hipError_t launch_init_tables(const Tables& t, long long nkeys, hipStream_t s);
-hipError_t launch_block_step(const Tables& t, int grid, hipStream_t s);
+// e0 / e1 (optional): events stamped by the dispatch itself at the kernel's
+// start and end (no separate event packets around it)
+hipError_t launch_block_step(const Tables& t, int grid, hipStream_t s, hipEvent_t e0 = nullptr,
+                             hipEvent_t e1 = nullptr);
 int block_step_occupancy(bool adaptive = false);   // resident 256-thread workgroups per CU
 hipError_t launch_plan(const Tables& t, int grid, hipStream_t s);
 hipError_t launch_advance(const Tables& t, hipStream_t s);   // step without an activation update
@@ -149,7 +152,8 @@ struct DenseArgs {
     float* nxt;                      // holds phi^{n-1} on entry, phi^{n+1} on exit
     const float* c2;
 };
-hipError_t launch_dense_step(const DenseArgs& a, hipStream_t s);
+hipError_t launch_dense_step(const DenseArgs& a, hipStream_t s, hipEvent_t e0 = nullptr,
+                             hipEvent_t e1 = nullptr);
 hipError_t launch_dense_inject(float* nxt, int n, const Src* src, int nsrc, const float* srcw,
                                const Rec* rec, int nrec, float* traces, int trace_row,
                                hipStream_t s);

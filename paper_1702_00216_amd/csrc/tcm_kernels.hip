@@ -26,6 +26,8 @@
 //   next = (2 phi - prev) + C2 lap;  compiled with -ffp-contract=off.
 #include "tcm_internal.h"
 
+#include <hip/hip_ext.h>
+
 namespace tcmk {
 
 // --------------------------------------------------------------------------
@@ -424,11 +426,17 @@ int block_step_occupancy(bool adaptive) {
     return e == hipSuccess ? nb : 0;
 }
 
-hipError_t launch_block_step(const Tables& t, int grid, hipStream_t s) {
-    if (t.adaptive)
+hipError_t launch_block_step(const Tables& t, int grid, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    if (e0 || e1) {                 // timed launch (never inside a graph capture)
+        if (t.adaptive)
+            hipExtLaunchKernelGGL(k_block_step<true>, dim3(grid), dim3(256), 0, s, e0, e1, 0, t);
+        else
+            hipExtLaunchKernelGGL(k_block_step<false>, dim3(grid), dim3(256), 0, s, e0, e1, 0, t);
+    } else if (t.adaptive) {
         hipLaunchKernelGGL(k_block_step<true>, dim3(grid), dim3(256), 0, s, t);
-    else
+    } else {
         hipLaunchKernelGGL(k_block_step<false>, dim3(grid), dim3(256), 0, s, t);
+    }
     return hipGetLastError();
 }
 
@@ -1153,10 +1161,13 @@ __global__ __launch_bounds__(256) void k_dense_step(DenseArgs a) {
     }
 }
 
-hipError_t launch_dense_step(const DenseArgs& a, hipStream_t s) {
+hipError_t launch_dense_step(const DenseArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     dim3 grid((a.nx + DENSE_TX - 1) / DENSE_TX, (a.ny + DENSE_TY - 1) / DENSE_TY,
               (a.nz + DENSE_DZ - 1) / DENSE_DZ);
-    hipLaunchKernelGGL(k_dense_step, grid, dim3(256), 0, s, a);
+    if (e0 || e1)
+        hipExtLaunchKernelGGL(k_dense_step, grid, dim3(256), 0, s, e0, e1, 0, a);
+    else
+        hipLaunchKernelGGL(k_dense_step, grid, dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -486,9 +486,7 @@ hipError_t enqueue_step(tcm_handle* h, hipEvent_t e0, hipEvent_t e1) {
     hipError_t e;
     const long long n = h->hstep++;
     const int k = h->t.interval > 1 ? h->t.interval : 1;
-    if (e0 && (e = hipEventRecord(e0, h->stream)) != hipSuccess) return e;
-    if ((e = launch_block_step(h->t, h->grid_step, h->stream)) != hipSuccess) return e;
-    if (e1 && (e = hipEventRecord(e1, h->stream)) != hipSuccess) return e;
+    if ((e = launch_block_step(h->t, h->grid_step, h->stream, e0, e1)) != hipSuccess) return e;
     if ((n + 1) % k != 0) return launch_advance(h->t, h->stream);
     if ((e = launch_plan(h->t, h->grid_plan, h->stream)) != hipSuccess) return e;
     if ((e = launch_pool_count(h->t, h->grid_pool, h->stream)) != hipSuccess) return e;
@@ -500,9 +498,7 @@ hipError_t enqueue_dense_step(tcm_handle* h, hipEvent_t e0, hipEvent_t e1) {
     const long long n = h->dense_step;
     DenseArgs a{S.nx, S.ny, S.nz, h->d_phi[n & 1], h->d_phi[1 - (n & 1)], h->d_c2};
     hipError_t e;
-    if (e0 && (e = hipEventRecord(e0, h->stream)) != hipSuccess) return e;
-    if ((e = launch_dense_step(a, h->stream)) != hipSuccess) return e;
-    if (e1 && (e = hipEventRecord(e1, h->stream)) != hipSuccess) return e;
+    if ((e = launch_dense_step(a, h->stream, e0, e1)) != hipSuccess) return e;
     const long long row = n - h->t.trace_step0;
     const int trow = (h->t.nrec > 0 && row >= 0 && row < h->t.trace_cap) ? (int)row : -1;
     if (h->t.nsrc > 0 || trow >= 0) {
