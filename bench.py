@@ -57,12 +57,14 @@ def run_once(sim, w, steps):
 
 
 def kernel_source_hash() -> str:
-    """sha256 (16 hex digits) of the k_block_step function source: the
-    counters in profiles/ are used only while it is unchanged."""
+    """sha256 (16 hex digits) of the k_block_step function source, from its
+    template line to its closing brace: the counters in profiles/ are used
+    only while it is unchanged."""
     import hashlib
     src = open(os.path.join(ROOT, "paper_1702_00216_amd", "csrc", "tcm_kernels.hip")).read()
-    a = src.index("template <bool ADAPT>\n__global__")
-    b = src.index("int block_step_occupancy")
+    k = src.index(" void k_block_step(Tables t) {")
+    a = src.rindex("\ntemplate <", 0, k) + 1
+    b = src.index("\n}\n", k) + 3
     return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
 
 
@@ -216,7 +218,8 @@ def bench_c4(args, tcm):
     shapes = [s.shape for s in shots]
     media = [s.lattice for s in shots]
     sim = tcm.Simulation(shapes, 1.0, w0.dt, media, w0.trigger, w0.retire,
-                         wg_per_cu=args.wg_per_cu, graph_steps=args.graph_steps)
+                         wg_per_cu=args.wg_per_cu, graph_steps=args.graph_steps,
+                         blocks_per_wg=args.blocks_per_wg)
 
     def run_batch():
         sim.reset()
@@ -240,7 +243,8 @@ def bench_c4(args, tcm):
         sim.step(steps // 2)
         tuning = sim.autotune(probe_steps=32, cache=os.environ.get("TCM_TUNE_CACHE"),
                               key=f"gfx950/c4/{len(shots)}shots")
-        log(f"c4 autotune: wg_per_cu {tuning['wg_per_cu']} graph_steps {tuning['graph_steps']} "
+        log(f"c4 autotune: tile {tuning['blocks_per_wg']} blocks, wg_per_cu {tuning['wg_per_cu']}, "
+            f"graph_steps {tuning['graph_steps']} "
             f"({tuning['ms_per_step']:.3f} ms/step)")
     tot, upd = 0.0, 0
     for i in range(args.steps):
@@ -254,7 +258,8 @@ def bench_c4(args, tcm):
         t_seq, u_seq = 0.0, 0
         for s in shots:
             one = tcm.Simulation(s.shape, 1.0, s.dt, s.lattice, s.trigger, s.retire,
-                                 wg_per_cu=args.wg_per_cu)
+                                 wg_per_cu=(tuning or {}).get("wg_per_cu", args.wg_per_cu),
+                                 blocks_per_wg=(tuning or {}).get("blocks_per_wg", args.blocks_per_wg))
             one.add_source(s.source, s.wavelet.w32)
             one.step(8)
             one.reset()
@@ -366,6 +371,7 @@ def main():
     ap.add_argument("--graphs", action="store_true",
                     help="time with hipGraph replay instead of per-launch HIP events")
     ap.add_argument("--wg-per-cu", type=int, default=0)
+    ap.add_argument("--blocks-per-wg", type=int, default=0, help="stencil workgroup tile (2, 4, 8)")
     ap.add_argument("--graph-steps", type=int, default=0)
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-uniform-c2", action="store_true",
@@ -410,7 +416,8 @@ def main():
     opts = dict(uniform_c2=not args.no_uniform_c2, trigger_interval=args.interval,
                 shutdown_steps=args.shutdown_steps, shutdown_alpha=args.shutdown_alpha)
     sim = tcm.Simulation(w.shape, w.dx, w.dt, media_of(w), w.trigger, w.retire,
-                         timing=not args.graphs, wg_per_cu=args.wg_per_cu, **opts)
+                         timing=not args.graphs, wg_per_cu=args.wg_per_cu,
+                         blocks_per_wg=args.blocks_per_wg, **opts)
     for i in range(args.warmup):
         el, st = run_once(sim, w, steps)
         log(f"warmup {i}: {el:.3f} s, {st['cell_updates']:.3e} updates")
@@ -423,7 +430,8 @@ def main():
         tuning = sim.autotune(probe_steps=32, cache=os.environ.get("TCM_TUNE_CACHE"),
                               key=f"gfx950/{w.name}/k{args.interval}")
         tuning.pop("candidates", None)
-        log(f"autotune: wg_per_cu {tuning['wg_per_cu']} graph_steps {tuning['graph_steps']}")
+        log(f"autotune: tile {tuning['blocks_per_wg']} blocks, wg_per_cu {tuning['wg_per_cu']}, "
+            f"graph_steps {tuning['graph_steps']}")
     tot_t, tot_u, st_ms, st_cells, st_launch, st_cells_u = 0.0, 0, 0.0, 0, 0, 0
     for i in range(args.steps):
         el, st = run_once(sim, w, steps)
@@ -443,6 +451,7 @@ def main():
         # the same runs replayed as hipGraphs (no per-launch events)
         gsim = tcm.Simulation(w.shape, w.dx, w.dt, media_of(w), w.trigger, w.retire,
                               timing=False, wg_per_cu=(tuning or {}).get("wg_per_cu", args.wg_per_cu),
+                              blocks_per_wg=(tuning or {}).get("blocks_per_wg", args.blocks_per_wg),
                               graph_steps=(tuning or {}).get("graph_steps", 0), **opts)
         run_once(gsim, w, steps)
         gel, gst = run_once(gsim, w, steps)
@@ -537,7 +546,8 @@ def main():
             o = g8[name]
             ksim = tcm.Simulation(w.shape, w.dx, w.dt, media_of(w), o["trigger"], o["retire"],
                                   timing=True, trigger_interval=g8["interval"],
-                                  wg_per_cu=(tuning or {}).get("wg_per_cu", args.wg_per_cu))
+                                  wg_per_cu=(tuning or {}).get("wg_per_cu", args.wg_per_cu),
+                                  blocks_per_wg=(tuning or {}).get("blocks_per_wg", args.blocks_per_wg))
             run_once(ksim, w, steps)
             el, kst = run_once(ksim, w, steps)
             ksim.close()

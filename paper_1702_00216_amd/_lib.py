@@ -33,7 +33,7 @@ class Config(C.Structure):
                 ("graph_steps", C.c_int32), ("wg_per_cu", C.c_int32),
                 ("shutdown_steps", C.c_int32), ("shutdown_alpha", C.c_float),
                 ("trigger_rel", C.c_float), ("retire_rel", C.c_float),
-                ("trigger_interval", C.c_int32)]
+                ("trigger_interval", C.c_int32), ("blocks_per_wg", C.c_int32)]
 
 
 class Media(C.Structure):
@@ -63,7 +63,8 @@ class Stats(C.Structure):
 class Tuning(C.Structure):
     _fields_ = [("wg_per_cu", C.c_int32), ("graph_steps", C.c_int32), ("ms_per_step", C.c_double),
                 ("ncand", C.c_int32), ("cand_wg_per_cu", C.c_int32 * 32),
-                ("cand_graph_steps", C.c_int32 * 32), ("cand_ms_per_step", C.c_double * 32)]
+                ("cand_graph_steps", C.c_int32 * 32), ("cand_ms_per_step", C.c_double * 32),
+                ("blocks_per_wg", C.c_int32), ("cand_blocks_per_wg", C.c_int32 * 32)]
 
 
 _lib = None
@@ -99,7 +100,7 @@ def lib():
         L.tcm_adjoint.argtypes = [H, P, I, I, P, I]
         L.tcm_reset.argtypes = [H]
         L.tcm_autotune.argtypes = [H, I, F(Tuning)]
-        L.tcm_set_launch.argtypes = [H, I, I]
+        L.tcm_set_launch.argtypes = [H, I, I, I]
         L.tcm_stats.argtypes = [H, F(Stats)]
         L.tcm_destroy.argtypes = [H]
         L.tcm_destroy.restype = None

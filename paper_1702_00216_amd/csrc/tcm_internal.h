@@ -128,11 +128,11 @@ constexpr int POOL_COUNT_MAX_WG = 1024;
 
 // ---- launch wrappers (tcm_kernels.hip) -----------------------------------
 hipError_t launch_init_tables(const Tables& t, long long nkeys, hipStream_t s);
-// e0 / e1 (optional): events stamped by the dispatch itself at the kernel's
-// start and end (no separate event packets around it)
-hipError_t launch_block_step(const Tables& t, int grid, hipStream_t s, hipEvent_t e0 = nullptr,
-                             hipEvent_t e1 = nullptr);
-int block_step_occupancy(bool adaptive = false);   // resident 256-thread workgroups per CU
+// w: blocks per workgroup (2, 4 or 8; 64 * w threads).  e0 / e1 (optional):
+// events stamped by the dispatch itself at the kernel's start and end.
+hipError_t launch_block_step(const Tables& t, int grid, int w, hipStream_t s,
+                             hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+int block_step_occupancy(bool adaptive, int w);   // resident workgroups per CU
 hipError_t launch_plan(const Tables& t, int grid, hipStream_t s);
 hipError_t launch_advance(const Tables& t, hipStream_t s);   // step without an activation update
 hipError_t launch_pool_count(const Tables& t, int grid, hipStream_t s);   // grid >= scan_wgs

@@ -203,11 +203,12 @@ hipError_t launch_init_tables(const Tables& t, long long nkeys, hipStream_t s) {
 constexpr int TILE_COLS = 10;
 constexpr int TILE_FLOATS = TILE_COLS * TILE_COLS * BE;
 
-template <bool ADAPT>
-__global__ __launch_bounds__(256) void k_block_step(Tables t) {
+// W: blocks (waves) per workgroup, the workgroup's tile of x-adjacent blocks
+template <bool ADAPT, int W>
+__global__ __launch_bounds__(64 * W) void k_block_step(Tables t) {
     // two sets of per-wave tiles: iteration k writes set k & 1, so one
     // workgroup barrier per iteration separates writes from every read
-    __shared__ __align__(16) float lds[2][4][TILE_FLOATS];
+    __shared__ __align__(16) float lds[2][W][TILE_FLOATS];
     const DevState* st = t.st;
     if (st->error) return;
     const int n = st->step;
@@ -236,12 +237,12 @@ __global__ __launch_bounds__(256) void k_block_step(Tables t) {
     const scalar_ptr<int> rows = as_scalar((const int*)t.rows);
     const scalar_ptr<int> pin_until = as_scalar((const int*)t.pin_until);
     const scalar_ptr<float> slot_c2u = as_scalar((const float*)t.slot_c2u);
-    const int stride = per * 4;
-    // The workgroup's four waves take consecutive entries ib + wid, so the
-    // loop count is uniform over the workgroup (barriers below).  In a full
-    // tile consecutive entries are x neighbours: a wave then takes the x face
+    const int stride = per * W;
+    // The workgroup's W waves take consecutive entries ib + wid, so the loop
+    // count is uniform over the workgroup (barriers below).  In a full tile
+    // consecutive entries are x neighbours: a wave then takes the x face
     // shared with the previous / next wave's block from that wave's tile.
-    int ib = beg + jw * 4;
+    int ib = beg + jw * W;
     int r[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     int sl_prev = EMPTY, sl_next = EMPTY;
     {
@@ -250,7 +251,7 @@ __global__ __launch_bounds__(256) void k_block_step(Tables t) {
 #pragma unroll
             for (int k = 0; k < 8; k++) r[k] = rows[8 * (size_t)i + k];
             if (wid > 0) sl_prev = rows[8 * (size_t)(i - 1)];
-            if (wid < 3 && i + 1 < end) sl_next = rows[8 * (size_t)(i + 1)];
+            if (wid < W - 1 && i + 1 < end) sl_next = rows[8 * (size_t)(i + 1)];
         }
     }
     int buf = 0;
@@ -261,7 +262,7 @@ __global__ __launch_bounds__(256) void k_block_step(Tables t) {
         const int nb[6] = {r[1], r[2], r[3], r[4], r[5], r[6]};
         const int G = r[7];
         const bool share_m = have && wid > 0 && nb[0] >= 0 && nb[0] == sl_prev;
-        const bool share_p = have && wid < 3 && nb[1] >= 0 && nb[1] == sl_next;
+        const bool share_p = have && wid < W - 1 && nb[1] >= 0 && nb[1] == sl_next;
         {
             const int in = i + stride;
             sl_prev = EMPTY;
@@ -270,7 +271,7 @@ __global__ __launch_bounds__(256) void k_block_step(Tables t) {
 #pragma unroll
                 for (int k = 0; k < 8; k++) r[k] = rows[8 * (size_t)in + k];
                 if (wid > 0) sl_prev = rows[8 * (size_t)(in - 1)];
-                if (wid < 3 && in + 1 < end) sl_next = rows[8 * (size_t)(in + 1)];
+                if (wid < W - 1 && in + 1 < end) sl_next = rows[8 * (size_t)(in + 1)];
             }
         }
         float* T = lds[buf][wid];
@@ -317,7 +318,7 @@ __global__ __launch_bounds__(256) void k_block_step(Tables t) {
         float xm[8], xp[8], ym[8], yp[8];
         {
             const float* Tm = lds[buf][wid > 0 ? wid - 1 : 0];
-            const float* Tp = lds[buf][wid < 3 ? wid + 1 : 3];
+            const float* Tp = lds[buf][wid < W - 1 ? wid + 1 : W - 1];
             const float4* c_xm = (const float4*)(x == 0 && share_m ? Tm + ((y + 1) * TILE_COLS + 8) * BE
                                                                    : T + ((y + 1) * TILE_COLS + x) * BE);
             const float4* c_xp = (const float4*)(x == 7 && share_p ? Tp + ((y + 1) * TILE_COLS + 1) * BE
@@ -418,24 +419,40 @@ __global__ __launch_bounds__(256) void k_block_step(Tables t) {
         atomicMax((unsigned*)&t.st->maxbits, __float_as_uint(wave_max));   // non-negative floats order as integers
 }
 
-int block_step_occupancy(bool adaptive) {
+template <bool ADAPT>
+static int occupancy_w(int w) {
     int nb = 0;
-    hipError_t e = adaptive
-        ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_block_step<true>, 256, 0)
-        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_block_step<false>, 256, 0);
+    hipError_t e = hipErrorInvalidValue;
+    if (w == 2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_block_step<ADAPT, 2>, 128, 0);
+    if (w == 4) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_block_step<ADAPT, 4>, 256, 0);
+    if (w == 8) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_block_step<ADAPT, 8>, 512, 0);
     return e == hipSuccess ? nb : 0;
 }
 
-hipError_t launch_block_step(const Tables& t, int grid, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-    if (e0 || e1) {                 // timed launch (never inside a graph capture)
-        if (t.adaptive)
-            hipExtLaunchKernelGGL(k_block_step<true>, dim3(grid), dim3(256), 0, s, e0, e1, 0, t);
-        else
-            hipExtLaunchKernelGGL(k_block_step<false>, dim3(grid), dim3(256), 0, s, e0, e1, 0, t);
-    } else if (t.adaptive) {
-        hipLaunchKernelGGL(k_block_step<true>, dim3(grid), dim3(256), 0, s, t);
+int block_step_occupancy(bool adaptive, int w) {
+    return adaptive ? occupancy_w<true>(w) : occupancy_w<false>(w);
+}
+
+template <bool ADAPT, int W>
+static void launch_w(const Tables& t, int grid, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    void (*kern)(Tables) = k_block_step<ADAPT, W>;
+    if (e0 || e1)                   // timed launch (never inside a graph capture)
+        hipExtLaunchKernelGGL(kern, dim3(grid), dim3(64 * W), 0, s, e0, e1, 0, t);
+    else
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * W), 0, s, t);
+}
+
+hipError_t launch_block_step(const Tables& t, int grid, int w, hipStream_t s, hipEvent_t e0,
+                             hipEvent_t e1) {
+    if (w != 2 && w != 4 && w != 8) return hipErrorInvalidValue;
+    if (t.adaptive) {
+        if (w == 2) launch_w<true, 2>(t, grid, s, e0, e1);
+        if (w == 4) launch_w<true, 4>(t, grid, s, e0, e1);
+        if (w == 8) launch_w<true, 8>(t, grid, s, e0, e1);
     } else {
-        hipLaunchKernelGGL(k_block_step<false>, dim3(grid), dim3(256), 0, s, t);
+        if (w == 2) launch_w<false, 2>(t, grid, s, e0, e1);
+        if (w == 4) launch_w<false, 4>(t, grid, s, e0, e1);
+        if (w == 8) launch_w<false, 8>(t, grid, s, e0, e1);
     }
     return hipGetLastError();
 }

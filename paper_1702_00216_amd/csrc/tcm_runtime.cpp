@@ -76,6 +76,7 @@ struct tcm_handle {
     // graph replay
     hipGraphExec_t gexec = nullptr;
     int gsteps = 0;
+    int tile_w = 4;                     // blocks (waves) per stencil workgroup
     bool graph_failed = false;
 
     // timing (TCM_FLAG_TIMING)
@@ -366,10 +367,12 @@ tcm_status setup_engine(tcm_handle* h, long long word_base) {
     if (launch_init_tables(t, h->nkeys, h->stream) != hipSuccess) return dev_fail(h, hipGetLastError(), "init_tables");
     if (hipStreamSynchronize(h->stream) != hipSuccess) return dev_fail(h, hipGetLastError(), "sync");
 
-    // persistent stencil grid: exactly the resident workgroups (a larger grid
-    // would leave a tail of workgroups that start after the first wave of them)
-    const int occ = block_step_occupancy(t.adaptive != 0);
-    const int wpc = cfg->wg_per_cu > 0 ? cfg->wg_per_cu : (occ > 0 ? occ : 4);
+    // persistent stencil grid of resident workgroups (a grid beyond residency
+    // would leave a tail of workgroups that start after the first wave); by
+    // default about 12 waves per CU, the best shape measured on full lists
+    h->tile_w = cfg->blocks_per_wg > 0 ? cfg->blocks_per_wg : 4;
+    const int occ = std::max(1, block_step_occupancy(t.adaptive != 0, h->tile_w));
+    const int wpc = cfg->wg_per_cu > 0 ? cfg->wg_per_cu : std::min(occ, std::max(1, 12 / h->tile_w));
     h->grid_step = std::max(8, (h->ncu * wpc) / 8 * 8);
     // one plan thread per entry up to 4 x 256 x CUs entries; the allocator
     // fills new blocks with 2 workgroups per CU, of which the first scan_wgs
@@ -406,6 +409,8 @@ tcm_status create_common(const tcm_config* cfg, const tcm_shot* shots, int nshot
         return set_err(nullptr, TCM_E_ARG, "relative levels must satisfy 0 <= retire_rel <= trigger_rel");
     if (cfg->trigger_interval < 0 || cfg->trigger_interval > BE)
         return set_err(nullptr, TCM_E_ARG, "trigger_interval must be in [0, 8] (0 and 1: every step)");
+    if (cfg->blocks_per_wg != 0 && cfg->blocks_per_wg != 2 && cfg->blocks_per_wg != 4 && cfg->blocks_per_wg != 8)
+        return set_err(nullptr, TCM_E_ARG, "blocks_per_wg must be 0, 2, 4 or 8");
     if (cfg->device_pool && cfg->pool_bytes < SLOT_BYTES)
         return set_err(nullptr, TCM_E_ARG, "a caller device_pool needs its size in pool_bytes");
     if (cfg->engine == TCM_ENGINE_DENSE && nshots != 1)
@@ -486,7 +491,7 @@ hipError_t enqueue_step(tcm_handle* h, hipEvent_t e0, hipEvent_t e1) {
     hipError_t e;
     const long long n = h->hstep++;
     const int k = h->t.interval > 1 ? h->t.interval : 1;
-    if ((e = launch_block_step(h->t, h->grid_step, h->stream, e0, e1)) != hipSuccess) return e;
+    if ((e = launch_block_step(h->t, h->grid_step, h->tile_w, h->stream, e0, e1)) != hipSuccess) return e;
     if ((n + 1) % k != 0) return launch_advance(h->t, h->stream);
     if ((e = launch_plan(h->t, h->grid_plan, h->stream)) != hipSuccess) return e;
     if ((e = launch_pool_count(h->t, h->grid_pool, h->stream)) != hipSuccess) return e;
@@ -1232,55 +1237,68 @@ tcm_status tcm_autotune(tcm_handle* h, int32_t probe_steps, tcm_tuning* out) {
     char* snap = nullptr;
     st = ck_save(h, &snap);
     if (st) return st;
-    const int occ = std::max(1, block_step_occupancy(h->t.adaptive != 0));
-    std::vector<int> wpcs;
-    for (int v : {1, 2, 3, 4, 6, 8})
-        if (v <= occ) wpcs.push_back(v);
-    if (std::find(wpcs.begin(), wpcs.end(), occ) == wpcs.end()) wpcs.push_back(occ);
-    const int gss[] = {8, 16, 32};
-    const int keep_grid = h->grid_step, keep_gs = h->gsteps, keep_flags = h->cfg.flags;
+    const int keep_grid = h->grid_step, keep_gs = h->gsteps, keep_w = h->tile_w, keep_flags = h->cfg.flags;
     h->cfg.flags &= ~TCM_FLAG_TIMING;
     hipEvent_t e0, e1;
     HIP_OR_FAIL(h, hipEventCreate(&e0));
     HIP_OR_FAIL(h, hipEventCreate(&e1));
     tcm_tuning res{};
     res.ms_per_step = 1e300;
-    int best_grid = keep_grid, best_gs = keep_gs;
-    for (int wpc : wpcs) {
-        for (int gs : gss) {
-            if (res.ncand >= 32) break;
-            h->grid_step = std::max(8, (h->ncu * wpc) / 8 * 8);
-            h->gsteps = round_graph_steps(h, gs);
-            drop_graph(h);
-            // one untimed graph launch so capture/instantiation is not timed
-            const long long step0 = h->h_state->step;
-            st = ck_restore(h, snap);
-            h->hstep = step0;
-            if (!st) st = issue_steps(h, std::min(gs, probe_steps));
-            if (!st) st = ck_restore(h, snap);
-            h->hstep = step0;
-            if (st) break;
-            HIP_OR_FAIL(h, hipEventRecord(e0, h->stream));
-            st = issue_steps(h, probe_steps);
-            if (st) break;
-            HIP_OR_FAIL(h, hipEventRecord(e1, h->stream));
-            HIP_OR_FAIL(h, hipEventSynchronize(e1));
-            float ms = 0.f;
-            HIP_OR_FAIL(h, hipEventElapsedTime(&ms, e0, e1));
-            const double per = ms / probe_steps;
+    int best_grid = keep_grid, best_gs = keep_gs, best_w = keep_w;
+
+    // time probe_steps steps of one shape from the saved state
+    auto probe = [&](int w, int wpc, int gs) -> tcm_status {
+        h->tile_w = w;
+        h->grid_step = std::max(8, (h->ncu * wpc) / 8 * 8);
+        h->gsteps = round_graph_steps(h, gs);
+        drop_graph(h);
+        // one untimed graph launch so capture/instantiation is not timed
+        const long long step0 = h->h_state->step;
+        tcm_status s = ck_restore(h, snap);
+        h->hstep = step0;
+        if (!s) s = issue_steps(h, std::min(gs, probe_steps));
+        if (!s) s = ck_restore(h, snap);
+        h->hstep = step0;
+        if (s) return s;
+        HIP_OR_FAIL(h, hipEventRecord(e0, h->stream));
+        s = issue_steps(h, probe_steps);
+        if (s) return s;
+        HIP_OR_FAIL(h, hipEventRecord(e1, h->stream));
+        HIP_OR_FAIL(h, hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIP_OR_FAIL(h, hipEventElapsedTime(&ms, e0, e1));
+        const double per = ms / probe_steps;
+        if (res.ncand < 32) {
+            res.cand_blocks_per_wg[res.ncand] = w;
             res.cand_wg_per_cu[res.ncand] = wpc;
             res.cand_graph_steps[res.ncand] = h->gsteps;
             res.cand_ms_per_step[res.ncand] = per;
             res.ncand++;
-            if (per < res.ms_per_step) {
-                res.ms_per_step = per;
-                res.wg_per_cu = wpc;
-                res.graph_steps = h->gsteps;
-                best_grid = h->grid_step;
-                best_gs = h->gsteps;
-            }
         }
-        if (st) break;
+        if (per < res.ms_per_step) {
+            res.ms_per_step = per;
+            res.blocks_per_wg = w;
+            res.wg_per_cu = wpc;
+            res.graph_steps = h->gsteps;
+            best_grid = h->grid_step;
+            best_gs = h->gsteps;
+            best_w = w;
+        }
+        return TCM_OK;
+    };
+    // the workgroup tile (2, 4 or 8 x-adjacent blocks) x workgroups per CU,
+    // 4 to 24 waves per CU, at 16 steps per graph; then the graph length
+    for (int w : {2, 4, 8}) {
+        const int occ = std::max(1, block_step_occupancy(h->t.adaptive != 0, w));
+        for (int wpc : {1, 2, 3, 4, 6, 8, 12}) {
+            if (st || wpc > occ || w * wpc < 4 || w * wpc > 24) continue;
+            st = probe(w, wpc, 16);
+        }
+    }
+    const int bw = res.blocks_per_wg, bwpc = res.wg_per_cu;
+    for (int gs : {8, 32}) {
+        if (st || bw == 0) break;
+        st = probe(bw, bwpc, gs);
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -1291,24 +1309,29 @@ tcm_status tcm_autotune(tcm_handle* h, int32_t probe_steps, tcm_tuning* out) {
     if (st || rs) {
         h->grid_step = keep_grid;
         h->gsteps = keep_gs;
+        h->tile_w = keep_w;
         return st ? st : rs;
     }
     h->grid_step = best_grid;
     h->gsteps = best_gs;
+    h->tile_w = best_w;
     st = sync_state(h);
     if (st) return st;
     if (out) *out = res;
     return TCM_OK;
 }
 
-tcm_status tcm_set_launch(tcm_handle* h, int32_t wg_per_cu, int32_t graph_steps) {
+tcm_status tcm_set_launch(tcm_handle* h, int32_t wg_per_cu, int32_t graph_steps, int32_t blocks_per_wg) {
     tcm_status st = check_live(h);
     if (st) return st;
     if (h->engine != TCM_ENGINE_BLOCKS) return set_err(h, TCM_E_STATE, "launch shape applies to the block engine");
-    const int occ = std::max(1, block_step_occupancy(h->t.adaptive != 0));
+    const int w = blocks_per_wg > 0 ? blocks_per_wg : h->tile_w;
+    if (w != 2 && w != 4 && w != 8) return set_err(h, TCM_E_ARG, "blocks_per_wg must be 0, 2, 4 or 8");
+    const int occ = std::max(1, block_step_occupancy(h->t.adaptive != 0, w));
     if (wg_per_cu < 1 || wg_per_cu > occ || graph_steps < 1)
         return set_err(h, TCM_E_ARG, fmt("launch shape needs 1 <= wg_per_cu <= %d and graph_steps >= 1", occ));
     HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+    h->tile_w = w;
     h->grid_step = std::max(8, (h->ncu * wg_per_cu) / 8 * 8);
     h->gsteps = round_graph_steps(h, graph_steps);
     drop_graph(h);

@@ -62,7 +62,7 @@ class Simulation:
                  checkpoint_every: int = 0, graph_steps: int = 0, wg_per_cu: int = 0,
                  device_pool=None, uniform_c2: bool = True, shutdown_steps: int = 0,
                  shutdown_alpha: float = 1.0, trigger_rel: float = 0.0, retire_rel: float = 0.0,
-                 trigger_interval: int = 1):
+                 trigger_interval: int = 1, blocks_per_wg: int = 0):
         lib = L.lib()
         cfg = L.Config()
         cfg.dx, cfg.dt = float(dx), float(dt)
@@ -79,6 +79,7 @@ class Simulation:
         cfg.trigger_rel = float(trigger_rel)
         cfg.retire_rel = float(retire_rel)
         cfg.trigger_interval = int(trigger_interval)
+        cfg.blocks_per_wg = int(blocks_per_wg)
         self._pool_tensor = device_pool
         if device_pool is not None:
             cfg.device_pool = device_pool.data_ptr()
@@ -195,39 +196,42 @@ class Simulation:
 
     def autotune(self, probe_steps: int = 32, cache: Optional[str] = None,
                  key: Optional[str] = None) -> dict:
-        """Pick the launch shape (stencil workgroups per CU, steps per graph)
-        by timing probe_steps steps from the current state for each candidate;
-        the state is unchanged.  With ``cache`` (a JSON file) and ``key``, a
-        stored choice is applied without probing and new choices are stored."""
+        """Pick the launch shape (stencil workgroup tile of 2, 4 or 8 blocks,
+        workgroups per CU, steps per graph) by timing probe_steps steps from
+        the current state for each candidate; the state is unchanged.  With
+        ``cache`` (a JSON file) and ``key``, a stored choice is applied
+        without probing and new choices are stored."""
         import json
         import os
         if cache and key and os.path.exists(cache):
             with open(cache) as f:
                 stored = json.load(f).get(key)
-            if stored:
-                self._apply_tuning(stored["wg_per_cu"], stored["graph_steps"])
+            if stored and "blocks_per_wg" in stored:
+                self._apply_tuning(stored["wg_per_cu"], stored["graph_steps"], stored["blocks_per_wg"])
                 return dict(stored, cached=True)
         t = L.Tuning()
         self._check(L.lib().tcm_autotune(self._h, int(probe_steps), C.byref(t)))
-        res = {"wg_per_cu": t.wg_per_cu, "graph_steps": t.graph_steps,
-               "ms_per_step": t.ms_per_step, "cached": False,
-               "candidates": [(t.cand_wg_per_cu[i], t.cand_graph_steps[i], t.cand_ms_per_step[i])
-                              for i in range(t.ncand)]}
+        res = {"blocks_per_wg": t.blocks_per_wg, "wg_per_cu": t.wg_per_cu,
+               "graph_steps": t.graph_steps, "ms_per_step": t.ms_per_step, "cached": False,
+               "candidates": [(t.cand_blocks_per_wg[i], t.cand_wg_per_cu[i], t.cand_graph_steps[i],
+                               t.cand_ms_per_step[i]) for i in range(t.ncand)]}
         if cache and key:
             data = {}
             if os.path.exists(cache):
                 with open(cache) as f:
                     data = json.load(f)
-            data[key] = {k: res[k] for k in ("wg_per_cu", "graph_steps", "ms_per_step")}
+            data[key] = {k: res[k] for k in ("blocks_per_wg", "wg_per_cu", "graph_steps", "ms_per_step")}
             with open(cache, "w") as f:
                 json.dump(data, f, indent=1)
         return res
 
-    def _apply_tuning(self, wg_per_cu: int, graph_steps: int):
-        self._check(L.lib().tcm_set_launch(self._h, int(wg_per_cu), int(graph_steps)))
+    def _apply_tuning(self, wg_per_cu: int, graph_steps: int, blocks_per_wg: int = 0):
+        self._check(L.lib().tcm_set_launch(self._h, int(wg_per_cu), int(graph_steps), int(blocks_per_wg)))
 
-    def set_launch(self, wg_per_cu: int, graph_steps: int):
-        self._apply_tuning(wg_per_cu, graph_steps)
+    def set_launch(self, wg_per_cu: int, graph_steps: int, blocks_per_wg: int = 0):
+        """Launch shape: workgroups per CU, steps per graph, workgroup tile
+        (2, 4 or 8 blocks; 0 keeps the current one)."""
+        self._apply_tuning(wg_per_cu, graph_steps, blocks_per_wg)
 
     def reset(self):
         self._check(L.lib().tcm_reset(self._h))

@@ -70,6 +70,16 @@ def test_bad_thresholds_rejected():
     assert _create((4, 4, 4), c, 0.5, dx=0.0)[0] == L.TCM_E_ARG
 
 
+def test_bad_configuration_rejected():
+    c = np.ones((4, 4, 4), np.float32)
+    assert _create((4, 4, 4), c, 0.5, blocks_per_wg=3)[0] == L.TCM_E_ARG
+    assert _create((4, 4, 4), c, 0.5, trigger_interval=9)[0] == L.TCM_E_ARG
+    assert _create((4, 4, 4), c, 0.5, shutdown_steps=300, shutdown_alpha=0.5)[0] == L.TCM_E_ARG
+    assert _create((4, 4, 4), c, 0.5, trigger_rel=1e-4, retire_rel=1e-3)[0] == L.TCM_E_ARG
+    rc, msg = _create((4, 4, 4), c, 0.5, device_pool=1234)
+    assert rc == L.TCM_E_ARG and "pool_bytes" in msg
+
+
 def test_lattice_media_validated():
     cfg = L.Config()
     cfg.nx = cfg.ny = cfg.nz = 64

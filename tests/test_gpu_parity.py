@@ -275,6 +275,31 @@ def test_launch_modes_and_reads_agree():
     assert values_equal(a.read(0), phi)
 
 
+@pytest.mark.parametrize("tile", [2, 4, 8])
+def test_workgroup_tiles_agree_with_oracle(tile):
+    """Every stencil workgroup tile (2, 4 or 8 x-adjacent blocks sharing x
+    faces through LDS), with a few workgroups per CU so that waves of one
+    workgroup meet ragged list ends, equals the CPU TCM at a threshold and
+    the dense oracle at threshold 0 (random media, ragged grid)."""
+    announce(f"workgroup tile {tile}")
+    shape = (45, 38, 27)
+    c = ti.random_media(shape, seed=31, cmin=0.3, cmax=1.0)
+    src = [((20, 17, 11), ti.ricker(0.12, 0.5).w32), ((44, 0, 26), ti.ricker(0.2, 0.5).w32)]
+    phi, prev, _ = oracle.dense_run(c, 0.5, 1.0, 110, np.float32, sources=src)
+    for wpc in (1, 3):
+        sim = gpu_run(shape, 0.5, c, src, 110, blocks_per_wg=tile, wg_per_cu=wpc)
+        assert values_equal(sim.read(0), phi) and values_equal(sim.read(1), prev)
+    lev = np.float32(3e-4)
+    t = oracle.TCM(c, 0.5, 1.0, lev, np.float32(5e-5))
+    for xyz, w in src:
+        t.add_source(xyz, w)
+    assert t.step(110) == 0
+    sim = gpu_run(shape, 0.5, c, src, 110, lev, np.float32(5e-5), blocks_per_wg=tile, timing=True)
+    assert values_equal(sim.read(0), t.read(0))
+    g, o = sim.stats(), t.stats()
+    assert g["cell_updates"] == o["updates"] and g["activations"] == o["activations"]
+
+
 def test_source_added_mid_run():
     announce("source added after 30 steps")
     w = ti.c1(steps=80)
