@@ -300,7 +300,8 @@ def bench_c5(args, tcm):
         resid = np.load(p)
     else:
         resid = np.random.default_rng(55).standard_normal((steps, len(w.receivers))).astype(np.float32)
-    sim = tcm.Simulation(w.shape, w.dx, w.dt, c, checkpoint_every=50, wg_per_cu=args.wg_per_cu)
+    sim = tcm.Simulation(w.shape, w.dx, w.dt, c, checkpoint_every=50, wg_per_cu=args.wg_per_cu,
+                         blocks_per_wg=args.blocks_per_wg)
 
     def run():
         sim.reset()
@@ -318,6 +319,18 @@ def bench_c5(args, tcm):
     for i in range(args.warmup):
         f, a, _ = run()
         log(f"c5 warmup {i}: forward {f:.3f} s, adjoint {a:.3f} s")
+    tuning = None
+    if not args.no_autotune and not args.wg_per_cu:
+        # launch shape tuned on the final forward state (the adjoint sweep
+        # steps full lists); the adjoint field and the recomputation use it
+        sim.reset()
+        sim.add_source(w.source, w.wavelet.w32)
+        sim.set_receivers(w.receivers)
+        sim.step(steps)
+        tuning = sim.autotune(probe_steps=32, cache=os.environ.get("TCM_TUNE_CACHE"), key="gfx950/c5")
+        tuning.pop("candidates", None)
+        log(f"c5 autotune: tile {tuning['blocks_per_wg']} blocks, wg_per_cu {tuning['wg_per_cu']}, "
+            f"graph_steps {tuning['graph_steps']}")
     tf, ta = 0.0, 0.0
     for i in range(args.steps):
         f, a, g = run()
@@ -354,7 +367,7 @@ def bench_c5(args, tcm):
                       "time_steps_per_run": steps},
            "roofline": None, "cpu_baseline": cpu,
            "adjoint": {"forward_s": round(tf / args.steps, 4), "adjoint_s": round(ta / args.steps, 4),
-                       "adjoint_over_forward": round(ta / tf, 3)}}
+                       "adjoint_over_forward": round(ta / tf, 3)}, "autotune": tuning}
     print(json.dumps(out), flush=True)
 
 

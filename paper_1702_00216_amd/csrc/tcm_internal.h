@@ -163,7 +163,8 @@ hipError_t launch_read_dense(const float* f, int nx, int ny, int x0, int y0, int
 // adjoint support
 hipError_t launch_receiver_c2(const Shot* shots, const int* xyz, const int* rshot, int nrec,
                               double dt, double dx, float* out, hipStream_t s);
-hipError_t launch_adjoint_grad(const Tables& mu, int grid, const float* u, double* g, hipStream_t s);
+hipError_t launch_adjoint_grad(const Tables& mu, const Shot& shot, const float* u, double* g,
+                               hipStream_t s);
 hipError_t launch_grad_finish(const Shot& shot, const Shot* dshot, const double* g, float* out,
                               hipStream_t s);
 

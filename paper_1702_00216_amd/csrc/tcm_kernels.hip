@@ -1254,39 +1254,40 @@ hipError_t launch_receiver_c2(const Shot* shots, const int* xyz, const int* rsho
 // g += mu^m * (L u^{m-1}) over the blocks where the adjoint field is active
 // (mu is zero elsewhere).  mu: current level of the adjoint tables; u: the
 // forward level as a dense grid of shot 0; L with zero ghosts, in FP64.
+// g += mu^m (L u^{m-1}) at every node of a block active in the adjoint field
+// (mu is zero elsewhere).  One thread per node along x-fastest rows, so the
+// dense u snapshot and the FP64 accumulator are read and written in full
+// rows; mu comes from the adjoint pool through the block table.
 __global__ __launch_bounds__(256) void k_adjoint_grad(Tables mu, const float* __restrict__ u,
                                                        double* __restrict__ g) {
     const DevState* st = mu.st;
-    const int nact = st->n_act;
     const int plane = st->step & 1;
     const Shot& S = mu.shots[0];
-    const int lane = lane_id();
-    const int x = lane & 7, y = lane >> 3;
+    const int gx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gx >= S.nx) return;
     const size_t sy = (size_t)S.nx, sz = (size_t)S.nx * S.ny;
-    const int nwaves = gridDim.x * (blockDim.x >> 6);
-    for (int i = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); i < nact; i += nwaves) {
-        const int slot = mu.act_slot[i];
-        int bx, by, bz;
-        key_to_block(S, mu.act_key[i], bx, by, bz);
-        const int gx = bx * BE + x, gy = by * BE + y;
-        if (gx >= S.nx || gy >= S.ny) continue;
-        const float* m = mu.pool + (size_t)slot * SLOT + plane * BV;
-        for (int z = 0; z < BE; z++) {
-            const int gz = bz * BE + z;
-            if (gz >= S.nz) break;
-            const size_t idx = (size_t)gz * sz + (size_t)gy * sy + (size_t)gx;
-            const double c = u[idx];
-            const double xm = gx > 0 ? u[idx - 1] : 0.0, xp = gx + 1 < S.nx ? u[idx + 1] : 0.0;
-            const double ym = gy > 0 ? u[idx - sy] : 0.0, yp = gy + 1 < S.ny ? u[idx + sy] : 0.0;
-            const double zm = gz > 0 ? u[idx - sz] : 0.0, zp = gz + 1 < S.nz ? u[idx + sz] : 0.0;
-            const double lap = (((xp + xm) + (yp + ym)) + (zp + zm)) - 6.0 * c;
-            g[idx] += (double)m[z * 64 + lane] * lap;
-        }
+    const long long rows = (long long)S.ny * S.nz;
+    for (long long row = blockIdx.y; row < rows; row += gridDim.y) {
+        const int gy = (int)(row % S.ny), gz = (int)(row / S.ny);
+        const long long key = S.key_base + (long long)block_to_key(S, gx >> 3, gy >> 3, gz >> 3);
+        const int slot = mu.cell2box[key];
+        if (slot < 0) continue;
+        const float m = mu.pool[(size_t)slot * SLOT + plane * BV + ((gz & 7) * 8 + (gy & 7)) * 8 + (gx & 7)];
+        const size_t idx = (size_t)row * sy + (size_t)gx;
+        const double c = u[idx];
+        const double xm = gx > 0 ? u[idx - 1] : 0.0, xp = gx + 1 < S.nx ? u[idx + 1] : 0.0;
+        const double ym = gy > 0 ? u[idx - sy] : 0.0, yp = gy + 1 < S.ny ? u[idx + sy] : 0.0;
+        const double zm = gz > 0 ? u[idx - sz] : 0.0, zp = gz + 1 < S.nz ? u[idx + sz] : 0.0;
+        const double lap = (((xp + xm) + (yp + ym)) + (zp + zm)) - 6.0 * c;
+        g[idx] += (double)m * lap;
     }
 }
 
-hipError_t launch_adjoint_grad(const Tables& mu, int grid, const float* u, double* g, hipStream_t s) {
-    hipLaunchKernelGGL(k_adjoint_grad, dim3(grid), dim3(256), 0, s, mu, u, g);
+hipError_t launch_adjoint_grad(const Tables& mu, const Shot& shot, const float* u, double* g,
+                               hipStream_t s) {
+    const long long rows = (long long)shot.ny * shot.nz;
+    dim3 grid((unsigned)((shot.nx + 255) / 256), (unsigned)std::min<long long>(rows, 65535));
+    hipLaunchKernelGGL(k_adjoint_grad, grid, dim3(256), 0, s, mu, u, g);
     return hipGetLastError();
 }
 

@@ -1153,6 +1153,11 @@ tcm_status tcm_adjoint(tcm_handle* h, const float* resid, int32_t nt, int32_t re
     st = tcm_reset(a);
     if (st) return set_err(h, st, std::string("adjoint tables: ") + a->err);
     a->hstep = 0;
+    // the adjoint field runs at full occupancy (measured best for the sweep,
+    // whose lists start at the receivers); the recomputation keeps the forward
+    // handle's launch shape
+    a->tile_w = 4;
+    a->grid_step = std::max(8, (a->ncu * std::max(1, block_step_occupancy(a->t.adaptive != 0, 4))) / 8 * 8);
     {
         // adjoint step k (k = 0..nt-1) produces mu^{nt-k}; its source sample at
         // receiver r is C2_r * resid[nt-1-k][r]
@@ -1184,7 +1189,6 @@ tcm_status tcm_adjoint(tcm_handle* h, const float* resid, int32_t nt, int32_t re
     }
     h->in_adjoint = true;
     hipError_t e = hipMemsetAsync(g, 0, sizeof(double) * N, h->stream);
-    const int ggrid = h->ncu * 4;
     for (int j = nseg - 1; j >= 0 && e == hipSuccess; j--) {
         const int s0 = j * K, end = std::min(s0 + K, nt);
         st = ck_restore(h, h->ckpts[j].buf);
@@ -1199,7 +1203,7 @@ tcm_status tcm_adjoint(tcm_handle* h, const float* resid, int32_t nt, int32_t re
         // adjoint levels mu^{end} .. mu^{s0+1}, each with L u^{m-1}
         for (int m = end; m > s0 && e == hipSuccess; m--) {
             e = enqueue_step(a, nullptr, nullptr);
-            if (e == hipSuccess) e = launch_adjoint_grad(a->t, ggrid, lvl + (size_t)(m - 1 - s0) * N, g, h->stream);
+            if (e == hipSuccess) e = launch_adjoint_grad(a->t, S, lvl + (size_t)(m - 1 - s0) * N, g, h->stream);
         }
     }
     if (e != hipSuccess) { cleanup(); return dev_fail(h, e, "adjoint sweep"); }
