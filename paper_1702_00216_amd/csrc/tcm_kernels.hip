@@ -1094,33 +1094,48 @@ hipError_t launch_activate(const Tables& t, long long key, int shot, unsigned lo
 // --------------------------------------------------------------------------
 // read: gather a box of phi^n / phi^{n-1} (inactive nodes -> 0)
 // --------------------------------------------------------------------------
+// One thread per node of a box row (x fastest); each thread takes RB rows at
+// a time, issuing all their block-table loads, then all pool loads, then the
+// stores, so the dependent loads of different rows overlap.
+constexpr int READ_RB = 8;
+
 __global__ void k_read(Tables t, int shot, int which, int x0, int y0, int z0, int sx, int sy,
-                       int sz, float* out) {
-    const long long total = (long long)sx * sy * sz;
-    const long long gs = (long long)gridDim.x * blockDim.x;
+                       int sz, float* __restrict__ out) {
+    const int lx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (lx >= sx) return;
     const int plane = which == 0 ? (t.st->step & 1) : 1 - (t.st->step & 1);
     const Shot& S = t.shots[shot];
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gs) {
-        const int lx = (int)(i % sx);
-        const long long r = i / sx;
-        const int ly = (int)(r % sy), lz = (int)(r / sy);
-        const int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
-        const int bx = gx >> 3, by = gy >> 3, bz = gz >> 3;
-        const long long G = S.key_base + (long long)block_to_key(S, bx, by, bz);
-        const int s = t.cell2box[G];
-        out[i] = s >= 0 ? t.pool[(size_t)s * SLOT + plane * BV + ((gz & 7) * 8 + (gy & 7)) * 8 + (gx & 7)]
-                        : 0.f;
+    const int gx = x0 + lx;
+    const long long rows = (long long)sy * sz;
+    for (long long r0 = (long long)blockIdx.y * READ_RB; r0 < rows; r0 += (long long)gridDim.y * READ_RB) {
+        int slot[READ_RB], loc[READ_RB];
+#pragma unroll
+        for (int k = 0; k < READ_RB; k++) {
+            slot[k] = EMPTY;
+            loc[k] = 0;
+            const long long row = r0 + k;
+            if (row < rows) {
+                const int gy = y0 + (int)(row % sy), gz = z0 + (int)(row / sy);
+                slot[k] = t.cell2box[S.key_base + (long long)block_to_key(S, gx >> 3, gy >> 3, gz >> 3)];
+                loc[k] = ((gz & 7) * 8 + (gy & 7)) * 8 + (gx & 7);
+            }
+        }
+        float v[READ_RB];
+#pragma unroll
+        for (int k = 0; k < READ_RB; k++)
+            v[k] = slot[k] >= 0 ? t.pool[(size_t)slot[k] * SLOT + plane * BV + loc[k]] : 0.f;
+#pragma unroll
+        for (int k = 0; k < READ_RB; k++)
+            if (r0 + k < rows) out[(size_t)(r0 + k) * sx + lx] = v[k];
     }
 }
 
 hipError_t launch_read(const Tables& t, int shot, int which, int x0, int y0, int z0, int sx, int sy,
                        int sz, float* out, hipStream_t s) {
-    const long long total = (long long)sx * sy * sz;
-    long long grid = (total + 255) / 256;
-    if (grid > 16384) grid = 16384;
-    if (grid < 1) grid = 1;
-    hipLaunchKernelGGL(k_read, dim3((unsigned)grid), dim3(256), 0, s, t, shot, which, x0, y0, z0,
-                       sx, sy, sz, out);
+    if (sx <= 0 || sy <= 0 || sz <= 0) return hipSuccess;
+    const long long groups = ((long long)sy * sz + READ_RB - 1) / READ_RB;
+    dim3 grid((unsigned)((sx + 255) / 256), (unsigned)std::min<long long>(groups, 65535));
+    hipLaunchKernelGGL(k_read, grid, dim3(256), 0, s, t, shot, which, x0, y0, z0, sx, sy, sz, out);
     return hipGetLastError();
 }
 
@@ -1254,12 +1269,17 @@ hipError_t launch_receiver_c2(const Shot* shots, const int* xyz, const int* rsho
 // g += mu^m * (L u^{m-1}) over the blocks where the adjoint field is active
 // (mu is zero elsewhere).  mu: current level of the adjoint tables; u: the
 // forward level as a dense grid of shot 0; L with zero ghosts, in FP64.
-// g += mu^m (L u^{m-1}) at every node of a block active in the adjoint field
-// (mu is zero elsewhere).  One thread per node along x-fastest rows, so the
-// dense u snapshot and the FP64 accumulator are read and written in full
-// rows; mu comes from the adjoint pool through the block table.
+// gs += mu^m (L u^{m-1}) at every node of a block active in the adjoint field
+// (mu is zero elsewhere); the product is formed in FP64 and summed in FP32
+// over a group of adjoint steps, then folded into the FP64 gradient
+// (k_grad_flush).  One thread per node along x-fastest rows, GB rows at a
+// time (block-table loads, then mu, u and gs loads, then the updates), so the
+// dense u snapshot and the accumulator move in full rows; mu comes from the
+// adjoint pool through the block table.
+constexpr int GRAD_RB = 4;
+
 __global__ __launch_bounds__(256) void k_adjoint_grad(Tables mu, const float* __restrict__ u,
-                                                       double* __restrict__ g) {
+                                                       float* __restrict__ gs) {
     const DevState* st = mu.st;
     const int plane = st->step & 1;
     const Shot& S = mu.shots[0];
@@ -1267,27 +1287,66 @@ __global__ __launch_bounds__(256) void k_adjoint_grad(Tables mu, const float* __
     if (gx >= S.nx) return;
     const size_t sy = (size_t)S.nx, sz = (size_t)S.nx * S.ny;
     const long long rows = (long long)S.ny * S.nz;
-    for (long long row = blockIdx.y; row < rows; row += gridDim.y) {
-        const int gy = (int)(row % S.ny), gz = (int)(row / S.ny);
-        const long long key = S.key_base + (long long)block_to_key(S, gx >> 3, gy >> 3, gz >> 3);
-        const int slot = mu.cell2box[key];
-        if (slot < 0) continue;
-        const float m = mu.pool[(size_t)slot * SLOT + plane * BV + ((gz & 7) * 8 + (gy & 7)) * 8 + (gx & 7)];
-        const size_t idx = (size_t)row * sy + (size_t)gx;
-        const double c = u[idx];
-        const double xm = gx > 0 ? u[idx - 1] : 0.0, xp = gx + 1 < S.nx ? u[idx + 1] : 0.0;
-        const double ym = gy > 0 ? u[idx - sy] : 0.0, yp = gy + 1 < S.ny ? u[idx + sy] : 0.0;
-        const double zm = gz > 0 ? u[idx - sz] : 0.0, zp = gz + 1 < S.nz ? u[idx + sz] : 0.0;
-        const double lap = (((xp + xm) + (yp + ym)) + (zp + zm)) - 6.0 * c;
-        g[idx] += (double)m * lap;
+    for (long long r0 = (long long)blockIdx.y * GRAD_RB; r0 < rows; r0 += (long long)gridDim.y * GRAD_RB) {
+        int slot[GRAD_RB], gyk[GRAD_RB], gzk[GRAD_RB];
+#pragma unroll
+        for (int k = 0; k < GRAD_RB; k++) {
+            const long long row = r0 + k;
+            slot[k] = EMPTY;
+            gyk[k] = 0;
+            gzk[k] = 0;
+            if (row < rows) {
+                gyk[k] = (int)(row % S.ny);
+                gzk[k] = (int)(row / S.ny);
+                slot[k] = mu.cell2box[S.key_base + (long long)block_to_key(S, gx >> 3, gyk[k] >> 3, gzk[k] >> 3)];
+            }
+        }
+        float m[GRAD_RB], acc[GRAD_RB];
+        double lap[GRAD_RB];
+#pragma unroll
+        for (int k = 0; k < GRAD_RB; k++) {
+            m[k] = 0.f;
+            acc[k] = 0.f;
+            lap[k] = 0.0;
+            if (slot[k] < 0) continue;
+            const int gy = gyk[k], gz = gzk[k];
+            m[k] = mu.pool[(size_t)slot[k] * SLOT + plane * BV + ((gz & 7) * 8 + (gy & 7)) * 8 + (gx & 7)];
+            const size_t idx = (size_t)(r0 + k) * sy + (size_t)gx;
+            const double c = u[idx];
+            const double xm = gx > 0 ? u[idx - 1] : 0.0, xp = gx + 1 < S.nx ? u[idx + 1] : 0.0;
+            const double ym = gy > 0 ? u[idx - sy] : 0.0, yp = gy + 1 < S.ny ? u[idx + sy] : 0.0;
+            const double zm = gz > 0 ? u[idx - sz] : 0.0, zp = gz + 1 < S.nz ? u[idx + sz] : 0.0;
+            lap[k] = (((xp + xm) + (yp + ym)) + (zp + zm)) - 6.0 * c;
+            acc[k] = gs[idx];
+        }
+#pragma unroll
+        for (int k = 0; k < GRAD_RB; k++)
+            if (slot[k] >= 0) gs[(size_t)(r0 + k) * sy + (size_t)gx] = acc[k] + (float)((double)m[k] * lap[k]);
     }
 }
 
-hipError_t launch_adjoint_grad(const Tables& mu, const Shot& shot, const float* u, double* g,
+hipError_t launch_adjoint_grad(const Tables& mu, const Shot& shot, const float* u, float* gs,
                                hipStream_t s) {
-    const long long rows = (long long)shot.ny * shot.nz;
-    dim3 grid((unsigned)((shot.nx + 255) / 256), (unsigned)std::min<long long>(rows, 65535));
-    hipLaunchKernelGGL(k_adjoint_grad, grid, dim3(256), 0, s, mu, u, g);
+    const long long groups = ((long long)shot.ny * shot.nz + GRAD_RB - 1) / GRAD_RB;
+    dim3 grid((unsigned)((shot.nx + 255) / 256), (unsigned)std::min<long long>(groups, 65535));
+    hipLaunchKernelGGL(k_adjoint_grad, grid, dim3(256), 0, s, mu, u, gs);
+    return hipGetLastError();
+}
+
+// g += gs, gs = 0 (end of a group of adjoint steps)
+__global__ void k_grad_flush(double* __restrict__ g, float* __restrict__ gs, long long n) {
+    const long long st = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += st) {
+        g[i] += (double)gs[i];
+        gs[i] = 0.f;
+    }
+}
+
+hipError_t launch_grad_flush(double* g, float* gs, long long n, hipStream_t s) {
+    long long grid = (n + 255) / 256;
+    if (grid > 65536) grid = 65536;
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL(k_grad_flush, dim3((unsigned)grid), dim3(256), 0, s, g, gs, n);
     return hipGetLastError();
 }
 

@@ -1175,20 +1175,24 @@ tcm_status tcm_adjoint(tcm_handle* h, const float* resid, int32_t nt, int32_t re
     if (st) return st;
     float* lvl = nullptr;
     double* g = nullptr;
+    float* gs = nullptr;
     auto cleanup = [&]() {
         if (lvl) (void)hipFree(lvl);
         if (g) (void)hipFree(g);
+        if (gs) (void)hipFree(gs);
         if (now) (void)hipFree(now);
         h->in_adjoint = false;
     };
     if (hipMalloc((void**)&lvl, sizeof(float) * N * (size_t)K) != hipSuccess ||
-        hipMalloc((void**)&g, sizeof(double) * N) != hipSuccess) {
+        hipMalloc((void**)&g, sizeof(double) * N) != hipSuccess ||
+        hipMalloc((void**)&gs, sizeof(float) * N) != hipSuccess) {
         (void)hipGetLastError();
         cleanup();
         return set_err(h, TCM_E_NOMEM, "no device memory for the adjoint level buffers");
     }
     h->in_adjoint = true;
     hipError_t e = hipMemsetAsync(g, 0, sizeof(double) * N, h->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(gs, 0, sizeof(float) * N, h->stream);
     for (int j = nseg - 1; j >= 0 && e == hipSuccess; j--) {
         const int s0 = j * K, end = std::min(s0 + K, nt);
         st = ck_restore(h, h->ckpts[j].buf);
@@ -1203,7 +1207,8 @@ tcm_status tcm_adjoint(tcm_handle* h, const float* resid, int32_t nt, int32_t re
         // adjoint levels mu^{end} .. mu^{s0+1}, each with L u^{m-1}
         for (int m = end; m > s0 && e == hipSuccess; m--) {
             e = enqueue_step(a, nullptr, nullptr);
-            if (e == hipSuccess) e = launch_adjoint_grad(a->t, S, lvl + (size_t)(m - 1 - s0) * N, g, h->stream);
+            if (e == hipSuccess) e = launch_adjoint_grad(a->t, S, lvl + (size_t)(m - 1 - s0) * N, gs, h->stream);
+            if (e == hipSuccess && (m - 1) % GRAD_GROUP == 0) e = launch_grad_flush(g, gs, (long long)N, h->stream);
         }
     }
     if (e != hipSuccess) { cleanup(); return dev_fail(h, e, "adjoint sweep"); }
