@@ -15,11 +15,16 @@
 //   k_pool_count  lock-free slot allocator: a new block claims the first free
 //                 slot at or after (global key mod pool size) with a
 //                 compare-and-swap, so the pool keeps the spatial order of the
-//                 active list; zero-fill + C2 of new blocks; popcounts of the
-//                 bitmap; the last workgroup scans the counts and commits the
-//                 step counters.
-//   k_emit        prefix-sum compaction of the bitmap into the next active list
-//                 (spatial tile order), clearing the bitmap for the next step.
+//                 active list; zero-fill + C2 of new blocks; a two-level scan
+//                 of the bitmap (chunk ranges per workgroup, then the range
+//                 totals in the last one), which also lists the non-empty
+//                 chunks and commits the step counters.
+//   k_emit        compaction of the bitmap into the next active list and its
+//                 neighbour rows (spatial tile order), clearing the bitmap for
+//                 the next step.
+//
+// A step without an activation update (update interval > 1) is k_block_step
+// and k_advance (receivers, step counter).
 //
 // Arithmetic of the node update (eq.(3)), fixed for bit-exact comparisons:
 //   s = ((x+ + x-) + (y+ + y-)) + (z+ + z-);  lap = s - 6 phi;
