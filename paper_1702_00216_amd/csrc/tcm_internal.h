@@ -76,6 +76,7 @@ struct Tables {
     const Shot* shots;
     int nshots;
     int cap;                        // pool slots
+    long long nkeys;                // global block keys (all shots)
     float* pool;
     int* cell2box;                  // per global key: slot, EMPTY or CLAIMED
     unsigned long long* bitmap;     // next active set, one bit per global key

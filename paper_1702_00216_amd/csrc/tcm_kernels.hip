@@ -463,17 +463,30 @@ hipError_t launch_block_step(const Tables& t, int grid, int w, hipStream_t s, hi
 }
 
 // --------------------------------------------------------------------------
-// slot placement (whole wave): claim the first free slot at or after
-// G mod cap, 64 slots per probe, with a compare-and-swap on slot_key.  With a
-// pool of at least one slot per key this is the identity, so the pool is laid
-// out in the order of the active list and the stencil streams it; a smaller
-// pool wraps the key range over the slots.  Returns -1 only if no slot was
-// free in a full pass.
+// slot placement (whole wave): claim the first free slot at or after the
+// preferred slot, 64 slots per probe, with a compare-and-swap on slot_key.
+// With a pool of at least one slot per key the preferred slot is the key, so
+// the pool is laid out in the order of the active list and the stencil
+// streams it.  A smaller pool places whole tiles (64 consecutive keys) at a
+// hashed group of 64 slots: an active region that is compact in space (and
+// so spans a few ranges of keys) spreads evenly over the pool, and each
+// tile's blocks stay contiguous.  Returns -1 only if no slot was free in a
+// full pass.
 // --------------------------------------------------------------------------
+__device__ __forceinline__ long long preferred_slot(const Tables& t, long long G) {
+    const long long cap = t.cap;
+    if (cap >= t.nkeys) return G;
+    const long long groups = cap >> 6;
+    if (groups < 1) return G % cap;
+    // Fibonacci hashing of the tile number
+    const unsigned long long h = (unsigned long long)(G >> 6) * 0x9E3779B97F4A7C15ull;
+    return (long long)((h >> 32) % (unsigned long long)groups) * 64 + (G & 63);
+}
+
 __device__ int place_slot(const Tables& t, long long G) {
     const int lane = lane_id();
     const long long cap = t.cap;
-    const long long start = G % cap;
+    const long long start = preferred_slot(t, G);
     const long long passes = cap / 64 + 2;
     for (long long it = 0; it < passes; it++) {
         long long s = start + it * 64 + lane;

@@ -328,6 +328,7 @@ tcm_status setup_engine(tcm_handle* h, long long word_base) {
     if (cap > h->nkeys) cap = h->nkeys;
     if (cap > 0x7fffffffLL) cap = 0x7fffffffLL;
     t.cap = (int)cap;
+    t.nkeys = h->nkeys;
 
     bool ok = true;
     if (cfg->device_pool) {
