@@ -274,12 +274,47 @@ def bench_c4(args, tcm):
         seq = {"seconds": round(t_seq, 4), "updates_per_s": u_seq / t_seq,
                "batch_speedup": round(t_seq / (tot / args.steps), 3)}
         log(f"c4 one-by-one: {t_seq:.3f} s")
+    # the stencil's achieved bandwidth: one more batch run with per-launch
+    # events (16 B per node: lognormal C2 is not uniform over a block)
+    tsim = tcm.Simulation(shapes, 1.0, w0.dt, media, w0.trigger, w0.retire, timing=True,
+                          wg_per_cu=(tuning or {}).get("wg_per_cu", args.wg_per_cu),
+                          blocks_per_wg=(tuning or {}).get("blocks_per_wg", args.blocks_per_wg))
+    for i, s in enumerate(shots):
+        tsim.add_source(s.source, s.wavelet.w32, shot=i)
+    tsim.step(steps)
+    ts = tsim.stats()
+    tsim.close()
+    alg = BYTES_PER_UPDATE * ts["stencil_cells"] - 4 * ts["stencil_cells_uniform"]
+    achieved = alg / (ts["stencil_ms"] * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_block_step",
+            "avg_launch_us": round(ts["stencil_ms"] * 1e3 / max(ts["stencil_launches"], 1), 2),
+            "algorithmic_bytes_per_launch": round(alg / max(ts["stencil_launches"], 1))}
+    cpu = None
+    if not args.no_cpu:
+        # the CPU TCM oracle on shot 0 (the same media, thresholds and steps), bounded
+        import oracle
+        s = shots[0]
+        t = oracle.TCM(ti.lattice_to_dense(s.lattice, s.shape), s.dt, s.dx, np.float32(s.trigger),
+                       np.float32(s.retire))
+        t.add_source(s.source, s.wavelet.w32)
+        t0 = time.perf_counter()
+        done = 0
+        while done < steps and time.perf_counter() - t0 < args.cpu_budget:
+            t.step(25)
+            done += 25
+        el = time.perf_counter() - t0
+        ost = t.stats()
+        t.close()
+        cpu = {"value": ost["updates"] / el, "unit": "active-cell updates/s", "cores": oracle.openmp_threads(),
+               "kind": "oracle", "sample": f"CPU TCM oracle (FP32, OpenMP) on shot 0 ({s.shape}), steps 0-{done} "
+                                           f"({ost['updates']:.3e} updates in {el:.1f} s)"}
     cells = sum(a * b * c for a, b, c in shapes)
     _line(upd / tot, args.steps, args.warmup, tot / args.steps * 1e3,
           {"workload": f"c4: {len(shots)} shots, edges 96..384 (seed 4), lognormal media, "
                        f"{steps} steps, trigger 1e-6 / retire 1e-7, shared pool, hipGraph replay",
            "time_steps_per_run": steps, "dense_equivalent_nodes": cells},
-          roofline=None, cpu_baseline=None,
+          roofline=roof, cpu_baseline=cpu,
           tcm={"peak_active_blocks": st["peak_active_blocks"], "peak_pool_bytes": st["peak_pool_bytes"],
                "updates_per_run": st["cell_updates"]},
           one_by_one=seq, autotune=tuning)
