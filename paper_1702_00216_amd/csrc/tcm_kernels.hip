@@ -959,16 +959,17 @@ __global__ __launch_bounds__(64 * EMIT_WAVES) void k_emit(Tables t) {
             if (lane >= o) incl += u;
         }
         const unsigned base = emit ? t.wg_total[chunk / t.chunks_per_wg] + t.partial[chunk] : 0u;
-        for (int j = wid; j == wid; j++) {          // the wave's own word
+        const int j = wid;                      // the wave's own word
+        do {
             const unsigned long long m = __shfl(myword, j);
-            if (m == 0ull) continue;
+            if (m == 0ull) break;
             const long long w = chunk * CHUNK_WORDS + j;
             const bool mine = (m >> lane) & 1ull;
             const long long G = w * 64 + lane;
             if (!emit) {
                 // the step failed: undo its claims, keep the current list
                 if (mine && t.cell2box[G] == CLAIMED) t.cell2box[G] = EMPTY;
-                continue;
+                break;
             }
             const unsigned off = base + __shfl(incl - cnt, j) +
                                  (unsigned)__popcll(m & ((1ull << lane) - 1ull));
@@ -996,7 +997,7 @@ __global__ __launch_bounds__(64 * EMIT_WAVES) void k_emit(Tables t) {
                 rp[0] = make_int4(slot, nb[0], nb[1], nb[2]);
                 rp[1] = make_int4(nb[3], nb[4], nb[5], (int)G);
             }
-        }
+        } while (false);
         __syncthreads();                       // every wave has read the chunk
         if (wid == 0 && word_lane && myword) t.bitmap[w_lane] = 0ull;
     }
