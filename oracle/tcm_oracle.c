@@ -10,11 +10,13 @@
  *       phi^{n+1} overwrites phi^{n-1}); 1-D/2-D variants of the same
  *       central-difference operator for closed-form pins.
  *   O2  otcm_*_{f32,f64}: TCM with the paper's cell bookkeeping (Table 1:
- *       Triggered_cells, Triggered_hist, Max_cell_val, Cell2box, Box2cell),
- *       boxes padded with the neighbours' boundaries before the basic
- *       calculation ("Time stepping"), and the activation process of
- *       "Updating active cells" run every step (items 1-4, 6-8; diagonal
- *       triggering is not needed when the update runs every step).
+ *       Triggered_cells, Triggered_hist, Max_cell_val, Cell2box, Box2cell,
+ *       Shutdown_log, Trig_level), boxes padded with the neighbours'
+ *       boundaries before the basic calculation ("Time stepping"), and the
+ *       activation process of "Updating active cells" (items 1-4, 6-8) run
+ *       every step, or every k <= 8 steps (eq.(5)) with the diagonal
+ *       neighbourhood of item 5 / Figure 3; optional shutdown decay
+ *       (eq.(6)) and levels relative to the domain maximum.
  *   O3  oracle_adjoint_f64: discrete adjoint of O1 (FP64) with
  *       checkpoint-and-recompute, gradient with respect to c.
  *   eq.(4), eq.(5), eq.(6): the paper's closed forms.
@@ -26,7 +28,11 @@
  *     activation process; its cell stays active while samples remain;
  *   - activation: a cell stays active while any |phi^{n+1}| or |phi^n| in
  *     it exceeds `retire`; a face whose |phi^{n+1}| exceeds `trigger`
- *     activates the cell across it; a cell that stops is unboxed at once.
+ *     activates the cell across it; a cell that stops is unboxed at once,
+ *     or after `shutdown_steps` steps scaled by alpha (eq.(6));
+ *   - update every k > 1 steps: a cell with any |phi| of either level above
+ *     `trigger` (or a source still inserting) activates and keeps its 26
+ *     neighbours, and a source's 26 neighbours are boxed with it.
  *
  * Build: gcc -O3 -fopenmp -ffp-contract=off -fno-fast-math (no FTZ/DAZ).
  */
