@@ -761,7 +761,9 @@ __global__ __launch_bounds__(256) void k_pool_count(Tables t) {
             const int nwaves = gridDim.x * (blockDim.x >> 6);
             for (int k = blockIdx.x * (blockDim.x >> 6) + wid; k < nn; k += nwaves) {
                 const long long G = t.new_key[k];
-                const int slot = k < handoff ? t.ret_slot[k] : place_slot(t, G);
+                // one slot per key: slot G is only ever key G's (and no slot is
+                // handed over, the free slots always outnumber the new blocks)
+                const int slot = t.cap >= t.nkeys ? (int)G : k < handoff ? t.ret_slot[k] : place_slot(t, G);
                 if (slot < 0) {                      // unreachable (see above): fail the step
                     if (lane == 0) {
                         st->err_step = st->step;
@@ -1042,7 +1044,7 @@ __global__ __launch_bounds__(64) void k_activate(Tables t, long long G, int shot
         if (lane == 0) st->add_error = -3;
         return;
     }
-    const int slot = place_slot(t, G);
+    const int slot = t.cap >= t.nkeys ? (int)G : place_slot(t, G);
     if (slot < 0) {                      // unreachable: a slot is free
         if (lane == 0) st->add_error = -6;
         return;

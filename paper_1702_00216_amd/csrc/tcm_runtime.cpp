@@ -379,7 +379,10 @@ tcm_status setup_engine(tcm_handle* h, long long word_base) {
     // fills new blocks with 2 workgroups per CU, of which the first scan_wgs
     // also scan the bitmap
     h->grid_plan = std::max(1, h->ncu * 4);
-    t.scan_wgs = std::min(POOL_COUNT_MAX_WG, std::max(64, std::min((t.nchunks + 3) / 4, h->ncu)));
+    // up to 1024 chunks (64 Ki blocks) one workgroup scans the whole bitmap:
+    // no completion chain between workgroups
+    t.scan_wgs = t.nchunks <= 1024 ? 1
+                                   : std::min(POOL_COUNT_MAX_WG, std::max(64, std::min((t.nchunks + 3) / 4, h->ncu)));
     t.chunks_per_wg = (t.nchunks + t.scan_wgs - 1) / t.scan_wgs;
     h->grid_pool = std::max(t.scan_wgs, h->ncu * 2);
     // compaction: 16-wave workgroups over the non-empty chunks
