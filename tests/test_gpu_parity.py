@@ -300,6 +300,32 @@ def test_workgroup_tiles_agree_with_oracle(tile):
     assert g["cell_updates"] == o["updates"] and g["activations"] == o["activations"]
 
 
+def test_caller_pool_and_stream():
+    """The pool in a caller's torch tensor and the work on a caller's torch
+    stream (steps, reads into a CUDA tensor); two handles on separate streams
+    stay independent."""
+    announce("caller device pool + torch streams")
+    import torch
+    w = ti.c1(steps=70)
+    src = [(w.source, w.wavelet.w32)]
+    phi, _, _ = oracle.dense_run(w.c_dense, w.dt, 1.0, 70, np.float32, sources=src)
+    slots = 512
+    pool = torch.empty(slots * 1536, dtype=torch.float32, device="cuda")
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    a = gpu_run(w.shape, w.dt, w.c_dense, src, 0, device_pool=pool, pool_bytes=slots * 6144, stream=s1)
+    b = gpu_run(w.shape, w.dt, w.c_dense, src, 0, stream=s2)
+    for k in range(7):
+        a.step(10)
+        b.step(10)
+    out = torch.empty(w.shape[0] * w.shape[1] * w.shape[2], dtype=torch.float32, device="cuda")
+    with torch.cuda.stream(s1):
+        a.read(0, out=out)
+    torch.cuda.synchronize()
+    assert values_equal(out.cpu().numpy().reshape(phi.shape), phi)
+    assert values_equal(b.read(0), phi)
+    assert a.stats()["pool_bytes"] == slots * 6144
+
+
 def test_source_added_mid_run():
     announce("source added after 30 steps")
     w = ti.c1(steps=80)
