@@ -481,3 +481,54 @@ def test_update_interval_matches_cpu_tcm(k, rel, n):
         assert g["activations"] == o["activations"] and g["retirements"] == o["retirements"]
         assert g["cell_updates"] == o["updates"]
     assert values_equal(sim.read(0), t.read(0)) and values_equal(sim.read(1), t.read(1))
+
+
+@pytest.mark.parametrize("seed", list(range(40)))
+def test_random_configurations_match_cpu_tcm(seed):
+    """Seeded random problems: ragged shape, random or z-layered media, two or
+    three sources (one added mid-run), levels, update interval, shutdown decay,
+    relative levels, uniform-C2 switch and workgroup tile.  Both field levels
+    and the work statistics equal the CPU TCM."""
+    rng = np.random.default_rng(1000 + seed)
+    shape = tuple(int(v) for v in rng.integers(5, 60, size=3))
+    if rng.random() < 0.5:
+        c = ti.random_media(shape, seed=2000 + seed, cmin=float(rng.uniform(0.2, 0.6)), cmax=1.0)
+    else:
+        c = np.full(shape[::-1], 0.6, np.float32)
+        c[int(rng.integers(0, shape[2])):] = 1.0
+    dt = 0.55
+    tr = float(rng.choice([0.0, 1e-4, 1e-3, 1e-2]))
+    trig = np.float32(tr)
+    ret = np.float32(tr * float(rng.choice([1.0, 0.3, 0.1])))
+    interval = int(rng.choice([1, 1, 2, 3, 8]))
+    sd = int(rng.choice([0, 0, 3, 10]))
+    alpha = np.float32(rng.choice([0.5, 0.9]))
+    rel = bool(rng.random() < 0.25)
+    trel, rrel = (np.float32(1e-3), np.float32(2e-4)) if rel else (np.float32(0), np.float32(0))
+    tile = int(rng.choice([2, 4, 8]))
+    unif = bool(rng.random() < 0.7)
+    srcs = [(tuple(int(rng.integers(0, e)) for e in shape), ti.ricker(float(rng.uniform(0.08, 0.2)), dt).w32)
+            for _ in range(int(rng.integers(1, 3)))]
+    late = (tuple(int(rng.integers(0, e)) for e in shape), ti.ricker(0.15, dt).w32)
+    n1, n2 = int(rng.integers(10, 50)), int(rng.integers(10, 140))
+    announce(f"random {seed}: shape {shape} levels {tr:g}/{float(ret):g} k {interval} shutdown {sd} "
+             f"rel {rel} tile {tile} uniform {unif}")
+    t = oracle.TCM(c, dt, 1.0, trig, ret, shutdown_steps=sd, shutdown_alpha=alpha, trigger_rel=trel,
+                   retire_rel=rrel, interval=interval)
+    sim = tcm.Simulation(shape, 1.0, dt, c, trig, ret, shutdown_steps=sd, shutdown_alpha=float(alpha),
+                         trigger_rel=float(trel), retire_rel=float(rrel), trigger_interval=interval,
+                         blocks_per_wg=tile, uniform_c2=unif, timing=bool(seed % 2))
+    for xyz, w in srcs:
+        t.add_source(xyz, w)
+        sim.add_source(xyz, w)
+    assert t.step(n1) == 0
+    sim.step(n1)
+    t.add_source(*late)
+    sim.add_source(*late)
+    assert t.step(n2) == 0
+    sim.step(n2)
+    assert values_equal(sim.read(0), t.read(0)) and values_equal(sim.read(1), t.read(1))
+    g, o = sim.stats(), t.stats()
+    assert g["step"] == o["step"] and g["active_blocks"] == o["active"]
+    assert g["activations"] == o["activations"] and g["retirements"] == o["retirements"]
+    assert g["cell_updates"] == o["updates"]
