@@ -1185,14 +1185,14 @@ hipError_t launch_media_c2(const Shot& shot, const Shot* dshot, double dt, doubl
     return hipGetLastError();
 }
 
-// 2.5-D z-marching: a 64 x 4 workgroup owns an (x, y) tile and walks DZ
+// 2.5-D z-marching: a 128 x 4 workgroup owns an (x, y) tile and walks DZ
 // planes, keeping z-1, z, z+1 of its column in registers; x/y neighbours come
 // through the L1/L2 caches.
-constexpr int DENSE_TX = 64, DENSE_TY = 4, DENSE_DZ = 32;
+constexpr int DENSE_TX = 128, DENSE_TY = 4, DENSE_DZ = 32;   // fastest of a measured sweep
 
-__global__ __launch_bounds__(256) void k_dense_step(DenseArgs a) {
-    const int x = blockIdx.x * DENSE_TX + (threadIdx.x & 63);
-    const int y = blockIdx.y * DENSE_TY + (threadIdx.x >> 6);
+__global__ __launch_bounds__(DENSE_TX * DENSE_TY) void k_dense_step(DenseArgs a) {
+    const int x = blockIdx.x * DENSE_TX + (int)(threadIdx.x % DENSE_TX);
+    const int y = blockIdx.y * DENSE_TY + (int)(threadIdx.x / DENSE_TX);
     const int z0 = blockIdx.z * DENSE_DZ;
     if (x >= a.nx || y >= a.ny) return;
     const size_t sy = (size_t)a.nx, sz = (size_t)a.nx * a.ny;
@@ -1208,7 +1208,11 @@ __global__ __launch_bounds__(256) void k_dense_step(DenseArgs a) {
         const float yp = y + 1 < a.ny ? a.cur[i + sy] : 0.f;
         const float s = ((xp + xm) + (yp + ym)) + (zp + zm);
         const float lap = s - 6.0f * c;
-        a.nxt[i] = (2.0f * c - a.nxt[i]) + a.c2[i] * lap;
+        // phi^{n-1}, C2 and phi^{n+1} are touched once per step: streamed past
+        // L2, which keeps the phi^n planes the neighbouring columns re-read
+        const float prev = __builtin_nontemporal_load(&a.nxt[i]);
+        const float k2 = __builtin_nontemporal_load(&a.c2[i]);
+        __builtin_nontemporal_store((2.0f * c - prev) + k2 * lap, &a.nxt[i]);
         zm = c;
         c = zp;
     }
@@ -1218,9 +1222,9 @@ hipError_t launch_dense_step(const DenseArgs& a, hipStream_t s, hipEvent_t e0, h
     dim3 grid((a.nx + DENSE_TX - 1) / DENSE_TX, (a.ny + DENSE_TY - 1) / DENSE_TY,
               (a.nz + DENSE_DZ - 1) / DENSE_DZ);
     if (e0 || e1)
-        hipExtLaunchKernelGGL(k_dense_step, grid, dim3(256), 0, s, e0, e1, 0, a);
+        hipExtLaunchKernelGGL(k_dense_step, grid, dim3(DENSE_TX * DENSE_TY), 0, s, e0, e1, 0, a);
     else
-        hipLaunchKernelGGL(k_dense_step, grid, dim3(256), 0, s, a);
+        hipLaunchKernelGGL(k_dense_step, grid, dim3(DENSE_TX * DENSE_TY), 0, s, a);
     return hipGetLastError();
 }
 
