@@ -511,21 +511,33 @@ def test_random_configurations_match_cpu_tcm(seed):
             for _ in range(int(rng.integers(1, 3)))]
     late = (tuple(int(rng.integers(0, e)) for e in shape), ti.ricker(0.15, dt).w32)
     n1, n2 = int(rng.integers(10, 50)), int(rng.integers(10, 140))
+    kw = dict(shutdown_steps=sd, shutdown_alpha=alpha, trigger_rel=trel, retire_rel=rrel, interval=interval)
+
+    def oracle_run(cap=0):
+        t = oracle.TCM(c, dt, 1.0, trig, ret, cap=cap, **kw)
+        for xyz, w in srcs:
+            t.add_source(xyz, w)
+        assert t.step(n1) == 0
+        t.add_source(*late)
+        assert t.step(n2) == 0
+        return t
+
+    t = oracle_run()
+    # every third problem runs in a pool of just above its peak block count
+    # (at least 64 slots): tiles placed at hashed slot groups, probing, hand-offs
+    cap = 0
+    if seed % 3 == 0:
+        cap = max(64, t.stats()["peak_active"] + int(rng.integers(0, 20)))
+        t = oracle_run(cap)
     announce(f"random {seed}: shape {shape} levels {tr:g}/{float(ret):g} k {interval} shutdown {sd} "
-             f"rel {rel} tile {tile} uniform {unif}")
-    t = oracle.TCM(c, dt, 1.0, trig, ret, shutdown_steps=sd, shutdown_alpha=alpha, trigger_rel=trel,
-                   retire_rel=rrel, interval=interval)
+             f"rel {rel} tile {tile} uniform {unif} pool {cap or 'auto'}")
     sim = tcm.Simulation(shape, 1.0, dt, c, trig, ret, shutdown_steps=sd, shutdown_alpha=float(alpha),
                          trigger_rel=float(trel), retire_rel=float(rrel), trigger_interval=interval,
-                         blocks_per_wg=tile, uniform_c2=unif, timing=bool(seed % 2))
+                         blocks_per_wg=tile, uniform_c2=unif, timing=bool(seed % 2), pool_bytes=cap * 6144)
     for xyz, w in srcs:
-        t.add_source(xyz, w)
         sim.add_source(xyz, w)
-    assert t.step(n1) == 0
     sim.step(n1)
-    t.add_source(*late)
     sim.add_source(*late)
-    assert t.step(n2) == 0
     sim.step(n2)
     assert values_equal(sim.read(0), t.read(0)) and values_equal(sim.read(1), t.read(1))
     g, o = sim.stats(), t.stats()
