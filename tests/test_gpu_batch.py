@@ -114,3 +114,46 @@ def test_autotune_keeps_state_and_results(tmp_path):
     assert r2["blocks_per_wg"] == r1["blocks_per_wg"]
     with pytest.raises(tcm.TCMError):
         ref.set_launch(0, 16)
+
+
+@pytest.mark.parametrize("seed", list(range(8)))
+def test_random_batches_match_cpu_tcm_per_shot(seed):
+    """Seeded random batches: 2-7 shots of random shapes, media and sources
+    over one pool (auto or just above the summed peaks), random levels,
+    update interval and workgroup tile; every shot equals the CPU TCM run
+    on its own."""
+    rng = np.random.default_rng(500 + seed)
+    nshot = int(rng.integers(2, 8))
+    dt = 0.55
+    tr = float(rng.choice([0.0, 1e-4, 1e-3]))
+    trig, ret = np.float32(tr), np.float32(tr * 0.3)
+    interval = int(rng.choice([1, 1, 2, 8]))
+    tile = int(rng.choice([2, 4, 8]))
+    steps = int(rng.integers(30, 120))
+    shots = []
+    for i in range(nshot):
+        shape = tuple(int(v) for v in rng.integers(4, 48, size=3))
+        c = ti.random_media(shape, seed=6000 + 10 * seed + i, cmin=0.3, cmax=1.0)
+        src = tuple(int(rng.integers(0, e)) for e in shape)
+        shots.append((shape, c, src, ti.ricker(float(rng.uniform(0.08, 0.2)), dt).w32))
+    ref = []
+    for shape, c, src, w in shots:
+        t = oracle.TCM(c, dt, 1.0, trig, ret, interval=interval)
+        t.add_source(src, w)
+        assert t.step(steps) == 0
+        ref.append(t)
+    cap = 0
+    if seed % 2:
+        cap = max(64, sum(t.stats()["peak_active"] for t in ref) + int(rng.integers(0, 30)))
+    announce(f"random batch {seed}: {nshot} shots, levels {tr:g}, k {interval}, tile {tile}, pool {cap or 'auto'}")
+    b = tcm.Simulation([s[0] for s in shots], 1.0, dt, [s[1] for s in shots], trig, ret,
+                       trigger_interval=interval, blocks_per_wg=tile, pool_bytes=cap * 6144)
+    for i, (shape, c, src, w) in enumerate(shots):
+        b.add_source(src, w, shot=i)
+    b.step(steps)
+    tot = 0
+    for i, t in enumerate(ref):
+        assert values_equal(b.read(0, shot=i), t.read(0)), i
+        assert values_equal(b.read(1, shot=i), t.read(1)), i
+        tot += t.stats()["updates"]
+    assert b.stats()["cell_updates"] == tot
