@@ -233,6 +233,23 @@ tcm_status tcm_set_launch(tcm_handle* h, int32_t wg_per_cu, int32_t graph_steps,
  * media, configuration and allocations are kept. */
 tcm_status tcm_reset(tcm_handle* h);
 
+/* Save the whole state at the current step (block engine: pool, block
+ * tables and counters; dense engine: both field arrays) into device memory
+ * that the snapshot owns; *snap receives an opaque pointer, freed by
+ * tcm_snapshot_free.  The handle keeps its state.  TCM_E_NOMEM when the
+ * device memory is short. */
+tcm_status tcm_snapshot(tcm_handle* h, void** snap);
+
+/* Return h to the step and state of a snapshot of h.  Stepping on from
+ * there repeats the same results.  TCM_E_ARG for a snapshot of another
+ * handle; TCM_E_STATE when sources or receivers were added since the
+ * snapshot (they are part of the state: a source boxes its block when it is
+ * added). */
+tcm_status tcm_restore(tcm_handle* h, const void* snap);
+
+/* Free a snapshot (NULL is allowed).  Call before destroying its handle. */
+void tcm_snapshot_free(void* snap);
+
 tcm_status tcm_stats(tcm_handle* h, tcm_stats_t* out);
 
 void tcm_destroy(tcm_handle* h);

@@ -20,7 +20,7 @@ EXPORTS = [
     "tcm_create", "tcm_create_batch", "tcm_add_source", "tcm_add_source_shot", "tcm_step",
     "tcm_read", "tcm_read_shot", "tcm_set_receivers", "tcm_read_traces", "tcm_adjoint",
     "tcm_reset", "tcm_stats", "tcm_destroy", "tcm_last_error", "tcm_version", "tcm_autotune",
-    "tcm_set_launch",
+    "tcm_set_launch", "tcm_snapshot", "tcm_restore", "tcm_snapshot_free",
 ]
 
 
@@ -99,6 +99,10 @@ def lib():
         L.tcm_read_traces.argtypes = [H, P, I, F(C.c_int32)]
         L.tcm_adjoint.argtypes = [H, P, I, I, P, I]
         L.tcm_reset.argtypes = [H]
+        L.tcm_snapshot.argtypes = [H, F(P)]
+        L.tcm_restore.argtypes = [H, P]
+        L.tcm_snapshot_free.argtypes = [P]
+        L.tcm_snapshot_free.restype = None
         L.tcm_autotune.argtypes = [H, I, F(Tuning)]
         L.tcm_set_launch.argtypes = [H, I, I, I]
         L.tcm_stats.argtypes = [H, F(Stats)]

@@ -1069,6 +1069,15 @@ tcm_status tcm_stats(tcm_handle* h, tcm_stats_t* o) {
     return TCM_OK;
 }
 
+// A caller-owned copy of a handle's state (tcm_snapshot / tcm_restore).
+struct SnapImpl {
+    tcm_handle* owner = nullptr;
+    char* buf = nullptr;
+    long long hstep = 0, dense_step = 0;
+    size_t nsrc = 0;
+    int nrec = 0;
+};
+
 tcm_status tcm_reset(tcm_handle* h) {
     tcm_status st = check_live(h);
     if (st) return st;
@@ -1106,6 +1115,72 @@ tcm_status tcm_reset(tcm_handle* h) {
     h->hstep = 0;
     HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
     return TCM_OK;
+}
+
+tcm_status tcm_snapshot(tcm_handle* h, void** snap) {
+    tcm_status st = check_live(h);
+    if (st) return st;
+    if (!snap) return set_err(h, TCM_E_ARG, "snap is NULL");
+    *snap = nullptr;
+    HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+    SnapImpl* s = new SnapImpl();
+    s->owner = h;
+    s->hstep = h->hstep;
+    s->dense_step = h->dense_step;
+    s->nsrc = h->h_src.size();
+    s->nrec = h->t.nrec;
+    if (h->engine == TCM_ENGINE_DENSE) {
+        const Shot& S = h->shots[0];
+        const size_t N = (size_t)S.nx * S.ny * S.nz;
+        if (hipMalloc((void**)&s->buf, 2 * N * sizeof(float)) != hipSuccess) {
+            (void)hipGetLastError();
+            delete s;
+            return set_err(h, TCM_E_NOMEM, "no device memory for the snapshot");
+        }
+        HIP_OR_FAIL(h, hipMemcpyAsync(s->buf, h->d_phi[0], N * sizeof(float), hipMemcpyDeviceToDevice, h->stream));
+        HIP_OR_FAIL(h, hipMemcpyAsync(s->buf + N * sizeof(float), h->d_phi[1], N * sizeof(float),
+                                      hipMemcpyDeviceToDevice, h->stream));
+    } else {
+        st = ck_save(h, &s->buf);
+        if (st) {
+            delete s;
+            return st;
+        }
+    }
+    HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+    *snap = s;
+    return TCM_OK;
+}
+
+tcm_status tcm_restore(tcm_handle* h, const void* snap) {
+    tcm_status st = check_live(h);
+    if (st) return st;
+    const SnapImpl* s = (const SnapImpl*)snap;
+    if (!s || s->owner != h) return set_err(h, TCM_E_ARG, "not a snapshot of this handle");
+    if (s->nsrc != h->h_src.size() || s->nrec != h->t.nrec)
+        return set_err(h, TCM_E_STATE, "sources or receivers were added after the snapshot");
+    HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+    drop_graph(h);
+    if (h->engine == TCM_ENGINE_DENSE) {
+        const Shot& S = h->shots[0];
+        const size_t N = (size_t)S.nx * S.ny * S.nz;
+        HIP_OR_FAIL(h, hipMemcpyAsync(h->d_phi[0], s->buf, N * sizeof(float), hipMemcpyDeviceToDevice, h->stream));
+        HIP_OR_FAIL(h, hipMemcpyAsync(h->d_phi[1], s->buf + N * sizeof(float), N * sizeof(float),
+                                      hipMemcpyDeviceToDevice, h->stream));
+        h->dense_step = s->dense_step;
+    } else {
+        st = ck_restore(h, s->buf);
+        if (st) return st;
+    }
+    h->hstep = s->hstep;
+    return sync_state(h);
+}
+
+void tcm_snapshot_free(void* snap) {
+    SnapImpl* s = (SnapImpl*)snap;
+    if (!s) return;
+    if (s->buf) (void)hipFree(s->buf);
+    delete s;
 }
 
 tcm_status tcm_adjoint(tcm_handle* h, const float* resid, int32_t nt, int32_t resid_is_device,

@@ -236,10 +236,40 @@ class Simulation:
     def reset(self):
         self._check(L.lib().tcm_reset(self._h))
 
+    def snapshot(self) -> "Snapshot":
+        """Device copy of the whole state at the current step (tcm_snapshot)."""
+        p = C.c_void_p()
+        self._check(L.lib().tcm_snapshot(self._h, C.byref(p)))
+        return Snapshot(p, self)
+
+    def restore(self, snap: "Snapshot"):
+        """Return to the step and state of ``snap`` (taken from this handle)."""
+        self._check(L.lib().tcm_restore(self._h, snap._p))
+
     def stats(self) -> dict:
         s = L.Stats()
         self._check(L.lib().tcm_stats(self._h, C.byref(s)))
         return {k: getattr(s, k) for k, _ in L.Stats._fields_}
+
+
+class Snapshot:
+    """A state saved by Simulation.snapshot(); frees its device memory when
+    garbage-collected or closed (before its handle is destroyed)."""
+
+    def __init__(self, p, owner):
+        self._p = p
+        self._owner = owner          # keeps the handle alive while the snapshot lives
+
+    def close(self):
+        if getattr(self, "_p", None):
+            L.lib().tcm_snapshot_free(self._p)
+            self._p = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def version() -> str:

@@ -326,6 +326,41 @@ def test_caller_pool_and_stream():
     assert a.stats()["pool_bytes"] == slots * 6144
 
 
+@pytest.mark.parametrize("engine,interval", [("blocks", 1), ("blocks", 8), ("dense", 1)])
+def test_snapshot_restore_repeats_the_run(engine, interval):
+    """Snapshot at step 37, step on, restore, step again: the same fields,
+    statistics and traces; a snapshot of another handle and a restore after
+    a new source are refused."""
+    announce(f"snapshot / restore ({engine}, interval {interval})")
+    w = ti.c1(steps=100)
+    src = [(w.source, w.wavelet.w32)]
+    lev = np.float32(1e-4 if engine == "blocks" else 0.0)
+    sim = gpu_run(w.shape, w.dt, w.c_dense, src, 0, lev, np.float32(lev / 5), engine=engine,
+                  receivers=[(3, 4, 5), (32, 40, 10)], trigger_interval=interval)
+    sim.step(37)
+    snap = sim.snapshot()
+    sim.step(45)
+    first = (sim.read(0), sim.read(1), sim.stats(), sim.read_traces())
+    sim.restore(snap)
+    assert sim.stats()["step"] == 37
+    sim.step(20)
+    sim.step(25)
+    again = (sim.read(0), sim.read(1), sim.stats(), sim.read_traces())
+    assert values_equal(first[0], again[0]) and values_equal(first[1], again[1])
+    for k in ("step", "active_blocks", "cell_updates", "activations", "retirements"):
+        assert first[2][k] == again[2][k], k
+    assert values_equal(first[3], again[3])
+    other = gpu_run(w.shape, w.dt, w.c_dense, src, 0, engine=engine)
+    with pytest.raises(tcm.TCMError) as ei:
+        other.restore(snap)
+    assert ei.value.status == -1
+    sim.add_source((10, 10, 10), w.wavelet.w32)
+    with pytest.raises(tcm.TCMError) as ei:
+        sim.restore(snap)
+    assert ei.value.status == -6
+    snap.close()
+
+
 def test_source_added_mid_run():
     announce("source added after 30 steps")
     w = ti.c1(steps=80)
