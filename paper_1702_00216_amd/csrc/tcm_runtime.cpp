@@ -1117,6 +1117,13 @@ tcm_status tcm_reset(tcm_handle* h) {
     return TCM_OK;
 }
 
+void tcm_snapshot_free(void* snap) {
+    SnapImpl* s = (SnapImpl*)snap;
+    if (!s) return;
+    if (s->buf) (void)hipFree(s->buf);
+    delete s;
+}
+
 tcm_status tcm_snapshot(tcm_handle* h, void** snap) {
     tcm_status st = check_live(h);
     if (st) return st;
@@ -1129,25 +1136,29 @@ tcm_status tcm_snapshot(tcm_handle* h, void** snap) {
     s->dense_step = h->dense_step;
     s->nsrc = h->h_src.size();
     s->nrec = h->t.nrec;
+    auto fail = [&](tcm_status why) {
+        tcm_snapshot_free(s);
+        return why;
+    };
     if (h->engine == TCM_ENGINE_DENSE) {
         const Shot& S = h->shots[0];
         const size_t N = (size_t)S.nx * S.ny * S.nz;
         if (hipMalloc((void**)&s->buf, 2 * N * sizeof(float)) != hipSuccess) {
             (void)hipGetLastError();
-            delete s;
-            return set_err(h, TCM_E_NOMEM, "no device memory for the snapshot");
+            s->buf = nullptr;
+            return fail(set_err(h, TCM_E_NOMEM, "no device memory for the snapshot"));
         }
-        HIP_OR_FAIL(h, hipMemcpyAsync(s->buf, h->d_phi[0], N * sizeof(float), hipMemcpyDeviceToDevice, h->stream));
-        HIP_OR_FAIL(h, hipMemcpyAsync(s->buf + N * sizeof(float), h->d_phi[1], N * sizeof(float),
-                                      hipMemcpyDeviceToDevice, h->stream));
+        hipError_t e = hipMemcpyAsync(s->buf, h->d_phi[0], N * sizeof(float), hipMemcpyDeviceToDevice, h->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(s->buf + N * sizeof(float), h->d_phi[1], N * sizeof(float),
+                               hipMemcpyDeviceToDevice, h->stream);
+        if (e != hipSuccess) return fail(dev_fail(h, e, "snapshot copy"));
     } else {
         st = ck_save(h, &s->buf);
-        if (st) {
-            delete s;
-            return st;
-        }
+        if (st) return fail(st);
     }
-    HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+    const hipError_t e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return fail(dev_fail(h, e, "snapshot copy"));
     *snap = s;
     return TCM_OK;
 }
@@ -1176,12 +1187,6 @@ tcm_status tcm_restore(tcm_handle* h, const void* snap) {
     return sync_state(h);
 }
 
-void tcm_snapshot_free(void* snap) {
-    SnapImpl* s = (SnapImpl*)snap;
-    if (!s) return;
-    if (s->buf) (void)hipFree(s->buf);
-    delete s;
-}
 
 tcm_status tcm_adjoint(tcm_handle* h, const float* resid, int32_t nt, int32_t resid_is_device,
                        float* grad_c, int32_t out_is_device) {
