@@ -84,6 +84,26 @@ def measured_traffic(name: str):
     return int(kv["traffic_bytes_per_dispatch"])
 
 
+def host_info(cores: int) -> dict:
+    """The CPU the baseline ran on: model, logical CPUs (all, and those this
+    process may use) and the STREAM triad bandwidth with the baseline's
+    thread count."""
+    import oracle
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    oracle.set_threads(cores)
+    return {"cpu_model": model, "nproc": os.cpu_count(), "usable_cpus": len(os.sched_getaffinity(0)),
+            "stream_triad_GBps": round(oracle.stream_triad(1 << 26, 5), 1),
+            "stream_triad_threads": cores}
+
+
 def cpu_baseline(w, budget_s: float):
     """CPU TCM oracle (OpenMP) on the first steps of the same workload, until
     about budget_s seconds of work are done."""
@@ -115,7 +135,7 @@ def cpu_baseline(w, budget_s: float):
     t.close()
     oracle.set_threads(cores)
     return {"value": st["updates"] / el, "unit": "active-cell updates/s",
-            "cores": cores, "kind": "oracle",
+            "cores": cores, "kind": "oracle", "host": host_info(cores),
             "sample": f"CPU TCM oracle (FP32, OpenMP) on steps 0-{done} of the same workload "
                       f"({st['updates']:.3e} updates in {el:.1f} s)",
             "single_core": {"value": st1["updates"] / el1, "cores": 1,
@@ -434,6 +454,7 @@ def main():
                     help="skip the runs with the activation update every 8 steps")
     ap.add_argument("--no-graph-replay", action="store_true",
                     help="skip the hipGraph replay run (counter-collection runs)")
+    ap.add_argument("--no-probe", action="store_true", help="skip the HBM ceiling probe")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device-to-device torch copy (counter calibration)")
     args = ap.parse_args()
@@ -521,6 +542,20 @@ def main():
                 "algorithmic_bytes_per_launch": round(alg_bytes / st_launch),
                 "uniform_c2_node_fraction": round(st_cells_u / max(st_cells, 1), 4),
                 "achieved_if_16B_per_node": round(BYTES_PER_UPDATE * st_cells / (st_ms * 1e-3) / 1e9, 1)}
+
+    # the achievable HBM ceiling of a kernel of the stencil's shape (three
+    # streams in, one out, non-temporal): best over a few grid sizes
+    if roof and not args.no_probe:
+        probes = [tcm.hbm_probe(3, wg_per_cu=g) for g in (4, 8, 16)]
+        best = max(probes, key=lambda p: p["GBps"])
+        copy1 = tcm.hbm_probe(1, wg_per_cu=best["wg_per_cu"])
+        roof["ceiling"] = {"kernel": "k_hbm_probe (12 B read : 4 B written per element, 1 GiB per stream)",
+                           "GBps": round(best["GBps"], 1), "wg_per_cu": best["wg_per_cu"],
+                           "frac": round(roof["achieved"] / best["GBps"], 4),
+                           "copy_GBps": round(copy1["GBps"], 1),
+                           "results_ok": all(p["result_ok"] for p in probes + [copy1])}
+        log(f"HBM probe: {best['GBps']:.0f} GB/s (3 reads : 1 write), copy {copy1['GBps']:.0f} GB/s; "
+            f"stencil at {roof['ceiling']['frac']:.1%} of the probe")
 
     dense = None
     if not args.no_dense:

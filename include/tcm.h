@@ -254,8 +254,28 @@ tcm_status tcm_stats(tcm_handle* h, tcm_stats_t* out);
 
 void tcm_destroy(tcm_handle* h);
 
-/* Message of the last failed call on h, or of the last failed create on this
- * thread when h is NULL.  Never NULL. */
+/* Measurement helper, not part of the method: the HBM bandwidth that a
+ * streaming kernel of the block stencil's shape reaches on the current
+ * device, the ceiling its roofline fraction is compared with.  The kernel
+ * computes dst[i] = src[i] (+ src[n + i] (+ src[2n + i])) for i < n with
+ * coalesced 256-byte wave accesses and non-temporal loads and stores; with
+ * nread = 3 it reads 12 and writes 4 bytes per element, the stencil's mix.
+ *   src      device, nread * n floats (the sources back to back)
+ *   dst      device, n floats; must not overlap src
+ *   n        floats per source, > 0 and a multiple of 2048
+ *   nread    1, 2 or 3
+ *   wg_per_cu  workgroups (256 threads) per compute unit; 0 => 8
+ *   reps     launches, 1..1000
+ *   stream   hipStream_t, NULL => the null stream
+ *   best_ms  host; the shortest launch, timed with events stamped at the
+ *            dispatch's start and end
+ * Synchronous.  The caller owns the buffers.  TCM_E_ARG for a bad argument
+ * (message in tcm_last_error(NULL)); TCM_E_DEVICE for a HIP error. */
+tcm_status tcm_hbm_probe(const float* src, float* dst, uint64_t n, int32_t nread, int32_t wg_per_cu,
+                         int32_t reps, void* stream, float* best_ms);
+
+/* Message of the last failed call on h, or of the last failed call without
+ * a handle (create, probe) on this thread when h is NULL.  Never NULL. */
 const char* tcm_last_error(const tcm_handle* h);
 
 /* Library version string. */

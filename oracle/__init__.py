@@ -119,6 +119,8 @@ def _declare(L):
     L.oracle_openmp_threads.restype = _I
     L.oracle_set_threads.argtypes = [_I]
     L.oracle_set_threads.restype = None
+    L.oracle_stream_triad.argtypes = [C.c_long, _I]
+    L.oracle_stream_triad.restype = _D
 
 
 def _ptr(a: Optional[np.ndarray]):
@@ -331,6 +333,11 @@ def decay_total(alpha: float, n: int) -> float:
 
 def openmp_threads() -> int:
     return int(lib().oracle_openmp_threads())
+
+
+def stream_triad(n: int = 1 << 26, reps: int = 5) -> float:
+    """Host STREAM triad bandwidth in GB/s with the current thread count."""
+    return float(lib().oracle_stream_triad(int(n), int(reps)))
 
 
 def set_threads(n: int) -> None:

@@ -40,6 +40,7 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#include <time.h>
 
 #define REAL float
 #define SFX(name) name##_f32
@@ -85,6 +86,35 @@ int oracle_openmp_threads(void)
 #else
     return 1;
 #endif
+}
+
+/* Host memory bandwidth beside the CPU baseline: the STREAM triad
+ * a[i] = b[i] + s*c[i] over n doubles per array (24 bytes per element),
+ * best of reps passes, in GB/s.  Arrays are first touched by the threads
+ * that later use them.  Returns -1 when the arrays cannot be allocated. */
+double oracle_stream_triad(long n, int reps)
+{
+    double *a = malloc((size_t)n * sizeof(double));
+    double *b = malloc((size_t)n * sizeof(double));
+    double *c = malloc((size_t)n * sizeof(double));
+    double best = -1.0;
+    if (!a || !b || !c) goto out;
+#pragma omp parallel for schedule(static)
+    for (long i = 0; i < n; i++) { a[i] = 0.0; b[i] = 1.0; c[i] = 2.0; }
+    for (int r = 0; r < reps; r++) {
+        struct timespec t0, t1;
+        clock_gettime(CLOCK_MONOTONIC, &t0);
+#pragma omp parallel for schedule(static)
+        for (long i = 0; i < n; i++) a[i] = b[i] + 3.0 * c[i];
+        clock_gettime(CLOCK_MONOTONIC, &t1);
+        const double s = (double)(t1.tv_sec - t0.tv_sec) + 1e-9 * (double)(t1.tv_nsec - t0.tv_nsec);
+        const double gbs = 24.0 * (double)n / s / 1e9;
+        if (a[n / 2] != 7.0) { best = -1.0; goto out; }
+        if (gbs > best) best = gbs;
+    }
+out:
+    free(a); free(b); free(c);
+    return best;
 }
 
 /* Thread count of the following parallel loops (timing on one core). */

@@ -6,6 +6,6 @@ not touch the GPU; creating a :class:`Simulation` loads the library and fails
 loudly if it has not been built.
 """
 from ._lib import TCMError, EXPORTS  # noqa: F401
-from .sim import Simulation, Snapshot, version  # noqa: F401
+from .sim import Simulation, Snapshot, hbm_probe, version  # noqa: F401
 
 __all__ = ["Simulation", "TCMError", "version"]

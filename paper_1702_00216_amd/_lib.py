@@ -20,7 +20,7 @@ EXPORTS = [
     "tcm_create", "tcm_create_batch", "tcm_add_source", "tcm_add_source_shot", "tcm_step",
     "tcm_read", "tcm_read_shot", "tcm_set_receivers", "tcm_read_traces", "tcm_adjoint",
     "tcm_reset", "tcm_stats", "tcm_destroy", "tcm_last_error", "tcm_version", "tcm_autotune",
-    "tcm_set_launch", "tcm_snapshot", "tcm_restore", "tcm_snapshot_free",
+    "tcm_set_launch", "tcm_snapshot", "tcm_restore", "tcm_snapshot_free", "tcm_hbm_probe",
 ]
 
 
@@ -105,6 +105,7 @@ def lib():
         L.tcm_snapshot_free.restype = None
         L.tcm_autotune.argtypes = [H, I, F(Tuning)]
         L.tcm_set_launch.argtypes = [H, I, I, I]
+        L.tcm_hbm_probe.argtypes = [P, P, C.c_uint64, I, I, I, P, F(C.c_float)]
         L.tcm_stats.argtypes = [H, F(Stats)]
         L.tcm_destroy.argtypes = [H]
         L.tcm_destroy.restype = None

@@ -173,5 +173,9 @@ hipError_t launch_grad_flush(double* g, float* gs, long long n, hipStream_t s);
 constexpr int GRAD_GROUP = 32;
 hipError_t launch_grad_finish(const Shot& shot, const Shot* dshot, const double* g, float* out,
                               hipStream_t s);
+// HBM ceiling probe (n floats per source, n a multiple of hbm_probe_chunk())
+long long hbm_probe_chunk();
+hipError_t launch_hbm_probe(const float* src, float* dst, long long n, int nread, int grid, hipStream_t s,
+                            hipEvent_t e0, hipEvent_t e1);
 
 }  // namespace tcmk

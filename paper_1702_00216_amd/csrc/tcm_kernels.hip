@@ -225,14 +225,23 @@ __global__ __launch_bounds__(64 * W) void k_block_step(Tables t) {
     // face loaders: lane -> (a, zz) on a side face
     const int a = lane & 7, zz = lane >> 3;
 
-    // XCD-aware split: workgroup b runs on XCD b % 8; each XCD walks its own
-    // contiguous eighth of the (spatially ordered) list so that neighbouring
-    // blocks share that XCD's L2.
+    // XCD-aware split: workgroup b runs on XCD b % 8.  The (spatially
+    // ordered) list is cut into groups of 2^lg entries dealt round-robin to
+    // the XCDs, so neighbouring blocks of a group share one XCD's L2 while all
+    // XCDs sweep one common window of the pool (one front in HBM rather than
+    // eight).  Entry j of XCD x is list entry gidx(j).  Groups are 256 entries
+    // (four 4^3 tiles), fewer for short lists so that every XCD has work.
     const int per = gridDim.x >> 3;
     const int xcd = blockIdx.x & 7, jw = blockIdx.x >> 3;
-    const int seg = (nact + 7) >> 3;
-    const int beg = xcd * seg;
-    const int end = min(nact, beg + seg);
+    int lg = 8;
+    while (lg > 3 && (nact >> 3) < (1 << lg)) lg--;          // W <= 8 divides every group
+    const int grp = 1 << lg;
+    const int ng = (nact + grp - 1) >> lg;
+    const int nfull = nact >> lg, rem = nact - (nfull << lg);
+    int end = ng > xcd ? (((ng - 1 - xcd) >> 3) + 1) << lg : 0;
+    if (rem && (nfull & 7) == xcd) end -= grp - rem;          // the partial group is this XCD's last
+    const int beg = 0;
+    auto gidx = [&](int j) { return ((((j >> lg) << 3) + xcd) << lg) + (j & (grp - 1)); };
     const float trig = t.trigger, ret = t.retire;
     float wave_max = 0.f;
 
@@ -254,9 +263,9 @@ __global__ __launch_bounds__(64 * W) void k_block_step(Tables t) {
         const int i = ib + wid;
         if (i < end) {
 #pragma unroll
-            for (int k = 0; k < 8; k++) r[k] = rows[8 * (size_t)i + k];
-            if (wid > 0) sl_prev = rows[8 * (size_t)(i - 1)];
-            if (wid < W - 1 && i + 1 < end) sl_next = rows[8 * (size_t)(i + 1)];
+            for (int k = 0; k < 8; k++) r[k] = rows[8 * (size_t)gidx(i) + k];
+            if (wid > 0) sl_prev = rows[8 * (size_t)gidx(i - 1)];
+            if (wid < W - 1 && i + 1 < end) sl_next = rows[8 * (size_t)gidx(i + 1)];
         }
     }
     int buf = 0;
@@ -274,9 +283,9 @@ __global__ __launch_bounds__(64 * W) void k_block_step(Tables t) {
             sl_next = EMPTY;
             if (in < end) {
 #pragma unroll
-                for (int k = 0; k < 8; k++) r[k] = rows[8 * (size_t)in + k];
-                if (wid > 0) sl_prev = rows[8 * (size_t)(in - 1)];
-                if (wid < W - 1 && in + 1 < end) sl_next = rows[8 * (size_t)(in + 1)];
+                for (int k = 0; k < 8; k++) r[k] = rows[8 * (size_t)gidx(in) + k];
+                if (wid > 0) sl_prev = rows[8 * (size_t)gidx(in - 1)];
+                if (wid < W - 1 && in + 1 < end) sl_next = rows[8 * (size_t)gidx(in + 1)];
             }
         }
         float* T = lds[buf][wid];
@@ -1396,6 +1405,49 @@ hipError_t launch_grad_finish(const Shot& shot, const Shot* dshot, const double*
     if (grid > 65536) grid = 65536;
     if (grid < 1) grid = 1;
     hipLaunchKernelGGL(k_grad_finish, dim3((unsigned)grid), dim3(256), 0, s, dshot, g, out);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// HBM ceiling probe.  dst = src_0 (+ src_1 (+ src_2)), streamed the way the
+// block stencil streams its planes: each lane owns one float of a 64-float
+// row, a wave moves 256 contiguous bytes per access, loads and stores are
+// non-temporal, and every thread handles PROBE_UNROLL rows 256 floats apart
+// so that the loads of one thread are in flight together.  With three
+// sources the read:write mix is the stencil's 12:4 bytes per node.
+constexpr int PROBE_UNROLL = 8;
+constexpr long long PROBE_CHUNK = 256LL * PROBE_UNROLL;   // floats per workgroup pass
+
+template <int NR>
+__global__ __launch_bounds__(256) void k_hbm_probe(const float* __restrict__ src, float* __restrict__ dst,
+                                                  long long n) {
+    const long long nchunks = n / PROBE_CHUNK;
+    for (long long c = blockIdx.x; c < nchunks; c += gridDim.x) {
+        const long long base = c * PROBE_CHUNK + threadIdx.x;
+        float v[PROBE_UNROLL];
+#pragma unroll
+        for (int u = 0; u < PROBE_UNROLL; u++) v[u] = __builtin_nontemporal_load(&src[base + u * 256]);
+        if (NR >= 2) {
+#pragma unroll
+            for (int u = 0; u < PROBE_UNROLL; u++) v[u] += __builtin_nontemporal_load(&src[n + base + u * 256]);
+        }
+        if (NR >= 3) {
+#pragma unroll
+            for (int u = 0; u < PROBE_UNROLL; u++)
+                v[u] += __builtin_nontemporal_load(&src[2 * n + base + u * 256]);
+        }
+#pragma unroll
+        for (int u = 0; u < PROBE_UNROLL; u++) __builtin_nontemporal_store(v[u], &dst[base + u * 256]);
+    }
+}
+
+long long hbm_probe_chunk() { return PROBE_CHUNK; }
+
+hipError_t launch_hbm_probe(const float* src, float* dst, long long n, int nread, int grid, hipStream_t s,
+                            hipEvent_t e0, hipEvent_t e1) {
+    void (*k)(const float*, float*, long long) =
+        nread == 1 ? k_hbm_probe<1> : nread == 2 ? k_hbm_probe<2> : k_hbm_probe<3>;
+    hipExtLaunchKernelGGL(k, dim3(grid), dim3(256), 0, s, e0, e1, 0, src, dst, n);
     return hipGetLastError();
 }
 

@@ -710,6 +710,41 @@ extern "C" {
 
 const char* tcm_version(void) { return "tcm-mi355x 0.1 (gfx950)"; }
 
+tcm_status tcm_hbm_probe(const float* src, float* dst, uint64_t n, int32_t nread, int32_t wg_per_cu,
+                         int32_t reps, void* stream, float* best_ms) {
+    if (!src || !dst || !best_ms) return set_err(nullptr, TCM_E_ARG, "hbm probe: NULL pointer");
+    const uint64_t chunk = (uint64_t)tcmk::hbm_probe_chunk();
+    if (n == 0 || n % chunk) return set_err(nullptr, TCM_E_ARG, fmt("hbm probe: n must be a positive multiple of %llu", (unsigned long long)chunk));
+    if (nread < 1 || nread > 3) return set_err(nullptr, TCM_E_ARG, "hbm probe: nread must be 1, 2 or 3");
+    if (wg_per_cu < 0 || wg_per_cu > 32) return set_err(nullptr, TCM_E_ARG, "hbm probe: wg_per_cu must be 0..32");
+    if (reps < 1 || reps > 1000) return set_err(nullptr, TCM_E_ARG, "hbm probe: reps must be 1..1000");
+    const uintptr_t s0 = (uintptr_t)src, s1 = s0 + (uintptr_t)nread * n * sizeof(float);
+    const uintptr_t d0 = (uintptr_t)dst, d1 = d0 + (uintptr_t)n * sizeof(float);
+    if (d0 < s1 && s0 < d1) return set_err(nullptr, TCM_E_ARG, "hbm probe: dst overlaps src");
+    int dev = 0, ncu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return dev_fail(nullptr, e, "hbm probe: device query");
+    const int grid = std::max(1, ncu * (wg_per_cu ? wg_per_cu : 8));
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    float best = -1.0f;
+    for (int r = 0; r < reps && e == hipSuccess; r++) {
+        e = tcmk::launch_hbm_probe(src, dst, (long long)n, nread, grid, s, e0, e1);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e == hipSuccess && (best < 0.0f || ms < best)) best = ms;
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return dev_fail(nullptr, e, "hbm probe");
+    *best_ms = best;
+    return TCM_OK;
+}
+
 const char* tcm_last_error(const tcm_handle* h) {
     if (!h) return g_create_error.c_str();
     return h->err.c_str();

@@ -274,3 +274,23 @@ class Snapshot:
 
 def version() -> str:
     return L.lib().tcm_version().decode()
+
+
+def hbm_probe(nread: int = 3, n: int = 1 << 28, wg_per_cu: int = 0, reps: int = 5) -> dict:
+    """Achievable HBM bandwidth of a stencil-shaped streaming kernel
+    (tcm_hbm_probe): nread sources of n floats each, one destination.
+    Returns the best launch time and the GB/s it moves."""
+    import torch
+    src = torch.ones(nread * n, dtype=torch.float32, device="cuda")
+    dst = torch.empty(n, dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+    ms = C.c_float(0.0)
+    rc = L.lib().tcm_hbm_probe(src.data_ptr(), dst.data_ptr(), n, nread, wg_per_cu, reps, stream,
+                               C.byref(ms))
+    if rc != 0:
+        raise L.TCMError(rc, L.lib().tcm_last_error(None).decode())
+    ok = bool(torch.all(dst == float(nread)).item())
+    del src, dst
+    nbytes = (nread + 1) * 4 * n
+    return {"nread": nread, "bytes": nbytes, "best_ms": ms.value,
+            "GBps": nbytes / (ms.value * 1e-3) / 1e9, "wg_per_cu": wg_per_cu or 8, "result_ok": ok}
