@@ -142,6 +142,29 @@ def cpu_baseline(w, budget_s: float):
                             "sample": f"steps 0-{done1} ({st1['updates']:.3e} updates in {el1:.1f} s)"}}
 
 
+def add_ceiling(tcm, roof, fu=None):
+    """The achievable HBM ceiling of a kernel of the stencil's shape
+    (tcm_hbm_probe): the best of a few grid sizes for each read:write mix
+    (2:1 for nodes of blocks with a uniform C2, 3:1 otherwise), blended by
+    the nodes of each kind, and the stencil's fraction of it."""
+    def best_probe(nread):
+        return max((tcm.hbm_probe(nread, wg_per_cu=g) for g in (4, 8, 16)), key=lambda p: p["GBps"])
+    if fu is None:
+        fu = roof["uniform_c2_node_fraction"]
+    p2, p3 = best_probe(2), best_probe(3)
+    copy1 = tcm.hbm_probe(1, wg_per_cu=p3["wg_per_cu"])
+    per_node_ns = fu * 12 / p2["GBps"] + (1 - fu) * 16 / p3["GBps"]
+    ceil = (fu * 12 + (1 - fu) * 16) / per_node_ns
+    roof["ceiling"] = {"kernel": "k_hbm_probe (nread sources + 1 destination, 1 GiB per stream)",
+                       "GBps": round(ceil, 1), "frac": round(roof["achieved"] / ceil, 4),
+                       "read2_write1_GBps": round(p2["GBps"], 1), "read3_write1_GBps": round(p3["GBps"], 1),
+                       "copy_GBps": round(copy1["GBps"], 1),
+                       "blend": f"{fu:.4f} of the nodes at 2:1, the rest at 3:1",
+                       "results_ok": all(p["result_ok"] for p in (p2, p3, copy1))}
+    log(f"HBM probe: {p2['GBps']:.0f} GB/s (2 reads : 1 write), {p3['GBps']:.0f} GB/s (3 : 1), "
+        f"copy {copy1['GBps']:.0f} GB/s; stencil at {roof['ceiling']['frac']:.1%} of the blended probe")
+
+
 def _line(metric_value, steps, warmup, ms, config, **extra):
     out = {"metric": "TCM active-cell updates/s + HBM GB/s vs dense FDTD on same GPU at equal error",
            "value": metric_value, "unit": "active-cell updates/s", "n_gpus": 1, "steps": steps,
@@ -183,7 +206,16 @@ def bench_c3(args, tcm):
     st = sim.stats()
     sim.close()
     nx, ny, nz = w.shape
-    achieved = BYTES_PER_UPDATE * st["stencil_cells"] / (st["stencil_ms"] * 1e-3) / 1e9
+    alg = BYTES_PER_UPDATE * st["stencil_cells"] - 4 * st["stencil_cells_uniform"]
+    achieved = alg / (st["stencil_ms"] * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": "k_block_step",
+            "avg_launch_us": round(st["stencil_ms"] * 1e3 / max(st["stencil_launches"], 1), 2),
+            "algorithmic_bytes_per_launch": round(alg / max(st["stencil_launches"], 1)),
+            "uniform_c2_node_fraction": round(st["stencil_cells_uniform"] / max(st["stencil_cells"], 1), 4)}
+    if not args.no_probe:
+        add_ceiling(tcm, roof)
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline_crop(w, args.cpu_budget)
@@ -191,9 +223,7 @@ def bench_c3(args, tcm):
           {"workload": f"c3: virtual {nx}x{ny}x{nz} lognormal (sigma 16, [1500,4500], seed 3), Ricker "
                        f"100 Hz at the centre, {steps} steps, trigger 1e-6 / retire 1e-7 of peak, "
                        f"pool cap {w.pool_bytes / 1e9:.0f} GB", "time_steps_per_run": steps},
-          roofline={"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                    "kernel": "k_block_step"},
+          roofline=roof,
           cpu_baseline=cpu,
           tcm={"steps_done": st["step"], "error": err, "peak_active_blocks": st["peak_active_blocks"],
                "peak_pool_bytes": st["peak_pool_bytes"], "pool_bytes": st["pool_bytes"],
@@ -309,7 +339,10 @@ def bench_c4(args, tcm):
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_block_step",
             "avg_launch_us": round(ts["stencil_ms"] * 1e3 / max(ts["stencil_launches"], 1), 2),
-            "algorithmic_bytes_per_launch": round(alg / max(ts["stencil_launches"], 1))}
+            "algorithmic_bytes_per_launch": round(alg / max(ts["stencil_launches"], 1)),
+            "uniform_c2_node_fraction": round(ts["stencil_cells_uniform"] / max(ts["stencil_cells"], 1), 4)}
+    if not args.no_probe:
+        add_ceiling(tcm, roof)
     cpu = None
     if not args.no_cpu:
         # the CPU TCM oracle on shot 0 (the same media, thresholds and steps), bounded
@@ -395,6 +428,30 @@ def bench_c5(args, tcm):
     sim.close()
     nodes = w.shape[0] * w.shape[1] * w.shape[2]
     tot = (tf + ta) / args.steps
+    # one more forward + adjoint with HIP events around every gradient launch
+    # (16 B per node of an active adjoint block: u, mu, gs read, gs written)
+    roof = None
+    if not args.no_roofline:
+        tsim = tcm.Simulation(w.shape, w.dx, w.dt, c, checkpoint_every=50, timing=True,
+                              wg_per_cu=(tuning or {}).get("wg_per_cu", args.wg_per_cu),
+                              blocks_per_wg=(tuning or {}).get("blocks_per_wg", args.blocks_per_wg))
+        tsim.add_source(w.source, w.wavelet.w32)
+        tsim.set_receivers(w.receivers)
+        tsim.step(steps)
+        tsim.adjoint(resid)
+        ts = tsim.stats()
+        tsim.close()
+        if ts["grad_launches"] > 0 and ts["grad_ms"] > 0:
+            alg = 16 * ts["grad_cells"]
+            achieved = alg / (ts["grad_ms"] * 1e-3) / 1e9
+            roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_adjoint_grad",
+                    "avg_launch_us": round(ts["grad_ms"] * 1e3 / ts["grad_launches"], 2),
+                    "algorithmic_bytes_per_launch": round(alg / ts["grad_launches"]),
+                    "active_node_fraction": round(ts["grad_cells"] / (nodes * ts["grad_launches"]), 4)}
+            if not args.no_probe:
+                add_ceiling(tcm, roof, fu=0.0)
+            log(f"c5 gradient kernel: {roof['avg_launch_us']:.1f} us per launch, {achieved:.0f} GB/s")
     cpu = None
     if not args.no_cpu:
         import oracle
@@ -420,7 +477,7 @@ def bench_c5(args, tcm):
            "config": {"workload": f"c5: 256^3 lognormal (seed 5), Ricker 100 Hz at {w.source}, {steps} steps, "
                                   f"128 receivers on z = 240, checkpoints every 50, threshold 0",
                       "time_steps_per_run": steps},
-           "roofline": None, "cpu_baseline": cpu,
+           "roofline": roof, "cpu_baseline": cpu,
            "adjoint": {"forward_s": round(tf / args.steps, 4), "adjoint_s": round(ta / args.steps, 4),
                        "adjoint_over_forward": round(ta / tf, 3)}, "autotune": tuning}
     print(json.dumps(out), flush=True)
@@ -455,6 +512,7 @@ def main():
     ap.add_argument("--no-graph-replay", action="store_true",
                     help="skip the hipGraph replay run (counter-collection runs)")
     ap.add_argument("--no-probe", action="store_true", help="skip the HBM ceiling probe")
+    ap.add_argument("--no-roofline", action="store_true", help="c5: skip the timed gradient pass")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device-to-device torch copy (counter calibration)")
     args = ap.parse_args()
@@ -543,19 +601,8 @@ def main():
                 "uniform_c2_node_fraction": round(st_cells_u / max(st_cells, 1), 4),
                 "achieved_if_16B_per_node": round(BYTES_PER_UPDATE * st_cells / (st_ms * 1e-3) / 1e9, 1)}
 
-    # the achievable HBM ceiling of a kernel of the stencil's shape (three
-    # streams in, one out, non-temporal): best over a few grid sizes
     if roof and not args.no_probe:
-        probes = [tcm.hbm_probe(3, wg_per_cu=g) for g in (4, 8, 16)]
-        best = max(probes, key=lambda p: p["GBps"])
-        copy1 = tcm.hbm_probe(1, wg_per_cu=best["wg_per_cu"])
-        roof["ceiling"] = {"kernel": "k_hbm_probe (12 B read : 4 B written per element, 1 GiB per stream)",
-                           "GBps": round(best["GBps"], 1), "wg_per_cu": best["wg_per_cu"],
-                           "frac": round(roof["achieved"] / best["GBps"], 4),
-                           "copy_GBps": round(copy1["GBps"], 1),
-                           "results_ok": all(p["result_ok"] for p in probes + [copy1])}
-        log(f"HBM probe: {best['GBps']:.0f} GB/s (3 reads : 1 write), copy {copy1['GBps']:.0f} GB/s; "
-            f"stencil at {roof['ceiling']['frac']:.1%} of the probe")
+        add_ceiling(tcm, roof)
 
     dense = None
     if not args.no_dense:

@@ -144,6 +144,10 @@ typedef struct {
     int64_t decay_block_steps;    /* block-steps of the shutdown decay (eq.(6)) */
     double  trigger_level;        /* levels used by the last step (adaptive or constant) */
     double  retire_level;
+    double  grad_ms;              /* TCM_FLAG_TIMING: summed gradient-kernel time of tcm_adjoint calls */
+    int64_t grad_launches;        /* TCM_FLAG_TIMING: launches summed in grad_ms (one per adjoint step) */
+    int64_t grad_cells;           /* TCM_FLAG_TIMING: adjoint-field node updates of those calls (the nodes
+                                   * whose gradient term the kernel formed) */
 } tcm_stats_t;
 
 /* Create a single-shot handle (eq.(3) on an nx*ny*nz grid, "Cells construction").

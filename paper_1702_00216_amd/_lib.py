@@ -57,7 +57,8 @@ class Stats(C.Structure):
                 ("stencil_ms", C.c_double), ("stencil_launches", C.c_int64),
                 ("stencil_cells", C.c_int64), ("uniform_cell_updates", C.c_int64),
                 ("stencil_cells_uniform", C.c_int64), ("decay_block_steps", C.c_int64),
-                ("trigger_level", C.c_double), ("retire_level", C.c_double)]
+                ("trigger_level", C.c_double), ("retire_level", C.c_double),
+                ("grad_ms", C.c_double), ("grad_launches", C.c_int64), ("grad_cells", C.c_int64)]
 
 
 class Tuning(C.Structure):

@@ -165,7 +165,7 @@ hipError_t launch_read_dense(const float* f, int nx, int ny, int x0, int y0, int
 hipError_t launch_receiver_c2(const Shot* shots, const int* xyz, const int* rshot, int nrec,
                               double dt, double dx, float* out, hipStream_t s);
 hipError_t launch_adjoint_grad(const Tables& mu, const Shot& shot, const float* u, float* gs,
-                               hipStream_t s);
+                               hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_grad_flush(double* g, float* gs, long long n, hipStream_t s);
 // adjoint steps whose FP32 partial gradient is summed before it is folded
 // into the FP64 gradient (groups of absolute step numbers, so the result does

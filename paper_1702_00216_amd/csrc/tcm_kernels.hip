@@ -1300,70 +1300,60 @@ hipError_t launch_receiver_c2(const Shot* shots, const int* xyz, const int* rsho
     return hipGetLastError();
 }
 
-// g += mu^m * (L u^{m-1}) over the blocks where the adjoint field is active
-// (mu is zero elsewhere).  mu: current level of the adjoint tables; u: the
-// forward level as a dense grid of shot 0; L with zero ghosts, in FP64.
 // gs += mu^m (L u^{m-1}) at every node of a block active in the adjoint field
-// (mu is zero elsewhere); the product is formed in FP64 and summed in FP32
-// over a group of adjoint steps, then folded into the FP64 gradient
-// (k_grad_flush).  One thread per node along x-fastest rows, GB rows at a
-// time (block-table loads, then mu, u and gs loads, then the updates), so the
-// dense u snapshot and the accumulator move in full rows; mu comes from the
-// adjoint pool through the block table.
-constexpr int GRAD_RB = 4;
+// (mu is zero elsewhere); u is the forward level as a dense grid of shot 0, L
+// has zero ghosts.  The Laplacian and the product are formed in FP32, as the
+// forward update forms the same Laplacian of the same FP32 values; the sum
+// runs in FP32 over a group of adjoint steps, then is folded into the FP64
+// gradient (k_grad_flush).  (FP64 here cost a third more time per launch for
+// no gain over the FP32 forward's own error.)  The dense snapshot is walked
+// like the dense stencil: a workgroup owns a 128 x 4 column of nodes over one
+// 8^3 block of planes along z, carrying u of the planes below and above in
+// registers, with the column's block slot looked up first.  u, gs and mu move
+// in full cache lines (the four y rows of a tile plane in one 8^3 block are
+// 128 contiguous bytes of that block's mu plane); at 256^3 the grid is 4096
+// workgroups (measured: 8 planes per workgroup beat 16 and 32).
+constexpr int GRAD_TX = 128, GRAD_TY = 4, GRAD_DZ = 8;
 
-__global__ __launch_bounds__(256) void k_adjoint_grad(Tables mu, const float* __restrict__ u,
-                                                       float* __restrict__ gs) {
+__global__ __launch_bounds__(GRAD_TX * GRAD_TY) void k_adjoint_grad(Tables mu, const float* __restrict__ u,
+                                                                   float* __restrict__ gs) {
     const DevState* st = mu.st;
     const int plane = st->step & 1;
     const Shot& S = mu.shots[0];
-    const int gx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (gx >= S.nx) return;
+    const int x = blockIdx.x * GRAD_TX + (int)(threadIdx.x % GRAD_TX);
+    const int y = blockIdx.y * GRAD_TY + (int)(threadIdx.x / GRAD_TX);
+    const int z0 = blockIdx.z * GRAD_DZ;
+    if (x >= S.nx || y >= S.ny) return;
     const size_t sy = (size_t)S.nx, sz = (size_t)S.nx * S.ny;
-    const long long rows = (long long)S.ny * S.nz;
-    for (long long r0 = (long long)blockIdx.y * GRAD_RB; r0 < rows; r0 += (long long)gridDim.y * GRAD_RB) {
-        int slot[GRAD_RB], gyk[GRAD_RB], gzk[GRAD_RB];
-#pragma unroll
-        for (int k = 0; k < GRAD_RB; k++) {
-            const long long row = r0 + k;
-            slot[k] = EMPTY;
-            gyk[k] = 0;
-            gzk[k] = 0;
-            if (row < rows) {
-                gyk[k] = (int)(row % S.ny);
-                gzk[k] = (int)(row / S.ny);
-                slot[k] = mu.cell2box[S.key_base + (long long)block_to_key(S, gx >> 3, gyk[k] >> 3, gzk[k] >> 3)];
-            }
+    const int z1 = min(S.nz, z0 + GRAD_DZ);
+    const int slot = mu.cell2box[S.key_base + (long long)block_to_key(S, x >> 3, y >> 3, z0 >> 3)];
+    const float* __restrict__ mub = mu.pool + (size_t)(slot >= 0 ? slot : 0) * SLOT + plane * BV +
+                                    (y & 7) * 8 + (x & 7);
+    size_t i = (size_t)z0 * sz + (size_t)y * sy + (size_t)x;
+    float zm = z0 > 0 ? u[i - sz] : 0.f;
+    float c = u[i];
+    for (int z = z0; z < z1; z++, i += sz) {
+        const float zp = z + 1 < S.nz ? u[i + sz] : 0.f;
+        if (slot >= 0) {
+            const float xm = x > 0 ? u[i - 1] : 0.f, xp = x + 1 < S.nx ? u[i + 1] : 0.f;
+            const float ym = y > 0 ? u[i - sy] : 0.f, yp = y + 1 < S.ny ? u[i + sy] : 0.f;
+            const float lap = (((xp + xm) + (yp + ym)) + (zp + zm)) - 6.0f * c;
+            const float m = mub[(z & 7) * 64];
+            gs[i] = gs[i] + m * lap;
         }
-        float m[GRAD_RB], acc[GRAD_RB];
-        double lap[GRAD_RB];
-#pragma unroll
-        for (int k = 0; k < GRAD_RB; k++) {
-            m[k] = 0.f;
-            acc[k] = 0.f;
-            lap[k] = 0.0;
-            if (slot[k] < 0) continue;
-            const int gy = gyk[k], gz = gzk[k];
-            m[k] = mu.pool[(size_t)slot[k] * SLOT + plane * BV + ((gz & 7) * 8 + (gy & 7)) * 8 + (gx & 7)];
-            const size_t idx = (size_t)(r0 + k) * sy + (size_t)gx;
-            const double c = u[idx];
-            const double xm = gx > 0 ? u[idx - 1] : 0.0, xp = gx + 1 < S.nx ? u[idx + 1] : 0.0;
-            const double ym = gy > 0 ? u[idx - sy] : 0.0, yp = gy + 1 < S.ny ? u[idx + sy] : 0.0;
-            const double zm = gz > 0 ? u[idx - sz] : 0.0, zp = gz + 1 < S.nz ? u[idx + sz] : 0.0;
-            lap[k] = (((xp + xm) + (yp + ym)) + (zp + zm)) - 6.0 * c;
-            acc[k] = gs[idx];
-        }
-#pragma unroll
-        for (int k = 0; k < GRAD_RB; k++)
-            if (slot[k] >= 0) gs[(size_t)(r0 + k) * sy + (size_t)gx] = acc[k] + (float)((double)m[k] * lap[k]);
+        zm = c;
+        c = zp;
     }
 }
 
 hipError_t launch_adjoint_grad(const Tables& mu, const Shot& shot, const float* u, float* gs,
-                               hipStream_t s) {
-    const long long groups = ((long long)shot.ny * shot.nz + GRAD_RB - 1) / GRAD_RB;
-    dim3 grid((unsigned)((shot.nx + 255) / 256), (unsigned)std::min<long long>(groups, 65535));
-    hipLaunchKernelGGL(k_adjoint_grad, grid, dim3(256), 0, s, mu, u, gs);
+                               hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    dim3 grid((shot.nx + GRAD_TX - 1) / GRAD_TX, (shot.ny + GRAD_TY - 1) / GRAD_TY,
+              (shot.nz + GRAD_DZ - 1) / GRAD_DZ);
+    if (e0 || e1)
+        hipExtLaunchKernelGGL(k_adjoint_grad, grid, dim3(GRAD_TX * GRAD_TY), 0, s, e0, e1, 0, mu, u, gs);
+    else
+        hipLaunchKernelGGL(k_adjoint_grad, grid, dim3(GRAD_TX * GRAD_TY), 0, s, mu, u, gs);
     return hipGetLastError();
 }
 

@@ -82,6 +82,9 @@ struct tcm_handle {
     // timing (TCM_FLAG_TIMING)
     std::vector<hipEvent_t> events;
     double stencil_ms = 0.0;
+    double grad_ms = 0.0;               // gradient kernel of tcm_adjoint (timing flag)
+    long long grad_launches = 0, grad_cells = 0;
+    std::vector<hipEvent_t> gev;        // events around the timed gradient launches
     long long stencil_launches = 0, stencil_cells = 0, stencil_cells_u = 0;
 
     // dense engine
@@ -254,6 +257,8 @@ void destroy_all(tcm_handle* h) {
     drop_graph(h);
     for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
     h->events.clear();
+    for (hipEvent_t e : h->gev) (void)hipEventDestroy(e);
+    h->gev.clear();
     for (void* p : h->allocs) (void)hipFree(p);
     h->allocs.clear();
     if (h->h_state) (void)hipHostFree(h->h_state);
@@ -1073,6 +1078,9 @@ tcm_status tcm_stats(tcm_handle* h, tcm_stats_t* o) {
     o->stencil_launches = h->stencil_launches;
     o->stencil_cells = h->stencil_cells;
     o->stencil_cells_uniform = h->stencil_cells_u;
+    o->grad_ms = h->grad_ms;
+    o->grad_launches = h->grad_launches;
+    o->grad_cells = h->grad_cells;
     o->table_bytes = (int64_t)h->table_bytes;
     if (h->engine == TCM_ENGINE_DENSE) {
         HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
@@ -1138,6 +1146,9 @@ tcm_status tcm_reset(tcm_handle* h) {
     h->stencil_launches = 0;
     h->stencil_cells = 0;
     h->stencil_cells_u = 0;
+    h->grad_ms = 0.0;
+    h->grad_launches = 0;
+    h->grad_cells = 0;
     if (h->engine == TCM_ENGINE_DENSE) {
         const Shot& S = h->shots[0];
         const size_t N = (size_t)S.nx * S.ny * S.nz;
@@ -1310,6 +1321,18 @@ tcm_status tcm_adjoint(tcm_handle* h, const float* resid, int32_t nt, int32_t re
         return set_err(h, TCM_E_NOMEM, "no device memory for the adjoint level buffers");
     }
     h->in_adjoint = true;
+    // timed runs: events around every gradient launch of a segment, read
+    // after the segment
+    const bool timing = (h->cfg.flags & TCM_FLAG_TIMING) != 0;
+    while (timing && (int)h->gev.size() < 2 * K) {
+        hipEvent_t ev;
+        if (hipEventCreate(&ev) != hipSuccess) {
+            (void)hipGetLastError();
+            cleanup();
+            return set_err(h, TCM_E_DEVICE, "hipEventCreate failed");
+        }
+        h->gev.push_back(ev);
+    }
     hipError_t e = hipMemsetAsync(g, 0, sizeof(double) * N, h->stream);
     if (e == hipSuccess) e = hipMemsetAsync(gs, 0, sizeof(float) * N, h->stream);
     for (int j = nseg - 1; j >= 0 && e == hipSuccess; j--) {
@@ -1325,9 +1348,21 @@ tcm_status tcm_adjoint(tcm_handle* h, const float* resid, int32_t nt, int32_t re
         }
         // adjoint levels mu^{end} .. mu^{s0+1}, each with L u^{m-1}
         for (int m = end; m > s0 && e == hipSuccess; m--) {
+            const int q = end - m;
             e = enqueue_step(a, nullptr, nullptr);
-            if (e == hipSuccess) e = launch_adjoint_grad(a->t, S, lvl + (size_t)(m - 1 - s0) * N, gs, h->stream);
+            if (e == hipSuccess)
+                e = launch_adjoint_grad(a->t, S, lvl + (size_t)(m - 1 - s0) * N, gs, h->stream,
+                                        timing ? h->gev[2 * q] : nullptr, timing ? h->gev[2 * q + 1] : nullptr);
             if (e == hipSuccess && (m - 1) % GRAD_GROUP == 0) e = launch_grad_flush(g, gs, (long long)N, h->stream);
+        }
+        if (timing && e == hipSuccess) {
+            e = hipStreamSynchronize(h->stream);
+            for (int q = 0; q < end - s0 && e == hipSuccess; q++) {
+                float ms = 0.f;
+                e = hipEventElapsedTime(&ms, h->gev[2 * q], h->gev[2 * q + 1]);
+                h->grad_ms += ms;
+            }
+            h->grad_launches += end - s0;
         }
     }
     if (e != hipSuccess) { cleanup(); return dev_fail(h, e, "adjoint sweep"); }
@@ -1343,6 +1378,7 @@ tcm_status tcm_adjoint(tcm_handle* h, const float* resid, int32_t nt, int32_t re
     st = sync_state(a);
     if (st) { cleanup(); return set_err(h, st, "adjoint tables failed"); }
     const int aerr = a->h_state->error;
+    if (timing) h->grad_cells += a->h_state->updates;
     st = ck_restore(h, now);
     if (st) { cleanup(); return st; }
     st = sync_state(h);

@@ -104,3 +104,23 @@ def test_autograd_function_gradient():
         e = np.linalg.norm(g - ref) / np.linalg.norm(ref)
         print(f"autograd ({dev}) rel-L2 vs FP64 = {e:.3e}")
         assert e <= 1e-3
+
+
+def test_timed_adjoint_counts_gradient_launches_and_keeps_results():
+    """With the timing flag every gradient launch is timed (one per adjoint
+    step) and counted; the gradient is the one an untimed run gives."""
+    announce("adjoint timing statistics")
+    c, dt, w, src, rec, resid, nt = setup(nt=45, seed=9)
+    sim_a, ga = gpu_grad(c, dt, w, src, rec, resid, nt, K=20)
+    sim_t = tcm.Simulation(c.shape[::-1], 1.0, dt, c, checkpoint_every=20, timing=True)
+    sim_t.add_source(src, w)
+    sim_t.set_receivers(rec)
+    sim_t.step(nt)
+    gt = sim_t.adjoint(resid)
+    st = sim_t.stats()
+    assert np.array_equal(ga, gt)
+    assert st["grad_launches"] == nt and st["grad_ms"] > 0.0
+    nodes = c.size
+    # at threshold 0 the adjoint field grows from the receivers: some, at most all, nodes per step
+    assert 0 < st["grad_cells"] <= nodes * nt
+    assert sim_a.stats()["grad_launches"] == 0
