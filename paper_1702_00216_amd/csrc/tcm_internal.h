@@ -56,6 +56,8 @@ struct DevState {
     float trig_cur, ret_cur;         // levels used by the last plan
     int n_ne;                        // per step: chunks of the bitmap with a set bit
     unsigned long long activations, retirements;
+    int free_next;                   // free slots after this step's allocation: installed, and the
+                                     // step's n_new / n_ret / n_dec cleared, by the compaction
 };
 
 struct Src {

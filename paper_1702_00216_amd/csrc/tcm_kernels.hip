@@ -186,6 +186,7 @@ __global__ void k_init_tables(Tables t, long long nkeys) {
         st->cells_cur = 0; st->updates = 0; st->activations = 0; st->retirements = 0;
         st->cells_cur_u = 0; st->updates_u = 0; st->decays = 0;
         st->maxbits = 0u; st->trig_cur = t.trigger; st->ret_cur = t.retire; st->n_ne = 0;
+        st->free_next = t.cap;
     }
 }
 
@@ -736,6 +737,37 @@ hipError_t launch_advance(const Tables& t, hipStream_t s) {
 // K3a + K4: pool allocator and bitmap popcounts; the last workgroup scans the
 // counts and commits the step ("Boxes": vacant boxes are reused).
 // --------------------------------------------------------------------------
+// End of the activation update (one thread): the step's counters, the next
+// list's length, and whether the compaction emits it (0: the step failed).
+// The counters that every allocating workgroup reads at its start (n_new,
+// n_ret, n_dec, free_cnt) are left alone here, since some of those
+// workgroups may not have started yet: the compaction, the next launch,
+// installs free_next and clears the others.
+constexpr int SCAN1_MAX = 4;          // chunks per thread of the one-workgroup scan
+__device__ void commit_step(const Tables& t, DevState* st, int nn, int nr, int nfree, unsigned total) {
+    const int err = st->error;
+    if (!err || st->err_step == st->step) {   // the step's phi^{n+1} is complete
+        st->updates += st->cells_cur;
+        st->updates_u += st->cells_cur_u;
+        st->step += 1;
+    }
+    st->free_next = err ? nfree : nfree + nr - nn;
+    if (!err) {
+        st->activations += (unsigned long long)nn;
+        st->retirements += (unsigned long long)nr;
+        st->decays += (unsigned long long)st->n_dec;
+        st->n_act = (int)total;
+        if ((int)total > st->peak_act) st->peak_act = (int)total;
+        st->cells_cur = 0;
+        st->cells_cur_u = 0;
+        st->emit = 1;
+    } else {
+        st->emit = 0;
+    }
+    st->maxbits = 0u;
+    __threadfence();
+}
+
 __global__ __launch_bounds__(256) void k_pool_count(Tables t) {
     DevState* st = t.st;
     __shared__ unsigned red[4];
@@ -744,11 +776,18 @@ __global__ __launch_bounds__(256) void k_pool_count(Tables t) {
     const int wid = threadIdx.x >> 6;
     const int err0 = st->error;
     const int nn = st->n_new, nr = st->n_ret, nfree = st->free_cnt;
+    const int n0 = st->step;
+    // When the grid has workgroups beyond the scanning ones, those allocate
+    // and the scan starts at once (it reads only the bitmap); otherwise every
+    // workgroup allocates.  aw: this workgroup's index among the allocating
+    // ones (-1: none), nalloc: their number.
+    const int a0 = (int)gridDim.x > t.scan_wgs ? t.scan_wgs : 0;
+    const int aw = (int)blockIdx.x - a0, nalloc = (int)gridDim.x - a0;
 
     if (!err0) {
         if (nn > nfree + nr) {
             if (blockIdx.x == 0 && threadIdx.x == 0) {
-                st->err_step = st->step;
+                st->err_step = n0;
                 st->error = -3;   // TCM_E_POOL
             }
         } else {
@@ -759,23 +798,23 @@ __global__ __launch_bounds__(256) void k_pool_count(Tables t) {
             // slots are free as there are placing blocks, so every placement
             // succeeds (slots freed here may be taken as well).
             const int handoff = nn > nfree ? nn - nfree : 0;
-            const int gsz = gridDim.x * blockDim.x;
-            for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < nr; r += gsz) {
+            const int gsz = nalloc * blockDim.x;
+            for (int r = aw * blockDim.x + threadIdx.x; aw >= 0 && r < nr; r += gsz) {
                 t.cell2box[t.ret_key[r]] = EMPTY;
                 if (r >= handoff)
                     __hip_atomic_store(&t.slot_key[t.ret_slot[r]], -1LL, __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
             }
             // new blocks (wave per entry): slot, zero phi levels, C2 from media
-            const int nwaves = gridDim.x * (blockDim.x >> 6);
-            for (int k = blockIdx.x * (blockDim.x >> 6) + wid; k < nn; k += nwaves) {
+            const int nwaves = nalloc * (blockDim.x >> 6);
+            for (int k = aw * (blockDim.x >> 6) + wid; aw >= 0 && k < nn; k += nwaves) {
                 const long long G = t.new_key[k];
                 // one slot per key: slot G is only ever key G's (and no slot is
                 // handed over, the free slots always outnumber the new blocks)
                 const int slot = t.cap >= t.nkeys ? (int)G : k < handoff ? t.ret_slot[k] : place_slot(t, G);
                 if (slot < 0) {                      // unreachable (see above): fail the step
                     if (lane == 0) {
-                        st->err_step = st->step;
+                        st->err_step = n0;
                         st->error = -6;
                     }
                     continue;
@@ -800,8 +839,8 @@ __global__ __launch_bounds__(256) void k_pool_count(Tables t) {
     if (!err0 && nn <= nfree + nr) {
         const int nd = st->n_dec;
         const float alpha = t.shutdown_alpha;
-        const int nwaves = gridDim.x * (blockDim.x >> 6);
-        for (int k = blockIdx.x * (blockDim.x >> 6) + wid; k < nd; k += nwaves) {
+        const int nwaves = nalloc * (blockDim.x >> 6);
+        for (int k = aw * (blockDim.x >> 6) + wid; aw >= 0 && k < nd; k += nwaves) {
             float* blk = t.pool + (size_t)t.dec_slot[k] * SLOT;
 #pragma unroll
             for (int j = 0; j < 16; j++) blk[j * 64 + lane] = blk[j * 64 + lane] * alpha;
@@ -813,112 +852,139 @@ __global__ __launch_bounds__(256) void k_pool_count(Tables t) {
     // thread counts a contiguous run of them, the workgroup scans the runs
     // and stores every chunk's offset inside the range and the range total;
     // the last scanning workgroup to finish turns the totals into range
-    // offsets.
-    if ((int)blockIdx.x >= t.scan_wgs) return;
-    const int C = t.chunks_per_wg;
-    const long long c0 = (long long)blockIdx.x * C;
-    const long long c1 = min((long long)t.nchunks, c0 + C);
-    const int K = (C + (int)blockDim.x - 1) / (int)blockDim.x;
-    const long long tc0 = c0 + (long long)threadIdx.x * K;
-    unsigned tsum = 0;
-    for (int k = 0; k < K; k++) {                // K is uniform: every lane runs the ballots
-        const long long c = tc0 + k;
-        unsigned cnt = 0;
-        if (c < c1) {
-            const ulonglong2* bw = (const ulonglong2*)(t.bitmap + c * CHUNK_WORDS);
-#pragma unroll
-            for (int j = 0; j < CHUNK_WORDS / 2; j++) {
-                const ulonglong2 v = bw[j];
-                cnt += (unsigned)__popcll(v.x) + (unsigned)__popcll(v.y);
-            }
-            t.partial[c] = cnt;
-            tsum += cnt;
-        }
-        // the compaction visits only the chunks listed here
-        const int q = wave_append(&st->n_ne, cnt > 0u);
-        if (q >= 0) t.ne_chunks[q] = (int)c;
-    }
+    // offsets and commits the step.
     const int nw = blockDim.x >> 6;
-    unsigned incl = tsum;
-    for (int o = 1; o < 64; o <<= 1) {
-        const unsigned u = __shfl_up(incl, o);
-        if (lane >= o) incl += u;
-    }
-    if (lane == 63) red[wid] = incl;
-    __syncthreads();
-    unsigned run = incl - tsum, wg_sum = 0;
-    for (int w = 0; w < nw; w++) {
-        if (w < wid) run += red[w];
-        wg_sum += red[w];
-    }
-    for (int k = 0; k < K; k++) {
-        const long long c = tc0 + k;
-        if (c >= c1) break;
-        const unsigned v = t.partial[c];
-        t.partial[c] = run;
-        run += v;
-    }
-    if (threadIdx.x == 0) t.wg_total[blockIdx.x] = wg_sum;
-    __syncthreads();
-    if (threadIdx.x == 0) {
+    do {
+        if ((int)blockIdx.x >= t.scan_wgs) break;
+        if (t.scan_wgs == 1 && t.nchunks <= SCAN1_MAX * (int)blockDim.x) {
+            // one scanning workgroup (small tables): counts stay in registers,
+            // the chunk offsets are the final ones, and no range pass is needed
+            const int K1 = (t.nchunks + (int)blockDim.x - 1) / (int)blockDim.x;
+            const int c0 = (int)threadIdx.x * K1;
+            unsigned cnt1[SCAN1_MAX];
+            unsigned tsum = 0;
+#pragma unroll
+            for (int k = 0; k < SCAN1_MAX; k++) {
+                const int c = c0 + k;
+                unsigned cnt = 0;
+                if (k < K1 && c < t.nchunks) {
+                    const ulonglong2* bw = (const ulonglong2*)(t.bitmap + (long long)c * CHUNK_WORDS);
+#pragma unroll
+                    for (int j = 0; j < CHUNK_WORDS / 2; j++) {
+                        const ulonglong2 v = bw[j];
+                        cnt += (unsigned)__popcll(v.x) + (unsigned)__popcll(v.y);
+                    }
+                }
+                cnt1[k] = cnt;
+                tsum += cnt;
+                const int q = wave_append(&st->n_ne, cnt > 0u);
+                if (q >= 0) t.ne_chunks[q] = c;
+            }
+            unsigned incl = tsum;
+            for (int o = 1; o < 64; o <<= 1) {
+                const unsigned u = __shfl_up(incl, o);
+                if (lane >= o) incl += u;
+            }
+            if (lane == 63) red[wid] = incl;
+            __syncthreads();
+            unsigned run = incl - tsum, total = 0;
+            for (int w = 0; w < nw; w++) {
+                if (w < wid) run += red[w];
+                total += red[w];
+            }
+#pragma unroll
+            for (int k = 0; k < SCAN1_MAX; k++) {
+                const int c = c0 + k;
+                if (k < K1 && c < t.nchunks) t.partial[c] = run;
+                run += cnt1[k];
+            }
+            if (threadIdx.x == 0) {
+                t.wg_total[0] = 0u;
+                commit_step(t, st, nn, nr, nfree, total);
+            }
+            break;
+        }
+        const int C = t.chunks_per_wg;
+        const long long c0 = (long long)blockIdx.x * C;
+        const long long c1 = min((long long)t.nchunks, c0 + C);
+        const int K = (C + (int)blockDim.x - 1) / (int)blockDim.x;
+        const long long tc0 = c0 + (long long)threadIdx.x * K;
+        unsigned tsum = 0;
+        for (int k = 0; k < K; k++) {                // K is uniform: every lane runs the ballots
+            const long long c = tc0 + k;
+            unsigned cnt = 0;
+            if (c < c1) {
+                const ulonglong2* bw = (const ulonglong2*)(t.bitmap + c * CHUNK_WORDS);
+#pragma unroll
+                for (int j = 0; j < CHUNK_WORDS / 2; j++) {
+                    const ulonglong2 v = bw[j];
+                    cnt += (unsigned)__popcll(v.x) + (unsigned)__popcll(v.y);
+                }
+                t.partial[c] = cnt;
+                tsum += cnt;
+            }
+            // the compaction visits only the chunks listed here
+            const int q = wave_append(&st->n_ne, cnt > 0u);
+            if (q >= 0) t.ne_chunks[q] = (int)c;
+        }
+        unsigned incl = tsum;
+        for (int o = 1; o < 64; o <<= 1) {
+            const unsigned u = __shfl_up(incl, o);
+            if (lane >= o) incl += u;
+        }
+        if (lane == 63) red[wid] = incl;
+        __syncthreads();
+        unsigned run = incl - tsum, wg_sum = 0;
+        for (int w = 0; w < nw; w++) {
+            if (w < wid) run += red[w];
+            wg_sum += red[w];
+        }
+        for (int k = 0; k < K; k++) {
+            const long long c = tc0 + k;
+            if (c >= c1) break;
+            const unsigned v = t.partial[c];
+            t.partial[c] = run;
+            run += v;
+        }
+        if (threadIdx.x == 0) t.wg_total[blockIdx.x] = wg_sum;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            __threadfence();
+            last = atomicAdd(&st->done_wgs, 1) == t.scan_wgs - 1;
+        }
+        __syncthreads();
+        if (!last) break;
         __threadfence();
-        last = atomicAdd(&st->done_wgs, 1) == t.scan_wgs - 1;
-    }
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
 
-    // last workgroup: exclusive scan of the range totals (at most 1024, each
-    // thread a contiguous run), then commit the step's counters
-    const int ng = t.scan_wgs;
-    const int per = (ng + (int)blockDim.x - 1) / (int)blockDim.x;
-    const int g0 = min(ng, (int)threadIdx.x * per), g1 = min(ng, g0 + per);
-    unsigned mine = 0;
-    for (int g = g0; g < g1; g++) mine += __atomic_load_n(&t.wg_total[g], __ATOMIC_RELAXED);
-    incl = mine;
-    for (int o = 1; o < 64; o <<= 1) {
-        const unsigned u = __shfl_up(incl, o);
-        if (lane >= o) incl += u;
-    }
-    __syncthreads();                       // red[] is reused
-    if (lane == 63) red[wid] = incl;
-    __syncthreads();
-    run = incl - mine;
-    for (int w = 0; w < wid; w++) run += red[w];
-    unsigned total = 0;
-    for (int w = 0; w < nw; w++) total += red[w];
-    for (int g = g0; g < g1; g++) {
-        const unsigned v = __atomic_load_n(&t.wg_total[g], __ATOMIC_RELAXED);
-        t.wg_total[g] = run;
-        run += v;
-    }
-    if (threadIdx.x == 0) {
-        const int err = st->error;
-        if (!err || st->err_step == st->step) {   // the step's phi^{n+1} is complete
-            st->updates += st->cells_cur;
-            st->updates_u += st->cells_cur_u;
-            st->step += 1;
+        // last scanning workgroup: exclusive scan of the range totals (at most
+        // 1024, each thread a contiguous run), then commit the step
+        const int ng = t.scan_wgs;
+        const int per = (ng + (int)blockDim.x - 1) / (int)blockDim.x;
+        const int g0 = min(ng, (int)threadIdx.x * per), g1 = min(ng, g0 + per);
+        unsigned mine = 0;
+        for (int g = g0; g < g1; g++) mine += __atomic_load_n(&t.wg_total[g], __ATOMIC_RELAXED);
+        incl = mine;
+        for (int o = 1; o < 64; o <<= 1) {
+            const unsigned u = __shfl_up(incl, o);
+            if (lane >= o) incl += u;
         }
-        if (!err) {
-            st->free_cnt = nfree + nr - nn;
-            st->activations += (unsigned long long)nn;
-            st->retirements += (unsigned long long)nr;
-            st->decays += (unsigned long long)st->n_dec;
-            st->n_act = (int)total;
-            if ((int)total > st->peak_act) st->peak_act = (int)total;
-            st->cells_cur = 0;
-            st->cells_cur_u = 0;
-            st->emit = 1;
-        } else {
-            st->emit = 0;
+        __syncthreads();                       // red[] is reused
+        if (lane == 63) red[wid] = incl;
+        __syncthreads();
+        run = incl - mine;
+        for (int w = 0; w < wid; w++) run += red[w];
+        unsigned total = 0;
+        for (int w = 0; w < nw; w++) total += red[w];
+        for (int g = g0; g < g1; g++) {
+            const unsigned v = __atomic_load_n(&t.wg_total[g], __ATOMIC_RELAXED);
+            t.wg_total[g] = run;
+            run += v;
         }
-        st->n_new = 0;
-        st->n_ret = 0;
-        st->n_dec = 0;
-        st->maxbits = 0u;
-        st->done_wgs = 0;
-        __threadfence();
-    }
+        if (threadIdx.x == 0) {
+            st->done_wgs = 0;
+            commit_step(t, st, nn, nr, nfree, total);
+        }
+    } while (false);
 }
 
 hipError_t launch_pool_count(const Tables& t, int grid, hipStream_t s) {
@@ -953,6 +1019,13 @@ __global__ __launch_bounds__(64 * EMIT_WAVES) void k_emit(Tables t) {
     const int lane = lane_id();
     const int wid = threadIdx.x >> 6;
     const int emit = st->emit;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        // the allocator has finished: its free count and cleared step counters
+        st->free_cnt = st->free_next;
+        st->n_new = 0;
+        st->n_ret = 0;
+        st->n_dec = 0;
+    }
     // a grid that covers every chunk takes them directly (empty ones cost a
     // load); otherwise it walks the list of non-empty chunks
     const bool direct = t.nchunks <= (int)gridDim.x;
@@ -971,12 +1044,29 @@ __global__ __launch_bounds__(64 * EMIT_WAVES) void k_emit(Tables t) {
         }
         const unsigned base = emit ? t.wg_total[chunk / t.chunks_per_wg] + t.partial[chunk] : 0u;
         const int j = wid;                      // the wave's own word
+        // The block-table entries of the word's 64 keys and of their face
+        // neighbours are loaded before the word's bits are known (keys past
+        // the table read nothing), so that they travel with the chunk load;
+        // only the uniform-C2 lookup waits for a slot.
+        const long long w = chunk * CHUNK_WORDS + j;
+        const long long G = w * 64 + lane;
+        const bool g_ok = emit && w < t.nwords && G < t.nkeys;
+        const int shot = g_ok ? shot_of_word(t, w) : 0;
+        const Shot& S = t.shots[shot];
+        const unsigned key = (unsigned)(G - S.key_base);
+        int bx = 0, by = 0, bz = 0;
+        if (g_ok) key_to_block(S, key, bx, by, bz);
+        const int slot = g_ok ? t.cell2box[G] : EMPTY;
+        int nb[6];
+#pragma unroll
+        for (int d = 0; d < 6; d++) {
+            const long long nk = g_ok ? neighbour_key(S, bx, by, bz, d) : -1;
+            nb[d] = nk >= 0 ? t.cell2box[nk] : EMPTY;
+        }
         do {
             const unsigned long long m = __shfl(myword, j);
             if (m == 0ull) break;
-            const long long w = chunk * CHUNK_WORDS + j;
             const bool mine = (m >> lane) & 1ull;
-            const long long G = w * 64 + lane;
             if (!emit) {
                 // the step failed: undo its claims, keep the current list
                 if (mine && t.cell2box[G] == CLAIMED) t.cell2box[G] = EMPTY;
@@ -984,26 +1074,14 @@ __global__ __launch_bounds__(64 * EMIT_WAVES) void k_emit(Tables t) {
             }
             const unsigned off = base + __shfl(incl - cnt, j) +
                                  (unsigned)__popcll(m & ((1ull << lane) - 1ull));
-            const int shot = shot_of_word(t, w);
-            const Shot& S = t.shots[shot];
             if (mine) {
-                const unsigned key = (unsigned)(G - S.key_base);
-                const int slot = t.cell2box[G];
                 t.act_slot[off] = slot;
                 t.act_shot[off] = shot;
                 t.act_key[off] = key;
-                int bx, by, bz;
-                key_to_block(S, key, bx, by, bz);
                 const unsigned long long bc = (unsigned long long)block_cells(S, bx, by, bz);
                 cells += bc;
                 const float u = t.slot_c2u[slot];
                 if (u == u) ucells += bc;
-                int nb[6];
-#pragma unroll
-                for (int d = 0; d < 6; d++) {
-                    const long long nk = neighbour_key(S, bx, by, bz, d);
-                    nb[d] = nk >= 0 ? t.cell2box[nk] : EMPTY;
-                }
                 int4* rp = (int4*)(t.rows + 8 * (size_t)off);
                 rp[0] = make_int4(slot, nb[0], nb[1], nb[2]);
                 rp[1] = make_int4(nb[3], nb[4], nb[5], (int)G);
