@@ -1044,29 +1044,12 @@ __global__ __launch_bounds__(64 * EMIT_WAVES) void k_emit(Tables t) {
         }
         const unsigned base = emit ? t.wg_total[chunk / t.chunks_per_wg] + t.partial[chunk] : 0u;
         const int j = wid;                      // the wave's own word
-        // The block-table entries of the word's 64 keys and of their face
-        // neighbours are loaded before the word's bits are known (keys past
-        // the table read nothing), so that they travel with the chunk load;
-        // only the uniform-C2 lookup waits for a slot.
-        const long long w = chunk * CHUNK_WORDS + j;
-        const long long G = w * 64 + lane;
-        const bool g_ok = emit && w < t.nwords && G < t.nkeys;
-        const int shot = g_ok ? shot_of_word(t, w) : 0;
-        const Shot& S = t.shots[shot];
-        const unsigned key = (unsigned)(G - S.key_base);
-        int bx = 0, by = 0, bz = 0;
-        if (g_ok) key_to_block(S, key, bx, by, bz);
-        const int slot = g_ok ? t.cell2box[G] : EMPTY;
-        int nb[6];
-#pragma unroll
-        for (int d = 0; d < 6; d++) {
-            const long long nk = g_ok ? neighbour_key(S, bx, by, bz, d) : -1;
-            nb[d] = nk >= 0 ? t.cell2box[nk] : EMPTY;
-        }
         do {
             const unsigned long long m = __shfl(myword, j);
             if (m == 0ull) break;
+            const long long w = chunk * CHUNK_WORDS + j;
             const bool mine = (m >> lane) & 1ull;
+            const long long G = w * 64 + lane;
             if (!emit) {
                 // the step failed: undo its claims, keep the current list
                 if (mine && t.cell2box[G] == CLAIMED) t.cell2box[G] = EMPTY;
@@ -1074,14 +1057,26 @@ __global__ __launch_bounds__(64 * EMIT_WAVES) void k_emit(Tables t) {
             }
             const unsigned off = base + __shfl(incl - cnt, j) +
                                  (unsigned)__popcll(m & ((1ull << lane) - 1ull));
+            const int shot = shot_of_word(t, w);
+            const Shot& S = t.shots[shot];
             if (mine) {
+                const unsigned key = (unsigned)(G - S.key_base);
+                const int slot = t.cell2box[G];
                 t.act_slot[off] = slot;
                 t.act_shot[off] = shot;
                 t.act_key[off] = key;
+                int bx, by, bz;
+                key_to_block(S, key, bx, by, bz);
                 const unsigned long long bc = (unsigned long long)block_cells(S, bx, by, bz);
                 cells += bc;
                 const float u = t.slot_c2u[slot];
                 if (u == u) ucells += bc;
+                int nb[6];
+#pragma unroll
+                for (int d = 0; d < 6; d++) {
+                    const long long nk = neighbour_key(S, bx, by, bz, d);
+                    nb[d] = nk >= 0 ? t.cell2box[nk] : EMPTY;
+                }
                 int4* rp = (int4*)(t.rows + 8 * (size_t)off);
                 rp[0] = make_int4(slot, nb[0], nb[1], nb[2]);
                 rp[1] = make_int4(nb[3], nb[4], nb[5], (int)G);
