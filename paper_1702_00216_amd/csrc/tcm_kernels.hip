@@ -35,6 +35,11 @@
 
 namespace tcmk {
 
+// plane k (0, 1: phi levels; 2: C2) of a slot
+__device__ __forceinline__ float* plane_of(const Tables& t, long long slot, int k) {
+    return t.pool + ((size_t)k * (size_t)t.cap + (size_t)slot) * BV;
+}
+
 // --------------------------------------------------------------------------
 // small helpers
 // --------------------------------------------------------------------------
@@ -140,20 +145,23 @@ __device__ __forceinline__ float coeff_c2(float c, double dt, double dx) {
 // (one wave, lane = (x, y) column).  Returns (to every lane) the block's C2 if
 // all 512 nodes are in the domain and share it ("homogenic" cell of Table 1),
 // else NaN.
-__device__ float fill_slot(const Tables& t, const Shot& S, float* blk, int bx, int by, int bz) {
+__device__ float fill_slot(const Tables& t, const Shot& S, long long slot, int bx, int by, int bz) {
+    float* __restrict__ p0 = plane_of(t, slot, 0);
+    float* __restrict__ p1 = plane_of(t, slot, 1);
+    float* __restrict__ pc = plane_of(t, slot, PLANE_C2);
     const int lane = lane_id();
     const int x = lane & 7, y = lane >> 3;
     float first = 0.f;
     bool same = true;
 #pragma unroll
     for (int z = 0; z < 8; z++) {
-        blk[z * 64 + lane] = 0.f;
-        blk[BV + z * 64 + lane] = 0.f;
+        p0[z * 64 + lane] = 0.f;
+        p1[z * 64 + lane] = 0.f;
         const int gx = bx * BE + x, gy = by * BE + y, gz = bz * BE + z;
         float c2 = 0.f;   // nodes outside the domain keep C2 = 0 and stay zero
         const bool in = gx < S.nx && gy < S.ny && gz < S.nz;
         if (in) c2 = coeff_c2(media_speed(S, gx, gy, gz), t.dt, t.dx);
-        blk[C2_PLANE + z * 64 + lane] = c2;
+        pc[z * 64 + lane] = c2;
         if (z == 0) first = c2;
         same = same && in && c2 == first;
     }
@@ -297,10 +305,9 @@ __global__ __launch_bounds__(64 * W) void k_block_step(Tables t) {
         if (have) {
         pinned = t.nsrc > 0 ? pin_until[slot] : 0;
         const float c2u = slot_c2u[slot];
-        const float* __restrict__ blk = t.pool + (size_t)slot * SLOT;
-        const float* __restrict__ cur_p = blk + p * BV;
-        out_p = (float*)blk + (1 - p) * BV;
-        const float* __restrict__ c2_p = blk + C2_PLANE;
+        const float* __restrict__ cur_p = plane_of(t, slot, p);
+        out_p = plane_of(t, slot, 1 - p);
+        const float* __restrict__ c2_p = plane_of(t, slot, PLANE_C2);
 #pragma unroll
         for (int z = 0; z < 8; z++) {
             cur[z] = cur_p[z * 64 + lane];
@@ -313,13 +320,13 @@ __global__ __launch_bounds__(64 * W) void k_block_step(Tables t) {
 #pragma unroll
             for (int z = 0; z < 8; z++) k2[z] = __builtin_nontemporal_load(&c2_p[z * 64 + lane]);
         }
-        if (nb[4] >= 0) zlo = t.pool[(size_t)nb[4] * SLOT + p * BV + 7 * 64 + lane];
-        if (nb[5] >= 0) zhi = t.pool[(size_t)nb[5] * SLOT + p * BV + 0 * 64 + lane];
+        if (nb[4] >= 0) zlo = plane_of(t, nb[4], p)[7 * 64 + lane];
+        if (nb[5] >= 0) zhi = plane_of(t, nb[5], p)[0 * 64 + lane];
         float fmx = 0.f, fpx = 0.f, fmy = 0.f, fpy = 0.f;
-        if (nb[0] >= 0 && !share_m) fmx = t.pool[(size_t)nb[0] * SLOT + p * BV + zz * 64 + a * 8 + 7];
-        if (nb[1] >= 0 && !share_p) fpx = t.pool[(size_t)nb[1] * SLOT + p * BV + zz * 64 + a * 8 + 0];
-        if (nb[2] >= 0) fmy = t.pool[(size_t)nb[2] * SLOT + p * BV + zz * 64 + 7 * 8 + a];
-        if (nb[3] >= 0) fpy = t.pool[(size_t)nb[3] * SLOT + p * BV + zz * 64 + 0 * 8 + a];
+        if (nb[0] >= 0 && !share_m) fmx = plane_of(t, nb[0], p)[zz * 64 + a * 8 + 7];
+        if (nb[1] >= 0 && !share_p) fpx = plane_of(t, nb[1], p)[zz * 64 + a * 8 + 0];
+        if (nb[2] >= 0) fmy = plane_of(t, nb[2], p)[zz * 64 + 7 * 8 + a];
+        if (nb[3] >= 0) fpy = plane_of(t, nb[3], p)[zz * 64 + 0 * 8 + a];
         float4* own = (float4*)(T + ((y + 1) * TILE_COLS + (x + 1)) * BE);
         own[0] = make_float4(cur[0], cur[1], cur[2], cur[3]);
         own[1] = make_float4(cur[4], cur[5], cur[6], cur[7]);
@@ -551,7 +558,7 @@ __global__ __launch_bounds__(256) void k_plan(Tables t) {
             const Rec e = t.rec[r];
             const int s = t.cell2box[e.key];
             t.traces[(size_t)row * t.nrec + r] =
-                s >= 0 ? t.pool[(size_t)s * SLOT + (1 - p) * BV + e.local] : 0.f;
+                s >= 0 ? plane_of(t, s, 1 - p)[e.local] : 0.f;
         }
     }
 
@@ -716,7 +723,7 @@ __global__ __launch_bounds__(256) void k_advance(Tables t) {
             const Rec e = t.rec[r];
             const int s = t.cell2box[e.key];
             t.traces[(size_t)row * t.nrec + r] =
-                s >= 0 ? t.pool[(size_t)s * SLOT + (1 - p) * BV + e.local] : 0.f;
+                s >= 0 ? plane_of(t, s, 1 - p)[e.local] : 0.f;
         }
     }
     __syncthreads();
@@ -823,7 +830,7 @@ __global__ __launch_bounds__(256) void k_pool_count(Tables t) {
                 const Shot& S = t.shots[shot];
                 int bx, by, bz;
                 key_to_block(S, (unsigned)(G - S.key_base), bx, by, bz);
-                const float c2u = fill_slot(t, S, t.pool + (size_t)slot * SLOT, bx, by, bz);
+                const float c2u = fill_slot(t, S, slot, bx, by, bz);
                 if (lane == 0) {
                     t.slot_c2u[slot] = c2u;
                     t.sdlog[slot] = 0;
@@ -841,9 +848,13 @@ __global__ __launch_bounds__(256) void k_pool_count(Tables t) {
         const float alpha = t.shutdown_alpha;
         const int nwaves = nalloc * (blockDim.x >> 6);
         for (int k = aw * (blockDim.x >> 6) + wid; aw >= 0 && k < nd; k += nwaves) {
-            float* blk = t.pool + (size_t)t.dec_slot[k] * SLOT;
+            float* b0 = plane_of(t, t.dec_slot[k], 0);
+            float* b1 = plane_of(t, t.dec_slot[k], 1);
 #pragma unroll
-            for (int j = 0; j < 16; j++) blk[j * 64 + lane] = blk[j * 64 + lane] * alpha;
+            for (int j = 0; j < 8; j++) {
+                b0[j * 64 + lane] = b0[j * 64 + lane] * alpha;
+                b1[j * 64 + lane] = b1[j * 64 + lane] * alpha;
+            }
         }
     }
 
@@ -1134,7 +1145,7 @@ __global__ __launch_bounds__(64) void k_activate(Tables t, long long G, int shot
     const Shot& S = t.shots[shot];
     int bx, by, bz;
     key_to_block(S, key, bx, by, bz);
-    const float c2u = fill_slot(t, S, t.pool + (size_t)slot * SLOT, bx, by, bz);
+    const float c2u = fill_slot(t, S, slot, bx, by, bz);
     if (lane == 0) {
         t.slot_c2u[slot] = c2u;
         t.sdlog[slot] = 0;
@@ -1199,7 +1210,9 @@ hipError_t launch_activate(const Tables& t, long long key, int shot, unsigned lo
 // --------------------------------------------------------------------------
 // One thread per node of a box row (x fastest); each thread takes RB rows at
 // a time, issuing all their block-table loads, then all pool loads, then the
-// stores, so the dependent loads of different rows overlap.
+// stores, so the dependent loads of different rows overlap.  The output is
+// written once and read much later (the adjoint's snapshots), so it is stored
+// past the caches.
 constexpr int READ_RB = 8;
 
 __global__ void k_read(Tables t, int shot, int which, int x0, int y0, int z0, int sx, int sy,
@@ -1226,10 +1239,10 @@ __global__ void k_read(Tables t, int shot, int which, int x0, int y0, int z0, in
         float v[READ_RB];
 #pragma unroll
         for (int k = 0; k < READ_RB; k++)
-            v[k] = slot[k] >= 0 ? t.pool[(size_t)slot[k] * SLOT + plane * BV + loc[k]] : 0.f;
+            v[k] = slot[k] >= 0 ? plane_of(t, slot[k], plane)[loc[k]] : 0.f;
 #pragma unroll
         for (int k = 0; k < READ_RB; k++)
-            if (r0 + k < rows) out[(size_t)(r0 + k) * sx + lx] = v[k];
+            if (r0 + k < rows) __builtin_nontemporal_store(v[k], &out[(size_t)(r0 + k) * sx + lx]);
     }
 }
 
@@ -1400,8 +1413,7 @@ __global__ __launch_bounds__(GRAD_TX * GRAD_TY) void k_adjoint_grad(Tables mu, c
     const size_t sy = (size_t)S.nx, sz = (size_t)S.nx * S.ny;
     const int z1 = min(S.nz, z0 + GRAD_DZ);
     const int slot = mu.cell2box[S.key_base + (long long)block_to_key(S, x >> 3, y >> 3, z0 >> 3)];
-    const float* __restrict__ mub = mu.pool + (size_t)(slot >= 0 ? slot : 0) * SLOT + plane * BV +
-                                    (y & 7) * 8 + (x & 7);
+    const float* __restrict__ mub = plane_of(mu, slot >= 0 ? slot : 0, plane) + (y & 7) * 8 + (x & 7);
     size_t i = (size_t)z0 * sz + (size_t)y * sy + (size_t)x;
     float zm = z0 > 0 ? u[i - sz] : 0.f;
     float c = u[i];
