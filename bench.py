@@ -269,7 +269,7 @@ def bench_c4(args, tcm):
     media = [s.lattice for s in shots]
     sim = tcm.Simulation(shapes, 1.0, w0.dt, media, w0.trigger, w0.retire,
                          wg_per_cu=args.wg_per_cu, graph_steps=args.graph_steps,
-                         blocks_per_wg=args.blocks_per_wg)
+                         blocks_per_wg=args.blocks_per_wg, blocks_per_wave=args.blocks_per_wave)
 
     def run_batch():
         sim.reset()
@@ -293,7 +293,7 @@ def bench_c4(args, tcm):
         sim.step(steps // 2)
         tuning = sim.autotune(probe_steps=32, cache=os.environ.get("TCM_TUNE_CACHE"),
                               key=f"gfx950/c4/{len(shots)}shots")
-        log(f"c4 autotune: tile {tuning['blocks_per_wg']} blocks, wg_per_cu {tuning['wg_per_cu']}, "
+        log(f"c4 autotune: tile {tuning['blocks_per_wg']} blocks ({tuning['blocks_per_wave']} per wave), wg_per_cu {tuning['wg_per_cu']}, "
             f"graph_steps {tuning['graph_steps']} "
             f"({tuning['ms_per_step']:.3f} ms/step)")
     tot, upd = 0.0, 0
@@ -309,7 +309,8 @@ def bench_c4(args, tcm):
         for s in shots:
             one = tcm.Simulation(s.shape, 1.0, s.dt, s.lattice, s.trigger, s.retire,
                                  wg_per_cu=(tuning or {}).get("wg_per_cu", args.wg_per_cu),
-                                 blocks_per_wg=(tuning or {}).get("blocks_per_wg", args.blocks_per_wg))
+                                 blocks_per_wg=(tuning or {}).get("blocks_per_wg", args.blocks_per_wg),
+                              blocks_per_wave=(tuning or {}).get("blocks_per_wave", args.blocks_per_wave))
             one.add_source(s.source, s.wavelet.w32)
             one.step(8)
             one.reset()
@@ -328,7 +329,8 @@ def bench_c4(args, tcm):
     # events (16 B per node: lognormal C2 is not uniform over a block)
     tsim = tcm.Simulation(shapes, 1.0, w0.dt, media, w0.trigger, w0.retire, timing=True,
                           wg_per_cu=(tuning or {}).get("wg_per_cu", args.wg_per_cu),
-                          blocks_per_wg=(tuning or {}).get("blocks_per_wg", args.blocks_per_wg))
+                          blocks_per_wg=(tuning or {}).get("blocks_per_wg", args.blocks_per_wg),
+                              blocks_per_wave=(tuning or {}).get("blocks_per_wave", args.blocks_per_wave))
     for i, s in enumerate(shots):
         tsim.add_source(s.source, s.wavelet.w32, shot=i)
     tsim.step(steps)
@@ -389,7 +391,7 @@ def bench_c5(args, tcm):
     else:
         resid = np.random.default_rng(55).standard_normal((steps, len(w.receivers))).astype(np.float32)
     sim = tcm.Simulation(w.shape, w.dx, w.dt, c, checkpoint_every=50, wg_per_cu=args.wg_per_cu,
-                         blocks_per_wg=args.blocks_per_wg)
+                         blocks_per_wg=args.blocks_per_wg, blocks_per_wave=args.blocks_per_wave)
 
     def run():
         sim.reset()
@@ -417,7 +419,7 @@ def bench_c5(args, tcm):
         sim.step(steps)
         tuning = sim.autotune(probe_steps=32, cache=os.environ.get("TCM_TUNE_CACHE"), key="gfx950/c5")
         tuning.pop("candidates", None)
-        log(f"c5 autotune: tile {tuning['blocks_per_wg']} blocks, wg_per_cu {tuning['wg_per_cu']}, "
+        log(f"c5 autotune: tile {tuning['blocks_per_wg']} blocks ({tuning['blocks_per_wave']} per wave), wg_per_cu {tuning['wg_per_cu']}, "
             f"graph_steps {tuning['graph_steps']}")
     tf, ta = 0.0, 0.0
     for i in range(args.steps):
@@ -434,7 +436,8 @@ def bench_c5(args, tcm):
     if not args.no_roofline:
         tsim = tcm.Simulation(w.shape, w.dx, w.dt, c, checkpoint_every=50, timing=True,
                               wg_per_cu=(tuning or {}).get("wg_per_cu", args.wg_per_cu),
-                              blocks_per_wg=(tuning or {}).get("blocks_per_wg", args.blocks_per_wg))
+                              blocks_per_wg=(tuning or {}).get("blocks_per_wg", args.blocks_per_wg),
+                              blocks_per_wave=(tuning or {}).get("blocks_per_wave", args.blocks_per_wave))
         tsim.add_source(w.source, w.wavelet.w32)
         tsim.set_receivers(w.receivers)
         tsim.step(steps)
@@ -497,6 +500,7 @@ def main():
                     help="time with hipGraph replay instead of per-launch HIP events")
     ap.add_argument("--wg-per-cu", type=int, default=0)
     ap.add_argument("--blocks-per-wg", type=int, default=0, help="stencil workgroup tile (2, 4, 8)")
+    ap.add_argument("--blocks-per-wave", type=int, default=0, help="stencil blocks per wave (1, 2)")
     ap.add_argument("--graph-steps", type=int, default=0)
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-uniform-c2", action="store_true",
@@ -544,7 +548,7 @@ def main():
                 shutdown_steps=args.shutdown_steps, shutdown_alpha=args.shutdown_alpha)
     sim = tcm.Simulation(w.shape, w.dx, w.dt, media_of(w), w.trigger, w.retire,
                          timing=not args.graphs, wg_per_cu=args.wg_per_cu,
-                         blocks_per_wg=args.blocks_per_wg, **opts)
+                         blocks_per_wg=args.blocks_per_wg, blocks_per_wave=args.blocks_per_wave, **opts)
     for i in range(args.warmup):
         el, st = run_once(sim, w, steps)
         log(f"warmup {i}: {el:.3f} s, {st['cell_updates']:.3e} updates")
@@ -557,7 +561,7 @@ def main():
         tuning = sim.autotune(probe_steps=32, cache=os.environ.get("TCM_TUNE_CACHE"),
                               key=f"gfx950/{w.name}/k{args.interval}")
         tuning.pop("candidates", None)
-        log(f"autotune: tile {tuning['blocks_per_wg']} blocks, wg_per_cu {tuning['wg_per_cu']}, "
+        log(f"autotune: tile {tuning['blocks_per_wg']} blocks ({tuning['blocks_per_wave']} per wave), wg_per_cu {tuning['wg_per_cu']}, "
             f"graph_steps {tuning['graph_steps']}")
     tot_t, tot_u, st_ms, st_cells, st_launch, st_cells_u = 0.0, 0, 0.0, 0, 0, 0
     for i in range(args.steps):
@@ -579,6 +583,7 @@ def main():
         gsim = tcm.Simulation(w.shape, w.dx, w.dt, media_of(w), w.trigger, w.retire,
                               timing=False, wg_per_cu=(tuning or {}).get("wg_per_cu", args.wg_per_cu),
                               blocks_per_wg=(tuning or {}).get("blocks_per_wg", args.blocks_per_wg),
+                              blocks_per_wave=(tuning or {}).get("blocks_per_wave", args.blocks_per_wave),
                               graph_steps=(tuning or {}).get("graph_steps", 0), **opts)
         run_once(gsim, w, steps)
         gel, gst = run_once(gsim, w, steps)
@@ -677,7 +682,8 @@ def main():
             ksim = tcm.Simulation(w.shape, w.dx, w.dt, media_of(w), o["trigger"], o["retire"],
                                   timing=True, trigger_interval=g8["interval"],
                                   wg_per_cu=(tuning or {}).get("wg_per_cu", args.wg_per_cu),
-                                  blocks_per_wg=(tuning or {}).get("blocks_per_wg", args.blocks_per_wg))
+                                  blocks_per_wg=(tuning or {}).get("blocks_per_wg", args.blocks_per_wg),
+                              blocks_per_wave=(tuning or {}).get("blocks_per_wave", args.blocks_per_wave))
             run_once(ksim, w, steps)
             el, kst = run_once(ksim, w, steps)
             ksim.close()

@@ -98,8 +98,11 @@ typedef struct {
                                  trigger activates all 26 nearest and diagonal blocks (Figure 3),
                                  and a source block's 26 neighbours are activated with it, so
                                  that trigger = retire = 0 stays equal to the dense grid. */
-    int32_t  blocks_per_wg;   /* stencil workgroup tile: 2, 4 or 8 blocks (one wave each) taken
-                                 as consecutive list entries, sharing x faces (0: 4) */
+    int32_t  blocks_per_wg;   /* stencil workgroup tile: 2, 4 or 8 blocks taken as consecutive
+                                 list entries, sharing x faces (0: 4) */
+    int32_t  blocks_per_wave; /* 1: one block per wave; 2: each wave takes two consecutive
+                                 entries of the tile and loads them together (tile of 4 or 8
+                                 blocks); 0: 1 */
 } tcm_config;
 
 /* Wave-speed model ("Media": an array, or rules evaluated when a block is
@@ -215,11 +218,14 @@ typedef struct {
     double  cand_ms_per_step[32];
     int32_t blocks_per_wg;        /* chosen workgroup tile (blocks per workgroup) */
     int32_t cand_blocks_per_wg[32];
+    int32_t blocks_per_wave;      /* chosen blocks per wave (1 or 2) */
+    int32_t cand_blocks_per_wave[32];
 } tcm_tuning;
 
 /* Time probe_steps steps from the current state for each candidate launch
- * shape (workgroup tile of 2, 4 or 8 blocks x workgroups per CU of the
- * persistent stencil grid, then steps per graph), restore the state after
+ * shape (workgroup tile of 2, 4 or 8 blocks, one or two blocks per wave, x
+ * workgroups per CU of the persistent stencil grid, then steps per graph),
+ * restore the state after
  * each probe, and keep the fastest shape for later tcm_step calls.  The
  * block edge stays 8 (one 64-lane wave per block).  The field, statistics
  * and traces are unchanged on return.  TCM_E_STATE for the dense engine or
@@ -227,11 +233,12 @@ typedef struct {
 tcm_status tcm_autotune(tcm_handle* h, int32_t probe_steps, tcm_tuning* out);
 
 /* Set the launch shape directly (for example a stored tcm_autotune choice):
- * blocks_per_wg 2, 4 or 8 (0: keep), wg_per_cu in [1, resident workgroups
- * per CU for that tile], graph_steps >= 1.  Block engine only; TCM_E_ARG
- * out of range. */
+ * blocks_per_wg 2, 4 or 8 and blocks_per_wave 1 or 2 (2 needs a tile of 4
+ * or 8; 0: keep either), wg_per_cu in [1, resident workgroups per CU for
+ * that shape], graph_steps >= 1.  Block engine only; TCM_E_ARG out of
+ * range. */
 tcm_status tcm_set_launch(tcm_handle* h, int32_t wg_per_cu, int32_t graph_steps,
-                          int32_t blocks_per_wg);
+                          int32_t blocks_per_wg, int32_t blocks_per_wave);
 
 /* Return to level 0 (zero field, no active block, no sources, no traces);
  * media, configuration and allocations are kept. */

@@ -33,7 +33,8 @@ class Config(C.Structure):
                 ("graph_steps", C.c_int32), ("wg_per_cu", C.c_int32),
                 ("shutdown_steps", C.c_int32), ("shutdown_alpha", C.c_float),
                 ("trigger_rel", C.c_float), ("retire_rel", C.c_float),
-                ("trigger_interval", C.c_int32), ("blocks_per_wg", C.c_int32)]
+                ("trigger_interval", C.c_int32), ("blocks_per_wg", C.c_int32),
+                ("blocks_per_wave", C.c_int32)]
 
 
 class Media(C.Structure):
@@ -65,7 +66,8 @@ class Tuning(C.Structure):
     _fields_ = [("wg_per_cu", C.c_int32), ("graph_steps", C.c_int32), ("ms_per_step", C.c_double),
                 ("ncand", C.c_int32), ("cand_wg_per_cu", C.c_int32 * 32),
                 ("cand_graph_steps", C.c_int32 * 32), ("cand_ms_per_step", C.c_double * 32),
-                ("blocks_per_wg", C.c_int32), ("cand_blocks_per_wg", C.c_int32 * 32)]
+                ("blocks_per_wg", C.c_int32), ("cand_blocks_per_wg", C.c_int32 * 32),
+                ("blocks_per_wave", C.c_int32), ("cand_blocks_per_wave", C.c_int32 * 32)]
 
 
 _lib = None
@@ -105,7 +107,7 @@ def lib():
         L.tcm_snapshot_free.argtypes = [P]
         L.tcm_snapshot_free.restype = None
         L.tcm_autotune.argtypes = [H, I, F(Tuning)]
-        L.tcm_set_launch.argtypes = [H, I, I, I]
+        L.tcm_set_launch.argtypes = [H, I, I, I, I]
         L.tcm_hbm_probe.argtypes = [P, P, C.c_uint64, I, I, I, P, F(C.c_float)]
         L.tcm_stats.argtypes = [H, F(Stats)]
         L.tcm_destroy.argtypes = [H]

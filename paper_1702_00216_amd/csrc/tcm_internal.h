@@ -139,9 +139,11 @@ constexpr int POOL_COUNT_MAX_WG = 1024;
 hipError_t launch_init_tables(const Tables& t, long long nkeys, hipStream_t s);
 // w: blocks per workgroup (2, 4 or 8; 64 * w threads).  e0 / e1 (optional):
 // events stamped by the dispatch itself at the kernel's start and end.
-hipError_t launch_block_step(const Tables& t, int grid, int w, hipStream_t s,
+hipError_t launch_block_step(const Tables& t, int grid, int w, int pb, hipStream_t s,
                              hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
-int block_step_occupancy(bool adaptive, int w);   // resident workgroups per CU
+// w waves per workgroup, pb blocks per wave
+int block_step_occupancy(bool adaptive, int w, int pb);   // resident workgroups per CU
+bool block_step_shape_ok(int w, int pb);
 hipError_t launch_plan(const Tables& t, int grid, hipStream_t s);
 hipError_t launch_advance(const Tables& t, hipStream_t s);   // step without an activation update
 hipError_t launch_pool_count(const Tables& t, int grid, hipStream_t s);   // grid >= scan_wgs

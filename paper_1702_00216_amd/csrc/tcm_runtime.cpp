@@ -76,7 +76,8 @@ struct tcm_handle {
     // graph replay
     hipGraphExec_t gexec = nullptr;
     int gsteps = 0;
-    int tile_w = 4;                     // blocks (waves) per stencil workgroup
+    int tile_w = 4;                     // waves per stencil workgroup
+    int tile_p = 1;                     // blocks per stencil wave (1 or 2)
     bool graph_failed = false;
 
     // timing (TCM_FLAG_TIMING)
@@ -376,8 +377,9 @@ tcm_status setup_engine(tcm_handle* h, long long word_base) {
     // persistent stencil grid of resident workgroups (a grid beyond residency
     // would leave a tail of workgroups that start after the first wave); by
     // default about 12 waves per CU, the best shape measured on full lists
-    h->tile_w = cfg->blocks_per_wg > 0 ? cfg->blocks_per_wg : 4;
-    const int occ = std::max(1, block_step_occupancy(t.adaptive != 0, h->tile_w));
+    h->tile_p = cfg->blocks_per_wave > 1 ? cfg->blocks_per_wave : 1;
+    h->tile_w = (cfg->blocks_per_wg > 0 ? cfg->blocks_per_wg : 4) / h->tile_p;
+    const int occ = std::max(1, block_step_occupancy(t.adaptive != 0, h->tile_w, h->tile_p));
     const int wpc = cfg->wg_per_cu > 0 ? cfg->wg_per_cu : std::min(occ, std::max(1, 12 / h->tile_w));
     h->grid_step = std::max(8, (h->ncu * wpc) / 8 * 8);
     // one plan thread per entry up to 4 x 256 x CUs entries; the allocator
@@ -420,6 +422,9 @@ tcm_status create_common(const tcm_config* cfg, const tcm_shot* shots, int nshot
         return set_err(nullptr, TCM_E_ARG, "trigger_interval must be in [0, 8] (0 and 1: every step)");
     if (cfg->blocks_per_wg != 0 && cfg->blocks_per_wg != 2 && cfg->blocks_per_wg != 4 && cfg->blocks_per_wg != 8)
         return set_err(nullptr, TCM_E_ARG, "blocks_per_wg must be 0, 2, 4 or 8");
+    if (cfg->blocks_per_wave < 0 || cfg->blocks_per_wave > 2 ||
+        (cfg->blocks_per_wave == 2 && cfg->blocks_per_wg == 2))
+        return set_err(nullptr, TCM_E_ARG, "blocks_per_wave must be 0, 1 or 2 (2 with a tile of 4 or 8 blocks)");
     if (cfg->device_pool && cfg->pool_bytes < SLOT_BYTES)
         return set_err(nullptr, TCM_E_ARG, "a caller device_pool needs its size in pool_bytes");
     if (cfg->engine == TCM_ENGINE_DENSE && nshots != 1)
@@ -500,7 +505,7 @@ hipError_t enqueue_step(tcm_handle* h, hipEvent_t e0, hipEvent_t e1) {
     hipError_t e;
     const long long n = h->hstep++;
     const int k = h->t.interval > 1 ? h->t.interval : 1;
-    if ((e = launch_block_step(h->t, h->grid_step, h->tile_w, h->stream, e0, e1)) != hipSuccess) return e;
+    if ((e = launch_block_step(h->t, h->grid_step, h->tile_w, h->tile_p, h->stream, e0, e1)) != hipSuccess) return e;
     if ((n + 1) % k != 0) return launch_advance(h->t, h->stream);
     if ((e = launch_plan(h->t, h->grid_plan, h->stream)) != hipSuccess) return e;
     if ((e = launch_pool_count(h->t, h->grid_pool, h->stream)) != hipSuccess) return e;
@@ -1287,7 +1292,8 @@ tcm_status tcm_adjoint(tcm_handle* h, const float* resid, int32_t nt, int32_t re
     // whose lists start at the receivers); the recomputation keeps the forward
     // handle's launch shape
     a->tile_w = 4;
-    a->grid_step = std::max(8, (a->ncu * std::max(1, block_step_occupancy(a->t.adaptive != 0, 4))) / 8 * 8);
+    a->tile_p = 1;
+    a->grid_step = std::max(8, (a->ncu * std::max(1, block_step_occupancy(a->t.adaptive != 0, 4, 1))) / 8 * 8);
     {
         // adjoint step k (k = 0..nt-1) produces mu^{nt-k}; its source sample at
         // receiver r is C2_r * resid[nt-1-k][r]
@@ -1401,18 +1407,20 @@ tcm_status tcm_autotune(tcm_handle* h, int32_t probe_steps, tcm_tuning* out) {
     char* snap = nullptr;
     st = ck_save(h, &snap);
     if (st) return st;
-    const int keep_grid = h->grid_step, keep_gs = h->gsteps, keep_w = h->tile_w, keep_flags = h->cfg.flags;
+    const int keep_grid = h->grid_step, keep_gs = h->gsteps, keep_w = h->tile_w, keep_p = h->tile_p;
+    const int keep_flags = h->cfg.flags;
     h->cfg.flags &= ~TCM_FLAG_TIMING;
     hipEvent_t e0, e1;
     HIP_OR_FAIL(h, hipEventCreate(&e0));
     HIP_OR_FAIL(h, hipEventCreate(&e1));
     tcm_tuning res{};
     res.ms_per_step = 1e300;
-    int best_grid = keep_grid, best_gs = keep_gs, best_w = keep_w;
+    int best_grid = keep_grid, best_gs = keep_gs, best_w = keep_w, best_p = keep_p;
 
-    // time probe_steps steps of one shape from the saved state
-    auto probe = [&](int w, int wpc, int gs) -> tcm_status {
+    // time probe_steps steps of one shape (w waves of pb blocks) from the saved state
+    auto probe = [&](int w, int pb, int wpc, int gs) -> tcm_status {
         h->tile_w = w;
+        h->tile_p = pb;
         h->grid_step = std::max(8, (h->ncu * wpc) / 8 * 8);
         h->gsteps = round_graph_steps(h, gs);
         drop_graph(h);
@@ -1433,7 +1441,8 @@ tcm_status tcm_autotune(tcm_handle* h, int32_t probe_steps, tcm_tuning* out) {
         HIP_OR_FAIL(h, hipEventElapsedTime(&ms, e0, e1));
         const double per = ms / probe_steps;
         if (res.ncand < 32) {
-            res.cand_blocks_per_wg[res.ncand] = w;
+            res.cand_blocks_per_wg[res.ncand] = w * pb;
+            res.cand_blocks_per_wave[res.ncand] = pb;
             res.cand_wg_per_cu[res.ncand] = wpc;
             res.cand_graph_steps[res.ncand] = h->gsteps;
             res.cand_ms_per_step[res.ncand] = per;
@@ -1441,28 +1450,33 @@ tcm_status tcm_autotune(tcm_handle* h, int32_t probe_steps, tcm_tuning* out) {
         }
         if (per < res.ms_per_step) {
             res.ms_per_step = per;
-            res.blocks_per_wg = w;
+            res.blocks_per_wg = w * pb;
+            res.blocks_per_wave = pb;
             res.wg_per_cu = wpc;
             res.graph_steps = h->gsteps;
             best_grid = h->grid_step;
             best_gs = h->gsteps;
             best_w = w;
+            best_p = pb;
         }
         return TCM_OK;
     };
-    // the workgroup tile (2, 4 or 8 x-adjacent blocks) x workgroups per CU,
-    // 4 to 24 waves per CU, at 16 steps per graph; then the graph length
-    for (int w : {2, 4, 8}) {
-        const int occ = std::max(1, block_step_occupancy(h->t.adaptive != 0, w));
+    // the workgroup tile (2, 4 or 8 x-adjacent blocks, one or two per wave)
+    // x workgroups per CU, 4 to 24 waves per CU, at 16 steps per graph; then
+    // the graph length
+    const int shapes[5][2] = {{2, 1}, {4, 1}, {8, 1}, {2, 2}, {4, 2}};   // {waves, blocks per wave}
+    for (const auto& sh : shapes) {
+        const int w = sh[0], pb = sh[1];
+        const int occ = std::max(1, block_step_occupancy(h->t.adaptive != 0, w, pb));
         for (int wpc : {1, 2, 3, 4, 6, 8, 12}) {
             if (st || wpc > occ || w * wpc < 4 || w * wpc > 24) continue;
-            st = probe(w, wpc, 16);
+            st = probe(w, pb, wpc, 16);
         }
     }
-    const int bw = res.blocks_per_wg, bwpc = res.wg_per_cu;
+    const int bw = best_w, bp = best_p, bwpc = res.wg_per_cu;
     for (int gs : {8, 32}) {
-        if (st || bw == 0) break;
-        st = probe(bw, bwpc, gs);
+        if (st || res.blocks_per_wg == 0) break;
+        st = probe(bw, bp, bwpc, gs);
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -1474,28 +1488,36 @@ tcm_status tcm_autotune(tcm_handle* h, int32_t probe_steps, tcm_tuning* out) {
         h->grid_step = keep_grid;
         h->gsteps = keep_gs;
         h->tile_w = keep_w;
+        h->tile_p = keep_p;
         return st ? st : rs;
     }
     h->grid_step = best_grid;
     h->gsteps = best_gs;
     h->tile_w = best_w;
+    h->tile_p = best_p;
     st = sync_state(h);
     if (st) return st;
     if (out) *out = res;
     return TCM_OK;
 }
 
-tcm_status tcm_set_launch(tcm_handle* h, int32_t wg_per_cu, int32_t graph_steps, int32_t blocks_per_wg) {
+tcm_status tcm_set_launch(tcm_handle* h, int32_t wg_per_cu, int32_t graph_steps, int32_t blocks_per_wg,
+                          int32_t blocks_per_wave) {
     tcm_status st = check_live(h);
     if (st) return st;
     if (h->engine != TCM_ENGINE_BLOCKS) return set_err(h, TCM_E_STATE, "launch shape applies to the block engine");
-    const int w = blocks_per_wg > 0 ? blocks_per_wg : h->tile_w;
-    if (w != 2 && w != 4 && w != 8) return set_err(h, TCM_E_ARG, "blocks_per_wg must be 0, 2, 4 or 8");
-    const int occ = std::max(1, block_step_occupancy(h->t.adaptive != 0, w));
+    const int b = blocks_per_wg > 0 ? blocks_per_wg : h->tile_w * h->tile_p;
+    const int pb = blocks_per_wave > 0 ? blocks_per_wave : h->tile_p;
+    if ((b != 2 && b != 4 && b != 8) || pb < 1 || pb > 2 || b % pb || !block_step_shape_ok(b / pb, pb))
+        return set_err(h, TCM_E_ARG, "blocks_per_wg must be 0, 2, 4 or 8 and blocks_per_wave 0, 1 or 2 "
+                                     "(2 with a tile of 4 or 8 blocks)");
+    const int w = b / pb;
+    const int occ = std::max(1, block_step_occupancy(h->t.adaptive != 0, w, pb));
     if (wg_per_cu < 1 || wg_per_cu > occ || graph_steps < 1)
         return set_err(h, TCM_E_ARG, fmt("launch shape needs 1 <= wg_per_cu <= %d and graph_steps >= 1", occ));
     HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
     h->tile_w = w;
+    h->tile_p = pb;
     h->grid_step = std::max(8, (h->ncu * wg_per_cu) / 8 * 8);
     h->gsteps = round_graph_steps(h, graph_steps);
     drop_graph(h);

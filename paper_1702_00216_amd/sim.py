@@ -62,7 +62,7 @@ class Simulation:
                  checkpoint_every: int = 0, graph_steps: int = 0, wg_per_cu: int = 0,
                  device_pool=None, uniform_c2: bool = True, shutdown_steps: int = 0,
                  shutdown_alpha: float = 1.0, trigger_rel: float = 0.0, retire_rel: float = 0.0,
-                 trigger_interval: int = 1, blocks_per_wg: int = 0):
+                 trigger_interval: int = 1, blocks_per_wg: int = 0, blocks_per_wave: int = 0):
         lib = L.lib()
         cfg = L.Config()
         cfg.dx, cfg.dt = float(dx), float(dt)
@@ -80,6 +80,7 @@ class Simulation:
         cfg.retire_rel = float(retire_rel)
         cfg.trigger_interval = int(trigger_interval)
         cfg.blocks_per_wg = int(blocks_per_wg)
+        cfg.blocks_per_wave = int(blocks_per_wave)
         self._pool_tensor = device_pool
         if device_pool is not None:
             cfg.device_pool = device_pool.data_ptr()
@@ -197,7 +198,8 @@ class Simulation:
     def autotune(self, probe_steps: int = 32, cache: Optional[str] = None,
                  key: Optional[str] = None) -> dict:
         """Pick the launch shape (stencil workgroup tile of 2, 4 or 8 blocks,
-        workgroups per CU, steps per graph) by timing probe_steps steps from
+        one or two blocks per wave, workgroups per CU, steps per graph) by
+        timing probe_steps steps from
         the current state for each candidate; the state is unchanged.  With
         ``cache`` (a JSON file) and ``key``, a stored choice is applied
         without probing and new choices are stored."""
@@ -206,32 +208,39 @@ class Simulation:
         if cache and key and os.path.exists(cache):
             with open(cache) as f:
                 stored = json.load(f).get(key)
-            if stored and "blocks_per_wg" in stored:
-                self._apply_tuning(stored["wg_per_cu"], stored["graph_steps"], stored["blocks_per_wg"])
+            if stored and "blocks_per_wave" in stored:
+                self._apply_tuning(stored["wg_per_cu"], stored["graph_steps"], stored["blocks_per_wg"],
+                                   stored["blocks_per_wave"])
                 return dict(stored, cached=True)
         t = L.Tuning()
         self._check(L.lib().tcm_autotune(self._h, int(probe_steps), C.byref(t)))
-        res = {"blocks_per_wg": t.blocks_per_wg, "wg_per_cu": t.wg_per_cu,
-               "graph_steps": t.graph_steps, "ms_per_step": t.ms_per_step, "cached": False,
-               "candidates": [(t.cand_blocks_per_wg[i], t.cand_wg_per_cu[i], t.cand_graph_steps[i],
-                               t.cand_ms_per_step[i]) for i in range(t.ncand)]}
+        res = {"blocks_per_wg": t.blocks_per_wg, "blocks_per_wave": t.blocks_per_wave,
+               "wg_per_cu": t.wg_per_cu, "graph_steps": t.graph_steps, "ms_per_step": t.ms_per_step,
+               "cached": False,
+               "candidates": [(t.cand_blocks_per_wg[i], t.cand_blocks_per_wave[i], t.cand_wg_per_cu[i],
+                               t.cand_graph_steps[i], t.cand_ms_per_step[i]) for i in range(t.ncand)]}
         if cache and key:
             data = {}
             if os.path.exists(cache):
                 with open(cache) as f:
                     data = json.load(f)
-            data[key] = {k: res[k] for k in ("blocks_per_wg", "wg_per_cu", "graph_steps", "ms_per_step")}
+            data[key] = {k: res[k] for k in ("blocks_per_wg", "blocks_per_wave", "wg_per_cu", "graph_steps",
+                                             "ms_per_step")}
             with open(cache, "w") as f:
                 json.dump(data, f, indent=1)
         return res
 
-    def _apply_tuning(self, wg_per_cu: int, graph_steps: int, blocks_per_wg: int = 0):
-        self._check(L.lib().tcm_set_launch(self._h, int(wg_per_cu), int(graph_steps), int(blocks_per_wg)))
+    def _apply_tuning(self, wg_per_cu: int, graph_steps: int, blocks_per_wg: int = 0,
+                      blocks_per_wave: int = 0):
+        self._check(L.lib().tcm_set_launch(self._h, int(wg_per_cu), int(graph_steps), int(blocks_per_wg),
+                                           int(blocks_per_wave)))
 
-    def set_launch(self, wg_per_cu: int, graph_steps: int, blocks_per_wg: int = 0):
+    def set_launch(self, wg_per_cu: int, graph_steps: int, blocks_per_wg: int = 0,
+                   blocks_per_wave: int = 0):
         """Launch shape: workgroups per CU, steps per graph, workgroup tile
-        (2, 4 or 8 blocks; 0 keeps the current one)."""
-        self._apply_tuning(wg_per_cu, graph_steps, blocks_per_wg)
+        (2, 4 or 8 blocks) and blocks per wave (1 or 2); 0 keeps the current
+        tile or blocks per wave."""
+        self._apply_tuning(wg_per_cu, graph_steps, blocks_per_wg, blocks_per_wave)
 
     def reset(self):
         self._check(L.lib().tcm_reset(self._h))

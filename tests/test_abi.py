@@ -73,6 +73,8 @@ def test_bad_thresholds_rejected():
 def test_bad_configuration_rejected():
     c = np.ones((4, 4, 4), np.float32)
     assert _create((4, 4, 4), c, 0.5, blocks_per_wg=3)[0] == L.TCM_E_ARG
+    assert _create((4, 4, 4), c, 0.5, blocks_per_wave=3)[0] == L.TCM_E_ARG
+    assert _create((4, 4, 4), c, 0.5, blocks_per_wg=2, blocks_per_wave=2)[0] == L.TCM_E_ARG
     assert _create((4, 4, 4), c, 0.5, trigger_interval=9)[0] == L.TCM_E_ARG
     assert _create((4, 4, 4), c, 0.5, shutdown_steps=300, shutdown_alpha=0.5)[0] == L.TCM_E_ARG
     assert _create((4, 4, 4), c, 0.5, trigger_rel=1e-4, retire_rel=1e-3)[0] == L.TCM_E_ARG

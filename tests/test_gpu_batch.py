@@ -99,9 +99,10 @@ def test_autotune_keeps_state_and_results(tmp_path):
         assert values_equal(x, y)
     for k in ("step", "active_blocks", "cell_updates", "activations", "retirements"):
         assert before[1][k] == after[1][k], k
-    assert res["candidates"] and (res["blocks_per_wg"], res["wg_per_cu"], res["graph_steps"]) in \
-        [(c[0], c[1], c[2]) for c in res["candidates"]]
-    assert {c[0] for c in res["candidates"]} == {2, 4, 8}
+    assert res["candidates"] and (res["blocks_per_wg"], res["blocks_per_wave"], res["wg_per_cu"],
+                                  res["graph_steps"]) in [(c[0], c[1], c[2], c[3]) for c in res["candidates"]]
+    # every tile, with one and (tiles of 4 and 8) two blocks per wave
+    assert {(c[0], c[1]) for c in res["candidates"]} == {(2, 1), (4, 1), (8, 1), (4, 2), (8, 2)}
     a.step(60)
     ref = fresh()
     ref.step(100)
@@ -111,7 +112,7 @@ def test_autotune_keeps_state_and_results(tmp_path):
     r1 = ref.autotune(probe_steps=4, cache=cache, key="gfx950/test")
     r2 = fresh().autotune(probe_steps=4, cache=cache, key="gfx950/test")
     assert not r1["cached"] and r2["cached"] and r2["wg_per_cu"] == r1["wg_per_cu"]
-    assert r2["blocks_per_wg"] == r1["blocks_per_wg"]
+    assert r2["blocks_per_wg"] == r1["blocks_per_wg"] and r2["blocks_per_wave"] == r1["blocks_per_wave"]
     with pytest.raises(tcm.TCMError):
         ref.set_launch(0, 16)
 

@@ -275,26 +275,28 @@ def test_launch_modes_and_reads_agree():
     assert values_equal(a.read(0), phi)
 
 
-@pytest.mark.parametrize("tile", [2, 4, 8])
-def test_workgroup_tiles_agree_with_oracle(tile):
+@pytest.mark.parametrize("tile,per_wave", [(2, 1), (4, 1), (8, 1), (4, 2), (8, 2)])
+def test_workgroup_tiles_agree_with_oracle(tile, per_wave):
     """Every stencil workgroup tile (2, 4 or 8 x-adjacent blocks sharing x
-    faces through LDS), with a few workgroups per CU so that waves of one
-    workgroup meet ragged list ends, equals the CPU TCM at a threshold and
-    the dense oracle at threshold 0 (random media, ragged grid)."""
-    announce(f"workgroup tile {tile}")
+    faces through LDS; one or two blocks per wave), with a few workgroups per
+    CU so that waves of one workgroup meet ragged list ends, equals the CPU
+    TCM at a threshold and the dense oracle at threshold 0 (random media,
+    ragged grid)."""
+    announce(f"workgroup tile {tile}, {per_wave} per wave")
     shape = (45, 38, 27)
     c = ti.random_media(shape, seed=31, cmin=0.3, cmax=1.0)
     src = [((20, 17, 11), ti.ricker(0.12, 0.5).w32), ((44, 0, 26), ti.ricker(0.2, 0.5).w32)]
     phi, prev, _ = oracle.dense_run(c, 0.5, 1.0, 110, np.float32, sources=src)
     for wpc in (1, 3):
-        sim = gpu_run(shape, 0.5, c, src, 110, blocks_per_wg=tile, wg_per_cu=wpc)
+        sim = gpu_run(shape, 0.5, c, src, 110, blocks_per_wg=tile, blocks_per_wave=per_wave, wg_per_cu=wpc)
         assert values_equal(sim.read(0), phi) and values_equal(sim.read(1), prev)
     lev = np.float32(3e-4)
     t = oracle.TCM(c, 0.5, 1.0, lev, np.float32(5e-5))
     for xyz, w in src:
         t.add_source(xyz, w)
     assert t.step(110) == 0
-    sim = gpu_run(shape, 0.5, c, src, 110, lev, np.float32(5e-5), blocks_per_wg=tile, timing=True)
+    sim = gpu_run(shape, 0.5, c, src, 110, lev, np.float32(5e-5), blocks_per_wg=tile,
+                  blocks_per_wave=per_wave, timing=True)
     assert values_equal(sim.read(0), t.read(0))
     g, o = sim.stats(), t.stats()
     assert g["cell_updates"] == o["updates"] and g["activations"] == o["activations"]
@@ -541,6 +543,7 @@ def test_random_configurations_match_cpu_tcm(seed):
     rel = bool(rng.random() < 0.25)
     trel, rrel = (np.float32(1e-3), np.float32(2e-4)) if rel else (np.float32(0), np.float32(0))
     tile = int(rng.choice([2, 4, 8]))
+    per_wave = 1 + (seed // 2) % 2 if tile > 2 else 1     # not drawn: the other choices stay as they were
     unif = bool(rng.random() < 0.7)
     srcs = [(tuple(int(rng.integers(0, e)) for e in shape), ti.ricker(float(rng.uniform(0.08, 0.2)), dt).w32)
             for _ in range(int(rng.integers(1, 3)))]
@@ -565,10 +568,11 @@ def test_random_configurations_match_cpu_tcm(seed):
         cap = max(64, t.stats()["peak_active"] + int(rng.integers(0, 20)))
         t = oracle_run(cap)
     announce(f"random {seed}: shape {shape} levels {tr:g}/{float(ret):g} k {interval} shutdown {sd} "
-             f"rel {rel} tile {tile} uniform {unif} pool {cap or 'auto'}")
+             f"rel {rel} tile {tile}x{per_wave} uniform {unif} pool {cap or 'auto'}")
     sim = tcm.Simulation(shape, 1.0, dt, c, trig, ret, shutdown_steps=sd, shutdown_alpha=float(alpha),
                          trigger_rel=float(trel), retire_rel=float(rrel), trigger_interval=interval,
-                         blocks_per_wg=tile, uniform_c2=unif, timing=bool(seed % 2), pool_bytes=cap * 6144)
+                         blocks_per_wg=tile, blocks_per_wave=per_wave, uniform_c2=unif, timing=bool(seed % 2),
+                         pool_bytes=cap * 6144)
     for xyz, w in srcs:
         sim.add_source(xyz, w)
     sim.step(n1)
