@@ -3,12 +3,13 @@
 // One step n (phi^n -> phi^{n+1}) is four launches, all sized from device
 // counters so that a sequence of steps can be replayed as a hipGraph:
 //
-//   k_block_step  eq.(3) on every active 8^3 block: one 64-lane wave per block,
-//                 lane = (x, y) column with the 8 z values in registers, the
-//                 neighbour face planes staged in LDS (x faces shared between
-//                 the waves of a workgroup, which take x-adjacent blocks);
-//                 additive source insertion; wave-ballot face/keep predicates
-//                 -> one flag byte per slot.
+//   k_block_step  eq.(3) on every active 8^3 block: a 64-lane wave per block
+//                 (or per two consecutive blocks), lane = (x, y) column with
+//                 the 8 z values in registers, the neighbour face planes
+//                 staged in LDS (x faces shared between the blocks of a
+//                 workgroup, which takes x-adjacent blocks); additive source
+//                 insertion; wave-ballot face/keep predicates -> one flag
+//                 byte per slot.
 //   k_plan        keep / release each active block, claim empty face neighbours
 //                 with a compare-and-swap on the block table, mark the next
 //                 active set in a bitmap; receivers are recorded here.
