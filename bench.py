@@ -391,23 +391,24 @@ def bench_c5(args, tcm):
     else:
         resid = np.random.default_rng(55).standard_normal((steps, len(w.receivers))).astype(np.float32)
     sim = tcm.Simulation(w.shape, w.dx, w.dt, c, checkpoint_every=50, wg_per_cu=args.wg_per_cu,
-                         blocks_per_wg=args.blocks_per_wg, blocks_per_wave=args.blocks_per_wave)
+                         blocks_per_wg=args.blocks_per_wg, blocks_per_wave=args.blocks_per_wave,
+                         trigger_interval=args.interval)
 
-    def run():
-        sim.reset()
-        sim.add_source(w.source, w.wavelet.w32)
-        sim.set_receivers(w.receivers)
+    def run(s):
+        s.reset()
+        s.add_source(w.source, w.wavelet.w32)
+        s.set_receivers(w.receivers)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        sim.step(steps)
+        s.step(steps)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        g = sim.adjoint(resid)
+        g = s.adjoint(resid)
         t2 = time.perf_counter()
         return t1 - t0, t2 - t1, g
 
     for i in range(args.warmup):
-        f, a, _ = run()
+        f, a, _ = run(sim)
         log(f"c5 warmup {i}: forward {f:.3f} s, adjoint {a:.3f} s")
     tuning = None
     if not args.no_autotune and not args.wg_per_cu:
@@ -423,18 +424,34 @@ def bench_c5(args, tcm):
             f"graph_steps {tuning['graph_steps']}")
     tf, ta = 0.0, 0.0
     for i in range(args.steps):
-        f, a, g = run()
+        f, a, g = run(sim)
         tf += f
         ta += a
         log(f"c5 run {i}: forward {f:.3f} s, adjoint {a:.3f} s, |g| {np.linalg.norm(g):.3e}")
     sim.close()
     nodes = w.shape[0] * w.shape[1] * w.shape[2]
     tot = (tf + ta) / args.steps
+    # the paper's activation update every 8 steps (eq.(5) at Courant 0.5 for
+    # 8-node blocks): at threshold 0 forward, recomputation and adjoint field
+    # are exact either way, so the gradient must be bit-identical
+    k8 = None
+    if args.interval == 1 and not args.no_interval8:
+        ksim = tcm.Simulation(w.shape, w.dx, w.dt, c, checkpoint_every=50, trigger_interval=8,
+                              wg_per_cu=(tuning or {}).get("wg_per_cu", args.wg_per_cu),
+                              blocks_per_wg=(tuning or {}).get("blocks_per_wg", args.blocks_per_wg),
+                              blocks_per_wave=(tuning or {}).get("blocks_per_wave", args.blocks_per_wave))
+        run(ksim)                    # warm-up
+        kf, ka, g8 = run(ksim)
+        ksim.close()
+        k8 = {"interval": 8, "forward_s": round(kf, 4), "adjoint_s": round(ka, 4),
+              "value": nodes * steps / (kf + ka), "gradient_bit_identical": bool(np.array_equal(g8, g))}
+        log(f"c5 interval 8: forward {kf:.3f} s, adjoint {ka:.3f} s, gradient identical {k8['gradient_bit_identical']}")
     # one more forward + adjoint with HIP events around every gradient launch
     # (16 B per node of an active adjoint block: u, mu, gs read, gs written)
     roof = None
     if not args.no_roofline:
         tsim = tcm.Simulation(w.shape, w.dx, w.dt, c, checkpoint_every=50, timing=True,
+                              trigger_interval=args.interval,
                               wg_per_cu=(tuning or {}).get("wg_per_cu", args.wg_per_cu),
                               blocks_per_wg=(tuning or {}).get("blocks_per_wg", args.blocks_per_wg),
                               blocks_per_wave=(tuning or {}).get("blocks_per_wave", args.blocks_per_wave))
@@ -478,11 +495,12 @@ def bench_c5(args, tcm):
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
            "data": "synthetic",
            "config": {"workload": f"c5: 256^3 lognormal (seed 5), Ricker 100 Hz at {w.source}, {steps} steps, "
-                                  f"128 receivers on z = 240, checkpoints every 50, threshold 0",
+                                  f"128 receivers on z = 240, checkpoints every 50, threshold 0, "
+                                  f"activation update every {args.interval} step(s)",
                       "time_steps_per_run": steps},
            "roofline": roof, "cpu_baseline": cpu,
            "adjoint": {"forward_s": round(tf / args.steps, 4), "adjoint_s": round(ta / args.steps, 4),
-                       "adjoint_over_forward": round(ta / tf, 3)}, "autotune": tuning}
+                       "adjoint_over_forward": round(ta / tf, 3)}, "interval8": k8, "autotune": tuning}
     print(json.dumps(out), flush=True)
 
 

@@ -124,3 +124,20 @@ def test_timed_adjoint_counts_gradient_launches_and_keeps_results():
     # at threshold 0 the adjoint field grows from the receivers: some, at most all, nodes per step
     assert 0 < st["grad_cells"] <= nodes * nt
     assert sim_a.stats()["grad_launches"] == 0
+
+
+@pytest.mark.parametrize("k", [4, 8])
+def test_adjoint_with_update_interval_is_bit_identical_at_threshold_zero(k):
+    """At threshold 0 the activation update every k steps (eq.(5), with the
+    26-neighbour lookahead) computes the exact dense field, in the forward,
+    its recomputation and the adjoint field alike: the gradient equals the
+    every-step gradient bit for bit."""
+    announce(f"adjoint with update interval {k}")
+    c, dt, w, src, rec, resid, nt = setup(nt=70, seed=12)
+    _, g1 = gpu_grad(c, dt, w, src, rec, resid, nt, K=20)
+    sim = tcm.Simulation(c.shape[::-1], 1.0, dt, c, checkpoint_every=20, trigger_interval=k)
+    sim.add_source(src, w)
+    sim.set_receivers(rec)
+    sim.step(nt)
+    gk = sim.adjoint(resid)
+    assert np.array_equal(g1, gk)
