@@ -14,15 +14,18 @@
 //                 with a compare-and-swap on the block table, mark the next
 //                 active set in a bitmap; receivers are recorded here.
 //   k_pool_count  lock-free slot allocator: a new block claims the first free
-//                 slot at or after (global key mod pool size) with a
+//                 slot at or after its preferred slot (the key itself with one
+//                 slot per key, else a hashed 64-slot group of its tile) with a
 //                 compare-and-swap, so the pool keeps the spatial order of the
 //                 active list; zero-fill + C2 of new blocks; a two-level scan
-//                 of the bitmap (chunk ranges per workgroup, then the range
-//                 totals in the last one), which also lists the non-empty
-//                 chunks and commits the step counters.
+//                 of the bitmap (chunk ranges per scanning workgroup, then the
+//                 range totals in the last one), which also lists the
+//                 non-empty chunks and commits the step counters.
 //   k_emit        compaction of the bitmap into the next active list and its
 //                 neighbour rows (spatial tile order), clearing the bitmap for
-//                 the next step.
+//                 the next step; it also installs the allocator's free count
+//                 and clears the step's claim / release / decay counters,
+//                 which every allocating workgroup reads at its start.
 //
 // A step without an activation update (update interval > 1) is k_block_step
 // and k_advance (receivers, step counter).
