@@ -539,8 +539,8 @@ def main():
                     help="also run a 1 GiB device-to-device torch copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU: the TCM hot path is built and measured on a single "
-              "MI355X; multi-GPU runs are not part of this build.", file=sys.stderr)
+        print("bench.py measures one GPU: the TCM path runs on a single MI355X; how it would "
+              "shard over several GPUs is a design note, not an implementation.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
