@@ -121,8 +121,8 @@ def test_autotune_keeps_state_and_results(tmp_path):
 def test_random_batches_match_cpu_tcm_per_shot(seed):
     """Seeded random batches: 2-7 shots of random shapes, media and sources
     over one pool (auto or just above the summed peaks), random levels,
-    update interval and workgroup tile; every shot equals the CPU TCM run
-    on its own."""
+    update interval and workgroup tile (one or two blocks per wave); every
+    shot equals the CPU TCM run on its own."""
     rng = np.random.default_rng(500 + seed)
     nshot = int(rng.integers(2, 8))
     dt = 0.55
@@ -130,6 +130,7 @@ def test_random_batches_match_cpu_tcm_per_shot(seed):
     trig, ret = np.float32(tr), np.float32(tr * 0.3)
     interval = int(rng.choice([1, 1, 2, 8]))
     tile = int(rng.choice([2, 4, 8]))
+    per_wave = 1 + seed % 2 if tile > 2 else 1          # not drawn: the other choices stay as they were
     steps = int(rng.integers(30, 120))
     shots = []
     for i in range(nshot):
@@ -146,9 +147,11 @@ def test_random_batches_match_cpu_tcm_per_shot(seed):
     cap = 0
     if seed % 2:
         cap = max(64, sum(t.stats()["peak_active"] for t in ref) + int(rng.integers(0, 30)))
-    announce(f"random batch {seed}: {nshot} shots, levels {tr:g}, k {interval}, tile {tile}, pool {cap or 'auto'}")
+    announce(f"random batch {seed}: {nshot} shots, levels {tr:g}, k {interval}, tile {tile}x{per_wave}, "
+             f"pool {cap or 'auto'}")
     b = tcm.Simulation([s[0] for s in shots], 1.0, dt, [s[1] for s in shots], trig, ret,
-                       trigger_interval=interval, blocks_per_wg=tile, pool_bytes=cap * 6144)
+                       trigger_interval=interval, blocks_per_wg=tile, blocks_per_wave=per_wave,
+                       pool_bytes=cap * 6144)
     for i, (shape, c, src, w) in enumerate(shots):
         b.add_source(src, w, shot=i)
     b.step(steps)
