@@ -1445,6 +1445,7 @@ hipError_t launch_receiver_c2(const Shot* shots, const int* xyz, const int* rsho
 // 128 contiguous bytes of that block's mu plane); at 256^3 the grid is 4096
 // workgroups (measured: 8 planes per workgroup beat 16 and 32).
 constexpr int GRAD_TX = 128, GRAD_TY = 4, GRAD_DZ = 8;
+static_assert(GRAD_DZ == 8, "a gradient workgroup's planes are one block deep");
 
 __global__ __launch_bounds__(GRAD_TX * GRAD_TY) void k_adjoint_grad(Tables mu, const float* __restrict__ u,
                                                                    float* __restrict__ gs) {
@@ -1457,20 +1458,21 @@ __global__ __launch_bounds__(GRAD_TX * GRAD_TY) void k_adjoint_grad(Tables mu, c
     if (x >= S.nx || y >= S.ny) return;
     const size_t sy = (size_t)S.nx, sz = (size_t)S.nx * S.ny;
     const int z1 = min(S.nz, z0 + GRAD_DZ);
+    // the column lies in one block of the adjoint field: mu is zero there when
+    // that block is inactive, and nothing is added (no barrier below)
     const int slot = mu.cell2box[S.key_base + (long long)block_to_key(S, x >> 3, y >> 3, z0 >> 3)];
-    const float* __restrict__ mub = plane_of(mu, slot >= 0 ? slot : 0, plane) + (y & 7) * 8 + (x & 7);
+    if (slot < 0) return;
+    const float* __restrict__ mub = plane_of(mu, slot, plane) + (y & 7) * 8 + (x & 7);
     size_t i = (size_t)z0 * sz + (size_t)y * sy + (size_t)x;
     float zm = z0 > 0 ? u[i - sz] : 0.f;
     float c = u[i];
     for (int z = z0; z < z1; z++, i += sz) {
         const float zp = z + 1 < S.nz ? u[i + sz] : 0.f;
-        if (slot >= 0) {
-            const float xm = x > 0 ? u[i - 1] : 0.f, xp = x + 1 < S.nx ? u[i + 1] : 0.f;
-            const float ym = y > 0 ? u[i - sy] : 0.f, yp = y + 1 < S.ny ? u[i + sy] : 0.f;
-            const float lap = (((xp + xm) + (yp + ym)) + (zp + zm)) - 6.0f * c;
-            const float m = mub[(z & 7) * 64];
-            gs[i] = gs[i] + m * lap;
-        }
+        const float xm = x > 0 ? u[i - 1] : 0.f, xp = x + 1 < S.nx ? u[i + 1] : 0.f;
+        const float ym = y > 0 ? u[i - sy] : 0.f, yp = y + 1 < S.ny ? u[i + sy] : 0.f;
+        const float lap = (((xp + xm) + (yp + ym)) + (zp + zm)) - 6.0f * c;
+        const float m = mub[(z & 7) * 64];
+        gs[i] = gs[i] + m * lap;
         zm = c;
         c = zp;
     }
