@@ -143,8 +143,8 @@ def cpu_baseline(w, budget_s: float):
 
 
 def add_ceiling(tcm, roof, fu=None):
-    """The achievable HBM ceiling of a kernel of the stencil's shape
-    (tcm_hbm_probe): the best of a few grid sizes for each read:write mix
+    """The achievable HBM ceiling of a streaming kernel with the stencil's
+    read:write mix (tcm_hbm_probe): the best of a few grid sizes for each mix
     (2:1 for nodes of blocks with a uniform C2, 3:1 otherwise), blended by
     the nodes of each kind, and the stencil's fraction of it."""
     def best_probe(nread):

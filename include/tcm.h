@@ -268,12 +268,14 @@ void tcm_destroy(tcm_handle* h);
 /* Measurement helper, not part of the method: the HBM bandwidth that a
  * streaming kernel of the block stencil's shape reaches on the current
  * device, the ceiling its roofline fraction is compared with.  The kernel
- * computes dst[i] = src[i] (+ src[n + i] (+ src[2n + i])) for i < n with
- * coalesced 256-byte wave accesses and non-temporal loads and stores; with
- * nread = 3 it reads 12 and writes 4 bytes per element, the stencil's mix.
- *   src      device, nread * n floats (the sources back to back)
- *   dst      device, n floats; must not overlap src
- *   n        floats per source, > 0 and a multiple of 2048
+ * computes dst[i] = src[i] (+ src[n + i] (+ src[2n + i])) for i < n in the
+ * fastest streaming shape measured (two floats per lane, 512-byte wave
+ * accesses, 16 KiB of each stream per workgroup pass, non-temporal loads and
+ * stores); with nread = 3 it reads 12 and writes 4 bytes per element, the
+ * stencil's mix.
+ *   src      device, nread * n floats (the sources back to back), 8-byte aligned
+ *   dst      device, n floats, 8-byte aligned; must not overlap src
+ *   n        floats per source, > 0 and a multiple of 4096
  *   nread    1, 2 or 3
  *   wg_per_cu  workgroups (256 threads) per compute unit; 0 => 8
  *   reps     launches, 1..1000

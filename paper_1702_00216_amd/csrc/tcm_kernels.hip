@@ -1531,35 +1531,40 @@ hipError_t launch_grad_finish(const Shot& shot, const Shot* dshot, const double*
 }
 
 // ---------------------------------------------------------------------------
-// HBM ceiling probe.  dst = src_0 (+ src_1 (+ src_2)), streamed the way the
-// block stencil streams its planes: each lane owns one float of a 64-float
-// row, a wave moves 256 contiguous bytes per access, loads and stores are
-// non-temporal, and every thread handles PROBE_UNROLL rows 256 floats apart
-// so that the loads of one thread are in flight together.  With three
-// sources the read:write mix is the stencil's 12:4 bytes per node.
+// HBM ceiling probe.  dst = src_0 (+ src_1 (+ src_2)) in the fastest streaming
+// shape found by a sweep of load widths, unrolls and grid sizes: each lane
+// moves two consecutive floats (a wave 512 contiguous bytes per access), every
+// thread handles PROBE_UNROLL such pairs 512 floats apart so that its loads
+// are in flight together (a workgroup pass covers 16 KiB of each stream), and
+// loads and stores are non-temporal.  With three sources the read:write mix
+// is the stencil's 12:4 bytes per node.
 constexpr int PROBE_UNROLL = 8;
-constexpr long long PROBE_CHUNK = 256LL * PROBE_UNROLL;   // floats per workgroup pass
+constexpr long long PROBE_CHUNK = 512LL * PROBE_UNROLL;   // floats per workgroup pass
+typedef float probe_f2 __attribute__((ext_vector_type(2)));
 
 template <int NR>
 __global__ __launch_bounds__(256) void k_hbm_probe(const float* __restrict__ src, float* __restrict__ dst,
                                                   long long n) {
     const long long nchunks = n / PROBE_CHUNK;
+    const long long n2 = n / 2;                 // pairs per stream (n is a multiple of PROBE_CHUNK)
+    const probe_f2* __restrict__ s2 = (const probe_f2*)src;
+    probe_f2* __restrict__ d2 = (probe_f2*)dst;
     for (long long c = blockIdx.x; c < nchunks; c += gridDim.x) {
-        const long long base = c * PROBE_CHUNK + threadIdx.x;
-        float v[PROBE_UNROLL];
+        const long long base = c * (PROBE_CHUNK / 2) + threadIdx.x;
+        probe_f2 v[PROBE_UNROLL];
 #pragma unroll
-        for (int u = 0; u < PROBE_UNROLL; u++) v[u] = __builtin_nontemporal_load(&src[base + u * 256]);
+        for (int u = 0; u < PROBE_UNROLL; u++) v[u] = __builtin_nontemporal_load(&s2[base + u * 256]);
         if (NR >= 2) {
 #pragma unroll
-            for (int u = 0; u < PROBE_UNROLL; u++) v[u] += __builtin_nontemporal_load(&src[n + base + u * 256]);
+            for (int u = 0; u < PROBE_UNROLL; u++) v[u] += __builtin_nontemporal_load(&s2[n2 + base + u * 256]);
         }
         if (NR >= 3) {
 #pragma unroll
             for (int u = 0; u < PROBE_UNROLL; u++)
-                v[u] += __builtin_nontemporal_load(&src[2 * n + base + u * 256]);
+                v[u] += __builtin_nontemporal_load(&s2[2 * n2 + base + u * 256]);
         }
 #pragma unroll
-        for (int u = 0; u < PROBE_UNROLL; u++) __builtin_nontemporal_store(v[u], &dst[base + u * 256]);
+        for (int u = 0; u < PROBE_UNROLL; u++) __builtin_nontemporal_store(v[u], &d2[base + u * 256]);
     }
 }
 

@@ -736,6 +736,7 @@ tcm_status tcm_hbm_probe(const float* src, float* dst, uint64_t n, int32_t nread
     if (nread < 1 || nread > 3) return set_err(nullptr, TCM_E_ARG, "hbm probe: nread must be 1, 2 or 3");
     if (wg_per_cu < 0 || wg_per_cu > 32) return set_err(nullptr, TCM_E_ARG, "hbm probe: wg_per_cu must be 0..32");
     if (reps < 1 || reps > 1000) return set_err(nullptr, TCM_E_ARG, "hbm probe: reps must be 1..1000");
+    if (((uintptr_t)src | (uintptr_t)dst) & 7u) return set_err(nullptr, TCM_E_ARG, "hbm probe: src and dst must be 8-byte aligned");
     const uintptr_t s0 = (uintptr_t)src, s1 = s0 + (uintptr_t)nread * n * sizeof(float);
     const uintptr_t d0 = (uintptr_t)dst, d1 = d0 + (uintptr_t)n * sizeof(float);
     if (d0 < s1 && s0 < d1) return set_err(nullptr, TCM_E_ARG, "hbm probe: dst overlaps src");

@@ -286,8 +286,9 @@ def version() -> str:
 
 
 def hbm_probe(nread: int = 3, n: int = 1 << 28, wg_per_cu: int = 0, reps: int = 5) -> dict:
-    """Achievable HBM bandwidth of a stencil-shaped streaming kernel
-    (tcm_hbm_probe): nread sources of n floats each, one destination.
+    """Achievable HBM bandwidth of a plain streaming kernel in the fastest
+    shape measured (tcm_hbm_probe): nread sources of n floats each (n a
+    multiple of 4096), one destination.
     Returns the best launch time and the GB/s it moves."""
     import torch
     src = torch.ones(nread * n, dtype=torch.float32, device="cuda")

@@ -111,14 +111,16 @@ def test_hbm_probe_arguments_validated():
     lib = L.lib()
     ms = C.c_float(0.0)
     src, dst = 1 << 20, 1 << 40
-    assert lib.tcm_hbm_probe(None, dst, 2048, 3, 0, 1, None, C.byref(ms)) == L.TCM_E_ARG
-    assert lib.tcm_hbm_probe(src, dst, 2048, 3, 0, 1, None, None) == L.TCM_E_ARG
+    assert lib.tcm_hbm_probe(None, dst, 4096, 3, 0, 1, None, C.byref(ms)) == L.TCM_E_ARG
+    assert lib.tcm_hbm_probe(src, dst, 4096, 3, 0, 1, None, None) == L.TCM_E_ARG
     assert lib.tcm_hbm_probe(src, dst, 0, 3, 0, 1, None, C.byref(ms)) == L.TCM_E_ARG
     assert lib.tcm_hbm_probe(src, dst, 3000, 3, 0, 1, None, C.byref(ms)) == L.TCM_E_ARG
-    assert "multiple of 2048" in lib.tcm_last_error(None).decode()
-    assert lib.tcm_hbm_probe(src, dst, 2048, 4, 0, 1, None, C.byref(ms)) == L.TCM_E_ARG
-    assert lib.tcm_hbm_probe(src, dst, 2048, 3, 33, 1, None, C.byref(ms)) == L.TCM_E_ARG
-    assert lib.tcm_hbm_probe(src, dst, 2048, 3, 0, 0, None, C.byref(ms)) == L.TCM_E_ARG
+    assert "multiple of 4096" in lib.tcm_last_error(None).decode()
+    assert lib.tcm_hbm_probe(src, dst, 4096, 4, 0, 1, None, C.byref(ms)) == L.TCM_E_ARG
+    assert lib.tcm_hbm_probe(src, dst, 4096, 3, 33, 1, None, C.byref(ms)) == L.TCM_E_ARG
+    assert lib.tcm_hbm_probe(src, dst, 4096, 3, 0, 0, None, C.byref(ms)) == L.TCM_E_ARG
+    assert lib.tcm_hbm_probe(src + 4, dst, 4096, 3, 0, 1, None, C.byref(ms)) == L.TCM_E_ARG
+    assert "aligned" in lib.tcm_last_error(None).decode()
     # dst inside the three sources
-    assert lib.tcm_hbm_probe(src, src + 4 * 2048, 2048, 3, 0, 1, None, C.byref(ms)) == L.TCM_E_ARG
+    assert lib.tcm_hbm_probe(src, src + 4 * 4096, 4096, 3, 0, 1, None, C.byref(ms)) == L.TCM_E_ARG
     assert "overlaps" in lib.tcm_last_error(None).decode()
