@@ -56,22 +56,26 @@ def run_once(sim, w, steps):
     return time.perf_counter() - t0, sim.stats()
 
 
-def kernel_source_hash() -> str:
-    """sha256 (16 hex digits) of the k_block_step function source, from its
-    template line to its closing brace: the counters in profiles/ are used
-    only while it is unchanged."""
+def kernel_source_hash(kernel: str = "k_block_step") -> str:
+    """sha256 (16 hex digits) of a kernel's function source, from its first
+    line (its template line, if any) to its closing brace: the counters in
+    profiles/ are used only while it is unchanged."""
     import hashlib
     src = open(os.path.join(ROOT, "paper_1702_00216_amd", "csrc", "tcm_kernels.hip")).read()
-    k = src.index(" void k_block_step(Tables t) {")
-    a = src.rindex("\ntemplate <", 0, k) + 1
+    k = src.index(f" void {kernel}(")
+    a = src.rindex("\n", 0, k) + 1
+    prev = src.rindex("\n", 0, a - 1) + 1
+    if src.startswith("template <", prev):
+        a = prev
     b = src.index("\n}\n", k) + 3
     return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
 
 
-def measured_traffic(name: str):
-    """HBM bytes per k_block_step dispatch from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel source; else None."""
-    p = os.path.join(ROOT, "profiles", f"k_block_step_{name}_traffic.md")
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per dispatch of a kernel from the committed rocprofv3 counter
+    summary profiles/<kernel>_<workload>_traffic.md, if it was taken on the
+    current kernel source; else None."""
+    p = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.md")
     if not os.path.exists(p):
         return None
     kv = {}
@@ -79,9 +83,31 @@ def measured_traffic(name: str):
         if "=" in line and not line.startswith(" "):
             k, v = line.strip().split("=", 1)
             kv[k] = v
-    if kv.get("k_block_step_source_sha256_16") != kernel_source_hash():
+    if kv.get(f"{kernel}_source_sha256_16") != kernel_source_hash(kernel):
         return None
     return int(kv["traffic_bytes_per_dispatch"])
+
+
+def copy_calibration():
+    """A plain elementwise copy of 1 GiB (read 1 GiB, write 1 GiB): what the
+    HBM byte counters read for it scales them to bytes."""
+    import torch
+    n = 1 << 28                                   # 1 GiB of float32 per buffer
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    times = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        torch.mul(a, 1.0, out=b)          # plain elementwise copy kernel
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    copy = {"kernel": "torch.mul(a, 1.0, out=b) (vectorized_elementwise_kernel)",
+            "bytes_read": 4 * n, "bytes_written": 4 * n,
+            "best_GBps": round(8 * n / min(times) / 1e9, 1)}
+    del a, b
+    log(f"copy calibration: {copy}")
+    return copy
 
 
 def host_info(cores: int) -> dict:
@@ -465,7 +491,8 @@ def bench_c5(args, tcm):
             alg = 16 * ts["grad_cells"]
             achieved = alg / (ts["grad_ms"] * 1e-3) / 1e9
             roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_adjoint_grad",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": measured_traffic("k_adjoint_grad", "c5"), "kernel": "k_adjoint_grad",
                     "avg_launch_us": round(ts["grad_ms"] * 1e3 / ts["grad_launches"], 2),
                     "algorithmic_bytes_per_launch": round(alg / ts["grad_launches"]),
                     "active_node_fraction": round(ts["grad_cells"] / (nodes * ts["grad_launches"]), 4)}
@@ -500,7 +527,8 @@ def bench_c5(args, tcm):
                       "time_steps_per_run": steps},
            "roofline": roof, "cpu_baseline": cpu,
            "adjoint": {"forward_s": round(tf / args.steps, 4), "adjoint_s": round(ta / args.steps, 4),
-                       "adjoint_over_forward": round(ta / tf, 3)}, "interval8": k8, "autotune": tuning}
+                       "adjoint_over_forward": round(ta / tf, 3)}, "interval8": k8, "autotune": tuning,
+           "copy_calibration": copy_calibration() if args.copy_calibration else None}
     print(json.dumps(out), flush=True)
 
 
@@ -610,7 +638,7 @@ def main():
         log(f"graph replay: {gel:.3f} s")
 
     roof = None
-    traffic = measured_traffic(w.name)
+    traffic = measured_traffic("k_block_step", w.name)
     if st_launch > 0 and st_ms > 0:
         # 16 B per node; blocks with a uniform C2 read a scalar instead of the
         # C2 plane: 12 B per node
@@ -638,23 +666,7 @@ def main():
                  "tcm_speedup_wall": round(el / (tot_t / args.steps), 3)}
         log(f"dense: {el:.3f} s ({dense_rate:.3e} node updates/s)")
 
-    copy = None
-    if args.copy_calibration:
-        n = 1 << 28                                   # 1 GiB of float32 per buffer
-        a = torch.ones(n, dtype=torch.float32, device="cuda")
-        b = torch.empty_like(a)
-        times = []
-        for _ in range(3):
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            torch.mul(a, 1.0, out=b)          # plain elementwise copy kernel
-            torch.cuda.synchronize()
-            times.append(time.perf_counter() - t0)
-        copy = {"kernel": "torch.mul(a, 1.0, out=b) (vectorized_elementwise_kernel)",
-                "bytes_read": 4 * n, "bytes_written": 4 * n,
-                "best_GBps": round(8 * n / min(times) / 1e9, 1)}
-        del a, b
-        log(f"copy calibration: {copy}")
+    copy = copy_calibration() if args.copy_calibration else None
 
     err_table = None
     p = os.path.join(ROOT, "tests", "golden", f"{w.name}_golden.json")
