@@ -313,8 +313,14 @@ __global__ __launch_bounds__(64 * W) void k_block_step(Tables t) {
             share_p[q] = have[q] && j < B - 1 && nb[q][1] >= 0 && nb[q][1] == sl_next[q];
         }
         fetch(ib + stride);
-        // all loads of the wave's blocks, then their tiles
+        // all loads of the wave's blocks, then their tiles.  The wave raises
+        // its own issue priority while it issues the loads, so that a wave
+        // starting its blocks gets its loads out ahead of waves busy with
+        // their arithmetic and LDS work (on the 512^3 two-layer workload 138.2
+        // against 140.5 us per launch with one block per wave at 16 waves per
+        // CU, 140.5 against 147.1 us with two blocks per wave).
         float fmx[P], fpx[P], fmy[P], fpy[P];
+        __builtin_amdgcn_s_setprio(1);
 #pragma unroll
         for (int q = 0; q < P; q++) {
             zlo[q] = 0.f; zhi[q] = 0.f; pinned[q] = 0; out_p[q] = nullptr;
@@ -344,6 +350,7 @@ __global__ __launch_bounds__(64 * W) void k_block_step(Tables t) {
             if (nb[q][2] >= 0) fmy[q] = plane_of(t, nb[q][2], p)[zz * 64 + 7 * 8 + a];
             if (nb[q][3] >= 0) fpy[q] = plane_of(t, nb[q][3], p)[zz * 64 + 0 * 8 + a];
         }
+        __builtin_amdgcn_s_setprio(0);
 #pragma unroll
         for (int q = 0; q < P; q++) {
             if (!have[q]) continue;
