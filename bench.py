@@ -71,10 +71,11 @@ def kernel_source_hash(kernel: str = "k_block_step") -> str:
     return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
 
 
-def measured_traffic(kernel: str, workload: str):
+def measured_traffic(kernel: str, workload: str, shape: str = None):
     """HBM bytes per dispatch of a kernel from the committed rocprofv3 counter
     summary profiles/<kernel>_<workload>_traffic.md, if it was taken on the
-    current kernel source; else None."""
+    current kernel source (and, where the summary names one, at the launch
+    shape given as "<tile>x<blocks per wave>@<workgroups per CU>"); else None."""
     p = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.md")
     if not os.path.exists(p):
         return None
@@ -85,7 +86,44 @@ def measured_traffic(kernel: str, workload: str):
             kv[k] = v
     if kv.get(f"{kernel}_source_sha256_16") != kernel_source_hash(kernel):
         return None
+    if shape is not None and kv.get("launch_shape", shape) != shape:
+        return None
     return int(kv["traffic_bytes_per_dispatch"])
+
+
+def launch_shape(tuning, args) -> str:
+    """The stencil's launch shape as "<tile>x<blocks per wave>@<workgroups per
+    CU>": the tuned one, else the options given, else the library's default
+    (tile of 4, one block per wave, about 12 waves per CU)."""
+    if tuning:
+        return f"{tuning['blocks_per_wg']}x{tuning['blocks_per_wave']}@{tuning['wg_per_cu']}"
+    bw = args.blocks_per_wg or 4
+    bp = args.blocks_per_wave or 1
+    return f"{bw}x{bp}@{args.wg_per_cu or max(1, 12 // (bw // bp))}"
+
+
+def whole_run_pick(sim, w, steps, tuning, cands):
+    """The probe times candidates on one state; the active set of a run grows
+    from a few blocks to the whole domain, and the shape that wins on one
+    state need not win over the run.  Take each shape family's (tile, blocks
+    per wave) best workgroups per CU from the probe, time two whole runs of
+    each (untimed for the result) and keep the fastest."""
+    fam = {}
+    for bw, bp, wpc, gs, ms in cands:
+        if (bw, bp) not in fam or ms < fam[(bw, bp)][3]:
+            fam[(bw, bp)] = (bw, bp, wpc, ms)
+    runs = []
+    for bw, bp, wpc, _ in sorted(fam.values(), key=lambda c: c[3]):
+        sim.set_launch(wpc, tuning["graph_steps"], bw, bp)
+        el = min(run_once(sim, w, steps)[0] for _ in range(2))
+        runs.append((el, bw, bp, wpc))
+    el, bw, bp, wpc = min(runs)
+    sim.set_launch(wpc, tuning["graph_steps"], bw, bp)
+    tuning["probe_choice"] = {k: tuning[k] for k in ("blocks_per_wg", "blocks_per_wave", "wg_per_cu")}
+    tuning.update(blocks_per_wg=bw, blocks_per_wave=bp, wg_per_cu=wpc)
+    tuning["whole_run_s"] = {f"{b}x{p}@{c}": round(e, 4) for e, b, p, c in runs}
+    log(f"whole-run pick: tile {bw} blocks ({bp} per wave), wg_per_cu {wpc}: {el:.4f} s "
+        f"({', '.join(f'{b}x{p}@{c} {e:.4f}' for e, b, p, c in runs)})")
 
 
 def copy_calibration():
@@ -606,9 +644,11 @@ def main():
         sim.step(steps // 2)
         tuning = sim.autotune(probe_steps=32, cache=os.environ.get("TCM_TUNE_CACHE"),
                               key=f"gfx950/{w.name}/k{args.interval}")
-        tuning.pop("candidates", None)
+        cands = tuning.pop("candidates", None)
         log(f"autotune: tile {tuning['blocks_per_wg']} blocks ({tuning['blocks_per_wave']} per wave), wg_per_cu {tuning['wg_per_cu']}, "
             f"graph_steps {tuning['graph_steps']}")
+        if cands:
+            whole_run_pick(sim, w, steps, tuning, cands)
     tot_t, tot_u, st_ms, st_cells, st_launch, st_cells_u = 0.0, 0, 0.0, 0, 0, 0
     for i in range(args.steps):
         el, st = run_once(sim, w, steps)
@@ -638,7 +678,8 @@ def main():
         log(f"graph replay: {gel:.3f} s")
 
     roof = None
-    traffic = measured_traffic("k_block_step", w.name)
+    shape = launch_shape(tuning, args)
+    traffic = measured_traffic("k_block_step", w.name, shape)
     if st_launch > 0 and st_ms > 0:
         # 16 B per node; blocks with a uniform C2 read a scalar instead of the
         # C2 plane: 12 B per node
@@ -646,7 +687,7 @@ def main():
         achieved = alg_bytes / (st_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "k_block_step",
+                "kernel": "k_block_step", "launch_shape": shape,
                 "avg_launch_us": round(st_ms * 1e3 / st_launch, 2),
                 "algorithmic_bytes_per_launch": round(alg_bytes / st_launch),
                 "uniform_c2_node_fraction": round(st_cells_u / max(st_cells, 1), 4),
@@ -687,7 +728,10 @@ def main():
         if ok:
             rel, rec = max(ok, key=lambda kv: kv[0])
             esim = tcm.Simulation(w.shape, w.dx, w.dt, media_of(w), rel * w.wavelet.peak,
-                                  rel * w.wavelet.peak / 10, timing=True)
+                                  rel * w.wavelet.peak / 10, timing=True,
+                                  wg_per_cu=(tuning or {}).get("wg_per_cu", args.wg_per_cu),
+                                  blocks_per_wg=(tuning or {}).get("blocks_per_wg", args.blocks_per_wg),
+                                  blocks_per_wave=(tuning or {}).get("blocks_per_wave", args.blocks_per_wave))
             run_once(esim, w, steps)
             el, est = run_once(esim, w, steps)
             esim.close()
