@@ -1298,9 +1298,54 @@ __global__ void k_read(Tables t, int shot, int which, int x0, int y0, int z0, in
     }
 }
 
+// The same with each thread taking two neighbouring nodes of a row (x0 and
+// sx even, out 8-byte aligned): both lie in one block, so one 8-byte load
+// from its plane and one 8-byte store.
+typedef float read_f2 __attribute__((ext_vector_type(2)));
+
+__global__ void k_read_pairs(Tables t, int shot, int which, int x0, int y0, int z0, int sx, int sy,
+                             int sz, float* __restrict__ out) {
+    const int lp = blockIdx.x * blockDim.x + threadIdx.x;
+    if (2 * lp >= sx) return;
+    const int plane = which == 0 ? (t.st->step & 1) : 1 - (t.st->step & 1);
+    const Shot& S = t.shots[shot];
+    const int gx = x0 + 2 * lp;
+    const long long rows = (long long)sy * sz;
+    for (long long r0 = (long long)blockIdx.y * READ_RB; r0 < rows; r0 += (long long)gridDim.y * READ_RB) {
+        int slot[READ_RB], loc[READ_RB];
+#pragma unroll
+        for (int k = 0; k < READ_RB; k++) {
+            slot[k] = EMPTY;
+            loc[k] = 0;
+            const long long row = r0 + k;
+            if (row < rows) {
+                const int gy = y0 + (int)(row % sy), gz = z0 + (int)(row / sy);
+                slot[k] = t.cell2box[S.key_base + (long long)block_to_key(S, gx >> 3, gy >> 3, gz >> 3)];
+                loc[k] = ((gz & 7) * 8 + (gy & 7)) * 8 + (gx & 7);
+            }
+        }
+        read_f2 v[READ_RB];
+#pragma unroll
+        for (int k = 0; k < READ_RB; k++) {
+            v[k] = read_f2{0.f, 0.f};
+            if (slot[k] >= 0) v[k] = *(const read_f2*)(plane_of(t, slot[k], plane) + loc[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < READ_RB; k++)
+            if (r0 + k < rows)
+                __builtin_nontemporal_store(v[k], (read_f2*)&out[(size_t)(r0 + k) * sx + 2 * lp]);
+    }
+}
+
 hipError_t launch_read(const Tables& t, int shot, int which, int x0, int y0, int z0, int sx, int sy,
                        int sz, float* out, hipStream_t s) {
     if (sx <= 0 || sy <= 0 || sz <= 0) return hipSuccess;
+    if (x0 % 2 == 0 && sx % 2 == 0 && ((uintptr_t)out & 7u) == 0) {
+        const long long groups = ((long long)sy * sz + READ_RB - 1) / READ_RB;
+        dim3 grid((unsigned)((sx / 2 + 255) / 256), (unsigned)std::min<long long>(groups, 65535));
+        hipLaunchKernelGGL(k_read_pairs, grid, dim3(256), 0, s, t, shot, which, x0, y0, z0, sx, sy, sz, out);
+        return hipGetLastError();
+    }
     const long long groups = ((long long)sy * sz + READ_RB - 1) / READ_RB;
     dim3 grid((unsigned)((sx + 255) / 256), (unsigned)std::min<long long>(groups, 65535));
     hipLaunchKernelGGL(k_read, grid, dim3(256), 0, s, t, shot, which, x0, y0, z0, sx, sy, sz, out);

@@ -268,6 +268,14 @@ def test_launch_modes_and_reads_agree():
     out = torch.empty(11 * 9 * 20, dtype=torch.float32, device="cuda")
     a.read(0, box=((3, 17, 30), (20, 9, 11)), out=out)
     assert values_equal(out.cpu().numpy().reshape(11, 9, 20), phi[30:41, 17:26, 3:23])
+    # even x origin and width: two nodes per thread; odd width, or an output
+    # that is not 8-byte aligned: one node per thread
+    assert values_equal(a.read(0, box=((4, 17, 30), (20, 9, 11))), phi[30:41, 17:26, 4:24])
+    assert values_equal(a.read(0, box=((4, 17, 30), (19, 9, 11))), phi[30:41, 17:26, 4:23])
+    big = torch.empty(1 + 11 * 9 * 20, dtype=torch.float32, device="cuda")
+    a.read(0, box=((4, 17, 30), (20, 9, 11)), out=big[1:])
+    assert values_equal(big[1:].cpu().numpy().reshape(11, 9, 20), phi[30:41, 17:26, 4:24])
+    assert values_equal(a.read(1, box=((56, 0, 60), (8, 64, 4))), a.read(1)[60:64, :, 56:64])
     a.reset()
     assert not a.read(0).any() and a.stats()["step"] == 0
     a.add_source(w.source, w.wavelet.w32)
