@@ -7,9 +7,10 @@
 //                 (or per two consecutive blocks), lane = (x, y) column with
 //                 the 8 z values in registers, the neighbour face planes
 //                 staged in LDS (x faces shared between the blocks of a
-//                 workgroup, which takes x-adjacent blocks); additive source
-//                 insertion; wave-ballot face/keep predicates -> one flag
-//                 byte per slot.
+//                 workgroup, which takes x-adjacent blocks); a wave raises
+//                 its issue priority while it issues a block's loads;
+//                 additive source insertion; wave-ballot face/keep
+//                 predicates -> one flag byte per slot.
 //   k_plan        keep / release each active block, claim empty face neighbours
 //                 with a compare-and-swap on the block table, mark the next
 //                 active set in a bitmap; receivers are recorded here.
