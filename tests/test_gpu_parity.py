@@ -136,6 +136,56 @@ def test_retirement_path_matches_cpu_tcm():
     assert not sim.read(0).any()
 
 
+@pytest.mark.parametrize("levels,w", [((0.0, 0.0), (0.25, -0.5)), ((1e30, 0.125), (0.25, -0.5)),
+                                      ((0.25, 0.0), (0.25, -0.25)),
+                                      ((float(np.nextafter(np.float32(0.25), np.float32(0))), 0.0),
+                                       (0.25, -0.25)),
+                                      ((1e30, 0.25), (0.25, -0.25)),
+                                      ((1e30, float(np.nextafter(np.float32(0.25), np.float32(0)))),
+                                       (0.25, -0.25))])
+def test_exact_level_cases_match_cpu_tcm(levels, w):
+    """C2 = 0, so the field changes only at its source node: a value exactly at
+    the trigger or keep level (strict comparisons), one ulp above it, and a
+    cell whose new level is zero while its current level is not (kept at
+    threshold 0).  Active sets and fields equal the CPU TCM every step."""
+    announce(f"exact-level rules {levels} w={w}")
+    trig, ret = (np.float32(v) for v in levels)
+    c = np.zeros((24, 16, 16), np.float32)
+    ws = np.array(w, np.float32)
+    xyz = (7, 3, 3) if ws[1] == -ws[0] else (3, 4, 5)
+    t = oracle.TCM(c, 0.5, 1.0, trig, ret)
+    t.add_source(xyz, ws)
+    sim = gpu_run((16, 16, 24), 0.5, c, [(xyz, ws)], 0, trig, ret)
+    for k in range(8):
+        assert t.step(1) == 0
+        sim.step(1)
+        assert sim.stats()["active_blocks"] == t.stats()["active"], k
+        assert values_equal(sim.read(0), t.read(0)) and values_equal(sim.read(1), t.read(1)), k
+    g, o = sim.stats(), t.stats()
+    assert g["activations"] == o["activations"] and g["retirements"] == o["retirements"]
+
+
+def test_retiring_pulse_matches_cpu_tcm_every_step():
+    """Homogeneous box at a single level: the pulse leaves cells behind it,
+    some released one step after their new level fell below the level."""
+    announce("retiring pulse, single level, every step")
+    shape = (56, 52, 48)
+    c = np.ones(shape[::-1], np.float32)
+    w = ti.ricker(0.15, 0.5).w32
+    lvl = np.float32(3e-3 * float(np.max(np.abs(w))))
+    t = oracle.TCM(c, 0.5, 1.0, lvl, lvl)
+    t.add_source((20, 18, 15), w)
+    sim = gpu_run(shape, 0.5, c, [((20, 18, 15), w)], 0, lvl, lvl)
+    for k in range(90):
+        assert t.step(1) == 0
+        sim.step(1)
+        assert sim.stats()["active_blocks"] == t.stats()["active"], k
+    assert values_equal(sim.read(0), t.read(0)) and values_equal(sim.read(1), t.read(1))
+    g, o = sim.stats(), t.stats()
+    assert o["retirements"] > 0 and g["retirements"] == o["retirements"]
+    assert g["cell_updates"] == o["updates"]
+
+
 def test_pool_cap_fails_like_cpu_tcm():
     announce("pool cap E_POOL")
     w = ti.c1(steps=60)

@@ -6,7 +6,8 @@
 * an infinite trigger level isolates the source cell: the result is the dense
   solution on that cell alone with zero ghosts;
 * bookkeeping invariants of Table 1 (Cell2box / Box2cell bijection, every box
-  either active or vacant, vacant boxes initialised);
+  either active or vacant, vacant boxes initialised); the activation rules
+  themselves are pinned in test_oracle_rules.py;
 * the result does not depend on the order in which boxes are stepped;
 * a box cap fails deterministically and keeps the last complete step.
 """
@@ -85,7 +86,10 @@ def test_infinite_trigger_isolates_source_cell():
     assert t.check() == 0
 
 
-def test_invariants_and_rules_random_thresholds():
+def test_invariants_random_thresholds():
+    """Table 1 bookkeeping stays consistent over uneven step chunks at
+    thresholds above zero (the activation rules themselves are checked step by
+    step in test_oracle_rules.py)."""
     rng = np.random.default_rng(9)
     shape = (40, 36, 30)
     c = ti.random_media(shape, seed=9, cmin=0.4, cmax=1.0)
@@ -94,20 +98,9 @@ def test_invariants_and_rules_random_thresholds():
     trig, ret = np.float32(3e-4), np.float32(5e-5)
     t = oracle.TCM(c, dt, 1.0, trig, ret)
     t.add_source((20, 18, 15), w)
-    B = 8
     for k in range(25):
         assert t.step(int(rng.integers(1, 6))) == 0
         assert t.check() == 0
-        trg = t.triggered().astype(bool)
-        cur, prv = t.read(0), t.read(1)
-        # every cell holding a value above `retire` is active; inactive cells are zero
-        nz, ny, nx = shape[::-1]
-        mz, my, mx = trg.shape
-        pad = np.zeros((mz * B, my * B, mx * B), np.float32)
-        big = np.maximum(np.abs(cur), np.abs(prv))
-        pad[:nz, :ny, :nx] = big
-        cellmax = pad.reshape(mz, B, my, B, mx, B).max(axis=(1, 3, 5))
-        assert not np.any(cellmax[~trg] > 0)
     st = t.stats()
     assert 0 < st["active"] <= st["peak_active"] <= st["boxes"]
     assert st["activations"] - st["retirements"] == st["active"]
