@@ -970,8 +970,10 @@ tcm_status tcm_step(tcm_handle* h, int32_t nsteps) {
     if (h->h_state->error) return set_err(h, (tcm_status)h->h_state->error, "pool exhausted at an earlier step");
     st = ensure_trace_capacity(h, h->h_state->step + (long long)nsteps - h->t.trace_step0);
     if (st) return st;
-    const unsigned long long upd0 = h->h_state->updates + h->h_state->cells_cur;
-    const unsigned long long updu0 = h->h_state->updates_u + h->h_state->cells_cur_u;
+    // nodes stepped by this call: the lists C_0 .. C_{n-1} it runs (the list
+    // left for the next call is not stepped here)
+    const unsigned long long upd0 = h->h_state->updates;
+    const unsigned long long updu0 = h->h_state->updates_u;
     h->hstep = h->h_state->step;
 
     // one run of n steps: graph replay, or direct launches with HIP events
@@ -1011,8 +1013,8 @@ tcm_status tcm_step(tcm_handle* h, int32_t nsteps) {
     st = sync_state(h);
     if (st) return st;
     if (timing) {
-        h->stencil_cells += (long long)(h->h_state->updates + h->h_state->cells_cur - upd0);
-        h->stencil_cells_u += (long long)(h->h_state->updates_u + h->h_state->cells_cur_u - updu0);
+        h->stencil_cells += (long long)(h->h_state->updates - upd0);
+        h->stencil_cells_u += (long long)(h->h_state->updates_u - updu0);
     }
     if (h->h_state->error) {
         return set_err(h, (tcm_status)h->h_state->error,

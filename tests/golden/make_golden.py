@@ -4,6 +4,7 @@ Calls only the CPU oracle (oracle/) and the input generators (tcm_inputs/).
 Usage:  python tests/golden/make_golden.py c2 [--sweep]
         python tests/golden/make_golden.py c5
         python tests/golden/make_golden.py c4
+        python tests/golden/make_golden.py c4tau      (after c4)
         python tests/golden/make_golden.py c2k8
         python tests/golden/make_golden.py c5resid
 
@@ -213,6 +214,33 @@ def make_c2k8():
         log(f"c2k8 {name}: err {res[name]['err']:.3e} updates {st['updates']:.3e} ({time.time() - t0:.0f} s)")
 
 
+C4_TAU_SHOTS = (17, 61, 41)      # the three smallest shots (about 3e6 nodes each)
+
+
+def make_c4tau():
+    """Shots 17, 61 and 41 of the 64-shot workload at its thresholds (trigger
+    1e-6 / retire 1e-7 of the source peak), 1500 steps: SHA-256 of the FP32
+    CPU TCM's final phi^n and phi^{n-1}, and its statistics."""
+    path = os.path.join(HERE, "c4_golden.json")
+    res = json.load(open(path))
+    shots = ti.c4_shots()
+    res["tau_shots"] = []
+    for i in C4_TAU_SHOTS:
+        s = shots[i]
+        t0 = time.time()
+        t = oracle.TCM(ti.lattice_to_dense(s.lattice, s.shape), s.dt, s.dx, np.float32(s.trigger),
+                       np.float32(s.retire))
+        t.add_source(s.source, s.wavelet.w32)
+        assert t.step(s.steps) == 0
+        res["tau_shots"].append({"shot": i, "shape": s.shape, "trigger": float(np.float32(s.trigger)),
+                                 "retire": float(np.float32(s.retire)),
+                                 "phi_sha256": digest(t.read(0)), "prev_sha256": digest(t.read(1)),
+                                 "stats": t.stats()})
+        t.close()
+        json.dump(res, open(path, "w"))
+        log(f"{s.name} {s.shape} at the workload thresholds: {time.time() - t0:.0f} s")
+
+
 def make_c4():
     """Shots 0-3 of the 64-shot workload at threshold 0: SHA-256 of the FP32
     dense oracle's final phi^n (equal to the TCM at threshold 0)."""
@@ -236,6 +264,8 @@ if __name__ == "__main__":
         make_c5()
     elif which == "c4":
         make_c4()
+    elif which == "c4tau":
+        make_c4tau()
     elif which == "c2k8":
         make_c2k8()
     elif which == "c5resid":

@@ -59,6 +59,25 @@ def test_c2_full_run_bitexact_to_cpu_tcm():
     assert digest(tr) == g["traces_sha256"]
 
 
+def test_c2_equal_error_run_bitexact_to_cpu_tcm():
+    """The run the equal-error speed-up is quoted on: 512^3 two-layer, 2000
+    steps, trigger 1e-9 / retire 1e-10 of the source peak, activation update
+    every step.  The final field and the work equal the CPU TCM's (threshold
+    sweep of c2_golden.json)."""
+    announce("C2 trigger 1e-9 / retire 1e-10 vs stored CPU TCM result")
+    g = load("c2_golden.json")["sweep"]["1e-09"]
+    w = ti.c2()
+    trig = np.float32(1e-9 * w.wavelet.peak)
+    ret = np.float32(trig / 10)
+    sim = tcm.Simulation(w.shape, w.dx, w.dt, w.layered, float(trig), float(ret), timing=True)
+    sim.add_source(w.source, w.wavelet.w32)
+    sim.step(w.steps)
+    st = sim.stats()
+    assert st["step"] == w.steps and st["error"] == 0
+    assert st["cell_updates"] == g["updates"] and st["peak_active_blocks"] == g["peak_active"]
+    assert digest(sim.read(0)) == g["sha256"]
+
+
 @pytest.mark.parametrize("name", ["workload", "1e-09"])
 def test_c2_interval8_full_run_bitexact_to_cpu_tcm(name):
     """512^3 two-layer, 2000 steps with the activation update every 8 steps
@@ -110,7 +129,8 @@ def test_c3_virtual_4096_first_steps_match_cpu_tcm_on_crop():
 
 def test_c4_full_batch_equals_single_shots():
     """64 shots (edges 96..384) over one shared pool, 1500 steps at the
-    workload thresholds: every shot equals its own single-shot run."""
+    workload thresholds: shots 17, 61 and 41 equal the CPU TCM (stored
+    hashes), and every shot equals its own single-shot run."""
     announce("C4 64-shot batch vs single shots")
     shots = ti.c4_shots()
     b = tcm.Simulation([s.shape for s in shots], 1.0, shots[0].dt, [s.lattice for s in shots],
@@ -118,6 +138,12 @@ def test_c4_full_batch_equals_single_shots():
     for i, s in enumerate(shots):
         b.add_source(s.source, s.wavelet.w32, shot=i)
     b.step(shots[0].steps)
+    # three shots against the CPU TCM at these thresholds
+    for o in load("c4_golden.json")["tau_shots"]:
+        i = o["shot"]
+        assert np.float32(shots[i].trigger) == np.float32(o["trigger"])
+        assert digest(b.read(0, shot=i)) == o["phi_sha256"], i
+        assert digest(b.read(1, shot=i)) == o["prev_sha256"], i
     tot = 0
     for i, s in enumerate(shots):
         one = tcm.Simulation(s.shape, 1.0, s.dt, s.lattice, s.trigger, s.retire)
@@ -177,8 +203,13 @@ def test_c5_gradient_against_fp64_adjoint_and_finite_differences():
     fd_err = [abs(grad_e2e[z, y, x] - f["fd"]) / abs(f["fd"])
               for f in g["fd_cells"] for (x, y, z) in [f["xyz"]]]
     e2e_sub = np.linalg.norm(grad_e2e[::8, ::8, ::8] - sub) / np.linalg.norm(sub)
+    # the residual is the trace difference of a 2 % model change: the FP32
+    # forward's rounding of the traces is a much larger part of it than of the
+    # traces, and the gradient is linear in the residual
+    e_res = float(np.linalg.norm(resid.astype(np.float64) - resid_o) / np.linalg.norm(resid_o))
     print(f"C5 same residual: rel-L2 vs FP64 adjoint (every 8th node) {e_sub:.3e}, (4096 nodes) "
           f"{e_smp:.3e}; end to end: max rel err vs FD over {len(fd_err)} nodes {max(fd_err):.3e}, "
-          f"rel-L2 every 8th node {e2e_sub:.3e}")
+          f"rel-L2 every 8th node {e2e_sub:.3e} (FP32 residual vs FP64: {e_res:.3e})")
     assert len(fd_err) == 32
     assert e_sub <= 1e-3 and e_smp <= 1e-3 and max(fd_err) <= 1e-2
+    assert e2e_sub <= 5e-3

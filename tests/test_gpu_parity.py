@@ -474,6 +474,14 @@ def test_uniform_c2_blocks_give_identical_results():
     # blocks straddling z = 37 (not a multiple of 8) or cut by the domain edge are not uniform
     assert 0 < sa["uniform_cell_updates"] < sa["cell_updates"]
     assert 0 < sa["stencil_cells_uniform"] <= sa["stencil_cells"]
+    # the timed launches stepped exactly the nodes the run counts as updated,
+    # over several calls as well
+    for n in (7, 1, 30):
+        a.step(n)
+        sa = a.stats()
+        assert sa["stencil_cells"] == sa["cell_updates"], n
+        assert sa["stencil_cells_uniform"] == sa["uniform_cell_updates"], n
+        assert sa["stencil_launches"] == sa["step"], n
 
 
 @pytest.mark.parametrize("n,alpha", [(20, 0.8), (3, 0.0), (1, 1.0)])
