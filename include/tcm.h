@@ -190,6 +190,19 @@ tcm_status tcm_read_shot(tcm_handle* h, int32_t shot, int32_t which, int32_t x0,
                          int32_t z0, int32_t sx, int32_t sy, int32_t sz, float* out,
                          int32_t out_is_device);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * read as tcm_read_shot into host memory `out` (sx*sy*sz floats, x fastest),
+ * staged through a static device array of the library (8 Mi floats = 32 MiB
+ * per GPU, kept until the process ends) instead of a staging buffer the
+ * handle allocates.  Calls no hipMalloc / hipFree.  Every call on one GPU
+ * uses that GPU's one staging array: calls that overlap on one GPU (other
+ * threads, other handles) race.  Synchronises the handle's stream.
+ * TCM_E_ARG for a box of more than 8 Mi nodes or a NULL out; TCM_E_RANGE
+ * outside the grid. */
+tcm_status tcm_read_noalloc(tcm_handle* h, int32_t shot, int32_t which, int32_t x0, int32_t y0,
+                            int32_t z0, int32_t sx, int32_t sy, int32_t sz, float* out);
+
 /* Receivers: rec_xyz holds nrec (x,y,z) triples of shot 0 (rec_shot NULL) or
  * of shots rec_shot[r].  From the next step on, traces[k][r] = phi^{m+k+1} at
  * receiver r, where phi^m is the level when receivers were set. */

@@ -21,6 +21,7 @@ EXPORTS = [
     "tcm_read", "tcm_read_shot", "tcm_set_receivers", "tcm_read_traces", "tcm_adjoint",
     "tcm_reset", "tcm_stats", "tcm_destroy", "tcm_last_error", "tcm_version", "tcm_autotune",
     "tcm_set_launch", "tcm_snapshot", "tcm_restore", "tcm_snapshot_free", "tcm_hbm_probe",
+    "tcm_read_noalloc",
 ]
 
 
@@ -98,6 +99,7 @@ def lib():
         L.tcm_step.argtypes = [H, I]
         L.tcm_read.argtypes = [H, I, I, I, I, I, I, I, P, I]
         L.tcm_read_shot.argtypes = [H, I, I, I, I, I, I, I, I, P, I]
+        L.tcm_read_noalloc.argtypes = [H, I, I, I, I, I, I, I, I, P]
         L.tcm_set_receivers.argtypes = [H, P, P, I]
         L.tcm_read_traces.argtypes = [H, P, I, F(C.c_int32)]
         L.tcm_adjoint.argtypes = [H, P, I, I, P, I]

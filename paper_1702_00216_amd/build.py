@@ -24,7 +24,7 @@ COMMON = ["-O3", "-fPIC", "-std=c++17", "-ffp-contract=off", "-fno-fast-math",
 DEVICE = [f"--offload-arch={ARCH}", "-mcode-object-version=5", "-Xclang", "-target-feature", "-Xclang",
           "-packed-fp32-ops"]
 
-SOURCES = [("tcm_kernels.hip", True), ("tcm_runtime.cpp", False)]
+SOURCES = [("tcm_kernels.hip", True), ("tcm_noalloc.hip", True), ("tcm_runtime.cpp", False)]
 
 
 def build(verbose: bool = False) -> str:

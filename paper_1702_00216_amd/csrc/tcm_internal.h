@@ -188,4 +188,9 @@ long long hbm_probe_chunk();
 hipError_t launch_hbm_probe(const float* src, float* dst, long long n, int nread, int grid, hipStream_t s,
                             hipEvent_t e0, hipEvent_t e1);
 
+// staging of tcm_read_noalloc (tcm_noalloc.hip): a static device array of
+// NOALLOC_FLOATS floats per GPU; its device address for the current device
+constexpr long long NOALLOC_FLOATS = 8LL << 20;
+hipError_t noalloc_staging(float** out);
+
 }  // namespace tcmk

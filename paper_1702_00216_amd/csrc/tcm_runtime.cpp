@@ -1061,6 +1061,36 @@ tcm_status tcm_read(tcm_handle* h, int32_t which, int32_t x0, int32_t y0, int32_
     return tcm_read_shot(h, 0, which, x0, y0, z0, sx, sy, sz, out, out_is_device);
 }
 
+tcm_status tcm_read_noalloc(tcm_handle* h, int32_t shot, int32_t which, int32_t x0, int32_t y0, int32_t z0,
+                            int32_t sx, int32_t sy, int32_t sz, float* out) {
+    tcm_status st = check_live(h);
+    if (st) return st;
+    if (shot < 0 || shot >= (int)h->shots.size()) return set_err(h, TCM_E_RANGE, "shot index out of range");
+    if (which != 0 && which != 1) return set_err(h, TCM_E_ARG, "which must be 0 (phi^n) or 1 (phi^{n-1})");
+    const Shot& S = h->shots[shot];
+    if (sx < 0 || sy < 0 || sz < 0 || x0 < 0 || y0 < 0 || z0 < 0 || x0 + (long long)sx > S.nx ||
+        y0 + (long long)sy > S.ny || z0 + (long long)sz > S.nz)
+        return set_err(h, TCM_E_RANGE, "read box outside the grid");
+    const long long count = (long long)sx * sy * sz;
+    if (count == 0) return TCM_OK;
+    if (count > NOALLOC_FLOATS)
+        return set_err(h, TCM_E_ARG, fmt("box of %lld nodes exceeds the %lld-node staging array of "
+                                         "tcm_read_noalloc", count, NOALLOC_FLOATS));
+    if (!out) return set_err(h, TCM_E_ARG, "out is NULL");
+    float* stage = nullptr;
+    HIP_OR_FAIL(h, noalloc_staging(&stage));
+    if (h->engine == TCM_ENGINE_DENSE) {
+        const long long n = h->dense_step;
+        const float* f = h->d_phi[which == 0 ? (n & 1) : 1 - (n & 1)];
+        HIP_OR_FAIL(h, launch_read_dense(f, S.nx, S.ny, x0, y0, z0, sx, sy, sz, stage, h->stream));
+    } else {
+        HIP_OR_FAIL(h, launch_read(h->t, shot, which, x0, y0, z0, sx, sy, sz, stage, h->stream));
+    }
+    HIP_OR_FAIL(h, hipMemcpyAsync(out, stage, (size_t)count * sizeof(float), hipMemcpyDeviceToHost, h->stream));
+    HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+    return TCM_OK;
+}
+
 tcm_status tcm_read_traces(tcm_handle* h, float* out, int32_t out_is_device, int32_t* nsteps) {
     tcm_status st = check_live(h);
     if (st) return st;
