@@ -518,9 +518,10 @@ def bench_c5(args, tcm):
         k8 = {"interval": 8, "forward_s": round(kf, 4), "adjoint_s": round(ka, 4),
               "value": nodes * steps / (kf + ka), "gradient_bit_identical": bool(np.array_equal(g8, g))}
         log(f"c5 interval 8: forward {kf:.3f} s, adjoint {ka:.3f} s, gradient identical {k8['gradient_bit_identical']}")
-    # one more forward + adjoint with HIP events around every gradient launch
-    # (16 B per node of an active adjoint block: u, mu, gs read, gs written)
-    roof = None
+    # one more forward + adjoint with HIP events around every adjoint-field
+    # launch (the stencil that forms mu^m and adds mu^m (L u^{m-1}) to the
+    # gradient) and every recomputed forward launch (which also stores L u)
+    roof, adj_detail = None, None
     if not args.no_roofline:
         tsim = tcm.Simulation(w.shape, w.dx, w.dt, c, checkpoint_every=50, timing=True,
                               trigger_interval=args.interval,
@@ -534,17 +535,42 @@ def bench_c5(args, tcm):
         ts = tsim.stats()
         tsim.close()
         if ts["grad_launches"] > 0 and ts["grad_ms"] > 0:
-            alg = 16 * ts["grad_cells"]
-            achieved = alg / (ts["grad_ms"] * 1e-3) / 1e9
+            # per adjoint step three kernels stream: the recomputed forward step
+            # (16 B per node, 12 B with a scalar C2, + 4 B of L u written), the
+            # adjoint field's step (16 B / 12 B per node) and the gradient term
+            # (mu, L u, partial gradient read and written: 16 B per term node)
+            kern = {
+                "recompute": (20 * ts["recompute_cells"] - 4 * ts["recompute_cells_uniform"],
+                              ts["recompute_ms"], ts["recompute_launches"],
+                              "k_block_step (recomputed forward step, also storing L u)"),
+                "adjoint_field": (16 * ts["adjoint_field_cells"] - 4 * ts["adjoint_field_cells_uniform"],
+                                  ts["adjoint_field_ms"], ts["adjoint_field_launches"],
+                                  "k_block_step (adjoint field)"),
+                "gradient": (16 * ts["grad_cells"], ts["grad_ms"], ts["grad_launches"],
+                             "k_grad_accum (gradient term mu (L u))")}
+            per = {k: {"kernel": v[3], "avg_launch_us": round(v[1] * 1e3 / max(v[2], 1), 2),
+                       "algorithmic_bytes_per_launch": round(v[0] / max(v[2], 1)),
+                       "achieved_GBps": round(v[0] / (v[1] * 1e-3) / 1e9, 1)} for k, v in kern.items()}
+            dom = max(kern, key=lambda k: kern[k][1])
+            alg, ms, nl, kname = kern[dom]
+            achieved = alg / (ms * 1e-3) / 1e9
             roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "traffic": measured_traffic("k_adjoint_grad", "c5"), "kernel": "k_adjoint_grad",
-                    "avg_launch_us": round(ts["grad_ms"] * 1e3 / ts["grad_launches"], 2),
-                    "algorithmic_bytes_per_launch": round(alg / ts["grad_launches"]),
-                    "active_node_fraction": round(ts["grad_cells"] / (nodes * ts["grad_launches"]), 4)}
+                    "traffic": measured_traffic("k_block_step", "c5" + dom), "kernel": kname,
+                    "avg_launch_us": round(ms * 1e3 / nl, 2),
+                    "algorithmic_bytes_per_launch": round(alg / nl)}
+            step_bytes = sum(v[0] for v in kern.values()) / ts["grad_launches"]
+            adj_detail = {
+                "kernels": per,
+                "adjoint_field_node_fraction": round(ts["adjoint_field_cells"] / (nodes * ts["grad_launches"]), 4),
+                "gradient_term_node_fraction": round(ts["grad_cells"] / (nodes * ts["grad_launches"]), 4),
+                "algorithmic_bytes_per_adjoint_step": round(step_bytes),
+                "checkpoint_bytes": ts["checkpoint_bytes"], "checkpoints": ts["checkpoints"],
+                "adjoint_bytes": ts["adjoint_bytes"], "dense_field_bytes": 4 * nodes}
             if not args.no_probe:
                 add_ceiling(tcm, roof, fu=0.0)
-            log(f"c5 gradient kernel: {roof['avg_launch_us']:.1f} us per launch, {achieved:.0f} GB/s")
+            log("c5 adjoint kernels: " + ", ".join(f"{k} {v['avg_launch_us']:.1f} us ({v['achieved_GBps']:.0f} GB/s)"
+                                                   for k, v in per.items()))
     cpu = None
     if not args.no_cpu:
         import oracle
@@ -573,7 +599,11 @@ def bench_c5(args, tcm):
                       "time_steps_per_run": steps},
            "roofline": roof, "cpu_baseline": cpu,
            "adjoint": {"forward_s": round(tf / args.steps, 4), "adjoint_s": round(ta / args.steps, 4),
-                       "adjoint_over_forward": round(ta / tf, 3)}, "interval8": k8, "autotune": tuning,
+                       "adjoint_us_per_step": round(ta / args.steps / steps * 1e6, 2),
+                       "adjoint_step_GBps": (round(adj_detail["algorithmic_bytes_per_adjoint_step"]
+                                                   / (ta / args.steps / steps) / 1e9, 1) if adj_detail else None),
+                       "adjoint_over_forward": round(ta / tf, 3), "detail": adj_detail},
+           "interval8": k8, "autotune": tuning,
            "copy_calibration": copy_calibration() if args.copy_calibration else None}
     print(json.dumps(out), flush=True)
 

@@ -147,10 +147,25 @@ typedef struct {
     int64_t decay_block_steps;    /* block-steps of the shutdown decay (eq.(6)) */
     double  trigger_level;        /* levels used by the last step (adaptive or constant) */
     double  retire_level;
-    double  grad_ms;              /* TCM_FLAG_TIMING: summed gradient-kernel time of tcm_adjoint calls */
-    int64_t grad_launches;        /* TCM_FLAG_TIMING: launches summed in grad_ms (one per adjoint step) */
-    int64_t grad_cells;           /* TCM_FLAG_TIMING: adjoint-field node updates of those calls (the nodes
-                                   * whose gradient term the kernel formed) */
+    double  grad_ms;              /* TCM_FLAG_TIMING: summed time of the gradient-term kernel of
+                                     tcm_adjoint calls (one launch per adjoint step) */
+    int64_t grad_launches;        /* TCM_FLAG_TIMING: launches summed in grad_ms */
+    int64_t grad_cells;           /* TCM_FLAG_TIMING: nodes whose gradient term mu (L u) those launches
+                                     formed (adjoint block active, forward block active a step before) */
+    double  adjoint_field_ms;     /* TCM_FLAG_TIMING: summed block-stencil time of the adjoint field */
+    int64_t adjoint_field_launches;
+    int64_t adjoint_field_cells;  /* nodes those adjoint-field steps updated */
+    int64_t adjoint_field_cells_uniform; /* of those, nodes of blocks with a scalar C2 */
+    double  recompute_ms;         /* TCM_FLAG_TIMING: summed block-stencil time of the forward steps that
+                                     tcm_adjoint recomputed (they also store L u per node) */
+    int64_t recompute_launches;
+    int64_t recompute_cells;      /* nodes those recomputed steps updated */
+    int64_t recompute_cells_uniform; /* of recompute_cells, nodes of blocks with a scalar C2 */
+    int64_t checkpoint_bytes;     /* device bytes of the stored forward checkpoints (sparse: the
+                                     active blocks' two phi levels and tables, ~4 KiB per block) */
+    int64_t checkpoints;          /* forward checkpoints stored */
+    int64_t adjoint_bytes;        /* device bytes the last tcm_adjoint held besides the checkpoints:
+                                     L u store, key maps, gradient blocks, adjoint-field pool and tables */
 } tcm_stats_t;
 
 /* Create a single-shot handle (eq.(3) on an nx*ny*nz grid, "Cells construction").

@@ -64,13 +64,15 @@ struct DevState {
     unsigned long long activations, retirements;
     int free_next;                   // free slots after this step's allocation: installed, and the
                                      // step's n_new / n_ret / n_dec cleared, by the compaction
+    int n_gblocks;                   // adjoint: gradient blocks handed out (first gradient term of a key)
+    int grad_error;                  // adjoint: a gradient block or lap-store entry was out of range
 };
 
 struct Src {
     long long key;     // global block key
     int local;         // node inside the block, (z * 8 + y) * 8 + x
     int t0, ns;        // first step and sample count
-    int pad;
+    int next;          // next source of the same block in insertion order, or -1
     long long w_off;   // offset of the samples in the sample array
 };
 
@@ -95,6 +97,7 @@ struct Tables {
     int* rows;                      // per list entry: slot, 6 neighbour slots (or EMPTY), global key
     unsigned char* flags;           // per slot: face bits 0..5 and KEEP_BIT
     int* pin_until;                 // per slot: active while step < pin_until (sources)
+    int* src_head;                  // per slot: the block's first source (chained by Src::next), or -1
     float* slot_c2u;                // per slot: the block's C2 if uniform over the block, else NaN
     unsigned char* sdlog;           // per slot: shutdown steps left (0: not shutting down)
     int* dec_slot;                  // per step: slots whose levels are multiplied by alpha
@@ -126,6 +129,25 @@ struct Tables {
     int trace_step0, trace_cap;
     double dt, dx;
     float trigger, retire;
+    // Recomputation of a forward segment for the adjoint (null otherwise):
+    // the block stencil also stores L u^n of list entry i at rec_lap + i * 512
+    // (entries below rec_lapcap) and i at rec_fidx[global key].
+    float* rec_lap;
+    int* rec_fidx;
+    int rec_lapcap;
+    // Adjoint field with the gradient (null otherwise): after each stencil
+    // of the adjoint field, k_grad_accum adds mu^m (L u^{m-1}) to the FP32
+    // gradient block of each entry's key, where g_lap / g_fidx are the store
+    // of forward step m - 1.  Gradient blocks (512 FP32 partials in g_gs, 512
+    // FP64 sums in g_acc) are handed out on a key's first term:
+    // g_slot[global key] (-1: none yet), at most g_cap.
+    const float* g_lap;
+    const int* g_fidx;
+    float* g_gs;
+    double* g_acc;
+    int* g_slot;
+    int g_cap;
+    unsigned long long* g_terms_wg;   // per k_grad_accum workgroup: nodes whose term it formed
 };
 
 // The compaction works on chunks of 16 bitmap words (1024 blocks), one
@@ -141,16 +163,28 @@ hipError_t launch_init_tables(const Tables& t, long long nkeys, hipStream_t s);
 // events stamped by the dispatch itself at the kernel's start and end.
 hipError_t launch_block_step(const Tables& t, int grid, int w, int pb, hipStream_t s,
                              hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
-// w waves per workgroup, pb blocks per wave
-int block_step_occupancy(bool adaptive, int w, int pb);   // resident workgroups per CU
+// Variants of the block stencil: a plain step, or a recomputed forward step
+// of the adjoint (also stores L u per entry, Tables::rec_lap).
+// launch_block_step picks the variant from the Tables.
+constexpr int STEP_PLAIN = 0, STEP_RECORD = 1;
+// resident workgroups per CU of a variant (w waves per workgroup, pb blocks per wave)
+int block_step_occupancy(bool adaptive, int w, int pb, int mode = STEP_PLAIN);
 bool block_step_shape_ok(int w, int pb);
 hipError_t launch_plan(const Tables& t, int grid, hipStream_t s);
 hipError_t launch_advance(const Tables& t, hipStream_t s);   // step without an activation update
 hipError_t launch_pool_count(const Tables& t, int grid, hipStream_t s);   // grid >= scan_wgs
 hipError_t launch_emit(const Tables& t, int grid, hipStream_t s);
-hipError_t launch_activate(const Tables& t, long long key, int shot, unsigned local_key,
-                           int pin_until, hipStream_t s);
+// Activate n blocks (distinct global keys; shot and key inside the shot per
+// entry), pin each while step < pins[i] and, where heads[i] >= 0, make it the
+// block's first source; one wave per block.  Blocks that are active already
+// only raise their pin (and take the head).  No free slot: add_error = -3.
+hipError_t launch_activate_list(const Tables& t, const long long* keys, const int* shots,
+                                const unsigned* local_keys, const int* pins, const int* heads, int n,
+                                hipStream_t s);
 hipError_t launch_refresh_rows(const Tables& t, hipStream_t s);
+// after sources from index nsrc on were dropped: slots whose first source was
+// one of them lose it and its pin
+hipError_t launch_drop_sources(const Tables& t, int nsrc, hipStream_t s);
 hipError_t launch_read(const Tables& t, int shot, int which, int x0, int y0, int z0, int sx,
                        int sy, int sz, float* out, hipStream_t s);
 hipError_t launch_media_c2(const Shot& shot, const Shot* dshot, double dt, double dx, float* c2,
@@ -174,15 +208,29 @@ hipError_t launch_read_dense(const float* f, int nx, int ny, int x0, int y0, int
 // adjoint support
 hipError_t launch_receiver_c2(const Shot* shots, const int* xyz, const int* rshot, int nrec,
                               double dt, double dx, float* out, hipStream_t s);
-hipError_t launch_adjoint_grad(const Tables& mu, const Shot& shot, const float* u, float* gs,
-                               hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
-hipError_t launch_grad_flush(double* g, float* gs, long long n, hipStream_t s);
 // adjoint steps whose FP32 partial gradient is summed before it is folded
 // into the FP64 gradient (groups of absolute step numbers, so the result does
 // not depend on the checkpoint interval)
 constexpr int GRAD_GROUP = 32;
-hipError_t launch_grad_finish(const Shot& shot, const Shot* dshot, const double* g, float* out,
+// the gradient term mu^m (L u^{m-1}) of one adjoint step, after the adjoint
+// field's stencil (Tables::g_*): one wave per list entry; grid at most
+// GRAD_ACCUM_MAX_WG workgroups (one node-count slot each)
+constexpr int GRAD_ACCUM_MAX_WG = 4096;
+hipError_t launch_grad_accum(const Tables& mu, int grid, hipStream_t s, hipEvent_t e0 = nullptr,
+                             hipEvent_t e1 = nullptr);
+// g_acc += g_gs, g_gs = 0 over the gradient blocks handed out so far
+hipError_t launch_grad_flush(const Tables& mu, hipStream_t s);
+// out[node] = (2 / c) * gradient sum of shot 0 (0 where c = 0 or no term)
+hipError_t launch_grad_finish(const Tables& mu, const Shot& shot, const Shot* dshot, float* out,
                               hipStream_t s);
+// fill n ints with v
+hipError_t launch_fill_int(int* p, long long n, int v, hipStream_t s);
+// Sparse state copy of a block-engine handle: the active list (n entries)
+// with its slots' three planes and per-slot tables, to / from buf (layout in
+// tcm_kernels.hip, ck_layout); restore expects freshly initialised tables.
+size_t ck_sparse_bytes(long long n);
+hipError_t launch_ck_gather(const Tables& t, long long n, char* buf, hipStream_t s);
+hipError_t launch_ck_scatter(const Tables& t, long long n, const char* buf, hipStream_t s);
 // HBM ceiling probe (n floats per source, n a multiple of hbm_probe_chunk())
 long long hbm_probe_chunk();
 hipError_t launch_hbm_probe(const float* src, float* dst, long long n, int nread, int grid, hipStream_t s,

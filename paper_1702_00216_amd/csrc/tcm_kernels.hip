@@ -146,13 +146,10 @@ __device__ __forceinline__ float coeff_c2(float c, double dt, double dx) {
     return (float)(t * t);
 }
 
-// Zero both phi levels of a new slot and fill its C2 plane from the media
-// (one wave, lane = (x, y) column).  Returns (to every lane) the block's C2 if
-// all 512 nodes are in the domain and share it ("homogenic" cell of Table 1),
-// else NaN.
-__device__ float fill_slot(const Tables& t, const Shot& S, long long slot, int bx, int by, int bz) {
-    float* __restrict__ p0 = plane_of(t, slot, 0);
-    float* __restrict__ p1 = plane_of(t, slot, 1);
+// Fill the C2 plane of a slot from the media (one wave, lane = (x, y)
+// column).  Returns (to every lane) the block's C2 if all 512 nodes are in
+// the domain and share it ("homogenic" cell of Table 1), else NaN.
+__device__ float fill_c2(const Tables& t, const Shot& S, long long slot, int bx, int by, int bz) {
     float* __restrict__ pc = plane_of(t, slot, PLANE_C2);
     const int lane = lane_id();
     const int x = lane & 7, y = lane >> 3;
@@ -160,8 +157,6 @@ __device__ float fill_slot(const Tables& t, const Shot& S, long long slot, int b
     bool same = true;
 #pragma unroll
     for (int z = 0; z < 8; z++) {
-        p0[z * 64 + lane] = 0.f;
-        p1[z * 64 + lane] = 0.f;
         const int gx = bx * BE + x, gy = by * BE + y, gz = bz * BE + z;
         float c2 = 0.f;   // nodes outside the domain keep C2 = 0 and stay zero
         const bool in = gx < S.nx && gy < S.ny && gz < S.nz;
@@ -176,6 +171,19 @@ __device__ float fill_slot(const Tables& t, const Shot& S, long long slot, int b
     return uniform ? ref : __builtin_nanf("");
 }
 
+// Zero both phi levels of a new slot and fill its C2 plane (fill_c2).
+__device__ float fill_slot(const Tables& t, const Shot& S, long long slot, int bx, int by, int bz) {
+    float* __restrict__ p0 = plane_of(t, slot, 0);
+    float* __restrict__ p1 = plane_of(t, slot, 1);
+    const int lane = lane_id();
+#pragma unroll
+    for (int z = 0; z < 8; z++) {
+        p0[z * 64 + lane] = 0.f;
+        p1[z * 64 + lane] = 0.f;
+    }
+    return fill_c2(t, S, slot, bx, by, bz);
+}
+
 // --------------------------------------------------------------------------
 // table initialisation
 // --------------------------------------------------------------------------
@@ -187,6 +195,7 @@ __global__ void k_init_tables(Tables t, long long nkeys) {
     for (long long i = g0; i < t.cap; i += gs) {
         t.slot_key[i] = -1;
         t.pin_until[i] = 0;
+        t.src_head[i] = -1;
         t.flags[i] = 0;
         t.slot_c2u[i] = __builtin_nanf("");
         t.sdlog[i] = 0;
@@ -200,6 +209,7 @@ __global__ void k_init_tables(Tables t, long long nkeys) {
         st->cells_cur_u = 0; st->updates_u = 0; st->decays = 0;
         st->maxbits = 0u; st->trig_cur = t.trigger; st->ret_cur = t.retire; st->n_ne = 0;
         st->free_next = t.cap;
+        st->n_gblocks = 0; st->grad_error = 0;
     }
 }
 
@@ -229,8 +239,11 @@ constexpr int TILE_FLOATS = TILE_COLS * TILE_COLS * BE;
 // sit in consecutive slots, so each plane array is read as one 4 KiB run per
 // wave: on the stencil's access pattern 6.06 TB/s against 5.67 TB/s with one
 // block per wave at the same occupancy).
-template <bool ADAPT, int W, int P>
+// MODE: STEP_PLAIN, or STEP_RECORD (a recomputed forward step of the adjoint:
+// also store L u^n of every entry and its list index per key).
+template <bool ADAPT, int W, int P, int MODE>
 __global__ __launch_bounds__(64 * W) void k_block_step(Tables t) {
+    static_assert(MODE == STEP_PLAIN || MODE == STEP_RECORD, "stencil variants");
     constexpr int B = W * P;
     static_assert(B <= 8, "a pass of the workgroup stays inside one group of 8 entries");
     // two sets of per-block tiles: iteration k writes set k & 1, so one
@@ -271,6 +284,7 @@ __global__ __launch_bounds__(64 * W) void k_block_step(Tables t) {
     // processed, so only the data loads sit on the critical path.
     const scalar_ptr<int> rows = as_scalar((const int*)t.rows);
     const scalar_ptr<int> pin_until = as_scalar((const int*)t.pin_until);
+    const scalar_ptr<int> src_head = as_scalar((const int*)t.src_head);
     const scalar_ptr<float> slot_c2u = as_scalar((const float*)t.slot_c2u);
     const int stride = per * B;
     // The loop count is uniform over the workgroup (barriers below).  Entry
@@ -299,13 +313,14 @@ __global__ __launch_bounds__(64 * W) void k_block_step(Tables t) {
     int buf = 0;
     for (; ib < end; ib += stride, buf ^= 1) {
         bool have[P], share_m[P], share_p[P];
-        int slot[P], nb[P][6], G[P], pinned[P];
+        int slot[P], nb[P][6], G[P], pinned[P], shead[P], li[P];
         float cur[P][8], prv[P][8], k2[P][8], zlo[P], zhi[P];
         float* out_p[P];
 #pragma unroll
         for (int q = 0; q < P; q++) {
             const int j = wid * P + q;
             have[q] = ib + j < end;
+            li[q] = gidx(ib + j);
             slot[q] = r[q][0];
 #pragma unroll
             for (int d = 0; d < 6; d++) nb[q][d] = r[q][1 + d];
@@ -324,10 +339,11 @@ __global__ __launch_bounds__(64 * W) void k_block_step(Tables t) {
         __builtin_amdgcn_s_setprio(1);
 #pragma unroll
         for (int q = 0; q < P; q++) {
-            zlo[q] = 0.f; zhi[q] = 0.f; pinned[q] = 0; out_p[q] = nullptr;
+            zlo[q] = 0.f; zhi[q] = 0.f; pinned[q] = 0; shead[q] = -1; out_p[q] = nullptr;
             fmx[q] = 0.f; fpx[q] = 0.f; fmy[q] = 0.f; fpy[q] = 0.f;
             if (!have[q]) continue;
             pinned[q] = t.nsrc > 0 ? pin_until[slot[q]] : 0;
+            if (pinned[q] > n) shead[q] = src_head[slot[q]];
             const float c2u = slot_c2u[slot[q]];
             const float* __restrict__ cur_p = plane_of(t, slot[q], p);
             out_p[q] = plane_of(t, slot[q], 1 - p);
@@ -393,20 +409,31 @@ __global__ __launch_bounds__(64 * W) void k_block_step(Tables t) {
                 yp[0] = v0.x; yp[1] = v0.y; yp[2] = v0.z; yp[3] = v0.w;
                 yp[4] = v1.x; yp[5] = v1.y; yp[6] = v1.z; yp[7] = v1.w;
             }
-            float nv[8];
+            float nv[8], lapv[8];
 #pragma unroll
             for (int z = 0; z < 8; z++) {
                 const float zd = z > 0 ? cur[q][z - 1] : zlo[q];
                 const float zu = z < 7 ? cur[q][z + 1] : zhi[q];
                 const float s = ((xp[z] + xm[z]) + (yp[z] + ym[z])) + (zu + zd);
-                const float lap = s - 6.0f * cur[q][z];
-                nv[z] = (2.0f * cur[q][z] - prv[q][z]) + k2[q][z] * lap;
+                lapv[z] = s - 6.0f * cur[q][z];
+                nv[z] = (2.0f * cur[q][z] - prv[q][z]) + k2[q][z] * lapv[z];
             }
-            // additive source insertion (before the predicates)
+            if constexpr (MODE == STEP_RECORD) {
+                // L u^n of this entry, for the gradient terms of adjoint step n + 1
+                if (li[q] < t.rec_lapcap) {
+                    float* __restrict__ lp = t.rec_lap + (size_t)li[q] * BV;
+#pragma unroll
+                    for (int z = 0; z < 8; z++) __builtin_nontemporal_store(lapv[z], &lp[z * 64 + lane]);
+                    if (lane == 0) t.rec_fidx[G[q]] = li[q];
+                } else if (lane == 0) {
+                    t.st->grad_error = 1;
+                }
+            }
+            // additive source insertion (before the predicates): the block's
+            // own sources, in the order they were added
             if (pinned[q] > n) {
-                for (int s = 0; s < t.nsrc; s++) {
+                for (int s = shead[q]; s >= 0; s = t.src[s].next) {
                     const Src e = t.src[s];
-                    if (e.key != (long long)G[q]) continue;
                     const int k = n - e.t0;
                     if (k < 0 || k >= e.ns) continue;
                     const float w = t.srcw[e.w_off + k];
@@ -475,41 +502,53 @@ __global__ __launch_bounds__(64 * W) void k_block_step(Tables t) {
         atomicMax((unsigned*)&t.st->maxbits, __float_as_uint(wave_max));   // non-negative floats order as integers
 }
 
-template <bool ADAPT, int W, int P>
-static int occupancy_wp() {
+template <bool ADAPT, int W, int P, int MODE>
+static int occupancy_wpm() {
     int nb = 0;
-    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_block_step<ADAPT, W, P>, 64 * W, 0);
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_block_step<ADAPT, W, P, MODE>,
+                                                                      64 * W, 0);
     return e == hipSuccess ? nb : 0;
 }
 
+template <bool ADAPT, int W, int P>
+static int occupancy_wp(int mode) {
+    return mode == STEP_RECORD ? occupancy_wpm<ADAPT, W, P, STEP_RECORD>() : occupancy_wpm<ADAPT, W, P, STEP_PLAIN>();
+}
+
 template <bool ADAPT>
-static int occupancy_w(int w, int pb) {
+static int occupancy_w(int w, int pb, int mode) {
     if (pb == 1) {
-        if (w == 2) return occupancy_wp<ADAPT, 2, 1>();
-        if (w == 4) return occupancy_wp<ADAPT, 4, 1>();
-        if (w == 8) return occupancy_wp<ADAPT, 8, 1>();
+        if (w == 2) return occupancy_wp<ADAPT, 2, 1>(mode);
+        if (w == 4) return occupancy_wp<ADAPT, 4, 1>(mode);
+        if (w == 8) return occupancy_wp<ADAPT, 8, 1>(mode);
     } else if (pb == 2) {
-        if (w == 2) return occupancy_wp<ADAPT, 2, 2>();
-        if (w == 4) return occupancy_wp<ADAPT, 4, 2>();
+        if (w == 2) return occupancy_wp<ADAPT, 2, 2>(mode);
+        if (w == 4) return occupancy_wp<ADAPT, 4, 2>(mode);
     }
     return 0;
 }
 
-int block_step_occupancy(bool adaptive, int w, int pb) {
-    return adaptive ? occupancy_w<true>(w, pb) : occupancy_w<false>(w, pb);
+int block_step_occupancy(bool adaptive, int w, int pb, int mode) {
+    return adaptive ? occupancy_w<true>(w, pb, mode) : occupancy_w<false>(w, pb, mode);
 }
 
 bool block_step_shape_ok(int w, int pb) {
     return (pb == 1 && (w == 2 || w == 4 || w == 8)) || (pb == 2 && (w == 2 || w == 4));
 }
 
-template <bool ADAPT, int W, int P>
-static void launch_wp(const Tables& t, int grid, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-    void (*kern)(Tables) = k_block_step<ADAPT, W, P>;
+template <bool ADAPT, int W, int P, int MODE>
+static void launch_wpm(const Tables& t, int grid, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    void (*kern)(Tables) = k_block_step<ADAPT, W, P, MODE>;
     if (e0 || e1)                   // timed launch (never inside a graph capture)
         hipExtLaunchKernelGGL(kern, dim3(grid), dim3(64 * W), 0, s, e0, e1, 0, t);
     else
         hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * W), 0, s, t);
+}
+
+template <bool ADAPT, int W, int P>
+static void launch_wp(const Tables& t, int grid, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    if (t.rec_lap) launch_wpm<ADAPT, W, P, STEP_RECORD>(t, grid, s, e0, e1);
+    else launch_wpm<ADAPT, W, P, STEP_PLAIN>(t, grid, s, e0, e1);
 }
 
 template <bool ADAPT>
@@ -890,6 +929,7 @@ __global__ __launch_bounds__(256) void k_pool_count(Tables t) {
                     t.cell2box[G] = slot;
                     t.slot_key[slot] = G;
                     t.pin_until[slot] = 0;
+                    t.src_head[slot] = -1;
                 }
             }
         }
@@ -1175,26 +1215,43 @@ hipError_t launch_emit(const Tables& t, int grid, hipStream_t s) {
 }
 
 // --------------------------------------------------------------------------
-// source activation (one wave): box the block of a new source by hand
+// source activation: box the blocks of new sources by hand, one wave per
+// block (distinct keys), appending them to the active list
 // --------------------------------------------------------------------------
-__global__ __launch_bounds__(64) void k_activate(Tables t, long long G, int shot, unsigned key,
-                                                 int pin) {
+__global__ __launch_bounds__(256) void k_activate_list(Tables t, const long long* keys, const int* shots,
+                                                       const unsigned* lkeys, const int* pins, const int* heads,
+                                                       int n) {
     DevState* st = t.st;
     const int lane = lane_id();
+    const int k = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    if (k >= n) return;                      // uniform over the wave
+    const long long G = keys[k];
+    const int pin = pins[k];
+    const int head = heads[k];
     const int cur = t.cell2box[G];
-    if (cur >= 0) {
-        if (lane == 0 && t.pin_until[cur] < pin) t.pin_until[cur] = pin;
+    if (cur >= 0) {                          // active already: raise its pin
+        if (lane == 0) {
+            if (t.pin_until[cur] < pin) t.pin_until[cur] = pin;
+            if (head >= 0) t.src_head[cur] = head;
+        }
         return;
     }
-    if (st->free_cnt <= 0) {
-        if (lane == 0) st->add_error = -3;
-        return;
+    int ok = 1;
+    if (lane == 0) {
+        if (atomicSub(&st->free_cnt, 1) <= 0) {
+            atomicAdd(&st->free_cnt, 1);
+            st->add_error = -3;
+            ok = 0;
+        }
     }
+    if (!__shfl(ok, 0)) return;
     const int slot = t.cap >= t.nkeys ? (int)G : place_slot(t, G);
-    if (slot < 0) {                      // unreachable: a slot is free
+    if (slot < 0) {                          // unreachable: a slot was reserved above
         if (lane == 0) st->add_error = -6;
         return;
     }
+    const int shot = shots[k];
+    const unsigned key = lkeys[k];
     const Shot& S = t.shots[shot];
     int bx, by, bz;
     key_to_block(S, key, bx, by, bz);
@@ -1202,28 +1259,29 @@ __global__ __launch_bounds__(64) void k_activate(Tables t, long long G, int shot
     if (lane == 0) {
         t.slot_c2u[slot] = c2u;
         t.sdlog[slot] = 0;
-        st->free_cnt -= 1;
         t.cell2box[G] = slot;
         t.slot_key[slot] = G;
         t.pin_until[slot] = pin;
-        const int i = st->n_act;
+        t.src_head[slot] = head;
+        const int i = atomicAdd(&st->n_act, 1);
         t.act_slot[i] = slot;
         t.act_shot[i] = shot;
         t.act_key[i] = key;
-        int nb[6];
-        for (int d = 0; d < 6; d++) {
-            const long long nk = neighbour_key(S, bx, by, bz, d);
-            nb[d] = nk >= 0 ? t.cell2box[nk] : EMPTY;
-        }
-        int4* rp = (int4*)(t.rows + 8 * (size_t)i);
-        rp[0] = make_int4(slot, nb[0], nb[1], nb[2]);
-        rp[1] = make_int4(nb[3], nb[4], nb[5], (int)G);
-        st->n_act = i + 1;
-        if (i + 1 > st->peak_act) st->peak_act = i + 1;
-        st->cells_cur += (unsigned long long)block_cells(S, bx, by, bz);
-        if (c2u == c2u) st->cells_cur_u += (unsigned long long)block_cells(S, bx, by, bz);
-        st->activations += 1ull;
+        atomicMax(&st->peak_act, i + 1);
+        const unsigned long long bc = (unsigned long long)block_cells(S, bx, by, bz);
+        atomicAdd(&st->cells_cur, bc);
+        if (c2u == c2u) atomicAdd(&st->cells_cur_u, bc);
+        atomicAdd(&st->activations, 1ull);
     }
+}
+
+hipError_t launch_activate_list(const Tables& t, const long long* keys, const int* shots,
+                                const unsigned* local_keys, const int* pins, const int* heads, int n,
+                                hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_activate_list, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, t, keys, shots,
+                       local_keys, pins, heads, n);
+    return hipGetLastError();
 }
 
 // Rewrite the neighbour row of every active entry from the block table
@@ -1252,9 +1310,18 @@ hipError_t launch_refresh_rows(const Tables& t, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_activate(const Tables& t, long long key, int shot, unsigned local_key, int pin,
-                           hipStream_t s) {
-    hipLaunchKernelGGL(k_activate, dim3(1), dim3(64), 0, s, t, key, shot, local_key, pin);
+__global__ void k_drop_sources(Tables t, int nsrc) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < t.cap;
+         i += (long long)gridDim.x * blockDim.x) {
+        if (t.src_head[i] >= nsrc) {
+            t.src_head[i] = -1;
+            t.pin_until[i] = 0;
+        }
+    }
+}
+
+hipError_t launch_drop_sources(const Tables& t, int nsrc, hipStream_t s) {
+    hipLaunchKernelGGL(k_drop_sources, dim3(256), dim3(256), 0, s, t, nsrc);
     return hipGetLastError();
 }
 
@@ -1484,83 +1551,106 @@ hipError_t launch_receiver_c2(const Shot* shots, const int* xyz, const int* rsho
     return hipGetLastError();
 }
 
-// gs += mu^m (L u^{m-1}) at every node of a block active in the adjoint field
-// (mu is zero elsewhere); u is the forward level as a dense grid of shot 0, L
-// has zero ghosts.  The Laplacian and the product are formed in FP32, as the
-// forward update forms the same Laplacian of the same FP32 values; the sum
-// runs in FP32 over a group of adjoint steps, then is folded into the FP64
-// gradient (k_grad_flush).  (FP64 here cost a third more time per launch for
-// no gain over the FP32 forward's own error.)  The dense snapshot is walked
-// like the dense stencil: a workgroup owns a 128 x 4 column of nodes over one
-// 8^3 block of planes along z, carrying u of the planes below and above in
-// registers, with the column's block slot looked up first.  u, gs and mu move
-// in full cache lines (the four y rows of a tile plane in one 8^3 block are
-// 128 contiguous bytes of that block's mu plane); at 256^3 the grid is 4096
-// workgroups (measured: 8 planes per workgroup beat 16 and 32).
-constexpr int GRAD_TX = 128, GRAD_TY = 4, GRAD_DZ = 8;
-static_assert(GRAD_DZ == 8, "a gradient workgroup's planes are one block deep");
-
-__global__ __launch_bounds__(GRAD_TX * GRAD_TY) void k_adjoint_grad(Tables mu, const float* __restrict__ u,
-                                                                   float* __restrict__ gs) {
+// Gradient term of one adjoint step, right after the adjoint-field stencil
+// (before its activation update, so the list is the one the stencil ran):
+// for every entry whose forward block was active at step m - 1, add
+// mu^m (L u^{m-1}) to the key's FP32 gradient block (handed out on the key's
+// first term; its FP64 sum is cleared then).  One wave per entry, lane =
+// (x, y) column over the 8 z planes: each of mu, L u and the partial gradient
+// moves as eight 256-byte rows.  The product is FP32, the sum FP32 over the
+// step group.
+__global__ __launch_bounds__(256) void k_grad_accum(Tables mu) {
+    __shared__ unsigned long long wg_nodes;
     const DevState* st = mu.st;
-    const int plane = st->step & 1;
-    const Shot& S = mu.shots[0];
-    const int x = blockIdx.x * GRAD_TX + (int)(threadIdx.x % GRAD_TX);
-    const int y = blockIdx.y * GRAD_TY + (int)(threadIdx.x / GRAD_TX);
-    const int z0 = blockIdx.z * GRAD_DZ;
-    if (x >= S.nx || y >= S.ny) return;
-    const size_t sy = (size_t)S.nx, sz = (size_t)S.nx * S.ny;
-    const int z1 = min(S.nz, z0 + GRAD_DZ);
-    // the column lies in one block of the adjoint field: mu is zero there when
-    // that block is inactive, and nothing is added (no barrier below)
-    const int slot = mu.cell2box[S.key_base + (long long)block_to_key(S, x >> 3, y >> 3, z0 >> 3)];
-    if (slot < 0) return;
-    const float* __restrict__ mub = plane_of(mu, slot, plane) + (y & 7) * 8 + (x & 7);
-    size_t i = (size_t)z0 * sz + (size_t)y * sy + (size_t)x;
-    float zm = z0 > 0 ? u[i - sz] : 0.f;
-    float c = u[i];
-    for (int z = z0; z < z1; z++, i += sz) {
-        const float zp = z + 1 < S.nz ? u[i + sz] : 0.f;
-        const float xm = x > 0 ? u[i - 1] : 0.f, xp = x + 1 < S.nx ? u[i + 1] : 0.f;
-        const float ym = y > 0 ? u[i - sy] : 0.f, yp = y + 1 < S.ny ? u[i + sy] : 0.f;
-        const float lap = (((xp + xm) + (yp + ym)) + (zp + zm)) - 6.0f * c;
-        const float m = mub[(z & 7) * 64];
-        gs[i] = gs[i] + m * lap;
-        zm = c;
-        c = zp;
+    if (st->error) return;                           // uniform: no barrier below is skipped by part of it
+    if (threadIdx.x == 0) wg_nodes = 0;
+    __syncthreads();
+    const int nact = st->n_act;
+    const int p_out = 1 - (st->step & 1);          // the stencil wrote mu^m here
+    const int lane = lane_id();
+    const int nw = (int)((gridDim.x * blockDim.x) >> 6);
+    unsigned long long nodes = 0;
+    for (int i = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6); i < nact; i += nw) {
+        const int4* rp = (const int4*)(mu.rows + 8 * (size_t)i);
+        const int slot = __builtin_amdgcn_readfirstlane(rp[0].x);
+        const int G = __builtin_amdgcn_readfirstlane(rp[1].w);
+        const int fi = __builtin_amdgcn_readfirstlane(mu.g_fidx[G]);
+        if (fi < 0) continue;                      // the forward block was inactive: no term
+        int g = __builtin_amdgcn_readfirstlane(mu.g_slot[G]);
+        const float* __restrict__ mp = plane_of(mu, slot, p_out);
+        const float* __restrict__ lp = mu.g_lap + (size_t)fi * BV;
+        float m[8], l[8], a[8];
+#pragma unroll
+        for (int z = 0; z < 8; z++) {
+            m[z] = __builtin_nontemporal_load(&mp[z * 64 + lane]);
+            l[z] = __builtin_nontemporal_load(&lp[z * 64 + lane]);
+        }
+        if (g >= 0) {
+            const float* __restrict__ gp = mu.g_gs + (size_t)g * BV;
+#pragma unroll
+            for (int z = 0; z < 8; z++) a[z] = __builtin_nontemporal_load(&gp[z * 64 + lane]);
+        } else {
+            if (lane == 0) {
+                g = atomicAdd(&mu.st->n_gblocks, 1);
+                if (g < mu.g_cap) mu.g_slot[G] = g;
+                else mu.st->grad_error = 1;
+            }
+            g = __shfl(g, 0);
+            if (g >= mu.g_cap) continue;
+            double* __restrict__ ap = mu.g_acc + (size_t)g * BV;
+#pragma unroll
+            for (int z = 0; z < 8; z++) {
+                ap[z * 64 + lane] = 0.0;
+                a[z] = 0.f;
+            }
+        }
+        float* __restrict__ gp = mu.g_gs + (size_t)g * BV;
+#pragma unroll
+        for (int z = 0; z < 8; z++) __builtin_nontemporal_store(a[z] + m[z] * l[z], &gp[z * 64 + lane]);
+        const Shot& S0 = mu.shots[0];
+        int bx, by, bz;
+        key_to_block(S0, (unsigned)((long long)G - S0.key_base), bx, by, bz);
+        nodes += (unsigned long long)block_cells(S0, bx, by, bz);
     }
+    // node count: one slot per workgroup (a global atomic from every wave
+    // would serialise thousands of updates of one address at the kernel's end)
+    if (lane == 0 && nodes) atomicAdd(&wg_nodes, nodes);
+    __syncthreads();
+    if (threadIdx.x == 0 && wg_nodes) mu.g_terms_wg[blockIdx.x] += wg_nodes;
 }
 
-hipError_t launch_adjoint_grad(const Tables& mu, const Shot& shot, const float* u, float* gs,
-                               hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-    dim3 grid((shot.nx + GRAD_TX - 1) / GRAD_TX, (shot.ny + GRAD_TY - 1) / GRAD_TY,
-              (shot.nz + GRAD_DZ - 1) / GRAD_DZ);
+hipError_t launch_grad_accum(const Tables& mu, int grid, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    if (grid > GRAD_ACCUM_MAX_WG) return hipErrorInvalidValue;
     if (e0 || e1)
-        hipExtLaunchKernelGGL(k_adjoint_grad, grid, dim3(GRAD_TX * GRAD_TY), 0, s, e0, e1, 0, mu, u, gs);
+        hipExtLaunchKernelGGL(k_grad_accum, dim3(grid), dim3(256), 0, s, e0, e1, 0, mu);
     else
-        hipLaunchKernelGGL(k_adjoint_grad, grid, dim3(GRAD_TX * GRAD_TY), 0, s, mu, u, gs);
+        hipLaunchKernelGGL(k_grad_accum, dim3(grid), dim3(256), 0, s, mu);
     return hipGetLastError();
 }
 
-// g += gs, gs = 0 (end of a group of adjoint steps)
-__global__ void k_grad_flush(double* __restrict__ g, float* __restrict__ gs, long long n) {
-    const long long st = (long long)gridDim.x * blockDim.x;
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += st) {
-        g[i] += (double)gs[i];
-        gs[i] = 0.f;
+// g_acc += g_gs, g_gs = 0 over the gradient blocks handed out so far (end of
+// a group of adjoint steps)
+__global__ void k_grad_flush(Tables mu) {
+    const long long n = (long long)min(mu.st->n_gblocks, mu.g_cap) * BV;   // the counter may run past the cap
+    const long long gs = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gs) {
+        mu.g_acc[i] += (double)mu.g_gs[i];
+        mu.g_gs[i] = 0.f;
     }
 }
 
-hipError_t launch_grad_flush(double* g, float* gs, long long n, hipStream_t s) {
-    long long grid = (n + 255) / 256;
-    if (grid > 65536) grid = 65536;
+hipError_t launch_grad_flush(const Tables& mu, hipStream_t s) {
+    long long grid = ((long long)mu.g_cap * BV + 255) / 256;
+    if (grid > 16384) grid = 16384;
     if (grid < 1) grid = 1;
-    hipLaunchKernelGGL(k_grad_flush, dim3((unsigned)grid), dim3(256), 0, s, g, gs, n);
+    hipLaunchKernelGGL(k_grad_flush, dim3((unsigned)grid), dim3(256), 0, s, mu);
     return hipGetLastError();
 }
 
-// dJ/dc = (2 / c) g, zero where c = 0 (there dC2/dc = 0)
-__global__ void k_grad_finish(const Shot* dshot, const double* g, float* out) {
+// dJ/dc = (2 / c) g at every node of shot 0, g the FP64 sum of the node's
+// gradient block (0 where its key never had a term, and where c = 0: there
+// dC2/dc = 0)
+__global__ void k_grad_finish(Tables mu, const Shot* dshot, float* out) {
     const Shot& S = *dshot;
     const long long total = (long long)S.nx * S.ny * S.nz;
     const long long gs = (long long)gridDim.x * blockDim.x;
@@ -1568,18 +1658,148 @@ __global__ void k_grad_finish(const Shot* dshot, const double* g, float* out) {
         const int gx = (int)(i % S.nx);
         const long long r = i / S.nx;
         const int gy = (int)(r % S.ny), gz = (int)(r / S.ny);
-        const double c = media_speed(S, gx, gy, gz);
-        out[i] = c != 0.0 ? (float)(2.0 / c * g[i]) : 0.f;
+        const int gb = mu.g_slot[S.key_base + (long long)block_to_key(S, gx >> 3, gy >> 3, gz >> 3)];
+        float v = 0.f;
+        if (gb >= 0) {
+            const double c = media_speed(S, gx, gy, gz);
+            const double g = mu.g_acc[(size_t)gb * BV + (size_t)(((gz & 7) * 8 + (gy & 7)) * 8 + (gx & 7))];
+            v = c != 0.0 ? (float)(2.0 / c * g) : 0.f;
+        }
+        out[i] = v;
     }
 }
 
-hipError_t launch_grad_finish(const Shot& shot, const Shot* dshot, const double* g, float* out,
+hipError_t launch_grad_finish(const Tables& mu, const Shot& shot, const Shot* dshot, float* out,
                               hipStream_t s) {
     const long long total = (long long)shot.nx * shot.ny * shot.nz;
     long long grid = (total + 255) / 256;
     if (grid > 65536) grid = 65536;
     if (grid < 1) grid = 1;
-    hipLaunchKernelGGL(k_grad_finish, dim3((unsigned)grid), dim3(256), 0, s, dshot, g, out);
+    hipLaunchKernelGGL(k_grad_finish, dim3((unsigned)grid), dim3(256), 0, s, mu, dshot, out);
+    return hipGetLastError();
+}
+
+__global__ void k_fill_int(int* p, long long n, int v) {
+    const long long gs = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gs) p[i] = v;
+}
+
+hipError_t launch_fill_int(int* p, long long n, int v, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    long long grid = (n + 255) / 256;
+    if (grid > 16384) grid = 16384;
+    hipLaunchKernelGGL(k_fill_int, dim3((unsigned)grid), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// sparse state copy (checkpoints, snapshots): the device counters, then per
+// active entry its list row and slot tables, then its slot's two phi planes;
+// the C2 plane is a function of the block and the media and is filled again
+// at restore, as at the block's allocation
+// --------------------------------------------------------------------------
+struct CkEntry {
+    int slot, shot;
+    unsigned key;
+    int pin;
+    float c2u;
+    unsigned char flags, sdlog, pad0, pad1;
+    long long slot_key;
+    int row[8];
+    int src_head, pad2;
+};
+static_assert(sizeof(CkEntry) == 72, "checkpoint entries are 72 bytes");
+
+struct CkLayout {
+    size_t entries, planes, total;
+};
+
+__host__ __device__ inline CkLayout ck_layout(long long n) {
+    CkLayout L;
+    const size_t head = (sizeof(DevState) + 255) / 256 * 256;
+    L.entries = head;
+    L.planes = head + ((size_t)n * sizeof(CkEntry) + 255) / 256 * 256;
+    L.total = L.planes + (size_t)n * 2 * BV * sizeof(float);
+    return L;
+}
+
+size_t ck_sparse_bytes(long long n) { return ck_layout(n).total; }
+
+// one wave per entry
+__global__ __launch_bounds__(256) void k_ck_gather(Tables t, long long n, char* buf) {
+    const CkLayout L = ck_layout(n);
+    const long long i = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = lane_id();
+    if (i >= n) return;
+    const int slot = t.act_slot[i];
+    float* dst = (float*)(buf + L.planes) + (size_t)i * 2 * BV;
+#pragma unroll
+    for (int k = 0; k < 2; k++) {
+        const float* src = plane_of(t, slot, k);
+#pragma unroll
+        for (int z = 0; z < 8; z++) dst[k * BV + z * 64 + lane] = src[z * 64 + lane];
+    }
+    if (lane == 0) {
+        CkEntry e;
+        e.slot = slot;
+        e.shot = t.act_shot[i];
+        e.key = t.act_key[i];
+        e.pin = t.pin_until[slot];
+        e.c2u = t.slot_c2u[slot];
+        e.flags = t.flags[slot];
+        e.sdlog = t.sdlog[slot];
+        e.pad0 = e.pad1 = 0;
+        e.src_head = t.src_head[slot];
+        e.pad2 = 0;
+        e.slot_key = t.slot_key[slot];
+        for (int k = 0; k < 8; k++) e.row[k] = t.rows[8 * (size_t)i + k];
+        ((CkEntry*)(buf + L.entries))[i] = e;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_ck_scatter(Tables t, long long n, const char* buf) {
+    const CkLayout L = ck_layout(n);
+    const long long i = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = lane_id();
+    if (i >= n) return;
+    const CkEntry e = ((const CkEntry*)(buf + L.entries))[i];
+    const float* src = (const float*)(buf + L.planes) + (size_t)i * 2 * BV;
+#pragma unroll
+    for (int k = 0; k < 2; k++) {
+        float* dst = plane_of(t, e.slot, k);
+#pragma unroll
+        for (int z = 0; z < 8; z++) dst[z * 64 + lane] = src[k * BV + z * 64 + lane];
+    }
+    {
+        const Shot& S = t.shots[e.shot];
+        int bx, by, bz;
+        key_to_block(S, e.key, bx, by, bz);
+        (void)fill_c2(t, S, e.slot, bx, by, bz);
+    }
+    if (lane == 0) {
+        t.act_slot[i] = e.slot;
+        t.act_shot[i] = e.shot;
+        t.act_key[i] = e.key;
+        for (int k = 0; k < 8; k++) t.rows[8 * (size_t)i + k] = e.row[k];
+        t.pin_until[e.slot] = e.pin;
+        t.src_head[e.slot] = e.src_head;
+        t.slot_c2u[e.slot] = e.c2u;
+        t.flags[e.slot] = e.flags;
+        t.sdlog[e.slot] = e.sdlog;
+        t.slot_key[e.slot] = e.slot_key;
+        t.cell2box[e.slot_key] = e.slot;
+    }
+}
+
+hipError_t launch_ck_gather(const Tables& t, long long n, char* buf, hipStream_t s) {
+    if (n > 0)
+        hipLaunchKernelGGL(k_ck_gather, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, t, n, buf);
+    return hipGetLastError();
+}
+
+hipError_t launch_ck_scatter(const Tables& t, long long n, const char* buf, hipStream_t s) {
+    if (n > 0)
+        hipLaunchKernelGGL(k_ck_scatter, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, t, n, buf);
     return hipGetLastError();
 }
 

@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "tcm.h"
@@ -64,6 +65,7 @@ struct tcm_handle {
 
     // sources / receivers (host mirrors)
     std::vector<Src> h_src;
+    std::unordered_map<long long, std::pair<int, int>> src_chain;   // block key -> first, last source
     std::vector<float> h_srcw;
     Src* d_src = nullptr;
     size_t d_src_cap = 0;
@@ -83,8 +85,10 @@ struct tcm_handle {
     // timing (TCM_FLAG_TIMING)
     std::vector<hipEvent_t> events;
     double stencil_ms = 0.0;
-    double grad_ms = 0.0;               // gradient kernel of tcm_adjoint (timing flag)
+    double grad_ms = 0.0;               // gradient-term kernel of tcm_adjoint (timing flag)
     long long grad_launches = 0, grad_cells = 0;
+    double af_ms = 0.0;                 // adjoint-field stencil of tcm_adjoint (timing flag)
+    long long af_launches = 0, af_cells = 0, af_cells_u = 0;
     std::vector<hipEvent_t> gev;        // events around the timed gradient launches
     long long stencil_launches = 0, stencil_cells = 0, stencil_cells_u = 0;
 
@@ -102,15 +106,25 @@ struct tcm_handle {
     // receivers as given (positions of the adjoint sources)
     std::vector<int> rec_xyz, rec_shot;
 
-    // forward checkpoints for tcm_adjoint: full copies of the block-engine
-    // state at levels 0, K, 2K, ... (K = checkpoint_every)
+    // forward checkpoints for tcm_adjoint at levels 0, K, 2K, ... (K =
+    // checkpoint_every): sparse copies of the block-engine state (the active
+    // list, its two phi planes and per-slot tables; see ck_save)
     struct Ckpt {
         long long step = -1;
+        long long n = 0;                // active entries stored
         char* buf = nullptr;
+        size_t cap = 0, bytes = 0;      // allocated, used
     };
     std::vector<Ckpt> ckpts;
     bool in_adjoint = false;
     tcm_handle* adj = nullptr;          // tables of the adjoint field (shares the media)
+    size_t adjoint_bytes = 0;           // device memory the last tcm_adjoint held
+    // timed recomputed forward steps of tcm_adjoint (TCM_FLAG_TIMING)
+    double rec_ms = 0.0;
+    long long rec_launches = 0, rec_cells = 0, rec_cells_u = 0;
+    // source activation requests (keys, shots, keys in the shot, pins, heads)
+    void* d_act_req = nullptr;
+    size_t d_act_req_cap = 0;
 };
 
 namespace {
@@ -255,6 +269,8 @@ void destroy_all(tcm_handle* h) {
     for (auto& c : h->ckpts)
         if (c.buf) (void)hipFree(c.buf);
     h->ckpts.clear();
+    if (h->d_act_req) (void)hipFree(h->d_act_req);
+    h->d_act_req = nullptr;
     drop_graph(h);
     for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
     h->events.clear();
@@ -314,7 +330,7 @@ tcm_status setup_engine(tcm_handle* h, long long word_base) {
     size_t free_b = 0, total_b = 0;
     (void)hipMemGetInfo(&free_b, &total_b);
     // per-slot bookkeeping bytes besides the 6 KiB slot
-    const size_t per_slot_tab = 4 + 4 + 4 + 32 + 1 + 4 + 4 + 1 + 4 + 8 + 8 + 4 + 4 + 8;
+    const size_t per_slot_tab = 4 + 4 + 4 + 32 + 1 + 4 + 4 + 4 + 1 + 4 + 8 + 8 + 4 + 4 + 8;
     const size_t fixed = (size_t)h->nkeys * 4 + (size_t)word_base * 8 + (size_t)t.nchunks * 4 + (1 << 20);
     long long cap;
     if (cfg->pool_bytes > 0) {
@@ -358,6 +374,7 @@ tcm_status setup_engine(tcm_handle* h, long long word_base) {
     ok = ok && dalloc(h, &t.rows, (size_t)cap * 8) == hipSuccess;
     ok = ok && dalloc(h, &t.flags, (size_t)cap) == hipSuccess;
     ok = ok && dalloc(h, &t.pin_until, (size_t)cap) == hipSuccess;
+    ok = ok && dalloc(h, &t.src_head, (size_t)cap) == hipSuccess;
     ok = ok && dalloc(h, &t.slot_c2u, (size_t)cap) == hipSuccess;
     ok = ok && dalloc(h, &t.sdlog, (size_t)cap) == hipSuccess;
     ok = ok && dalloc(h, &t.dec_slot, (size_t)cap) == hipSuccess;
@@ -509,11 +526,17 @@ tcm_status create_common(const tcm_config* cfg, const tcm_shot* shots, int nshot
 // Step h->hstep: the stencil, then the activation update when the step ends
 // an update interval ("Updating active cells", eq.(5)), else only the
 // receivers and the step counter.
-hipError_t enqueue_step(tcm_handle* h, hipEvent_t e0, hipEvent_t e1) {
+hipError_t enqueue_step(tcm_handle* h, hipEvent_t e0, hipEvent_t e1, hipEvent_t g0 = nullptr,
+                        hipEvent_t g1 = nullptr) {
     hipError_t e;
     const long long n = h->hstep++;
     const int k = h->t.interval > 1 ? h->t.interval : 1;
     if ((e = launch_block_step(h->t, h->grid_step, h->tile_w, h->tile_p, h->stream, e0, e1)) != hipSuccess) return e;
+    // the adjoint field: the gradient term of this step, over the list the
+    // stencil ran (before the activation update replaces it)
+    if (h->t.g_lap &&
+        (e = launch_grad_accum(h->t, std::min(GRAD_ACCUM_MAX_WG, h->ncu * 8), h->stream, g0, g1)) != hipSuccess)
+        return e;
     if ((n + 1) % k != 0) return launch_advance(h->t, h->stream);
     if ((e = launch_plan(h->t, h->grid_plan, h->stream)) != hipSuccess) return e;
     if ((e = launch_pool_count(h->t, h->grid_pool, h->stream)) != hipSuccess) return e;
@@ -576,58 +599,61 @@ tcm_status scratch(tcm_handle* h, size_t bytes, float** p) {
 
 
 // ---- checkpoints ------------------------------------------------------------
-struct CkPart {
-    void* dev;
-    size_t bytes;
-};
+// The state of the block engine between two steps is the device counters,
+// the active list with its rows, and the slots of the active blocks (two phi
+// planes and the per-slot tables); the block table holds exactly those
+// blocks, the bitmap is clear and free slots carry no state.  A checkpoint
+// stores that much (about 4 KiB per active block), so its size follows the
+// active set; restoring re-initialises the tables, scatters the blocks back
+// into the same slots and refills their C2 planes from the media.
+using Ckpt = tcm_handle::Ckpt;
 
-std::vector<CkPart> ck_parts(tcm_handle* h) {
-    const Tables& t = h->t;
-    const size_t cap = (size_t)t.cap;
-    return {{t.pool, cap * SLOT_BYTES},          {t.cell2box, (size_t)h->nkeys * 4},
-            {t.act_slot, cap * 4},               {t.act_shot, cap * 4},
-            {t.act_key, cap * 4},                {t.rows, cap * 32},
-            {t.flags, cap},                      {t.pin_until, cap * 4},
-            {t.slot_c2u, cap * 4},               {t.sdlog, cap},
-            {t.slot_key, cap * 8},               {t.st, sizeof(DevState)}};
-}
-
-size_t ck_bytes(tcm_handle* h) {
-    size_t b = 0;
-    for (const CkPart& p : ck_parts(h)) b += (p.bytes + 255) / 256 * 256;
-    return b;
-}
-
-tcm_status ck_save(tcm_handle* h, char** buf) {
-    if (!*buf) {
+tcm_status ck_save(tcm_handle* h, Ckpt& c) {
+    tcm_status st = sync_state(h);
+    if (st) return st;
+    const long long n = h->h_state->n_act;
+    const size_t bytes = ck_sparse_bytes(n);
+    if (c.cap < bytes) {
+        if (c.buf) (void)hipFree(c.buf);
+        c.buf = nullptr;
+        c.cap = 0;
         void* q = nullptr;
-        if (hipMalloc(&q, ck_bytes(h)) != hipSuccess) {
+        if (hipMalloc(&q, bytes) != hipSuccess) {
             (void)hipGetLastError();
-            return set_err(h, TCM_E_NOMEM, "no device memory for a forward checkpoint");
+            return set_err(h, TCM_E_NOMEM, "no device memory for a state copy");
         }
-        *buf = (char*)q;
+        c.buf = (char*)q;
+        c.cap = bytes;
     }
-    size_t off = 0;
-    for (const CkPart& p : ck_parts(h)) {
-        HIP_OR_FAIL(h, hipMemcpyAsync(*buf + off, p.dev, p.bytes, hipMemcpyDeviceToDevice, h->stream));
-        off += (p.bytes + 255) / 256 * 256;
-    }
+    HIP_OR_FAIL(h, hipMemcpyAsync(c.buf, h->t.st, sizeof(DevState), hipMemcpyDeviceToDevice, h->stream));
+    HIP_OR_FAIL(h, launch_ck_gather(h->t, n, c.buf, h->stream));
+    c.n = n;
+    c.bytes = bytes;
+    c.step = h->h_state->step;
     return TCM_OK;
 }
 
-tcm_status ck_restore(tcm_handle* h, const char* buf) {
-    size_t off = 0;
-    for (const CkPart& p : ck_parts(h)) {
-        HIP_OR_FAIL(h, hipMemcpyAsync(p.dev, buf + off, p.bytes, hipMemcpyDeviceToDevice, h->stream));
-        off += (p.bytes + 255) / 256 * 256;
-    }
+tcm_status ck_restore(tcm_handle* h, const Ckpt& c) {
+    HIP_OR_FAIL(h, launch_init_tables(h->t, h->nkeys, h->stream));
+    HIP_OR_FAIL(h, launch_ck_scatter(h->t, c.n, c.buf, h->stream));
+    HIP_OR_FAIL(h, hipMemcpyAsync(h->t.st, c.buf, sizeof(DevState), hipMemcpyDeviceToDevice, h->stream));
     return TCM_OK;
+}
+
+void ck_free(Ckpt& c) {
+    if (c.buf) (void)hipFree(c.buf);
+    c = Ckpt{};
 }
 
 void ck_clear(tcm_handle* h) {
-    for (auto& c : h->ckpts)
-        if (c.buf) (void)hipFree(c.buf);
+    for (auto& c : h->ckpts) ck_free(c);
     h->ckpts.clear();
+}
+
+size_t ck_stored_bytes(const tcm_handle* h) {
+    size_t b = 0;
+    for (const auto& c : h->ckpts) b += c.bytes;
+    return b;
 }
 
 // Issue n steps (graph replays where possible); no synchronisation.
@@ -688,13 +714,212 @@ tcm_status issue_steps_timed(tcm_handle* h, int n) {
     return TCM_OK;
 }
 
+// Source chains from the table (after sources were dropped).
+void rebuild_chains(tcm_handle* h) {
+    h->src_chain.clear();
+    for (size_t i = 0; i < h->h_src.size(); i++) {
+        Src& e = h->h_src[i];
+        e.next = -1;
+        if (h->engine != TCM_ENGINE_BLOCKS) continue;
+        auto it = h->src_chain.find(e.key);
+        if (it == h->src_chain.end()) {
+            h->src_chain[e.key] = {(int)i, (int)i};
+        } else {
+            h->h_src[(size_t)it->second.second].next = (int)i;
+            it->second.second = (int)i;
+        }
+    }
+}
+
+// Add n point sources at once ("Source insertion"): source k is at
+// xyz[3k..3k+2] of shot shots[k] with samples w[k * ns .. k * ns + ns).  The
+// source table is uploaded once, and the blocks to box (each source block,
+// and with an update interval above one the 26 blocks around it, since the
+// source reaches them before the next update) are activated by one launch,
+// each distinct block once with the largest pin among its sources.
+tcm_status add_sources(tcm_handle* h, int n, const int* shots, const int* xyz, const float* w, int ns) {
+    if (n < 0 || ns < 0 || (n > 0 && (!shots || !xyz)) || (n > 0 && ns > 0 && !w))
+        return set_err(h, TCM_E_ARG, "bad source samples");
+    for (int k = 0; k < n; k++) {
+        if (shots[k] < 0 || shots[k] >= (int)h->shots.size()) return set_err(h, TCM_E_RANGE, "shot index out of range");
+        const Shot& S = h->shots[shots[k]];
+        const int ix = xyz[3 * k], iy = xyz[3 * k + 1], iz = xyz[3 * k + 2];
+        if (ix < 0 || iy < 0 || iz < 0 || ix >= S.nx || iy >= S.ny || iz >= S.nz)
+            return set_err(h, TCM_E_RANGE, fmt("source (%d,%d,%d) outside the %dx%dx%d grid", ix, iy, iz, S.nx, S.ny, S.nz));
+    }
+    for (size_t k = 0; k < (size_t)n * ns; k++)
+        if (!std::isfinite(w[k])) return set_err(h, TCM_E_ARG, "source sample not finite");
+    if (n == 0) return TCM_OK;
+    tcm_status st;
+    if (h->engine == TCM_ENGINE_BLOCKS) {
+        st = sync_state(h);
+        if (st) return st;
+    }
+    const long long step = current_step(h);
+    if (step > 0 && !h->ckpts.empty()) ck_clear(h);   // earlier checkpoints no longer replay this run
+    const size_t keep_src = h->h_src.size(), keep_w = h->h_srcw.size();
+    // blocks to box: global key -> (shot, key inside the shot, pin)
+    std::vector<long long> keys;
+    std::vector<int> kshot, kpin, khead;
+    std::vector<unsigned> kloc;
+    auto want = [&](int shot, int bx, int by, int bz, int pin, int head) {
+        const Shot& S = h->shots[shot];
+        const unsigned tile = ((unsigned)(bz >> 2) * S.ty + (unsigned)(by >> 2)) * S.tx + (unsigned)(bx >> 2);
+        const unsigned lk = tile * 64u + ((unsigned)(bz & 3) << 4) + ((unsigned)(by & 3) << 2) + (unsigned)(bx & 3);
+        const long long G = S.key_base + lk;
+        for (size_t q = 0; q < keys.size(); q++)
+            if (keys[q] == G) {
+                kpin[q] = std::max(kpin[q], pin);
+                if (khead[q] < 0) khead[q] = head;
+                return;
+            }
+        keys.push_back(G);
+        kshot.push_back(shot);
+        kloc.push_back(lk);
+        kpin.push_back(pin);
+        khead.push_back(head);
+    };
+    // sources of one block form a chain in insertion order (Src::next) that
+    // the block's slot points to: the stencil visits only its own sources
+    auto chain = [&](long long G, int idx) -> int {      // returns the block's first source
+        auto it = h->src_chain.find(G);
+        if (it == h->src_chain.end()) {
+            h->src_chain[G] = {idx, idx};
+            return idx;
+        }
+        h->h_src[(size_t)it->second.second].next = idx;
+        it->second.second = idx;
+        return it->second.first;
+    };
+    for (int k = 0; k < n; k++) {
+        const Shot& S = h->shots[shots[k]];
+        const int ix = xyz[3 * k], iy = xyz[3 * k + 1], iz = xyz[3 * k + 2];
+        Src e{};
+        if (h->engine == TCM_ENGINE_DENSE) {
+            e.key = (long long)ix + (long long)S.nx * ((long long)iy + (long long)S.ny * iz);
+            e.local = 0;
+        } else {
+            const int bx = ix >> 3, by = iy >> 3, bz = iz >> 3;
+            const unsigned tile = ((unsigned)(bz >> 2) * S.ty + (unsigned)(by >> 2)) * S.tx + (unsigned)(bx >> 2);
+            e.key = S.key_base + tile * 64u + ((unsigned)(bz & 3) << 4) + ((unsigned)(by & 3) << 2) + (unsigned)(bx & 3);
+            e.local = ((iz & 7) * 8 + (iy & 7)) * 8 + (ix & 7);
+        }
+        e.t0 = (int)step;
+        e.ns = ns;
+        e.next = -1;
+        e.w_off = (long long)h->h_srcw.size();
+        h->h_srcw.insert(h->h_srcw.end(), w + (size_t)k * ns, w + (size_t)(k + 1) * ns);
+        h->h_src.push_back(e);
+        if (h->engine == TCM_ENGINE_BLOCKS) {
+            const int bx = ix >> 3, by = iy >> 3, bz = iz >> 3;
+            const int head = chain(e.key, (int)h->h_src.size() - 1);
+            want(shots[k], bx, by, bz, (int)(step + ns), head);
+            if (h->t.interval > 1) {
+                for (int d = 0; d < 27; d++) {
+                    const int x2 = bx + d % 3 - 1, y2 = by + (d / 3) % 3 - 1, z2 = bz + d / 9 - 1;
+                    if (d == 13 || x2 < 0 || y2 < 0 || z2 < 0 || x2 >= S.bx || y2 >= S.by || z2 >= S.bz) continue;
+                    want(shots[k], x2, y2, z2, 0, -1);
+                }
+            }
+        }
+    }
+    auto undo = [&]() {
+        h->h_src.resize(keep_src);
+        h->h_srcw.resize(keep_w);
+        h->t.nsrc = (int)h->h_src.size();
+        rebuild_chains(h);
+    };
+    // upload the source tables
+    if (h->h_src.size() > h->d_src_cap) {
+        size_t c = std::max<size_t>(16, h->d_src_cap * 2);
+        while (c < h->h_src.size()) c *= 2;
+        Src* d = nullptr;
+        if (dalloc(h, &d, c) != hipSuccess) { undo(); return dev_fail(h, hipErrorOutOfMemory, "source table"); }
+        dfree(h, h->d_src);
+        h->d_src = d;
+        h->d_src_cap = c;
+    }
+    if (h->h_srcw.size() > h->d_srcw_cap) {
+        size_t c = std::max<size_t>(1024, h->d_srcw_cap * 2);
+        while (c < h->h_srcw.size()) c *= 2;
+        float* d = nullptr;
+        if (dalloc(h, &d, c) != hipSuccess) { undo(); return dev_fail(h, hipErrorOutOfMemory, "source samples"); }
+        dfree(h, h->d_srcw);
+        h->d_srcw = d;
+        h->d_srcw_cap = c;
+    }
+    HIP_OR_FAIL(h, hipMemcpyAsync(h->d_src, h->h_src.data(), h->h_src.size() * sizeof(Src), hipMemcpyHostToDevice, h->stream));
+    if (!h->h_srcw.empty())
+        HIP_OR_FAIL(h, hipMemcpyAsync(h->d_srcw, h->h_srcw.data(), h->h_srcw.size() * sizeof(float), hipMemcpyHostToDevice, h->stream));
+    h->t.src = h->d_src;
+    h->t.srcw = h->d_srcw;
+    h->t.nsrc = (int)h->h_src.size();
+    drop_graph(h);
+    if (h->engine != TCM_ENGINE_BLOCKS) {
+        HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+        return TCM_OK;
+    }
+    // one activation launch for all blocks, then the rows of the whole list
+    const size_t nk = keys.size();
+    const size_t need = nk * (sizeof(long long) + 4 * sizeof(int));
+    if (need > h->d_act_req_cap) {
+        if (h->d_act_req) (void)hipFree(h->d_act_req);
+        h->d_act_req = nullptr;
+        h->d_act_req_cap = 0;
+        if (hipMalloc(&h->d_act_req, need) != hipSuccess) {
+            (void)hipGetLastError();
+            undo();
+            return set_err(h, TCM_E_NOMEM, "no device memory for the source activation list");
+        }
+        h->d_act_req_cap = need;
+    }
+    std::vector<char> req(need);
+    memcpy(req.data(), keys.data(), nk * sizeof(long long));
+    memcpy(req.data() + nk * 8, kshot.data(), nk * 4);
+    memcpy(req.data() + nk * 12, kloc.data(), nk * 4);
+    memcpy(req.data() + nk * 16, kpin.data(), nk * 4);
+    memcpy(req.data() + nk * 20, khead.data(), nk * 4);
+    char* d = (char*)h->d_act_req;
+    HIP_OR_FAIL(h, hipMemcpyAsync(d, req.data(), need, hipMemcpyHostToDevice, h->stream));
+    HIP_OR_FAIL(h, launch_activate_list(h->t, (const long long*)d, (const int*)(d + nk * 8),
+                                        (const unsigned*)(d + nk * 12), (const int*)(d + nk * 16),
+                                        (const int*)(d + nk * 20), (int)nk, h->stream));
+    HIP_OR_FAIL(h, launch_refresh_rows(h->t, h->stream));
+    st = sync_state(h);       // also keeps the request list alive until the launch has run
+    if (st) return st;
+    if (h->h_state->add_error) {
+        // no slot for some block: the sources are not added (blocks boxed so
+        // far stay, as zero blocks, and are released when they stay quiet);
+        // the table is cut back and no slot keeps a dropped source
+        HIP_OR_FAIL(h, hipMemsetAsync(&h->t.st->add_error, 0, sizeof(int), h->stream));
+        undo();
+        if (!h->h_src.empty())
+            HIP_OR_FAIL(h, hipMemcpyAsync(h->d_src, h->h_src.data(), h->h_src.size() * sizeof(Src),
+                                          hipMemcpyHostToDevice, h->stream));
+        HIP_OR_FAIL(h, launch_drop_sources(h->t, (int)h->h_src.size(), h->stream));
+        HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+        return set_err(h, TCM_E_POOL, "no free pool slot for a source block");
+    }
+    return TCM_OK;
+}
+
 // Tables for the adjoint field: same shots and media (shared), own pool.
+// The adjoint field runs at threshold 0, whatever the forward's levels: its
+// scale (C2_r times the residual) has nothing to do with theirs, and at
+// threshold 0 the TCM of the adjoint field is exact, with the activation
+// update every 8 steps (the 26-neighbour lookahead: exact at threshold 0,
+// and a management pass on one step in eight).
 tcm_status make_adjoint_handle(tcm_handle* h) {
     tcm_handle* a = new tcm_handle();
     a->cfg = h->cfg;
     a->cfg.checkpoint_every = 0;
-    a->cfg.flags = TCM_FLAG_NO_GRAPH;
-    a->cfg.device_pool = nullptr;
+    a->cfg.flags = TCM_FLAG_NO_GRAPH | (h->cfg.flags & TCM_FLAG_NO_UNIFORM_C2);
+    a->cfg.device_pool = nullptr;           // a capped forward pool caps the adjoint field's alike
+
+    a->cfg.trigger = a->cfg.retire = 0.f;
+    a->cfg.trigger_rel = a->cfg.retire_rel = 0.f;
+    a->cfg.shutdown_steps = 0;
+    a->cfg.trigger_interval = BE;
     a->cfg.stream = h->stream;
     a->engine = TCM_ENGINE_BLOCKS;
     a->device = h->device;
@@ -788,93 +1013,8 @@ tcm_status tcm_add_source_shot(tcm_handle* h, int32_t shot, int32_t ix, int32_t 
                                const float* w, int32_t nsamples) {
     tcm_status st = check_live(h);
     if (st) return st;
-    if (shot < 0 || shot >= (int)h->shots.size()) return set_err(h, TCM_E_RANGE, "shot index out of range");
-    const Shot& S = h->shots[shot];
-    if (ix < 0 || iy < 0 || iz < 0 || ix >= S.nx || iy >= S.ny || iz >= S.nz)
-        return set_err(h, TCM_E_RANGE, fmt("source (%d,%d,%d) outside the %dx%dx%d grid", ix, iy, iz, S.nx, S.ny, S.nz));
-    if (nsamples < 0 || (nsamples > 0 && !w)) return set_err(h, TCM_E_ARG, "bad source samples");
-    for (int k = 0; k < nsamples; k++)
-        if (!std::isfinite(w[k])) return set_err(h, TCM_E_ARG, "source sample not finite");
-    if (h->engine == TCM_ENGINE_BLOCKS) {
-        st = sync_state(h);
-        if (st) return st;
-    }
-    const long long n = current_step(h);
-    if (n > 0 && !h->ckpts.empty()) ck_clear(h);   // earlier checkpoints no longer replay this run
-    Src e{};
-    unsigned local_key = 0;
-    if (h->engine == TCM_ENGINE_DENSE) {
-        e.key = (long long)ix + (long long)S.nx * ((long long)iy + (long long)S.ny * iz);
-        e.local = 0;
-    } else {
-        const int bx = ix >> 3, by = iy >> 3, bz = iz >> 3;
-        const unsigned tile = ((unsigned)(bz >> 2) * S.ty + (unsigned)(by >> 2)) * S.tx + (unsigned)(bx >> 2);
-        local_key = tile * 64u + ((unsigned)(bz & 3) << 4) + ((unsigned)(by & 3) << 2) + (unsigned)(bx & 3);
-        e.key = S.key_base + local_key;
-        e.local = ((iz & 7) * 8 + (iy & 7)) * 8 + (ix & 7);
-    }
-    e.t0 = (int)n;
-    e.ns = nsamples;
-    e.w_off = (long long)h->h_srcw.size();
-    std::vector<float> keepw = h->h_srcw;
-    h->h_srcw.insert(h->h_srcw.end(), w, w + nsamples);
-    h->h_src.push_back(e);
-    // upload source tables
-    if (h->h_src.size() > h->d_src_cap) {
-        size_t c = std::max<size_t>(16, h->d_src_cap * 2);
-        while (c < h->h_src.size()) c *= 2;
-        Src* d = nullptr;
-        HIP_OR_FAIL(h, dalloc(h, &d, c));
-        dfree(h, h->d_src);
-        h->d_src = d;
-        h->d_src_cap = c;
-    }
-    if (h->h_srcw.size() > h->d_srcw_cap) {
-        size_t c = std::max<size_t>(1024, h->d_srcw_cap * 2);
-        while (c < h->h_srcw.size()) c *= 2;
-        float* d = nullptr;
-        HIP_OR_FAIL(h, dalloc(h, &d, c));
-        dfree(h, h->d_srcw);
-        h->d_srcw = d;
-        h->d_srcw_cap = c;
-    }
-    HIP_OR_FAIL(h, hipMemcpyAsync(h->d_src, h->h_src.data(), h->h_src.size() * sizeof(Src), hipMemcpyHostToDevice, h->stream));
-    if (!h->h_srcw.empty())
-        HIP_OR_FAIL(h, hipMemcpyAsync(h->d_srcw, h->h_srcw.data(), h->h_srcw.size() * sizeof(float), hipMemcpyHostToDevice, h->stream));
-    h->t.src = h->d_src;
-    h->t.srcw = h->d_srcw;
-    h->t.nsrc = (int)h->h_src.size();
-    drop_graph(h);
-    if (h->engine == TCM_ENGINE_BLOCKS) {
-        HIP_OR_FAIL(h, launch_activate(h->t, e.key, shot, local_key, (int)(n + nsamples), h->stream));
-        if (h->t.interval > 1) {
-            // the source reaches the 26 blocks around it before the next update
-            const int bx = ix >> 3, by = iy >> 3, bz = iz >> 3;
-            for (int d = 0; d < 27; d++) {
-                const int x2 = bx + d % 3 - 1, y2 = by + (d / 3) % 3 - 1, z2 = bz + d / 9 - 1;
-                if (d == 13 || x2 < 0 || y2 < 0 || z2 < 0 || x2 >= S.bx || y2 >= S.by || z2 >= S.bz) continue;
-                const unsigned tile2 = ((unsigned)(z2 >> 2) * S.ty + (unsigned)(y2 >> 2)) * S.tx + (unsigned)(x2 >> 2);
-                const unsigned lk = tile2 * 64u + ((unsigned)(z2 & 3) << 4) + ((unsigned)(y2 & 3) << 2) + (unsigned)(x2 & 3);
-                HIP_OR_FAIL(h, launch_activate(h->t, S.key_base + lk, shot, lk, 0, h->stream));
-            }
-        }
-        // rows written before later activations name those blocks EMPTY
-        HIP_OR_FAIL(h, launch_refresh_rows(h->t, h->stream));
-        st = sync_state(h);
-        if (st) return st;
-        if (h->h_state->add_error) {
-            // undo: no slot for the source block
-            HIP_OR_FAIL(h, hipMemsetAsync(&h->t.st->add_error, 0, sizeof(int), h->stream));
-            h->h_src.pop_back();
-            h->h_srcw = keepw;
-            h->t.nsrc = (int)h->h_src.size();
-            HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
-            return set_err(h, TCM_E_POOL, "no free pool slot for the source block");
-        }
-    } else {
-        HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
-    }
-    return TCM_OK;
+    const int xyz[3] = {ix, iy, iz};
+    return add_sources(h, 1, &shot, xyz, w, nsamples);
 }
 
 tcm_status tcm_add_source(tcm_handle* h, int32_t ix, int32_t iy, int32_t iz, const float* w, int32_t nsamples) {
@@ -991,9 +1131,8 @@ tcm_status tcm_step(tcm_handle* h, int32_t nsteps) {
                 const size_t idx = (size_t)(cur / K);
                 if (h->ckpts.size() <= idx) h->ckpts.resize(idx + 1);
                 if (h->ckpts[idx].step != cur) {
-                    st = ck_save(h, &h->ckpts[idx].buf);
+                    st = ck_save(h, h->ckpts[idx]);
                     if (st) return st;
-                    h->ckpts[idx].step = cur;
                 }
             }
             const int chunk = (int)std::min<long long>(left, K - cur % K);
@@ -1127,6 +1266,17 @@ tcm_status tcm_stats(tcm_handle* h, tcm_stats_t* o) {
     o->grad_ms = h->grad_ms;
     o->grad_launches = h->grad_launches;
     o->grad_cells = h->grad_cells;
+    o->adjoint_field_ms = h->af_ms;
+    o->adjoint_field_launches = h->af_launches;
+    o->adjoint_field_cells = h->af_cells;
+    o->adjoint_field_cells_uniform = h->af_cells_u;
+    o->recompute_ms = h->rec_ms;
+    o->recompute_launches = h->rec_launches;
+    o->recompute_cells = h->rec_cells;
+    o->recompute_cells_uniform = h->rec_cells_u;
+    o->checkpoint_bytes = (int64_t)ck_stored_bytes(h);
+    o->checkpoints = (int64_t)h->ckpts.size();
+    o->adjoint_bytes = (int64_t)h->adjoint_bytes;
     o->table_bytes = (int64_t)h->table_bytes;
     if (h->engine == TCM_ENGINE_DENSE) {
         HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
@@ -1161,7 +1311,8 @@ tcm_status tcm_stats(tcm_handle* h, tcm_stats_t* o) {
 // A caller-owned copy of a handle's state (tcm_snapshot / tcm_restore).
 struct SnapImpl {
     tcm_handle* owner = nullptr;
-    char* buf = nullptr;
+    char* buf = nullptr;                // dense engine: both field arrays
+    Ckpt ck;                            // block engine: sparse state copy
     long long hstep = 0, dense_step = 0;
     size_t nsrc = 0;
     int nrec = 0;
@@ -1176,6 +1327,7 @@ tcm_status tcm_reset(tcm_handle* h) {
     h->rec_xyz.clear();
     h->rec_shot.clear();
     h->h_src.clear();
+    h->src_chain.clear();
     h->h_srcw.clear();
     h->t.nsrc = 0;
     h->h_rec.clear();
@@ -1195,6 +1347,14 @@ tcm_status tcm_reset(tcm_handle* h) {
     h->grad_ms = 0.0;
     h->grad_launches = 0;
     h->grad_cells = 0;
+    h->af_ms = 0.0;
+    h->af_launches = 0;
+    h->af_cells = 0;
+    h->af_cells_u = 0;
+    h->rec_ms = 0.0;
+    h->rec_launches = 0;
+    h->rec_cells = 0;
+    h->rec_cells_u = 0;
     if (h->engine == TCM_ENGINE_DENSE) {
         const Shot& S = h->shots[0];
         const size_t N = (size_t)S.nx * S.ny * S.nz;
@@ -1213,6 +1373,7 @@ void tcm_snapshot_free(void* snap) {
     SnapImpl* s = (SnapImpl*)snap;
     if (!s) return;
     if (s->buf) (void)hipFree(s->buf);
+    ck_free(s->ck);
     delete s;
 }
 
@@ -1246,7 +1407,7 @@ tcm_status tcm_snapshot(tcm_handle* h, void** snap) {
                                hipMemcpyDeviceToDevice, h->stream);
         if (e != hipSuccess) return fail(dev_fail(h, e, "snapshot copy"));
     } else {
-        st = ck_save(h, &s->buf);
+        st = ck_save(h, s->ck);
         if (st) return fail(st);
     }
     const hipError_t e = hipStreamSynchronize(h->stream);
@@ -1272,7 +1433,7 @@ tcm_status tcm_restore(tcm_handle* h, const void* snap) {
                                       hipMemcpyDeviceToDevice, h->stream));
         h->dense_step = s->dense_step;
     } else {
-        st = ck_restore(h, s->buf);
+        st = ck_restore(h, s->ck);
         if (st) return st;
     }
     h->hstep = s->hstep;
@@ -1334,44 +1495,66 @@ tcm_status tcm_adjoint(tcm_handle* h, const float* resid, int32_t nt, int32_t re
     // handle's launch shape
     a->tile_w = 4;
     a->tile_p = 1;
-    a->grid_step = std::max(8, (a->ncu * std::max(1, block_step_occupancy(a->t.adaptive != 0, 4, 1))) / 8 * 8);
+    a->grid_step = std::max(8, (a->ncu * std::max(1, block_step_occupancy(false, 4, 1))) / 8 * 8);
     {
         // adjoint step k (k = 0..nt-1) produces mu^{nt-k}; its source sample at
-        // receiver r is C2_r * resid[nt-1-k][r]
-        std::vector<float> w(nt);
-        for (int q = 0; q < nrec; q++) {
-            for (int k = 0; k < nt; k++) w[k] = c2r[q] * r[(size_t)(nt - 1 - k) * nrec + q];
-            st = tcm_add_source_shot(a, 0, h->rec_xyz[3 * q], h->rec_xyz[3 * q + 1], h->rec_xyz[3 * q + 2],
-                                     w.data(), nt);
-            if (st) return set_err(h, st, std::string("adjoint source: ") + a->err);
-        }
+        // receiver r is C2_r * resid[nt-1-k][r]; all receivers in one activation
+        std::vector<float> w((size_t)nrec * nt);
+        std::vector<int> zero_shot(nrec, 0);
+        for (int q = 0; q < nrec; q++)
+            for (int k = 0; k < nt; k++) w[(size_t)q * nt + k] = c2r[q] * r[(size_t)(nt - 1 - k) * nrec + q];
+        st = add_sources(a, nrec, zero_shot.data(), h->rec_xyz.data(), w.data(), nt);
+        if (st) return set_err(h, st, std::string("adjoint sources: ") + a->err);
     }
     // keep the caller's forward state
-    char* now = nullptr;
-    st = ck_save(h, &now);
+    Ckpt now;
+    st = ck_save(h, now);
     if (st) return st;
-    float* lvl = nullptr;
-    double* g = nullptr;
+    // L u^n of every forward step of a segment, one 512-float tile per list
+    // entry (at most the run's largest list); per step a key -> entry map;
+    // gradient blocks for at most the blocks ever activated in the forward
+    const long long lapcap = std::max<long long>(1, h->h_state->peak_act);
+    const long long nkeys = h->nkeys;
+    const long long gcap = std::max<long long>(1, std::min<long long>(nkeys, (long long)h->h_state->activations));
+    float* lap = nullptr;
+    int* fidx = nullptr;
     float* gs = nullptr;
+    double* gacc = nullptr;
+    int* gslot = nullptr;
+    unsigned long long* gterms = nullptr;
+    int keep_grid_step = -1;
     auto cleanup = [&]() {
-        if (lvl) (void)hipFree(lvl);
-        if (g) (void)hipFree(g);
-        if (gs) (void)hipFree(gs);
-        if (now) (void)hipFree(now);
+        if (keep_grid_step > 0) h->grid_step = keep_grid_step;
+        for (void* q : {(void*)lap, (void*)fidx, (void*)gs, (void*)gacc, (void*)gslot, (void*)gterms})
+            if (q) (void)hipFree(q);
+        ck_free(now);
         h->in_adjoint = false;
+        h->t.rec_lap = nullptr;
+        h->t.rec_fidx = nullptr;
+        a->t.g_lap = nullptr;
+        a->t.g_fidx = nullptr;
+        a->t.g_gs = nullptr;
+        a->t.g_acc = nullptr;
+        a->t.g_slot = nullptr;
+        a->t.g_terms_wg = nullptr;
     };
-    if (hipMalloc((void**)&lvl, sizeof(float) * N * (size_t)K) != hipSuccess ||
-        hipMalloc((void**)&g, sizeof(double) * N) != hipSuccess ||
-        hipMalloc((void**)&gs, sizeof(float) * N) != hipSuccess) {
+    const size_t lap_b = sizeof(float) * (size_t)K * (size_t)lapcap * BV;
+    const size_t fidx_b = sizeof(int) * (size_t)K * (size_t)nkeys;
+    const size_t g_b = (sizeof(float) + sizeof(double)) * (size_t)gcap * BV + sizeof(int) * (size_t)nkeys;
+    if (hipMalloc((void**)&lap, lap_b) != hipSuccess || hipMalloc((void**)&fidx, fidx_b) != hipSuccess ||
+        hipMalloc((void**)&gs, sizeof(float) * (size_t)gcap * BV) != hipSuccess ||
+        hipMalloc((void**)&gacc, sizeof(double) * (size_t)gcap * BV) != hipSuccess ||
+        hipMalloc((void**)&gslot, sizeof(int) * (size_t)nkeys) != hipSuccess ||
+        hipMalloc((void**)&gterms, sizeof(unsigned long long) * GRAD_ACCUM_MAX_WG) != hipSuccess) {
         (void)hipGetLastError();
         cleanup();
-        return set_err(h, TCM_E_NOMEM, "no device memory for the adjoint level buffers");
+        return set_err(h, TCM_E_NOMEM, fmt("no device memory for the adjoint stores (%.2f GB)",
+                                           (lap_b + fidx_b + g_b) / 1e9));
     }
+    h->adjoint_bytes = lap_b + fidx_b + g_b + a->table_bytes + (size_t)a->t.cap * SLOT * sizeof(float);
     h->in_adjoint = true;
-    // timed runs: events around every gradient launch of a segment, read
-    // after the segment
     const bool timing = (h->cfg.flags & TCM_FLAG_TIMING) != 0;
-    while (timing && (int)h->gev.size() < 2 * K) {
+    while (timing && (int)h->gev.size() < 6 * K) {
         hipEvent_t ev;
         if (hipEventCreate(&ev) != hipSuccess) {
             (void)hipGetLastError();
@@ -1380,36 +1563,71 @@ tcm_status tcm_adjoint(tcm_handle* h, const float* resid, int32_t nt, int32_t re
         }
         h->gev.push_back(ev);
     }
-    hipError_t e = hipMemsetAsync(g, 0, sizeof(double) * N, h->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(gs, 0, sizeof(float) * N, h->stream);
+    a->t.g_gs = gs;
+    a->t.g_acc = gacc;
+    a->t.g_slot = gslot;
+    a->t.g_cap = (int)gcap;
+    a->t.g_terms_wg = gterms;
+    hipError_t e = launch_fill_int(gslot, nkeys, -1, h->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(gterms, 0, sizeof(unsigned long long) * GRAD_ACCUM_MAX_WG, h->stream);
+    const unsigned long long a_upd0 = a->h_state->updates, a_updu0 = a->h_state->updates_u;
+    // the recomputing stencil keeps the forward's launch shape within its
+    // own residency (a persistent grid beyond it would leave a tail)
+    keep_grid_step = h->grid_step;
+    h->grid_step = std::min(h->grid_step,
+                            std::max(8, (h->ncu * std::max(1, block_step_occupancy(h->t.adaptive != 0, h->tile_w,
+                                                                                   h->tile_p, STEP_RECORD))) / 8 * 8));
     for (int j = nseg - 1; j >= 0 && e == hipSuccess; j--) {
         const int s0 = j * K, end = std::min(s0 + K, nt);
-        st = ck_restore(h, h->ckpts[j].buf);
+        st = ck_restore(h, h->ckpts[j]);
+        if (!st && timing) st = sync_state(h);
         if (st) { cleanup(); return st; }
+        const unsigned long long rec_u0 = h->h_state->updates, rec_uu0 = h->h_state->updates_u;
         h->hstep = s0;
-        // forward levels s0 .. end-1 into lvl[0 .. end-1-s0]
-        e = launch_read(h->t, 0, 0, 0, 0, 0, S.nx, S.ny, S.nz, lvl, h->stream);
-        for (int l = 1; l < end - s0 && e == hipSuccess; l++) {
-            e = enqueue_step(h, nullptr, nullptr);
-            if (e == hipSuccess) e = launch_read(h->t, 0, 0, 0, 0, 0, S.nx, S.ny, S.nz, lvl + (size_t)l * N, h->stream);
+        // recompute forward steps s0 .. end-1, storing L u^n (n = s0 .. end-1)
+        e = launch_fill_int(fidx, (long long)(end - s0) * nkeys, -1, h->stream);
+        for (int n = s0; n < end && e == hipSuccess; n++) {
+            h->t.rec_lap = lap + (size_t)(n - s0) * (size_t)lapcap * BV;
+            h->t.rec_fidx = fidx + (size_t)(n - s0) * (size_t)nkeys;
+            h->t.rec_lapcap = (int)lapcap;
+            const int q = n - s0;
+            e = enqueue_step(h, timing ? h->gev[2 * K + 2 * q] : nullptr, timing ? h->gev[2 * K + 2 * q + 1] : nullptr);
         }
-        // adjoint levels mu^{end} .. mu^{s0+1}, each with L u^{m-1}
+        h->t.rec_lap = nullptr;
+        h->t.rec_fidx = nullptr;
+        // adjoint levels mu^{end} .. mu^{s0+1}: the adjoint-field step that
+        // forms mu^m also adds mu^m (L u^{m-1}) to the gradient
         for (int m = end; m > s0 && e == hipSuccess; m--) {
             const int q = end - m;
-            e = enqueue_step(a, nullptr, nullptr);
-            if (e == hipSuccess)
-                e = launch_adjoint_grad(a->t, S, lvl + (size_t)(m - 1 - s0) * N, gs, h->stream,
-                                        timing ? h->gev[2 * q] : nullptr, timing ? h->gev[2 * q + 1] : nullptr);
-            if (e == hipSuccess && (m - 1) % GRAD_GROUP == 0) e = launch_grad_flush(g, gs, (long long)N, h->stream);
+            a->t.g_lap = lap + (size_t)(m - 1 - s0) * (size_t)lapcap * BV;
+            a->t.g_fidx = fidx + (size_t)(m - 1 - s0) * (size_t)nkeys;
+            e = enqueue_step(a, timing ? h->gev[2 * q] : nullptr, timing ? h->gev[2 * q + 1] : nullptr,
+                             timing ? h->gev[4 * K + 2 * q] : nullptr, timing ? h->gev[4 * K + 2 * q + 1] : nullptr);
+            if (e == hipSuccess && (m - 1) % GRAD_GROUP == 0) e = launch_grad_flush(a->t, h->stream);
         }
+        a->t.g_lap = nullptr;
+        a->t.g_fidx = nullptr;
         if (timing && e == hipSuccess) {
             e = hipStreamSynchronize(h->stream);
             for (int q = 0; q < end - s0 && e == hipSuccess; q++) {
                 float ms = 0.f;
                 e = hipEventElapsedTime(&ms, h->gev[2 * q], h->gev[2 * q + 1]);
+                h->af_ms += ms;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, h->gev[2 * K + 2 * q], h->gev[2 * K + 2 * q + 1]);
+                h->rec_ms += ms;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, h->gev[4 * K + 2 * q], h->gev[4 * K + 2 * q + 1]);
                 h->grad_ms += ms;
             }
+            h->af_launches += end - s0;
             h->grad_launches += end - s0;
+            h->rec_launches += end - s0;
+        }
+        if (timing && e == hipSuccess) {
+            // nodes the recomputation stepped in this segment
+            st = sync_state(h);
+            if (st) { cleanup(); return st; }
+            h->rec_cells += (long long)(h->h_state->updates - rec_u0);
+            h->rec_cells_u += (long long)(h->h_state->updates_u - rec_uu0);
         }
     }
     if (e != hipSuccess) { cleanup(); return dev_fail(h, e, "adjoint sweep"); }
@@ -1418,20 +1636,31 @@ tcm_status tcm_adjoint(tcm_handle* h, const float* resid, int32_t nt, int32_t re
         st = scratch(h, N * sizeof(float), &dst);
         if (st) { cleanup(); return st; }
     }
-    e = launch_grad_finish(S, h->d_shots, g, dst, h->stream);
+    e = launch_grad_finish(a->t, S, h->d_shots, dst, h->stream);
     if (e == hipSuccess && !out_is_device)
         e = hipMemcpyAsync(grad_c, dst, N * sizeof(float), hipMemcpyDeviceToHost, h->stream);
     if (e != hipSuccess) { cleanup(); return dev_fail(h, e, "adjoint gradient"); }
     st = sync_state(a);
     if (st) { cleanup(); return set_err(h, st, "adjoint tables failed"); }
-    const int aerr = a->h_state->error;
-    if (timing) h->grad_cells += a->h_state->updates;
+    const int aerr = a->h_state->error, gerr = a->h_state->grad_error;
+    if (timing) {
+        h->af_cells += (long long)(a->h_state->updates - a_upd0);
+        h->af_cells_u += (long long)(a->h_state->updates_u - a_updu0);
+        std::vector<unsigned long long> wg(GRAD_ACCUM_MAX_WG);
+        if (hipMemcpy(wg.data(), gterms, sizeof(unsigned long long) * GRAD_ACCUM_MAX_WG, hipMemcpyDeviceToHost) !=
+            hipSuccess) {
+            cleanup();
+            return dev_fail(h, hipGetLastError(), "gradient node counts");
+        }
+        for (unsigned long long v : wg) h->grad_cells += (long long)v;
+    }
     st = ck_restore(h, now);
     if (st) { cleanup(); return st; }
     st = sync_state(h);
     cleanup();
     if (st) return st;
     if (aerr) return set_err(h, TCM_E_POOL, "pool exhausted in the adjoint field");
+    if (gerr) return set_err(h, TCM_E_STATE, "adjoint stores overflowed (forward lists longer than the run's peak)");
     return TCM_OK;
 }
 
@@ -1445,8 +1674,8 @@ tcm_status tcm_autotune(tcm_handle* h, int32_t probe_steps, tcm_tuning* out) {
     if (h->h_state->error) return set_err(h, TCM_E_STATE, "the run has failed (pool)");
     st = ensure_trace_capacity(h, h->h_state->step + (long long)probe_steps - h->t.trace_step0);
     if (st) return st;
-    char* snap = nullptr;
-    st = ck_save(h, &snap);
+    Ckpt snap;
+    st = ck_save(h, snap);
     if (st) return st;
     const int keep_grid = h->grid_step, keep_gs = h->gsteps, keep_w = h->tile_w, keep_p = h->tile_p;
     const int keep_flags = h->cfg.flags;
@@ -1523,7 +1752,8 @@ tcm_status tcm_autotune(tcm_handle* h, int32_t probe_steps, tcm_tuning* out) {
     (void)hipEventDestroy(e1);
     h->cfg.flags = keep_flags;
     tcm_status rs = ck_restore(h, snap);
-    (void)hipFree(snap);
+    if (!rs) rs = sync_state(h);
+    ck_free(snap);
     drop_graph(h);
     if (st || rs) {
         h->grid_step = keep_grid;

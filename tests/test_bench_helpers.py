@@ -24,7 +24,7 @@ def test_launch_shape_names_tuned_given_and_default_shapes():
 
 def test_kernel_source_hash_covers_the_whole_function():
     h = bench.kernel_source_hash("k_block_step")
-    g = bench.kernel_source_hash("k_adjoint_grad")
+    g = bench.kernel_source_hash("k_plan")
     assert len(h) == 16 and len(g) == 16 and h != g
 
 

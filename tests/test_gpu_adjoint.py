@@ -2,7 +2,9 @@
 
 The GPU runs the forward and the adjoint field in FP32 and accumulates the
 gradient in FP64; the stated bound is relative L2 <= 1e-3 over the grid
-(the measured value is printed).
+(the measured value is printed).  With a forward at thresholds above zero
+the gradient is the dense model's adjoint evaluated on the TCM's fields; its
+distance to the dense FP64 gradient is bounded by the forward's truncation.
 """
 import numpy as np
 import pytest
@@ -141,3 +143,71 @@ def test_adjoint_with_update_interval_is_bit_identical_at_threshold_zero(k):
     sim.step(nt)
     gk = sim.adjoint(resid)
     assert np.array_equal(g1, gk)
+
+
+@pytest.mark.parametrize("rel", [1e-4, 1e-3])
+def test_adjoint_with_a_thresholded_forward(rel):
+    """Forward at trigger rel / retire rel/10 of the source peak: the adjoint
+    field still runs at threshold 0 (its scale, C2_r times the residual, is
+    unrelated to the forward's levels), so the gradient stays within the
+    forward's own truncation of the FP64 dense gradient."""
+    announce(f"adjoint with forward trigger {rel:g} of the peak")
+    c, dt, w, src, rec, resid, nt = setup(nt=90, seed=6)
+    peak = float(np.max(np.abs(w)))
+    trig, ret = np.float32(rel * peak), np.float32(rel * peak / 10)
+    sim = tcm.Simulation(c.shape[::-1], 1.0, dt, c, trig, ret, checkpoint_every=20)
+    sim.add_source(src, w)
+    sim.set_receivers(rec)
+    sim.step(nt)
+    g = sim.adjoint(resid)
+    ref = oracle.adjoint_f64(c.astype(np.float64), dt, 1.0, [(src, w.astype(np.float64))], rec,
+                             resid.astype(np.float64), ckpt=10)
+    e = np.linalg.norm(g - ref) / np.linalg.norm(ref)
+    # the forward's own error at these levels, against the FP64 dense field
+    fwd, _, _ = oracle.dense_run(c.astype(np.float64), dt, 1.0, nt, np.float64,
+                                 sources=[(src, w.astype(np.float64))])
+    ef = np.linalg.norm(sim.read(0) - fwd) / np.linalg.norm(fwd)
+    print(f"trigger {rel:g}: gradient rel-L2 vs dense FP64 {e:.3e}; forward field error {ef:.3e}")
+    assert sim.stats()["retirements"] >= 0 and e <= 20 * max(ef, 1e-5)
+
+
+def test_adjoint_on_512_cube_equals_crop_and_memory_follows_active_set():
+    """512^3 grid, a source and receivers near one corner, 200 steps: neither
+    the forward nor the adjoint field gets beyond 320 nodes from the corner,
+    so the gradient equals the one on the 320^3 crop bit for bit (zero
+    beyond it).  The checkpoints and the adjoint's stores hold only what was
+    active: far below the dense arrays."""
+    announce("adjoint 512^3 vs its 320^3 crop; checkpoint and adjoint memory")
+    n, m, nt, K = 512, 320, 200, 50
+    lat = ti.lognormal_lattice((n, n, n), seed=12, sigma=8.0, spacing=8)
+    dt = 0.5 / 4500.0
+    w = ti.ricker(300.0, dt).w32
+    src = (64, 64, 64)
+    rec = np.array([(40 + 12 * i, 40 + 12 * j, 96) for j in range(5) for i in range(5)], np.int32)
+    rng = np.random.default_rng(3)
+    resid = rng.standard_normal((nt, len(rec))).astype(np.float32)
+    out = {}
+    pool = 48000 * 6144            # capped pools: the forward and the adjoint field
+    for edge in (n, m):
+        # the lattice sits at the origin, so the crop sees the same media
+        sim = tcm.Simulation((edge,) * 3, 1.0, dt, lat, checkpoint_every=K, pool_bytes=pool)
+        sim.add_source(src, w)
+        sim.set_receivers(rec)
+        sim.step(nt)
+        out[edge] = (sim.adjoint(resid), sim.stats())
+        sim.close()
+    g_full, st = out[n]
+    g_crop, _ = out[m]
+    assert np.abs(g_crop).max() > 0
+    assert np.array_equal(g_full[:m, :m, :m], g_crop)
+    assert not g_full[m:].any() and not g_full[:, m:].any() and not g_full[:, :, m:].any()
+    dense_bytes = 3 * 4 * n ** 3
+    print(f"512^3: checkpoints {st['checkpoints']} x, {st['checkpoint_bytes'] / 1e6:.1f} MB; adjoint stores "
+          f"{st['adjoint_bytes'] / 1e6:.1f} MB; dense arrays {dense_bytes / 1e6:.0f} MB; peak active "
+          f"{st['peak_active_blocks']} blocks")
+    assert st["checkpoints"] == nt // K
+    # about 4 KiB per active block at each checkpoint
+    assert 0 < st["checkpoint_bytes"] <= st["checkpoints"] * (st["peak_active_blocks"] * 4200 + 4096)
+    assert st["checkpoint_bytes"] < 0.05 * dense_bytes
+    # L u of K forward steps over the run's largest list, not K dense levels
+    assert st["adjoint_bytes"] < 0.2 * K * 4 * n ** 3
