@@ -639,6 +639,8 @@ def main():
                     help="skip the hipGraph replay run (counter-collection runs)")
     ap.add_argument("--no-probe", action="store_true", help="skip the HBM ceiling probe")
     ap.add_argument("--no-roofline", action="store_true", help="c5: skip the timed gradient pass")
+    ap.add_argument("--three-pass-update", action="store_true",
+                    help="run the activation update as three launches where two would do")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device-to-device torch copy (counter calibration)")
     args = ap.parse_args()
@@ -667,7 +669,8 @@ def main():
     nx, ny, nz = w.shape
     log(f"workload {w.name} {w.shape} x {steps} steps, trigger {w.trigger:.3g} retire {w.retire:.3g}")
     opts = dict(uniform_c2=not args.no_uniform_c2, trigger_interval=args.interval,
-                shutdown_steps=args.shutdown_steps, shutdown_alpha=args.shutdown_alpha)
+                shutdown_steps=args.shutdown_steps, shutdown_alpha=args.shutdown_alpha,
+                three_pass_update=args.three_pass_update)
     sim = tcm.Simulation(w.shape, w.dx, w.dt, media_of(w), w.trigger, w.retire,
                          timing=not args.graphs, wg_per_cu=args.wg_per_cu,
                          blocks_per_wg=args.blocks_per_wg, blocks_per_wave=args.blocks_per_wave, **opts)

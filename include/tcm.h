@@ -63,8 +63,12 @@ enum { TCM_ENGINE_BLOCKS = 0, TCM_ENGINE_DENSE = 1 };
 enum {
     TCM_FLAG_TIMING = 1,    /* time every block-stencil launch with HIP events */
     TCM_FLAG_NO_GRAPH = 2,  /* launch each step's kernels directly (no hipGraph replay) */
-    TCM_FLAG_NO_UNIFORM_C2 = 4  /* always read the per-node C2 plane (no scalar C2 for
+    TCM_FLAG_NO_UNIFORM_C2 = 4, /* always read the per-node C2 plane (no scalar C2 for
                                    blocks whose C2 is uniform, "Media" hybrid engine) */
+    TCM_FLAG_THREE_PASS_UPDATE = 8  /* run the activation update as plan, allocation and
+                                   compaction launches even where the two-launch update applies
+                                   (constant levels, update every step, no shutdown, one pool
+                                   slot per block key, at most 2^20 keys); the results are the same */
 };
 
 /* Run configuration.  Zero-initialise, then set the fields. */

@@ -13,7 +13,7 @@ STATUS_NAMES = {0: "TCM_OK", -1: "TCM_E_ARG", -2: "TCM_E_CFL", -3: "TCM_E_POOL",
                 -5: "TCM_E_DEVICE", -6: "TCM_E_STATE", -7: "TCM_E_NOMEM"}
 MEDIA_DENSE, MEDIA_LAYERED, MEDIA_LATTICE = 0, 1, 2
 ENGINE_BLOCKS, ENGINE_DENSE = 0, 1
-FLAG_TIMING, FLAG_NO_GRAPH, FLAG_NO_UNIFORM_C2 = 1, 2, 4
+FLAG_TIMING, FLAG_NO_GRAPH, FLAG_NO_UNIFORM_C2, FLAG_THREE_PASS_UPDATE = 1, 2, 4, 8
 
 # every symbol include/tcm.h declares
 EXPORTS = [

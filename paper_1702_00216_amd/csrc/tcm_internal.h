@@ -64,6 +64,7 @@ struct DevState {
     unsigned long long activations, retirements;
     int free_next;                   // free slots after this step's allocation: installed, and the
                                      // step's n_new / n_ret / n_dec cleared, by the compaction
+    int fast_par;                    // two-launch update: parity of the next active set (k_fast_plan)
     int n_gblocks;                   // adjoint: gradient blocks handed out (first gradient term of a key)
     int grad_error;                  // adjoint: a gradient block or lap-store entry was out of range
 };
@@ -72,7 +73,7 @@ struct Src {
     long long key;     // global block key
     int local;         // node inside the block, (z * 8 + y) * 8 + x
     int t0, ns;        // first step and sample count
-    int next;          // next source of the same block in insertion order, or -1
+    int pad;
     long long w_off;   // offset of the samples in the sample array
 };
 
@@ -89,15 +90,24 @@ struct Tables {
     long long nkeys;                // global block keys (all shots)
     float* pool;
     int* cell2box;                  // per global key: slot, EMPTY or CLAIMED
-    unsigned long long* bitmap;     // next active set, one bit per global key
+    unsigned long long* bitmap;     // next active set, one bit per global key (two-launch update:
+                                    // the active set of even steps)
+    unsigned long long* bitmap2;    // two-launch update: the active set of odd steps
+    int fast;                       // 1: the two-launch activation update (launch_fast_update)
+    int nfchunks;                   // two-launch update: groups of FAST_WORDS bitmap words
+    int* fc_cnt;                    // per group: blocks of the next set,
+    int* fc_new;                    //   activations,
+    int* fc_ret;                    //   releases,
+    unsigned long long* fc_cells;   //   in-domain nodes of the next set (all, then scalar-C2 blocks)
     long long nwords;
     int* act_slot;                  // active list (length n_act)
     int* act_shot;
     unsigned* act_key;              // key inside the shot
     int* rows;                      // per list entry: slot, 6 neighbour slots (or EMPTY), global key
     unsigned char* flags;           // per slot: face bits 0..5 and KEEP_BIT
-    int* pin_until;                 // per slot: active while step < pin_until (sources)
-    int* src_head;                  // per slot: the block's first source (chained by Src::next), or -1
+    int* pin_until;                 // per slot two ints: [2 slot] active while step < it (sources);
+                                    // [2 slot + 1] the block's sources in the (key-ordered) source
+                                    // table, count << 24 | first, or -1
     float* slot_c2u;                // per slot: the block's C2 if uniform over the block, else NaN
     unsigned char* sdlog;           // per slot: shutdown steps left (0: not shutting down)
     int* dec_slot;                  // per step: slots whose levels are multiplied by alpha
@@ -174,17 +184,23 @@ hipError_t launch_plan(const Tables& t, int grid, hipStream_t s);
 hipError_t launch_advance(const Tables& t, hipStream_t s);   // step without an activation update
 hipError_t launch_pool_count(const Tables& t, int grid, hipStream_t s);   // grid >= scan_wgs
 hipError_t launch_emit(const Tables& t, int grid, hipStream_t s);
+// The activation update in two launches for constant levels, an update every
+// step, no shutdown and one slot per key (Tables::fast): k_fast_plan then
+// k_fast_emit (tcm_kernels.hip).  FAST_WORDS bitmap words per workgroup;
+// at most FAST_MAX_CHUNKS groups (each workgroup sums the groups' counts).
+constexpr int FAST_WORDS = 4;
+constexpr int FAST_MAX_CHUNKS = 4096;
+hipError_t launch_fast_update(const Tables& t, int grid, hipStream_t s);
 // Activate n blocks (distinct global keys; shot and key inside the shot per
-// entry), pin each while step < pins[i] and, where heads[i] >= 0, make it the
-// block's first source; one wave per block.  Blocks that are active already
-// only raise their pin (and take the head).  No free slot: add_error = -3.
+// entry), pin each while step < pins[i] and, where heads[i] >= 0, give it
+// that source range; one wave per block.  Blocks that are active already
+// only raise their pin (and take the range).  pins[i] == -1: only refresh the
+// range of an active block; -2: clear pin and range of an active block.  No
+// free slot: add_error = -3.
 hipError_t launch_activate_list(const Tables& t, const long long* keys, const int* shots,
                                 const unsigned* local_keys, const int* pins, const int* heads, int n,
                                 hipStream_t s);
 hipError_t launch_refresh_rows(const Tables& t, hipStream_t s);
-// after sources from index nsrc on were dropped: slots whose first source was
-// one of them lose it and its pin
-hipError_t launch_drop_sources(const Tables& t, int nsrc, hipStream_t s);
 hipError_t launch_read(const Tables& t, int shot, int which, int x0, int y0, int z0, int sx,
                        int sy, int sz, float* out, hipStream_t s);
 hipError_t launch_media_c2(const Shot& shot, const Shot* dshot, double dt, double dx, float* c2,

@@ -191,11 +191,14 @@ __global__ void k_init_tables(Tables t, long long nkeys) {
     const long long gs = (long long)gridDim.x * blockDim.x;
     const long long g0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     for (long long i = g0; i < nkeys; i += gs) t.cell2box[i] = EMPTY;
-    for (long long i = g0; i < (long long)t.nchunks * CHUNK_WORDS; i += gs) t.bitmap[i] = 0ull;
+    for (long long i = g0; i < (long long)t.nchunks * CHUNK_WORDS; i += gs) {
+        t.bitmap[i] = 0ull;
+        if (t.fast) t.bitmap2[i] = 0ull;
+    }
     for (long long i = g0; i < t.cap; i += gs) {
         t.slot_key[i] = -1;
-        t.pin_until[i] = 0;
-        t.src_head[i] = -1;
+        t.pin_until[2 * (size_t)(i)] = 0;
+        t.pin_until[2 * (size_t)(i) + 1] = -1;
         t.flags[i] = 0;
         t.slot_c2u[i] = __builtin_nanf("");
         t.sdlog[i] = 0;
@@ -229,6 +232,7 @@ hipError_t launch_init_tables(const Tables& t, long long nkeys, hipStream_t s) {
 // LDS tile per wave: columns (xx, yy) in [0,10)^2 (node x = xx - 1,
 // y = yy - 1) of 8 z values each; interior 8x8 from the block, the four x/y
 // side faces from the neighbours, corners unused.
+typedef int row8 __attribute__((ext_vector_type(8)));
 constexpr int TILE_COLS = 10;
 constexpr int TILE_FLOATS = TILE_COLS * TILE_COLS * BE;
 
@@ -283,8 +287,9 @@ __global__ __launch_bounds__(64 * W) void k_block_step(Tables t) {
     // the compaction; the next rows are fetched while the current blocks are
     // processed, so only the data loads sit on the critical path.
     const scalar_ptr<int> rows = as_scalar((const int*)t.rows);
-    const scalar_ptr<int> pin_until = as_scalar((const int*)t.pin_until);
-    const scalar_ptr<int> src_head = as_scalar((const int*)t.src_head);
+    // per slot {pin, first source}: one 8-byte scalar load for both (a second
+    // scalar load per block cost 2 % of the stencil's time)
+    const scalar_ptr<unsigned long long> pin_head = as_scalar((const unsigned long long*)t.pin_until);
     const scalar_ptr<float> slot_c2u = as_scalar((const float*)t.slot_c2u);
     const int stride = per * B;
     // The loop count is uniform over the workgroup (barriers below).  Entry
@@ -301,8 +306,11 @@ __global__ __launch_bounds__(64 * W) void k_block_step(Tables t) {
             sl_prev[q] = EMPTY;
             sl_next[q] = EMPTY;
             if (i < end) {
+                // the whole 32-byte row in one scalar load, whichever fields
+                // the variant uses (split loads measured 2 % slower)
+                const row8 v = *(const __attribute__((address_space(4))) row8*)(rows + 8 * (size_t)gidx(i));
 #pragma unroll
-                for (int k = 0; k < 8; k++) r[q][k] = rows[8 * (size_t)gidx(i) + k];
+                for (int k = 0; k < 8; k++) r[q][k] = v[k];
                 if (j > 0) sl_prev[q] = rows[8 * (size_t)gidx(i - 1)];
                 if (j < B - 1 && i + 1 < end) sl_next[q] = rows[8 * (size_t)gidx(i + 1)];
             }
@@ -342,8 +350,11 @@ __global__ __launch_bounds__(64 * W) void k_block_step(Tables t) {
             zlo[q] = 0.f; zhi[q] = 0.f; pinned[q] = 0; shead[q] = -1; out_p[q] = nullptr;
             fmx[q] = 0.f; fpx[q] = 0.f; fmy[q] = 0.f; fpy[q] = 0.f;
             if (!have[q]) continue;
-            pinned[q] = t.nsrc > 0 ? pin_until[slot[q]] : 0;
-            if (pinned[q] > n) shead[q] = src_head[slot[q]];
+            if (t.nsrc > 0) {
+                const unsigned long long ph = pin_head[slot[q]];    // {pin, first source}
+                pinned[q] = (int)(unsigned)ph;
+                shead[q] = (int)(unsigned)(ph >> 32);
+            }
             const float c2u = slot_c2u[slot[q]];
             const float* __restrict__ cur_p = plane_of(t, slot[q], p);
             out_p[q] = plane_of(t, slot[q], 1 - p);
@@ -430,9 +441,12 @@ __global__ __launch_bounds__(64 * W) void k_block_step(Tables t) {
                 }
             }
             // additive source insertion (before the predicates): the block's
-            // own sources, in the order they were added
-            if (pinned[q] > n) {
-                for (int s = shead[q]; s >= 0; s = t.src[s].next) {
+            // own sources, a range of the key-ordered table, in the order they
+            // were added (a counted loop: walking a chain of indices cost 2 %
+            // of the stencil's time, even for blocks without sources)
+            if (pinned[q] > n && shead[q] >= 0) {
+                const int first = shead[q] & 0xFFFFFF, cnt = shead[q] >> 24;
+                for (int s = first; s < first + cnt; s++) {
                     const Src e = t.src[s];
                     const int k = n - e.t0;
                     if (k < 0 || k >= e.ns) continue;
@@ -685,7 +699,7 @@ __global__ __launch_bounds__(256) void k_plan(Tables t) {
                 f = t.flags[slot];
             }
             key_to_block(t.shots[shot], key, bx, by, bz);
-            survive = (f & KEEP_BIT) != 0 || t.pin_until[slot] > n + 1;
+            survive = (f & KEEP_BIT) != 0 || t.pin_until[2 * (size_t)(slot)] > n + 1;
         }
         if (t.interval <= 1) {
             // an active neighbour whose face toward us is above trigger keeps us
@@ -717,7 +731,7 @@ __global__ __launch_bounds__(256) void k_plan(Tables t) {
             // update every `interval` (<= 8) steps: values move at most one node
             // per step, so a block that is hot (or still inserting a source)
             // must have all 26 nearest and diagonal neighbours active
-            const bool hot = valid && (((f & HOT_BIT) != 0) || t.pin_until[slot] > n + 1);
+            const bool hot = valid && (((f & HOT_BIT) != 0) || t.pin_until[2 * (size_t)(slot)] > n + 1);
             for (int d = 0; d < 27; d++) {
                 if (d == 13) continue;
                 bool claim = false;
@@ -736,7 +750,7 @@ __global__ __launch_bounds__(256) void k_plan(Tables t) {
                             } else {
                                 nhot = (t.flags[s_nb] & HOT_BIT) != 0;
                             }
-                            if (nhot || t.pin_until[s_nb] > n + 1) survive = true;
+                            if (nhot || t.pin_until[2 * (size_t)(s_nb)] > n + 1) survive = true;
                         } else if (hot && s_nb == EMPTY) {
                             claim = atomicCAS(&t.cell2box[nk], EMPTY, CLAIMED) == EMPTY;
                         }
@@ -928,8 +942,8 @@ __global__ __launch_bounds__(256) void k_pool_count(Tables t) {
                     t.sdlog[slot] = 0;
                     t.cell2box[G] = slot;
                     t.slot_key[slot] = G;
-                    t.pin_until[slot] = 0;
-                    t.src_head[slot] = -1;
+                    t.pin_until[2 * (size_t)(slot)] = 0;
+                    t.pin_until[2 * (size_t)(slot) + 1] = -1;
                 }
             }
         }
@@ -1215,6 +1229,248 @@ hipError_t launch_emit(const Tables& t, int grid, hipStream_t s) {
 }
 
 // --------------------------------------------------------------------------
+// Activation update in two launches (constant levels, update every step, no
+// shutdown, one pool slot per block key, so that a block's slot is its key).
+// The active set of step n is the bitmap act(n) = (n & 1 ? bitmap2 : bitmap).
+//
+// k_fast_plan: one 64-lane wave per bitmap word (lane = key), FAST_WORDS
+//   words per workgroup (a "fast chunk").  Each key pulls its decision from
+//   the stencil's flag bytes: an active block stays if its keep bit is set or
+//   its source still inserts; any block is in the next set if an active face
+//   neighbour's face toward it is above the trigger ("Updating active cells",
+//   items 3 and 4).  The workgroup writes its words of the next set, releases
+//   and allocates (zero levels, C2 from the media) its own blocks, and stores
+//   its counts; no two workgroups touch the same word, so nothing waits on
+//   another workgroup and no global atomic is used.
+// k_fast_emit: each workgroup sums the counts of the fast chunks before its
+//   own (its offset in the next list) and of all (the list's length), then
+//   compacts its words into the list and its rows in key order, and clears
+//   its words of act(n) for step n + 2; workgroup 0 commits the step.
+// --------------------------------------------------------------------------
+__device__ __forceinline__ unsigned long long* fast_bm(const Tables& t, int par) {
+    return par ? t.bitmap2 : t.bitmap;
+}
+
+__global__ __launch_bounds__(64 * FAST_WORDS) void k_fast_plan(Tables t) {
+    DevState* st = t.st;
+    __shared__ int s_new[64 * FAST_WORDS];
+    __shared__ int s_nnew, s_nret;
+    __shared__ unsigned s_cnt[FAST_WORDS];
+    __shared__ unsigned long long s_cells[FAST_WORDS], s_cellsu[FAST_WORDS];
+    if (st->error) return;
+    const int n = st->step;
+    const int p = n & 1;
+    const unsigned long long* cur = fast_bm(t, p);
+    unsigned long long* nxt = fast_bm(t, 1 - p);
+    const int lane = lane_id();
+    const int wid = threadIdx.x >> 6;
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->fast_par = 1 - p;   // read by k_fast_emit
+    // receivers: traces[n - trace_step0][r] = phi^{n+1} (slot = key)
+    const int row = n - t.trace_step0;
+    if (blockIdx.x == 0 && row >= 0 && row < t.trace_cap) {
+        for (int r = threadIdx.x; r < t.nrec; r += blockDim.x) {
+            const Rec e = t.rec[r];
+            const bool on = (cur[e.key >> 6] >> (e.key & 63)) & 1ull;
+            t.traces[(size_t)row * t.nrec + r] = on ? plane_of(t, e.key, 1 - p)[e.local] : 0.f;
+        }
+    }
+    const float trig = t.trigger;
+    (void)trig;
+    for (int c = blockIdx.x; c < t.nfchunks; c += gridDim.x) {       // uniform over the workgroup
+        if (threadIdx.x == 0) { s_nnew = 0; s_nret = 0; }
+        __syncthreads();
+        const long long w = (long long)c * FAST_WORDS + wid;
+        const long long G = w * 64 + lane;
+        const bool in_range = w < t.nwords;
+        const unsigned long long curw = in_range ? cur[w] : 0ull;
+        const bool active = (curw >> lane) & 1ull;
+        bool survive = false, in_dom = false;
+        int shot = 0, bx = 0, by = 0, bz = 0;
+        if (in_range) {
+            shot = shot_of_word(t, w);
+            const Shot& S = t.shots[shot];
+            key_to_block(S, (unsigned)(G - S.key_base), bx, by, bz);
+            in_dom = bx < S.bx && by < S.by && bz < S.bz;
+            if (in_dom) {
+                if (active)
+                    survive = (t.flags[G] & KEEP_BIT) != 0 || t.pin_until[2 * (size_t)(G)] > n + 1;
+#pragma unroll
+                for (int d = 0; d < 6; d++) {
+                    const long long nk = neighbour_key(S, bx, by, bz, d);
+                    if (nk >= 0 && ((cur[nk >> 6] >> (nk & 63)) & 1ull) && ((t.flags[nk] >> (d ^ 1)) & 1u))
+                        survive = true;
+                }
+            }
+        }
+        const unsigned long long nw = __ballot(survive);
+        if (lane == 0) {
+            nxt[w] = nw;
+            s_cnt[wid] = (unsigned)__popcll(nw);
+        }
+        if (active && !survive) {                        // released ("Updating active cells", item 7)
+            t.cell2box[G] = EMPTY;
+            t.slot_key[G] = -1;
+            atomicAdd(&s_nret, 1);
+        }
+        if (survive && !active) s_new[atomicAdd(&s_nnew, 1)] = (int)(G - (long long)c * FAST_WORDS * 64);
+        __syncthreads();
+        // new blocks, one wave each: zero levels, C2 from the media (item 8)
+        const int nnew = s_nnew;
+        for (int k = wid; k < nnew; k += FAST_WORDS) {
+            const long long G2 = (long long)c * FAST_WORDS * 64 + s_new[k];
+            const int sh = shot_of_word(t, G2 >> 6);
+            const Shot& S = t.shots[sh];
+            int x2, y2, z2;
+            key_to_block(S, (unsigned)(G2 - S.key_base), x2, y2, z2);
+            const float c2u = fill_slot(t, S, G2, x2, y2, z2);
+            if (lane == 0) {
+                t.slot_c2u[G2] = c2u;
+                t.sdlog[G2] = 0;
+                t.cell2box[G2] = (int)G2;
+                t.slot_key[G2] = G2;
+                t.pin_until[2 * (size_t)(G2)] = 0;
+                t.pin_until[2 * (size_t)(G2) + 1] = -1;
+            }
+        }
+        __syncthreads();
+        // in-domain nodes of the next set (and of its blocks with a scalar C2)
+        unsigned long long bc = 0, bu = 0;
+        if (survive) {
+            bc = (unsigned long long)block_cells(t.shots[shot], bx, by, bz);
+            const float u = t.slot_c2u[G];
+            if (u == u) bu = bc;
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            bc += __shfl_xor(bc, o);
+            bu += __shfl_xor(bu, o);
+        }
+        if (lane == 0) {
+            s_cells[wid] = bc;
+            s_cellsu[wid] = bu;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned cnt = 0;
+            unsigned long long cc = 0, cu = 0;
+            for (int k = 0; k < FAST_WORDS; k++) {
+                cnt += s_cnt[k];
+                cc += s_cells[k];
+                cu += s_cellsu[k];
+            }
+            t.fc_cnt[c] = (int)cnt;
+            t.fc_new[c] = s_nnew;
+            t.fc_ret[c] = s_nret;
+            t.fc_cells[2 * (size_t)c] = cc;
+            t.fc_cells[2 * (size_t)c + 1] = cu;
+        }
+        __syncthreads();                                   // LDS is reused by the next chunk
+    }
+}
+
+__global__ __launch_bounds__(64 * FAST_WORDS) void k_fast_emit(Tables t) {
+    DevState* st = t.st;
+    __shared__ unsigned long long s_red[FAST_WORDS][6];
+    __shared__ unsigned s_word[FAST_WORDS];
+    if (st->error) return;
+    const int par = st->fast_par;
+    const unsigned long long* nxt = fast_bm(t, par);
+    unsigned long long* old = fast_bm(t, 1 - par);
+    const int lane = lane_id();
+    const int wid = threadIdx.x >> 6;
+    const int nf = t.nfchunks;
+    for (int c = blockIdx.x; c < nf; c += gridDim.x) {          // uniform over the workgroup
+        // offset of this fast chunk in the next list and the list's length;
+        // the workgroup of chunk 0 also sums the step's statistics
+        unsigned long long v6[6] = {0, 0, 0, 0, 0, 0};   // before, total, cells, scalar-C2 cells, new, released
+        for (int k = threadIdx.x; k < nf; k += blockDim.x) {
+            const unsigned long long v = (unsigned)t.fc_cnt[k];
+            v6[1] += v;
+            if (k < c) v6[0] += v;
+            if (c == 0) {
+                v6[2] += t.fc_cells[2 * (size_t)k];
+                v6[3] += t.fc_cells[2 * (size_t)k + 1];
+                v6[4] += (unsigned)t.fc_new[k];
+                v6[5] += (unsigned)t.fc_ret[k];
+            }
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
+            for (int q = 0; q < 6; q++) v6[q] += __shfl_xor(v6[q], o);
+        }
+        if (lane == 0) {
+#pragma unroll
+            for (int q = 0; q < 6; q++) s_red[wid][q] = v6[q];
+        }
+        const long long w = (long long)c * FAST_WORDS + wid;
+        const bool in_range = w < t.nwords;
+        const unsigned long long myw = in_range ? nxt[w] : 0ull;
+        if (lane == 0) s_word[wid] = (unsigned)__popcll(myw);
+        __syncthreads();
+        unsigned long long base = 0, ntot = 0;
+        for (int k = 0; k < FAST_WORDS; k++) {
+            base += s_red[k][0];
+            ntot += s_red[k][1];
+        }
+        unsigned long long cc = 0, cu = 0, na = 0, nr = 0;
+        for (int k = 0; k < FAST_WORDS; k++) {
+            cc += s_red[k][2];
+            cu += s_red[k][3];
+            na += s_red[k][4];
+            nr += s_red[k][5];
+        }
+        for (int k = 0; k < wid; k++) base += s_word[k];
+        if ((myw >> lane) & 1ull) {
+            const long long G = w * 64 + lane;
+            const unsigned off = (unsigned)(base + (unsigned long long)__popcll(myw & ((1ull << lane) - 1ull)));
+            const int shot = shot_of_word(t, w);
+            const Shot& S = t.shots[shot];
+            const unsigned key = (unsigned)(G - S.key_base);
+            t.act_slot[off] = (int)G;
+            t.act_shot[off] = shot;
+            t.act_key[off] = key;
+            int bx, by, bz;
+            key_to_block(S, key, bx, by, bz);
+            int nb[6];
+#pragma unroll
+            for (int d = 0; d < 6; d++) {
+                const long long nk = neighbour_key(S, bx, by, bz, d);
+                nb[d] = (nk >= 0 && ((nxt[nk >> 6] >> (nk & 63)) & 1ull)) ? (int)nk : EMPTY;
+            }
+            int4* rp = (int4*)(t.rows + 8 * (size_t)off);
+            rp[0] = make_int4((int)G, nb[0], nb[1], nb[2]);
+            rp[1] = make_int4(nb[3], nb[4], nb[5], (int)G);
+        }
+        if (in_range && lane == 0) old[w] = 0ull;                 // act(n), reused as the set of step n + 2
+        // commit (workgroup 0, once): no other workgroup of this launch reads
+        // the fields it changes
+        if (c == 0 && threadIdx.x == 0) {
+            st->updates += st->cells_cur;
+            st->updates_u += st->cells_cur_u;
+            st->cells_cur = cc;
+            st->cells_cur_u = cu;
+            st->activations += na;
+            st->retirements += nr;
+            st->n_act = (int)ntot;
+            if ((int)ntot > st->peak_act) st->peak_act = (int)ntot;
+            st->free_cnt = t.cap - (int)ntot;
+            st->free_next = st->free_cnt;
+            st->step += 1;
+            st->maxbits = 0u;
+        }
+        __syncthreads();                                   // LDS is reused by the next chunk
+    }
+}
+
+hipError_t launch_fast_update(const Tables& t, int grid, hipStream_t s) {
+    if (!t.fast || t.nfchunks > FAST_MAX_CHUNKS) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_fast_plan, dim3(grid), dim3(64 * FAST_WORDS), 0, s, t);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_fast_emit, dim3(grid), dim3(64 * FAST_WORDS), 0, s, t);
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
 // source activation: box the blocks of new sources by hand, one wave per
 // block (distinct keys), appending them to the active list
 // --------------------------------------------------------------------------
@@ -1229,10 +1485,21 @@ __global__ __launch_bounds__(256) void k_activate_list(Tables t, const long long
     const int pin = pins[k];
     const int head = heads[k];
     const int cur = t.cell2box[G];
+    if (pin < 0) {                           // an earlier source block: refresh or clear its range
+        if (cur >= 0 && lane == 0) {
+            if (pin == -2) {
+                t.pin_until[2 * (size_t)(cur)] = 0;
+                t.pin_until[2 * (size_t)(cur) + 1] = -1;
+            } else if (head >= 0) {
+                t.pin_until[2 * (size_t)(cur) + 1] = head;
+            }
+        }
+        return;
+    }
     if (cur >= 0) {                          // active already: raise its pin
         if (lane == 0) {
-            if (t.pin_until[cur] < pin) t.pin_until[cur] = pin;
-            if (head >= 0) t.src_head[cur] = head;
+            if (t.pin_until[2 * (size_t)(cur)] < pin) t.pin_until[2 * (size_t)(cur)] = pin;
+            if (head >= 0) t.pin_until[2 * (size_t)(cur) + 1] = head;
         }
         return;
     }
@@ -1261,8 +1528,9 @@ __global__ __launch_bounds__(256) void k_activate_list(Tables t, const long long
         t.sdlog[slot] = 0;
         t.cell2box[G] = slot;
         t.slot_key[slot] = G;
-        t.pin_until[slot] = pin;
-        t.src_head[slot] = head;
+        t.pin_until[2 * (size_t)(slot)] = pin;
+        t.pin_until[2 * (size_t)(slot) + 1] = head;
+        if (t.fast) atomicOr(&fast_bm(t, st->step & 1)[G >> 6], 1ull << (G & 63));
         const int i = atomicAdd(&st->n_act, 1);
         t.act_slot[i] = slot;
         t.act_shot[i] = shot;
@@ -1310,20 +1578,6 @@ hipError_t launch_refresh_rows(const Tables& t, hipStream_t s) {
     return hipGetLastError();
 }
 
-__global__ void k_drop_sources(Tables t, int nsrc) {
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < t.cap;
-         i += (long long)gridDim.x * blockDim.x) {
-        if (t.src_head[i] >= nsrc) {
-            t.src_head[i] = -1;
-            t.pin_until[i] = 0;
-        }
-    }
-}
-
-hipError_t launch_drop_sources(const Tables& t, int nsrc, hipStream_t s) {
-    hipLaunchKernelGGL(k_drop_sources, dim3(256), dim3(256), 0, s, t, nsrc);
-    return hipGetLastError();
-}
 
 // --------------------------------------------------------------------------
 // read: gather a box of phi^n / phi^{n-1} (inactive nodes -> 0)
@@ -1744,12 +1998,12 @@ __global__ __launch_bounds__(256) void k_ck_gather(Tables t, long long n, char* 
         e.slot = slot;
         e.shot = t.act_shot[i];
         e.key = t.act_key[i];
-        e.pin = t.pin_until[slot];
+        e.pin = t.pin_until[2 * (size_t)(slot)];
         e.c2u = t.slot_c2u[slot];
         e.flags = t.flags[slot];
         e.sdlog = t.sdlog[slot];
         e.pad0 = e.pad1 = 0;
-        e.src_head = t.src_head[slot];
+        e.src_head = t.pin_until[2 * (size_t)(slot) + 1];
         e.pad2 = 0;
         e.slot_key = t.slot_key[slot];
         for (int k = 0; k < 8; k++) e.row[k] = t.rows[8 * (size_t)i + k];
@@ -1781,13 +2035,17 @@ __global__ __launch_bounds__(256) void k_ck_scatter(Tables t, long long n, const
         t.act_shot[i] = e.shot;
         t.act_key[i] = e.key;
         for (int k = 0; k < 8; k++) t.rows[8 * (size_t)i + k] = e.row[k];
-        t.pin_until[e.slot] = e.pin;
-        t.src_head[e.slot] = e.src_head;
+        t.pin_until[2 * (size_t)(e.slot)] = e.pin;
+        t.pin_until[2 * (size_t)(e.slot) + 1] = e.src_head;
         t.slot_c2u[e.slot] = e.c2u;
         t.flags[e.slot] = e.flags;
         t.sdlog[e.slot] = e.sdlog;
         t.slot_key[e.slot] = e.slot_key;
         t.cell2box[e.slot_key] = e.slot;
+        if (t.fast) {
+            const int step = ((const DevState*)buf)->step;
+            atomicOr(&fast_bm(t, step & 1)[e.slot_key >> 6], 1ull << (e.slot_key & 63));
+        }
     }
 }
 

@@ -12,7 +12,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
-#include <unordered_map>
+#include <map>
 #include <vector>
 
 #include "tcm.h"
@@ -64,8 +64,7 @@ struct tcm_handle {
     long long hstep = 0;                // index of the next step to enqueue
 
     // sources / receivers (host mirrors)
-    std::vector<Src> h_src;
-    std::unordered_map<long long, std::pair<int, int>> src_chain;   // block key -> first, last source
+    std::vector<Src> h_src;             // in the order added (the device copy is sorted by key)
     std::vector<float> h_srcw;
     Src* d_src = nullptr;
     size_t d_src_cap = 0;
@@ -122,7 +121,7 @@ struct tcm_handle {
     // timed recomputed forward steps of tcm_adjoint (TCM_FLAG_TIMING)
     double rec_ms = 0.0;
     long long rec_launches = 0, rec_cells = 0, rec_cells_u = 0;
-    // source activation requests (keys, shots, keys in the shot, pins, heads)
+    // source activation requests (keys, shots, keys in the shot, pins, source ranges)
     void* d_act_req = nullptr;
     size_t d_act_req_cap = 0;
 };
@@ -368,13 +367,24 @@ tcm_status setup_engine(tcm_handle* h, long long word_base) {
     }
     ok = ok && dalloc(h, &t.cell2box, (size_t)h->nkeys) == hipSuccess;
     ok = ok && dalloc(h, &t.bitmap, (size_t)t.nchunks * CHUNK_WORDS) == hipSuccess;
+    // the two-launch activation update (a block's slot is its key)
+    t.nfchunks = (int)((word_base + FAST_WORDS - 1) / FAST_WORDS);
+    t.fast = (!(cfg->flags & TCM_FLAG_THREE_PASS_UPDATE) && cfg->trigger_rel == 0.f && cfg->retire_rel == 0.f &&
+              cfg->trigger_interval <= 1 && cfg->shutdown_steps == 0 && cap >= h->nkeys &&
+              t.nfchunks <= FAST_MAX_CHUNKS) ? 1 : 0;
+    if (t.fast) {
+        ok = ok && dalloc(h, &t.bitmap2, (size_t)t.nchunks * CHUNK_WORDS) == hipSuccess;
+        ok = ok && dalloc(h, &t.fc_cnt, (size_t)t.nfchunks) == hipSuccess;
+        ok = ok && dalloc(h, &t.fc_new, (size_t)t.nfchunks) == hipSuccess;
+        ok = ok && dalloc(h, &t.fc_ret, (size_t)t.nfchunks) == hipSuccess;
+        ok = ok && dalloc(h, &t.fc_cells, 2 * (size_t)t.nfchunks) == hipSuccess;
+    }
     ok = ok && dalloc(h, &t.act_slot, (size_t)cap) == hipSuccess;
     ok = ok && dalloc(h, &t.act_shot, (size_t)cap) == hipSuccess;
     ok = ok && dalloc(h, &t.act_key, (size_t)cap) == hipSuccess;
     ok = ok && dalloc(h, &t.rows, (size_t)cap * 8) == hipSuccess;
     ok = ok && dalloc(h, &t.flags, (size_t)cap) == hipSuccess;
-    ok = ok && dalloc(h, &t.pin_until, (size_t)cap) == hipSuccess;
-    ok = ok && dalloc(h, &t.src_head, (size_t)cap) == hipSuccess;
+    ok = ok && dalloc(h, &t.pin_until, 2 * (size_t)cap) == hipSuccess;
     ok = ok && dalloc(h, &t.slot_c2u, (size_t)cap) == hipSuccess;
     ok = ok && dalloc(h, &t.sdlog, (size_t)cap) == hipSuccess;
     ok = ok && dalloc(h, &t.dec_slot, (size_t)cap) == hipSuccess;
@@ -538,6 +548,7 @@ hipError_t enqueue_step(tcm_handle* h, hipEvent_t e0, hipEvent_t e1, hipEvent_t 
         (e = launch_grad_accum(h->t, std::min(GRAD_ACCUM_MAX_WG, h->ncu * 8), h->stream, g0, g1)) != hipSuccess)
         return e;
     if ((n + 1) % k != 0) return launch_advance(h->t, h->stream);
+    if (h->t.fast) return launch_fast_update(h->t, h->t.nfchunks, h->stream);
     if ((e = launch_plan(h->t, h->grid_plan, h->stream)) != hipSuccess) return e;
     if ((e = launch_pool_count(h->t, h->grid_pool, h->stream)) != hipSuccess) return e;
     return launch_emit(h->t, h->grid_emit, h->stream);
@@ -714,29 +725,108 @@ tcm_status issue_steps_timed(tcm_handle* h, int n) {
     return TCM_OK;
 }
 
-// Source chains from the table (after sources were dropped).
-void rebuild_chains(tcm_handle* h) {
-    h->src_chain.clear();
-    for (size_t i = 0; i < h->h_src.size(); i++) {
-        Src& e = h->h_src[i];
-        e.next = -1;
-        if (h->engine != TCM_ENGINE_BLOCKS) continue;
-        auto it = h->src_chain.find(e.key);
-        if (it == h->src_chain.end()) {
-            h->src_chain[e.key] = {(int)i, (int)i};
-        } else {
-            h->h_src[(size_t)it->second.second].next = (int)i;
-            it->second.second = (int)i;
-        }
+// ---- sources ----------------------------------------------------------------
+// The device source table holds the sources ordered by key (block key for the
+// block engine, node for the dense engine), keeping the order in which
+// sources of one key were added; a source block's slot records the range of
+// its own sources in that table (packed as count << 24 | first), so the
+// stencil visits only those, in the order they were added.
+constexpr int SRC_RANGE_MAX = 127;          // sources of one block
+constexpr int SRC_FIRST_MAX = 1 << 24;      // table entries
+
+struct SrcKeyInfo {
+    int first = 0, count = 0;
+    int pin = 0;                            // largest t0 + ns of its sources
+};
+
+// Sorted device copy of h->h_src and the range of every key; uploads the
+// table and the samples.  TCM_E_ARG if a block holds too many sources.
+tcm_status upload_sources(tcm_handle* h, std::map<long long, SrcKeyInfo>* ranges) {
+    const size_t ns = h->h_src.size();
+    if (ns > (size_t)SRC_FIRST_MAX) return set_err(h, TCM_E_ARG, "too many sources");
+    std::vector<int> ord(ns);
+    for (size_t i = 0; i < ns; i++) ord[i] = (int)i;
+    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return h->h_src[x].key < h->h_src[y].key; });
+    std::vector<Src> sorted(ns);
+    ranges->clear();
+    for (size_t i = 0; i < ns; i++) {
+        sorted[i] = h->h_src[ord[i]];
+        SrcKeyInfo& r = (*ranges)[sorted[i].key];
+        if (r.count == 0) r.first = (int)i;
+        r.count++;
+        r.pin = std::max(r.pin, sorted[i].t0 + sorted[i].ns);
+        if (r.count > SRC_RANGE_MAX) return set_err(h, TCM_E_ARG, fmt("more than %d sources in one block", SRC_RANGE_MAX));
     }
+    if (ns > h->d_src_cap) {
+        size_t c = std::max<size_t>(16, h->d_src_cap * 2);
+        while (c < ns) c *= 2;
+        Src* d = nullptr;
+        if (dalloc(h, &d, c) != hipSuccess) return set_err(h, TCM_E_NOMEM, "no device memory for the source table");
+        dfree(h, h->d_src);
+        h->d_src = d;
+        h->d_src_cap = c;
+    }
+    if (h->h_srcw.size() > h->d_srcw_cap) {
+        size_t c = std::max<size_t>(1024, h->d_srcw_cap * 2);
+        while (c < h->h_srcw.size()) c *= 2;
+        float* d = nullptr;
+        if (dalloc(h, &d, c) != hipSuccess) return set_err(h, TCM_E_NOMEM, "no device memory for the source samples");
+        dfree(h, h->d_srcw);
+        h->d_srcw = d;
+        h->d_srcw_cap = c;
+    }
+    if (ns) HIP_OR_FAIL(h, hipMemcpyAsync(h->d_src, sorted.data(), ns * sizeof(Src), hipMemcpyHostToDevice, h->stream));
+    if (!h->h_srcw.empty())
+        HIP_OR_FAIL(h, hipMemcpyAsync(h->d_srcw, h->h_srcw.data(), h->h_srcw.size() * sizeof(float),
+                                      hipMemcpyHostToDevice, h->stream));
+    // pageable copies return once the data are staged: the vectors may go
+    HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+    h->t.src = h->d_src;
+    h->t.srcw = h->d_srcw;
+    h->t.nsrc = (int)ns;
+    drop_graph(h);
+    return TCM_OK;
+}
+
+// One launch over a list of block requests (launch_activate_list).
+tcm_status run_activation(tcm_handle* h, const std::vector<long long>& keys, const std::vector<int>& kshot,
+                          const std::vector<unsigned>& kloc, const std::vector<int>& kpin,
+                          const std::vector<int>& krange) {
+    const size_t nk = keys.size();
+    if (nk == 0) return TCM_OK;
+    const size_t need = nk * (sizeof(long long) + 4 * sizeof(int));
+    if (need > h->d_act_req_cap) {
+        if (h->d_act_req) (void)hipFree(h->d_act_req);
+        h->d_act_req = nullptr;
+        h->d_act_req_cap = 0;
+        if (hipMalloc(&h->d_act_req, need) != hipSuccess) {
+            (void)hipGetLastError();
+            return set_err(h, TCM_E_NOMEM, "no device memory for the source activation list");
+        }
+        h->d_act_req_cap = need;
+    }
+    std::vector<char> req(need);
+    memcpy(req.data(), keys.data(), nk * sizeof(long long));
+    memcpy(req.data() + nk * 8, kshot.data(), nk * 4);
+    memcpy(req.data() + nk * 12, kloc.data(), nk * 4);
+    memcpy(req.data() + nk * 16, kpin.data(), nk * 4);
+    memcpy(req.data() + nk * 20, krange.data(), nk * 4);
+    char* d = (char*)h->d_act_req;
+    HIP_OR_FAIL(h, hipMemcpyAsync(d, req.data(), need, hipMemcpyHostToDevice, h->stream));
+    HIP_OR_FAIL(h, launch_activate_list(h->t, (const long long*)d, (const int*)(d + nk * 8),
+                                        (const unsigned*)(d + nk * 12), (const int*)(d + nk * 16),
+                                        (const int*)(d + nk * 20), (int)nk, h->stream));
+    HIP_OR_FAIL(h, launch_refresh_rows(h->t, h->stream));
+    return sync_state(h);      // also keeps the request list alive until the launch has run
 }
 
 // Add n point sources at once ("Source insertion"): source k is at
 // xyz[3k..3k+2] of shot shots[k] with samples w[k * ns .. k * ns + ns).  The
-// source table is uploaded once, and the blocks to box (each source block,
-// and with an update interval above one the 26 blocks around it, since the
-// source reaches them before the next update) are activated by one launch,
-// each distinct block once with the largest pin among its sources.
+// table is uploaded once, and the blocks to box (each source block, and with
+// an update interval above one the 26 blocks around it, since the source
+// reaches them before the next update) are activated by one launch, each
+// distinct block once with the largest pin among its sources; blocks of
+// earlier sources only receive their new ranges.
 tcm_status add_sources(tcm_handle* h, int n, const int* shots, const int* xyz, const float* w, int ns) {
     if (n < 0 || ns < 0 || (n > 0 && (!shots || !xyz)) || (n > 0 && ns > 0 && !w))
         return set_err(h, TCM_E_ARG, "bad source samples");
@@ -756,41 +846,31 @@ tcm_status add_sources(tcm_handle* h, int n, const int* shots, const int* xyz, c
         if (st) return st;
     }
     const long long step = current_step(h);
-    if (step > 0 && !h->ckpts.empty()) ck_clear(h);   // earlier checkpoints no longer replay this run
     const size_t keep_src = h->h_src.size(), keep_w = h->h_srcw.size();
-    // blocks to box: global key -> (shot, key inside the shot, pin)
+    // block requests: global key -> (shot, key inside the shot, pin); pin -1:
+    // an earlier source block, whose range is refreshed if it is active
+    std::map<long long, size_t> at;
     std::vector<long long> keys;
-    std::vector<int> kshot, kpin, khead;
+    std::vector<int> kshot, kpin, krange;
     std::vector<unsigned> kloc;
-    auto want = [&](int shot, int bx, int by, int bz, int pin, int head) {
+    auto want = [&](int shot, int bx, int by, int bz, int pin) {
         const Shot& S = h->shots[shot];
         const unsigned tile = ((unsigned)(bz >> 2) * S.ty + (unsigned)(by >> 2)) * S.tx + (unsigned)(bx >> 2);
         const unsigned lk = tile * 64u + ((unsigned)(bz & 3) << 4) + ((unsigned)(by & 3) << 2) + (unsigned)(bx & 3);
         const long long G = S.key_base + lk;
-        for (size_t q = 0; q < keys.size(); q++)
-            if (keys[q] == G) {
-                kpin[q] = std::max(kpin[q], pin);
-                if (khead[q] < 0) khead[q] = head;
-                return;
-            }
+        auto it = at.find(G);
+        if (it != at.end()) {
+            kpin[it->second] = std::max(kpin[it->second], pin);
+            return;
+        }
+        at[G] = keys.size();
         keys.push_back(G);
         kshot.push_back(shot);
         kloc.push_back(lk);
         kpin.push_back(pin);
-        khead.push_back(head);
+        krange.push_back(-1);
     };
-    // sources of one block form a chain in insertion order (Src::next) that
-    // the block's slot points to: the stencil visits only its own sources
-    auto chain = [&](long long G, int idx) -> int {      // returns the block's first source
-        auto it = h->src_chain.find(G);
-        if (it == h->src_chain.end()) {
-            h->src_chain[G] = {idx, idx};
-            return idx;
-        }
-        h->h_src[(size_t)it->second.second].next = idx;
-        it->second.second = idx;
-        return it->second.first;
-    };
+    std::map<long long, std::pair<int, unsigned>> key_shot;    // source keys of this call: shot, local key
     for (int k = 0; k < n; k++) {
         const Shot& S = h->shots[shots[k]];
         const int ix = xyz[3 * k], iy = xyz[3 * k + 1], iz = xyz[3 * k + 2];
@@ -803,101 +883,73 @@ tcm_status add_sources(tcm_handle* h, int n, const int* shots, const int* xyz, c
             const unsigned tile = ((unsigned)(bz >> 2) * S.ty + (unsigned)(by >> 2)) * S.tx + (unsigned)(bx >> 2);
             e.key = S.key_base + tile * 64u + ((unsigned)(bz & 3) << 4) + ((unsigned)(by & 3) << 2) + (unsigned)(bx & 3);
             e.local = ((iz & 7) * 8 + (iy & 7)) * 8 + (ix & 7);
-        }
-        e.t0 = (int)step;
-        e.ns = ns;
-        e.next = -1;
-        e.w_off = (long long)h->h_srcw.size();
-        h->h_srcw.insert(h->h_srcw.end(), w + (size_t)k * ns, w + (size_t)(k + 1) * ns);
-        h->h_src.push_back(e);
-        if (h->engine == TCM_ENGINE_BLOCKS) {
-            const int bx = ix >> 3, by = iy >> 3, bz = iz >> 3;
-            const int head = chain(e.key, (int)h->h_src.size() - 1);
-            want(shots[k], bx, by, bz, (int)(step + ns), head);
+            want(shots[k], bx, by, bz, (int)(step + ns));
             if (h->t.interval > 1) {
                 for (int d = 0; d < 27; d++) {
                     const int x2 = bx + d % 3 - 1, y2 = by + (d / 3) % 3 - 1, z2 = bz + d / 9 - 1;
                     if (d == 13 || x2 < 0 || y2 < 0 || z2 < 0 || x2 >= S.bx || y2 >= S.by || z2 >= S.bz) continue;
-                    want(shots[k], x2, y2, z2, 0, -1);
+                    want(shots[k], x2, y2, z2, 0);
                 }
             }
         }
+        e.t0 = (int)step;
+        e.ns = ns;
+        e.pad = 0;
+        e.w_off = (long long)h->h_srcw.size();
+        h->h_srcw.insert(h->h_srcw.end(), w + (size_t)k * ns, w + (size_t)(k + 1) * ns);
+        h->h_src.push_back(e);
     }
-    auto undo = [&]() {
+    std::map<long long, SrcKeyInfo> ranges;
+    st = upload_sources(h, &ranges);
+    if (st) {
         h->h_src.resize(keep_src);
         h->h_srcw.resize(keep_w);
-        h->t.nsrc = (int)h->h_src.size();
-        rebuild_chains(h);
-    };
-    // upload the source tables
-    if (h->h_src.size() > h->d_src_cap) {
-        size_t c = std::max<size_t>(16, h->d_src_cap * 2);
-        while (c < h->h_src.size()) c *= 2;
-        Src* d = nullptr;
-        if (dalloc(h, &d, c) != hipSuccess) { undo(); return dev_fail(h, hipErrorOutOfMemory, "source table"); }
-        dfree(h, h->d_src);
-        h->d_src = d;
-        h->d_src_cap = c;
+        std::map<long long, SrcKeyInfo> r2;
+        (void)upload_sources(h, &r2);
+        return st;
     }
-    if (h->h_srcw.size() > h->d_srcw_cap) {
-        size_t c = std::max<size_t>(1024, h->d_srcw_cap * 2);
-        while (c < h->h_srcw.size()) c *= 2;
-        float* d = nullptr;
-        if (dalloc(h, &d, c) != hipSuccess) { undo(); return dev_fail(h, hipErrorOutOfMemory, "source samples"); }
-        dfree(h, h->d_srcw);
-        h->d_srcw = d;
-        h->d_srcw_cap = c;
-    }
-    HIP_OR_FAIL(h, hipMemcpyAsync(h->d_src, h->h_src.data(), h->h_src.size() * sizeof(Src), hipMemcpyHostToDevice, h->stream));
-    if (!h->h_srcw.empty())
-        HIP_OR_FAIL(h, hipMemcpyAsync(h->d_srcw, h->h_srcw.data(), h->h_srcw.size() * sizeof(float), hipMemcpyHostToDevice, h->stream));
-    h->t.src = h->d_src;
-    h->t.srcw = h->d_srcw;
-    h->t.nsrc = (int)h->h_src.size();
-    drop_graph(h);
-    if (h->engine != TCM_ENGINE_BLOCKS) {
-        HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
-        return TCM_OK;
-    }
-    // one activation launch for all blocks, then the rows of the whole list
-    const size_t nk = keys.size();
-    const size_t need = nk * (sizeof(long long) + 4 * sizeof(int));
-    if (need > h->d_act_req_cap) {
-        if (h->d_act_req) (void)hipFree(h->d_act_req);
-        h->d_act_req = nullptr;
-        h->d_act_req_cap = 0;
-        if (hipMalloc(&h->d_act_req, need) != hipSuccess) {
-            (void)hipGetLastError();
-            undo();
-            return set_err(h, TCM_E_NOMEM, "no device memory for the source activation list");
+    if (h->engine != TCM_ENGINE_BLOCKS) return TCM_OK;
+    // every source block receives its (possibly moved) range
+    auto packed = [](const SrcKeyInfo& r) { return (r.count << 24) | r.first; };
+    for (const auto& kv : ranges) {
+        auto it = at.find(kv.first);
+        if (it != at.end()) {
+            krange[it->second] = packed(kv.second);
+        } else {                                    // an earlier source's block: refresh only
+            at[kv.first] = keys.size();
+            keys.push_back(kv.first);
+            kshot.push_back(0);
+            kloc.push_back(0);
+            kpin.push_back(-1);
+            krange.push_back(packed(kv.second));
         }
-        h->d_act_req_cap = need;
     }
-    std::vector<char> req(need);
-    memcpy(req.data(), keys.data(), nk * sizeof(long long));
-    memcpy(req.data() + nk * 8, kshot.data(), nk * 4);
-    memcpy(req.data() + nk * 12, kloc.data(), nk * 4);
-    memcpy(req.data() + nk * 16, kpin.data(), nk * 4);
-    memcpy(req.data() + nk * 20, khead.data(), nk * 4);
-    char* d = (char*)h->d_act_req;
-    HIP_OR_FAIL(h, hipMemcpyAsync(d, req.data(), need, hipMemcpyHostToDevice, h->stream));
-    HIP_OR_FAIL(h, launch_activate_list(h->t, (const long long*)d, (const int*)(d + nk * 8),
-                                        (const unsigned*)(d + nk * 12), (const int*)(d + nk * 16),
-                                        (const int*)(d + nk * 20), (int)nk, h->stream));
-    HIP_OR_FAIL(h, launch_refresh_rows(h->t, h->stream));
-    st = sync_state(h);       // also keeps the request list alive until the launch has run
+    st = run_activation(h, keys, kshot, kloc, kpin, krange);
     if (st) return st;
     if (h->h_state->add_error) {
         // no slot for some block: the sources are not added (blocks boxed so
         // far stay, as zero blocks, and are released when they stay quiet);
-        // the table is cut back and no slot keeps a dropped source
+        // the table is cut back, earlier source blocks get their ranges back
+        // and the blocks of only the dropped sources lose pin and range
         HIP_OR_FAIL(h, hipMemsetAsync(&h->t.st->add_error, 0, sizeof(int), h->stream));
-        undo();
-        if (!h->h_src.empty())
-            HIP_OR_FAIL(h, hipMemcpyAsync(h->d_src, h->h_src.data(), h->h_src.size() * sizeof(Src),
-                                          hipMemcpyHostToDevice, h->stream));
-        HIP_OR_FAIL(h, launch_drop_sources(h->t, (int)h->h_src.size(), h->stream));
-        HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+        h->h_src.resize(keep_src);
+        h->h_srcw.resize(keep_w);
+        std::map<long long, SrcKeyInfo> back;
+        st = upload_sources(h, &back);
+        if (st) return st;
+        std::vector<long long> k2;
+        std::vector<int> s2, p2, r2;
+        std::vector<unsigned> l2;
+        for (const auto& kv : ranges) {
+            auto it = back.find(kv.first);
+            k2.push_back(kv.first);
+            s2.push_back(0);
+            l2.push_back(0);
+            p2.push_back(it == back.end() ? -2 : -1);
+            r2.push_back(it == back.end() ? -1 : packed(it->second));
+        }
+        st = run_activation(h, k2, s2, l2, p2, r2);
+        if (st) return st;
         return set_err(h, TCM_E_POOL, "no free pool slot for a source block");
     }
     return TCM_OK;
@@ -1327,7 +1379,6 @@ tcm_status tcm_reset(tcm_handle* h) {
     h->rec_xyz.clear();
     h->rec_shot.clear();
     h->h_src.clear();
-    h->src_chain.clear();
     h->h_srcw.clear();
     h->t.nsrc = 0;
     h->h_rec.clear();

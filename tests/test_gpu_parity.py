@@ -634,11 +634,12 @@ def test_random_configurations_match_cpu_tcm(seed):
         cap = max(64, t.stats()["peak_active"] + int(rng.integers(0, 20)))
         t = oracle_run(cap)
     announce(f"random {seed}: shape {shape} levels {tr:g}/{float(ret):g} k {interval} shutdown {sd} "
-             f"rel {rel} tile {tile}x{per_wave} uniform {unif} pool {cap or 'auto'}")
+             f"rel {rel} tile {tile}x{per_wave} uniform {unif} pool {cap or 'auto'} three-pass {seed % 4 == 1}")
+    three = seed % 4 == 1      # where the two-launch update applies, also run the three-pass one
     sim = tcm.Simulation(shape, 1.0, dt, c, trig, ret, shutdown_steps=sd, shutdown_alpha=float(alpha),
                          trigger_rel=float(trel), retire_rel=float(rrel), trigger_interval=interval,
                          blocks_per_wg=tile, blocks_per_wave=per_wave, uniform_c2=unif, timing=bool(seed % 2),
-                         pool_bytes=cap * 6144)
+                         pool_bytes=cap * 6144, three_pass_update=three)
     for xyz, w in srcs:
         sim.add_source(xyz, w)
     sim.step(n1)
@@ -649,3 +650,40 @@ def test_random_configurations_match_cpu_tcm(seed):
     assert g["step"] == o["step"] and g["active_blocks"] == o["active"]
     assert g["activations"] == o["activations"] and g["retirements"] == o["retirements"]
     assert g["cell_updates"] == o["updates"]
+
+
+@pytest.mark.parametrize("levels", [(0.0, 0.0), (3e-3, 3e-3), (1e-3, 1e-4)])
+def test_two_launch_update_equals_three_pass_every_step(levels):
+    """The two-launch activation update (one slot per key, constant levels,
+    update every step) and the three-pass update give the same active counts
+    and work every step and the same fields, with a batch of two shots, a
+    source added mid-run, receivers, and a snapshot restored mid-run."""
+    announce(f"two-launch vs three-pass update {levels}")
+    shapes = [(70, 45, 60), (33, 81, 24)]
+    media = [ti.random_media(s, seed=50 + i, cmin=0.5, cmax=1.0) for i, s in enumerate(shapes)]
+    w = ti.ricker(0.12, 0.5).w32
+    trig, ret = (np.float32(v) for v in levels)
+    sims = [tcm.Simulation(shapes, 1.0, 0.5, media, trig, ret, three_pass_update=tp) for tp in (False, True)]
+    for sim in sims:
+        sim.add_source((35, 20, 30), w, shot=0)
+        sim.add_source((16, 40, 12), -0.5 * w, shot=1)
+        sim.set_receivers([(35, 25, 30), (3, 3, 3), (16, 60, 12)], shots=[0, 0, 1])
+    for k in range(150):
+        for sim in sims:
+            if k == 60:
+                sim.add_source((5, 5, 5), w, shot=1)
+            sim.step(1)
+        a, b = sims[0].stats(), sims[1].stats()
+        for key in ("step", "active_blocks", "activations", "retirements", "cell_updates", "peak_active_blocks"):
+            assert a[key] == b[key], (k, key)
+        if k == 90:
+            snaps = [sim.snapshot() for sim in sims]
+    for sim, snap in zip(sims, snaps):
+        ref = (sim.read(0, shot=1), sim.read_traces())
+        sim.restore(snap)
+        sim.step(59)
+        assert values_equal(sim.read(0, shot=1), ref[0]) and values_equal(sim.read_traces(), ref[1])
+    for shot in (0, 1):
+        assert values_equal(sims[0].read(0, shot=shot), sims[1].read(0, shot=shot))
+        assert values_equal(sims[0].read(1, shot=shot), sims[1].read(1, shot=shot))
+    assert values_equal(sims[0].read_traces(), sims[1].read_traces())
