@@ -55,7 +55,8 @@ typedef enum {
     TCM_E_RANGE = -4,   /* source, receiver or read box outside the domain */
     TCM_E_DEVICE = -5,  /* HIP runtime error; the handle is poisoned (destroy only) */
     TCM_E_STATE = -6,   /* call not valid in the handle's state */
-    TCM_E_NOMEM = -7    /* device or host allocation failed */
+    TCM_E_NOMEM = -7,   /* device or host allocation failed */
+    TCM_E_NONFINITE = -8 /* a field value became NaN or infinite; sticky, like TCM_E_POOL */
 } tcm_status;
 
 enum { TCM_MEDIA_DENSE = 0, TCM_MEDIA_LAYERED = 1, TCM_MEDIA_LATTICE = 2 };
@@ -65,10 +66,12 @@ enum {
     TCM_FLAG_NO_GRAPH = 2,  /* launch each step's kernels directly (no hipGraph replay) */
     TCM_FLAG_NO_UNIFORM_C2 = 4, /* always read the per-node C2 plane (no scalar C2 for
                                    blocks whose C2 is uniform, "Media" hybrid engine) */
-    TCM_FLAG_THREE_PASS_UPDATE = 8  /* run the activation update as plan, allocation and
+    TCM_FLAG_THREE_PASS_UPDATE = 8, /* run the activation update as plan, allocation and
                                    compaction launches even where the two-launch update applies
                                    (constant levels, update every step, no shutdown, one pool
                                    slot per block key, at most 2^20 keys); the results are the same */
+    TCM_FLAG_DEBUG_CHECKS = 16  /* tcm_step runs tcm_check at its end and returns TCM_E_STATE
+                                   when a table invariant is violated */
 };
 
 /* Run configuration.  Zero-initialise, then set the fields. */
@@ -141,7 +144,7 @@ typedef struct {
     int64_t activations;
     int64_t retirements;
     int64_t cell_updates;         /* in-domain nodes updated so far (dense: nodes x steps) */
-    int32_t error;                /* sticky device error (TCM_E_POOL) or 0 */
+    int32_t error;                /* sticky device error (TCM_E_POOL, TCM_E_NONFINITE) or 0 */
     int32_t nshots;
     double  stencil_ms;           /* TCM_FLAG_TIMING: summed block-stencil kernel time */
     int64_t stencil_launches;     /* TCM_FLAG_TIMING: launches summed in stencil_ms */
@@ -194,10 +197,19 @@ tcm_status tcm_add_source_shot(tcm_handle* h, int32_t shot, int32_t ix, int32_t 
 
 /* Advance nsteps leapfrog steps (eq.(3)) with block activation and release
  * every step ("Updating active cells", "Time stepping").  Returns TCM_E_POOL if
- * a step needed more slots than the pool has: that step's phi^{n+1} is kept
- * (the level advances to n+1 with the old active set) and later steps do
- * nothing; reads and stats stay valid. */
+ * a step needed more slots than the pool has, TCM_E_NONFINITE if a step
+ * produced a NaN or infinite value (the stencil checks every value it
+ * writes): that step's phi^{n+1} is kept (the level advances to n+1 with the
+ * old active set) and later steps do nothing; reads and stats stay valid. */
 tcm_status tcm_step(tcm_handle* h, int32_t nsteps);
+
+/* Check the block tables between two steps (Table 1's Cell2box / Box2cell
+ * bijection, the active list holding each active block once, its neighbour
+ * rows, and the current-set bitmap of the two-launch update); *violations
+ * receives the number of violations (0 for a consistent state).
+ * Synchronous; allocates a scratch array of one int per slot.  TCM_E_STATE
+ * for the dense engine. */
+tcm_status tcm_check(tcm_handle* h, int64_t* violations);
 
 /* Copy phi^n (which = 0) or phi^{n-1} (which = 1) of the box
  * [x0,x0+sx)x[y0,y0+sy)x[z0,z0+sz) of shot 0 into out (sx*sy*sz floats,

@@ -9,11 +9,12 @@ LIB_PATH = os.path.join(HERE, "libtcm.so")
 
 TCM_OK, TCM_E_ARG, TCM_E_CFL, TCM_E_POOL, TCM_E_RANGE, TCM_E_DEVICE, TCM_E_STATE, TCM_E_NOMEM = \
     0, -1, -2, -3, -4, -5, -6, -7
+TCM_E_NONFINITE = -8
 STATUS_NAMES = {0: "TCM_OK", -1: "TCM_E_ARG", -2: "TCM_E_CFL", -3: "TCM_E_POOL", -4: "TCM_E_RANGE",
-                -5: "TCM_E_DEVICE", -6: "TCM_E_STATE", -7: "TCM_E_NOMEM"}
+                -5: "TCM_E_DEVICE", -6: "TCM_E_STATE", -7: "TCM_E_NOMEM", -8: "TCM_E_NONFINITE"}
 MEDIA_DENSE, MEDIA_LAYERED, MEDIA_LATTICE = 0, 1, 2
 ENGINE_BLOCKS, ENGINE_DENSE = 0, 1
-FLAG_TIMING, FLAG_NO_GRAPH, FLAG_NO_UNIFORM_C2, FLAG_THREE_PASS_UPDATE = 1, 2, 4, 8
+FLAG_TIMING, FLAG_NO_GRAPH, FLAG_NO_UNIFORM_C2, FLAG_THREE_PASS_UPDATE, FLAG_DEBUG_CHECKS = 1, 2, 4, 8, 16
 
 # every symbol include/tcm.h declares
 EXPORTS = [
@@ -21,7 +22,7 @@ EXPORTS = [
     "tcm_read", "tcm_read_shot", "tcm_set_receivers", "tcm_read_traces", "tcm_adjoint",
     "tcm_reset", "tcm_stats", "tcm_destroy", "tcm_last_error", "tcm_version", "tcm_autotune",
     "tcm_set_launch", "tcm_snapshot", "tcm_restore", "tcm_snapshot_free", "tcm_hbm_probe",
-    "tcm_read_noalloc",
+    "tcm_read_noalloc", "tcm_check",
 ]
 
 
@@ -117,6 +118,7 @@ def lib():
         L.tcm_set_launch.argtypes = [H, I, I, I, I]
         L.tcm_hbm_probe.argtypes = [P, P, C.c_uint64, I, I, I, P, F(C.c_float)]
         L.tcm_stats.argtypes = [H, F(Stats)]
+        L.tcm_check.argtypes = [H, F(C.c_int64)]
         L.tcm_destroy.argtypes = [H]
         L.tcm_destroy.restype = None
         L.tcm_last_error.argtypes = [H]

@@ -23,6 +23,8 @@ constexpr int SLOT = 3 * BV;                 // floats of pool per slot
 constexpr int PLANE_C2 = 2;                  // plane kinds: 0, 1 (phi levels), 2 (C2)
 constexpr int EMPTY = -1;
 constexpr int CLAIMED = -2;
+constexpr int ERR_POOL = -3;       // sticky device errors (TCM_E_POOL, TCM_E_NONFINITE)
+constexpr int ERR_NONFINITE = -8;
 constexpr int KEEP_BIT = 64;
 constexpr int HOT_BIT = 128;       // any |phi| of either level above the trigger
 
@@ -67,6 +69,7 @@ struct DevState {
     int fast_par;                    // two-launch update: parity of the next active set (k_fast_plan)
     int n_gblocks;                   // adjoint: gradient blocks handed out (first gradient term of a key)
     int grad_error;                  // adjoint: a gradient block or lap-store entry was out of range
+    int nf_step;                     // n + 1 for the first step n that wrote a non-finite value, else 0
 };
 
 struct Src {
@@ -201,6 +204,9 @@ hipError_t launch_activate_list(const Tables& t, const long long* keys, const in
                                 const unsigned* local_keys, const int* pins, const int* heads, int n,
                                 hipStream_t s);
 hipError_t launch_refresh_rows(const Tables& t, hipStream_t s);
+// table invariants between steps: mark = cap zeroed ints, bad = two zeroed
+// counters (violations, keys with a slot)
+hipError_t launch_check(const Tables& t, int* mark, unsigned long long* bad, hipStream_t s);
 hipError_t launch_read(const Tables& t, int shot, int which, int x0, int y0, int z0, int sx,
                        int sy, int sz, float* out, hipStream_t s);
 hipError_t launch_media_c2(const Shot& shot, const Shot* dshot, double dt, double dx, float* c2,

@@ -48,6 +48,18 @@ __device__ __forceinline__ float* plane_of(const Tables& t, long long slot, int 
 // --------------------------------------------------------------------------
 // small helpers
 // --------------------------------------------------------------------------
+// First error of the run and the step it happened in (sticky; the step's
+// phi^{n+1} is kept).
+__device__ __forceinline__ void report_error(DevState* st, int code, int step) {
+    if (atomicCAS(&st->error, 0, code) == 0) st->err_step = step;
+}
+// A non-finite value written by the stencil of step n sets nf_step = n + 1
+// (only the stencil writes it, so every other workgroup of that launch still
+// runs).  The step completes with its old active set, like a pool failure;
+// later steps do nothing.
+__device__ __forceinline__ bool halted_before(const DevState* st, int n) {
+    return st->error || (st->nf_step && st->nf_step != n + 1);
+}
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
 // Read-only (for the reading kernel) tables addressed uniformly by a wave are
@@ -206,7 +218,7 @@ __global__ void k_init_tables(Tables t, long long nkeys) {
     if (g0 == 0) {
         DevState* st = t.st;
         st->step = 0; st->n_act = 0; st->n_new = 0; st->n_ret = 0;
-        st->free_cnt = t.cap; st->error = 0; st->err_step = -1; st->emit = 0;
+        st->free_cnt = t.cap; st->error = 0; st->err_step = -1; st->emit = 0; st->nf_step = 0;
         st->peak_act = 0; st->done_wgs = 0; st->add_error = 0; st->n_dec = 0;
         st->cells_cur = 0; st->updates = 0; st->activations = 0; st->retirements = 0;
         st->cells_cur_u = 0; st->updates_u = 0; st->decays = 0;
@@ -254,8 +266,8 @@ __global__ __launch_bounds__(64 * W) void k_block_step(Tables t) {
     // workgroup barrier per iteration separates writes from every read
     __shared__ __align__(16) float lds[2][B][TILE_FLOATS];
     const DevState* st = t.st;
-    if (st->error) return;
     const int n = st->step;
+    if (halted_before(st, n)) return;
     const int nact = st->n_act;
     const int p = n & 1;
     const int lane = lane_id();
@@ -461,16 +473,21 @@ __global__ __launch_bounds__(64 * W) void k_block_step(Tables t) {
             }
 #pragma unroll
             for (int z = 0; z < 8; z++) __builtin_nontemporal_store(nv[z], &out_p[q][z * 64 + lane]);
+            // column maxima of |phi^{n+1}| (NaN if the column holds one) and |phi^n|
+            float colmax = fabsf(nv[0]), curmax = fabsf(cur[q][0]);
+#pragma unroll
+            for (int z = 1; z < 8; z++) {
+                colmax = __builtin_elementwise_maximum(colmax, fabsf(nv[z]));
+                curmax = fmaxf(curmax, fabsf(cur[q][z]));
+            }
+            // a value that is not finite fails every level comparison, so its
+            // block would just be released and the value lost: stop the run
+            // after this step instead
+            if (__ballot(!(colmax <= 3.402823466e38f)) && lane == 0) atomicCAS(&t.st->nf_step, 0, n + 1);
 
             if constexpr (ADAPT) {
                 // per-block maxima (Table 1 Max_cell_val, per face and whole block);
                 // the plan compares them with this step's levels
-                float colmax = 0.f, curmax = 0.f;
-#pragma unroll
-                for (int z = 0; z < 8; z++) {
-                    colmax = fmaxf(colmax, fabsf(nv[z]));
-                    curmax = fmaxf(curmax, fabsf(cur[q][z]));
-                }
                 float v[8] = {x == 0 ? colmax : 0.f, x == 7 ? colmax : 0.f, y == 0 ? colmax : 0.f,
                               y == 7 ? colmax : 0.f, fabsf(nv[0]), fabsf(nv[7]), colmax, curmax};
                 for (int o = 32; o > 0; o >>= 1) {
@@ -484,14 +501,8 @@ __global__ __launch_bounds__(64 * W) void k_block_step(Tables t) {
                 }
                 wave_max = fmaxf(wave_max, v[6]);
             } else {
-                bool keep = false, col = false, hot = false;
-#pragma unroll
-                for (int z = 0; z < 8; z++) {
-                    const float an = fabsf(nv[z]), ac = fabsf(cur[q][z]);
-                    keep = keep || an > ret || ac > ret;
-                    col = col || an > trig;
-                    hot = hot || ac > trig;
-                }
+                const bool keep = colmax > ret || curmax > ret;
+                const bool col = colmax > trig, hot = curmax > trig;
                 const unsigned long long bk = __ballot(keep);
                 const unsigned long long bc = __ballot(col);
                 const unsigned long long bh = __ballot(hot);
@@ -638,8 +649,8 @@ __device__ int place_slot(const Tables& t, long long G) {
 // --------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_plan(Tables t) {
     DevState* st = t.st;
-    if (st->error) return;
     const int n = st->step;
+    if (halted_before(st, n)) return;
     const int nact = st->n_act;
     const int p = n & 1;
     const int gsz = gridDim.x * blockDim.x;
@@ -667,6 +678,9 @@ __global__ __launch_bounds__(256) void k_plan(Tables t) {
                 s >= 0 ? plane_of(t, s, 1 - p)[e.local] : 0.f;
         }
     }
+    // a step that wrote a non-finite value keeps its list: the allocator
+    // and the compaction see that and only advance the step
+    if (st->nf_step) return;
 
     for (int base = blockIdx.x * blockDim.x; base < nact; base += gsz) {
         const int i = base + threadIdx.x;
@@ -820,8 +834,8 @@ hipError_t launch_plan(const Tables& t, int grid, hipStream_t s) {
 // receivers of phi^{n+1}, then advance the step counter.  One workgroup.
 __global__ __launch_bounds__(256) void k_advance(Tables t) {
     DevState* st = t.st;
-    if (st->error) return;
-    const int n = st->step;
+    const int n = st->step;                 // read by every thread before thread 0 writes it
+    if (halted_before(st, n)) return;
     const int p = n & 1;
     const int row = n - t.trace_step0;
     if (row >= 0 && row < t.trace_cap) {
@@ -858,8 +872,9 @@ hipError_t launch_advance(const Tables& t, hipStream_t s) {
 // installs free_next and clears the others.
 constexpr int SCAN1_MAX = 4;          // chunks per thread of the one-workgroup scan
 __device__ void commit_step(const Tables& t, DevState* st, int nn, int nr, int nfree, unsigned total) {
-    const int err = st->error;
-    if (!err || st->err_step == st->step) {   // the step's phi^{n+1} is complete
+    const int err = st->error || st->nf_step;
+    if (!err || (st->error ? st->err_step == st->step : st->nf_step == st->step + 1)) {
+        // the step's phi^{n+1} is complete
         st->updates += st->cells_cur;
         st->updates_u += st->cells_cur_u;
         st->step += 1;
@@ -887,7 +902,7 @@ __global__ __launch_bounds__(256) void k_pool_count(Tables t) {
     __shared__ int last;
     const int lane = lane_id();
     const int wid = threadIdx.x >> 6;
-    const int err0 = st->error;
+    const int err0 = st->error || st->nf_step;
     const int nn = st->n_new, nr = st->n_ret, nfree = st->free_cnt;
     const int n0 = st->step;
     // When the grid has workgroups beyond the scanning ones, those allocate
@@ -899,10 +914,7 @@ __global__ __launch_bounds__(256) void k_pool_count(Tables t) {
 
     if (!err0) {
         if (nn > nfree + nr) {
-            if (blockIdx.x == 0 && threadIdx.x == 0) {
-                st->err_step = n0;
-                st->error = -3;   // TCM_E_POOL
-            }
+            if (blockIdx.x == 0 && threadIdx.x == 0) report_error(st, ERR_POOL, n0);
         } else {
             // Only when the free slots alone cannot hold the new blocks are
             // released slots handed over directly: new block k < handoff takes
@@ -926,10 +938,7 @@ __global__ __launch_bounds__(256) void k_pool_count(Tables t) {
                 // handed over, the free slots always outnumber the new blocks)
                 const int slot = t.cap >= t.nkeys ? (int)G : k < handoff ? t.ret_slot[k] : place_slot(t, G);
                 if (slot < 0) {                      // unreachable (see above): fail the step
-                    if (lane == 0) {
-                        st->err_step = n0;
-                        st->error = -6;
-                    }
+                    if (lane == 0) report_error(st, -6, n0);
                     continue;
                 }
                 const int shot = t.new_shot[k];
@@ -1257,11 +1266,12 @@ __global__ __launch_bounds__(64 * FAST_WORDS) void k_fast_plan(Tables t) {
     __shared__ int s_nnew, s_nret;
     __shared__ unsigned s_cnt[FAST_WORDS];
     __shared__ unsigned long long s_cells[FAST_WORDS], s_cellsu[FAST_WORDS];
-    if (st->error) return;
     const int n = st->step;
+    if (halted_before(st, n)) return;
     const int p = n & 1;
     const unsigned long long* cur = fast_bm(t, p);
     unsigned long long* nxt = fast_bm(t, 1 - p);
+    const bool failed = st->nf_step != 0;     // this step wrote a non-finite value
     const int lane = lane_id();
     const int wid = threadIdx.x >> 6;
     if (blockIdx.x == 0 && threadIdx.x == 0) st->fast_par = 1 - p;   // read by k_fast_emit
@@ -1273,6 +1283,15 @@ __global__ __launch_bounds__(64 * FAST_WORDS) void k_fast_plan(Tables t) {
             const bool on = (cur[e.key >> 6] >> (e.key & 63)) & 1ull;
             t.traces[(size_t)row * t.nrec + r] = on ? plane_of(t, e.key, 1 - p)[e.local] : 0.f;
         }
+    }
+    if (failed) {
+        // the step keeps its list: the next set is the current one (the
+        // emit only advances the step)
+        for (int c = blockIdx.x; c < t.nfchunks; c += gridDim.x) {
+            const long long w = (long long)c * FAST_WORDS + wid;
+            if (lane == 0 && w < t.nwords) nxt[w] = cur[w];
+        }
+        return;
     }
     const float trig = t.trigger;
     (void)trig;
@@ -1371,7 +1390,17 @@ __global__ __launch_bounds__(64 * FAST_WORDS) void k_fast_emit(Tables t) {
     DevState* st = t.st;
     __shared__ unsigned long long s_red[FAST_WORDS][6];
     __shared__ unsigned s_word[FAST_WORDS];
-    if (st->error) return;
+    if (st->error || st->nf_step) {
+        // the step that wrote a non-finite value completes (its phi^{n+1} is
+        // kept) with the same list; thread 0 of workgroup 0 is the only
+        // reader and writer of the step counter in this launch
+        if (blockIdx.x == 0 && threadIdx.x == 0 && !st->error && st->nf_step == st->step + 1) {
+            st->updates += st->cells_cur;
+            st->updates_u += st->cells_cur_u;
+            st->step += 1;
+        }
+        return;
+    }
     const int par = st->fast_par;
     const unsigned long long* nxt = fast_bm(t, par);
     unsigned long long* old = fast_bm(t, 1 - par);
@@ -1467,6 +1496,84 @@ hipError_t launch_fast_update(const Tables& t, int grid, hipStream_t s) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_fast_emit, dim3(grid), dim3(64 * FAST_WORDS), 0, s, t);
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// Table invariants between two steps (tcm_check): the active list, the
+// block table (Table 1 Cell2box), the slots' keys (Box2cell) and the
+// current-set bitmap of the two-launch update agree; every listed slot is
+// listed once; every neighbour slot in a row is that neighbour's slot.
+// Violations are counted in bad[0]; bad[1] counts keys with a slot.
+// --------------------------------------------------------------------------
+__global__ void k_check_list(Tables t, int* mark, unsigned long long* bad) {
+    const DevState* st = t.st;
+    const int nact = min(st->n_act, t.cap);     // a longer list is counted on the host
+    const int p = st->step & 1;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nact;
+         i += (long long)gridDim.x * blockDim.x) {
+        unsigned long long nbad = 0;
+        const int s = t.act_slot[i];
+        const int shot = t.act_shot[i];
+        if (s < 0 || s >= t.cap || shot < 0 || shot >= t.nshots) {
+            atomicAdd(bad, 1ull);
+            continue;
+        }
+        const Shot& S = t.shots[shot];
+        const long long G = S.key_base + (long long)t.act_key[i];
+        if (G < 0 || G >= t.nkeys) {
+            atomicAdd(bad, 1ull);
+            continue;
+        }
+        atomicAdd(&mark[s], 1);
+        nbad += t.cell2box[G] != s;
+        nbad += t.slot_key[s] != G;
+        nbad += t.rows[8 * (size_t)i] != s;
+        nbad += t.rows[8 * (size_t)i + 7] != (int)G;
+        int bx, by, bz;
+        key_to_block(S, t.act_key[i], bx, by, bz);
+        nbad += !(bx < S.bx && by < S.by && bz < S.bz);
+        for (int d = 0; d < 6; d++) {
+            const long long nk = neighbour_key(S, bx, by, bz, d);
+            nbad += t.rows[8 * (size_t)i + 1 + d] != (nk >= 0 ? t.cell2box[nk] : EMPTY);
+        }
+        if (t.fast) nbad += !((fast_bm(t, p)[G >> 6] >> (G & 63)) & 1ull);
+        if (nbad) atomicAdd(bad, nbad);
+    }
+}
+
+__global__ void k_check_keys(Tables t, const int* mark, unsigned long long* bad) {
+    const int p = t.st->step & 1;
+    for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < t.nkeys;
+         k += (long long)gridDim.x * blockDim.x) {
+        const int c = t.cell2box[k];
+        unsigned long long nbad = 0;
+        if (c >= 0) {
+            atomicAdd(&bad[1], 1ull);
+            nbad += c >= t.cap || t.slot_key[c] != k || mark[c] != 1;
+        } else {
+            nbad += c != EMPTY;                  // no claim is left between steps
+        }
+        if (t.fast) nbad += ((fast_bm(t, p)[k >> 6] >> (k & 63)) & 1ull) != (unsigned long long)(c >= 0);
+        if (nbad) atomicAdd(bad, nbad);
+    }
+}
+
+__global__ void k_check_slots(Tables t, const int* mark, unsigned long long* bad) {
+    for (long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x; s < t.cap;
+         s += (long long)gridDim.x * blockDim.x) {
+        const long long k = t.slot_key[s];
+        unsigned long long nbad = mark[s] > 1;
+        if (k >= 0) nbad += k >= t.nkeys || t.cell2box[k] != (int)s;
+        else nbad += k != -1 || mark[s] != 0;
+        if (nbad) atomicAdd(bad, nbad);
+    }
+}
+
+hipError_t launch_check(const Tables& t, int* mark, unsigned long long* bad, hipStream_t s) {
+    hipLaunchKernelGGL(k_check_list, dim3(1024), dim3(256), 0, s, t, mark, bad);
+    hipLaunchKernelGGL(k_check_keys, dim3(1024), dim3(256), 0, s, t, mark, bad);
+    hipLaunchKernelGGL(k_check_slots, dim3(1024), dim3(256), 0, s, t, mark, bad);
     return hipGetLastError();
 }
 
@@ -1816,7 +1923,7 @@ hipError_t launch_receiver_c2(const Shot* shots, const int* xyz, const int* rsho
 __global__ __launch_bounds__(256) void k_grad_accum(Tables mu) {
     __shared__ unsigned long long wg_nodes;
     const DevState* st = mu.st;
-    if (st->error) return;                           // uniform: no barrier below is skipped by part of it
+    if (halted_before(st, st->step)) return;         // uniform: no barrier below is skipped by part of it
     if (threadIdx.x == 0) wg_nodes = 0;
     __syncthreads();
     const int nact = st->n_act;

@@ -1124,6 +1124,23 @@ tcm_status tcm_set_receivers(tcm_handle* h, const int32_t* xyz, const int32_t* r
     return TCM_OK;
 }
 
+// The sticky device error of a state copy: a pool or table failure, else a
+// non-finite value written by the stencil (0: none).
+int dev_error(const DevState& d) { return d.error ? d.error : d.nf_step ? ERR_NONFINITE : 0; }
+
+tcm_status report_device_error(tcm_handle* h) {
+    const DevState& d = *h->h_state;
+    const int code = dev_error(d);
+    const long long at = d.error ? (long long)d.err_step + 1 : (long long)d.nf_step;
+    if (code == ERR_NONFINITE)
+        return set_err(h, TCM_E_NONFINITE, fmt("a field value that is not finite appeared at step %lld; the "
+                                               "field is kept at that step and later steps do nothing", at));
+    if (code == ERR_POOL)
+        return set_err(h, TCM_E_POOL, fmt("pool of %d slots exhausted at step %lld; the field is kept at that step",
+                                          h->t.cap, at));
+    return set_err(h, (tcm_status)code, fmt("device error %d at step %lld", code, at));
+}
+
 tcm_status tcm_step(tcm_handle* h, int32_t nsteps) {
     tcm_status st = check_live(h);
     if (st) return st;
@@ -1159,7 +1176,7 @@ tcm_status tcm_step(tcm_handle* h, int32_t nsteps) {
 
     st = sync_state(h);
     if (st) return st;
-    if (h->h_state->error) return set_err(h, (tcm_status)h->h_state->error, "pool exhausted at an earlier step");
+    if (dev_error(*h->h_state)) return report_device_error(h);
     st = ensure_trace_capacity(h, h->h_state->step + (long long)nsteps - h->t.trace_step0);
     if (st) return st;
     // nodes stepped by this call: the lists C_0 .. C_{n-1} it runs (the list
@@ -1192,7 +1209,7 @@ tcm_status tcm_step(tcm_handle* h, int32_t nsteps) {
             if (st) return st;
             st = sync_state(h);
             if (st) return st;
-            if (h->h_state->error) break;
+            if (dev_error(*h->h_state)) break;
             cur = h->h_state->step;
             h->hstep = cur;
             left -= chunk;
@@ -1207,11 +1224,44 @@ tcm_status tcm_step(tcm_handle* h, int32_t nsteps) {
         h->stencil_cells += (long long)(h->h_state->updates - upd0);
         h->stencil_cells_u += (long long)(h->h_state->updates_u - updu0);
     }
-    if (h->h_state->error) {
-        return set_err(h, (tcm_status)h->h_state->error,
-                       fmt("pool of %d slots exhausted at step %d; the field is kept at that step",
-                           h->t.cap, h->h_state->err_step + 1));
+    if (dev_error(*h->h_state)) return report_device_error(h);
+    if (h->cfg.flags & TCM_FLAG_DEBUG_CHECKS) {
+        int64_t bad = 0;
+        st = tcm_check(h, &bad);
+        if (st) return st;
+        if (bad) return set_err(h, TCM_E_STATE, fmt("table invariants violated (%lld) after step %lld",
+                                                    (long long)bad, (long long)h->h_state->step));
     }
+    return TCM_OK;
+}
+
+tcm_status tcm_check(tcm_handle* h, int64_t* violations) {
+    tcm_status st = check_live(h);
+    if (st) return st;
+    if (!violations) return set_err(h, TCM_E_ARG, "violations is NULL");
+    if (h->engine != TCM_ENGINE_BLOCKS) return set_err(h, TCM_E_STATE, "tcm_check applies to the block engine");
+    st = sync_state(h);
+    if (st) return st;
+    int* mark = nullptr;
+    unsigned long long* bad = nullptr;
+    if (hipMalloc((void**)&mark, sizeof(int) * (size_t)h->t.cap) != hipSuccess ||
+        hipMalloc((void**)&bad, 2 * sizeof(unsigned long long)) != hipSuccess) {
+        (void)hipGetLastError();
+        if (mark) (void)hipFree(mark);
+        return set_err(h, TCM_E_NOMEM, "no device memory for the check");
+    }
+    unsigned long long res[2] = {0, 0};
+    hipError_t e = launch_fill_int(mark, h->t.cap, 0, h->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(bad, 0, sizeof res, h->stream);
+    if (e == hipSuccess) e = launch_check(h->t, mark, bad, h->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(res, bad, sizeof res, hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    (void)hipFree(mark);
+    (void)hipFree(bad);
+    if (e != hipSuccess) return dev_fail(h, e, "tcm_check");
+    const int n_act = h->h_state->n_act;
+    *violations = (int64_t)res[0] + (res[1] != (unsigned long long)n_act ? 1 : 0) +
+                  (n_act < 0 || n_act > h->t.cap ? 1 : 0);
     return TCM_OK;
 }
 
@@ -1356,7 +1406,7 @@ tcm_status tcm_stats(tcm_handle* h, tcm_stats_t* o) {
     o->decay_block_steps = (int64_t)d.decays;
     o->trigger_level = d.trig_cur;
     o->retire_level = d.ret_cur;
-    o->error = d.error;
+    o->error = dev_error(d);
     return TCM_OK;
 }
 
@@ -1506,7 +1556,7 @@ tcm_status tcm_adjoint(tcm_handle* h, const float* resid, int32_t nt, int32_t re
     if (!resid || !grad_c) return set_err(h, TCM_E_ARG, "resid and grad_c are required");
     st = sync_state(h);
     if (st) return st;
-    if (h->h_state->error) return set_err(h, TCM_E_STATE, "the forward run failed (pool)");
+    if (dev_error(*h->h_state)) return set_err(h, TCM_E_STATE, "the forward run failed (pool or non-finite field)");
     const long long cur = h->h_state->step;
     if (nt <= 0 || nt > cur) return set_err(h, TCM_E_STATE, fmt("nt = %d outside the %lld recorded steps", nt, cur));
     const int nseg = (nt + K - 1) / K;
@@ -1693,7 +1743,7 @@ tcm_status tcm_adjoint(tcm_handle* h, const float* resid, int32_t nt, int32_t re
     if (e != hipSuccess) { cleanup(); return dev_fail(h, e, "adjoint gradient"); }
     st = sync_state(a);
     if (st) { cleanup(); return set_err(h, st, "adjoint tables failed"); }
-    const int aerr = a->h_state->error, gerr = a->h_state->grad_error;
+    const int aerr = dev_error(*a->h_state), gerr = a->h_state->grad_error;
     if (timing) {
         h->af_cells += (long long)(a->h_state->updates - a_upd0);
         h->af_cells_u += (long long)(a->h_state->updates_u - a_updu0);
@@ -1710,7 +1760,8 @@ tcm_status tcm_adjoint(tcm_handle* h, const float* resid, int32_t nt, int32_t re
     st = sync_state(h);
     cleanup();
     if (st) return st;
-    if (aerr) return set_err(h, TCM_E_POOL, "pool exhausted in the adjoint field");
+    if (aerr == ERR_NONFINITE) return set_err(h, TCM_E_NONFINITE, "the adjoint field became non-finite");
+    if (aerr) return set_err(h, (tcm_status)aerr, "the adjoint field failed (pool)");
     if (gerr) return set_err(h, TCM_E_STATE, "adjoint stores overflowed (forward lists longer than the run's peak)");
     return TCM_OK;
 }
@@ -1722,7 +1773,7 @@ tcm_status tcm_autotune(tcm_handle* h, int32_t probe_steps, tcm_tuning* out) {
     if (probe_steps < 1) return set_err(h, TCM_E_ARG, "probe_steps must be >= 1");
     st = sync_state(h);
     if (st) return st;
-    if (h->h_state->error) return set_err(h, TCM_E_STATE, "the run has failed (pool)");
+    if (dev_error(*h->h_state)) return set_err(h, TCM_E_STATE, "the run has failed (pool or non-finite field)");
     st = ensure_trace_capacity(h, h->h_state->step + (long long)probe_steps - h->t.trace_step0);
     if (st) return st;
     Ckpt snap;

@@ -63,7 +63,7 @@ class Simulation:
                  device_pool=None, uniform_c2: bool = True, shutdown_steps: int = 0,
                  shutdown_alpha: float = 1.0, trigger_rel: float = 0.0, retire_rel: float = 0.0,
                  trigger_interval: int = 1, blocks_per_wg: int = 0, blocks_per_wave: int = 0,
-                 three_pass_update: bool = False):
+                 three_pass_update: bool = False, debug_checks: bool = False):
         lib = L.lib()
         cfg = L.Config()
         cfg.dx, cfg.dt = float(dx), float(dt)
@@ -72,7 +72,8 @@ class Simulation:
         cfg.engine = L.ENGINE_DENSE if engine == "dense" else L.ENGINE_BLOCKS
         cfg.flags = ((L.FLAG_TIMING if timing else 0) | (0 if graphs else L.FLAG_NO_GRAPH)
                      | (0 if uniform_c2 else L.FLAG_NO_UNIFORM_C2)
-                     | (L.FLAG_THREE_PASS_UPDATE if three_pass_update else 0))
+                     | (L.FLAG_THREE_PASS_UPDATE if three_pass_update else 0)
+                     | (L.FLAG_DEBUG_CHECKS if debug_checks else 0))
         cfg.checkpoint_every = int(checkpoint_every)
         cfg.graph_steps = int(graph_steps)
         cfg.wg_per_cu = int(wg_per_cu)
@@ -148,11 +149,16 @@ class Simulation:
                                               None if s is None else s.ctypes.data, self.nrec))
 
     def step(self, n: int):
-        """Advance n steps; raises TCMError (TCM_E_POOL) if the pool overflowed."""
+        """Advance n steps; raises TCMError (TCM_E_POOL) if the pool overflowed,
+        (TCM_E_NONFINITE) if a step wrote a NaN or infinite value."""
         self._check(L.lib().tcm_step(self._h, int(n)))
 
     def step_status(self, n: int) -> int:
         return int(L.lib().tcm_step(self._h, int(n)))
+
+    def last_error(self) -> str:
+        """Message of the handle's last failed call."""
+        return L.lib().tcm_last_error(self._h).decode()
 
     def read(self, which: int = 0, box=None, shot: int = 0, out=None) -> np.ndarray:
         """phi^n (which=0) or phi^{n-1} (which=1) of a box ((x0,y0,z0),(sx,sy,sz))
@@ -256,6 +262,12 @@ class Simulation:
     def restore(self, snap: "Snapshot"):
         """Return to the step and state of ``snap`` (taken from this handle)."""
         self._check(L.lib().tcm_restore(self._h, snap._p))
+
+    def check(self) -> int:
+        """Violations of the block-table invariants (tcm_check); 0 when consistent."""
+        v = C.c_int64(0)
+        self._check(L.lib().tcm_check(self._h, C.byref(v)))
+        return int(v.value)
 
     def stats(self) -> dict:
         s = L.Stats()

@@ -639,12 +639,15 @@ def test_random_configurations_match_cpu_tcm(seed):
     sim = tcm.Simulation(shape, 1.0, dt, c, trig, ret, shutdown_steps=sd, shutdown_alpha=float(alpha),
                          trigger_rel=float(trel), retire_rel=float(rrel), trigger_interval=interval,
                          blocks_per_wg=tile, blocks_per_wave=per_wave, uniform_c2=unif, timing=bool(seed % 2),
-                         pool_bytes=cap * 6144, three_pass_update=three)
+                         pool_bytes=cap * 6144, three_pass_update=three, debug_checks=seed % 5 == 0)
     for xyz, w in srcs:
         sim.add_source(xyz, w)
     sim.step(n1)
+    assert sim.check() == 0
     sim.add_source(*late)
+    assert sim.check() == 0
     sim.step(n2)
+    assert sim.check() == 0
     assert values_equal(sim.read(0), t.read(0)) and values_equal(sim.read(1), t.read(1))
     g, o = sim.stats(), t.stats()
     assert g["step"] == o["step"] and g["active_blocks"] == o["active"]
@@ -663,7 +666,8 @@ def test_two_launch_update_equals_three_pass_every_step(levels):
     media = [ti.random_media(s, seed=50 + i, cmin=0.5, cmax=1.0) for i, s in enumerate(shapes)]
     w = ti.ricker(0.12, 0.5).w32
     trig, ret = (np.float32(v) for v in levels)
-    sims = [tcm.Simulation(shapes, 1.0, 0.5, media, trig, ret, three_pass_update=tp) for tp in (False, True)]
+    sims = [tcm.Simulation(shapes, 1.0, 0.5, media, trig, ret, three_pass_update=tp, debug_checks=True)
+            for tp in (False, True)]
     for sim in sims:
         sim.add_source((35, 20, 30), w, shot=0)
         sim.add_source((16, 40, 12), -0.5 * w, shot=1)
@@ -687,3 +691,59 @@ def test_two_launch_update_equals_three_pass_every_step(levels):
         assert values_equal(sims[0].read(0, shot=shot), sims[1].read(0, shot=shot))
         assert values_equal(sims[0].read(1, shot=shot), sims[1].read(1, shot=shot))
     assert values_equal(sims[0].read_traces(), sims[1].read_traces())
+
+
+def block_key(shape, bx, by, bz):
+    """Key of block (bx, by, bz): blocks in 4x4x4 tiles, tiles x-fastest,
+    blocks inside a tile x-fastest (one pool slot per key when the pool holds
+    every key)."""
+    tx, ty = -(-shape[0] // 32), -(-shape[1] // 32)
+    tile = ((bz >> 2) * ty + (by >> 2)) * tx + (bx >> 2)
+    return tile * 64 + ((bz & 3) << 4) + ((by & 3) << 2) + (bx & 3)
+
+
+@pytest.mark.parametrize("path,interval,at", [("two-launch", 1, 10), ("three-pass", 1, 10),
+                                              ("interval", 8, 10), ("interval", 8, 7)])
+def test_nonfinite_value_stops_the_run(path, interval, at):
+    """A NaN written into phi^n of an active block (through a caller-owned
+    pool, one slot per key): the next step reports TCM_E_NONFINITE, completes
+    with its old active set (the NaN and its six neighbours are in phi^{n+1}),
+    and later steps do nothing; the tables stay consistent and a snapshot
+    from before the write runs on as a clean run does."""
+    import torch
+    announce(f"non-finite field: {path} update, interval {interval}, NaN at step {at}")
+    shape = (64, 48, 40)
+    nkeys = 2 * 2 * 2 * 64
+    c = ti.random_media(shape, seed=77, cmin=0.6, cmax=1.0)
+    w = ti.ricker(0.12, 0.5).w32
+    src = (20, 21, 19)
+    pool = torch.zeros(nkeys * 1536, dtype=torch.float32, device="cuda")
+    sim = tcm.Simulation(shape, 1.0, 0.5, c, 1e-6, 1e-6, device_pool=pool, pool_bytes=nkeys * 6144,
+                         three_pass_update=path == "three-pass", trigger_interval=interval)
+    clean = tcm.Simulation(shape, 1.0, 0.5, c, 1e-6, 1e-6, three_pass_update=path == "three-pass",
+                           trigger_interval=interval)
+    for s in (sim, clean):
+        s.add_source(src, w)
+        s.step(at)
+    snap = sim.snapshot()
+    key = block_key(shape, src[0] // 8, src[1] // 8, src[2] // 8)
+    local = ((src[2] % 8) * 8 + src[1] % 8) * 8 + src[0] % 8
+    pool[((at & 1) * nkeys + key) * 512 + local] = float("nan")   # phi^at of the source node
+    torch.cuda.synchronize()
+    assert sim.step_status(5) == tcm.TCM_E_NONFINITE
+    st = sim.stats()
+    assert st["step"] == at + 1 and st["error"] == tcm.TCM_E_NONFINITE
+    assert "not finite" in sim.last_error()
+    phi = sim.read(0)
+    bad = np.argwhere(np.isnan(phi))
+    want = {(src[2], src[1], src[0])} | {(src[2] + dz, src[1] + dy, src[0] + dx) for dx, dy, dz in
+                                         [(1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)]}
+    assert {tuple(int(v) for v in b) for b in bad} == want
+    assert sim.check() == 0
+    assert sim.step_status(1) == tcm.TCM_E_NONFINITE and sim.stats()["step"] == at + 1
+    sim.restore(snap)
+    assert sim.stats()["error"] == 0
+    sim.step(6)
+    clean.step(6)
+    assert values_equal(sim.read(0), clean.read(0)) and values_equal(sim.read(1), clean.read(1))
+    assert sim.stats()["active_blocks"] == clean.stats()["active_blocks"]
