@@ -534,20 +534,20 @@ def bench_c5(args, tcm):
         tsim.adjoint(resid)
         ts = tsim.stats()
         tsim.close()
-        if ts["grad_launches"] > 0 and ts["grad_ms"] > 0:
-            # per adjoint step three kernels stream: the recomputed forward step
-            # (16 B per node, 12 B with a scalar C2, + 4 B of L u written), the
-            # adjoint field's step (16 B / 12 B per node) and the gradient term
-            # (mu, L u, partial gradient read and written: 16 B per term node)
+        nadj = ts["adjoint_field_launches"]
+        if nadj > 0 and ts["adjoint_field_ms"] > 0:
+            # per adjoint step two kernels stream: the recomputed forward step
+            # (16 B per node, 12 B with a scalar C2, + 4 B of L u written) and
+            # the adjoint field's step (16 B / 12 B per node), which also adds
+            # the gradient term where the forward block was active (L u read,
+            # FP32 partial gradient read and written: 12 B per term node)
             kern = {
                 "recompute": (20 * ts["recompute_cells"] - 4 * ts["recompute_cells_uniform"],
                               ts["recompute_ms"], ts["recompute_launches"],
                               "k_block_step (recomputed forward step, also storing L u)"),
-                "adjoint_field": (16 * ts["adjoint_field_cells"] - 4 * ts["adjoint_field_cells_uniform"],
-                                  ts["adjoint_field_ms"], ts["adjoint_field_launches"],
-                                  "k_block_step (adjoint field)"),
-                "gradient": (16 * ts["grad_cells"], ts["grad_ms"], ts["grad_launches"],
-                             "k_grad_accum (gradient term mu (L u))")}
+                "adjoint_field": (16 * ts["adjoint_field_cells"] - 4 * ts["adjoint_field_cells_uniform"]
+                                  + 12 * ts["grad_cells"], ts["adjoint_field_ms"], nadj,
+                                  "k_block_step (adjoint field, with the gradient term mu (L u))")}
             per = {k: {"kernel": v[3], "avg_launch_us": round(v[1] * 1e3 / max(v[2], 1), 2),
                        "algorithmic_bytes_per_launch": round(v[0] / max(v[2], 1)),
                        "achieved_GBps": round(v[0] / (v[1] * 1e-3) / 1e9, 1)} for k, v in kern.items()}
@@ -559,11 +559,11 @@ def bench_c5(args, tcm):
                     "traffic": measured_traffic("k_block_step", "c5" + dom), "kernel": kname,
                     "avg_launch_us": round(ms * 1e3 / nl, 2),
                     "algorithmic_bytes_per_launch": round(alg / nl)}
-            step_bytes = sum(v[0] for v in kern.values()) / ts["grad_launches"]
+            step_bytes = sum(v[0] for v in kern.values()) / nadj
             adj_detail = {
                 "kernels": per,
-                "adjoint_field_node_fraction": round(ts["adjoint_field_cells"] / (nodes * ts["grad_launches"]), 4),
-                "gradient_term_node_fraction": round(ts["grad_cells"] / (nodes * ts["grad_launches"]), 4),
+                "adjoint_field_node_fraction": round(ts["adjoint_field_cells"] / (nodes * nadj), 4),
+                "gradient_term_node_fraction": round(ts["grad_cells"] / (nodes * nadj), 4),
                 "algorithmic_bytes_per_adjoint_step": round(step_bytes),
                 "checkpoint_bytes": ts["checkpoint_bytes"], "checkpoints": ts["checkpoints"],
                 "adjoint_bytes": ts["adjoint_bytes"], "dense_field_bytes": 4 * nodes}

@@ -154,12 +154,11 @@ typedef struct {
     int64_t decay_block_steps;    /* block-steps of the shutdown decay (eq.(6)) */
     double  trigger_level;        /* levels used by the last step (adaptive or constant) */
     double  retire_level;
-    double  grad_ms;              /* TCM_FLAG_TIMING: summed time of the gradient-term kernel of
-                                     tcm_adjoint calls (one launch per adjoint step) */
-    int64_t grad_launches;        /* TCM_FLAG_TIMING: launches summed in grad_ms */
-    int64_t grad_cells;           /* TCM_FLAG_TIMING: nodes whose gradient term mu (L u) those launches
-                                     formed (adjoint block active, forward block active a step before) */
-    double  adjoint_field_ms;     /* TCM_FLAG_TIMING: summed block-stencil time of the adjoint field */
+    int64_t grad_cells;           /* TCM_FLAG_TIMING: nodes whose gradient term mu (L u) the adjoint-field
+                                     launches formed (adjoint block active, forward block active a
+                                     step before) */
+    double  adjoint_field_ms;     /* TCM_FLAG_TIMING: summed block-stencil time of the adjoint field
+                                     (each launch also adds the step's gradient terms) */
     int64_t adjoint_field_launches;
     int64_t adjoint_field_cells;  /* nodes those adjoint-field steps updated */
     int64_t adjoint_field_cells_uniform; /* of those, nodes of blocks with a scalar C2 */

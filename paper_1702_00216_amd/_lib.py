@@ -61,7 +61,7 @@ class Stats(C.Structure):
                 ("stencil_cells", C.c_int64), ("uniform_cell_updates", C.c_int64),
                 ("stencil_cells_uniform", C.c_int64), ("decay_block_steps", C.c_int64),
                 ("trigger_level", C.c_double), ("retire_level", C.c_double),
-                ("grad_ms", C.c_double), ("grad_launches", C.c_int64), ("grad_cells", C.c_int64),
+                ("grad_cells", C.c_int64),
                 ("adjoint_field_ms", C.c_double), ("adjoint_field_launches", C.c_int64),
                 ("adjoint_field_cells", C.c_int64), ("adjoint_field_cells_uniform", C.c_int64),
                 ("recompute_ms", C.c_double), ("recompute_launches", C.c_int64),

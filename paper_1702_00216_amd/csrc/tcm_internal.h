@@ -148,8 +148,8 @@ struct Tables {
     float* rec_lap;
     int* rec_fidx;
     int rec_lapcap;
-    // Adjoint field with the gradient (null otherwise): after each stencil
-    // of the adjoint field, k_grad_accum adds mu^m (L u^{m-1}) to the FP32
+    // Adjoint field with the gradient (null otherwise): the stencil of the
+    // adjoint field that forms mu^m also adds mu^m (L u^{m-1}) to the FP32
     // gradient block of each entry's key, where g_lap / g_fidx are the store
     // of forward step m - 1.  Gradient blocks (512 FP32 partials in g_gs, 512
     // FP64 sums in g_acc) are handed out on a key's first term:
@@ -160,7 +160,7 @@ struct Tables {
     double* g_acc;
     int* g_slot;
     int g_cap;
-    unsigned long long* g_terms_wg;   // per k_grad_accum workgroup: nodes whose term it formed
+    unsigned long long* g_terms_wg;   // per stencil workgroup: nodes whose gradient term it formed
 };
 
 // The compaction works on chunks of 16 bitmap words (1024 blocks), one
@@ -176,10 +176,11 @@ hipError_t launch_init_tables(const Tables& t, long long nkeys, hipStream_t s);
 // events stamped by the dispatch itself at the kernel's start and end.
 hipError_t launch_block_step(const Tables& t, int grid, int w, int pb, hipStream_t s,
                              hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
-// Variants of the block stencil: a plain step, or a recomputed forward step
-// of the adjoint (also stores L u per entry, Tables::rec_lap).
+// Variants of the block stencil: a plain step, a recomputed forward step of
+// the adjoint (also stores L u per entry, Tables::rec_lap), or a step of the
+// adjoint field (also adds the gradient term, Tables::g_lap).
 // launch_block_step picks the variant from the Tables.
-constexpr int STEP_PLAIN = 0, STEP_RECORD = 1;
+constexpr int STEP_PLAIN = 0, STEP_RECORD = 1, STEP_GRAD = 2;
 // resident workgroups per CU of a variant (w waves per workgroup, pb blocks per wave)
 int block_step_occupancy(bool adaptive, int w, int pb, int mode = STEP_PLAIN);
 bool block_step_shape_ok(int w, int pb);
@@ -234,12 +235,9 @@ hipError_t launch_receiver_c2(const Shot* shots, const int* xyz, const int* rsho
 // into the FP64 gradient (groups of absolute step numbers, so the result does
 // not depend on the checkpoint interval)
 constexpr int GRAD_GROUP = 32;
-// the gradient term mu^m (L u^{m-1}) of one adjoint step, after the adjoint
-// field's stencil (Tables::g_*): one wave per list entry; grid at most
-// GRAD_ACCUM_MAX_WG workgroups (one node-count slot each)
+// the adjoint field's stencil, which also forms the gradient terms, runs on
+// at most GRAD_ACCUM_MAX_WG workgroups (one node-count slot each)
 constexpr int GRAD_ACCUM_MAX_WG = 4096;
-hipError_t launch_grad_accum(const Tables& mu, int grid, hipStream_t s, hipEvent_t e0 = nullptr,
-                             hipEvent_t e1 = nullptr);
 // g_acc += g_gs, g_gs = 0 over the gradient blocks handed out so far
 hipError_t launch_grad_flush(const Tables& mu, hipStream_t s);
 // out[node] = (2 / c) * gradient sum of shot 0 (0 where c = 0 or no term)

@@ -259,7 +259,8 @@ constexpr int TILE_FLOATS = TILE_COLS * TILE_COLS * BE;
 // also store L u^n of every entry and its list index per key).
 template <bool ADAPT, int W, int P, int MODE>
 __global__ __launch_bounds__(64 * W) void k_block_step(Tables t) {
-    static_assert(MODE == STEP_PLAIN || MODE == STEP_RECORD, "stencil variants");
+    static_assert(MODE == STEP_PLAIN || MODE == STEP_RECORD || MODE == STEP_GRAD, "stencil variants");
+    static_assert(MODE != STEP_GRAD || (!ADAPT && P == 1), "the adjoint field: constant levels, a block per wave");
     constexpr int B = W * P;
     static_assert(B <= 8, "a pass of the workgroup stays inside one group of 8 entries");
     // two sets of per-block tiles: iteration k writes set k & 1, so one
@@ -294,6 +295,13 @@ __global__ __launch_bounds__(64 * W) void k_block_step(Tables t) {
     auto gidx = [&](int j) { return ((((j >> lg) << 3) + xcd) << lg) + (j & (grp - 1)); };
     const float trig = t.trigger, ret = t.retire;
     float wave_max = 0.f;
+    // adjoint field: nodes whose gradient term this workgroup formed
+    __shared__ unsigned long long wg_terms;
+    unsigned long long terms = 0;
+    if constexpr (MODE == STEP_GRAD) {
+        if (threadIdx.x == 0) wg_terms = 0;
+        __syncthreads();
+    }
 
     // Each list entry has a row {slot, 6 neighbour slots, global key} written by
     // the compaction; the next rows are fetched while the current blocks are
@@ -336,6 +344,11 @@ __global__ __launch_bounds__(64 * W) void k_block_step(Tables t) {
         int slot[P], nb[P][6], G[P], pinned[P], shead[P], li[P];
         float cur[P][8], prv[P][8], k2[P][8], zlo[P], zhi[P];
         float* out_p[P];
+        // adjoint field: L u^{m-1} of the forward block (fi: its entry in the
+        // store of forward step m - 1, -1 if it was inactive), the key's
+        // FP32 partial gradient (gb: its gradient block, -1 if none yet)
+        float lu[P][8], ga[P][8];
+        int fi[P], gb[P];
 #pragma unroll
         for (int q = 0; q < P; q++) {
             const int j = wid * P + q;
@@ -361,7 +374,22 @@ __global__ __launch_bounds__(64 * W) void k_block_step(Tables t) {
         for (int q = 0; q < P; q++) {
             zlo[q] = 0.f; zhi[q] = 0.f; pinned[q] = 0; shead[q] = -1; out_p[q] = nullptr;
             fmx[q] = 0.f; fpx[q] = 0.f; fmy[q] = 0.f; fpy[q] = 0.f;
+            fi[q] = -1; gb[q] = -1;
             if (!have[q]) continue;
+            if constexpr (MODE == STEP_GRAD) {
+                fi[q] = as_scalar(t.g_fidx)[G[q]];
+                if (fi[q] >= 0) {
+                    gb[q] = as_scalar((const int*)t.g_slot)[G[q]];
+                    const float* __restrict__ lp = t.g_lap + (size_t)fi[q] * BV;
+#pragma unroll
+                    for (int z = 0; z < 8; z++) lu[q][z] = __builtin_nontemporal_load(&lp[z * 64 + lane]);
+                    if (gb[q] >= 0) {
+                        const float* __restrict__ gp = t.g_gs + (size_t)gb[q] * BV;
+#pragma unroll
+                        for (int z = 0; z < 8; z++) ga[q][z] = __builtin_nontemporal_load(&gp[z * 64 + lane]);
+                    }
+                }
+            }
             if (t.nsrc > 0) {
                 const unsigned long long ph = pin_head[slot[q]];    // {pin, first source}
                 pinned[q] = (int)(unsigned)ph;
@@ -473,6 +501,39 @@ __global__ __launch_bounds__(64 * W) void k_block_step(Tables t) {
             }
 #pragma unroll
             for (int z = 0; z < 8; z++) __builtin_nontemporal_store(nv[z], &out_p[q][z * 64 + lane]);
+            if constexpr (MODE == STEP_GRAD) {
+                // gradient term mu^m (L u^{m-1}) of the key, FP32 product and
+                // sum; a key's first term hands out its gradient block and
+                // clears the block's FP64 sum
+                if (fi[q] >= 0) {
+                    int g = gb[q];
+                    if (g < 0) {
+                        if (lane == 0) {
+                            g = atomicAdd(&t.st->n_gblocks, 1);
+                            if (g < t.g_cap) t.g_slot[G[q]] = g;
+                            else t.st->grad_error = 1;
+                        }
+                        g = __shfl(g, 0);
+                        if (g < t.g_cap) {
+                            double* __restrict__ ap = t.g_acc + (size_t)g * BV;
+#pragma unroll
+                            for (int z = 0; z < 8; z++) {
+                                ap[z * 64 + lane] = 0.0;
+                                ga[q][z] = 0.f;
+                            }
+                        }
+                    }
+                    if (g < t.g_cap) {
+                        float* __restrict__ gp = t.g_gs + (size_t)g * BV;
+#pragma unroll
+                        for (int z = 0; z < 8; z++) __builtin_nontemporal_store(ga[q][z] + nv[z] * lu[q][z], &gp[z * 64 + lane]);
+                        const Shot& S0 = t.shots[0];
+                        int bx, by, bz;
+                        key_to_block(S0, (unsigned)((long long)G[q] - S0.key_base), bx, by, bz);
+                        terms += (unsigned long long)block_cells(S0, bx, by, bz);
+                    }
+                }
+            }
             // column maxima of |phi^{n+1}| (NaN if the column holds one) and |phi^n|
             float colmax = fabsf(nv[0]), curmax = fabsf(cur[q][0]);
 #pragma unroll
@@ -525,6 +586,13 @@ __global__ __launch_bounds__(64 * W) void k_block_step(Tables t) {
     }
     if (ADAPT && lane == 0 && wave_max > 0.f)
         atomicMax((unsigned*)&t.st->maxbits, __float_as_uint(wave_max));   // non-negative floats order as integers
+    if constexpr (MODE == STEP_GRAD) {
+        // one slot per workgroup (a global atomic from every wave would
+        // serialise on one address at the kernel's end)
+        if (lane == 0 && terms) atomicAdd(&wg_terms, terms);
+        __syncthreads();
+        if (threadIdx.x == 0 && wg_terms && blockIdx.x < GRAD_ACCUM_MAX_WG) t.g_terms_wg[blockIdx.x] += wg_terms;
+    }
 }
 
 template <bool ADAPT, int W, int P, int MODE>
@@ -535,8 +603,16 @@ static int occupancy_wpm() {
     return e == hipSuccess ? nb : 0;
 }
 
+// the adjoint field's variant: constant levels, a block per wave, tiles of 4 or 8
+template <bool ADAPT, int W, int P>
+constexpr bool grad_variant() { return !ADAPT && P == 1 && (W == 4 || W == 8); }
+
 template <bool ADAPT, int W, int P>
 static int occupancy_wp(int mode) {
+    if (mode == STEP_GRAD) {
+        if constexpr (grad_variant<ADAPT, W, P>()) return occupancy_wpm<ADAPT, W, P, STEP_GRAD>();
+        return 0;
+    }
     return mode == STEP_RECORD ? occupancy_wpm<ADAPT, W, P, STEP_RECORD>() : occupancy_wpm<ADAPT, W, P, STEP_PLAIN>();
 }
 
@@ -572,8 +648,13 @@ static void launch_wpm(const Tables& t, int grid, hipStream_t s, hipEvent_t e0, 
 
 template <bool ADAPT, int W, int P>
 static void launch_wp(const Tables& t, int grid, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-    if (t.rec_lap) launch_wpm<ADAPT, W, P, STEP_RECORD>(t, grid, s, e0, e1);
-    else launch_wpm<ADAPT, W, P, STEP_PLAIN>(t, grid, s, e0, e1);
+    if (t.g_lap) {
+        if constexpr (grad_variant<ADAPT, W, P>()) launch_wpm<ADAPT, W, P, STEP_GRAD>(t, grid, s, e0, e1);
+    } else if (t.rec_lap) {
+        launch_wpm<ADAPT, W, P, STEP_RECORD>(t, grid, s, e0, e1);
+    } else {
+        launch_wpm<ADAPT, W, P, STEP_PLAIN>(t, grid, s, e0, e1);
+    }
 }
 
 template <bool ADAPT>
@@ -591,6 +672,10 @@ static void launch_adapt(const Tables& t, int grid, int w, int pb, hipStream_t s
 hipError_t launch_block_step(const Tables& t, int grid, int w, int pb, hipStream_t s, hipEvent_t e0,
                              hipEvent_t e1) {
     if (!block_step_shape_ok(w, pb)) return hipErrorInvalidValue;
+    // the adjoint field's variant exists for constant levels and tiles of 4 or
+    // 8 blocks, one per wave; its grid stays within GRAD_ACCUM_MAX_WG
+    if (t.g_lap && (t.adaptive || pb != 1 || (w != 4 && w != 8) || grid > GRAD_ACCUM_MAX_WG))
+        return hipErrorInvalidValue;
     if (t.adaptive) launch_adapt<true>(t, grid, w, pb, s, e0, e1);
     else launch_adapt<false>(t, grid, w, pb, s, e0, e1);
     return hipGetLastError();
@@ -1912,82 +1997,6 @@ hipError_t launch_receiver_c2(const Shot* shots, const int* xyz, const int* rsho
     return hipGetLastError();
 }
 
-// Gradient term of one adjoint step, right after the adjoint-field stencil
-// (before its activation update, so the list is the one the stencil ran):
-// for every entry whose forward block was active at step m - 1, add
-// mu^m (L u^{m-1}) to the key's FP32 gradient block (handed out on the key's
-// first term; its FP64 sum is cleared then).  One wave per entry, lane =
-// (x, y) column over the 8 z planes: each of mu, L u and the partial gradient
-// moves as eight 256-byte rows.  The product is FP32, the sum FP32 over the
-// step group.
-__global__ __launch_bounds__(256) void k_grad_accum(Tables mu) {
-    __shared__ unsigned long long wg_nodes;
-    const DevState* st = mu.st;
-    if (halted_before(st, st->step)) return;         // uniform: no barrier below is skipped by part of it
-    if (threadIdx.x == 0) wg_nodes = 0;
-    __syncthreads();
-    const int nact = st->n_act;
-    const int p_out = 1 - (st->step & 1);          // the stencil wrote mu^m here
-    const int lane = lane_id();
-    const int nw = (int)((gridDim.x * blockDim.x) >> 6);
-    unsigned long long nodes = 0;
-    for (int i = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6); i < nact; i += nw) {
-        const int4* rp = (const int4*)(mu.rows + 8 * (size_t)i);
-        const int slot = __builtin_amdgcn_readfirstlane(rp[0].x);
-        const int G = __builtin_amdgcn_readfirstlane(rp[1].w);
-        const int fi = __builtin_amdgcn_readfirstlane(mu.g_fidx[G]);
-        if (fi < 0) continue;                      // the forward block was inactive: no term
-        int g = __builtin_amdgcn_readfirstlane(mu.g_slot[G]);
-        const float* __restrict__ mp = plane_of(mu, slot, p_out);
-        const float* __restrict__ lp = mu.g_lap + (size_t)fi * BV;
-        float m[8], l[8], a[8];
-#pragma unroll
-        for (int z = 0; z < 8; z++) {
-            m[z] = __builtin_nontemporal_load(&mp[z * 64 + lane]);
-            l[z] = __builtin_nontemporal_load(&lp[z * 64 + lane]);
-        }
-        if (g >= 0) {
-            const float* __restrict__ gp = mu.g_gs + (size_t)g * BV;
-#pragma unroll
-            for (int z = 0; z < 8; z++) a[z] = __builtin_nontemporal_load(&gp[z * 64 + lane]);
-        } else {
-            if (lane == 0) {
-                g = atomicAdd(&mu.st->n_gblocks, 1);
-                if (g < mu.g_cap) mu.g_slot[G] = g;
-                else mu.st->grad_error = 1;
-            }
-            g = __shfl(g, 0);
-            if (g >= mu.g_cap) continue;
-            double* __restrict__ ap = mu.g_acc + (size_t)g * BV;
-#pragma unroll
-            for (int z = 0; z < 8; z++) {
-                ap[z * 64 + lane] = 0.0;
-                a[z] = 0.f;
-            }
-        }
-        float* __restrict__ gp = mu.g_gs + (size_t)g * BV;
-#pragma unroll
-        for (int z = 0; z < 8; z++) __builtin_nontemporal_store(a[z] + m[z] * l[z], &gp[z * 64 + lane]);
-        const Shot& S0 = mu.shots[0];
-        int bx, by, bz;
-        key_to_block(S0, (unsigned)((long long)G - S0.key_base), bx, by, bz);
-        nodes += (unsigned long long)block_cells(S0, bx, by, bz);
-    }
-    // node count: one slot per workgroup (a global atomic from every wave
-    // would serialise thousands of updates of one address at the kernel's end)
-    if (lane == 0 && nodes) atomicAdd(&wg_nodes, nodes);
-    __syncthreads();
-    if (threadIdx.x == 0 && wg_nodes) mu.g_terms_wg[blockIdx.x] += wg_nodes;
-}
-
-hipError_t launch_grad_accum(const Tables& mu, int grid, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-    if (grid > GRAD_ACCUM_MAX_WG) return hipErrorInvalidValue;
-    if (e0 || e1)
-        hipExtLaunchKernelGGL(k_grad_accum, dim3(grid), dim3(256), 0, s, e0, e1, 0, mu);
-    else
-        hipLaunchKernelGGL(k_grad_accum, dim3(grid), dim3(256), 0, s, mu);
-    return hipGetLastError();
-}
 
 // g_acc += g_gs, g_gs = 0 over the gradient blocks handed out so far (end of
 // a group of adjoint steps)

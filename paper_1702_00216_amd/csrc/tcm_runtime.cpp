@@ -84,8 +84,7 @@ struct tcm_handle {
     // timing (TCM_FLAG_TIMING)
     std::vector<hipEvent_t> events;
     double stencil_ms = 0.0;
-    double grad_ms = 0.0;               // gradient-term kernel of tcm_adjoint (timing flag)
-    long long grad_launches = 0, grad_cells = 0;
+    long long grad_cells = 0;           // gradient-term nodes of tcm_adjoint (timing flag)
     double af_ms = 0.0;                 // adjoint-field stencil of tcm_adjoint (timing flag)
     long long af_launches = 0, af_cells = 0, af_cells_u = 0;
     std::vector<hipEvent_t> gev;        // events around the timed gradient launches
@@ -536,17 +535,11 @@ tcm_status create_common(const tcm_config* cfg, const tcm_shot* shots, int nshot
 // Step h->hstep: the stencil, then the activation update when the step ends
 // an update interval ("Updating active cells", eq.(5)), else only the
 // receivers and the step counter.
-hipError_t enqueue_step(tcm_handle* h, hipEvent_t e0, hipEvent_t e1, hipEvent_t g0 = nullptr,
-                        hipEvent_t g1 = nullptr) {
+hipError_t enqueue_step(tcm_handle* h, hipEvent_t e0, hipEvent_t e1) {
     hipError_t e;
     const long long n = h->hstep++;
     const int k = h->t.interval > 1 ? h->t.interval : 1;
     if ((e = launch_block_step(h->t, h->grid_step, h->tile_w, h->tile_p, h->stream, e0, e1)) != hipSuccess) return e;
-    // the adjoint field: the gradient term of this step, over the list the
-    // stencil ran (before the activation update replaces it)
-    if (h->t.g_lap &&
-        (e = launch_grad_accum(h->t, std::min(GRAD_ACCUM_MAX_WG, h->ncu * 8), h->stream, g0, g1)) != hipSuccess)
-        return e;
     if ((n + 1) % k != 0) return launch_advance(h->t, h->stream);
     if (h->t.fast) return launch_fast_update(h->t, h->t.nfchunks, h->stream);
     if ((e = launch_plan(h->t, h->grid_plan, h->stream)) != hipSuccess) return e;
@@ -1365,8 +1358,6 @@ tcm_status tcm_stats(tcm_handle* h, tcm_stats_t* o) {
     o->stencil_launches = h->stencil_launches;
     o->stencil_cells = h->stencil_cells;
     o->stencil_cells_uniform = h->stencil_cells_u;
-    o->grad_ms = h->grad_ms;
-    o->grad_launches = h->grad_launches;
     o->grad_cells = h->grad_cells;
     o->adjoint_field_ms = h->af_ms;
     o->adjoint_field_launches = h->af_launches;
@@ -1445,8 +1436,6 @@ tcm_status tcm_reset(tcm_handle* h) {
     h->stencil_launches = 0;
     h->stencil_cells = 0;
     h->stencil_cells_u = 0;
-    h->grad_ms = 0.0;
-    h->grad_launches = 0;
     h->grad_cells = 0;
     h->af_ms = 0.0;
     h->af_launches = 0;
@@ -1596,7 +1585,8 @@ tcm_status tcm_adjoint(tcm_handle* h, const float* resid, int32_t nt, int32_t re
     // handle's launch shape
     a->tile_w = 4;
     a->tile_p = 1;
-    a->grid_step = std::max(8, (a->ncu * std::max(1, block_step_occupancy(false, 4, 1))) / 8 * 8);
+    a->grid_step = std::min(GRAD_ACCUM_MAX_WG,
+                            std::max(8, (a->ncu * std::max(1, block_step_occupancy(false, 4, 1, STEP_GRAD))) / 8 * 8));
     {
         // adjoint step k (k = 0..nt-1) produces mu^{nt-k}; its source sample at
         // receiver r is C2_r * resid[nt-1-k][r]; all receivers in one activation
@@ -1655,7 +1645,7 @@ tcm_status tcm_adjoint(tcm_handle* h, const float* resid, int32_t nt, int32_t re
     h->adjoint_bytes = lap_b + fidx_b + g_b + a->table_bytes + (size_t)a->t.cap * SLOT * sizeof(float);
     h->in_adjoint = true;
     const bool timing = (h->cfg.flags & TCM_FLAG_TIMING) != 0;
-    while (timing && (int)h->gev.size() < 6 * K) {
+    while (timing && (int)h->gev.size() < 4 * K) {
         hipEvent_t ev;
         if (hipEventCreate(&ev) != hipSuccess) {
             (void)hipGetLastError();
@@ -1702,8 +1692,7 @@ tcm_status tcm_adjoint(tcm_handle* h, const float* resid, int32_t nt, int32_t re
             const int q = end - m;
             a->t.g_lap = lap + (size_t)(m - 1 - s0) * (size_t)lapcap * BV;
             a->t.g_fidx = fidx + (size_t)(m - 1 - s0) * (size_t)nkeys;
-            e = enqueue_step(a, timing ? h->gev[2 * q] : nullptr, timing ? h->gev[2 * q + 1] : nullptr,
-                             timing ? h->gev[4 * K + 2 * q] : nullptr, timing ? h->gev[4 * K + 2 * q + 1] : nullptr);
+            e = enqueue_step(a, timing ? h->gev[2 * q] : nullptr, timing ? h->gev[2 * q + 1] : nullptr);
             if (e == hipSuccess && (m - 1) % GRAD_GROUP == 0) e = launch_grad_flush(a->t, h->stream);
         }
         a->t.g_lap = nullptr;
@@ -1716,11 +1705,8 @@ tcm_status tcm_adjoint(tcm_handle* h, const float* resid, int32_t nt, int32_t re
                 h->af_ms += ms;
                 if (e == hipSuccess) e = hipEventElapsedTime(&ms, h->gev[2 * K + 2 * q], h->gev[2 * K + 2 * q + 1]);
                 h->rec_ms += ms;
-                if (e == hipSuccess) e = hipEventElapsedTime(&ms, h->gev[4 * K + 2 * q], h->gev[4 * K + 2 * q + 1]);
-                h->grad_ms += ms;
             }
             h->af_launches += end - s0;
-            h->grad_launches += end - s0;
             h->rec_launches += end - s0;
         }
         if (timing && e == hipSuccess) {
