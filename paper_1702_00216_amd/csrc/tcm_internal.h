@@ -121,6 +121,8 @@ struct Tables {
     float trigger_rel, retire_rel;
     float* bmax;                    // adaptive: per slot 6 face maxima, max |phi^{n+1}|, max |phi^n|
     int uniform_c2;                 // 1: blocks with a uniform C2 read it as a scalar
+    int c2_ready;                   // 1: a slot is always its key's (a pool of one slot per key), and
+                                    // every slot's C2 plane and slot_c2u were filled at creation
     long long* slot_key;            // per slot: global key, or -1 when the slot is free
     long long* new_key;             // per step: claimed keys
     int* new_shot;
@@ -205,6 +207,8 @@ hipError_t launch_activate_list(const Tables& t, const long long* keys, const in
                                 const unsigned* local_keys, const int* pins, const int* heads, int n,
                                 hipStream_t s);
 hipError_t launch_refresh_rows(const Tables& t, hipStream_t s);
+// C2 plane and slot_c2u of every slot from its key's block (c2_ready pools)
+hipError_t launch_prefill_c2(const Tables& t, long long nkeys, hipStream_t s);
 // table invariants between steps: mark = cap zeroed ints, bad = two zeroed
 // counters (violations, keys with a slot)
 hipError_t launch_check(const Tables& t, int* mark, unsigned long long* bad, hipStream_t s);

@@ -183,7 +183,9 @@ __device__ float fill_c2(const Tables& t, const Shot& S, long long slot, int bx,
     return uniform ? ref : __builtin_nanf("");
 }
 
-// Zero both phi levels of a new slot and fill its C2 plane (fill_c2).
+// Zero both phi levels of a new slot and fill its C2 plane (fill_c2), unless
+// the pool's C2 planes were filled at creation (then the slot's scalar C2
+// is returned as stored).
 __device__ float fill_slot(const Tables& t, const Shot& S, long long slot, int bx, int by, int bz) {
     float* __restrict__ p0 = plane_of(t, slot, 0);
     float* __restrict__ p1 = plane_of(t, slot, 1);
@@ -193,12 +195,23 @@ __device__ float fill_slot(const Tables& t, const Shot& S, long long slot, int b
         p0[z * 64 + lane] = 0.f;
         p1[z * 64 + lane] = 0.f;
     }
+    if (t.c2_ready) return t.slot_c2u[slot];
     return fill_c2(t, S, slot, bx, by, bz);
 }
 
 // --------------------------------------------------------------------------
 // table initialisation
 // --------------------------------------------------------------------------
+// shot owning bitmap word w (shots own consecutive key ranges)
+__device__ __forceinline__ int shot_of_word(const Tables& t, long long w) {
+    int lo = 0, hi = t.nshots - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (t.shots[mid].word_base <= w) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
 __global__ void k_init_tables(Tables t, long long nkeys) {
     const long long gs = (long long)gridDim.x * blockDim.x;
     const long long g0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -212,7 +225,7 @@ __global__ void k_init_tables(Tables t, long long nkeys) {
         t.pin_until[2 * (size_t)(i)] = 0;
         t.pin_until[2 * (size_t)(i) + 1] = -1;
         t.flags[i] = 0;
-        t.slot_c2u[i] = __builtin_nanf("");
+        if (!t.c2_ready) t.slot_c2u[i] = __builtin_nanf("");
         t.sdlog[i] = 0;
     }
     if (g0 == 0) {
@@ -226,6 +239,28 @@ __global__ void k_init_tables(Tables t, long long nkeys) {
         st->free_next = t.cap;
         st->n_gblocks = 0; st->grad_error = 0;
     }
+}
+
+// One wave per key: with a pool of one slot per key a block's C2 plane
+// depends only on its key, so it is computed once, when the pool is made
+// (the activation of a block then only zeroes its two phi levels).
+__global__ __launch_bounds__(256) void k_prefill_c2(Tables t, long long nkeys) {
+    const long long G = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (G >= nkeys) return;
+    const int shot = shot_of_word(t, G >> 6);
+    const Shot& S = t.shots[shot];
+    int bx, by, bz;
+    key_to_block(S, (unsigned)(G - S.key_base), bx, by, bz);
+    const float u = fill_c2(t, S, G, bx, by, bz);
+    if (lane_id() == 0) t.slot_c2u[G] = u;
+}
+
+hipError_t launch_prefill_c2(const Tables& t, long long nkeys, hipStream_t s) {
+    if (!t.c2_ready || t.cap < nkeys) return hipErrorInvalidValue;
+    const long long grid = (nkeys + 3) / 4;
+    if (grid > 0x7fffffffLL) return hipErrorInvalidValue;
+    if (grid > 0) hipLaunchKernelGGL(k_prefill_c2, dim3((unsigned)grid), dim3(256), 0, s, t, nkeys);
+    return hipGetLastError();
 }
 
 hipError_t launch_init_tables(const Tables& t, long long nkeys, hipStream_t s) {
@@ -1210,14 +1245,6 @@ hipError_t launch_pool_count(const Tables& t, int grid, hipStream_t s) {
 // --------------------------------------------------------------------------
 // K3b: compaction of the bitmap into the next active list
 // --------------------------------------------------------------------------
-__device__ __forceinline__ int shot_of_word(const Tables& t, long long w) {
-    int lo = 0, hi = t.nshots - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (t.shots[mid].word_base <= w) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-}
 
 // Workgroups of 16 waves take the chunks with a set bit (listed by the
 // allocator's scan; all chunks when the grid covers them) in turn.  Every wave loads the chunk (lane = word) and
@@ -2140,7 +2167,7 @@ __global__ __launch_bounds__(256) void k_ck_scatter(Tables t, long long n, const
 #pragma unroll
         for (int z = 0; z < 8; z++) dst[z * 64 + lane] = src[k * BV + z * 64 + lane];
     }
-    {
+    if (!t.c2_ready) {
         const Shot& S = t.shots[e.shot];
         int bx, by, bz;
         key_to_block(S, e.key, bx, by, bz);

@@ -405,7 +405,11 @@ tcm_status setup_engine(tcm_handle* h, long long word_base) {
     if (!ok) return set_err(h, TCM_E_NOMEM, "device allocation of the block tables failed");
     h->table_bytes += fixed + (size_t)cap * per_slot_tab;
 
+    // a pool of one slot per key: every C2 plane is filled now, once
+    t.c2_ready = cap >= h->nkeys ? 1 : 0;
     if (launch_init_tables(t, h->nkeys, h->stream) != hipSuccess) return dev_fail(h, hipGetLastError(), "init_tables");
+    if (t.c2_ready && launch_prefill_c2(t, h->nkeys, h->stream) != hipSuccess)
+        return dev_fail(h, hipGetLastError(), "prefill_c2");
     if (hipStreamSynchronize(h->stream) != hipSuccess) return dev_fail(h, hipGetLastError(), "sync");
 
     // persistent stencil grid of resident workgroups (a grid beyond residency
