@@ -110,30 +110,6 @@ def launch_shape(tuning, args) -> str:
     return f"{bw}x{bp}@{args.wg_per_cu or max(1, 12 // (bw // bp))}"
 
 
-def whole_run_pick(sim, w, steps, tuning, cands):
-    """The probe times candidates on one state; the active set of a run grows
-    from a few blocks to the whole domain, and the shape that wins on one
-    state need not win over the run.  Take each shape family's (tile, blocks
-    per wave) best workgroups per CU from the probe, time two whole runs of
-    each (untimed for the result) and keep the fastest."""
-    fam = {}
-    for bw, bp, wpc, gs, ms in cands:
-        if (bw, bp) not in fam or ms < fam[(bw, bp)][3]:
-            fam[(bw, bp)] = (bw, bp, wpc, ms)
-    runs = []
-    for bw, bp, wpc, _ in sorted(fam.values(), key=lambda c: c[3]):
-        sim.set_launch(wpc, tuning["graph_steps"], bw, bp)
-        el = min(run_once(sim, w, steps)[0] for _ in range(2))
-        runs.append((el, bw, bp, wpc))
-    el, bw, bp, wpc = min(runs)
-    sim.set_launch(wpc, tuning["graph_steps"], bw, bp)
-    tuning["probe_choice"] = {k: tuning[k] for k in ("blocks_per_wg", "blocks_per_wave", "wg_per_cu")}
-    tuning.update(blocks_per_wg=bw, blocks_per_wave=bp, wg_per_cu=wpc)
-    tuning["whole_run_s"] = {f"{b}x{p}@{c}": round(e, 4) for e, b, p, c in runs}
-    log(f"whole-run pick: tile {bw} blocks ({bp} per wave), wg_per_cu {wpc}: {el:.4f} s "
-        f"({', '.join(f'{b}x{p}@{c} {e:.4f}' for e, b, p, c in runs)})")
-
-
 def copy_calibration():
     """A plain elementwise copy of 1 GiB (read 1 GiB, write 1 GiB): what the
     HBM byte counters read for it scales them to bytes."""
@@ -679,17 +655,16 @@ def main():
         log(f"warmup {i}: {el:.3f} s, {st['cell_updates']:.3e} updates")
     tuning = None
     if not args.no_autotune and not args.wg_per_cu:
-        # pick the launch shape on the mid-run active set, then time from step 0
+        # the library picks the launch shape for the whole run from step 0
+        # (probes at three states along it, then whole runs per tile family)
         sim.reset()
         sim.add_source(w.source, w.wavelet.w32)
-        sim.step(steps // 2)
-        tuning = sim.autotune(probe_steps=32, cache=os.environ.get("TCM_TUNE_CACHE"),
-                              key=f"gfx950/{w.name}/k{args.interval}")
-        cands = tuning.pop("candidates", None)
-        log(f"autotune: tile {tuning['blocks_per_wg']} blocks ({tuning['blocks_per_wave']} per wave), wg_per_cu {tuning['wg_per_cu']}, "
-            f"graph_steps {tuning['graph_steps']}")
-        if cands:
-            whole_run_pick(sim, w, steps, tuning, cands)
+        tuning = sim.autotune_run(steps, probe_steps=32, cache=os.environ.get("TCM_TUNE_CACHE"),
+                                  key=f"gfx950/{w.name}/k{args.interval}/run")
+        tuning.pop("candidates", None)
+        log(f"autotune (whole run): tile {tuning['blocks_per_wg']} blocks ({tuning['blocks_per_wave']} per wave), "
+            f"wg_per_cu {tuning['wg_per_cu']}, graph_steps {tuning['graph_steps']}; "
+            f"families {tuning.get('families')}")
     tot_t, tot_u, st_ms, st_cells, st_launch, st_cells_u = 0.0, 0, 0.0, 0, 0, 0
     for i in range(args.steps):
         el, st = run_once(sim, w, steps)

@@ -263,6 +263,11 @@ typedef struct {
     int32_t cand_blocks_per_wg[32];
     int32_t blocks_per_wave;      /* chosen blocks per wave (1 or 2) */
     int32_t cand_blocks_per_wave[32];
+    int32_t nfam;                 /* tcm_autotune_run: tile families timed over the whole run */
+    int32_t fam_blocks_per_wg[8]; /*   each family's best probe shape ... */
+    int32_t fam_blocks_per_wave[8];
+    int32_t fam_wg_per_cu[8];
+    double  fam_run_ms[8];        /*   ... and its whole-run time (best of two) */
 } tcm_tuning;
 
 /* Time probe_steps steps from the current state for each candidate launch
@@ -274,6 +279,19 @@ typedef struct {
  * and traces are unchanged on return.  TCM_E_STATE for the dense engine or
  * a failed run; out may be NULL. */
 tcm_status tcm_autotune(tcm_handle* h, int32_t probe_steps, tcm_tuning* out);
+
+/* Pick the launch shape for a run of nsteps steps from the current state:
+ * every candidate of tcm_autotune is probed for probe_steps steps at three
+ * states along the run (a quarter, half and three quarters of the way,
+ * reached with the current shape) and ranked by its mean probe time; the
+ * steps per graph are chosen on the fastest; the best shape of each tile
+ * family (blocks per workgroup x blocks per wave) then runs the whole run
+ * from the current state twice, and the family with the fastest run is
+ * kept (out->ms_per_step = its run time / nsteps; out->fam_* lists the
+ * families' whole-run times).  The field, statistics and traces are
+ * unchanged on return.  nsteps >= 4; TCM_E_STATE for the dense engine or a
+ * failed run (also when the run fails while the tuner steps it). */
+tcm_status tcm_autotune_run(tcm_handle* h, int32_t nsteps, int32_t probe_steps, tcm_tuning* out);
 
 /* Set the launch shape directly (for example a stored tcm_autotune choice):
  * blocks_per_wg 2, 4 or 8 and blocks_per_wave 1 or 2 (2 needs a tile of 4

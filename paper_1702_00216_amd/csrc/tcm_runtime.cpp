@@ -1864,6 +1864,191 @@ tcm_status tcm_autotune(tcm_handle* h, int32_t probe_steps, tcm_tuning* out) {
     return TCM_OK;
 }
 
+// Whole-run launch-shape choice.  The shape that is fastest on one state
+// need not be fastest over a run whose active set grows from a few blocks to
+// the whole domain, so every candidate is probed at three states along the
+// run (a quarter, half and three quarters of the way, reached with the
+// current shape) and ranked by its summed probe time; the best candidate of
+// each tile family (workgroup tile x blocks per wave) then runs the whole
+// run from the current state twice, and the family with the fastest run
+// wins.  The state is restored afterwards.
+tcm_status tcm_autotune_run(tcm_handle* h, int32_t nsteps, int32_t probe_steps, tcm_tuning* out) {
+    tcm_status st = check_live(h);
+    if (st) return st;
+    if (h->engine != TCM_ENGINE_BLOCKS) return set_err(h, TCM_E_STATE, "autotune applies to the block engine");
+    if (probe_steps < 1 || nsteps < 4) return set_err(h, TCM_E_ARG, "nsteps >= 4 and probe_steps >= 1 required");
+    st = sync_state(h);
+    if (st) return st;
+    if (dev_error(*h->h_state)) return set_err(h, TCM_E_STATE, "the run has failed (pool or non-finite field)");
+    const long long step0 = h->h_state->step;
+    st = ensure_trace_capacity(h, step0 + (long long)nsteps + probe_steps - h->t.trace_step0);
+    if (st) return st;
+    const int keep_grid = h->grid_step, keep_gs = h->gsteps, keep_w = h->tile_w, keep_p = h->tile_p;
+    const int keep_flags = h->cfg.flags;
+    Ckpt s0;
+    std::vector<Ckpt> states(3);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto finish = [&](tcm_status s) -> tcm_status {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        h->cfg.flags = keep_flags;
+        tcm_status rs = TCM_OK;
+        if (s0.buf) {
+            rs = ck_restore(h, s0);
+            h->hstep = step0;
+            if (!rs) rs = sync_state(h);
+        }
+        ck_free(s0);
+        for (auto& c : states) ck_free(c);
+        drop_graph(h);
+        if (s || rs) {
+            h->grid_step = keep_grid;
+            h->gsteps = keep_gs;
+            h->tile_w = keep_w;
+            h->tile_p = keep_p;
+        }
+        return s ? s : rs;
+    };
+    st = ck_save(h, s0);
+    if (st) return finish(st);
+    h->cfg.flags &= ~TCM_FLAG_TIMING;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return finish(dev_fail(h, hipGetLastError(), "hipEventCreate"));
+    // the probe states, reached with the current shape
+    long long at = step0;
+    for (int k = 0; k < 3; k++) {
+        const long long target = step0 + (long long)nsteps * (k + 1) / 4;
+        st = issue_steps(h, (int)(target - at));
+        at = target;
+        if (!st) st = sync_state(h);
+        if (!st && dev_error(*h->h_state)) st = report_device_error(h);
+        if (!st) st = ck_save(h, states[k]);
+        if (st) return finish(st);
+    }
+    auto set_shape = [&](int w, int pb, int wpc, int gs) {
+        h->tile_w = w;
+        h->tile_p = pb;
+        h->grid_step = std::max(8, (h->ncu * wpc) / 8 * 8);
+        h->gsteps = round_graph_steps(h, gs);
+        drop_graph(h);
+    };
+    // time n steps from a state (one untimed graph launch first, so capture
+    // and instantiation are not timed)
+    auto timed = [&](const Ckpt& c, int n, int gs, double* ms_out) -> tcm_status {
+        const long long s = c.step;
+        tcm_status r = ck_restore(h, c);
+        h->hstep = s;
+        if (!r) r = issue_steps(h, std::min(gs, n));
+        if (!r) r = ck_restore(h, c);
+        h->hstep = s;
+        if (r) return r;
+        HIP_OR_FAIL(h, hipEventRecord(e0, h->stream));
+        r = issue_steps(h, n);
+        if (r) return r;
+        HIP_OR_FAIL(h, hipEventRecord(e1, h->stream));
+        HIP_OR_FAIL(h, hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIP_OR_FAIL(h, hipEventElapsedTime(&ms, e0, e1));
+        *ms_out = ms;
+        return TCM_OK;
+    };
+    // mean time per step over the three states
+    auto probe = [&](int w, int pb, int wpc, int gs, double* per) -> tcm_status {
+        set_shape(w, pb, wpc, gs);
+        double sum = 0.0;
+        for (const auto& c : states) {
+            double ms = 0.0;
+            tcm_status r = timed(c, probe_steps, gs, &ms);
+            if (r) return r;
+            sum += ms;
+        }
+        *per = sum / (3.0 * probe_steps);
+        return TCM_OK;
+    };
+    tcm_tuning res{};
+    res.ms_per_step = 1e300;
+    struct Fam { int w, pb, wpc; double per; };
+    std::vector<Fam> fams;
+    const int shapes[5][2] = {{2, 1}, {4, 1}, {8, 1}, {2, 2}, {4, 2}};   // {waves, blocks per wave}
+    for (const auto& sh : shapes) {
+        const int w = sh[0], pb = sh[1];
+        const int occ = std::max(1, block_step_occupancy(h->t.adaptive != 0, w, pb));
+        Fam best{w, pb, 0, 1e300};
+        for (int wpc : {1, 2, 3, 4, 6, 8, 12}) {
+            if (wpc > occ || w * wpc < 4 || w * wpc > 24) continue;
+            double per = 0.0;
+            st = probe(w, pb, wpc, 16, &per);
+            if (st) return finish(st);
+            if (res.ncand < 32) {
+                res.cand_blocks_per_wg[res.ncand] = w * pb;
+                res.cand_blocks_per_wave[res.ncand] = pb;
+                res.cand_wg_per_cu[res.ncand] = wpc;
+                res.cand_graph_steps[res.ncand] = h->gsteps;
+                res.cand_ms_per_step[res.ncand] = per;
+                res.ncand++;
+            }
+            if (per < best.per) best = Fam{w, pb, wpc, per};
+        }
+        if (best.wpc > 0) fams.push_back(best);
+    }
+    if (fams.empty()) return finish(set_err(h, TCM_E_STATE, "no launch shape fits"));
+    // steps per graph, on the family that probed fastest
+    int gsteps = 16;
+    {
+        const Fam* f0 = &fams[0];
+        for (const auto& f : fams)
+            if (f.per < f0->per) f0 = &f;
+        double best = f0->per;
+        for (int gs : {8, 32}) {
+            double per = 0.0;
+            st = probe(f0->w, f0->pb, f0->wpc, gs, &per);
+            if (st) return finish(st);
+            if (per < best) {
+                best = per;
+                gsteps = gs;
+            }
+        }
+    }
+    // whole runs: each family's best probe shape, twice
+    int win = -1;
+    double win_ms = 1e300;
+    for (size_t i = 0; i < fams.size(); i++) {
+        const Fam& f = fams[i];
+        set_shape(f.w, f.pb, f.wpc, gsteps);
+        double run = 1e300;
+        for (int r = 0; r < 2; r++) {
+            double ms = 0.0;
+            st = timed(s0, nsteps, h->gsteps, &ms);
+            if (st) return finish(st);
+            run = std::min(run, ms);
+        }
+        if (i < 8) {
+            res.fam_blocks_per_wg[i] = f.w * f.pb;
+            res.fam_blocks_per_wave[i] = f.pb;
+            res.fam_wg_per_cu[i] = f.wpc;
+            res.fam_run_ms[i] = run;
+            res.nfam = (int)i + 1;
+        }
+        if (run < win_ms) {
+            win_ms = run;
+            win = (int)i;
+        }
+    }
+    const Fam& f = fams[win];
+    st = finish(TCM_OK);
+    if (st) return st;
+    set_shape(f.w, f.pb, f.wpc, gsteps);
+    res.blocks_per_wg = f.w * f.pb;
+    res.blocks_per_wave = f.pb;
+    res.wg_per_cu = f.wpc;
+    res.graph_steps = h->gsteps;
+    res.ms_per_step = win_ms / nsteps;
+    st = sync_state(h);
+    if (st) return st;
+    if (out) *out = res;
+    return TCM_OK;
+}
+
 tcm_status tcm_set_launch(tcm_handle* h, int32_t wg_per_cu, int32_t graph_steps, int32_t blocks_per_wg,
                           int32_t blocks_per_wave) {
     tcm_status st = check_live(h);

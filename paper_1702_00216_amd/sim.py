@@ -238,6 +238,41 @@ class Simulation:
                 json.dump(data, f, indent=1)
         return res
 
+    def autotune_run(self, nsteps: int, probe_steps: int = 32, cache: Optional[str] = None,
+                     key: Optional[str] = None) -> dict:
+        """Pick the launch shape for a run of ``nsteps`` steps from the current
+        state (tcm_autotune_run): candidates probed at three states along the
+        run, then each tile family's best timed over the whole run; the state
+        is unchanged.  ``cache`` / ``key`` as for :meth:`autotune`."""
+        import json
+        import os
+        if cache and key and os.path.exists(cache):
+            with open(cache) as f:
+                stored = json.load(f).get(key)
+            if stored and "families" in stored:
+                self._apply_tuning(stored["wg_per_cu"], stored["graph_steps"], stored["blocks_per_wg"],
+                                   stored["blocks_per_wave"])
+                return dict(stored, cached=True)
+        t = L.Tuning()
+        self._check(L.lib().tcm_autotune_run(self._h, int(nsteps), int(probe_steps), C.byref(t)))
+        res = {"blocks_per_wg": t.blocks_per_wg, "blocks_per_wave": t.blocks_per_wave,
+               "wg_per_cu": t.wg_per_cu, "graph_steps": t.graph_steps, "ms_per_step": t.ms_per_step,
+               "cached": False,
+               "families": {f"{t.fam_blocks_per_wg[i]}x{t.fam_blocks_per_wave[i]}@{t.fam_wg_per_cu[i]}":
+                            round(t.fam_run_ms[i], 3) for i in range(t.nfam)},
+               "candidates": [(t.cand_blocks_per_wg[i], t.cand_blocks_per_wave[i], t.cand_wg_per_cu[i],
+                               t.cand_graph_steps[i], t.cand_ms_per_step[i]) for i in range(t.ncand)]}
+        if cache and key:
+            data = {}
+            if os.path.exists(cache):
+                with open(cache) as f:
+                    data = json.load(f)
+            data[key] = {k: res[k] for k in ("blocks_per_wg", "blocks_per_wave", "wg_per_cu", "graph_steps",
+                                             "ms_per_step", "families")}
+            with open(cache, "w") as f:
+                json.dump(data, f, indent=1)
+        return res
+
     def _apply_tuning(self, wg_per_cu: int, graph_steps: int, blocks_per_wg: int = 0,
                       blocks_per_wave: int = 0):
         self._check(L.lib().tcm_set_launch(self._h, int(wg_per_cu), int(graph_steps), int(blocks_per_wg),

@@ -117,6 +117,45 @@ def test_autotune_keeps_state_and_results(tmp_path):
         ref.set_launch(0, 16)
 
 
+def test_autotune_run_keeps_state_and_picks_a_timed_family(tmp_path):
+    """The whole-run tuner steps the run to probe three states and times every
+    tile family over the whole run, then restores the state: the field,
+    statistics and later results are those of an untuned run, and the shape
+    it keeps is the family with the shortest whole run."""
+    announce("autotune over a whole run")
+    dt = 0.5 / 4500
+    w = ti.ricker(300.0, dt).w32
+    shots = make_shots(3, seed=23)
+    def fresh():
+        b = tcm.Simulation([s[0] for s in shots], 1.0, dt, [s[1] for s in shots], 1e-4, 1e-5)
+        for i, (shape, lat, src) in enumerate(shots):
+            b.add_source(src, w, shot=i)
+        return b
+    a = fresh()
+    a.step(5)
+    before = [a.read(0, shot=i) for i in range(3)], a.stats()
+    res = a.autotune_run(48, probe_steps=4)
+    after = [a.read(0, shot=i) for i in range(3)], a.stats()
+    for x, y in zip(before[0], after[0]):
+        assert values_equal(x, y)
+    for k in ("step", "active_blocks", "cell_updates", "activations", "retirements"):
+        assert before[1][k] == after[1][k], k
+    fam = res["families"]
+    assert len(fam) == 5 and all(v > 0 for v in fam.values())
+    chosen = f"{res['blocks_per_wg']}x{res['blocks_per_wave']}@{res['wg_per_cu']}"
+    assert fam[chosen] == min(fam.values())
+    assert res["ms_per_step"] == pytest.approx(fam[chosen] / 48, abs=1e-4)
+    a.step(60)
+    ref = fresh()
+    ref.step(65)
+    for i in range(3):
+        assert values_equal(a.read(0, shot=i), ref.read(0, shot=i))
+    cache = str(tmp_path / "tune.json")
+    r1 = fresh().autotune_run(16, probe_steps=2, cache=cache, key="gfx950/test/run")
+    r2 = fresh().autotune_run(16, probe_steps=2, cache=cache, key="gfx950/test/run")
+    assert not r1["cached"] and r2["cached"] and r2["families"] == r1["families"]
+
+
 @pytest.mark.parametrize("seed", list(range(8)))
 def test_random_batches_match_cpu_tcm_per_shot(seed):
     """Seeded random batches: 2-7 shots of random shapes, media and sources
