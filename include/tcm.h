@@ -210,10 +210,14 @@ tcm_status tcm_step(tcm_handle* h, int32_t nsteps);
  * for the dense engine. */
 tcm_status tcm_check(tcm_handle* h, int64_t* violations);
 
-/* Copy phi^n (which = 0) or phi^{n-1} (which = 1) of the box
- * [x0,x0+sx)x[y0,y0+sy)x[z0,z0+sz) of shot 0 into out (sx*sy*sz floats,
- * x fastest), on the host (out_is_device = 0) or the device (1, on the
- * handle's stream).  Nodes of inactive blocks read 0. */
+/* Copy phi^n (which = 0) or phi^{n-1} (which = 1), the two field levels
+ * that eq.(3) keeps, of the box [x0,x0+sx)x[y0,y0+sy)x[z0,z0+sz) of shot 0
+ * into out (sx*sy*sz floats, x fastest), on the host (out_is_device = 0) or
+ * the device (1, on the handle's stream).  Nodes of inactive blocks read 0:
+ * a cell that is not boxed holds no field ("Boxes", "Updating active
+ * cells": an unboxed cell's values are dropped).  Synchronous for host
+ * output.  TCM_E_RANGE for a box outside the domain, TCM_E_ARG for which
+ * not 0 or 1 or a NULL out. */
 tcm_status tcm_read(tcm_handle* h, int32_t which, int32_t x0, int32_t y0, int32_t z0,
                     int32_t sx, int32_t sy, int32_t sz, float* out, int32_t out_is_device);
 tcm_status tcm_read_shot(tcm_handle* h, int32_t shot, int32_t which, int32_t x0, int32_t y0,
