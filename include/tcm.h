@@ -309,6 +309,19 @@ tcm_status tcm_set_launch(tcm_handle* h, int32_t wg_per_cu, int32_t graph_steps,
  * media, configuration and allocations are kept. */
 tcm_status tcm_reset(tcm_handle* h);
 
+/* Replace the wave speed of one shot ("Media": an array or rules) by media
+ * of the same kind and sizes as at creation (dense: nx*ny*nz speeds; layered:
+ * the same layer count; lattice: the same lattice size and spacing), then
+ * return the handle to level 0 as tcm_reset does (sources, receivers,
+ * traces and checkpoints cleared).  The C2 planes follow the new speeds.
+ * Lets a caller that runs many models of one geometry (an inversion) keep
+ * one handle and its allocations.  Host data is copied before return.
+ * TCM_E_ARG for another kind or size or invalid speeds, TCM_E_CFL if the
+ * new speeds violate eq.(4) (the handle keeps its media then), TCM_E_RANGE
+ * for a shot index out of range.  Snapshots taken before the call are
+ * refused by tcm_restore (TCM_E_STATE). */
+tcm_status tcm_set_media(tcm_handle* h, int32_t shot, const tcm_media* media);
+
 /* Save the whole state at the current step (block engine: pool, block
  * tables and counters; dense engine: both field arrays) into device memory
  * that the snapshot owns; *snap receives an opaque pointer, freed by

@@ -20,7 +20,7 @@ FLAG_TIMING, FLAG_NO_GRAPH, FLAG_NO_UNIFORM_C2, FLAG_THREE_PASS_UPDATE, FLAG_DEB
 EXPORTS = [
     "tcm_create", "tcm_create_batch", "tcm_add_source", "tcm_add_source_shot", "tcm_step",
     "tcm_read", "tcm_read_shot", "tcm_set_receivers", "tcm_read_traces", "tcm_adjoint",
-    "tcm_reset", "tcm_stats", "tcm_destroy", "tcm_last_error", "tcm_version", "tcm_autotune", "tcm_autotune_run",
+    "tcm_reset", "tcm_stats", "tcm_destroy", "tcm_last_error", "tcm_version", "tcm_autotune", "tcm_autotune_run", "tcm_set_media",
     "tcm_set_launch", "tcm_snapshot", "tcm_restore", "tcm_snapshot_free", "tcm_hbm_probe",
     "tcm_read_noalloc", "tcm_check",
 ]
@@ -118,6 +118,7 @@ def lib():
         L.tcm_snapshot_free.restype = None
         L.tcm_autotune.argtypes = [H, I, F(Tuning)]
         L.tcm_autotune_run.argtypes = [H, I, I, F(Tuning)]
+        L.tcm_set_media.argtypes = [H, I, F(Media)]
         L.tcm_set_launch.argtypes = [H, I, I, I, I]
         L.tcm_hbm_probe.argtypes = [P, P, C.c_uint64, I, I, I, P, F(C.c_float)]
         L.tcm_stats.argtypes = [H, F(Stats)]

@@ -8,7 +8,7 @@ Only argument marshalling happens here.
 from __future__ import annotations
 
 from dataclasses import dataclass
-from typing import Optional, Sequence
+from typing import Dict, List, Optional, Sequence
 
 import numpy as np
 import torch
@@ -31,6 +31,26 @@ class ShotSpec:
     pool_bytes: int = 0
 
 
+# Idle handles by geometry and configuration.  A forward takes one (giving
+# it the new wave speed with tcm_set_media, which keeps its allocations) or
+# makes one; the backward hands it back, so an inversion loop creates a
+# handle once per concurrently live forward, not once per iteration.
+_IDLE: Dict[tuple, List[Simulation]] = {}
+
+
+def _config_key(shape, spec: ShotSpec) -> tuple:
+    return (tuple(shape), float(spec.dx), float(spec.dt), float(spec.trigger), float(spec.retire),
+            int(spec.pool_bytes), int(spec.checkpoint_every))
+
+
+def release_handles() -> None:
+    """Destroy the idle handles kept for reuse."""
+    for sims in _IDLE.values():
+        for s in sims:
+            s.close()
+    _IDLE.clear()
+
+
 class TCMForward(torch.autograd.Function):
     """traces = TCMForward.apply(c, spec); c is a (nz, ny, nx) float32 tensor."""
 
@@ -38,13 +58,20 @@ class TCMForward(torch.autograd.Function):
     def forward(ctx, c: torch.Tensor, spec: ShotSpec):
         nz, ny, nx = c.shape
         c_host = np.ascontiguousarray(c.detach().to("cpu", torch.float32).numpy())
-        sim = Simulation((nx, ny, nz), spec.dx, spec.dt, c_host, spec.trigger, spec.retire,
-                         pool_bytes=spec.pool_bytes, checkpoint_every=spec.checkpoint_every)
+        key = _config_key((nx, ny, nz), spec)
+        idle = _IDLE.get(key)
+        if idle:
+            sim = idle.pop()
+            sim.set_media(c_host)
+        else:
+            sim = Simulation((nx, ny, nz), spec.dx, spec.dt, c_host, spec.trigger, spec.retire,
+                             pool_bytes=spec.pool_bytes, checkpoint_every=spec.checkpoint_every)
         sim.add_source(spec.source, spec.wavelet)
         sim.set_receivers(spec.receivers)
         sim.step(spec.nt)
         traces = torch.from_numpy(sim.read_traces()).to(c.device)
         ctx.sim = sim
+        ctx.key = key
         ctx.c_device = c.device
         return traces
 
@@ -57,7 +84,7 @@ class TCMForward(torch.autograd.Function):
             sim.adjoint_device(g, out)
         else:
             out = torch.from_numpy(sim.adjoint(g.numpy()))
-        sim.close()
+        _IDLE.setdefault(ctx.key, []).append(sim)
         ctx.sim = None
         return out.to(ctx.c_device), None
 

@@ -116,6 +116,7 @@ struct tcm_handle {
     std::vector<Ckpt> ckpts;
     bool in_adjoint = false;
     tcm_handle* adj = nullptr;          // tables of the adjoint field (shares the media)
+    long long media_gen = 0;            // tcm_set_media calls so far (snapshots record it)
     size_t adjoint_bytes = 0;           // device memory the last tcm_adjoint held
     // timed recomputed forward steps of tcm_adjoint (TCM_FLAG_TIMING)
     double rec_ms = 0.0;
@@ -1413,6 +1414,7 @@ struct SnapImpl {
     long long hstep = 0, dense_step = 0;
     size_t nsrc = 0;
     int nrec = 0;
+    long long media_gen = 0;
 };
 
 tcm_status tcm_reset(tcm_handle* h) {
@@ -1463,6 +1465,57 @@ tcm_status tcm_reset(tcm_handle* h) {
     return TCM_OK;
 }
 
+tcm_status tcm_set_media(tcm_handle* h, int32_t shot, const tcm_media* media) {
+    tcm_status st = check_live(h);
+    if (st) return st;
+    if (!media) return set_err(h, TCM_E_ARG, "media is NULL");
+    if (shot < 0 || shot >= (int)h->shots.size()) return set_err(h, TCM_E_RANGE, "shot index out of range");
+    Shot& S = h->shots[shot];
+    if (media->kind != S.media_kind) return set_err(h, TCM_E_ARG, "the media kind differs from the shot's");
+    if (media->kind == TCM_MEDIA_LAYERED && media->nlayers != S.nlayers)
+        return set_err(h, TCM_E_ARG, "the layer count differs from the shot's");
+    if (media->kind == TCM_MEDIA_LATTICE &&
+        (media->lx != S.lx || media->ly != S.ly || media->lz != S.lz || media->log2_spacing != S.log2s))
+        return set_err(h, TCM_E_ARG, "the lattice size or spacing differs from the shot's");
+    std::string why;
+    double cmax = 0.0;
+    st = validate_media(media, S.nx, S.ny, S.nz, &cmax, &why);
+    if (st) return set_err(h, st, why);
+    const double r = cmax * h->cfg.dt / h->cfg.dx;
+    if (r * r * 3.0 > 1.0 + 4.0 * DBL_EPSILON)
+        return set_err(h, TCM_E_CFL, fmt("eq.(4) violated: cmax dt / dx = %.9g > 1/sqrt(3)", r));
+    HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+    // the shot's device media keep their buffers (same kind and sizes)
+    if (media->kind == TCM_MEDIA_DENSE) {
+        HIP_OR_FAIL(h, hipMemcpy((void*)S.c, media->c, (size_t)S.nx * S.ny * S.nz * sizeof(float),
+                                 hipMemcpyHostToDevice));
+    } else if (media->kind == TCM_MEDIA_LAYERED) {
+        HIP_OR_FAIL(h, hipMemcpy((void*)S.z_top, media->z_top, S.nlayers * sizeof(int), hipMemcpyHostToDevice));
+        HIP_OR_FAIL(h, hipMemcpy((void*)S.c_layer, media->c_layer, S.nlayers * sizeof(float), hipMemcpyHostToDevice));
+    } else {
+        HIP_OR_FAIL(h, hipMemcpy((void*)S.lattice, media->lattice, (size_t)S.lx * S.ly * S.lz * sizeof(double),
+                                 hipMemcpyHostToDevice));
+    }
+    h->hshots[shot].cmax = cmax;
+    h->media_gen++;
+    // the adjoint field's pool holds C2 planes of the old media: made anew
+    // by the next tcm_adjoint
+    if (h->adj) {
+        destroy_all(h->adj);
+        h->adj = nullptr;
+    }
+    st = tcm_reset(h);
+    if (st) return st;
+    if (h->engine == TCM_ENGINE_DENSE) {
+        HIP_OR_FAIL(h, launch_media_c2(S, h->d_shots, h->cfg.dt, h->cfg.dx, h->d_c2, h->stream));
+    } else if (h->t.c2_ready) {
+        HIP_OR_FAIL(h, launch_prefill_c2(h->t, h->nkeys, h->stream));
+    }
+    // (a capped pool fills a block's C2 plane when the block is activated)
+    HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+    return TCM_OK;
+}
+
 void tcm_snapshot_free(void* snap) {
     SnapImpl* s = (SnapImpl*)snap;
     if (!s) return;
@@ -1479,6 +1532,7 @@ tcm_status tcm_snapshot(tcm_handle* h, void** snap) {
     HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
     SnapImpl* s = new SnapImpl();
     s->owner = h;
+    s->media_gen = h->media_gen;
     s->hstep = h->hstep;
     s->dense_step = h->dense_step;
     s->nsrc = h->h_src.size();
@@ -1515,6 +1569,7 @@ tcm_status tcm_restore(tcm_handle* h, const void* snap) {
     if (st) return st;
     const SnapImpl* s = (const SnapImpl*)snap;
     if (!s || s->owner != h) return set_err(h, TCM_E_ARG, "not a snapshot of this handle");
+    if (s->media_gen != h->media_gen) return set_err(h, TCM_E_STATE, "the media changed after the snapshot");
     if (s->nsrc != h->h_src.size() || s->nrec != h->t.nrec)
         return set_err(h, TCM_E_STATE, "sources or receivers were added after the snapshot");
     HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));

@@ -287,6 +287,15 @@ class Simulation:
 
     def reset(self):
         self._check(L.lib().tcm_reset(self._h))
+        self.nrec = 0
+
+    def set_media(self, media, shot: int = 0):
+        """New wave speed for a shot (same kind and sizes as at creation); the
+        handle returns to level 0 as after :meth:`reset` (tcm_set_media)."""
+        keep: list = []
+        m = _media_struct(media, self.shapes[shot], keep)
+        self._check(L.lib().tcm_set_media(self._h, int(shot), C.byref(m)))
+        self.nrec = 0
 
     def snapshot(self) -> "Snapshot":
         """Device copy of the whole state at the current step (tcm_snapshot)."""

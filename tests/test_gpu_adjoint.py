@@ -108,6 +108,47 @@ def test_autograd_function_gradient():
         assert e <= 1e-3
 
 
+def test_autograd_reuses_one_handle_across_iterations():
+    """An inversion loop: each forward takes the idle handle of the previous
+    iteration and gives it the new wave speed (tcm_set_media) instead of
+    creating one; every iteration's gradient equals a fresh handle's bit for
+    bit."""
+    announce("autograd handle reuse")
+    import torch
+    from paper_1702_00216_amd import autograd as ag
+    c, dt, w, src, rec, _, nt = setup(nt=60, seed=13)
+    spec = ag.ShotSpec(dx=1.0, dt=dt, source=src, wavelet=w, receivers=rec, nt=nt, checkpoint_every=16)
+    d_obs = torch.tensor(oracle.dense_run(c * np.float32(1.02), dt, 1.0, nt, np.float64,
+                                          sources=[(src, w.astype(np.float64))], receivers=rec)[2],
+                         device="cuda")
+    ag.release_handles()
+    ct = torch.tensor(c, device="cuda", requires_grad=True)
+    handles = set()
+    for it in range(3):
+        tr = ag.TCMForward.apply(ct, spec)
+        loss = 0.5 * ((tr.double() - d_obs) ** 2).sum()
+        loss.backward()
+        g = ct.grad.detach().clone()
+        idle = [s for v in ag._IDLE.values() for s in v]
+        assert len(idle) == 1
+        handles.add(id(idle[0]))
+        # the same iteration on a fresh handle
+        c_it = ct.detach().cpu().numpy()
+        fresh = tcm.Simulation(c_it.shape[::-1], 1.0, dt, c_it, checkpoint_every=16)
+        fresh.add_source(src, w)
+        fresh.set_receivers(rec)
+        fresh.step(nt)
+        resid = (torch.from_numpy(fresh.read_traces()).to("cuda").double() - d_obs).float().cpu().numpy()
+        assert np.array_equal(fresh.read_traces(), tr.detach().cpu().numpy())
+        assert np.array_equal(fresh.adjoint(resid), g.cpu().numpy())
+        fresh.close()
+        with torch.no_grad():
+            ct.mul_(0.98)                      # a new wave speed for the next iteration
+        ct.grad = None
+    assert len(handles) == 1
+    ag.release_handles()
+
+
 def test_timed_adjoint_counts_gradient_launches_and_keeps_results():
     """With the timing flag every adjoint-field launch (which also forms the
     step's gradient terms) and every recomputed forward launch is timed and

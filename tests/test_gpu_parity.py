@@ -747,3 +747,48 @@ def test_nonfinite_value_stops_the_run(path, interval, at):
     clean.step(6)
     assert values_equal(sim.read(0), clean.read(0)) and values_equal(sim.read(1), clean.read(1))
     assert sim.stats()["active_blocks"] == clean.stats()["active_blocks"]
+
+
+@pytest.mark.parametrize("engine,pool", [("blocks", "key"), ("blocks", "capped"), ("dense", "key")])
+def test_set_media_equals_a_fresh_handle(engine, pool):
+    """tcm_set_media on a handle that has run: the next run equals a handle
+    created with the new media (fields and work), with a pool of one slot per
+    key (C2 planes filled when the pool was made) or a capped pool; a
+    snapshot from before the change is refused, speeds that break eq.(4)
+    are refused and leave the old media in place, another media kind is
+    refused."""
+    announce(f"set_media ({engine}, {pool} pool)")
+    shape = (40, 33, 27)
+    a = ti.random_media(shape, seed=81, cmin=0.5, cmax=1.0)
+    b = ti.random_media(shape, seed=82, cmin=0.4, cmax=0.9)
+    w = ti.ricker(0.12, 0.5).w32
+    src = (19, 16, 12)
+    cap = 0 if pool == "key" else 60
+    kw = dict(engine=engine, pool_bytes=cap * 6144)
+    def run(sim, n):
+        sim.add_source(src, w)
+        sim.set_receivers([(3, 4, 5), (20, 16, 12)])
+        sim.step(n)
+        return sim.read(0), sim.read(1), sim.read_traces(), sim.stats()
+    sim = tcm.Simulation(shape, 1.0, 0.5, a, 1e-4, 1e-5, **kw)
+    run(sim, 30)
+    snap = sim.snapshot()
+    sim.set_media(b)
+    assert sim.stats()["step"] == 0
+    got = run(sim, 50)
+    ref = run(tcm.Simulation(shape, 1.0, 0.5, b, 1e-4, 1e-5, **kw), 50)
+    for x, y in zip(got[:3], ref[:3]):
+        assert values_equal(x, y)
+    for k in ("step", "active_blocks", "cell_updates", "activations", "retirements"):
+        assert got[3][k] == ref[3][k], k
+    with pytest.raises(tcm.TCMError):
+        sim.restore(snap)
+    with pytest.raises(tcm.TCMError) as e:
+        sim.set_media(b * np.float32(2.0))          # cmax dt / dx = 0.9 > 1/sqrt(3)
+    assert e.value.status == tcm.TCM_E_CFL
+    with pytest.raises(tcm.TCMError):
+        sim.set_media(ti.LayeredMedia(z_top=[0, 10], c_layer=[0.5, 0.9]))
+    sim.reset()
+    again = run(sim, 50)
+    for x, y in zip(again[:3], ref[:3]):
+        assert values_equal(x, y)
