@@ -1520,31 +1520,35 @@ __global__ __launch_bounds__(64 * FAST_WORDS) void k_fast_emit(Tables t) {
     const int wid = threadIdx.x >> 6;
     const int nf = t.nfchunks;
     for (int c = blockIdx.x; c < nf; c += gridDim.x) {          // uniform over the workgroup
-        // offset of this fast chunk in the next list and the list's length;
-        // the workgroup of chunk 0 also sums the step's statistics
+        // this wave's word and its shot first: their loads overlap the sums below
+        const long long w = (long long)c * FAST_WORDS + wid;
+        const bool in_range = w < t.nwords;
+        const unsigned long long myw = in_range ? nxt[w] : 0ull;
+        const int shot = in_range ? shot_of_word(t, w) : 0;
+        const Shot S = t.shots[shot];
+        // offset of this fast chunk in the next list; the workgroup of chunk 0
+        // also sums the list's length and the step's statistics
         unsigned long long v6[6] = {0, 0, 0, 0, 0, 0};   // before, total, cells, scalar-C2 cells, new, released
-        for (int k = threadIdx.x; k < nf; k += blockDim.x) {
-            const unsigned long long v = (unsigned)t.fc_cnt[k];
-            v6[1] += v;
-            if (k < c) v6[0] += v;
-            if (c == 0) {
+        if (c == 0) {
+            for (int k = threadIdx.x; k < nf; k += blockDim.x) {
+                v6[1] += (unsigned)t.fc_cnt[k];
                 v6[2] += t.fc_cells[2 * (size_t)k];
                 v6[3] += t.fc_cells[2 * (size_t)k + 1];
                 v6[4] += (unsigned)t.fc_new[k];
                 v6[5] += (unsigned)t.fc_ret[k];
             }
-        }
-        for (int o = 32; o > 0; o >>= 1) {
+            for (int o = 32; o > 0; o >>= 1) {
 #pragma unroll
-            for (int q = 0; q < 6; q++) v6[q] += __shfl_xor(v6[q], o);
+                for (int q = 1; q < 6; q++) v6[q] += __shfl_xor(v6[q], o);
+            }
+        } else {
+            for (int k = threadIdx.x; k < c; k += blockDim.x) v6[0] += (unsigned)t.fc_cnt[k];
+            for (int o = 32; o > 0; o >>= 1) v6[0] += __shfl_xor(v6[0], o);
         }
         if (lane == 0) {
 #pragma unroll
             for (int q = 0; q < 6; q++) s_red[wid][q] = v6[q];
         }
-        const long long w = (long long)c * FAST_WORDS + wid;
-        const bool in_range = w < t.nwords;
-        const unsigned long long myw = in_range ? nxt[w] : 0ull;
         if (lane == 0) s_word[wid] = (unsigned)__popcll(myw);
         __syncthreads();
         unsigned long long base = 0, ntot = 0;
@@ -1563,8 +1567,6 @@ __global__ __launch_bounds__(64 * FAST_WORDS) void k_fast_emit(Tables t) {
         if ((myw >> lane) & 1ull) {
             const long long G = w * 64 + lane;
             const unsigned off = (unsigned)(base + (unsigned long long)__popcll(myw & ((1ull << lane) - 1ull)));
-            const int shot = shot_of_word(t, w);
-            const Shot& S = t.shots[shot];
             const unsigned key = (unsigned)(G - S.key_base);
             t.act_slot[off] = (int)G;
             t.act_shot[off] = shot;
