@@ -1413,24 +1413,36 @@ __global__ __launch_bounds__(64 * FAST_WORDS) void k_fast_plan(Tables t) {
         const long long w = (long long)c * FAST_WORDS + wid;
         const long long G = w * 64 + lane;
         const bool in_range = w < t.nwords;
+        const int shot = in_range ? shot_of_word(t, w) : 0;
+        const Shot S = t.shots[shot];
         const unsigned long long curw = in_range ? cur[w] : 0ull;
         const bool active = (curw >> lane) & 1ull;
         bool survive = false, in_dom = false;
-        int shot = 0, bx = 0, by = 0, bz = 0;
+        float c2u = 0.f;
+        int bx = 0, by = 0, bz = 0;
         if (in_range) {
-            shot = shot_of_word(t, w);
-            const Shot& S = t.shots[shot];
             key_to_block(S, (unsigned)(G - S.key_base), bx, by, bz);
             in_dom = bx < S.bx && by < S.by && bz < S.bz;
             if (in_dom) {
-                if (active)
-                    survive = (t.flags[G] & KEEP_BIT) != 0 || t.pin_until[2 * (size_t)(G)] > n + 1;
+                // every load of the decision at once (the key's flags, scalar
+                // C2 and pin, each neighbour's word and flags), then decide
+                const unsigned own = t.flags[G];
+                c2u = t.slot_c2u[G];
+                const int pin = active ? t.pin_until[2 * (size_t)(G)] : 0;
+                long long nk[6];
+                unsigned long long nwd[6];
+                unsigned nfl[6];
 #pragma unroll
                 for (int d = 0; d < 6; d++) {
-                    const long long nk = neighbour_key(S, bx, by, bz, d);
-                    if (nk >= 0 && ((cur[nk >> 6] >> (nk & 63)) & 1ull) && ((t.flags[nk] >> (d ^ 1)) & 1u))
-                        survive = true;
+                    nk[d] = neighbour_key(S, bx, by, bz, d);
+                    nwd[d] = nk[d] >= 0 ? cur[nk[d] >> 6] : 0ull;
+                    nfl[d] = nk[d] >= 0 ? t.flags[nk[d]] : 0u;
                 }
+                survive = active && ((own & KEEP_BIT) != 0 || pin > n + 1);
+#pragma unroll
+                for (int d = 0; d < 6; d++)
+                    if (nk[d] >= 0 && ((nwd[d] >> (nk[d] & 63)) & 1ull) && ((nfl[d] >> (d ^ 1)) & 1u))
+                        survive = true;
             }
         }
         const unsigned long long nw = __ballot(survive);
@@ -1464,11 +1476,12 @@ __global__ __launch_bounds__(64 * FAST_WORDS) void k_fast_plan(Tables t) {
             }
         }
         __syncthreads();
-        // in-domain nodes of the next set (and of its blocks with a scalar C2)
+        // in-domain nodes of the next set (and of its blocks with a scalar C2;
+        // a new block's scalar C2 is the one filling it left in slot_c2u)
         unsigned long long bc = 0, bu = 0;
         if (survive) {
-            bc = (unsigned long long)block_cells(t.shots[shot], bx, by, bz);
-            const float u = t.slot_c2u[G];
+            bc = (unsigned long long)block_cells(S, bx, by, bz);
+            const float u = active || t.c2_ready ? c2u : t.slot_c2u[G];
             if (u == u) bu = bc;
         }
         for (int o = 32; o > 0; o >>= 1) {
