@@ -1526,9 +1526,10 @@ __global__ __launch_bounds__(64 * FAST_WORDS) void k_fast_emit(Tables t) {
         }
         return;
     }
+    // the plan wrote every word of the next set (so neither bitmap is ever
+    // cleared: the current one becomes the plan's output two steps on)
     const int par = st->fast_par;
     const unsigned long long* nxt = fast_bm(t, par);
-    unsigned long long* old = fast_bm(t, 1 - par);
     const int lane = lane_id();
     const int wid = threadIdx.x >> 6;
     const int nf = t.nfchunks;
@@ -1563,6 +1564,21 @@ __global__ __launch_bounds__(64 * FAST_WORDS) void k_fast_emit(Tables t) {
             for (int q = 0; q < 6; q++) s_red[wid][q] = v6[q];
         }
         if (lane == 0) s_word[wid] = (unsigned)__popcll(myw);
+        // the rows' neighbour bits, loaded before the barrier so that they
+        // overlap the sums
+        const bool mine = (myw >> lane) & 1ull;
+        const long long G = w * 64 + lane;
+        const unsigned key = (unsigned)(G - S.key_base);
+        int nb[6] = {EMPTY, EMPTY, EMPTY, EMPTY, EMPTY, EMPTY};
+        int bx = 0, by = 0, bz = 0;
+        if (mine) {
+            key_to_block(S, key, bx, by, bz);
+#pragma unroll
+            for (int d = 0; d < 6; d++) {
+                const long long nk = neighbour_key(S, bx, by, bz, d);
+                nb[d] = (nk >= 0 && ((nxt[nk >> 6] >> (nk & 63)) & 1ull)) ? (int)nk : EMPTY;
+            }
+        }
         __syncthreads();
         unsigned long long base = 0, ntot = 0;
         for (int k = 0; k < FAST_WORDS; k++) {
@@ -1577,26 +1593,15 @@ __global__ __launch_bounds__(64 * FAST_WORDS) void k_fast_emit(Tables t) {
             nr += s_red[k][5];
         }
         for (int k = 0; k < wid; k++) base += s_word[k];
-        if ((myw >> lane) & 1ull) {
-            const long long G = w * 64 + lane;
+        if (mine) {
             const unsigned off = (unsigned)(base + (unsigned long long)__popcll(myw & ((1ull << lane) - 1ull)));
-            const unsigned key = (unsigned)(G - S.key_base);
             t.act_slot[off] = (int)G;
             t.act_shot[off] = shot;
             t.act_key[off] = key;
-            int bx, by, bz;
-            key_to_block(S, key, bx, by, bz);
-            int nb[6];
-#pragma unroll
-            for (int d = 0; d < 6; d++) {
-                const long long nk = neighbour_key(S, bx, by, bz, d);
-                nb[d] = (nk >= 0 && ((nxt[nk >> 6] >> (nk & 63)) & 1ull)) ? (int)nk : EMPTY;
-            }
             int4* rp = (int4*)(t.rows + 8 * (size_t)off);
             rp[0] = make_int4((int)G, nb[0], nb[1], nb[2]);
             rp[1] = make_int4(nb[3], nb[4], nb[5], (int)G);
         }
-        if (in_range && lane == 0) old[w] = 0ull;                 // act(n), reused as the set of step n + 2
         // commit (workgroup 0, once): no other workgroup of this launch reads
         // the fields it changes
         if (c == 0 && threadIdx.x == 0) {
