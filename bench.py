@@ -532,7 +532,7 @@ def bench_c5(args, tcm):
             achieved = alg / (ms * 1e-3) / 1e9
             roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "traffic": measured_traffic("k_block_step", "c5" + dom), "kernel": kname,
+                    "traffic": measured_traffic("k_block_step", "c5" + dom.replace("_", "")), "kernel": kname,
                     "avg_launch_us": round(ms * 1e3 / nl, 2),
                     "algorithmic_bytes_per_launch": round(alg / nl)}
             step_bytes = sum(v[0] for v in kern.values()) / nadj

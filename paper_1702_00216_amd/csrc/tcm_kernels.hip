@@ -330,6 +330,7 @@ __global__ __launch_bounds__(64 * W) void k_block_step(Tables t) {
     auto gidx = [&](int j) { return ((((j >> lg) << 3) + xcd) << lg) + (j & (grp - 1)); };
     const float trig = t.trigger, ret = t.retire;
     float wave_max = 0.f;
+    unsigned long long nonfinite = 0ull;       // lanes that wrote a NaN or infinity
     // adjoint field: nodes whose gradient term this workgroup formed
     __shared__ unsigned long long wg_terms;
     unsigned long long terms = 0;
@@ -569,17 +570,25 @@ __global__ __launch_bounds__(64 * W) void k_block_step(Tables t) {
                     }
                 }
             }
-            // column maxima of |phi^{n+1}| (NaN if the column holds one) and |phi^n|
+            // column maxima of |phi^{n+1}| and |phi^n|
             float colmax = fabsf(nv[0]), curmax = fabsf(cur[q][0]);
 #pragma unroll
             for (int z = 1; z < 8; z++) {
-                colmax = __builtin_elementwise_maximum(colmax, fabsf(nv[z]));
+                colmax = fmaxf(colmax, fabsf(nv[z]));
                 curmax = fmaxf(curmax, fabsf(cur[q][z]));
             }
             // a value that is not finite fails every level comparison, so its
-            // block would just be released and the value lost: stop the run
-            // after this step instead
-            if (__ballot(!(colmax <= 3.402823466e38f)) && lane == 0) atomicCAS(&t.st->nf_step, 0, n + 1);
+            // block would just be released and the value lost: the run stops
+            // after this step instead (recorded once per wave, after its
+            // loop).  An infinity makes the column maximum infinite; a NaN,
+            // which the maximum skips, makes the column's sum NaN (an
+            // overflowing sum of finite values is infinite, not NaN).  Both
+            // cost no more time than the maximum alone; a NaN-propagating
+            // maximum cost 1.8 % of the stencil's time on 16-byte nodes.
+            {
+                const float sum = ((nv[0] + nv[1]) + (nv[2] + nv[3])) + ((nv[4] + nv[5]) + (nv[6] + nv[7]));
+                nonfinite |= __ballot(sum != sum || !(colmax <= 3.402823466e38f));
+            }
 
             if constexpr (ADAPT) {
                 // per-block maxima (Table 1 Max_cell_val, per face and whole block);
@@ -621,6 +630,7 @@ __global__ __launch_bounds__(64 * W) void k_block_step(Tables t) {
     }
     if (ADAPT && lane == 0 && wave_max > 0.f)
         atomicMax((unsigned*)&t.st->maxbits, __float_as_uint(wave_max));   // non-negative floats order as integers
+    if (nonfinite && lane == 0) atomicCAS(&t.st->nf_step, 0, n + 1);
     if constexpr (MODE == STEP_GRAD) {
         // one slot per workgroup (a global atomic from every wave would
         // serialise on one address at the kernel's end)
