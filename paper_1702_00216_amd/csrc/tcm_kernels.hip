@@ -62,6 +62,15 @@ __device__ __forceinline__ bool halted_before(const DevState* st, int n) {
 }
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
+// A list row's last field is the global key, with bit 31 set when the slot
+// has sources in the source table (keys are below 2^31): the stencil loads
+// a block's pin and source range only then, instead of for every block.
+constexpr int ROW_SRC_BIT = (int)0x80000000u;
+__device__ __forceinline__ int row_key_field(const Tables& t, long long slot, long long G) {
+    return (int)G | (t.pin_until[2 * (size_t)slot + 1] >= 0 ? ROW_SRC_BIT : 0);
+}
+__device__ __forceinline__ int row_key(int v) { return v & 0x7fffffff; }
+
 // Read-only (for the reading kernel) tables addressed uniformly by a wave are
 // read through the scalar data cache: constant address space loads.
 template <class T>
@@ -343,8 +352,13 @@ __global__ __launch_bounds__(64 * W) void k_block_step(Tables t) {
     // the compaction; the next rows are fetched while the current blocks are
     // processed, so only the data loads sit on the critical path.
     const scalar_ptr<int> rows = as_scalar((const int*)t.rows);
-    // per slot {pin, first source}: one 8-byte scalar load for both (a second
-    // scalar load per block cost 2 % of the stencil's time)
+    // per slot {pin, first source}: one 8-byte scalar load for both, made
+    // only for blocks whose row says they have sources.  (Scalar loads share
+    // their wait counter with the LDS, so one that misses the scalar cache
+    // delays the block's LDS waits: loading it for every block cost 3.7 %
+    // of the stencil's time on the 64-shot batch, 1468 against 1415 us per
+    // launch, whose per-slot table is 21 MB; a second scalar load per block
+    // cost 2 % on the 512^3 workload.)
     const scalar_ptr<unsigned long long> pin_head = as_scalar((const unsigned long long*)t.pin_until);
     const scalar_ptr<float> slot_c2u = as_scalar((const float*)t.slot_c2u);
     const int stride = per * B;
@@ -378,6 +392,7 @@ __global__ __launch_bounds__(64 * W) void k_block_step(Tables t) {
     for (; ib < end; ib += stride, buf ^= 1) {
         bool have[P], share_m[P], share_p[P];
         int slot[P], nb[P][6], G[P], pinned[P], shead[P], li[P];
+        bool has_src[P];
         float cur[P][8], prv[P][8], k2[P][8], zlo[P], zhi[P];
         float* out_p[P];
         // adjoint field: L u^{m-1} of the forward block (fi: its entry in the
@@ -393,7 +408,8 @@ __global__ __launch_bounds__(64 * W) void k_block_step(Tables t) {
             slot[q] = r[q][0];
 #pragma unroll
             for (int d = 0; d < 6; d++) nb[q][d] = r[q][1 + d];
-            G[q] = r[q][7];
+            G[q] = row_key(r[q][7]);
+            has_src[q] = r[q][7] < 0;
             share_m[q] = have[q] && j > 0 && nb[q][0] >= 0 && nb[q][0] == sl_prev[q];
             share_p[q] = have[q] && j < B - 1 && nb[q][1] >= 0 && nb[q][1] == sl_next[q];
         }
@@ -426,7 +442,7 @@ __global__ __launch_bounds__(64 * W) void k_block_step(Tables t) {
                     }
                 }
             }
-            if (t.nsrc > 0) {
+            if (has_src[q]) {
                 const unsigned long long ph = pin_head[slot[q]];    // {pin, first source}
                 pinned[q] = (int)(unsigned)ph;
                 shead[q] = (int)(unsigned)(ph >> 32);
@@ -831,7 +847,7 @@ __global__ __launch_bounds__(256) void k_plan(Tables t) {
             nbs[0] = r0.y; nbs[1] = r0.z; nbs[2] = r0.w;
             nbs[3] = r1.x; nbs[4] = r1.y; nbs[5] = r1.z;
             shot = t.act_shot[i];
-            key = (unsigned)((long long)r1.w - t.shots[shot].key_base);
+            key = (unsigned)((long long)row_key(r1.w) - t.shots[shot].key_base);
             if (t.adaptive) {
                 const float* bm = t.bmax + 8 * (size_t)slot;
                 f = 0;
@@ -1328,7 +1344,7 @@ __global__ __launch_bounds__(64 * EMIT_WAVES) void k_emit(Tables t) {
                 }
                 int4* rp = (int4*)(t.rows + 8 * (size_t)off);
                 rp[0] = make_int4(slot, nb[0], nb[1], nb[2]);
-                rp[1] = make_int4(nb[3], nb[4], nb[5], (int)G);
+                rp[1] = make_int4(nb[3], nb[4], nb[5], row_key_field(t, slot, G));
             }
         } while (false);
         __syncthreads();                       // every wave has read the chunk
@@ -1580,8 +1596,9 @@ __global__ __launch_bounds__(64 * FAST_WORDS) void k_fast_emit(Tables t) {
         const long long G = w * 64 + lane;
         const unsigned key = (unsigned)(G - S.key_base);
         int nb[6] = {EMPTY, EMPTY, EMPTY, EMPTY, EMPTY, EMPTY};
-        int bx = 0, by = 0, bz = 0;
+        int bx = 0, by = 0, bz = 0, kf = 0;
         if (mine) {
+            kf = row_key_field(t, G, G);
             key_to_block(S, key, bx, by, bz);
 #pragma unroll
             for (int d = 0; d < 6; d++) {
@@ -1610,7 +1627,7 @@ __global__ __launch_bounds__(64 * FAST_WORDS) void k_fast_emit(Tables t) {
             t.act_key[off] = key;
             int4* rp = (int4*)(t.rows + 8 * (size_t)off);
             rp[0] = make_int4((int)G, nb[0], nb[1], nb[2]);
-            rp[1] = make_int4(nb[3], nb[4], nb[5], (int)G);
+            rp[1] = make_int4(nb[3], nb[4], nb[5], kf);
         }
         // commit (workgroup 0, once): no other workgroup of this launch reads
         // the fields it changes
@@ -1671,7 +1688,8 @@ __global__ void k_check_list(Tables t, int* mark, unsigned long long* bad) {
         nbad += t.cell2box[G] != s;
         nbad += t.slot_key[s] != G;
         nbad += t.rows[8 * (size_t)i] != s;
-        nbad += t.rows[8 * (size_t)i + 7] != (int)G;
+        nbad += row_key(t.rows[8 * (size_t)i + 7]) != (int)G;
+        nbad += (t.rows[8 * (size_t)i + 7] < 0) != (t.pin_until[2 * (size_t)s + 1] >= 0);
         int bx, by, bz;
         key_to_block(S, t.act_key[i], bx, by, bz);
         nbad += !(bx < S.bx && by < S.by && bz < S.bz);
@@ -1818,7 +1836,7 @@ __global__ void k_refresh_rows(Tables t) {
         }
         int4* rp = (int4*)(t.rows + 8 * (size_t)i);
         rp[0] = make_int4(t.act_slot[i], nb[0], nb[1], nb[2]);
-        rp[1] = make_int4(nb[3], nb[4], nb[5], (int)(S.key_base + (long long)key));
+        rp[1] = make_int4(nb[3], nb[4], nb[5], row_key_field(t, t.act_slot[i], S.key_base + (long long)key));
     }
 }
 
