@@ -69,7 +69,7 @@ enum {
     TCM_FLAG_THREE_PASS_UPDATE = 8, /* run the activation update as plan, allocation and
                                    compaction launches even where the two-launch update applies
                                    (constant levels, update every step, no shutdown, one pool
-                                   slot per block key, at most 2^20 keys); the results are the same */
+                                   slot per block key, at most 2^24 keys); the results are the same */
     TCM_FLAG_DEBUG_CHECKS = 16  /* tcm_step runs tcm_check at its end and returns TCM_E_STATE
                                    when a table invariant is violated */
 };

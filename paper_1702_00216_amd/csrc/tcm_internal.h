@@ -98,10 +98,16 @@ struct Tables {
     unsigned long long* bitmap2;    // two-launch update: the active set of odd steps
     int fast;                       // 1: the two-launch activation update (launch_fast_update)
     int nfchunks;                   // two-launch update: groups of FAST_WORDS bitmap words
-    int* fc_cnt;                    // per group: blocks of the next set,
+    int* fc_cnt;                    // per group: blocks of the next set
+    // up to FAST_DIRECT_CHUNKS groups, per group:
     int* fc_new;                    //   activations,
     int* fc_ret;                    //   releases,
-    unsigned long long* fc_cells;   //   in-domain nodes of the next set (all, then scalar-C2 blocks)
+    unsigned long long* fc_cells;   //   in-domain nodes of the next set (all, then scalar-C2 blocks);
+    // beyond, per run of FAST_BLK groups:
+    int nfblk;                      // runs (0: up to FAST_DIRECT_CHUNKS groups)
+    unsigned long long* fc_blk;     // [2][nfblk][2] per run, summed by the plan of an even / odd
+                                    // step: {blocks of the next set, activations, releases} (21 bits
+                                    // each), {its in-domain nodes, of scalar-C2 blocks} (32 bits each)
     long long nwords;
     int* act_slot;                  // active list (length n_act)
     int* act_shot;
@@ -192,10 +198,16 @@ hipError_t launch_pool_count(const Tables& t, int grid, hipStream_t s);   // gri
 hipError_t launch_emit(const Tables& t, int grid, hipStream_t s);
 // The activation update in two launches for constant levels, an update every
 // step, no shutdown and one slot per key (Tables::fast): k_fast_plan then
-// k_fast_emit (tcm_kernels.hip).  FAST_WORDS bitmap words per workgroup;
-// at most FAST_MAX_CHUNKS groups (each workgroup sums the groups' counts).
+// k_fast_emit (tcm_kernels.hip).  FAST_WORDS bitmap words per workgroup.
+// Up to FAST_DIRECT_CHUNKS groups each compaction workgroup sums the counts
+// of the groups before its own; beyond, the plan also sums the counts of
+// each run of FAST_BLK groups (device atomics), so that a compaction
+// workgroup finds its offset from at most FAST_MAX_CHUNKS / FAST_BLK run
+// sums and FAST_BLK - 1 group counts.
 constexpr int FAST_WORDS = 4;
-constexpr int FAST_MAX_CHUNKS = 4096;
+constexpr int FAST_DIRECT_CHUNKS = 4096;
+constexpr int FAST_BLK = 16;
+constexpr int FAST_MAX_CHUNKS = FAST_BLK * 4096;
 hipError_t launch_fast_update(const Tables& t, int grid, hipStream_t s);
 // Activate n blocks (distinct global keys; shot and key inside the shot per
 // entry), pin each while step < pins[i] and, where heads[i] >= 0, give it

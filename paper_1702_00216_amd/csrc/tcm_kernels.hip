@@ -229,6 +229,8 @@ __global__ void k_init_tables(Tables t, long long nkeys) {
         t.bitmap[i] = 0ull;
         if (t.fast) t.bitmap2[i] = 0ull;
     }
+    if (t.fast)
+        for (long long i = g0; i < 4ll * t.nfblk; i += gs) t.fc_blk[i] = 0ull;
     for (long long i = g0; i < t.cap; i += gs) {
         t.slot_key[i] = -1;
         t.pin_until[2 * (size_t)(i)] = 0;
@@ -1398,6 +1400,16 @@ __device__ __forceinline__ unsigned long long* fast_bm(const Tables& t, int par)
     return par ? t.bitmap2 : t.bitmap;
 }
 
+// A run's block, activation and release counts in one word, 21 bits each
+// (a run holds at most FAST_BLK * 256 keys); its in-domain node counts in
+// another, 32 bits each (at most FAST_BLK * 256 * 512 nodes).
+constexpr unsigned long long FAST_FIELD = (1ull << 21) - 1ull;
+static_assert(FAST_BLK * 64 * FAST_WORDS < (1 << 21) && FAST_BLK * 64 * FAST_WORDS * 512ll < (1ll << 32),
+              "run sums fit their fields");
+__device__ __forceinline__ unsigned long long fast_pack3(unsigned a, unsigned b, unsigned c) {
+    return (unsigned long long)a | ((unsigned long long)b << 21) | ((unsigned long long)c << 42);
+}
+
 __global__ __launch_bounds__(64 * FAST_WORDS) void k_fast_plan(Tables t) {
     DevState* st = t.st;
     __shared__ int s_new[64 * FAST_WORDS];
@@ -1528,10 +1540,20 @@ __global__ __launch_bounds__(64 * FAST_WORDS) void k_fast_plan(Tables t) {
                 cu += s_cellsu[k];
             }
             t.fc_cnt[c] = (int)cnt;
-            t.fc_new[c] = s_nnew;
-            t.fc_ret[c] = s_nret;
-            t.fc_cells[2 * (size_t)c] = cc;
-            t.fc_cells[2 * (size_t)c + 1] = cu;
+            if (t.nfblk) {
+                // the run's sums, two packed words (this step's parity; the
+                // compaction clears the other parity's for the next step)
+                unsigned long long* b = t.fc_blk + ((size_t)p * t.nfblk + (size_t)(c / FAST_BLK)) * 2;
+                const unsigned long long k3 = fast_pack3(cnt, (unsigned)s_nnew, (unsigned)s_nret);
+                const unsigned long long k2 = cc | (cu << 32);
+                if (k3) atomicAdd(&b[0], k3);
+                if (k2) atomicAdd(&b[1], k2);
+            } else {
+                t.fc_new[c] = s_nnew;
+                t.fc_ret[c] = s_nret;
+                t.fc_cells[2 * (size_t)c] = cc;
+                t.fc_cells[2 * (size_t)c + 1] = cu;
+            }
         }
         __syncthreads();                                   // LDS is reused by the next chunk
     }
@@ -1559,6 +1581,14 @@ __global__ __launch_bounds__(64 * FAST_WORDS) void k_fast_emit(Tables t) {
     const int lane = lane_id();
     const int wid = threadIdx.x >> 6;
     const int nf = t.nfchunks;
+    // the plan summed the runs into parity 1 - par; the next step's plan sums
+    // into parity par, cleared here (nothing in this launch reads it)
+    const unsigned long long* blk = t.fc_blk + (size_t)(1 - par) * t.nfblk * 2;
+    if (t.nfblk) {
+        unsigned long long* clr = t.fc_blk + (size_t)par * t.nfblk * 2;
+        const long long gs = (long long)gridDim.x * blockDim.x;
+        for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < 2ll * t.nfblk; k += gs) clr[k] = 0ull;
+    }
     for (int c = blockIdx.x; c < nf; c += gridDim.x) {          // uniform over the workgroup
         // this wave's word and its shot first: their loads overlap the sums below
         const long long w = (long long)c * FAST_WORDS + wid;
@@ -1566,23 +1596,46 @@ __global__ __launch_bounds__(64 * FAST_WORDS) void k_fast_emit(Tables t) {
         const unsigned long long myw = in_range ? nxt[w] : 0ull;
         const int shot = in_range ? shot_of_word(t, w) : 0;
         const Shot S = t.shots[shot];
-        // offset of this fast chunk in the next list; the workgroup of chunk 0
-        // also sums the list's length and the step's statistics
+        // offset of this fast chunk in the next list: the sums of the runs
+        // before its own, then the counts of its run's chunks before it (or,
+        // with up to FAST_DIRECT_CHUNKS chunks, the counts of all chunks
+        // before it); the workgroup of chunk 0 also sums the list's length
+        // and the step's statistics
         unsigned long long v6[6] = {0, 0, 0, 0, 0, 0};   // before, total, cells, scalar-C2 cells, new, released
-        if (c == 0) {
-            for (int k = threadIdx.x; k < nf; k += blockDim.x) {
-                v6[1] += (unsigned)t.fc_cnt[k];
-                v6[2] += t.fc_cells[2 * (size_t)k];
-                v6[3] += t.fc_cells[2 * (size_t)k + 1];
-                v6[4] += (unsigned)t.fc_new[k];
-                v6[5] += (unsigned)t.fc_ret[k];
+        if (!t.nfblk) {
+            if (c == 0) {
+                for (int k = threadIdx.x; k < nf; k += blockDim.x) {
+                    v6[1] += (unsigned)t.fc_cnt[k];
+                    v6[2] += t.fc_cells[2 * (size_t)k];
+                    v6[3] += t.fc_cells[2 * (size_t)k + 1];
+                    v6[4] += (unsigned)t.fc_new[k];
+                    v6[5] += (unsigned)t.fc_ret[k];
+                }
+                for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
+                    for (int q = 1; q < 6; q++) v6[q] += __shfl_xor(v6[q], o);
+                }
+            } else {
+                for (int k = threadIdx.x; k < c; k += blockDim.x) v6[0] += (unsigned)t.fc_cnt[k];
+                for (int o = 32; o > 0; o >>= 1) v6[0] += __shfl_xor(v6[0], o);
+            }
+        } else if (c == 0) {
+            for (int k = threadIdx.x; k < t.nfblk; k += blockDim.x) {
+                const unsigned long long k3 = blk[2 * (size_t)k], k2 = blk[2 * (size_t)k + 1];
+                v6[1] += k3 & FAST_FIELD;
+                v6[2] += k2 & 0xffffffffull;
+                v6[3] += k2 >> 32;
+                v6[4] += (k3 >> 21) & FAST_FIELD;
+                v6[5] += k3 >> 42;
             }
             for (int o = 32; o > 0; o >>= 1) {
 #pragma unroll
                 for (int q = 1; q < 6; q++) v6[q] += __shfl_xor(v6[q], o);
             }
         } else {
-            for (int k = threadIdx.x; k < c; k += blockDim.x) v6[0] += (unsigned)t.fc_cnt[k];
+            const int cb = c / FAST_BLK;
+            for (int k = threadIdx.x; k < cb; k += blockDim.x) v6[0] += blk[2 * (size_t)k] & FAST_FIELD;
+            for (int k = cb * FAST_BLK + (int)threadIdx.x; k < c; k += blockDim.x) v6[0] += (unsigned)t.fc_cnt[k];
             for (int o = 32; o > 0; o >>= 1) v6[0] += __shfl_xor(v6[0], o);
         }
         if (lane == 0) {

@@ -375,9 +375,15 @@ tcm_status setup_engine(tcm_handle* h, long long word_base) {
     if (t.fast) {
         ok = ok && dalloc(h, &t.bitmap2, (size_t)t.nchunks * CHUNK_WORDS) == hipSuccess;
         ok = ok && dalloc(h, &t.fc_cnt, (size_t)t.nfchunks) == hipSuccess;
-        ok = ok && dalloc(h, &t.fc_new, (size_t)t.nfchunks) == hipSuccess;
-        ok = ok && dalloc(h, &t.fc_ret, (size_t)t.nfchunks) == hipSuccess;
-        ok = ok && dalloc(h, &t.fc_cells, 2 * (size_t)t.nfchunks) == hipSuccess;
+        if (t.nfchunks <= FAST_DIRECT_CHUNKS) {
+            t.nfblk = 0;
+            ok = ok && dalloc(h, &t.fc_new, (size_t)t.nfchunks) == hipSuccess;
+            ok = ok && dalloc(h, &t.fc_ret, (size_t)t.nfchunks) == hipSuccess;
+            ok = ok && dalloc(h, &t.fc_cells, 2 * (size_t)t.nfchunks) == hipSuccess;
+        } else {
+            t.nfblk = (t.nfchunks + FAST_BLK - 1) / FAST_BLK;
+            ok = ok && dalloc(h, &t.fc_blk, 4 * (size_t)t.nfblk) == hipSuccess;
+        }
     }
     ok = ok && dalloc(h, &t.act_slot, (size_t)cap) == hipSuccess;
     ok = ok && dalloc(h, &t.act_shot, (size_t)cap) == hipSuccess;

@@ -693,6 +693,69 @@ def test_two_launch_update_equals_three_pass_every_step(levels):
     assert values_equal(sims[0].read_traces(), sims[1].read_traces())
 
 
+def test_two_launch_update_over_many_runs_of_chunks():
+    """A batch of three shots with 225 groups of 256 keys (15 runs of 16
+    groups, whose sums give each compaction workgroup its offset): the
+    two-launch update and the three-pass update give the same counts and work
+    every step and the same fields, as the wave crosses the runs."""
+    announce("two-launch vs three-pass update, 225 key groups")
+    shapes = [(200, 180, 160), (150, 210, 130), (256, 256, 256)]
+    media = [ti.random_media(s, seed=60 + i, cmin=0.5, cmax=1.0) for i, s in enumerate(shapes)]
+    w = ti.ricker(0.1, 0.5).w32
+    sims = [tcm.Simulation(shapes, 1.0, 0.5, media, np.float32(1e-4), np.float32(1e-5), three_pass_update=tp)
+            for tp in (False, True)]
+    for sim in sims:
+        sim.add_source((100, 90, 80), w, shot=0)
+        sim.add_source((75, 105, 65), -w, shot=1)
+        sim.add_source((128, 130, 126), w, shot=2)
+        sim.add_source((20, 240, 30), 0.5 * w, shot=2)
+    keys = ("step", "active_blocks", "activations", "retirements", "cell_updates", "peak_active_blocks")
+    for k in range(160):
+        for sim in sims:
+            sim.step(1)
+        a, b = sims[0].stats(), sims[1].stats()
+        for key in keys:
+            assert a[key] == b[key], (k, key)
+    assert sims[0].stats()["active_blocks"] > 2000
+    assert sims[0].check() == 0
+    for shot in range(3):
+        assert values_equal(sims[0].read(0, shot=shot), sims[1].read(0, shot=shot))
+        assert values_equal(sims[0].read(1, shot=shot), sims[1].read(1, shot=shot))
+
+
+def test_two_launch_update_with_run_sums():
+    """Five 512^3 shots in one handle: 5120 groups of 256 keys, beyond the
+    4096 whose counts a compaction workgroup sums directly, so the plan also
+    sums runs of 16 groups with device atomics and the compaction takes its
+    offset from those.  Counts and work equal the three-pass update every
+    step, and the fields equal it at the end."""
+    announce("two-launch (run sums) vs three-pass update, 5 x 512^3 shots")
+    shapes = [(512, 512, 512)] * 5
+    lay = ti.LayeredMedia(np.array([0, 200, 330], np.int32), np.array([1500, 3000, 2200], np.float32))
+    dt = 0.5 / 3000
+    w = ti.ricker(250.0, dt).w32
+    srcs = [(256, 256, 256), (5, 7, 9), (500, 250, 60), (130, 480, 400), (255, 255, 320)]
+    sims = [tcm.Simulation(shapes, 1.0, dt, [lay] * 5, np.float32(1e-5), np.float32(1e-6), three_pass_update=tp)
+            for tp in (False, True)]
+    for sim in sims:
+        for i, xyz in enumerate(srcs):
+            sim.add_source(xyz, (1.0 - 0.3 * i) * w, shot=i)
+    keys = ("step", "active_blocks", "activations", "retirements", "cell_updates", "peak_active_blocks")
+    for k in range(150):
+        for sim in sims:
+            sim.step(1)
+        a, b = sims[0].stats(), sims[1].stats()
+        for key in keys:
+            assert a[key] == b[key], (k, key)
+    assert sims[0].stats()["active_blocks"] > 1000
+    assert sims[0].check() == 0
+    for shot in range(5):
+        assert values_equal(sims[0].read(0, shot=shot), sims[1].read(0, shot=shot))
+        assert values_equal(sims[0].read(1, shot=shot), sims[1].read(1, shot=shot))
+    for sim in sims:
+        sim.close()
+
+
 def block_key(shape, bx, by, bz):
     """Key of block (bx, by, bz): blocks in 4x4x4 tiles, tiles x-fastest,
     blocks inside a tile x-fastest (one pool slot per key when the pool holds
