@@ -89,6 +89,7 @@ struct Tables {
     DevState* st;
     const Shot* shots;
     int nshots;
+    const int* word_shot;           // per bitmap word: its shot (nullptr with one shot)
     int cap;                        // pool slots
     long long nkeys;                // global block keys (all shots)
     float* pool;

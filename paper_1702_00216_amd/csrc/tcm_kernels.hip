@@ -211,8 +211,10 @@ __device__ float fill_slot(const Tables& t, const Shot& S, long long slot, int b
 // --------------------------------------------------------------------------
 // table initialisation
 // --------------------------------------------------------------------------
-// shot owning bitmap word w (shots own consecutive key ranges)
+// shot owning bitmap word w (shots own consecutive key ranges): the word's
+// entry of the table, or a search over the shots
 __device__ __forceinline__ int shot_of_word(const Tables& t, long long w) {
+    if (t.word_shot) return t.word_shot[w];
     int lo = 0, hi = t.nshots - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;

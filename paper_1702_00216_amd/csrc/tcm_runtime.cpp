@@ -326,6 +326,20 @@ tcm_status setup_engine(tcm_handle* h, long long word_base) {
         return set_err(h, TCM_E_ARG, "more than 2^31 block keys: grid too large for one handle");
     t.nwords = word_base;
     t.nchunks = (int)((word_base + CHUNK_WORDS - 1) / CHUNK_WORDS);
+    // with several shots, the shot of every bitmap word (one load for the
+    // management kernels instead of a search over the shots)
+    t.word_shot = nullptr;
+    if (nshots > 1) {
+        std::vector<int> ws((size_t)word_base);
+        for (int i = 0; i < nshots; i++)
+            for (long long w = h->shots[i].word_base; w < h->shots[i].word_base + h->shots[i].nwords; w++)
+                ws[(size_t)w] = i;
+        int* d = nullptr;
+        if (dalloc(h, &d, ws.size()) != hipSuccess) return set_err(h, TCM_E_NOMEM, "device allocation failed");
+        if (hipMemcpy(d, ws.data(), ws.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
+            return dev_fail(h, hipGetLastError(), "hipMemcpy(word_shot)");
+        t.word_shot = d;
+    }
     size_t free_b = 0, total_b = 0;
     (void)hipMemGetInfo(&free_b, &total_b);
     // per-slot bookkeeping bytes besides the 6 KiB slot
