@@ -54,7 +54,9 @@ struct Shot {
 struct DevState {
     int step, n_act, n_new, n_ret;
     int free_cnt, error, err_step, emit;
-    int peak_act, done_wgs, add_error, n_dec;
+    int peak_act, add_error, n_dec;
+    unsigned long long scan_acc;     // k_pool_count: scanning workgroups arrived (high 32 bits) and
+                                     // their range totals (low 32 bits); 0 between steps
     unsigned long long cells_cur;    // in-domain nodes of the current active list
     unsigned long long updates;      // in-domain nodes stepped so far
     unsigned long long cells_cur_u;  // ... of those, nodes of blocks with a uniform C2
@@ -137,8 +139,8 @@ struct Tables {
     long long* ret_key;             //   ... and the global keys they held
     unsigned* partial;              // per 16-word chunk: set bits, then offset inside its range
     int nchunks;                    // ceil(nwords / 16); the bitmap is padded to whole chunks
-    unsigned* wg_total;             // per k_pool_count workgroup: set bits of its chunk range,
-                                    // then the offset of the range in the next list
+    unsigned* wg_total;             // per k_pool_count workgroup: set bits of its chunk range
+                                    // (k_emit scans them into the ranges' offsets)
     int chunks_per_wg;              // chunks per scanning k_pool_count workgroup (contiguous)
     int scan_wgs;                   // the first scan_wgs workgroups of k_pool_count scan
     int* ne_chunks;                 // per step: the chunks with a set bit (any order)

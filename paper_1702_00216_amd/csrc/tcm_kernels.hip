@@ -245,7 +245,7 @@ __global__ void k_init_tables(Tables t, long long nkeys) {
         DevState* st = t.st;
         st->step = 0; st->n_act = 0; st->n_new = 0; st->n_ret = 0;
         st->free_cnt = t.cap; st->error = 0; st->err_step = -1; st->emit = 0; st->nf_step = 0;
-        st->peak_act = 0; st->done_wgs = 0; st->add_error = 0; st->n_dec = 0;
+        st->peak_act = 0; st->scan_acc = 0; st->add_error = 0; st->n_dec = 0;
         st->cells_cur = 0; st->updates = 0; st->activations = 0; st->retirements = 0;
         st->cells_cur_u = 0; st->updates_u = 0; st->decays = 0;
         st->maxbits = 0u; st->trig_cur = t.trigger; st->ret_cur = t.retire; st->n_ne = 0;
@@ -1049,7 +1049,6 @@ __device__ void commit_step(const Tables& t, DevState* st, int nn, int nr, int n
 __global__ __launch_bounds__(256) void k_pool_count(Tables t) {
     DevState* st = t.st;
     __shared__ unsigned red[4];
-    __shared__ int last;
     const int lane = lane_id();
     const int wid = threadIdx.x >> 6;
     const int err0 = st->error || st->nf_step;
@@ -1128,8 +1127,8 @@ __global__ __launch_bounds__(256) void k_pool_count(Tables t) {
     // rest only allocate).  Workgroup g owns chunks [g * C, g * C + C): each
     // thread counts a contiguous run of them, the workgroup scans the runs
     // and stores every chunk's offset inside the range and the range total;
-    // the last scanning workgroup to finish turns the totals into range
-    // offsets and commits the step.
+    // the last scanning workgroup to finish commits the step, and the
+    // compaction turns the range totals into range offsets.
     const int nw = blockDim.x >> 6;
     do {
         if ((int)blockIdx.x >= t.scan_wgs) break;
@@ -1176,7 +1175,7 @@ __global__ __launch_bounds__(256) void k_pool_count(Tables t) {
                 run += cnt1[k];
             }
             if (threadIdx.x == 0) {
-                t.wg_total[0] = 0u;
+                t.wg_total[0] = 0u;            // offsets are global: one range
                 commit_step(t, st, nn, nr, nfree, total);
             }
             break;
@@ -1223,43 +1222,17 @@ __global__ __launch_bounds__(256) void k_pool_count(Tables t) {
             t.partial[c] = run;
             run += v;
         }
-        if (threadIdx.x == 0) t.wg_total[blockIdx.x] = wg_sum;
-        __syncthreads();
         if (threadIdx.x == 0) {
-            __threadfence();
-            last = atomicAdd(&st->done_wgs, 1) == t.scan_wgs - 1;
-        }
-        __syncthreads();
-        if (!last) break;
-        __threadfence();
-
-        // last scanning workgroup: exclusive scan of the range totals (at most
-        // 1024, each thread a contiguous run), then commit the step
-        const int ng = t.scan_wgs;
-        const int per = (ng + (int)blockDim.x - 1) / (int)blockDim.x;
-        const int g0 = min(ng, (int)threadIdx.x * per), g1 = min(ng, g0 + per);
-        unsigned mine = 0;
-        for (int g = g0; g < g1; g++) mine += __atomic_load_n(&t.wg_total[g], __ATOMIC_RELAXED);
-        incl = mine;
-        for (int o = 1; o < 64; o <<= 1) {
-            const unsigned u = __shfl_up(incl, o);
-            if (lane >= o) incl += u;
-        }
-        __syncthreads();                       // red[] is reused
-        if (lane == 63) red[wid] = incl;
-        __syncthreads();
-        run = incl - mine;
-        for (int w = 0; w < wid; w++) run += red[w];
-        unsigned total = 0;
-        for (int w = 0; w < nw; w++) total += red[w];
-        for (int g = g0; g < g1; g++) {
-            const unsigned v = __atomic_load_n(&t.wg_total[g], __ATOMIC_RELAXED);
-            t.wg_total[g] = run;
-            run += v;
-        }
-        if (threadIdx.x == 0) {
-            st->done_wgs = 0;
-            commit_step(t, st, nn, nr, nfree, total);
+            t.wg_total[blockIdx.x] = wg_sum;
+            // arrival and range total in one atomic: the last scanning
+            // workgroup reads the list's length from its own return value, so
+            // no workgroup needs a device-scope release (an L2 write-back per
+            // workgroup on gfx950); the compaction scans the range totals
+            const unsigned long long old = atomicAdd(&st->scan_acc, (1ull << 32) | (unsigned long long)wg_sum);
+            if ((int)(old >> 32) == t.scan_wgs - 1) {
+                st->scan_acc = 0ull;
+                commit_step(t, st, nn, nr, nfree, (unsigned)old + wg_sum);
+            }
         }
     } while (false);
 }
@@ -1285,9 +1258,27 @@ constexpr int EMIT_WAVES = CHUNK_WORDS;
 __global__ __launch_bounds__(64 * EMIT_WAVES) void k_emit(Tables t) {
     DevState* st = t.st;
     __shared__ unsigned long long csum[EMIT_WAVES], usum[EMIT_WAVES];
+    __shared__ unsigned s_rng[POOL_COUNT_MAX_WG], s_wsum[EMIT_WAVES];
+    static_assert(POOL_COUNT_MAX_WG <= 64 * EMIT_WAVES, "one range total per thread");
     const int lane = lane_id();
     const int wid = threadIdx.x >> 6;
     const int emit = st->emit;
+    {
+        // offsets of the allocator's chunk ranges: exclusive scan of their totals
+        const int g = threadIdx.x;
+        const unsigned v = g < t.scan_wgs ? t.wg_total[g] : 0u;
+        unsigned incl = v;
+        for (int o = 1; o < 64; o <<= 1) {
+            const unsigned u = __shfl_up(incl, o);
+            if (lane >= o) incl += u;
+        }
+        if (lane == 63) s_wsum[wid] = incl;
+        __syncthreads();
+        unsigned off = 0;
+        for (int w = 0; w < wid; w++) off += s_wsum[w];
+        if (g < t.scan_wgs) s_rng[g] = off + incl - v;
+        __syncthreads();
+    }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         // the allocator has finished: its free count and cleared step counters
         st->free_cnt = st->free_next;
@@ -1311,7 +1302,7 @@ __global__ __launch_bounds__(64 * EMIT_WAVES) void k_emit(Tables t) {
             const unsigned u = __shfl_up(incl, o);
             if (lane >= o) incl += u;
         }
-        const unsigned base = emit ? t.wg_total[chunk / t.chunks_per_wg] + t.partial[chunk] : 0u;
+        const unsigned base = emit ? s_rng[chunk / t.chunks_per_wg] + t.partial[chunk] : 0u;
         const int j = wid;                      // the wave's own word
         do {
             const unsigned long long m = __shfl(myword, j);
