@@ -1335,12 +1335,14 @@ __global__ __launch_bounds__(64 * EMIT_WAVES) void k_emit(Tables t) {
                 cells += bc;
                 const float u = t.slot_c2u[slot];
                 if (u == u) ucells += bc;
+                long long nk[6];
                 int nb[6];
 #pragma unroll
-                for (int d = 0; d < 6; d++) {
-                    const long long nk = neighbour_key(S, bx, by, bz, d);
-                    nb[d] = nk >= 0 ? t.cell2box[nk] : EMPTY;
-                }
+                for (int d = 0; d < 6; d++) nk[d] = neighbour_key(S, bx, by, bz, d);
+#pragma unroll
+                for (int d = 0; d < 6; d++) nb[d] = t.cell2box[nk[d] >= 0 ? nk[d] : G];   // all loads at once
+#pragma unroll
+                for (int d = 0; d < 6; d++) if (nk[d] < 0) nb[d] = EMPTY;
                 int4* rp = (int4*)(t.rows + 8 * (size_t)off);
                 rp[0] = make_int4(slot, nb[0], nb[1], nb[2]);
                 rp[1] = make_int4(nb[3], nb[4], nb[5], row_key_field(t, slot, G));
@@ -1469,11 +1471,15 @@ __global__ __launch_bounds__(64 * FAST_WORDS) void k_fast_plan(Tables t) {
                 long long nk[6];
                 unsigned long long nwd[6];
                 unsigned nfl[6];
+                // (a missing neighbour loads the key's own entries, ignored
+                // below: conditional loads compile to branches that wait
+                // after each load)
 #pragma unroll
                 for (int d = 0; d < 6; d++) {
                     nk[d] = neighbour_key(S, bx, by, bz, d);
-                    nwd[d] = nk[d] >= 0 ? cur[nk[d] >> 6] : 0ull;
-                    nfl[d] = nk[d] >= 0 ? t.flags[nk[d]] : 0u;
+                    const long long kk = nk[d] >= 0 ? nk[d] : G;
+                    nwd[d] = cur[kk >> 6];
+                    nfl[d] = t.flags[kk];
                 }
                 survive = active && ((own & KEEP_BIT) != 0 || pin > n + 1);
 #pragma unroll
@@ -1685,11 +1691,14 @@ __global__ __launch_bounds__(64 * FAST_WORDS) void k_fast_emit(Tables t) {
         if (mine) {
             kf = row_key_field(t, G, G);
             key_to_block(S, key, bx, by, bz);
+            long long nk[6];
+            unsigned long long nw[6];
 #pragma unroll
-            for (int d = 0; d < 6; d++) {
-                const long long nk = neighbour_key(S, bx, by, bz, d);
-                nb[d] = (nk >= 0 && ((nxt[nk >> 6] >> (nk & 63)) & 1ull)) ? (int)nk : EMPTY;
-            }
+            for (int d = 0; d < 6; d++) nk[d] = neighbour_key(S, bx, by, bz, d);
+#pragma unroll
+            for (int d = 0; d < 6; d++) nw[d] = nxt[(nk[d] >= 0 ? nk[d] : G) >> 6];   // all loads at once
+#pragma unroll
+            for (int d = 0; d < 6; d++) nb[d] = (nk[d] >= 0 && ((nw[d] >> (nk[d] & 63)) & 1ull)) ? (int)nk[d] : EMPTY;
         }
         __syncthreads();
         unsigned long long base = 0, ntot = 0;
