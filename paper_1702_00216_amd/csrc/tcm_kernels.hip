@@ -870,14 +870,15 @@ __global__ __launch_bounds__(256) void k_plan(Tables t) {
             survive = (f & KEEP_BIT) != 0 || t.pin_until[2 * (size_t)(slot)] > n + 1;
         }
         if (t.interval <= 1) {
-            // an active neighbour whose face toward us is above trigger keeps us
+            // an active neighbour whose face toward us is above trigger keeps
+            // us (a missing neighbour loads the entry's own slot, ignored:
+            // conditional loads compile to a wait after each)
 #pragma unroll
             for (int d = 0; d < 6; d++) {
-                if (nbs[d] >= 0) {
-                    const bool face = t.adaptive ? t.bmax[8 * (size_t)nbs[d] + (d ^ 1)] > trig
-                                                 : ((t.flags[nbs[d]] >> (d ^ 1)) & 1u) != 0;
-                    if (face) survive = true;
-                }
+                const int s2 = nbs[d] >= 0 ? nbs[d] : slot;
+                const bool face = t.adaptive ? t.bmax[8 * (size_t)s2 + (d ^ 1)] > trig
+                                             : ((t.flags[s2] >> (d ^ 1)) & 1u) != 0;
+                if (nbs[d] >= 0 && face) survive = true;
             }
             for (int d = 0; d < 6; d++) {
                 bool claim = false;
@@ -900,30 +901,46 @@ __global__ __launch_bounds__(256) void k_plan(Tables t) {
             // per step, so a block that is hot (or still inserting a source)
             // must have all 26 nearest and diagonal neighbours active
             const bool hot = valid && (((f & HOT_BIT) != 0) || t.pin_until[2 * (size_t)(slot)] > n + 1);
+            // the 26 neighbours, a layer of nine at a time: their keys and
+            // slots, then their flags and pins, each set of loads issued
+            // together (a missing neighbour loads the entry's own key and
+            // slot, ignored; loads under a condition compile to a wait after
+            // each)
+            const Shot& S = t.shots[shot];
+            const int own = (int)(S.key_base + (long long)key);
+            int nk26[27], s26[27];
+#pragma unroll
+            for (int zl = 0; zl < 3; zl++) {
+#pragma unroll
+                for (int j = 0; j < 9; j++) {
+                    const int d = zl * 9 + j;
+                    const int x2 = bx + d % 3 - 1, y2 = by + (d / 3) % 3 - 1, z2 = bz + d / 9 - 1;
+                    const bool in = valid && d != 13 && x2 >= 0 && y2 >= 0 && z2 >= 0 && x2 < S.bx &&
+                                    y2 < S.by && z2 < S.bz;
+                    nk26[d] = in ? (int)(S.key_base + (long long)block_to_key(S, x2, y2, z2)) : -1;
+                }
+                int sl[9];
+#pragma unroll
+                for (int j = 0; j < 9; j++) sl[j] = t.cell2box[nk26[zl * 9 + j] >= 0 ? nk26[zl * 9 + j] : own];
+                bool nh[9];
+#pragma unroll
+                for (int j = 0; j < 9; j++) {
+                    const int s2 = sl[j] >= 0 ? sl[j] : slot;
+                    const bool fh = t.adaptive ? (t.bmax[8 * (size_t)s2 + 6] > trig || t.bmax[8 * (size_t)s2 + 7] > trig)
+                                               : (t.flags[s2] & HOT_BIT) != 0;
+                    nh[j] = fh || t.pin_until[2 * (size_t)s2] > n + 1;
+                }
+#pragma unroll
+                for (int j = 0; j < 9; j++) {
+                    s26[zl * 9 + j] = sl[j];
+                    if (nk26[zl * 9 + j] >= 0 && sl[j] >= 0 && nh[j]) survive = true;
+                }
+            }
             for (int d = 0; d < 27; d++) {
                 if (d == 13) continue;
                 bool claim = false;
-                long long nk = -1;
-                if (valid) {
-                    const Shot& S = t.shots[shot];
-                    const int x2 = bx + d % 3 - 1, y2 = by + (d / 3) % 3 - 1, z2 = bz + d / 9 - 1;
-                    if (x2 >= 0 && y2 >= 0 && z2 >= 0 && x2 < S.bx && y2 < S.by && z2 < S.bz) {
-                        nk = S.key_base + (long long)block_to_key(S, x2, y2, z2);
-                        const int s_nb = t.cell2box[nk];
-                        if (s_nb >= 0) {
-                            bool nhot;
-                            if (t.adaptive) {
-                                const float* bm = t.bmax + 8 * (size_t)s_nb;
-                                nhot = bm[6] > trig || bm[7] > trig;
-                            } else {
-                                nhot = (t.flags[s_nb] & HOT_BIT) != 0;
-                            }
-                            if (nhot || t.pin_until[2 * (size_t)(s_nb)] > n + 1) survive = true;
-                        } else if (hot && s_nb == EMPTY) {
-                            claim = atomicCAS(&t.cell2box[nk], EMPTY, CLAIMED) == EMPTY;
-                        }
-                    }
-                }
+                const long long nk = nk26[d];
+                if (nk >= 0 && hot && s26[d] == EMPTY) claim = atomicCAS(&t.cell2box[nk], EMPTY, CLAIMED) == EMPTY;
                 const int k = wave_append(&st->n_new, claim);
                 if (claim) {
                     if (k < t.cap) {
