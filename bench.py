@@ -26,6 +26,19 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_UPDATE = 16          # read phi^n, phi^{n-1}, C2; write phi^{n+1} (FP32)
+# Bytes per lattice-record block (8 FP64 corners + 4 int32 offsets), read
+# instead of its 2 KiB C2 plane; such blocks have all 512 nodes in the domain.
+LAT_RECORD_BYTES = 80
+
+
+def stencil_bytes(cells, cells_u, cells_l, per_node=BYTES_PER_UPDATE):
+    """Algorithmic bytes of stencil launches that updated `cells` nodes:
+    per_node bytes each (phi^n and phi^{n-1} read, phi^{n+1} written, the C2
+    plane read), 4 B less for nodes of blocks with a uniform C2 (a scalar)
+    and for nodes of blocks with a lattice record (80 B per 512 nodes)."""
+    return per_node * cells - 4 * cells_u - (4 - LAT_RECORD_BYTES / 512) * cells_l
+
+
 
 
 def log(msg: str):
@@ -190,6 +203,11 @@ def cpu_baseline(w, budget_s: float):
                             "sample": f"steps 0-{done1} ({st1['updates']:.3e} updates in {el1:.1f} s)"}}
 
 
+def two_to_one_fraction(roof):
+    """Nodes streamed 2 reads : 1 write (uniform C2 or a lattice record)."""
+    return roof["uniform_c2_node_fraction"] + roof.get("lattice_record_node_fraction", 0.0)
+
+
 def add_ceiling(tcm, roof, fu=None):
     """The achievable HBM ceiling of a streaming kernel with the stencil's
     read:write mix (tcm_hbm_probe): the best of a few grid sizes for each mix
@@ -234,7 +252,7 @@ def bench_c3(args, tcm):
     steps = args.time_steps or w.steps
     log(f"c3 media lattice {w.lattice.lattice.shape} built in {time.perf_counter() - t0:.1f} s")
     sim = tcm.Simulation(w.shape, w.dx, w.dt, w.lattice, w.trigger, w.retire,
-                         pool_bytes=w.pool_bytes, timing=True, wg_per_cu=args.wg_per_cu)
+                         pool_bytes=w.pool_bytes, timing=True, wg_per_cu=args.wg_per_cu, c2_planes=args.c2_planes)
     sim.add_source(w.source, w.wavelet.w32)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -254,16 +272,17 @@ def bench_c3(args, tcm):
     st = sim.stats()
     sim.close()
     nx, ny, nz = w.shape
-    alg = BYTES_PER_UPDATE * st["stencil_cells"] - 4 * st["stencil_cells_uniform"]
+    alg = stencil_bytes(st["stencil_cells"], st["stencil_cells_uniform"], st["stencil_cells_lattice"])
     achieved = alg / (st["stencil_ms"] * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
             "kernel": "k_block_step",
             "avg_launch_us": round(st["stencil_ms"] * 1e3 / max(st["stencil_launches"], 1), 2),
             "algorithmic_bytes_per_launch": round(alg / max(st["stencil_launches"], 1)),
-            "uniform_c2_node_fraction": round(st["stencil_cells_uniform"] / max(st["stencil_cells"], 1), 4)}
+            "uniform_c2_node_fraction": round(st["stencil_cells_uniform"] / max(st["stencil_cells"], 1), 4),
+            "lattice_record_node_fraction": round(st["stencil_cells_lattice"] / max(st["stencil_cells"], 1), 4)}
     if not args.no_probe:
-        add_ceiling(tcm, roof)
+        add_ceiling(tcm, roof, two_to_one_fraction(roof))
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline_crop(w, args.cpu_budget)
@@ -316,7 +335,7 @@ def bench_c4(args, tcm):
     shapes = [s.shape for s in shots]
     media = [s.lattice for s in shots]
     sim = tcm.Simulation(shapes, 1.0, w0.dt, media, w0.trigger, w0.retire,
-                         wg_per_cu=args.wg_per_cu, graph_steps=args.graph_steps,
+                         wg_per_cu=args.wg_per_cu, graph_steps=args.graph_steps, c2_planes=args.c2_planes,
                          blocks_per_wg=args.blocks_per_wg, blocks_per_wave=args.blocks_per_wave)
 
     def run_batch():
@@ -375,7 +394,7 @@ def bench_c4(args, tcm):
         log(f"c4 one-by-one: {t_seq:.3f} s")
     # the stencil's achieved bandwidth: one more batch run with per-launch
     # events (16 B per node: lognormal C2 is not uniform over a block)
-    tsim = tcm.Simulation(shapes, 1.0, w0.dt, media, w0.trigger, w0.retire, timing=True,
+    tsim = tcm.Simulation(shapes, 1.0, w0.dt, media, w0.trigger, w0.retire, timing=True, c2_planes=args.c2_planes,
                           wg_per_cu=(tuning or {}).get("wg_per_cu", args.wg_per_cu),
                           blocks_per_wg=(tuning or {}).get("blocks_per_wg", args.blocks_per_wg),
                               blocks_per_wave=(tuning or {}).get("blocks_per_wave", args.blocks_per_wave))
@@ -384,15 +403,16 @@ def bench_c4(args, tcm):
     tsim.step(steps)
     ts = tsim.stats()
     tsim.close()
-    alg = BYTES_PER_UPDATE * ts["stencil_cells"] - 4 * ts["stencil_cells_uniform"]
+    alg = stencil_bytes(ts["stencil_cells"], ts["stencil_cells_uniform"], ts["stencil_cells_lattice"])
     achieved = alg / (ts["stencil_ms"] * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_block_step",
             "avg_launch_us": round(ts["stencil_ms"] * 1e3 / max(ts["stencil_launches"], 1), 2),
             "algorithmic_bytes_per_launch": round(alg / max(ts["stencil_launches"], 1)),
-            "uniform_c2_node_fraction": round(ts["stencil_cells_uniform"] / max(ts["stencil_cells"], 1), 4)}
+            "uniform_c2_node_fraction": round(ts["stencil_cells_uniform"] / max(ts["stencil_cells"], 1), 4),
+            "lattice_record_node_fraction": round(ts["stencil_cells_lattice"] / max(ts["stencil_cells"], 1), 4)}
     if not args.no_probe:
-        add_ceiling(tcm, roof)
+        add_ceiling(tcm, roof, two_to_one_fraction(roof))
     cpu = None
     if not args.no_cpu:
         # the CPU TCM oracle on shot 0 (the same media, thresholds and steps), bounded
@@ -438,9 +458,12 @@ def bench_c5(args, tcm):
         resid = np.load(p)
     else:
         resid = np.random.default_rng(55).standard_normal((steps, len(w.receivers))).astype(np.float32)
-    sim = tcm.Simulation(w.shape, w.dx, w.dt, c, checkpoint_every=50, wg_per_cu=args.wg_per_cu,
+    # the GPU runs take the lattice itself (C2 from lattice records where the
+    # block lies in one lattice cell; the same values as the dense c)
+    media = w.lattice
+    sim = tcm.Simulation(w.shape, w.dx, w.dt, media, checkpoint_every=50, wg_per_cu=args.wg_per_cu,
                          blocks_per_wg=args.blocks_per_wg, blocks_per_wave=args.blocks_per_wave,
-                         trigger_interval=args.interval)
+                         trigger_interval=args.interval, c2_planes=args.c2_planes)
 
     def run(s):
         s.reset()
@@ -484,7 +507,8 @@ def bench_c5(args, tcm):
     # are exact either way, so the gradient must be bit-identical
     k8 = None
     if args.interval == 1 and not args.no_interval8:
-        ksim = tcm.Simulation(w.shape, w.dx, w.dt, c, checkpoint_every=50, trigger_interval=8,
+        ksim = tcm.Simulation(w.shape, w.dx, w.dt, media, checkpoint_every=50, trigger_interval=8,
+                              c2_planes=args.c2_planes,
                               wg_per_cu=(tuning or {}).get("wg_per_cu", args.wg_per_cu),
                               blocks_per_wg=(tuning or {}).get("blocks_per_wg", args.blocks_per_wg),
                               blocks_per_wave=(tuning or {}).get("blocks_per_wave", args.blocks_per_wave))
@@ -499,7 +523,8 @@ def bench_c5(args, tcm):
     # gradient) and every recomputed forward launch (which also stores L u)
     roof, adj_detail = None, None
     if not args.no_roofline:
-        tsim = tcm.Simulation(w.shape, w.dx, w.dt, c, checkpoint_every=50, timing=True,
+        tsim = tcm.Simulation(w.shape, w.dx, w.dt, media, checkpoint_every=50, timing=True,
+                              c2_planes=args.c2_planes,
                               trigger_interval=args.interval,
                               wg_per_cu=(tuning or {}).get("wg_per_cu", args.wg_per_cu),
                               blocks_per_wg=(tuning or {}).get("blocks_per_wg", args.blocks_per_wg),
@@ -518,10 +543,12 @@ def bench_c5(args, tcm):
             # the gradient term where the forward block was active (L u read,
             # FP32 partial gradient read and written: 12 B per term node)
             kern = {
-                "recompute": (20 * ts["recompute_cells"] - 4 * ts["recompute_cells_uniform"],
+                "recompute": (stencil_bytes(ts["recompute_cells"], ts["recompute_cells_uniform"],
+                                            ts["recompute_cells_lattice"], per_node=20),
                               ts["recompute_ms"], ts["recompute_launches"],
                               "k_block_step (recomputed forward step, also storing L u)"),
-                "adjoint_field": (16 * ts["adjoint_field_cells"] - 4 * ts["adjoint_field_cells_uniform"]
+                "adjoint_field": (stencil_bytes(ts["adjoint_field_cells"], ts["adjoint_field_cells_uniform"],
+                                                ts["adjoint_field_cells_lattice"])
                                   + 12 * ts["grad_cells"], ts["adjoint_field_ms"], nadj,
                                   "k_block_step (adjoint field, with the gradient term mu (L u))")}
             per = {k: {"kernel": v[3], "avg_launch_us": round(v[1] * 1e3 / max(v[2], 1), 2),
@@ -617,6 +644,8 @@ def main():
     ap.add_argument("--no-roofline", action="store_true", help="c5: skip the timed gradient pass")
     ap.add_argument("--three-pass-update", action="store_true",
                     help="run the activation update as three launches where two would do")
+    ap.add_argument("--c2-planes", action="store_true",
+                    help="read every non-uniform block's C2 plane (no lattice records)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device-to-device torch copy (counter calibration)")
     args = ap.parse_args()
@@ -646,7 +675,7 @@ def main():
     log(f"workload {w.name} {w.shape} x {steps} steps, trigger {w.trigger:.3g} retire {w.retire:.3g}")
     opts = dict(uniform_c2=not args.no_uniform_c2, trigger_interval=args.interval,
                 shutdown_steps=args.shutdown_steps, shutdown_alpha=args.shutdown_alpha,
-                three_pass_update=args.three_pass_update)
+                three_pass_update=args.three_pass_update, c2_planes=args.c2_planes)
     sim = tcm.Simulation(w.shape, w.dx, w.dt, media_of(w), w.trigger, w.retire,
                          timing=not args.graphs, wg_per_cu=args.wg_per_cu,
                          blocks_per_wg=args.blocks_per_wg, blocks_per_wave=args.blocks_per_wave, **opts)
@@ -665,7 +694,7 @@ def main():
         log(f"autotune (whole run): tile {tuning['blocks_per_wg']} blocks ({tuning['blocks_per_wave']} per wave), "
             f"wg_per_cu {tuning['wg_per_cu']}, graph_steps {tuning['graph_steps']}; "
             f"families {tuning.get('families')}")
-    tot_t, tot_u, st_ms, st_cells, st_launch, st_cells_u = 0.0, 0, 0.0, 0, 0, 0
+    tot_t, tot_u, st_ms, st_cells, st_launch, st_cells_u, st_cells_l = 0.0, 0, 0.0, 0, 0, 0, 0
     for i in range(args.steps):
         el, st = run_once(sim, w, steps)
         tot_t += el
@@ -673,6 +702,7 @@ def main():
         st_ms += st["stencil_ms"]
         st_cells += st["stencil_cells"]
         st_cells_u += st["stencil_cells_uniform"]
+        st_cells_l += st["stencil_cells_lattice"]
         st_launch += st["stencil_launches"]
         log(f"run {i}: {el:.3f} s, {st['cell_updates']:.3e} updates, peak active "
             f"{st['peak_active_blocks']}, stencil {st['stencil_ms']:.1f} ms")
@@ -698,8 +728,8 @@ def main():
     traffic = measured_traffic("k_block_step", w.name, shape)
     if st_launch > 0 and st_ms > 0:
         # 16 B per node; blocks with a uniform C2 read a scalar instead of the
-        # C2 plane: 12 B per node
-        alg_bytes = BYTES_PER_UPDATE * st_cells - 4 * st_cells_u
+        # C2 plane: 12 B per node (lattice records: 12 B + 80 B per block)
+        alg_bytes = stencil_bytes(st_cells, st_cells_u, st_cells_l)
         achieved = alg_bytes / (st_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
@@ -707,10 +737,11 @@ def main():
                 "avg_launch_us": round(st_ms * 1e3 / st_launch, 2),
                 "algorithmic_bytes_per_launch": round(alg_bytes / st_launch),
                 "uniform_c2_node_fraction": round(st_cells_u / max(st_cells, 1), 4),
+                "lattice_record_node_fraction": round(st_cells_l / max(st_cells, 1), 4),
                 "achieved_if_16B_per_node": round(BYTES_PER_UPDATE * st_cells / (st_ms * 1e-3) / 1e9, 1)}
 
     if roof and not args.no_probe:
-        add_ceiling(tcm, roof)
+        add_ceiling(tcm, roof, two_to_one_fraction(roof))
 
     dense = None
     if not args.no_dense:

@@ -70,8 +70,13 @@ enum {
                                    compaction launches even where the two-launch update applies
                                    (constant levels, update every step, no shutdown, one pool
                                    slot per block key, at most 2^24 keys); the results are the same */
-    TCM_FLAG_DEBUG_CHECKS = 16  /* tcm_step runs tcm_check at its end and returns TCM_E_STATE
+    TCM_FLAG_DEBUG_CHECKS = 16, /* tcm_step runs tcm_check at its end and returns TCM_E_STATE
                                    when a table invariant is violated */
+    TCM_FLAG_C2_PLANES = 32     /* read every non-uniform block's C2 plane (by default, with
+                                   constant levels and lattice media of spacing >= 8, a block
+                                   inside the domain takes its C2 from the 8 corners of its
+                                   lattice cell, computed as the media evaluation does, instead
+                                   of reading its plane); the results are the same */
 };
 
 /* Run configuration.  Zero-initialise, then set the fields. */
@@ -172,6 +177,13 @@ typedef struct {
     int64_t checkpoints;          /* forward checkpoints stored */
     int64_t adjoint_bytes;        /* device bytes the last tcm_adjoint held besides the checkpoints:
                                      L u store, key maps, gradient blocks, adjoint-field pool and tables */
+    /* of the counts above, nodes of blocks whose C2 the stencil formed from a
+       lattice record (TCM_FLAG_C2_PLANES unset; the rest of the non-uniform
+       nodes read their C2 plane) */
+    int64_t lattice_cell_updates;        /* of cell_updates */
+    int64_t stencil_cells_lattice;       /* of stencil_cells */
+    int64_t adjoint_field_cells_lattice; /* of adjoint_field_cells */
+    int64_t recompute_cells_lattice;     /* of recompute_cells */
 } tcm_stats_t;
 
 /* Create a single-shot handle (eq.(3) on an nx*ny*nz grid, "Cells construction").

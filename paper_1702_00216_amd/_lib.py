@@ -15,6 +15,7 @@ STATUS_NAMES = {0: "TCM_OK", -1: "TCM_E_ARG", -2: "TCM_E_CFL", -3: "TCM_E_POOL",
 MEDIA_DENSE, MEDIA_LAYERED, MEDIA_LATTICE = 0, 1, 2
 ENGINE_BLOCKS, ENGINE_DENSE = 0, 1
 FLAG_TIMING, FLAG_NO_GRAPH, FLAG_NO_UNIFORM_C2, FLAG_THREE_PASS_UPDATE, FLAG_DEBUG_CHECKS = 1, 2, 4, 8, 16
+FLAG_C2_PLANES = 32
 
 # every symbol include/tcm.h declares
 EXPORTS = [
@@ -66,7 +67,9 @@ class Stats(C.Structure):
                 ("adjoint_field_cells", C.c_int64), ("adjoint_field_cells_uniform", C.c_int64),
                 ("recompute_ms", C.c_double), ("recompute_launches", C.c_int64),
                 ("recompute_cells", C.c_int64), ("recompute_cells_uniform", C.c_int64),
-                ("checkpoint_bytes", C.c_int64), ("checkpoints", C.c_int64), ("adjoint_bytes", C.c_int64)]
+                ("checkpoint_bytes", C.c_int64), ("checkpoints", C.c_int64), ("adjoint_bytes", C.c_int64),
+                ("lattice_cell_updates", C.c_int64), ("stencil_cells_lattice", C.c_int64),
+                ("adjoint_field_cells_lattice", C.c_int64), ("recompute_cells_lattice", C.c_int64)]
 
 
 class Tuning(C.Structure):

@@ -61,6 +61,8 @@ struct DevState {
     unsigned long long updates;      // in-domain nodes stepped so far
     unsigned long long cells_cur_u;  // ... of those, nodes of blocks with a uniform C2
     unsigned long long updates_u;
+    unsigned long long cells_cur_l;  // ... of those, nodes of blocks with a lattice record (STEP_LAT)
+    unsigned long long updates_l;
     unsigned long long decays;       // block-steps of the shutdown decay
     unsigned maxbits;                // adaptive levels: max |phi^{n+1}| of this step (float bits)
     float trig_cur, ret_cur;         // levels used by the last plan
@@ -105,12 +107,14 @@ struct Tables {
     // up to FAST_DIRECT_CHUNKS groups, per group:
     int* fc_new;                    //   activations,
     int* fc_ret;                    //   releases,
-    unsigned long long* fc_cells;   //   in-domain nodes of the next set (all, then scalar-C2 blocks);
+    unsigned long long* fc_cells;   //   in-domain nodes of the next set (all, scalar-C2 blocks,
+                                    //   lattice-record blocks);
     // beyond, per run of FAST_BLK groups:
     int nfblk;                      // runs (0: up to FAST_DIRECT_CHUNKS groups)
-    unsigned long long* fc_blk;     // [2][nfblk][2] per run, summed by the plan of an even / odd
+    unsigned long long* fc_blk;     // [2][nfblk][3] per run, summed by the plan of an even / odd
                                     // step: {blocks of the next set, activations, releases} (21 bits
-                                    // each), {its in-domain nodes, of scalar-C2 blocks} (32 bits each)
+                                    // each), {its in-domain nodes, of scalar-C2 blocks} (32 bits
+                                    // each), its nodes of lattice-record blocks
     long long nwords;
     int* act_slot;                  // active list (length n_act)
     int* act_shot;
@@ -121,6 +125,14 @@ struct Tables {
                                     // [2 slot + 1] the block's sources in the (key-ordered) source
                                     // table, count << 24 | first, or -1
     float* slot_c2u;                // per slot: the block's C2 if uniform over the block, else NaN
+                                    // (LAT_C2_BITS when the slot holds a lattice record)
+    double* slot_lat;               // per slot, lattice media with spacing >= 8 (the block inside one
+                                    // lattice cell, all of it in the domain): the cell's 8 corner
+                                    // speeds, [h * 4 + dy * 2 + dx] at (iz + h, iy + dy, ix + dx)
+    int4* slot_latm;                //   and {x, y, z offset of the block in the cell, log2 spacing}
+    int lat_c2;                     // 1: the stencil computes those blocks' C2 (STEP_LAT variants)
+    int dx_pow2;                    // dx is a power of two: (c dt) / dx == (c dt) * (1 / dx)
+    double rdx;                     // 1 / dx
     unsigned char* sdlog;           // per slot: shutdown steps left (0: not shutting down)
     int* dec_slot;                  // per step: slots whose levels are multiplied by alpha
     int shutdown_steps;             // eq.(6) n (0: release at once)
@@ -192,7 +204,14 @@ hipError_t launch_block_step(const Tables& t, int grid, int w, int pb, hipStream
 // adjoint field (also adds the gradient term, Tables::g_lap).
 // launch_block_step picks the variant from the Tables.
 constexpr int STEP_PLAIN = 0, STEP_RECORD = 1, STEP_GRAD = 2;
-// resident workgroups per CU of a variant (w waves per workgroup, pb blocks per wave)
+// Flag on top of those (constant levels only): blocks whose slot holds a
+// lattice record (Tables::slot_lat) take their C2 from it, computed as the
+// media evaluation does, instead of reading the slot's C2 plane.
+constexpr int STEP_LAT = 4;
+// slot_c2u of such a block: a quiet NaN (non-uniform C2) with this payload
+constexpr unsigned LAT_C2_BITS = 0x7fc0004cu;
+// resident workgroups per CU of a variant (w waves per workgroup, pb blocks per wave;
+// mode: STEP_PLAIN / STEP_RECORD / STEP_GRAD, with STEP_LAT for the lattice-record variants)
 int block_step_occupancy(bool adaptive, int w, int pb, int mode = STEP_PLAIN);
 bool block_step_shape_ok(int w, int pb);
 hipError_t launch_plan(const Tables& t, int grid, hipStream_t s);

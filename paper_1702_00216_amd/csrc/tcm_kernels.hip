@@ -189,7 +189,83 @@ __device__ float fill_c2(const Tables& t, const Shot& S, long long slot, int bx,
     const float ref = __shfl(first, 0);
     same = same && first == ref;
     const bool uniform = t.uniform_c2 && __ballot(!same) == 0ull;
-    return uniform ? ref : __builtin_nanf("");
+    if (uniform) return ref;
+    // lattice media with spacing >= 8: the block lies inside one lattice cell,
+    // whose 8 corners (and the block's offset in it) give every node's C2 as
+    // above; the stencil's STEP_LAT variants compute it from this record
+    // instead of reading the plane (blocks that reach outside the domain,
+    // whose outer nodes have C2 = 0, keep the plane)
+    const bool whole = (bx + 1) * BE <= S.nx && (by + 1) * BE <= S.ny && (bz + 1) * BE <= S.nz;
+    if (t.slot_lat && S.media_kind == 2 && S.log2s >= 3 && whole) {
+        const int sh = S.log2s;
+        const int ix = (bx * BE) >> sh, iy = (by * BE) >> sh, iz = (bz * BE) >> sh;
+        const size_t LX = (size_t)S.lx, LXY = (size_t)S.lx * (size_t)S.ly;
+        if (lane < 8) {
+            const int h = lane >> 2, dy = (lane >> 1) & 1, dx = lane & 1;
+            t.slot_lat[8 * (size_t)slot + lane] =
+                S.lattice[(size_t)(iz + h) * LXY + (size_t)(iy + dy) * LX + (size_t)(ix + dx)];
+        }
+        if (lane == 0) t.slot_latm[slot] = make_int4(bx * BE - (ix << sh), by * BE - (iy << sh), bz * BE - (iz << sh), sh);
+        return __uint_as_float(LAT_C2_BITS);
+    }
+    return __builtin_nanf("");
+}
+
+// 64-bit value of lane l (l uniform)
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// C2 of the 8 nodes of lane (x, y) of a block with a lattice record (its
+// corners in lanes 0-7 of lv, its offsets m): the trilinear interpolation of
+// media_speed and the coefficient of coeff_c2, operation for operation, so
+// the values equal the C2 plane bit for bit
+__device__ __forceinline__ void lattice_c2(const Tables& t, double lv, int4 m, int x, int y, float* k2) {
+    double L[8];
+#pragma unroll
+    for (int k = 0; k < 8; k++) L[k] = readlane_f64(lv, k);
+    const int sh = __builtin_amdgcn_readfirstlane(m.w);
+    const int ox = __builtin_amdgcn_readfirstlane(m.x), oy = __builtin_amdgcn_readfirstlane(m.y),
+              oz = __builtin_amdgcn_readfirstlane(m.z);
+    // 1 / 2^sh, exactly (as the division it stands for)
+    const double inv = __longlong_as_double((long long)(1023 - sh) << 52);
+    const double fx = (double)(ox + x) * inv;
+    const double fy = (double)(oy + y) * inv;
+    const double gx0 = 1.0 - fx, gy0 = 1.0 - fy;
+    double cy[2];
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+        const double cx0 = L[h * 4 + 0] * gx0 + L[h * 4 + 1] * fx;
+        const double cx1 = L[h * 4 + 2] * gx0 + L[h * 4 + 3] * fx;
+        cy[h] = cx0 * gy0 + cx1 * fy;
+    }
+    double cd[8];
+#pragma unroll
+    for (int z = 0; z < 8; z++) {
+        const double fz = (double)(oz + z) * inv;
+        const double gz0 = 1.0 - fz;
+        const float c = (float)(cy[0] * gz0 + cy[1] * fz);
+        cd[z] = (double)c * t.dt;
+    }
+    // (c dt) / dx: a product where 1 / dx is exact (the branch is uniform)
+    if (t.dx_pow2) {
+        const double r = t.rdx;
+#pragma unroll
+        for (int z = 0; z < 8; z++) {
+            const double tt = cd[z] * r;
+            k2[z] = (float)(tt * tt);
+        }
+    } else {
+        const double d = t.dx;
+#pragma unroll
+        for (int z = 0; z < 8; z++) {
+            const double tt = cd[z] / d;
+            k2[z] = (float)(tt * tt);
+        }
+    }
 }
 
 // Zero both phi levels of a new slot and fill its C2 plane (fill_c2), unless
@@ -236,7 +312,7 @@ __global__ void k_init_tables(Tables t, long long nkeys) {
         if (t.fast) t.bitmap2[i] = 0ull;
     }
     if (t.fast)
-        for (long long i = g0; i < 4ll * t.nfblk; i += gs) t.fc_blk[i] = 0ull;
+        for (long long i = g0; i < 6ll * t.nfblk; i += gs) t.fc_blk[i] = 0ull;
     for (long long i = g0; i < t.cap; i += gs) {
         t.slot_key[i] = -1;
         t.pin_until[2 * (size_t)(i)] = 0;
@@ -252,6 +328,7 @@ __global__ void k_init_tables(Tables t, long long nkeys) {
         st->peak_act = 0; st->scan_acc = 0; st->add_error = 0; st->n_dec = 0;
         st->cells_cur = 0; st->updates = 0; st->activations = 0; st->retirements = 0;
         st->cells_cur_u = 0; st->updates_u = 0; st->decays = 0;
+        st->cells_cur_l = 0; st->updates_l = 0;
         st->maxbits = 0u; st->trig_cur = t.trigger; st->ret_cur = t.retire; st->n_ne = 0;
         st->free_next = t.cap;
         st->n_gblocks = 0; st->grad_error = 0;
@@ -311,8 +388,11 @@ constexpr int TILE_FLOATS = TILE_COLS * TILE_COLS * BE;
 // also store L u^n of every entry and its list index per key).
 template <bool ADAPT, int W, int P, int MODE>
 __global__ __launch_bounds__(64 * W) void k_block_step(Tables t) {
-    static_assert(MODE == STEP_PLAIN || MODE == STEP_RECORD || MODE == STEP_GRAD, "stencil variants");
-    static_assert(MODE != STEP_GRAD || (!ADAPT && P == 1), "the adjoint field: constant levels, a block per wave");
+    constexpr int BASE = MODE & 3;
+    constexpr bool LAT = (MODE & STEP_LAT) != 0;
+    static_assert(BASE == STEP_PLAIN || BASE == STEP_RECORD || BASE == STEP_GRAD, "stencil variants");
+    static_assert(BASE != STEP_GRAD || (!ADAPT && P == 1), "the adjoint field: constant levels, a block per wave");
+    static_assert(!LAT || !ADAPT, "lattice records: constant levels");
     constexpr int B = W * P;
     static_assert(B <= 8, "a pass of the workgroup stays inside one group of 8 entries");
     // two sets of per-block tiles: iteration k writes set k & 1, so one
@@ -351,7 +431,7 @@ __global__ __launch_bounds__(64 * W) void k_block_step(Tables t) {
     // adjoint field: nodes whose gradient term this workgroup formed
     __shared__ unsigned long long wg_terms;
     unsigned long long terms = 0;
-    if constexpr (MODE == STEP_GRAD) {
+    if constexpr (BASE == STEP_GRAD) {
         if (threadIdx.x == 0) wg_terms = 0;
         __syncthreads();
     }
@@ -408,6 +488,10 @@ __global__ __launch_bounds__(64 * W) void k_block_step(Tables t) {
         // FP32 partial gradient (gb: its gradient block, -1 if none yet)
         float lu[P][8], ga[P][8];
         int fi[P], gb[P];
+        // lattice records (STEP_LAT)
+        bool islat[P];
+        double latv[P];
+        int4 latm[P];
 #pragma unroll
         for (int q = 0; q < P; q++) {
             const int j = wid * P + q;
@@ -436,7 +520,7 @@ __global__ __launch_bounds__(64 * W) void k_block_step(Tables t) {
             fmx[q] = 0.f; fpx[q] = 0.f; fmy[q] = 0.f; fpy[q] = 0.f;
             fi[q] = -1; gb[q] = -1;
             if (!have[q]) continue;
-            if constexpr (MODE == STEP_GRAD) {
+            if constexpr (BASE == STEP_GRAD) {
                 fi[q] = as_scalar(t.g_fidx)[G[q]];
                 if (fi[q] >= 0) {
                     gb[q] = as_scalar((const int*)t.g_slot)[G[q]];
@@ -464,9 +548,16 @@ __global__ __launch_bounds__(64 * W) void k_block_step(Tables t) {
                 cur[q][z] = cur_p[z * 64 + lane];
                 prv[q][z] = __builtin_nontemporal_load(&out_p[q][z * 64 + lane]);
             }
+            islat[q] = false;
             if (c2u == c2u) {
 #pragma unroll
                 for (int z = 0; z < 8; z++) k2[q][z] = c2u;
+            } else if (LAT && __float_as_uint(c2u) == LAT_C2_BITS) {
+                // the block's lattice record (80 B instead of the 2 KiB plane):
+                // corners in lanes 0-7, offsets in every lane; C2 formed below
+                islat[q] = true;
+                latv[q] = t.slot_lat[8 * (size_t)slot[q] + (lane & 7)];
+                latm[q] = t.slot_latm[slot[q]];
             } else {
 #pragma unroll
                 for (int z = 0; z < 8; z++) k2[q][z] = __builtin_nontemporal_load(&c2_p[z * 64 + lane]);
@@ -482,6 +573,11 @@ __global__ __launch_bounds__(64 * W) void k_block_step(Tables t) {
 #pragma unroll
         for (int q = 0; q < P; q++) {
             if (!have[q]) continue;
+            // C2 from the lattice record, while the face values are not yet
+            // live (fewer registers than after the barrier)
+            if constexpr (LAT) {
+                if (islat[q]) lattice_c2(t, latv[q], latm[q], x, y, k2[q]);
+            }
             float* T = lds[buf][wid * P + q];
             float4* own = (float4*)(T + ((y + 1) * TILE_COLS + (x + 1)) * BE);
             own[0] = make_float4(cur[q][0], cur[q][1], cur[q][2], cur[q][3]);
@@ -529,7 +625,7 @@ __global__ __launch_bounds__(64 * W) void k_block_step(Tables t) {
                 lapv[z] = s - 6.0f * cur[q][z];
                 nv[z] = (2.0f * cur[q][z] - prv[q][z]) + k2[q][z] * lapv[z];
             }
-            if constexpr (MODE == STEP_RECORD) {
+            if constexpr (BASE == STEP_RECORD) {
                 // L u^n of this entry, for the gradient terms of adjoint step n + 1
                 if (li[q] < t.rec_lapcap) {
                     float* __restrict__ lp = t.rec_lap + (size_t)li[q] * BV;
@@ -561,7 +657,7 @@ __global__ __launch_bounds__(64 * W) void k_block_step(Tables t) {
             }
 #pragma unroll
             for (int z = 0; z < 8; z++) __builtin_nontemporal_store(nv[z], &out_p[q][z * 64 + lane]);
-            if constexpr (MODE == STEP_GRAD) {
+            if constexpr (BASE == STEP_GRAD) {
                 // gradient term mu^m (L u^{m-1}) of the key, FP32 product and
                 // sum; a key's first term hands out its gradient block and
                 // clears the block's FP64 sum
@@ -655,7 +751,7 @@ __global__ __launch_bounds__(64 * W) void k_block_step(Tables t) {
     if (ADAPT && lane == 0 && wave_max > 0.f)
         atomicMax((unsigned*)&t.st->maxbits, __float_as_uint(wave_max));   // non-negative floats order as integers
     if (nonfinite && lane == 0) atomicCAS(&t.st->nf_step, 0, n + 1);
-    if constexpr (MODE == STEP_GRAD) {
+    if constexpr (BASE == STEP_GRAD) {
         // one slot per workgroup (a global atomic from every wave would
         // serialise on one address at the kernel's end)
         if (lane == 0 && terms) atomicAdd(&wg_terms, terms);
@@ -678,6 +774,18 @@ constexpr bool grad_variant() { return !ADAPT && P == 1 && (W == 4 || W == 8); }
 
 template <bool ADAPT, int W, int P>
 static int occupancy_wp(int mode) {
+    if constexpr (!ADAPT) {
+        if (mode & STEP_LAT) {
+            const int base = mode & 3;
+            if (base == STEP_GRAD) {
+                if constexpr (grad_variant<ADAPT, W, P>()) return occupancy_wpm<ADAPT, W, P, STEP_GRAD | STEP_LAT>();
+                return 0;
+            }
+            return base == STEP_RECORD ? occupancy_wpm<ADAPT, W, P, STEP_RECORD | STEP_LAT>()
+                                       : occupancy_wpm<ADAPT, W, P, STEP_PLAIN | STEP_LAT>();
+        }
+    }
+    mode &= 3;
     if (mode == STEP_GRAD) {
         if constexpr (grad_variant<ADAPT, W, P>()) return occupancy_wpm<ADAPT, W, P, STEP_GRAD>();
         return 0;
@@ -717,6 +825,18 @@ static void launch_wpm(const Tables& t, int grid, hipStream_t s, hipEvent_t e0, 
 
 template <bool ADAPT, int W, int P>
 static void launch_wp(const Tables& t, int grid, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    if constexpr (!ADAPT) {
+        if (t.lat_c2) {
+            if (t.g_lap) {
+                if constexpr (grad_variant<ADAPT, W, P>()) launch_wpm<ADAPT, W, P, STEP_GRAD | STEP_LAT>(t, grid, s, e0, e1);
+            } else if (t.rec_lap) {
+                launch_wpm<ADAPT, W, P, STEP_RECORD | STEP_LAT>(t, grid, s, e0, e1);
+            } else {
+                launch_wpm<ADAPT, W, P, STEP_PLAIN | STEP_LAT>(t, grid, s, e0, e1);
+            }
+            return;
+        }
+    }
     if (t.g_lap) {
         if constexpr (grad_variant<ADAPT, W, P>()) launch_wpm<ADAPT, W, P, STEP_GRAD>(t, grid, s, e0, e1);
     } else if (t.rec_lap) {
@@ -1021,6 +1141,7 @@ __global__ __launch_bounds__(256) void k_advance(Tables t) {
     if (threadIdx.x == 0) {
         st->updates += st->cells_cur;
         st->updates_u += st->cells_cur_u;
+        st->updates_l += st->cells_cur_l;
         st->step = n + 1;
         st->maxbits = 0u;
     }
@@ -1048,6 +1169,7 @@ __device__ void commit_step(const Tables& t, DevState* st, int nn, int nr, int n
         // the step's phi^{n+1} is complete
         st->updates += st->cells_cur;
         st->updates_u += st->cells_cur_u;
+        st->updates_l += st->cells_cur_l;
         st->step += 1;
     }
     st->free_next = err ? nfree : nfree + nr - nn;
@@ -1059,6 +1181,7 @@ __device__ void commit_step(const Tables& t, DevState* st, int nn, int nr, int n
         if ((int)total > st->peak_act) st->peak_act = (int)total;
         st->cells_cur = 0;
         st->cells_cur_u = 0;
+        st->cells_cur_l = 0;
         st->emit = 1;
     } else {
         st->emit = 0;
@@ -1278,7 +1401,7 @@ hipError_t launch_pool_count(const Tables& t, int grid, hipStream_t s) {
 constexpr int EMIT_WAVES = CHUNK_WORDS;
 __global__ __launch_bounds__(64 * EMIT_WAVES) void k_emit(Tables t) {
     DevState* st = t.st;
-    __shared__ unsigned long long csum[EMIT_WAVES], usum[EMIT_WAVES];
+    __shared__ unsigned long long csum[EMIT_WAVES], usum[EMIT_WAVES], lsum[EMIT_WAVES];
     __shared__ unsigned s_rng[POOL_COUNT_MAX_WG], s_wsum[EMIT_WAVES];
     static_assert(POOL_COUNT_MAX_WG <= 64 * EMIT_WAVES, "one range total per thread");
     const int lane = lane_id();
@@ -1311,7 +1434,7 @@ __global__ __launch_bounds__(64 * EMIT_WAVES) void k_emit(Tables t) {
     // load); otherwise it walks the list of non-empty chunks
     const bool direct = t.nchunks <= (int)gridDim.x;
     const int nq = direct ? t.nchunks : st->n_ne;
-    unsigned long long cells = 0, ucells = 0;
+    unsigned long long cells = 0, ucells = 0, lcells = 0;
     for (int q = blockIdx.x; q < nq; q += gridDim.x) {      // uniform over the workgroup
         const long long chunk = direct ? q : t.ne_chunks[q];
         const long long w_lane = chunk * CHUNK_WORDS + lane;
@@ -1352,6 +1475,7 @@ __global__ __launch_bounds__(64 * EMIT_WAVES) void k_emit(Tables t) {
                 cells += bc;
                 const float u = t.slot_c2u[slot];
                 if (u == u) ucells += bc;
+                if (__float_as_uint(u) == LAT_C2_BITS) lcells += bc;
                 long long nk[6];
                 int nb[6];
 #pragma unroll
@@ -1371,20 +1495,24 @@ __global__ __launch_bounds__(64 * EMIT_WAVES) void k_emit(Tables t) {
     for (int o = 32; o > 0; o >>= 1) {
         cells += __shfl_xor(cells, o);
         ucells += __shfl_xor(ucells, o);
+        lcells += __shfl_xor(lcells, o);
     }
     if (lane == 0) {
         csum[wid] = cells;
         usum[wid] = ucells;
+        lsum[wid] = lcells;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        unsigned long long c = 0, u = 0;
+        unsigned long long c = 0, u = 0, l = 0;
         for (int w = 0; w < EMIT_WAVES; w++) {
             c += csum[w];
             u += usum[w];
+            l += lsum[w];
         }
         if (c) atomicAdd(&st->cells_cur, c);
         if (u) atomicAdd(&st->cells_cur_u, u);
+        if (l) atomicAdd(&st->cells_cur_l, l);
     }
 }
 
@@ -1433,7 +1561,7 @@ __global__ __launch_bounds__(64 * FAST_WORDS) void k_fast_plan(Tables t) {
     __shared__ int s_new[64 * FAST_WORDS];
     __shared__ int s_nnew, s_nret;
     __shared__ unsigned s_cnt[FAST_WORDS];
-    __shared__ unsigned long long s_cells[FAST_WORDS], s_cellsu[FAST_WORDS];
+    __shared__ unsigned long long s_cells[FAST_WORDS], s_cellsu[FAST_WORDS], s_cellsl[FAST_WORDS];
     const int n = st->step;
     if (halted_before(st, n)) return;
     const int p = n & 1;
@@ -1544,43 +1672,49 @@ __global__ __launch_bounds__(64 * FAST_WORDS) void k_fast_plan(Tables t) {
         __syncthreads();
         // in-domain nodes of the next set (and of its blocks with a scalar C2;
         // a new block's scalar C2 is the one filling it left in slot_c2u)
-        unsigned long long bc = 0, bu = 0;
+        unsigned long long bc = 0, bu = 0, bl = 0;
         if (survive) {
             bc = (unsigned long long)block_cells(S, bx, by, bz);
             const float u = active || t.c2_ready ? c2u : t.slot_c2u[G];
             if (u == u) bu = bc;
+            if (__float_as_uint(u) == LAT_C2_BITS) bl = bc;
         }
         for (int o = 32; o > 0; o >>= 1) {
             bc += __shfl_xor(bc, o);
             bu += __shfl_xor(bu, o);
+            bl += __shfl_xor(bl, o);
         }
         if (lane == 0) {
             s_cells[wid] = bc;
             s_cellsu[wid] = bu;
+            s_cellsl[wid] = bl;
         }
         __syncthreads();
         if (threadIdx.x == 0) {
             unsigned cnt = 0;
-            unsigned long long cc = 0, cu = 0;
+            unsigned long long cc = 0, cu = 0, cl = 0;
             for (int k = 0; k < FAST_WORDS; k++) {
                 cnt += s_cnt[k];
                 cc += s_cells[k];
                 cu += s_cellsu[k];
+                cl += s_cellsl[k];
             }
             t.fc_cnt[c] = (int)cnt;
             if (t.nfblk) {
-                // the run's sums, two packed words (this step's parity; the
+                // the run's sums, three packed words (this step's parity; the
                 // compaction clears the other parity's for the next step)
-                unsigned long long* b = t.fc_blk + ((size_t)p * t.nfblk + (size_t)(c / FAST_BLK)) * 2;
+                unsigned long long* b = t.fc_blk + ((size_t)p * t.nfblk + (size_t)(c / FAST_BLK)) * 3;
                 const unsigned long long k3 = fast_pack3(cnt, (unsigned)s_nnew, (unsigned)s_nret);
                 const unsigned long long k2 = cc | (cu << 32);
                 if (k3) atomicAdd(&b[0], k3);
                 if (k2) atomicAdd(&b[1], k2);
+                if (cl) atomicAdd(&b[2], cl);
             } else {
                 t.fc_new[c] = s_nnew;
                 t.fc_ret[c] = s_nret;
-                t.fc_cells[2 * (size_t)c] = cc;
-                t.fc_cells[2 * (size_t)c + 1] = cu;
+                t.fc_cells[3 * (size_t)c] = cc;
+                t.fc_cells[3 * (size_t)c + 1] = cu;
+                t.fc_cells[3 * (size_t)c + 2] = cl;
             }
         }
         __syncthreads();                                   // LDS is reused by the next chunk
@@ -1589,7 +1723,7 @@ __global__ __launch_bounds__(64 * FAST_WORDS) void k_fast_plan(Tables t) {
 
 __global__ __launch_bounds__(64 * FAST_WORDS) void k_fast_emit(Tables t) {
     DevState* st = t.st;
-    __shared__ unsigned long long s_red[FAST_WORDS][6];
+    __shared__ unsigned long long s_red[FAST_WORDS][7];
     __shared__ unsigned s_word[FAST_WORDS];
     if (st->error || st->nf_step) {
         // the step that wrote a non-finite value completes (its phi^{n+1} is
@@ -1598,6 +1732,7 @@ __global__ __launch_bounds__(64 * FAST_WORDS) void k_fast_emit(Tables t) {
         if (blockIdx.x == 0 && threadIdx.x == 0 && !st->error && st->nf_step == st->step + 1) {
             st->updates += st->cells_cur;
             st->updates_u += st->cells_cur_u;
+            st->updates_l += st->cells_cur_l;
             st->step += 1;
         }
         return;
@@ -1611,11 +1746,11 @@ __global__ __launch_bounds__(64 * FAST_WORDS) void k_fast_emit(Tables t) {
     const int nf = t.nfchunks;
     // the plan summed the runs into parity 1 - par; the next step's plan sums
     // into parity par, cleared here (nothing in this launch reads it)
-    const unsigned long long* blk = t.fc_blk + (size_t)(1 - par) * t.nfblk * 2;
+    const unsigned long long* blk = t.fc_blk + (size_t)(1 - par) * t.nfblk * 3;
     if (t.nfblk) {
-        unsigned long long* clr = t.fc_blk + (size_t)par * t.nfblk * 2;
+        unsigned long long* clr = t.fc_blk + (size_t)par * t.nfblk * 3;
         const long long gs = (long long)gridDim.x * blockDim.x;
-        for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < 2ll * t.nfblk; k += gs) clr[k] = 0ull;
+        for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < 3ll * t.nfblk; k += gs) clr[k] = 0ull;
     }
     for (int c = blockIdx.x; c < nf; c += gridDim.x) {          // uniform over the workgroup
         // this wave's word and its shot first: their loads overlap the sums below
@@ -1629,7 +1764,8 @@ __global__ __launch_bounds__(64 * FAST_WORDS) void k_fast_emit(Tables t) {
         // with up to FAST_DIRECT_CHUNKS chunks, the counts of all chunks
         // before it); the workgroup of chunk 0 also sums the list's length
         // and the step's statistics
-        unsigned long long v6[6] = {0, 0, 0, 0, 0, 0};   // before, total, cells, scalar-C2 cells, new, released
+        // before, total, cells, scalar-C2 cells, new, released, lattice-record cells
+        unsigned long long v6[7] = {0, 0, 0, 0, 0, 0, 0};
         // (the direct sums take FAST_SUM_BATCH strided entries per thread at a
         // time, so that their loads are in flight together: 6.8 against 7.2
         // us per launch at 512^3; the same for the run sums cost 4.6 us per
@@ -1639,14 +1775,15 @@ __global__ __launch_bounds__(64 * FAST_WORDS) void k_fast_emit(Tables t) {
             if (c == 0) {
                 for (int k0 = threadIdx.x; k0 < nf; k0 += FAST_SUM_BATCH * bd) {
                     int n1[FAST_SUM_BATCH], n4[FAST_SUM_BATCH], n5[FAST_SUM_BATCH];
-                    unsigned long long n2[FAST_SUM_BATCH], n3[FAST_SUM_BATCH];
+                    unsigned long long n2[FAST_SUM_BATCH], n3[FAST_SUM_BATCH], n6[FAST_SUM_BATCH];
 #pragma unroll
                     for (int u = 0; u < FAST_SUM_BATCH; u++) {
                         const int k = k0 + u * bd;
                         const bool in = k < nf;
                         n1[u] = in ? t.fc_cnt[k] : 0;
-                        n2[u] = in ? t.fc_cells[2 * (size_t)k] : 0ull;
-                        n3[u] = in ? t.fc_cells[2 * (size_t)k + 1] : 0ull;
+                        n2[u] = in ? t.fc_cells[3 * (size_t)k] : 0ull;
+                        n3[u] = in ? t.fc_cells[3 * (size_t)k + 1] : 0ull;
+                        n6[u] = in ? t.fc_cells[3 * (size_t)k + 2] : 0ull;
                         n4[u] = in ? t.fc_new[k] : 0;
                         n5[u] = in ? t.fc_ret[k] : 0;
                     }
@@ -1657,11 +1794,12 @@ __global__ __launch_bounds__(64 * FAST_WORDS) void k_fast_emit(Tables t) {
                         v6[3] += n3[u];
                         v6[4] += (unsigned)n4[u];
                         v6[5] += (unsigned)n5[u];
+                        v6[6] += n6[u];
                     }
                 }
                 for (int o = 32; o > 0; o >>= 1) {
 #pragma unroll
-                    for (int q = 1; q < 6; q++) v6[q] += __shfl_xor(v6[q], o);
+                    for (int q = 1; q < 7; q++) v6[q] += __shfl_xor(v6[q], o);
                 }
             } else {
                 for (int k0 = threadIdx.x; k0 < c; k0 += FAST_SUM_BATCH * bd) {
@@ -1675,27 +1813,28 @@ __global__ __launch_bounds__(64 * FAST_WORDS) void k_fast_emit(Tables t) {
             }
         } else if (c == 0) {
             for (int k = threadIdx.x; k < t.nfblk; k += bd) {
-                const unsigned long long k3 = blk[2 * (size_t)k], k2 = blk[2 * (size_t)k + 1];
+                const unsigned long long k3 = blk[3 * (size_t)k], k2 = blk[3 * (size_t)k + 1];
                 v6[1] += k3 & FAST_FIELD;
                 v6[2] += k2 & 0xffffffffull;
                 v6[3] += k2 >> 32;
                 v6[4] += (k3 >> 21) & FAST_FIELD;
                 v6[5] += k3 >> 42;
+                v6[6] += blk[3 * (size_t)k + 2];
             }
             for (int o = 32; o > 0; o >>= 1) {
 #pragma unroll
-                for (int q = 1; q < 6; q++) v6[q] += __shfl_xor(v6[q], o);
+                for (int q = 1; q < 7; q++) v6[q] += __shfl_xor(v6[q], o);
             }
         } else {
             const int cb = c / FAST_BLK;
-            for (int k = threadIdx.x; k < cb; k += bd) v6[0] += blk[2 * (size_t)k] & FAST_FIELD;
+            for (int k = threadIdx.x; k < cb; k += bd) v6[0] += blk[3 * (size_t)k] & FAST_FIELD;
             const int k = cb * FAST_BLK + (int)threadIdx.x;        // FAST_BLK <= blockDim.x
             if (k < c) v6[0] += (unsigned)t.fc_cnt[k];
             for (int o = 32; o > 0; o >>= 1) v6[0] += __shfl_xor(v6[0], o);
         }
         if (lane == 0) {
 #pragma unroll
-            for (int q = 0; q < 6; q++) s_red[wid][q] = v6[q];
+            for (int q = 0; q < 7; q++) s_red[wid][q] = v6[q];
         }
         if (lane == 0) s_word[wid] = (unsigned)__popcll(myw);
         // the rows' neighbour bits, loaded before the barrier so that they
@@ -1723,12 +1862,13 @@ __global__ __launch_bounds__(64 * FAST_WORDS) void k_fast_emit(Tables t) {
             base += s_red[k][0];
             ntot += s_red[k][1];
         }
-        unsigned long long cc = 0, cu = 0, na = 0, nr = 0;
+        unsigned long long cc = 0, cu = 0, na = 0, nr = 0, cl = 0;
         for (int k = 0; k < FAST_WORDS; k++) {
             cc += s_red[k][2];
             cu += s_red[k][3];
             na += s_red[k][4];
             nr += s_red[k][5];
+            cl += s_red[k][6];
         }
         for (int k = 0; k < wid; k++) base += s_word[k];
         if (mine) {
@@ -1745,8 +1885,10 @@ __global__ __launch_bounds__(64 * FAST_WORDS) void k_fast_emit(Tables t) {
         if (c == 0 && threadIdx.x == 0) {
             st->updates += st->cells_cur;
             st->updates_u += st->cells_cur_u;
+            st->updates_l += st->cells_cur_l;
             st->cells_cur = cc;
             st->cells_cur_u = cu;
+            st->cells_cur_l = cl;
             st->activations += na;
             st->retirements += nr;
             st->n_act = (int)ntot;
@@ -1917,6 +2059,7 @@ __global__ __launch_bounds__(256) void k_activate_list(Tables t, const long long
         const unsigned long long bc = (unsigned long long)block_cells(S, bx, by, bz);
         atomicAdd(&st->cells_cur, bc);
         if (c2u == c2u) atomicAdd(&st->cells_cur_u, bc);
+        if (__float_as_uint(c2u) == LAT_C2_BITS) atomicAdd(&st->cells_cur_l, bc);
         atomicAdd(&st->activations, 1ull);
     }
 }

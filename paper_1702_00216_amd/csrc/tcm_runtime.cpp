@@ -86,9 +86,9 @@ struct tcm_handle {
     double stencil_ms = 0.0;
     long long grad_cells = 0;           // gradient-term nodes of tcm_adjoint (timing flag)
     double af_ms = 0.0;                 // adjoint-field stencil of tcm_adjoint (timing flag)
-    long long af_launches = 0, af_cells = 0, af_cells_u = 0;
+    long long af_launches = 0, af_cells = 0, af_cells_u = 0, af_cells_l = 0;
     std::vector<hipEvent_t> gev;        // events around the timed gradient launches
-    long long stencil_launches = 0, stencil_cells = 0, stencil_cells_u = 0;
+    long long stencil_launches = 0, stencil_cells = 0, stencil_cells_u = 0, stencil_cells_l = 0;
 
     // dense engine
     float* d_phi[2] = {nullptr, nullptr};
@@ -120,7 +120,7 @@ struct tcm_handle {
     size_t adjoint_bytes = 0;           // device memory the last tcm_adjoint held
     // timed recomputed forward steps of tcm_adjoint (TCM_FLAG_TIMING)
     double rec_ms = 0.0;
-    long long rec_launches = 0, rec_cells = 0, rec_cells_u = 0;
+    long long rec_launches = 0, rec_cells = 0, rec_cells_u = 0, rec_cells_l = 0;
     // source activation requests (keys, shots, keys in the shot, pins, source ranges)
     void* d_act_req = nullptr;
     size_t d_act_req_cap = 0;
@@ -131,6 +131,11 @@ namespace {
 tcm_status set_err(tcm_handle* h, tcm_status s, const std::string& m) {
     if (h) h->err = m; else g_create_error = m;
     return s;
+}
+
+// stencil variant of these tables (mode: STEP_PLAIN / STEP_RECORD / STEP_GRAD)
+int step_mode(const Tables& t, int mode = STEP_PLAIN) {
+    return mode | (t.lat_c2 && !t.adaptive ? STEP_LAT : 0);
 }
 
 tcm_status dev_fail(tcm_handle* h, hipError_t e, const char* what) {
@@ -340,10 +345,22 @@ tcm_status setup_engine(tcm_handle* h, long long word_base) {
             return dev_fail(h, hipGetLastError(), "hipMemcpy(word_shot)");
         t.word_shot = d;
     }
+    // lattice records (the stencil's STEP_LAT variants): with constant levels,
+    // for shots whose lattice spacing is at least the block edge
+    bool lat_any = false;
+    for (const Shot& S : h->shots) lat_any = lat_any || (S.media_kind == TCM_MEDIA_LATTICE && S.log2s >= 3);
+    const bool adaptive = cfg->trigger_rel > 0.f || cfg->retire_rel > 0.f;
+    t.lat_c2 = (lat_any && !adaptive && !(cfg->flags & TCM_FLAG_C2_PLANES)) ? 1 : 0;
+    {
+        int ex = 0;
+        const double m = std::frexp(cfg->dx, &ex);
+        t.dx_pow2 = m == 0.5 ? 1 : 0;
+        t.rdx = 1.0 / cfg->dx;
+    }
     size_t free_b = 0, total_b = 0;
     (void)hipMemGetInfo(&free_b, &total_b);
     // per-slot bookkeeping bytes besides the 6 KiB slot
-    const size_t per_slot_tab = 4 + 4 + 4 + 32 + 1 + 4 + 4 + 4 + 1 + 4 + 8 + 8 + 4 + 4 + 8;
+    const size_t per_slot_tab = 4 + 4 + 4 + 32 + 1 + 4 + 4 + 4 + 1 + 4 + 8 + 8 + 4 + 4 + 8 + (t.lat_c2 ? 80 : 0);
     const size_t fixed = (size_t)h->nkeys * 4 + (size_t)word_base * 8 + (size_t)t.nchunks * 4 + (1 << 20);
     long long cap;
     if (cfg->pool_bytes > 0) {
@@ -393,10 +410,10 @@ tcm_status setup_engine(tcm_handle* h, long long word_base) {
             t.nfblk = 0;
             ok = ok && dalloc(h, &t.fc_new, (size_t)t.nfchunks) == hipSuccess;
             ok = ok && dalloc(h, &t.fc_ret, (size_t)t.nfchunks) == hipSuccess;
-            ok = ok && dalloc(h, &t.fc_cells, 2 * (size_t)t.nfchunks) == hipSuccess;
+            ok = ok && dalloc(h, &t.fc_cells, 3 * (size_t)t.nfchunks) == hipSuccess;
         } else {
             t.nfblk = (t.nfchunks + FAST_BLK - 1) / FAST_BLK;
-            ok = ok && dalloc(h, &t.fc_blk, 4 * (size_t)t.nfblk) == hipSuccess;
+            ok = ok && dalloc(h, &t.fc_blk, 6 * (size_t)t.nfblk) == hipSuccess;
         }
     }
     ok = ok && dalloc(h, &t.act_slot, (size_t)cap) == hipSuccess;
@@ -406,6 +423,12 @@ tcm_status setup_engine(tcm_handle* h, long long word_base) {
     ok = ok && dalloc(h, &t.flags, (size_t)cap) == hipSuccess;
     ok = ok && dalloc(h, &t.pin_until, 2 * (size_t)cap) == hipSuccess;
     ok = ok && dalloc(h, &t.slot_c2u, (size_t)cap) == hipSuccess;
+    t.slot_lat = nullptr;
+    t.slot_latm = nullptr;
+    if (t.lat_c2) {
+        ok = ok && dalloc(h, &t.slot_lat, 8 * (size_t)cap) == hipSuccess;
+        ok = ok && dalloc(h, &t.slot_latm, (size_t)cap) == hipSuccess;
+    }
     ok = ok && dalloc(h, &t.sdlog, (size_t)cap) == hipSuccess;
     ok = ok && dalloc(h, &t.dec_slot, (size_t)cap) == hipSuccess;
     t.shutdown_steps = cfg->shutdown_steps;
@@ -438,7 +461,7 @@ tcm_status setup_engine(tcm_handle* h, long long word_base) {
     // default about 12 waves per CU, the best shape measured on full lists
     h->tile_p = cfg->blocks_per_wave > 1 ? cfg->blocks_per_wave : 1;
     h->tile_w = (cfg->blocks_per_wg > 0 ? cfg->blocks_per_wg : 4) / h->tile_p;
-    const int occ = std::max(1, block_step_occupancy(t.adaptive != 0, h->tile_w, h->tile_p));
+    const int occ = std::max(1, block_step_occupancy(t.adaptive != 0, h->tile_w, h->tile_p, step_mode(t)));
     const int wpc = cfg->wg_per_cu > 0 ? cfg->wg_per_cu : std::min(occ, std::max(1, 12 / h->tile_w));
     h->grid_step = std::max(8, (h->ncu * wpc) / 8 * 8);
     // one plan thread per entry up to 4 x 256 x CUs entries; the allocator
@@ -983,7 +1006,7 @@ tcm_status make_adjoint_handle(tcm_handle* h) {
     tcm_handle* a = new tcm_handle();
     a->cfg = h->cfg;
     a->cfg.checkpoint_every = 0;
-    a->cfg.flags = TCM_FLAG_NO_GRAPH | (h->cfg.flags & TCM_FLAG_NO_UNIFORM_C2);
+    a->cfg.flags = TCM_FLAG_NO_GRAPH | (h->cfg.flags & (TCM_FLAG_NO_UNIFORM_C2 | TCM_FLAG_C2_PLANES));
     a->cfg.device_pool = nullptr;           // a capped forward pool caps the adjoint field's alike
 
     a->cfg.trigger = a->cfg.retire = 0.f;
@@ -1200,7 +1223,7 @@ tcm_status tcm_step(tcm_handle* h, int32_t nsteps) {
     // nodes stepped by this call: the lists C_0 .. C_{n-1} it runs (the list
     // left for the next call is not stepped here)
     const unsigned long long upd0 = h->h_state->updates;
-    const unsigned long long updu0 = h->h_state->updates_u;
+    const unsigned long long updu0 = h->h_state->updates_u, updl0 = h->h_state->updates_l;
     h->hstep = h->h_state->step;
 
     // one run of n steps: graph replay, or direct launches with HIP events
@@ -1241,6 +1264,7 @@ tcm_status tcm_step(tcm_handle* h, int32_t nsteps) {
     if (timing) {
         h->stencil_cells += (long long)(h->h_state->updates - upd0);
         h->stencil_cells_u += (long long)(h->h_state->updates_u - updu0);
+        h->stencil_cells_l += (long long)(h->h_state->updates_l - updl0);
     }
     if (dev_error(*h->h_state)) return report_device_error(h);
     if (h->cfg.flags & TCM_FLAG_DEBUG_CHECKS) {
@@ -1383,15 +1407,18 @@ tcm_status tcm_stats(tcm_handle* h, tcm_stats_t* o) {
     o->stencil_launches = h->stencil_launches;
     o->stencil_cells = h->stencil_cells;
     o->stencil_cells_uniform = h->stencil_cells_u;
+    o->stencil_cells_lattice = h->stencil_cells_l;
     o->grad_cells = h->grad_cells;
     o->adjoint_field_ms = h->af_ms;
     o->adjoint_field_launches = h->af_launches;
     o->adjoint_field_cells = h->af_cells;
     o->adjoint_field_cells_uniform = h->af_cells_u;
+    o->adjoint_field_cells_lattice = h->af_cells_l;
     o->recompute_ms = h->rec_ms;
     o->recompute_launches = h->rec_launches;
     o->recompute_cells = h->rec_cells;
     o->recompute_cells_uniform = h->rec_cells_u;
+    o->recompute_cells_lattice = h->rec_cells_l;
     o->checkpoint_bytes = (int64_t)ck_stored_bytes(h);
     o->checkpoints = (int64_t)h->ckpts.size();
     o->adjoint_bytes = (int64_t)h->adjoint_bytes;
@@ -1419,6 +1446,7 @@ tcm_status tcm_stats(tcm_handle* h, tcm_stats_t* o) {
     o->retirements = (int64_t)d.retirements;
     o->cell_updates = (int64_t)d.updates;
     o->uniform_cell_updates = (int64_t)d.updates_u;
+    o->lattice_cell_updates = (int64_t)d.updates_l;
     o->decay_block_steps = (int64_t)d.decays;
     o->trigger_level = d.trig_cur;
     o->retire_level = d.ret_cur;
@@ -1462,15 +1490,18 @@ tcm_status tcm_reset(tcm_handle* h) {
     h->stencil_launches = 0;
     h->stencil_cells = 0;
     h->stencil_cells_u = 0;
+    h->stencil_cells_l = 0;
     h->grad_cells = 0;
     h->af_ms = 0.0;
     h->af_launches = 0;
     h->af_cells = 0;
     h->af_cells_u = 0;
+    h->af_cells_l = 0;
     h->rec_ms = 0.0;
     h->rec_launches = 0;
     h->rec_cells = 0;
     h->rec_cells_u = 0;
+    h->rec_cells_l = 0;
     if (h->engine == TCM_ENGINE_DENSE) {
         const Shot& S = h->shots[0];
         const size_t N = (size_t)S.nx * S.ny * S.nz;
@@ -1665,7 +1696,7 @@ tcm_status tcm_adjoint(tcm_handle* h, const float* resid, int32_t nt, int32_t re
     a->tile_w = 4;
     a->tile_p = 1;
     a->grid_step = std::min(GRAD_ACCUM_MAX_WG,
-                            std::max(8, (a->ncu * std::max(1, block_step_occupancy(false, 4, 1, STEP_GRAD))) / 8 * 8));
+                            std::max(8, (a->ncu * std::max(1, block_step_occupancy(false, 4, 1, step_mode(a->t, STEP_GRAD)))) / 8 * 8));
     {
         // adjoint step k (k = 0..nt-1) produces mu^{nt-k}; its source sample at
         // receiver r is C2_r * resid[nt-1-k][r]; all receivers in one activation
@@ -1740,19 +1771,21 @@ tcm_status tcm_adjoint(tcm_handle* h, const float* resid, int32_t nt, int32_t re
     a->t.g_terms_wg = gterms;
     hipError_t e = launch_fill_int(gslot, nkeys, -1, h->stream);
     if (e == hipSuccess) e = hipMemsetAsync(gterms, 0, sizeof(unsigned long long) * GRAD_ACCUM_MAX_WG, h->stream);
-    const unsigned long long a_upd0 = a->h_state->updates, a_updu0 = a->h_state->updates_u;
+    const unsigned long long a_upd0 = a->h_state->updates, a_updu0 = a->h_state->updates_u,
+                             a_updl0 = a->h_state->updates_l;
     // the recomputing stencil keeps the forward's launch shape within its
     // own residency (a persistent grid beyond it would leave a tail)
     keep_grid_step = h->grid_step;
     h->grid_step = std::min(h->grid_step,
                             std::max(8, (h->ncu * std::max(1, block_step_occupancy(h->t.adaptive != 0, h->tile_w,
-                                                                                   h->tile_p, STEP_RECORD))) / 8 * 8));
+                                                                                   h->tile_p, step_mode(h->t, STEP_RECORD)))) / 8 * 8));
     for (int j = nseg - 1; j >= 0 && e == hipSuccess; j--) {
         const int s0 = j * K, end = std::min(s0 + K, nt);
         st = ck_restore(h, h->ckpts[j]);
         if (!st && timing) st = sync_state(h);
         if (st) { cleanup(); return st; }
-        const unsigned long long rec_u0 = h->h_state->updates, rec_uu0 = h->h_state->updates_u;
+        const unsigned long long rec_u0 = h->h_state->updates, rec_uu0 = h->h_state->updates_u,
+                                 rec_ul0 = h->h_state->updates_l;
         h->hstep = s0;
         // recompute forward steps s0 .. end-1, storing L u^n (n = s0 .. end-1)
         e = launch_fill_int(fidx, (long long)(end - s0) * nkeys, -1, h->stream);
@@ -1794,6 +1827,7 @@ tcm_status tcm_adjoint(tcm_handle* h, const float* resid, int32_t nt, int32_t re
             if (st) { cleanup(); return st; }
             h->rec_cells += (long long)(h->h_state->updates - rec_u0);
             h->rec_cells_u += (long long)(h->h_state->updates_u - rec_uu0);
+            h->rec_cells_l += (long long)(h->h_state->updates_l - rec_ul0);
         }
     }
     if (e != hipSuccess) { cleanup(); return dev_fail(h, e, "adjoint sweep"); }
@@ -1812,6 +1846,7 @@ tcm_status tcm_adjoint(tcm_handle* h, const float* resid, int32_t nt, int32_t re
     if (timing) {
         h->af_cells += (long long)(a->h_state->updates - a_upd0);
         h->af_cells_u += (long long)(a->h_state->updates_u - a_updu0);
+        h->af_cells_l += (long long)(a->h_state->updates_l - a_updl0);
         std::vector<unsigned long long> wg(GRAD_ACCUM_MAX_WG);
         if (hipMemcpy(wg.data(), gterms, sizeof(unsigned long long) * GRAD_ACCUM_MAX_WG, hipMemcpyDeviceToHost) !=
             hipSuccess) {
@@ -1904,7 +1939,7 @@ tcm_status tcm_autotune(tcm_handle* h, int32_t probe_steps, tcm_tuning* out) {
     const int shapes[5][2] = {{2, 1}, {4, 1}, {8, 1}, {2, 2}, {4, 2}};   // {waves, blocks per wave}
     for (const auto& sh : shapes) {
         const int w = sh[0], pb = sh[1];
-        const int occ = std::max(1, block_step_occupancy(h->t.adaptive != 0, w, pb));
+        const int occ = std::max(1, block_step_occupancy(h->t.adaptive != 0, w, pb, step_mode(h->t)));
         for (int wpc : {1, 2, 3, 4, 6, 8, 12}) {
             if (st || wpc > occ || w * wpc < 4 || w * wpc > 24) continue;
             st = probe(w, pb, wpc, 16);
@@ -2047,7 +2082,7 @@ tcm_status tcm_autotune_run(tcm_handle* h, int32_t nsteps, int32_t probe_steps, 
     const int shapes[5][2] = {{2, 1}, {4, 1}, {8, 1}, {2, 2}, {4, 2}};   // {waves, blocks per wave}
     for (const auto& sh : shapes) {
         const int w = sh[0], pb = sh[1];
-        const int occ = std::max(1, block_step_occupancy(h->t.adaptive != 0, w, pb));
+        const int occ = std::max(1, block_step_occupancy(h->t.adaptive != 0, w, pb, step_mode(h->t)));
         Fam best{w, pb, 0, 1e300};
         for (int wpc : {1, 2, 3, 4, 6, 8, 12}) {
             if (wpc > occ || w * wpc < 4 || w * wpc > 24) continue;
@@ -2135,7 +2170,7 @@ tcm_status tcm_set_launch(tcm_handle* h, int32_t wg_per_cu, int32_t graph_steps,
         return set_err(h, TCM_E_ARG, "blocks_per_wg must be 0, 2, 4 or 8 and blocks_per_wave 0, 1 or 2 "
                                      "(2 with a tile of 4 or 8 blocks)");
     const int w = b / pb;
-    const int occ = std::max(1, block_step_occupancy(h->t.adaptive != 0, w, pb));
+    const int occ = std::max(1, block_step_occupancy(h->t.adaptive != 0, w, pb, step_mode(h->t)));
     if (wg_per_cu < 1 || wg_per_cu > occ || graph_steps < 1)
         return set_err(h, TCM_E_ARG, fmt("launch shape needs 1 <= wg_per_cu <= %d and graph_steps >= 1", occ));
     HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));

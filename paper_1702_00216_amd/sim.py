@@ -63,7 +63,8 @@ class Simulation:
                  device_pool=None, uniform_c2: bool = True, shutdown_steps: int = 0,
                  shutdown_alpha: float = 1.0, trigger_rel: float = 0.0, retire_rel: float = 0.0,
                  trigger_interval: int = 1, blocks_per_wg: int = 0, blocks_per_wave: int = 0,
-                 three_pass_update: bool = False, debug_checks: bool = False):
+                 three_pass_update: bool = False, debug_checks: bool = False,
+                 c2_planes: bool = False):
         lib = L.lib()
         cfg = L.Config()
         cfg.dx, cfg.dt = float(dx), float(dt)
@@ -73,7 +74,8 @@ class Simulation:
         cfg.flags = ((L.FLAG_TIMING if timing else 0) | (0 if graphs else L.FLAG_NO_GRAPH)
                      | (0 if uniform_c2 else L.FLAG_NO_UNIFORM_C2)
                      | (L.FLAG_THREE_PASS_UPDATE if three_pass_update else 0)
-                     | (L.FLAG_DEBUG_CHECKS if debug_checks else 0))
+                     | (L.FLAG_DEBUG_CHECKS if debug_checks else 0)
+                     | (L.FLAG_C2_PLANES if c2_planes else 0))
         cfg.checkpoint_every = int(checkpoint_every)
         cfg.graph_steps = int(graph_steps)
         cfg.wg_per_cu = int(wg_per_cu)

@@ -756,6 +756,58 @@ def test_two_launch_update_with_run_sums():
         sim.close()
 
 
+@pytest.mark.parametrize("pool", ["key", "capped"])
+def test_lattice_records_equal_c2_planes(pool):
+    """Lattice media: blocks inside one lattice cell (spacing 8 or 16) and
+    inside the domain take their C2 from the cell's 8 corners in the
+    stencil; the fields and the work equal those of the same runs reading
+    every C2 plane, bit for bit, and equal the CPU TCM on the dense media.
+    A batch with spacings 8, 16 and 4 (no records) and ragged edges, a pool
+    of one slot per key (records written when the pool is made) or a capped
+    pool (written at activation), and single shots with dx = 2 (a power of
+    two) and dx = 3."""
+    announce(f"lattice records vs C2 planes ({pool} pool)")
+    shapes = [(100, 90, 70), (64, 72, 64), (72, 40, 50)]
+    lats = [ti.lognormal_lattice(sh, seed=70 + i, sigma=10.0, spacing=sp)
+            for i, (sh, sp) in enumerate(zip(shapes, (8, 16, 4)))]
+    dt = 0.5 / 4500.0
+    w = ti.ricker(300.0, dt).w32
+    srcs = [(50, 45, 35), (20, 30, 40), (36, 20, 25)]
+    cap = 0 if pool == "key" else 3000      # capped: below the batch's 3840 keys, above its peak
+    runs = []
+    for planes in (False, True):
+        sim = tcm.Simulation(shapes, 1.0, dt, lats, np.float32(1e-7), np.float32(1e-8), c2_planes=planes,
+                             pool_bytes=cap * 6144)
+        for i, xyz in enumerate(srcs):
+            sim.add_source(xyz, w, shot=i)
+        sim.step(160)
+        assert sim.check() == 0
+        runs.append(([sim.read(k, shot=i) for i in range(3) for k in (0, 1)], sim.stats()))
+        sim.close()
+    (fa, sa), (fb, sb) = runs
+    assert all(values_equal(x, y) for x, y in zip(fa, fb))
+    for key in ("active_blocks", "activations", "retirements", "cell_updates", "peak_active_blocks"):
+        assert sa[key] == sb[key], key
+    assert sa["active_blocks"] > 100
+    # shot 1 against the CPU TCM on its dense media
+    c1 = ti.lattice_to_dense(lats[1], shapes[1])
+    t = oracle.TCM(c1, dt, 1.0, np.float32(1e-7), np.float32(1e-8))
+    t.add_source(srcs[1], w)
+    assert t.step(160) == 0
+    assert values_equal(fa[2], t.read(0)) and values_equal(fa[3], t.read(1))
+    # node spacings that are and are not powers of two
+    for dx in (2.0, 3.0):
+        out = []
+        for planes in (False, True):
+            sim = tcm.Simulation(shapes[0], dx, dt * dx, lats[0], 0.0, 0.0, c2_planes=planes,
+                                 pool_bytes=(0 if pool == "key" else 2000) * 6144)
+            sim.add_source(srcs[0], w)
+            sim.step(60)
+            out.append((sim.read(0), sim.read(1)))
+            sim.close()
+        assert values_equal(out[0][0], out[1][0]) and values_equal(out[0][1], out[1][1])
+
+
 def block_key(shape, bx, by, bz):
     """Key of block (bx, by, bz): blocks in 4x4x4 tiles, tiles x-fastest,
     blocks inside a tile x-fastest (one pool slot per key when the pool holds
