@@ -250,8 +250,12 @@ __device__ __forceinline__ void lattice_c2(const Tables& t, double lv, int4 m, i
         const float c = (float)(cy[0] * gz0 + cy[1] * fz);
         cd[z] = (double)c * t.dt;
     }
-    // (c dt) / dx: a product where 1 / dx is exact (the branch is uniform)
-    if (t.dx_pow2) {
+    // (c dt) / dx: nothing to do for dx = 1, a product where 1 / dx is exact
+    // (the branches are uniform)
+    if (t.dx == 1.0) {
+#pragma unroll
+        for (int z = 0; z < 8; z++) k2[z] = (float)(cd[z] * cd[z]);
+    } else if (t.dx_pow2) {
         const double r = t.rdx;
 #pragma unroll
         for (int z = 0; z < 8; z++) {
@@ -540,6 +544,14 @@ __global__ __launch_bounds__(64 * W) void k_block_step(Tables t) {
                 shead[q] = (int)(unsigned)(ph >> 32);
             }
             const float c2u = slot_c2u[slot[q]];
+            if constexpr (LAT) {
+                // the slot's lattice record (80 B instead of the 2 KiB plane:
+                // corners in lanes 0-7, offsets in every lane) before the data,
+                // and whether or not the slot holds one (no wait on c2u here),
+                // so that its C2 is formed while the data loads are in flight
+                latv[q] = t.slot_lat[8 * (size_t)slot[q] + (lane & 7)];
+                latm[q] = t.slot_latm[slot[q]];
+            }
             const float* __restrict__ cur_p = plane_of(t, slot[q], p);
             out_p[q] = plane_of(t, slot[q], 1 - p);
             const float* __restrict__ c2_p = plane_of(t, slot[q], PLANE_C2);
@@ -548,17 +560,11 @@ __global__ __launch_bounds__(64 * W) void k_block_step(Tables t) {
                 cur[q][z] = cur_p[z * 64 + lane];
                 prv[q][z] = __builtin_nontemporal_load(&out_p[q][z * 64 + lane]);
             }
-            islat[q] = false;
+            islat[q] = LAT && __float_as_uint(c2u) == LAT_C2_BITS;
             if (c2u == c2u) {
 #pragma unroll
                 for (int z = 0; z < 8; z++) k2[q][z] = c2u;
-            } else if (LAT && __float_as_uint(c2u) == LAT_C2_BITS) {
-                // the block's lattice record (80 B instead of the 2 KiB plane):
-                // corners in lanes 0-7, offsets in every lane; C2 formed below
-                islat[q] = true;
-                latv[q] = t.slot_lat[8 * (size_t)slot[q] + (lane & 7)];
-                latm[q] = t.slot_latm[slot[q]];
-            } else {
+            } else if (!islat[q]) {
 #pragma unroll
                 for (int z = 0; z < 8; z++) k2[q][z] = __builtin_nontemporal_load(&c2_p[z * 64 + lane]);
             }
@@ -570,14 +576,15 @@ __global__ __launch_bounds__(64 * W) void k_block_step(Tables t) {
             if (nb[q][3] >= 0) fpy[q] = plane_of(t, nb[q][3], p)[zz * 64 + 0 * 8 + a];
         }
         __builtin_amdgcn_s_setprio(0);
+        if constexpr (LAT) {
+            // C2 from the lattice records, while the blocks' data are in flight
+#pragma unroll
+            for (int q = 0; q < P; q++)
+                if (have[q] && islat[q]) lattice_c2(t, latv[q], latm[q], x, y, k2[q]);
+        }
 #pragma unroll
         for (int q = 0; q < P; q++) {
             if (!have[q]) continue;
-            // C2 from the lattice record, while the face values are not yet
-            // live (fewer registers than after the barrier)
-            if constexpr (LAT) {
-                if (islat[q]) lattice_c2(t, latv[q], latm[q], x, y, k2[q]);
-            }
             float* T = lds[buf][wid * P + q];
             float4* own = (float4*)(T + ((y + 1) * TILE_COLS + (x + 1)) * BE);
             own[0] = make_float4(cur[q][0], cur[q][1], cur[q][2], cur[q][3]);
