@@ -39,8 +39,6 @@ def stencil_bytes(cells, cells_u, cells_l, per_node=BYTES_PER_UPDATE):
     return per_node * cells - 4 * cells_u - (4 - LAT_RECORD_BYTES / 512) * cells_l
 
 
-
-
 def log(msg: str):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -252,7 +250,8 @@ def bench_c3(args, tcm):
     steps = args.time_steps or w.steps
     log(f"c3 media lattice {w.lattice.lattice.shape} built in {time.perf_counter() - t0:.1f} s")
     sim = tcm.Simulation(w.shape, w.dx, w.dt, w.lattice, w.trigger, w.retire,
-                         pool_bytes=w.pool_bytes, timing=True, wg_per_cu=args.wg_per_cu, c2_planes=args.c2_planes)
+                         pool_bytes=w.pool_bytes, timing=True, wg_per_cu=args.wg_per_cu, c2_planes=args.c2_planes,
+                         blocks_per_wg=args.blocks_per_wg, blocks_per_wave=args.blocks_per_wave)
     sim.add_source(w.source, w.wavelet.w32)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
