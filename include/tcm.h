@@ -76,7 +76,8 @@ enum {
                                    constant levels and lattice media of spacing >= 8, a block
                                    inside the domain takes its C2 from the 8 corners of its
                                    lattice cell, computed as the media evaluation does, instead
-                                   of reading its plane); the results are the same */
+                                   of reading its plane; TCM_FLAG_NO_UNIFORM_C2 implies this
+                                   flag); the results are the same */
 };
 
 /* Run configuration.  Zero-initialise, then set the fields. */

@@ -350,7 +350,8 @@ tcm_status setup_engine(tcm_handle* h, long long word_base) {
     bool lat_any = false;
     for (const Shot& S : h->shots) lat_any = lat_any || (S.media_kind == TCM_MEDIA_LATTICE && S.log2s >= 3);
     const bool adaptive = cfg->trigger_rel > 0.f || cfg->retire_rel > 0.f;
-    t.lat_c2 = (lat_any && !adaptive && !(cfg->flags & TCM_FLAG_C2_PLANES)) ? 1 : 0;
+    // (TCM_FLAG_NO_UNIFORM_C2 asks for every C2 plane read, so it turns them off too)
+    t.lat_c2 = (lat_any && !adaptive && !(cfg->flags & (TCM_FLAG_C2_PLANES | TCM_FLAG_NO_UNIFORM_C2))) ? 1 : 0;
     {
         int ex = 0;
         const double m = std::frexp(cfg->dx, &ex);
