@@ -808,6 +808,45 @@ def test_lattice_records_equal_c2_planes(pool):
         assert values_equal(out[0][0], out[1][0]) and values_equal(out[0][1], out[1][1])
 
 
+@pytest.mark.parametrize("pool", ["key", "capped"])
+def test_lattice_records_survive_restore_and_follow_set_media(pool):
+    """Lattice records with checkpoints and new media: a snapshot restored
+    mid-run repeats the run bit for bit (a capped pool rewrites the records
+    of the restored blocks), and after tcm_set_media the run equals a fresh
+    handle on the new media that reads every C2 plane."""
+    announce(f"lattice records: restore and set_media ({pool} pool)")
+    shape = (80, 72, 64)
+    a = ti.lognormal_lattice(shape, seed=90, sigma=10.0, spacing=8)
+    b = ti.lognormal_lattice(shape, seed=91, sigma=10.0, spacing=8)
+    dt = 0.5 / 4500.0
+    w = ti.ricker(300.0, dt).w32
+    src = (40, 36, 30)
+    kw = dict(pool_bytes=(0 if pool == "key" else 900) * 6144)
+    sim = tcm.Simulation(shape, 1.0, dt, a, np.float32(1e-7), np.float32(1e-8), **kw)
+    sim.add_source(src, w)
+    sim.step(60)
+    snap = sim.snapshot()
+    sim.step(40)
+    ref = (sim.read(0), sim.read(1), sim.stats()["cell_updates"])
+    assert sim.stats()["lattice_cell_updates"] > 0
+    sim.restore(snap)
+    sim.step(40)
+    assert values_equal(sim.read(0), ref[0]) and values_equal(sim.read(1), ref[1])
+    assert sim.stats()["cell_updates"] == ref[2]
+    snap.close()
+    sim.set_media(b)
+    sim.add_source(src, w)
+    sim.step(70)
+    fresh = tcm.Simulation(shape, 1.0, dt, b, np.float32(1e-7), np.float32(1e-8), c2_planes=True, **kw)
+    fresh.add_source(src, w)
+    fresh.step(70)
+    assert values_equal(sim.read(0), fresh.read(0)) and values_equal(sim.read(1), fresh.read(1))
+    assert sim.stats()["cell_updates"] == fresh.stats()["cell_updates"]
+    assert sim.stats()["lattice_cell_updates"] > 0 and fresh.stats()["lattice_cell_updates"] == 0
+    sim.close()
+    fresh.close()
+
+
 def block_key(shape, bx, by, bz):
     """Key of block (bx, by, bz): blocks in 4x4x4 tiles, tiles x-fastest,
     blocks inside a tile x-fastest (one pool slot per key when the pool holds
