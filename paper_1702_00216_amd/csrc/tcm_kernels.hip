@@ -1772,7 +1772,7 @@ __global__ __launch_bounds__(64 * FAST_WORDS) void k_fast_emit(Tables t) {
         // before it); the workgroup of chunk 0 also sums the list's length
         // and the step's statistics
         // before, total, cells, scalar-C2 cells, new, released, lattice-record cells
-        unsigned long long v6[7] = {0, 0, 0, 0, 0, 0, 0};
+        unsigned long long sums[7] = {0, 0, 0, 0, 0, 0, 0};
         // (the direct sums take FAST_SUM_BATCH strided entries per thread at a
         // time, so that their loads are in flight together: 6.8 against 7.2
         // us per launch at 512^3; the same for the run sums cost 4.6 us per
@@ -1796,17 +1796,17 @@ __global__ __launch_bounds__(64 * FAST_WORDS) void k_fast_emit(Tables t) {
                     }
 #pragma unroll
                     for (int u = 0; u < FAST_SUM_BATCH; u++) {
-                        v6[1] += (unsigned)n1[u];
-                        v6[2] += n2[u];
-                        v6[3] += n3[u];
-                        v6[4] += (unsigned)n4[u];
-                        v6[5] += (unsigned)n5[u];
-                        v6[6] += n6[u];
+                        sums[1] += (unsigned)n1[u];
+                        sums[2] += n2[u];
+                        sums[3] += n3[u];
+                        sums[4] += (unsigned)n4[u];
+                        sums[5] += (unsigned)n5[u];
+                        sums[6] += n6[u];
                     }
                 }
                 for (int o = 32; o > 0; o >>= 1) {
 #pragma unroll
-                    for (int q = 1; q < 7; q++) v6[q] += __shfl_xor(v6[q], o);
+                    for (int q = 1; q < 7; q++) sums[q] += __shfl_xor(sums[q], o);
                 }
             } else {
                 for (int k0 = threadIdx.x; k0 < c; k0 += FAST_SUM_BATCH * bd) {
@@ -1814,34 +1814,34 @@ __global__ __launch_bounds__(64 * FAST_WORDS) void k_fast_emit(Tables t) {
 #pragma unroll
                     for (int u = 0; u < FAST_SUM_BATCH; u++) n1[u] = k0 + u * bd < c ? t.fc_cnt[k0 + u * bd] : 0;
 #pragma unroll
-                    for (int u = 0; u < FAST_SUM_BATCH; u++) v6[0] += (unsigned)n1[u];
+                    for (int u = 0; u < FAST_SUM_BATCH; u++) sums[0] += (unsigned)n1[u];
                 }
-                for (int o = 32; o > 0; o >>= 1) v6[0] += __shfl_xor(v6[0], o);
+                for (int o = 32; o > 0; o >>= 1) sums[0] += __shfl_xor(sums[0], o);
             }
         } else if (c == 0) {
             for (int k = threadIdx.x; k < t.nfblk; k += bd) {
                 const unsigned long long k3 = blk[3 * (size_t)k], k2 = blk[3 * (size_t)k + 1];
-                v6[1] += k3 & FAST_FIELD;
-                v6[2] += k2 & 0xffffffffull;
-                v6[3] += k2 >> 32;
-                v6[4] += (k3 >> 21) & FAST_FIELD;
-                v6[5] += k3 >> 42;
-                v6[6] += blk[3 * (size_t)k + 2];
+                sums[1] += k3 & FAST_FIELD;
+                sums[2] += k2 & 0xffffffffull;
+                sums[3] += k2 >> 32;
+                sums[4] += (k3 >> 21) & FAST_FIELD;
+                sums[5] += k3 >> 42;
+                sums[6] += blk[3 * (size_t)k + 2];
             }
             for (int o = 32; o > 0; o >>= 1) {
 #pragma unroll
-                for (int q = 1; q < 7; q++) v6[q] += __shfl_xor(v6[q], o);
+                for (int q = 1; q < 7; q++) sums[q] += __shfl_xor(sums[q], o);
             }
         } else {
             const int cb = c / FAST_BLK;
-            for (int k = threadIdx.x; k < cb; k += bd) v6[0] += blk[3 * (size_t)k] & FAST_FIELD;
+            for (int k = threadIdx.x; k < cb; k += bd) sums[0] += blk[3 * (size_t)k] & FAST_FIELD;
             const int k = cb * FAST_BLK + (int)threadIdx.x;        // FAST_BLK <= blockDim.x
-            if (k < c) v6[0] += (unsigned)t.fc_cnt[k];
-            for (int o = 32; o > 0; o >>= 1) v6[0] += __shfl_xor(v6[0], o);
+            if (k < c) sums[0] += (unsigned)t.fc_cnt[k];
+            for (int o = 32; o > 0; o >>= 1) sums[0] += __shfl_xor(sums[0], o);
         }
         if (lane == 0) {
 #pragma unroll
-            for (int q = 0; q < 7; q++) s_red[wid][q] = v6[q];
+            for (int q = 0; q < 7; q++) s_red[wid][q] = sums[q];
         }
         if (lane == 0) s_word[wid] = (unsigned)__popcll(myw);
         // the rows' neighbour bits, loaded before the barrier so that they
