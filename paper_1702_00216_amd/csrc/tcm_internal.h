@@ -74,6 +74,7 @@ struct DevState {
     int n_gblocks;                   // adjoint: gradient blocks handed out (first gradient term of a key)
     int grad_error;                  // adjoint: a gradient block or lap-store entry was out of range
     int nf_step;                     // n + 1 for the first step n that wrote a non-finite value, else 0
+    int adv_tickets;                 // stencil advancing the step itself: workgroups done (0 between launches)
 };
 
 struct Src {
@@ -131,6 +132,9 @@ struct Tables {
                                     // speeds, [h * 4 + dy * 2 + dx] at (iz + h, iy + dy, ix + dx)
     int4* slot_latm;                //   and {x, y, z offset of the block in the cell, log2 spacing}
     int lat_c2;                     // 1: the stencil computes those blocks' C2 (STEP_LAT variants)
+    int self_advance;               // this stencil launch ends a step without an activation update
+                                    // and without receivers: its last workgroup advances the step
+                                    // (instead of a k_advance launch; constant levels only)
     int dx_pow2;                    // dx is a power of two: (c dt) / dx == (c dt) * (1 / dx)
     double rdx;                     // 1 / dx
     unsigned char* sdlog;           // per slot: shutdown steps left (0: not shutting down)

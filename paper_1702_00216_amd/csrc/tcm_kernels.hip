@@ -329,6 +329,7 @@ __global__ void k_init_tables(Tables t, long long nkeys) {
         DevState* st = t.st;
         st->step = 0; st->n_act = 0; st->n_new = 0; st->n_ret = 0;
         st->free_cnt = t.cap; st->error = 0; st->err_step = -1; st->emit = 0; st->nf_step = 0;
+        st->adv_tickets = 0;
         st->peak_act = 0; st->scan_acc = 0; st->add_error = 0; st->n_dec = 0;
         st->cells_cur = 0; st->updates = 0; st->activations = 0; st->retirements = 0;
         st->cells_cur_u = 0; st->updates_u = 0; st->decays = 0;
@@ -764,6 +765,22 @@ __global__ __launch_bounds__(64 * W) void k_block_step(Tables t) {
         if (lane == 0 && terms) atomicAdd(&wg_terms, terms);
         __syncthreads();
         if (threadIdx.x == 0 && wg_terms && blockIdx.x < GRAD_ACCUM_MAX_WG) t.g_terms_wg[blockIdx.x] += wg_terms;
+    }
+    if constexpr (!ADAPT) {
+        // a step without an activation update and without receivers: the
+        // last workgroup to finish advances the step, as k_advance would.
+        // Every workgroup read the step counter at its start, before taking
+        // its ticket, and the last one reads nothing that another wrote in
+        // this launch, so the tickets alone order it.
+        if (t.self_advance && threadIdx.x == 0 && atomicAdd(&t.st->adv_tickets, 1) == (int)gridDim.x - 1) {
+            DevState* sw = t.st;
+            sw->adv_tickets = 0;
+            sw->updates += sw->cells_cur;
+            sw->updates_u += sw->cells_cur_u;
+            sw->updates_l += sw->cells_cur_l;
+            sw->step = n + 1;
+            sw->maxbits = 0u;
+        }
     }
 }
 

@@ -588,8 +588,15 @@ hipError_t enqueue_step(tcm_handle* h, hipEvent_t e0, hipEvent_t e1) {
     hipError_t e;
     const long long n = h->hstep++;
     const int k = h->t.interval > 1 ? h->t.interval : 1;
-    if ((e = launch_block_step(h->t, h->grid_step, h->tile_w, h->tile_p, h->stream, e0, e1)) != hipSuccess) return e;
-    if ((n + 1) % k != 0) return launch_advance(h->t, h->stream);
+    // a step without an activation update: with no receivers to record and
+    // constant levels the stencil advances the step itself (no k_advance)
+    const bool update = (n + 1) % k == 0;
+    const bool self = !update && h->t.nrec == 0 && !h->t.adaptive;
+    h->t.self_advance = self ? 1 : 0;
+    e = launch_block_step(h->t, h->grid_step, h->tile_w, h->tile_p, h->stream, e0, e1);
+    h->t.self_advance = 0;
+    if (e != hipSuccess) return e;
+    if (!update) return self ? hipSuccess : launch_advance(h->t, h->stream);
     if (h->t.fast) return launch_fast_update(h->t, h->t.nfchunks, h->stream);
     if ((e = launch_plan(h->t, h->grid_plan, h->stream)) != hipSuccess) return e;
     if ((e = launch_pool_count(h->t, h->grid_pool, h->stream)) != hipSuccess) return e;
