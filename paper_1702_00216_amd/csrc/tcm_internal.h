@@ -74,7 +74,8 @@ struct DevState {
     int n_gblocks;                   // adjoint: gradient blocks handed out (first gradient term of a key)
     int grad_error;                  // adjoint: a gradient block or lap-store entry was out of range
     int nf_step;                     // n + 1 for the first step n that wrote a non-finite value, else 0
-    int adv_tickets;                 // stencil advancing the step itself: workgroups done (0 between launches)
+    int adv_tk[8], adv_top;          // stencil advancing the step itself: workgroups done per class
+                                     // (blockIdx % 8), then classes done (0 between launches)
 };
 
 struct Src {

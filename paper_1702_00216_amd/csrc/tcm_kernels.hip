@@ -329,7 +329,8 @@ __global__ void k_init_tables(Tables t, long long nkeys) {
         DevState* st = t.st;
         st->step = 0; st->n_act = 0; st->n_new = 0; st->n_ret = 0;
         st->free_cnt = t.cap; st->error = 0; st->err_step = -1; st->emit = 0; st->nf_step = 0;
-        st->adv_tickets = 0;
+        for (int g = 0; g < 8; g++) st->adv_tk[g] = 0;
+        st->adv_top = 0;
         st->peak_act = 0; st->scan_acc = 0; st->add_error = 0; st->n_dec = 0;
         st->cells_cur = 0; st->updates = 0; st->activations = 0; st->retirements = 0;
         st->cells_cur_u = 0; st->updates_u = 0; st->decays = 0;
@@ -771,10 +772,21 @@ __global__ __launch_bounds__(64 * W) void k_block_step(Tables t) {
         // last workgroup to finish advances the step, as k_advance would.
         // Every workgroup read the step counter at its start, before taking
         // its ticket, and the last one reads nothing that another wrote in
-        // this launch, so the tickets alone order it.
-        if (t.self_advance && threadIdx.x == 0 && atomicAdd(&t.st->adv_tickets, 1) == (int)gridDim.x - 1) {
+        // this launch, so the tickets alone order it.  Tickets per class of
+        // workgroups (blockIdx % 8), then one per class: no counter takes
+        // more than a few hundred same-address atomics (one counter for all
+        // 1024 workgroups of the adjoint field cost about 4 us per launch).
+        bool last = false;
+        if (t.self_advance && threadIdx.x == 0) {
+            const int g = blockIdx.x & 7;
+            const int in_g = ((int)gridDim.x - g + 7) >> 3;            // workgroups of class g
+            const int ng = gridDim.x < 8 ? (int)gridDim.x : 8;         // classes
+            if (atomicAdd(&t.st->adv_tk[g], 1) == in_g - 1) last = atomicAdd(&t.st->adv_top, 1) == ng - 1;
+        }
+        if (last) {
             DevState* sw = t.st;
-            sw->adv_tickets = 0;
+            for (int g = 0; g < 8; g++) sw->adv_tk[g] = 0;
+            sw->adv_top = 0;
             sw->updates += sw->cells_cur;
             sw->updates_u += sw->cells_cur_u;
             sw->updates_l += sw->cells_cur_l;
