@@ -155,6 +155,14 @@ tcm_status dev_fail(tcm_handle* h, hipError_t e, const char* what) {
         if (e__ != hipSuccess) return dev_fail((h), e__, #expr); \
     } while (0)
 
+// Events that only time work on the handle's stream.  A default event makes a
+// system-scope release and acquire at its record (cache write-back and
+// invalidation between the launches it separates); these are only read for
+// their timestamps once the stream has passed them, so they skip that fence.
+hipError_t timing_event(hipEvent_t* e) {
+    return hipEventCreateWithFlags(e, hipEventDisableSystemFence);
+}
+
 template <class T>
 hipError_t dalloc(tcm_handle* h, T** p, size_t count) {
     void* q = nullptr;
@@ -759,7 +767,7 @@ tcm_status issue_steps(tcm_handle* h, int n) {
 tcm_status issue_steps_timed(tcm_handle* h, int n) {
     while ((int)h->events.size() < 2 * n) {
         hipEvent_t e;
-        HIP_OR_FAIL(h, hipEventCreate(&e));
+        HIP_OR_FAIL(h, timing_event(&e));
         h->events.push_back(e);
     }
     for (int k = 0; k < n; k++)
@@ -1073,8 +1081,8 @@ tcm_status tcm_hbm_probe(const float* src, float* dst, uint64_t n, int32_t nread
     const int grid = std::max(1, ncu * (wg_per_cu ? wg_per_cu : 8));
     hipStream_t s = (hipStream_t)stream;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    e = hipEventCreate(&e0);
-    if (e == hipSuccess) e = hipEventCreate(&e1);
+    e = timing_event(&e0);
+    if (e == hipSuccess) e = timing_event(&e1);
     float best = -1.0f;
     for (int r = 0; r < reps && e == hipSuccess; r++) {
         e = tcmk::launch_hbm_probe(src, dst, (long long)n, nread, grid, s, e0, e1);
@@ -1203,7 +1211,7 @@ tcm_status tcm_step(tcm_handle* h, int32_t nsteps) {
         if (timing) {
             while ((int)h->events.size() < 2 * nsteps) {
                 hipEvent_t e;
-                HIP_OR_FAIL(h, hipEventCreate(&e));
+                HIP_OR_FAIL(h, timing_event(&e));
                 h->events.push_back(e);
             }
         }
@@ -1765,10 +1773,10 @@ tcm_status tcm_adjoint(tcm_handle* h, const float* resid, int32_t nt, int32_t re
     const bool timing = (h->cfg.flags & TCM_FLAG_TIMING) != 0;
     while (timing && (int)h->gev.size() < 4 * K) {
         hipEvent_t ev;
-        if (hipEventCreate(&ev) != hipSuccess) {
+        if (timing_event(&ev) != hipSuccess) {
             (void)hipGetLastError();
             cleanup();
-            return set_err(h, TCM_E_DEVICE, "hipEventCreate failed");
+            return set_err(h, TCM_E_DEVICE, "timing event creation failed");
         }
         h->gev.push_back(ev);
     }
@@ -1891,8 +1899,8 @@ tcm_status tcm_autotune(tcm_handle* h, int32_t probe_steps, tcm_tuning* out) {
     const int keep_flags = h->cfg.flags;
     h->cfg.flags &= ~TCM_FLAG_TIMING;
     hipEvent_t e0, e1;
-    HIP_OR_FAIL(h, hipEventCreate(&e0));
-    HIP_OR_FAIL(h, hipEventCreate(&e1));
+    HIP_OR_FAIL(h, timing_event(&e0));
+    HIP_OR_FAIL(h, timing_event(&e1));
     tcm_tuning res{};
     res.ms_per_step = 1e300;
     int best_grid = keep_grid, best_gs = keep_gs, best_w = keep_w, best_p = keep_p;
@@ -2030,8 +2038,8 @@ tcm_status tcm_autotune_run(tcm_handle* h, int32_t nsteps, int32_t probe_steps, 
     st = ck_save(h, s0);
     if (st) return finish(st);
     h->cfg.flags &= ~TCM_FLAG_TIMING;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
-        return finish(dev_fail(h, hipGetLastError(), "hipEventCreate"));
+    if (timing_event(&e0) != hipSuccess || timing_event(&e1) != hipSuccess)
+        return finish(dev_fail(h, hipGetLastError(), "timing event creation"));
     // the probe states, reached with the current shape
     long long at = step0;
     for (int k = 0; k < 3; k++) {
