@@ -63,11 +63,16 @@ __device__ __forceinline__ bool halted_before(const DevState* st, int n) {
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
 // A list row's last field is the global key, with bit 31 set when the slot
-// has sources in the source table (keys are below 2^31): the stencil loads
-// a block's pin and source range only then, instead of for every block.
+// has sources in the source table or a pin (keys are below 2^31): the
+// stencil loads a block's pin and source range only then, instead of for
+// every block, and folds a pin that still holds into the block's keep flag.
 constexpr int ROW_SRC_BIT = (int)0x80000000u;
+__device__ __forceinline__ bool slot_has_pin_or_src(const Tables& t, long long slot) {
+    const unsigned long long ph = ((const unsigned long long*)t.pin_until)[slot];   // {pin, first source}
+    return (int)(unsigned)ph > 0 || (int)(unsigned)(ph >> 32) >= 0;
+}
 __device__ __forceinline__ int row_key_field(const Tables& t, long long slot, long long G) {
-    return (int)G | (t.pin_until[2 * (size_t)slot + 1] >= 0 ? ROW_SRC_BIT : 0);
+    return (int)G | (slot_has_pin_or_src(t, slot) ? ROW_SRC_BIT : 0);
 }
 __device__ __forceinline__ int row_key(int v) { return v & 0x7fffffff; }
 
@@ -750,7 +755,9 @@ __global__ __launch_bounds__(64 * W) void k_block_step(Tables t) {
                     if (bc & 0xFF00000000000000ull) f |= 8u;    // y = 7
                     if (bz0) f |= 16u;
                     if (bz7) f |= 32u;
-                    if (bk) f |= (unsigned)KEEP_BIT;
+                    // a source pin that holds past this step also keeps the
+                    // block (only rows with the source bit load the pin)
+                    if (bk || pinned[q] > n + 1) f |= (unsigned)KEEP_BIT;
                     if (bc | bh) f |= (unsigned)HOT_BIT;
                     t.flags[slot[q]] = (unsigned char)f;
                 }
@@ -1592,18 +1599,25 @@ __device__ __forceinline__ unsigned long long fast_pack3(unsigned a, unsigned b,
     return (unsigned long long)a | ((unsigned long long)b << 21) | ((unsigned long long)c << 42);
 }
 
+// ONE: a single-shot handle (every word belongs to shot 0: no shot lookup)
+template <bool ONE>
 __global__ __launch_bounds__(64 * FAST_WORDS) void k_fast_plan(Tables t) {
     DevState* st = t.st;
     __shared__ int s_new[64 * FAST_WORDS];
     __shared__ int s_nnew, s_nret;
     __shared__ unsigned s_cnt[FAST_WORDS];
     __shared__ unsigned long long s_cells[FAST_WORDS], s_cellsu[FAST_WORDS], s_cellsl[FAST_WORDS];
-    const int n = st->step;
-    if (halted_before(st, n)) return;
+    // the state's fields and a single shot's record in one round of loads
+    // (each dependent round is a memory latency of this short kernel)
+    const int n = st->step, err = st->error, nfs = st->nf_step;
+    Shot S1;
+    if (ONE) S1 = t.shots[0];
+    // (no short-circuit: it would let the compiler load nf_step after error)
+    if ((err != 0) | ((nfs != 0) & (nfs != n + 1))) return;     // halted before this step
     const int p = n & 1;
     const unsigned long long* cur = fast_bm(t, p);
     unsigned long long* nxt = fast_bm(t, 1 - p);
-    const bool failed = st->nf_step != 0;     // this step wrote a non-finite value
+    const bool failed = nfs != 0;             // this step wrote a non-finite value
     const int lane = lane_id();
     const int wid = threadIdx.x >> 6;
     if (blockIdx.x == 0 && threadIdx.x == 0) st->fast_par = 1 - p;   // read by k_fast_emit
@@ -1633,23 +1647,31 @@ __global__ __launch_bounds__(64 * FAST_WORDS) void k_fast_plan(Tables t) {
         const long long w = (long long)c * FAST_WORDS + wid;
         const long long G = w * 64 + lane;
         const bool in_range = w < t.nwords;
-        const int shot = in_range ? shot_of_word(t, w) : 0;
-        const Shot S = t.shots[shot];
-        const unsigned long long curw = in_range ? cur[w] : 0ull;
-        const bool active = (curw >> lane) & 1ull;
-        bool survive = false, in_dom = false;
+        Shot S;
+        if constexpr (ONE) S = S1;
+        else S = t.shots[in_range ? shot_of_word(t, w) : 0];
+        // (keys outside a shot's domain are never active: their word bits
+        // are only loaded for keys inside it)
+        bool active = false, survive = false, in_dom = false;
         float c2u = 0.f;
         int bx = 0, by = 0, bz = 0;
         if (in_range) {
             key_to_block(S, (unsigned)(G - S.key_base), bx, by, bz);
             in_dom = bx < S.bx && by < S.by && bz < S.bz;
             if (in_dom) {
-                // every load of the decision at once (the key's flags, scalar
-                // C2 and pin, each neighbour's word and flags), then decide
+                // the neighbours' keys first, then every load of the decision
+                // at once (the key's word, flags and scalar C2, each
+                // neighbour's word and flags), then decide; a source pin is
+                // in the key's keep flag (the stencil folds it in)
+                long long nk[6], kk[6];
+#pragma unroll
+                for (int d = 0; d < 6; d++) {
+                    nk[d] = neighbour_key(S, bx, by, bz, d);
+                    kk[d] = nk[d] >= 0 ? nk[d] : G;
+                }
+                const unsigned long long curw = cur[w];
                 const unsigned own = t.flags[G];
                 c2u = t.slot_c2u[G];
-                const int pin = active ? t.pin_until[2 * (size_t)(G)] : 0;
-                long long nk[6];
                 unsigned long long nwd[6];
                 unsigned nfl[6];
                 // (a missing neighbour loads the key's own entries, ignored
@@ -1657,16 +1679,17 @@ __global__ __launch_bounds__(64 * FAST_WORDS) void k_fast_plan(Tables t) {
                 // after each load)
 #pragma unroll
                 for (int d = 0; d < 6; d++) {
-                    nk[d] = neighbour_key(S, bx, by, bz, d);
-                    const long long kk = nk[d] >= 0 ? nk[d] : G;
-                    nwd[d] = cur[kk >> 6];
-                    nfl[d] = t.flags[kk];
+                    nwd[d] = cur[kk[d] >> 6];
+                    nfl[d] = t.flags[kk[d]];
                 }
-                survive = active && ((own & KEEP_BIT) != 0 || pin > n + 1);
+                active = (curw >> lane) & 1ull;
+                survive = active && (own & KEEP_BIT) != 0;
+                // (bitwise, not short-circuit: a load that only one branch
+                // uses is moved into that branch and waited for there)
 #pragma unroll
                 for (int d = 0; d < 6; d++)
-                    if (nk[d] >= 0 && ((nwd[d] >> (nk[d] & 63)) & 1ull) && ((nfl[d] >> (d ^ 1)) & 1u))
-                        survive = true;
+                    survive |= (nk[d] >= 0) & (((nwd[d] >> (nk[d] & 63)) & 1ull) != 0) &
+                               (((nfl[d] >> (d ^ 1)) & 1u) != 0);
             }
         }
         const unsigned long long nw = __ballot(survive);
@@ -1757,15 +1780,20 @@ __global__ __launch_bounds__(64 * FAST_WORDS) void k_fast_plan(Tables t) {
     }
 }
 
+template <bool ONE>
 __global__ __launch_bounds__(64 * FAST_WORDS) void k_fast_emit(Tables t) {
     DevState* st = t.st;
     __shared__ unsigned long long s_red[FAST_WORDS][7];
     __shared__ unsigned s_word[FAST_WORDS];
-    if (st->error || st->nf_step) {
+    // the state's fields and a single shot's record in one round of loads
+    const int err = st->error, nfs = st->nf_step, par = st->fast_par;
+    Shot S1;
+    if (ONE) S1 = t.shots[0];
+    if ((err | nfs) != 0) {
         // the step that wrote a non-finite value completes (its phi^{n+1} is
         // kept) with the same list; thread 0 of workgroup 0 is the only
         // reader and writer of the step counter in this launch
-        if (blockIdx.x == 0 && threadIdx.x == 0 && !st->error && st->nf_step == st->step + 1) {
+        if (blockIdx.x == 0 && threadIdx.x == 0 && !err && nfs == st->step + 1) {
             st->updates += st->cells_cur;
             st->updates_u += st->cells_cur_u;
             st->updates_l += st->cells_cur_l;
@@ -1775,7 +1803,6 @@ __global__ __launch_bounds__(64 * FAST_WORDS) void k_fast_emit(Tables t) {
     }
     // the plan wrote every word of the next set (so neither bitmap is ever
     // cleared: the current one becomes the plan's output two steps on)
-    const int par = st->fast_par;
     const unsigned long long* nxt = fast_bm(t, par);
     const int lane = lane_id();
     const int wid = threadIdx.x >> 6;
@@ -1793,8 +1820,14 @@ __global__ __launch_bounds__(64 * FAST_WORDS) void k_fast_emit(Tables t) {
         const long long w = (long long)c * FAST_WORDS + wid;
         const bool in_range = w < t.nwords;
         const unsigned long long myw = in_range ? nxt[w] : 0ull;
-        const int shot = in_range ? shot_of_word(t, w) : 0;
-        const Shot S = t.shots[shot];
+        int shot = 0;
+        Shot S;
+        if constexpr (ONE) {
+            S = S1;
+        } else {
+            shot = in_range ? shot_of_word(t, w) : 0;
+            S = t.shots[shot];
+        }
         // offset of this fast chunk in the next list: the sums of the runs
         // before its own, then the counts of its run's chunks before it (or,
         // with up to FAST_DIRECT_CHUNKS chunks, the counts of all chunks
@@ -1940,10 +1973,18 @@ __global__ __launch_bounds__(64 * FAST_WORDS) void k_fast_emit(Tables t) {
 
 hipError_t launch_fast_update(const Tables& t, int grid, hipStream_t s) {
     if (!t.fast || t.nfchunks > FAST_MAX_CHUNKS) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_fast_plan, dim3(grid), dim3(64 * FAST_WORDS), 0, s, t);
+    if (t.nshots == 1) {
+        hipLaunchKernelGGL(k_fast_plan<true>, dim3(grid), dim3(64 * FAST_WORDS), 0, s, t);
+    } else {
+        hipLaunchKernelGGL(k_fast_plan<false>, dim3(grid), dim3(64 * FAST_WORDS), 0, s, t);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_fast_emit, dim3(grid), dim3(64 * FAST_WORDS), 0, s, t);
+    if (t.nshots == 1) {
+        hipLaunchKernelGGL(k_fast_emit<true>, dim3(grid), dim3(64 * FAST_WORDS), 0, s, t);
+    } else {
+        hipLaunchKernelGGL(k_fast_emit<false>, dim3(grid), dim3(64 * FAST_WORDS), 0, s, t);
+    }
     return hipGetLastError();
 }
 
@@ -1978,7 +2019,7 @@ __global__ void k_check_list(Tables t, int* mark, unsigned long long* bad) {
         nbad += t.slot_key[s] != G;
         nbad += t.rows[8 * (size_t)i] != s;
         nbad += row_key(t.rows[8 * (size_t)i + 7]) != (int)G;
-        nbad += (t.rows[8 * (size_t)i + 7] < 0) != (t.pin_until[2 * (size_t)s + 1] >= 0);
+        nbad += (t.rows[8 * (size_t)i + 7] < 0) != slot_has_pin_or_src(t, s);
         int bx, by, bz;
         key_to_block(S, t.act_key[i], bx, by, bz);
         nbad += !(bx < S.bx && by < S.by && bz < S.bz);
