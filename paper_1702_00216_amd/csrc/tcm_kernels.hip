@@ -756,9 +756,11 @@ __global__ __launch_bounds__(64 * W) void k_block_step(Tables t) {
                     if (bz0) f |= 16u;
                     if (bz7) f |= 32u;
                     // a source pin that holds past this step also keeps the
-                    // block (only rows with the source bit load the pin)
-                    if (bk || pinned[q] > n + 1) f |= (unsigned)KEEP_BIT;
-                    if (bc | bh) f |= (unsigned)HOT_BIT;
+                    // block and makes it hot for the 26-neighbour rule (only
+                    // rows with the source bit load the pin)
+                    const bool pin_holds = pinned[q] > n + 1;
+                    if (bk || pin_holds) f |= (unsigned)KEEP_BIT;
+                    if ((bc | bh) || pin_holds) f |= (unsigned)HOT_BIT;
                     t.flags[slot[q]] = (unsigned char)f;
                 }
             }
@@ -1030,7 +1032,9 @@ __global__ __launch_bounds__(256) void k_plan(Tables t) {
                 f = t.flags[slot];
             }
             key_to_block(t.shots[shot], key, bx, by, bz);
-            survive = (f & KEEP_BIT) != 0 || t.pin_until[2 * (size_t)(slot)] > n + 1;
+            // (the stencil folds a holding source pin into the flags; the
+            // levels of an adaptive run come from bmax, so it reads the pin)
+            survive = (f & KEEP_BIT) != 0 || (t.adaptive && t.pin_until[2 * (size_t)(slot)] > n + 1);
         }
         if (t.interval <= 1) {
             // an active neighbour whose face toward us is above trigger keeps
@@ -1063,12 +1067,12 @@ __global__ __launch_bounds__(256) void k_plan(Tables t) {
             // update every `interval` (<= 8) steps: values move at most one node
             // per step, so a block that is hot (or still inserting a source)
             // must have all 26 nearest and diagonal neighbours active
-            const bool hot = valid && (((f & HOT_BIT) != 0) || t.pin_until[2 * (size_t)(slot)] > n + 1);
+            const bool hot = valid && (((f & HOT_BIT) != 0) || (t.adaptive && t.pin_until[2 * (size_t)(slot)] > n + 1));
             // the 26 neighbours, a layer of nine at a time: their keys and
-            // slots, then their flags and pins, each set of loads issued
-            // together (a missing neighbour loads the entry's own key and
-            // slot, ignored; loads under a condition compile to a wait after
-            // each)
+            // slots, then their flags (and pins, in an adaptive run), each set
+            // of loads issued together (a missing neighbour loads the entry's
+            // own key and slot, ignored; loads under a condition compile to a
+            // wait after each)
             const Shot& S = t.shots[shot];
             const int own = (int)(S.key_base + (long long)key);
             int nk26[27], s26[27];
@@ -1086,12 +1090,16 @@ __global__ __launch_bounds__(256) void k_plan(Tables t) {
 #pragma unroll
                 for (int j = 0; j < 9; j++) sl[j] = t.cell2box[nk26[zl * 9 + j] >= 0 ? nk26[zl * 9 + j] : own];
                 bool nh[9];
+                if (t.adaptive) {
 #pragma unroll
-                for (int j = 0; j < 9; j++) {
-                    const int s2 = sl[j] >= 0 ? sl[j] : slot;
-                    const bool fh = t.adaptive ? (t.bmax[8 * (size_t)s2 + 6] > trig || t.bmax[8 * (size_t)s2 + 7] > trig)
-                                               : (t.flags[s2] & HOT_BIT) != 0;
-                    nh[j] = fh || t.pin_until[2 * (size_t)s2] > n + 1;
+                    for (int j = 0; j < 9; j++) {
+                        const int s2 = sl[j] >= 0 ? sl[j] : slot;
+                        nh[j] = t.bmax[8 * (size_t)s2 + 6] > trig || t.bmax[8 * (size_t)s2 + 7] > trig ||
+                                t.pin_until[2 * (size_t)s2] > n + 1;
+                    }
+                } else {
+#pragma unroll
+                    for (int j = 0; j < 9; j++) nh[j] = (t.flags[sl[j] >= 0 ? sl[j] : slot] & HOT_BIT) != 0;
                 }
 #pragma unroll
                 for (int j = 0; j < 9; j++) {
