@@ -310,9 +310,22 @@ def test_launch_modes_and_reads_agree():
     for k in range(64):
         b.step(1)
     c = gpu_run(w.shape, w.dt, w.c_dense, src, 64, timing=True)
-    for s in (a, b, c):
+    # timed runs split over calls, without graphs, and with the update every
+    # 4 steps from a step that is not on the interval boundary
+    d = gpu_run(w.shape, w.dt, w.c_dense, src, 0, timing=True, graph_steps=24)
+    d.step(5)
+    d.step(59)
+    e = gpu_run(w.shape, w.dt, w.c_dense, src, 64, timing=True, graphs=False)
+    f = gpu_run(w.shape, w.dt, w.c_dense, src, 0, timing=True, trigger_interval=4, graph_steps=8)
+    f.step(3)
+    f.step(61)
+    for s in (a, b, c, d, e, f):
         assert values_equal(s.read(0), phi)
-    assert c.stats()["stencil_launches"] == 64 and c.stats()["stencil_ms"] > 0
+    for s in (c, d, e, f):
+        assert s.stats()["stencil_launches"] == 64 and s.stats()["stencil_ms"] > 0
+        assert s.stats()["stencil_cells"] == s.stats()["cell_updates"]
+    for s in (d, e, f):
+        s.close()
     box = a.read(0, box=((3, 17, 30), (20, 9, 11)))
     assert values_equal(box, phi[30:41, 17:26, 3:23])
     out = torch.empty(11 * 9 * 20, dtype=torch.float32, device="cuda")
