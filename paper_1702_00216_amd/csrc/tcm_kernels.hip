@@ -1579,17 +1579,20 @@ hipError_t launch_emit(const Tables& t, int grid, hipStream_t s) {
 //
 // k_fast_plan: one 64-lane wave per bitmap word (lane = key), FAST_WORDS
 //   words per workgroup (a "fast chunk").  Each key pulls its decision from
-//   the stencil's flag bytes: an active block stays if its keep bit is set or
-//   its source still inserts; any block is in the next set if an active face
-//   neighbour's face toward it is above the trigger ("Updating active cells",
-//   items 3 and 4).  The workgroup writes its words of the next set, releases
-//   and allocates (zero levels, C2 from the media) its own blocks, and stores
-//   its counts; no two workgroups touch the same word, so nothing waits on
-//   another workgroup and no global atomic is used.
+//   the stencil's flag bytes: an active block stays if its keep bit is set
+//   (the stencil also sets it while the block's source pin holds); any block
+//   is in the next set if an active face neighbour's face toward it is above
+//   the trigger ("Updating active cells", items 3 and 4).  The workgroup
+//   writes every one of its words of the next set (the other bitmap, so
+//   neither bitmap is ever cleared), releases and allocates (zero levels, C2
+//   from the media) its own blocks, and stores its counts; no two workgroups
+//   touch the same word, so nothing waits on another workgroup (beyond
+//   FAST_DIRECT_CHUNKS chunks the counts of each run of FAST_BLK chunks are
+//   also summed with device atomics).
 // k_fast_emit: each workgroup sums the counts of the fast chunks before its
 //   own (its offset in the next list) and of all (the list's length), then
-//   compacts its words into the list and its rows in key order, and clears
-//   its words of act(n) for step n + 2; workgroup 0 commits the step.
+//   compacts its words into the list and its rows in key order; workgroup 0
+//   commits the step.
 // --------------------------------------------------------------------------
 __device__ __forceinline__ unsigned long long* fast_bm(const Tables& t, int par) {
     return par ? t.bitmap2 : t.bitmap;
