@@ -379,7 +379,7 @@ hipError_t launch_init_tables(const Tables& t, long long nkeys, hipStream_t s) {
 }
 
 // --------------------------------------------------------------------------
-// K1: block stencil + source insertion + face/keep ballots
+// Block stencil + source insertion + face/keep ballots
 // --------------------------------------------------------------------------
 // LDS tile per wave: columns (xx, yy) in [0,10)^2 (node x = xx - 1,
 // y = yy - 1) of 8 z values each; interior 8x8 from the block, the four x/y
@@ -964,7 +964,7 @@ __device__ int place_slot(const Tables& t, long long G) {
 }
 
 // --------------------------------------------------------------------------
-// K2: keep / release / claim ("Updating active cells", items 1-4, 6)
+// Keep / release / claim ("Updating active cells", items 1-4, 6)
 // --------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_plan(Tables t) {
     DevState* st = t.st;
@@ -1204,7 +1204,7 @@ hipError_t launch_advance(const Tables& t, hipStream_t s) {
 }
 
 // --------------------------------------------------------------------------
-// K3a + K4: pool allocator and bitmap popcounts; the last workgroup scans the
+// Pool allocator and bitmap popcounts; the last workgroup scans the
 // counts and commits the step ("Boxes": vacant boxes are reused).
 // --------------------------------------------------------------------------
 // End of the activation update (one thread): the step's counters, the next
@@ -1441,7 +1441,7 @@ hipError_t launch_pool_count(const Tables& t, int grid, hipStream_t s) {
 }
 
 // --------------------------------------------------------------------------
-// K3b: compaction of the bitmap into the next active list
+// Compaction of the bitmap into the next active list
 // --------------------------------------------------------------------------
 
 // Workgroups of 16 waves take the chunks with a set bit (listed by the
