@@ -186,6 +186,37 @@ def test_retiring_pulse_matches_cpu_tcm_every_step():
     assert g["cell_updates"] == o["updates"]
 
 
+@pytest.mark.parametrize("path,interval", [("two-launch", 1), ("three-pass", 1), ("three-pass", 8)])
+def test_source_pin_keeps_quiet_blocks(path, interval):
+    """A source whose wavelet starts with 24 zero samples: its block is kept
+    by its pin while the field there is below every level (and, with the
+    update every 8 steps, counts as hot, so its 26 neighbours are kept too),
+    then the pulse runs.  Active sets every step, counters and fields equal
+    the CPU TCM on both update paths."""
+    announce(f"source pin on a quiet block, {path}, interval {interval}")
+    shape = (48, 40, 40)
+    c = np.ones(shape[::-1], np.float32)
+    w = np.concatenate([np.zeros(24, np.float32), ti.ricker(0.15, 0.5).w32])
+    lvl = np.float32(3e-3 * float(np.max(np.abs(w))))
+    xyz = (20, 18, 15)
+    t = oracle.TCM(c, 0.5, 1.0, lvl, lvl, interval=interval)
+    t.add_source(xyz, w)
+    sim = gpu_run(shape, 0.5, c, [(xyz, w)], 0, lvl, lvl, trigger_interval=interval,
+                  three_pass_update=path == "three-pass")
+    for k in range(40):
+        assert t.step(1) == 0
+        sim.step(1)
+        assert sim.stats()["active_blocks"] == t.stats()["active"], k
+    assert t.step(80) == 0          # the pulse fills the box; some blocks retire
+    sim.step(80)
+    g, o = sim.stats(), t.stats()
+    assert g["active_blocks"] == o["active"]
+    assert g["activations"] == o["activations"] and g["retirements"] == o["retirements"]
+    assert g["cell_updates"] == o["updates"]
+    assert values_equal(sim.read(0), t.read(0)) and values_equal(sim.read(1), t.read(1))
+    sim.close()
+
+
 def test_pool_cap_fails_like_cpu_tcm():
     announce("pool cap E_POOL")
     w = ti.c1(steps=60)
