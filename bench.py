@@ -273,9 +273,11 @@ def bench_c3(args, tcm):
     nx, ny, nz = w.shape
     alg = stencil_bytes(st["stencil_cells"], st["stencil_cells_uniform"], st["stencil_cells_lattice"])
     achieved = alg / (st["stencil_ms"] * 1e-3) / 1e9
+    shape = launch_shape(None, args)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": "k_block_step",
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic("k_block_step", "c3", shape),
+            "kernel": "k_block_step", "launch_shape": shape,
             "avg_launch_us": round(st["stencil_ms"] * 1e3 / max(st["stencil_launches"], 1), 2),
             "algorithmic_bytes_per_launch": round(alg / max(st["stencil_launches"], 1)),
             "uniform_c2_node_fraction": round(st["stencil_cells_uniform"] / max(st["stencil_cells"], 1), 4),
@@ -295,7 +297,8 @@ def bench_c3(args, tcm):
                "peak_pool_bytes": st["peak_pool_bytes"], "pool_bytes": st["pool_bytes"],
                "table_bytes": st["table_bytes"], "dense_bytes": 3 * 4 * nx * ny * nz,
                "updates": st["cell_updates"], "activations": st["activations"],
-               "retirements": st["retirements"], "active_history": hist})
+               "retirements": st["retirements"], "active_history": hist},
+          copy_calibration=copy_calibration() if args.copy_calibration else None)
 
 
 def cpu_baseline_crop(w, budget_s: float, edge: int = 768):
@@ -404,8 +407,10 @@ def bench_c4(args, tcm):
     tsim.close()
     alg = stencil_bytes(ts["stencil_cells"], ts["stencil_cells_uniform"], ts["stencil_cells_lattice"])
     achieved = alg / (ts["stencil_ms"] * 1e-3) / 1e9
+    shape = launch_shape(tuning, args)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_block_step",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic("k_block_step", "c4", shape),
+            "kernel": "k_block_step", "launch_shape": shape,
             "avg_launch_us": round(ts["stencil_ms"] * 1e3 / max(ts["stencil_launches"], 1), 2),
             "algorithmic_bytes_per_launch": round(alg / max(ts["stencil_launches"], 1)),
             "uniform_c2_node_fraction": round(ts["stencil_cells_uniform"] / max(ts["stencil_cells"], 1), 4),
@@ -439,7 +444,8 @@ def bench_c4(args, tcm):
           roofline=roof, cpu_baseline=cpu,
           tcm={"peak_active_blocks": st["peak_active_blocks"], "peak_pool_bytes": st["peak_pool_bytes"],
                "updates_per_run": st["cell_updates"]},
-          one_by_one=seq, autotune=tuning)
+          one_by_one=seq, autotune=tuning,
+          copy_calibration=copy_calibration() if args.copy_calibration else None)
 
 
 def bench_c5(args, tcm):
