@@ -607,6 +607,30 @@ def test_update_interval_exact_at_tau0(k):
     assert values_equal(sim.read_traces(), tr)
 
 
+@pytest.mark.parametrize("k", [4, 8])
+def test_self_advancing_steps_equal_advance_launches(k):
+    """Steps without an activation update: with no receivers the stencil's
+    last workgroup advances the step, with receivers a k_advance launch does
+    (and records them); fields, active sets and counters are the same."""
+    announce(f"self-advancing steps vs k_advance, interval {k}")
+    w = ti.c1(steps=64)
+    src = [(w.source, w.wavelet.w32)]
+    lvl = np.float32(3e-3 * float(np.max(np.abs(w.wavelet.w32))))
+    a = gpu_run(w.shape, w.dt, w.c_dense, src, 0, lvl, lvl / 3, trigger_interval=k)
+    b = gpu_run(w.shape, w.dt, w.c_dense, src, 0, lvl, lvl / 3, trigger_interval=k,
+                receivers=np.array([[w.source[0] + 5, w.source[1], w.source[2]]], np.int32))
+    for n in (5, 27, 40):
+        a.step(n)
+        b.step(n)
+        sa, sb = a.stats(), b.stats()
+        for key in ("step", "active_blocks", "cell_updates", "activations", "retirements"):
+            assert sa[key] == sb[key], (n, key)
+        assert values_equal(a.read(0), b.read(0)) and values_equal(a.read(1), b.read(1)), n
+    assert np.any(b.read_traces() != 0)
+    a.close()
+    b.close()
+
+
 @pytest.mark.parametrize("k,rel,n", [(8, False, 0), (4, True, 0), (8, False, 5)])
 def test_update_interval_matches_cpu_tcm(k, rel, n):
     announce(f"update interval {k} vs CPU TCM (adaptive {rel}, shutdown {n})")
