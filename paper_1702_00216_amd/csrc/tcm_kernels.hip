@@ -424,11 +424,14 @@ __global__ __launch_bounds__(64 * W) void k_block_step(Tables t) {
     // ordered) list is cut into groups of 2^lg entries dealt round-robin to
     // the XCDs, so neighbouring blocks of a group share one XCD's L2 while all
     // XCDs sweep one common window of the pool (one front in HBM rather than
-    // eight).  Entry j of XCD x is list entry gidx(j).  Groups are 256 entries
-    // (four 4^3 tiles), fewer for short lists so that every XCD has work.
+    // eight).  Entry j of XCD x is list entry gidx(j).  Groups are 128 entries
+    // (two 4^3 tiles; where a row of tiles is 16 tiles, each XCD then takes
+    // the same two tiles of every row of a full set, with their y and z
+    // neighbours), 256 for the adjoint field (each measured faster for its
+    // variant), fewer for short lists so that every XCD has work.
     const int per = gridDim.x >> 3;
     const int xcd = blockIdx.x & 7, jw = blockIdx.x >> 3;
-    int lg = 8;
+    int lg = BASE == STEP_GRAD ? 8 : 7;
     while (lg > 3 && (nact >> 3) < (1 << lg)) lg--;          // B <= 8 divides every group
     const int grp = 1 << lg;
     const int ng = (nact + grp - 1) >> lg;
